@@ -1,0 +1,166 @@
+"""Workload descriptions and seeded input generators.
+
+Workloads (atomic units):
+  h_atom    H atom, Q2, box [-20,20]^3, 8^3 coarse cells, 2 levels in a
+            2-bohr ball at the origin; 1 electron, 1 orbital; field-free,
+            dt = 0.02, Krylov dimension 12, 100 steps.
+  h2        H2, nuclei at z = +-0.7, Q3, box [-30,30]^3, 12^3 coarse cells,
+            3 levels in 1.5-bohr balls around each nucleus; 2 electrons,
+            2 orbitals (4 determinants); sin^2 pulse along z, 800 nm,
+            E0 = 0.0534, 4 cycles, dt = 0.02, Krylov dimension 12.
+  h2o       H2O geometry (O at the origin, H at (+-1.42994, 1.10718, 0)),
+            Q3, box [-40,40]^3, 16^3 coarse cells, 4 levels within 6.5 bohr
+            of O and 3 levels within 6.5 bohr of each H; CAS(10e, 8o);
+            same pulse, 2 cycles.
+  h2_batch  64 H2 instances, bond length ~ U[1,2], depth ~ {2,3,4},
+            E0 ~ U[0.02, 0.06], drawn from default_rng(2301) in that order.
+
+Nothing here evaluates the method; the pulse is an input field.
+"""
+import numpy as np
+
+OMEGA_800NM = 0.0569542
+E0_1E14 = 0.0534
+
+
+def _ball(center, radius, levels):
+    return dict(center=tuple(float(v) for v in center), radius=float(radius), levels=int(levels))
+
+
+def workload(name):
+    """Geometry / molecule description of a named workload (plain dict)."""
+    if name == "h_atom":
+        return dict(name=name, lo=-20.0, hi=20.0, n_coarse=8, p=2,
+                    balls=[_ball((0, 0, 0), 2.0, 2)],
+                    nuclei=[(1.0, (0.0, 0.0, 0.0))], n_orb=1, n_alpha=1, n_beta=0,
+                    dt=0.02, krylov=12, steps=100, E0=0.0, cycles=0)
+    if name == "h2":
+        R = 0.7
+        return dict(name=name, lo=-30.0, hi=30.0, n_coarse=12, p=3,
+                    balls=[_ball((0, 0, R), 1.5, 3), _ball((0, 0, -R), 1.5, 3)],
+                    nuclei=[(1.0, (0.0, 0.0, R)), (1.0, (0.0, 0.0, -R))],
+                    n_orb=2, n_alpha=1, n_beta=1, dt=0.02, krylov=12,
+                    steps=22064, E0=E0_1E14, cycles=4)
+    if name == "h2o":
+        hx, hy = 1.42994, 1.10718
+        return dict(name=name, lo=-40.0, hi=40.0, n_coarse=16, p=3,
+                    balls=[_ball((0, 0, 0), 6.5, 4), _ball((hx, hy, 0), 6.5, 3),
+                           _ball((-hx, hy, 0), 6.5, 3)],
+                    nuclei=[(8.0, (0.0, 0.0, 0.0)), (1.0, (hx, hy, 0.0)), (1.0, (-hx, hy, 0.0))],
+                    n_orb=8, n_alpha=5, n_beta=5, dt=0.02, krylov=12,
+                    steps=11032, E0=E0_1E14, cycles=2)
+    raise KeyError(name)
+
+
+def small_workload(name, seed=0):
+    """Small meshes for parity cases (seconds for the oracle), several tiles
+    and a ragged tail of cells; seeded ball placement."""
+    rng = np.random.default_rng(seed)
+    if name == "tiny_q2":
+        return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                    balls=[_ball(rng.uniform(-1, 1, 3), 1.0, 1)],
+                    nuclei=[(1.0, (0.0, 0.0, 0.0))], n_orb=1, n_alpha=1, n_beta=0)
+    if name == "tiny_q3":
+        c1 = rng.uniform(-1.5, 1.5, 3)
+        return dict(name=name, lo=-8.0, hi=8.0, n_coarse=4, p=3,
+                    balls=[_ball(c1, 1.2, 2), _ball(-c1, 0.8, 1)],
+                    nuclei=[(1.0, tuple(c1 * 0.5)), (1.0, tuple(-c1 * 0.5))],
+                    n_orb=2, n_alpha=1, n_beta=1)
+    if name == "tiny_q1":
+        return dict(name=name, lo=-5.0, hi=5.0, n_coarse=4, p=1,
+                    balls=[_ball(rng.uniform(-0.5, 0.5, 3), 1.5, 2)],
+                    nuclei=[(1.0, (0.3, -0.2, 0.1))], n_orb=2, n_alpha=1, n_beta=1)
+    if name == "small_n3":
+        return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                    balls=[_ball((0.2, -0.3, 0.1), 1.5, 2)],
+                    nuclei=[(2.0, (0.0, 0.0, 0.0))], n_orb=3, n_alpha=2, n_beta=1)
+    raise KeyError(name)
+
+
+def batch_instances(n=64, seed=2301):
+    """H2 instances of the batched workload: (bond, depth, E0) per instance."""
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(1.0, 2.0, n)
+    depth = rng.integers(2, 5, n)
+    E0 = rng.uniform(0.02, 0.06, n)
+    out = []
+    for i in range(n):
+        h = R[i] / 2
+        out.append(dict(name=f"h2_b{i}", lo=-30.0, hi=30.0, n_coarse=12, p=3,
+                        balls=[_ball((0, 0, h), 1.5, depth[i]), _ball((0, 0, -h), 1.5, depth[i])],
+                        nuclei=[(1.0, (0.0, 0.0, h)), (1.0, (0.0, 0.0, -h))],
+                        n_orb=2, n_alpha=1, n_beta=1, dt=0.02, krylov=12, E0=float(E0[i]), cycles=4))
+    return out
+
+
+def pulse(t, E0, cycles, omega=OMEGA_800NM):
+    """E(t) = E0 sin^2(pi t / Tp) sin(omega t) on [0, Tp], zero outside."""
+    t = np.asarray(t, dtype=float)
+    Tp = cycles * 2 * np.pi / omega if cycles else 1.0
+    env = np.where((t >= 0) & (t <= Tp), np.sin(np.pi * t / Tp) ** 2, 0.0)
+    return E0 * env * np.sin(omega * t)
+
+
+def gaussian_orbitals(xyz, centers_exps, coeffs):
+    """Columns sum_k coeffs[k, p] exp(-a_k |x - c_k|^2) at the points xyz."""
+    cols = []
+    for (c, a) in centers_exps:
+        r2 = np.sum((xyz - np.asarray(c)[None, :]) ** 2, axis=1)
+        cols.append(np.exp(-a * r2))
+    B = np.stack(cols, axis=1)
+    return B @ np.asarray(coeffs)
+
+
+def random_orbitals(xyz, n, seed, n_gauss=6, spread=2.0):
+    """Seeded smooth complex test functions (sums of Gaussians) at xyz."""
+    rng = np.random.default_rng(seed)
+    ce = [(rng.uniform(-spread, spread, 3), rng.uniform(0.3, 2.0)) for _ in range(n_gauss)]
+    co = rng.standard_normal((n_gauss, n)) + 1j * rng.standard_normal((n_gauss, n))
+    return gaussian_orbitals(xyz, ce, co)
+
+
+def random_ci(dim, seed):
+    rng = np.random.default_rng(seed)
+    C = rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
+    return C / np.linalg.norm(C)
+
+
+def initial_guess(name, xyz):
+    """Unnormalised initial orbital guesses at the points xyz."""
+    if name in ("h_atom", "tiny_q2"):
+        return gaussian_orbitals(xyz, [((0, 0, 0), 1.0)], np.array([[1.0]])).astype(complex)
+    if name.startswith("h2") and name != "h2o":
+        return None
+    raise KeyError(name)
+
+
+def h2_guess(xyz, half_bond):
+    """sigma_g / sigma_u combinations of 1s-like Gaussians on the two nuclei."""
+    ce = [((0, 0, half_bond), 0.8), ((0, 0, -half_bond), 0.8)]
+    return gaussian_orbitals(xyz, ce, np.array([[1.0, 1.0], [1.0, -1.0]])).astype(complex)
+
+
+def h2o_guess(xyz):
+    """Eight Gaussian-type guesses: O 1s, 2s, 2px, 2py, 2pz and H 1s +- pair
+    combinations (orthonormalised by the caller)."""
+    hx, hy = 1.42994, 1.10718
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    r2 = x * x + y * y + z * z
+    cols = [np.exp(-7.0 * r2), np.exp(-0.8 * r2) - 0.3 * np.exp(-7.0 * r2),
+            x * np.exp(-0.9 * r2), y * np.exp(-0.9 * r2), z * np.exp(-0.9 * r2)]
+    ha = np.exp(-0.9 * ((x - hx) ** 2 + (y - hy) ** 2 + z * z))
+    hb = np.exp(-0.9 * ((x + hx) ** 2 + (y - hy) ** 2 + z * z))
+    cols += [ha + hb, ha - hb, x * y * np.exp(-0.6 * r2)]
+    return np.stack(cols, axis=1).astype(complex)
+
+
+def h2_ci_guess():
+    """CI start with every orbital occupied: (sqrt(0.99), 0, 0, -0.1)."""
+    return np.array([np.sqrt(0.99), 0.0, 0.0, -0.1], dtype=complex)
+
+
+def hf_ci(dim_alpha, dim_beta):
+    """Lowest determinant (first alpha string x first beta string)."""
+    C = np.zeros(dim_alpha * dim_beta, dtype=complex)
+    C[0] = 1.0
+    return C

@@ -1,0 +1,409 @@
+"""Pins of the CPU oracle against closed forms, invariants and brute force.
+
+Every test here checks the oracle against something other than itself:
+closed-form Gauss-Lobatto data, exactness of the Gauss-Lobatto rule on
+polynomials, hand counts of a nested Q2 mesh, the cube integral of 1/r,
+erf(r)/r for a Gaussian charge, harmonic functions, an explicit Fock-space
+CI built without the string code, dense matrix exponentials and the
+one-electron Schroedinger equation.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+from scipy import integrate
+from scipy.special import erf
+
+from oracle.gll import gll, operators_1d, lagrange_eval
+from oracle.mesh import Mesh, MeshDesc, Ball
+from oracle.fem import Operators, duffy_cell, _regular_cells
+from oracle.poisson import (PoissonSolver, boundary_legendre, boundary_direct, full_pairs)
+from oracle.ci import CISpace
+from oracle import mctdhf
+from tests.oracle_cases import case
+from synth import random_orbitals, random_ci
+
+
+# ---------------------------------------------------------------- GLL ----
+def test_gll_closed_forms():
+    xi, w = gll(2)
+    assert np.allclose(xi, [-1, 0, 1], atol=1e-15) and np.allclose(w, [1 / 3, 4 / 3, 1 / 3], atol=1e-15)
+    xi, w = gll(3)
+    s = 1 / np.sqrt(5)
+    assert np.allclose(xi, [-1, -s, s, 1], atol=1e-15) and np.allclose(w, [1 / 6, 5 / 6, 5 / 6, 1 / 6], atol=1e-15)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_gll_operators_exact_on_polynomials(p):
+    xi, w, D, A = operators_1d(p)
+    for k in range(p + 1):                       # D differentiates degree <= p exactly
+        assert np.allclose(D @ xi ** k, k * xi ** max(k - 1, 0) * (k > 0), atol=1e-12)
+    for k in range(2 * p):                       # the rule integrates degree <= 2p-1 exactly
+        assert abs(w @ xi ** k - (1 - (-1) ** (k + 1)) / (k + 1)) < 1e-13
+    assert np.allclose(A, A.T) and np.allclose(A.sum(axis=1), 0, atol=1e-13)
+    # A_ab = int l_a' l_b' by brute-force Gauss-Legendre with many points
+    g, gw = np.polynomial.legendre.leggauss(20)
+    from oracle.gll import lagrange_deriv
+    dL = lagrange_deriv(xi, g)
+    assert np.allclose(A, (dL * gw) @ dL.T, atol=1e-12)
+
+
+# --------------------------------------------------------------- mesh ----
+def test_nested_q2_mesh_hand_counts():
+    # 8^3 coarse Q2 cells (17^3 nodes); two nested refinements of the 2^3
+    # block around the origin add 2*(9^3 - 5^3) nodes; every refined block
+    # face carries 6*n*n - ... hanging nodes; boundary = 17^3 - 15^3.
+    w, mesh, ops = case("h_atom")
+    info = mesh.info()
+    assert info["n_cells"] == 504 + 56 + 64
+    assert info["level_counts"] == [504, 56, 64]
+    assert info["n_full"] == 17 ** 3 + 2 * (9 ** 3 - 5 ** 3)
+    assert info["n_bnd"] == 17 ** 3 - 15 ** 3
+    # each refined 2x2x2 block exposes 6 faces of 4 fine 3x3-node faces: per
+    # face (5x5 fine nodes) the 16 off-coarse-grid ones hang -> 6*4*... = 2*(6*56 - 12*4)
+    assert info["n_hang"] == 2 * (6 * 56 - 12 * 4)
+    assert info["n_dof"] == info["n_full"] - info["n_hang"] - info["n_bnd"]
+    assert info["chain_subst"] == 0
+
+
+@pytest.mark.parametrize("name", ["h_atom", "tiny_q3", "tiny_q1", "small_n3"])
+def test_constraints_reproduce_polynomials(name):
+    w, mesh, ops = case(name)
+    p = mesh.p
+    x, y, z = mesh.xyz.T
+    # a global polynomial of degree p in each variable lies in every cell's space
+    f = (1 + 0.3 * x - 0.2 * y ** min(p, 2) + 0.1 * z ** p + 0.05 * x * y * z ** (p - 1)
+         - 0.02 * (x ** p) * (y ** (p - 1)))
+    fd = f[mesh.dof_nodes]
+    fb = f[mesh.bnd_nodes]
+    rec = mesh.C @ fd + mesh.CB @ fb
+    assert np.max(np.abs(rec - f)) < 1e-12 * max(1.0, np.abs(f).max())
+
+
+@pytest.mark.parametrize("name", ["h_atom", "tiny_q3", "tiny_q1", "small_n3"])
+def test_mass_and_stiffness_invariants(name):
+    w, mesh, ops = case(name)
+    vol = (w["hi"] - w["lo"]) ** 3
+    assert abs(ops.m.sum() - vol) < 1e-10 * vol
+    x = mesh.xyz
+    inter = np.ones(mesh.n_dof, dtype=bool)
+    # linear function: int grad b_k . grad x = 0 for every interior DoF
+    r = mesh.C.T @ (ops.Kfull @ x[:, 0])
+    assert np.max(np.abs(r)) < 1e-11
+    if mesh.p >= 2:
+        # |x|^2: int grad b . grad u = -6 int b exactly (GLL exact here)
+        u = np.sum(x ** 2, axis=1)
+        lhs = mesh.C.T @ (ops.Kfull @ u)
+        rhs = -6.0 * (mesh.C.T @ ops.m)
+        assert np.max(np.abs(lhs - rhs)) < 1e-10 * np.abs(rhs).max()
+    # M is SPD and diagonal outside the interface masters
+    M = ops.M.tocsr()
+    off = M - np.diag(M.diagonal()) if mesh.n_dof < 3000 else None
+    rows = np.unique(M.nonzero()[0][M.nonzero()[0] != M.nonzero()[1]])
+    assert set(rows.tolist()) <= set(mesh.masters.tolist())
+    assert np.all(M.diagonal() > 0)
+
+
+# ---------------------------------------------------------- nuclear ----
+def test_nuclear_total_is_cube_integral():
+    # partition of unity: sum_i v_i = int_box -1/r = -8 a^2 (3 ln((1+sqrt3)/sqrt2) - pi/4)
+    w, mesh, ops = case("h_atom")
+    a = 20.0
+    exact = -8 * a * a * (3 * np.log((1 + np.sqrt(3)) / np.sqrt(2)) - np.pi / 4)
+    assert abs(ops.v.sum() - exact) < 1e-9 * abs(exact)
+
+
+def _graded_cubature(fun, o, h, corner, depth=30, q=8):
+    """Brute-force composite Gauss-Legendre: the cube is split into octants
+    recursively toward ``corner`` (the singular point), every other octant
+    gets a q^3 tensor rule; the innermost cube (volume h^3 8^-depth) is
+    dropped.  No Duffy map, no pyramids."""
+    g, gw = np.polynomial.legendre.leggauss(q)
+    g, gw = (g + 1) / 2, gw / 2
+    total = 0.0
+    o = np.array(o, dtype=float)
+    corner = np.array(corner, dtype=float)
+    for _ in range(depth):
+        hh = h / 2
+        for oct_ in itertools.product((0, 1), repeat=3):
+            oo = o + hh * np.array(oct_)
+            if np.allclose(oo + hh * (corner > oo + hh / 2), corner) or \
+               np.all((corner >= oo - 1e-15) & (corner <= oo + hh + 1e-15)):
+                sub = (oo, hh)
+                continue
+            X = oo[None, :] + hh * np.stack(np.meshgrid(g, g, g, indexing='ij'), -1).reshape(-1, 3)
+            W = (gw[:, None, None] * gw[None, :, None] * gw[None, None, :]).ravel() * hh ** 3
+            total += np.sum(W * fun(X))
+        o, h = sub
+    return total
+
+
+def test_duffy_and_gauss_against_graded_cubature():
+    w, mesh, ops = case("h_atom")
+    P = mesh.P
+    hc, org = mesh.cell_h(), mesh.cell_origin()
+    R = np.zeros(3)
+    # a cell with the nucleus on a vertex (Duffy) and a distant cell (Gauss)
+    near = [c for c in range(mesh.n_cells) if np.allclose(org[c], 0.0)][0]
+    far = int(np.argmax(np.linalg.norm(org, axis=1)))
+    dn = duffy_cell(mesh, 1.0, R, org[near], hc[near])
+    df = _regular_cells(mesh, 1.0, R, np.array([far]), mesh.p + 5)[0]
+    for cell, vals in ((near, dn), (far, df)):
+        o, h = org[cell], hc[cell]
+        for (a, b, c) in [(0, 0, 0), (1, 2, 0), (2, 2, 2)]:
+            i = a + P * (b + P * c)
+
+            def f(X):
+                xi = 2 * (X - o) / h - 1
+                L = [lagrange_eval(mesh.xi, xi[:, d]) for d in range(3)]
+                return L[0][a] * L[1][b] * L[2][c] * (-1.0 / np.linalg.norm(X, axis=1))
+            if cell == near:
+                ref = _graded_cubature(f, o, h, R, q=10)
+            else:
+                g, gw = np.polynomial.legendre.leggauss(24)
+                X = o + h * (np.stack(np.meshgrid(g, g, g, indexing='ij'), -1).reshape(-1, 3) + 1) / 2
+                ref = np.sum(np.einsum('i,j,k->ijk', gw, gw, gw).ravel() * f(X)) * (h / 2) ** 3
+            assert abs(vals[i] - ref) < 1e-10 * max(1e-2, abs(ref)), (cell, a, b, c, vals[i], ref)
+
+
+def test_hydrogen_1s_converges_to_minus_half():
+    errs = []
+    for lev in (2, 3):
+        mesh = Mesh(MeshDesc(-20, 20, 8, 2, [Ball((0, 0, 0), 2.0, lev)]))
+        ops = Operators(mesh, [(1.0, (0, 0, 0))])
+        e = spla.eigsh(ops.H1(0.0).tocsc(), k=1, M=ops.M.tocsc(), sigma=-0.6, which="LM")[0][0]
+        errs.append(abs(e + 0.5))
+    assert errs[0] < 0.02 and errs[1] < 0.005 and errs[1] < errs[0] / 3
+
+
+# ----------------------------------------------------------- Poisson ----
+def _gauss_density(mesh, c0, a=2.0):
+    r = np.linalg.norm(mesh.xyz - np.asarray(c0), axis=1)
+    rho = (a / np.pi) ** 1.5 * np.exp(-a * r ** 2)
+    ex = np.where(r > 0, erf(np.sqrt(a) * r) / np.where(r > 0, r, 1.0), 2 * np.sqrt(a / np.pi))
+    return rho, ex
+
+
+@pytest.mark.parametrize("c0", [(0, 0, 0), (0.3, -0.2, 0.7)])
+def test_multipole_boundary_values(c0):
+    w, mesh, ops = case("h_atom")
+    ps = PoissonSolver(ops)
+    rho, ex = _gauss_density(mesh, c0)
+    WB = ps.boundary_values(rho)
+    sel = np.arange(0, len(ps.xb), 97)
+    wts = ops.m * rho
+    # same truncated series through the Legendre addition theorem
+    assert np.max(np.abs(WB[sel] - boundary_legendre(ps.xb[sel], ps.xrel, wts))) < 1e-13
+    # truncation of the untruncated quadrature sum is ~ (r_rho/R)^13
+    assert np.max(np.abs(WB[sel] - boundary_direct(ps.xb[sel], ps.xrel, wts))) < 1e-10
+    if np.allclose(c0, 0):
+        # centred charge: closed form erf(sqrt(a) r)/r scaled by the discrete charge
+        q = wts.sum()
+        assert np.max(np.abs(WB - q * ex[mesh.bnd_nodes])) < 2e-6 * np.abs(ex[mesh.bnd_nodes]).max()
+
+
+def test_poisson_reproduces_harmonic_quadratic():
+    w, mesh, ops = case("tiny_q3")
+    ps = PoissonSolver(ops)
+    x, y, z = mesh.xyz.T
+    u = x * x - y * y + 0.5 * x * z
+    W = ps.solve_density(np.zeros(mesh.n_full), WB=u[mesh.bnd_nodes])
+    assert np.max(np.abs(W - u)) < 1e-10
+
+
+def test_poisson_gaussian_converges_to_erf():
+    errs = []
+    for lev in (2, 3):
+        mesh = Mesh(MeshDesc(-20, 20, 8, 2, [Ball((0, 0, 0), 2.0, lev)]))
+        ops = Operators(mesh, [(1.0, (0, 0, 0))])
+        rho, ex = _gauss_density(mesh, (0, 0, 0))
+        W = PoissonSolver(ops).solve_density(rho)
+        errs.append(np.sqrt(np.sum(ops.m * (W - ex) ** 2) / np.sum(ops.m * ex ** 2)))
+    assert errs[1] < errs[0] / 2 and errs[1] < 2e-3
+
+
+# ----------------------------------------------------------------- CI ----
+def _fock_hamiltonian(n, na, nb, h, g):
+    """Brute force: spin orbitals (alpha 0..n-1, beta n..2n-1), explicit
+    a+ a strings on 2n-bit occupation numbers, no alpha/beta factorisation."""
+    dets = [a | (b << n) for a in range(1 << n) for b in range(1 << n)
+            if bin(a).count('1') == na and bin(b).count('1') == nb]
+    dets.sort(key=lambda d: (d & ((1 << n) - 1), d >> n))   # (alpha mask, beta mask)
+    index = {d: i for i, d in enumerate(dets)}
+
+    def op(ops_list, d):
+        sign = 1
+        for kind, k in reversed(ops_list):
+            occ = (d >> k) & 1
+            if kind == 'a':
+                if not occ:
+                    return 0, None
+                sign *= (-1) ** bin(d & ((1 << k) - 1)).count('1')
+                d &= ~(1 << k)
+            else:
+                if occ:
+                    return 0, None
+                sign *= (-1) ** bin(d & ((1 << k) - 1)).count('1')
+                d |= 1 << k
+        return sign, d
+
+    H = np.zeros((len(dets), len(dets)), dtype=complex)
+    for j, d in enumerate(dets):
+        for p, q in itertools.product(range(n), repeat=2):
+            for s in (0, n):
+                sg, d2 = op([('c', p + s), ('a', q + s)], d)
+                if sg:
+                    H[index[d2], j] += h[p, q] * sg
+        for p, q, r, s_ in itertools.product(range(n), repeat=4):
+            for s1 in (0, n):
+                for s2 in (0, n):
+                    sg, d2 = op([('c', p + s1), ('c', r + s2), ('a', s_ + s2), ('a', q + s1)], d)
+                    if sg:
+                        H[index[d2], j] += 0.5 * g[p, q, r, s_] * sg
+    return H
+
+
+def _random_integrals(n, seed):
+    rng = np.random.default_rng(seed)
+    h = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    h = h + h.conj().T
+    # g_pqrs from orbital-pair densities: g = sum_k conj(A_k,pq) ... built as a
+    # Hermitian positive kernel with the (pq|rs) = (rs|pq) = conj(qp|sr) symmetry
+    X = rng.standard_normal((n * n, n * n)) + 1j * rng.standard_normal((n * n, n * n))
+    G = X @ X.conj().T
+    G = G.reshape(n, n, n, n)
+    g = 0.5 * (G + G.transpose(2, 3, 0, 1))
+    g = 0.5 * (g + np.conj(g.transpose(1, 0, 3, 2)))
+    return h, g
+
+
+@pytest.mark.parametrize("n,na,nb", [(2, 1, 1), (3, 2, 1), (3, 1, 1), (4, 2, 2)])
+def test_ci_hamiltonian_matches_fock_space(n, na, nb):
+    h, g = _random_integrals(n, 7 + n)
+    cs = CISpace(n, na, nb)
+    H = cs.hamiltonian(h, g)
+    Hb = _fock_hamiltonian(n, na, nb, h, g)
+    assert np.allclose(H, Hb, atol=1e-12)
+    assert np.allclose(H, H.conj().T, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,na,nb", [(2, 1, 1), (3, 2, 1), (4, 2, 2)])
+def test_rdm_identities(n, na, nb):
+    cs = CISpace(n, na, nb)
+    C = random_ci(cs.dim, 3)
+    h, g = _random_integrals(n, 11)
+    gam, Gam = cs.rdms(C)
+    N = na + nb
+    assert abs(np.trace(gam) - N) < 1e-12
+    assert np.allclose(np.einsum('pqrr->pq', Gam), (N - 1) * gam, atol=1e-12)
+    E1 = np.vdot(C, cs.hamiltonian(h, g) @ C)
+    E2 = np.sum(h * gam) + 0.5 * np.sum(g * Gam)
+    assert abs(E1 - E2) < 1e-10 * abs(E1)
+
+
+def test_full_ci_invariant_under_orbital_rotation():
+    n = 3
+    h, g = _random_integrals(n, 5)
+    cs = CISpace(n, 2, 1)
+    e0 = np.linalg.eigvalsh(cs.hamiltonian(h, g))
+    Q = sla.expm(1j * (lambda A: A + A.conj().T)(np.random.default_rng(1).standard_normal((n, n))))
+    h2 = Q.conj().T @ h @ Q
+    g2 = np.einsum('ap,bq,cr,ds,abcd->pqrs', Q.conj(), Q, Q.conj(), Q, g)
+    e1 = np.linalg.eigvalsh(cs.hamiltonian(h2, g2))
+    assert np.allclose(e0, e1, atol=1e-10)
+
+
+# ------------------------------------------------------ mean field ----
+def test_closed_shell_mean_field_is_2J_minus_K():
+    w, mesh, ops = case("small_n3")
+    n = 3
+    rng = np.random.default_rng(0)
+    Wfull = [[None] * n for _ in range(n)]
+    for r in range(n):
+        for s in range(r, n):
+            v = rng.standard_normal(mesh.n_full) + 1j * rng.standard_normal(mesh.n_full)
+            if r == s:
+                v = v.real + 0j
+            Wfull[r][s] = v
+            Wfull[s][r] = np.conj(v)
+    cs = CISpace(n, n, n)                         # every orbital doubly occupied
+    gam, Gam = cs.rdms(np.ones(1, dtype=complex))
+    assert np.allclose(gam, 2 * np.eye(n))
+    U = mctdhf.mean_field_U(Gam, Wfull)
+    V = np.einsum('po,xoq->xpq', np.linalg.inv(gam), U)
+    for p in range(n):
+        for q in range(n):
+            ref = (2 * sum(Wfull[r][r] for r in range(n)) if p == q else 0) - Wfull[q][p]
+            assert np.allclose(V[:, p, q], ref, atol=1e-12)
+
+
+# ---------------------------------------------------- propagation ----
+def _dense_G(fr, N, n):
+    G = np.zeros((N * n, N * n), dtype=complex)
+    for j in range(N * n):
+        e = np.zeros(N * n, dtype=complex)
+        e[j] = 1
+        G[:, j] = fr.G(e.reshape(N, n)).ravel()
+    return G
+
+
+def test_arnoldi_matches_dense_expm_on_tiny_mesh():
+    w, mesh, ops = case("tiny_q1")
+    n = 2
+    cs = CISpace(n, 1, 1)
+    c = mctdhf.orthonormalize(ops, random_orbitals(mesh.xyz[mesh.dof_nodes], n, 4))
+    C = random_ci(cs.dim, 2)
+    pr = mctdhf.Propagator(ops, cs)
+    fr = pr.freeze(c, C, 0.01)
+    N = mesh.n_dof
+    G = _dense_G(fr, N, n)
+    for tau in (0.02, -0.02j):
+        ex = (sla.expm(-1j * tau * G) @ c.ravel()).reshape(N, n)
+        out, err, m_eff, _ = mctdhf.arnoldi_step(ops, fr.G, c, tau, 12)
+        nrm = np.sqrt(mctdhf.inner(ops, ex, ex).real)
+        d = np.sqrt(mctdhf.inner(ops, out - ex, out - ex).real)
+        assert d <= 10 * err + 1e-12 * nrm, (tau, d, err)
+        # a full-dimension Krylov space is exact
+        out2, _, m2, _ = mctdhf.arnoldi_step(ops, fr.G, c, tau, N * n)
+        d2 = np.sqrt(mctdhf.inner(ops, out2 - ex, out2 - ex).real)
+        assert d2 < 1e-10 * nrm
+
+
+def test_one_orbital_mctdhf_is_tdse():
+    # n = 1, one electron: mean field vanishes (Gamma = 0); C phi follows
+    # exp(-i dt M^-1 H1) exactly, with the field frozen at t_n.
+    w, mesh, ops = case("tiny_q2")
+    cs = CISpace(1, 1, 0)
+    c = mctdhf.orthonormalize(ops, random_orbitals(mesh.xyz[mesh.dof_nodes], 1, 9))
+    C = np.ones(1, dtype=complex)
+    pr = mctdhf.Propagator(ops, cs)
+    psi = c[:, 0].copy()
+    Minv = np.linalg.inv(ops.M.toarray())
+    dt = 0.05
+    E_steps = [0.0, 0.03, -0.02, 0.05]
+    for E in E_steps:
+        c, C, _ = pr.step(c, C, E, dt, m=12)
+        psi = sla.expm(-1j * dt * Minv @ ops.H1(E).toarray()) @ psi
+        tot = C[0] * c[:, 0]
+        assert np.sqrt(mctdhf.inner(ops, tot - psi, tot - psi).real) < 1e-11
+
+
+def test_field_free_norm_and_orthonormality():
+    w, mesh, ops = case("tiny_q3")
+    n = 2
+    cs = CISpace(n, 1, 1)
+    c = mctdhf.orthonormalize(ops, random_orbitals(mesh.xyz[mesh.dof_nodes], n, 12, spread=1.0))
+    C = random_ci(cs.dim, 5)
+    pr = mctdhf.Propagator(ops, cs)
+    drifts = []
+    for dt in (0.02, 0.01):
+        cc, CC = c.copy(), C.copy()
+        for _ in range(int(round(0.04 / dt))):
+            cc, CC, obs = pr.step(cc, CC, 0.0, dt)
+        S = cc.conj().T @ (ops.M @ cc)
+        drifts.append(np.abs(S - np.eye(n)).max())
+        assert abs(np.linalg.norm(CC) - 1) < 1e-12
+    # orthonormality drift is O(dt^2) per step: halving dt roughly halves it
+    assert drifts[1] < 0.7 * drifts[0]
