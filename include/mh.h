@@ -1,0 +1,229 @@
+/*
+ * mh.h -- C ABI of the MI355X MCTDHF-on-octree-FEM hot path.
+ *
+ * Method: multiconfiguration time-dependent Hartree-Fock on an adaptive
+ * finite-element mesh (Orimo, Sato & Ishikawa, arXiv 2301.02387).  The
+ * library sets up the discretisation of Sec. III.A, applies the frozen
+ * packed orbital operator G of Sec. III.B (Eq. packed_orb_eom), solves the
+ * pair Poisson problems that give the mean-field potentials (Sec. III.A,
+ * Poisson equation with its boundary integral), takes short-iterative
+ * Arnoldi steps exp(-i G dt) and propagates orbitals and CI coefficients
+ * together (Sec. II, Eqs. ci_eom and orb_eom with X = 0).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Status: every entry point returns int; 0 = MH_OK, 1 = MH_NOT_CONVERGED
+ *    (outputs hold the last iterate), negative = failure.  The message of the
+ *    last failure on the calling thread is returned by mh_last_error().  No
+ *    C++ exception crosses this boundary.
+ *  - Complex numbers are complex128, stored as interleaved (re, im) doubles;
+ *    a "c128 array of length L" is 2L doubles.
+ *  - Node order: the library numbers the full (Gauss-Lobatto) nodes as
+ *    [0, N) unknown DoFs, [N, N + N_h) hanging nodes, [N + N_h, N_F) nodes on
+ *    the box boundary.  N_E = N + N_h.
+ *  - Orbital arrays are DEVICE c128 arrays [N_E][n] (orbital index fastest).
+ *    Rows [0, N) are the DoF coefficients; rows [N, N_E) are the hanging-node
+ *    values, which every output fills consistently (row h = sum_k c_hk row k)
+ *    and every input must carry consistently (mh_fill_hanging does it).
+ *    Boundary rows are not stored: orbitals vanish on the box boundary.
+ *  - Device arrays are owned by the caller; the library never frees them.
+ *    Handles (mh_mesh, mh_op) are owned by the library and freed by their
+ *    destroy call.  Internal device workspaces are allocated by the library
+ *    at mh_op_create.
+ *  - Streams: every device call is enqueued on the hipStream_t given as
+ *    `stream` (NULL = the default stream) and returns without synchronising,
+ *    except where a call returns host results (noted per call), which
+ *    synchronises that stream.  Asynchronous device errors surface at the next
+ *    synchronising call.
+ */
+#ifndef MH_H
+#define MH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MH_OK = 0,
+  MH_NOT_CONVERGED = 1,
+  MH_INVALID_ARG = -1,
+  MH_OOM = -2,
+  MH_HIP_ERROR = -3,
+  MH_SINGULAR_RDM = -4,
+  MH_NONFINITE = -5,
+  MH_UNSUPPORTED = -6
+};
+
+typedef struct mh_mesh mh_mesh;
+typedef struct mh_op mh_op;
+
+/* A refinement ball: leaves of level l that come strictly closer than
+ * `radius` to `center` are halved while l < levels (Sec. III.A: coarse cubes
+ * halved recursively where resolution is needed; geometric criterion). */
+typedef struct {
+  double center[3];
+  double radius;
+  int32_t levels;
+} mh_ball;
+
+/* Box [lo, hi]^3 covered by n_coarse^3 cubes, Lagrange degree p (1..3) on
+ * Gauss-Lobatto points (Sec. III.A), refined by the balls, then 2:1 balanced
+ * over all 26 neighbours. */
+typedef struct {
+  double lo, hi;
+  int32_t n_coarse;
+  int32_t p;
+  int32_t n_balls;
+  const mh_ball* balls;   /* host array, read during the call only */
+} mh_mesh_desc;
+
+typedef struct {
+  int64_t n_cells, n_full, n_dof, n_hang, n_bnd, n_masters, hang_nnz;
+  int32_t p, max_level;
+  int64_t level_counts[16];
+} mh_mesh_info;
+
+/* Build the octree, nodes, hanging-node constraints (bridged basis of
+ * Sec. III.A: a node is hanging iff the coarsest leaf containing it lacks it;
+ * its value is that leaf's interpolant) and the node numbering above.
+ * Host-only.  MH_UNSUPPORTED for p outside 1..3 or a hanging node on the box
+ * boundary. */
+int mh_mesh_create(const mh_mesh_desc* desc, mh_mesh** out);
+int mh_mesh_info_get(const mh_mesh* mesh, mh_mesh_info* info);
+/* Host double [N_F][3]: coordinates of every full node in library order. */
+int mh_mesh_node_coords(const mh_mesh* mesh, double* xyz);
+/* Host: hanging rows in CSR over full-node columns (masters are DoFs or
+ * boundary nodes).  ptr: int64 [N_h + 1]; col: int64 [hang_nnz]; w: double
+ * [hang_nnz].  Any pointer may be NULL to skip it. */
+int mh_mesh_constraints(const mh_mesh* mesh, int64_t* ptr, int64_t* col, double* w);
+int mh_mesh_destroy(mh_mesh* mesh);
+
+/* Molecule and operator settings. */
+typedef struct {
+  int32_t n_nuclei;
+  const double* charges;      /* host [n_nuclei] */
+  const double* positions;    /* host [n_nuclei][3] */
+  int32_t n_orb;              /* n spatial orbitals (1..8) */
+  int32_t n_alpha, n_beta;    /* electrons per spin (full CAS over n orbitals) */
+  double polarization[3];     /* unit field direction e (length gauge E(t) e.r) */
+  int32_t lmax_bc;            /* multipole order of the Poisson boundary values (<= 16) */
+  double poisson_rtol;        /* relative residual target of the pair Poisson CG */
+  int32_t poisson_maxit;      /* CG iteration cap */
+  double rdm_eps;             /* regularisation of the 1-RDM inverse */
+} mh_op_desc;
+
+/* Operator set-up (Sec. III.A): Gauss-Lobatto masses, stiffness data, the
+ * lumped nuclear potential v_i = sum_cells int f_i V_nuc (six-pyramid Duffy
+ * rule in cells whose closure holds a nucleus, Gauss-Legendre with p+5
+ * points elsewhere), dipole weights m (e.x), the hanging-interface block of
+ * the mass matrix and the multipole tables; uploads everything and allocates
+ * device workspaces.  Synchronises `stream`. */
+int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* stream, mh_op** out);
+int mh_op_destroy(mh_op* op);
+
+/* Hanging rows of an orbital array in place: x[h] = sum_k c_hk x[k]
+ * (Sec. III.A bridged functions).  x: device c128 [N_E][n]. */
+int mh_fill_hanging(mh_op* op, double* x, void* stream);
+
+/* Mass solve of the discretised orbital equation (Eq. discretized_eom):
+ * c = M^{-1} f with M = C^T diag(m) C (Gauss-Lobatto overlap of the bridged
+ * basis).  f: device c128 [N][n] load vector (DoF rows only are read);
+ * c: device c128 [N_E][n] output, hanging rows filled. */
+int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream);
+
+/* One-body load vector f = H1(E) c with H1(E) = K/2 + V_nuc + E (e.r) in
+ * Galerkin form (Eq. discretized_eom, length gauge).  c: device c128
+ * [N_E][n] (consistent); f: device c128 [N][n]. */
+int mh_h1_apply(mh_op* op, const double* c, double E, double* f, void* stream);
+
+/* Pair Poisson solves (Sec. III.A): for every pair r <= s, solve
+ * Laplace W_rs = -4 pi conj(phi_r) phi_s with Dirichlet values from the
+ * multipole expansion (order lmax_bc, about the box centre) of the boundary
+ * integral, by Jacobi-preconditioned CG on all pairs at once.
+ * phi: device c128 [N_E][n] (consistent).
+ * W:   device double [N_F][n*n] real columns, column order: for r = 0..n-1,
+ *      s = r..n-1: (r == s) one column Re W_rr; (r < s) two columns Re W_rs,
+ *      Im W_rs.  On entry W is the initial guess when `warm` != 0.
+ * iters: host int32 [1] CG iterations taken (may be NULL).
+ * Synchronises `stream`.  MH_NOT_CONVERGED if poisson_maxit is reached. */
+int mh_poisson_pairs(mh_op* op, const double* phi, double* W, int32_t warm, int32_t* iters,
+                     void* stream);
+
+/* Reduced density matrices of a CI vector (Sec. II, spin-summed):
+ * gamma_pq = <E_pq>, Gamma_pq,rs = <E_pq E_rs> - delta_qr gamma_ps.
+ * Ci: device c128 [N_CI] (alpha-string major, strings ordered by bit mask);
+ * gamma: device c128 [n][n]; Gamma: device c128 [n][n][n][n]. */
+int mh_ci_rdms(mh_op* op, const double* Ci, double* gamma, double* Gamma, void* stream);
+
+/* Freeze G at t_n (Eqs. orb_eom, discretized_eom, packed_orb_eom with X = 0):
+ * takes orbitals phi (device c128 [N_E][n]), RDMs (device c128, as above),
+ * the field value E and pair potentials W (device, layout of
+ * mh_poisson_pairs); builds U_oq(x) = sum_rs Gamma_oq,rs W_rs(x), the
+ * regularised gamma^{-1} and lam_qp = phi_q^H F_p(phi).  The frozen operator
+ * is held by `op` until the next freeze.  MH_SINGULAR_RDM if gamma is not
+ * positive after regularisation.  Synchronises `stream`. */
+int mh_freeze(mh_op* op, const double* phi, const double* gamma, const double* Gamma, double E,
+              const double* W, void* stream);
+
+/* Frozen orbital right-hand side: (G v)_p = M^{-1} F_p(v) - sum_q lam_qp v_q,
+ * F_p(v) = H1(E) v_p + C^T[m sum_q V_pq (C v_q)], V = gamma^{-1} U.
+ * v, Gv: device c128 [N_E][n] (v consistent; Gv filled consistently). */
+int mh_rhs_apply(mh_op* op, const double* v, double* Gv, void* stream);
+
+/* Short-iterative Arnoldi step (Sec. III.B): phi <- exp(-i tau G) phi with
+ * the frozen G, Krylov dimension m (<= 24), M-inner product over the packed
+ * orbital vector, classical Gram-Schmidt with one re-orthogonalisation,
+ * happy breakdown at h_{k+1,k} <= 1e-14 |G v_k|.  tau = (tau_re, tau_im):
+ * (dt, 0) real time, (0, -dtau) imaginary time.  err_est (host, may be
+ * NULL) receives beta h_{m+1,m} |e_m^T expm(-i tau H_m) e_1|; m_used (host,
+ * may be NULL) the Krylov dimension reached.  Synchronises when either host
+ * pointer is non-NULL. */
+int mh_arnoldi_step(mh_op* op, double* phi, double tau_re, double tau_im, int32_t m,
+                    double* err_est, int32_t* m_used, void* stream);
+
+/* Per-step observables written by mh_propagate, host arrays [n_steps + 1]. */
+typedef struct {
+  double* dipole;     /* sum_pq gamma_pq <phi_p|e.r|phi_q> */
+  double* energy;     /* sum h gamma + 1/2 sum g Gamma + nuclear repulsion */
+  double* err_est;    /* Arnoldi error estimate (0 for the final record) */
+  double* ortho;      /* max |S - I|, S_pq = <phi_p|phi_q> */
+  int32_t* cg_iters;  /* Poisson CG iterations */
+} mh_observables;
+
+/* Propagate orbitals and CI vector together for n_steps steps of size dt
+ * (Sec. II Eqs. ci_eom / orb_eom with X = 0; Sec. III.B frozen-operator
+ * exponential, first order): at t_n freeze G and the CI Hamiltonian from t_n
+ * data with field E_steps[n], then phi <- exp(-i dt G) phi by Arnoldi (m)
+ * and C <- exp(-i dt H_CI) C by Lanczos with min(12, N_CI) vectors.
+ * imaginary != 0: dt is an imaginary-time step; orbitals are then
+ * Gram-Schmidt orthonormalised in M and C normalised after every step.
+ * phi: device c128 [N_E][n] in-out; Ci: device c128 [N_CI] in-out;
+ * E_steps: host double [n_steps + 1] (the last value is used for the final
+ * record).  obs: host arrays (any member may be NULL).  W_work: device double
+ * [N_F][n*n] Poisson warm-start buffer (in-out, may hold zeros).
+ * Synchronises `stream`. */
+int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const double* E_steps,
+                 int32_t n_steps, double dt, int32_t m, int32_t imaginary, mh_observables* obs,
+                 void* stream);
+
+/* Sizes the caller needs to allocate device arrays. */
+typedef struct {
+  int64_t n_dof, n_ext, n_full, n_ci;
+  int32_t n_orb, n_pair_cols;
+} mh_op_sizes;
+int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sizes);
+
+/* Timing hook for measurement: average duration (ms) of the dominant
+ * kernel over the launches since the last reset, measured with HIP events
+ * recorded on the launch stream.  which: 0 = orbital cell kernel,
+ * 1 = Poisson cell kernel.  Synchronises the device. */
+int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, int64_t* count);
+
+const char* mh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MH_H */

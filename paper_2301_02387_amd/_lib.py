@@ -1,0 +1,268 @@
+"""ctypes binding of libmh.so; names follow include/mh.h."""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+MH_OK, MH_NOT_CONVERGED = 0, 1
+_NAMES = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP_ERROR", -4: "SINGULAR_RDM", -5: "NONFINITE",
+          -6: "UNSUPPORTED"}
+
+EXPORTS = ["mh_mesh_create", "mh_mesh_info_get", "mh_mesh_node_coords", "mh_mesh_constraints",
+           "mh_mesh_destroy", "mh_op_create", "mh_op_destroy", "mh_fill_hanging", "mh_mass_solve",
+           "mh_h1_apply", "mh_poisson_pairs", "mh_ci_rdms", "mh_freeze", "mh_rhs_apply",
+           "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_last_error"]
+
+
+class MHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mh error {code} ({_NAMES.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class _Ball(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("radius", C.c_double), ("levels", C.c_int32)]
+
+
+class _MeshDesc(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("n_coarse", C.c_int32), ("p", C.c_int32),
+                ("n_balls", C.c_int32), ("balls", C.POINTER(_Ball))]
+
+
+class _MeshInfo(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_full", C.c_int64), ("n_dof", C.c_int64), ("n_hang", C.c_int64),
+                ("n_bnd", C.c_int64), ("n_masters", C.c_int64), ("hang_nnz", C.c_int64), ("p", C.c_int32),
+                ("max_level", C.c_int32), ("level_counts", C.c_int64 * 16)]
+
+
+class _OpDesc(C.Structure):
+    _fields_ = [("n_nuclei", C.c_int32), ("charges", C.POINTER(C.c_double)),
+                ("positions", C.POINTER(C.c_double)), ("n_orb", C.c_int32), ("n_alpha", C.c_int32),
+                ("n_beta", C.c_int32), ("polarization", C.c_double * 3), ("lmax_bc", C.c_int32),
+                ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int32), ("rdm_eps", C.c_double)]
+
+
+class _Obs(C.Structure):
+    _fields_ = [("dipole", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double)),
+                ("err_est", C.POINTER(C.c_double)), ("ortho", C.POINTER(C.c_double)),
+                ("cg_iters", C.POINTER(C.c_int32))]
+
+
+class _Sizes(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_ext", C.c_int64), ("n_full", C.c_int64), ("n_ci", C.c_int64),
+                ("n_orb", C.c_int32), ("n_pair_cols", C.c_int32)]
+
+
+_lib = None
+
+
+def lib_path():
+    return os.path.join(_HERE, "libmh.so")
+
+
+def load_library():
+    """Load libmh.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2301_02387_amd.build`")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.mh_last_error.restype = C.c_char_p
+    lib.mh_mesh_create.argtypes = [C.POINTER(_MeshDesc), C.POINTER(vp)]
+    lib.mh_mesh_info_get.argtypes = [vp, C.POINTER(_MeshInfo)]
+    lib.mh_mesh_node_coords.argtypes = [vp, vp]
+    lib.mh_mesh_constraints.argtypes = [vp, vp, vp, vp]
+    lib.mh_mesh_destroy.argtypes = [vp]
+    lib.mh_op_create.argtypes = [vp, C.POINTER(_OpDesc), vp, C.POINTER(vp)]
+    lib.mh_op_destroy.argtypes = [vp]
+    lib.mh_op_sizes_get.argtypes = [vp, C.POINTER(_Sizes)]
+    lib.mh_fill_hanging.argtypes = [vp, vp, vp]
+    lib.mh_mass_solve.argtypes = [vp, vp, vp, vp]
+    lib.mh_h1_apply.argtypes = [vp, vp, C.c_double, vp, vp]
+    lib.mh_poisson_pairs.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_int32), vp]
+    lib.mh_ci_rdms.argtypes = [vp, vp, vp, vp, vp]
+    lib.mh_freeze.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
+    lib.mh_rhs_apply.argtypes = [vp, vp, vp, vp]
+    lib.mh_arnoldi_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int32), vp]
+    lib.mh_propagate.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                 C.POINTER(_Obs), vp]
+    lib.mh_kernel_timing.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    for name in EXPORTS:
+        if name != "mh_last_error":
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc, allow_nc=False):
+    if rc == MH_OK or (allow_nc and rc == MH_NOT_CONVERGED):
+        return rc
+    raise MHError(rc, _lib.mh_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+class Mesh:
+    """Octree mesh (host); see mh_mesh_create."""
+
+    def __init__(self, lo, hi, n_coarse, p, balls):
+        lib = load_library()
+        arr = (_Ball * max(1, len(balls)))()
+        for i, b in enumerate(balls):
+            arr[i].center[:] = list(map(float, b["center"]))
+            arr[i].radius = float(b["radius"])
+            arr[i].levels = int(b["levels"])
+        desc = _MeshDesc(float(lo), float(hi), int(n_coarse), int(p), len(balls), arr)
+        h = C.c_void_p()
+        _check(lib.mh_mesh_create(C.byref(desc), C.byref(h)))
+        self._h = h
+        info = _MeshInfo()
+        _check(lib.mh_mesh_info_get(h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in _MeshInfo._fields_ if k != "level_counts"}
+        self.info["level_counts"] = list(info.level_counts[:info.max_level + 1])
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w["lo"], w["hi"], w["n_coarse"], w["p"], w["balls"])
+
+    def coords(self):
+        out = np.zeros((self.info["n_full"], 3))
+        _check(_lib.mh_mesh_node_coords(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def constraints(self):
+        nh, nnz = self.info["n_hang"], self.info["hang_nnz"]
+        ptr = np.zeros(nh + 1, dtype=np.int64)
+        col = np.zeros(max(1, nnz), dtype=np.int64)
+        w = np.zeros(max(1, nnz))
+        _check(_lib.mh_mesh_constraints(self._h, ptr.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p),
+                                        w.ctypes.data_as(C.c_void_p)))
+        return ptr, col[:nnz], w[:nnz]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mh_mesh_destroy(self._h)
+            self._h = None
+
+
+class Operator:
+    """Operator set-up and device entry points (see include/mh.h)."""
+
+    def __init__(self, mesh, nuclei, n_orb, n_alpha, n_beta, polarization=(0.0, 0.0, 1.0), lmax_bc=12,
+                 poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, stream=None):
+        lib = load_library()
+        Z = np.array([z for z, _ in nuclei], dtype=np.float64)
+        R = np.array([r for _, r in nuclei], dtype=np.float64).reshape(-1, 3)
+        self._keep = (Z, R)
+        desc = _OpDesc(len(nuclei), Z.ctypes.data_as(C.POINTER(C.c_double)),
+                       R.ctypes.data_as(C.POINTER(C.c_double)), int(n_orb), int(n_alpha), int(n_beta),
+                       (C.c_double * 3)(*polarization), int(lmax_bc), float(poisson_rtol), int(poisson_maxit),
+                       float(rdm_eps))
+        h = C.c_void_p()
+        _check(lib.mh_op_create(mesh._h, C.byref(desc), _stream(stream), C.byref(h)))
+        self._h = h
+        self.mesh = mesh
+        sz = _Sizes()
+        _check(lib.mh_op_sizes_get(h, C.byref(sz)))
+        self.n_dof, self.n_ext, self.n_full, self.n_ci = sz.n_dof, sz.n_ext, sz.n_full, sz.n_ci
+        self.n_orb, self.n_pair_cols = sz.n_orb, sz.n_pair_cols
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mh_op_destroy(self._h)
+            self._h = None
+
+    def _need(self, t, rows, cols, dtype):
+        import torch
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError("expected a contiguous CUDA tensor of dtype %s" % dtype)
+        if t.numel() != rows * cols:
+            raise ValueError(f"expected {rows}x{cols} elements, got {tuple(t.shape)}")
+
+    def fill_hanging(self, x, stream=None):
+        import torch
+        self._need(x, self.n_ext, self.n_orb, torch.complex128)
+        _check(_lib.mh_fill_hanging(self._h, _ptr(x), _stream(stream)))
+
+    def mass_solve(self, f, c, stream=None):
+        import torch
+        self._need(c, self.n_ext, self.n_orb, torch.complex128)
+        if f.numel() < self.n_dof * self.n_orb:
+            raise ValueError("f too small")
+        _check(_lib.mh_mass_solve(self._h, _ptr(f), _ptr(c), _stream(stream)))
+
+    def h1_apply(self, c, E, f, stream=None):
+        import torch
+        self._need(c, self.n_ext, self.n_orb, torch.complex128)
+        self._need(f, self.n_dof, self.n_orb, torch.complex128)
+        _check(_lib.mh_h1_apply(self._h, _ptr(c), float(E), _ptr(f), _stream(stream)))
+
+    def poisson_pairs(self, phi, W, warm=False, stream=None):
+        import torch
+        self._need(phi, self.n_ext, self.n_orb, torch.complex128)
+        self._need(W, self.n_full, self.n_pair_cols, torch.float64)
+        it = C.c_int32(0)
+        rc = _check(_lib.mh_poisson_pairs(self._h, _ptr(phi), _ptr(W), int(bool(warm)), C.byref(it),
+                                          _stream(stream)), allow_nc=True)
+        return it.value, rc
+
+    def ci_rdms(self, Ci, gamma, Gamma, stream=None):
+        _check(_lib.mh_ci_rdms(self._h, _ptr(Ci), _ptr(gamma), _ptr(Gamma), _stream(stream)))
+
+    def freeze(self, phi, gamma, Gamma, E, W, stream=None):
+        _check(_lib.mh_freeze(self._h, _ptr(phi), _ptr(gamma), _ptr(Gamma), float(E), _ptr(W), _stream(stream)))
+
+    def rhs_apply(self, v, Gv, stream=None):
+        import torch
+        self._need(v, self.n_ext, self.n_orb, torch.complex128)
+        self._need(Gv, self.n_ext, self.n_orb, torch.complex128)
+        _check(_lib.mh_rhs_apply(self._h, _ptr(v), _ptr(Gv), _stream(stream)))
+
+    def arnoldi_step(self, phi, tau, m, stream=None):
+        import torch
+        self._need(phi, self.n_ext, self.n_orb, torch.complex128)
+        tau = complex(tau)
+        err = C.c_double(0)
+        mu = C.c_int32(0)
+        _check(_lib.mh_arnoldi_step(self._h, _ptr(phi), tau.real, tau.imag, int(m), C.byref(err), C.byref(mu),
+                                    _stream(stream)))
+        return err.value, mu.value
+
+    def propagate(self, phi, Ci, W, E_steps, dt, m=12, imaginary=False, stream=None):
+        import torch
+        self._need(phi, self.n_ext, self.n_orb, torch.complex128)
+        self._need(W, self.n_full, self.n_pair_cols, torch.float64)
+        E = np.ascontiguousarray(E_steps, dtype=np.float64)
+        n_steps = len(E) - 1
+        rec = {k: np.zeros(n_steps + 1) for k in ("dipole", "energy", "err_est", "ortho")}
+        rec["cg_iters"] = np.zeros(n_steps + 1, dtype=np.int32)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        obs = _Obs(dp(rec["dipole"]), dp(rec["energy"]), dp(rec["err_est"]), dp(rec["ortho"]),
+                   rec["cg_iters"].ctypes.data_as(C.POINTER(C.c_int32)))
+        rc = _check(_lib.mh_propagate(self._h, _ptr(phi), _ptr(Ci), _ptr(W), E.ctypes.data_as(C.c_void_p),
+                                      n_steps, float(dt), int(m), int(bool(imaginary)), C.byref(obs),
+                                      _stream(stream)), allow_nc=True)
+        rec["status"] = rc
+        return rec
+
+    def kernel_timing(self, which, enable):
+        avg = C.c_double(0)
+        cnt = C.c_int64(0)
+        _check(_lib.mh_kernel_timing(self._h, int(which), int(bool(enable)), C.byref(avg), C.byref(cnt)))
+        return avg.value, cnt.value

@@ -1,0 +1,728 @@
+// C ABI of the hot path: handles, device memory, and the orchestration of
+// the kernels for each entry point declared in include/mh.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mh.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+using namespace mh;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t _e = (x);                           \
+    if (_e != hipSuccess) throw HipError{_e, #x};  \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct mh_mesh {
+  Mesh M;
+};
+
+struct mh_op {
+  Mesh M;
+  OpHost H;
+  DevMesh d;
+  std::vector<void*> allocs;
+  int n = 0, ncol = 0, lmax = 12;
+  double rtol = 1e-12, rdm_eps = 1e-10, vnn = 0.0;
+  int maxit = 5000;
+  // device data
+  double* xyz = nullptr;
+  int* colinfo = nullptr;  // per real Poisson column: r | s<<8 | part<<16
+  int* colmap = nullptr;   // [n*n]: first column of pair (r<=s)
+  // orbital workspaces
+  double* acc = nullptr;    // [NE][n] c128
+  double* Upk = nullptr;    // [NE][n*n]
+  double* ginv = nullptr;   // [n][n] c128
+  double* lam = nullptr;    // [n][n] c128
+  double* F = nullptr;      // [N][n] c128
+  double* ma_b = nullptr, *ma_x = nullptr, *ma_r = nullptr, *ma_d0 = nullptr, *ma_d1 = nullptr;
+  double* gpart = nullptr;  // reduction partials
+  int gblk = 0;
+  double* Mr = nullptr;     // [n^2][n^2]
+  double* Gtmp = nullptr;   // [n^2][n^2] c128
+  int* flag = nullptr;
+  double E = 0.0;
+  bool frozen = false;
+  // Krylov
+  int m_alloc = 0;
+  std::vector<double*> V;   // host list of device vectors
+  double** Vdev = nullptr;  // device pointer table
+  Krylov K;
+  // Poisson
+  PoissonWs P;
+  // CI
+  CIDev ci;
+  int na = 0, nb = 0;
+  std::vector<double*> Qh;
+  double** Qdev = nullptr;
+  Krylov KC;
+  double* gam = nullptr, *Gam = nullptr, *hmat = nullptr, *gint = nullptr, *S = nullptr, *zmat = nullptr;
+  double* obs = nullptr;    // [4]
+  double* Rinv = nullptr;
+  double* hostpin = nullptr;
+  // timing of the dominant kernels: pools of event pairs recorded on the
+  // launch stream around each launch (no synchronisation while recording)
+  std::vector<hipEvent_t> ev[2];
+  int ev_used[2] = {0, 0};
+  bool timing = false;
+
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+    if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  ~mh_op() {
+    for (void* p : allocs) (void)hipFree(p);
+    for (int k = 0; k < 2; ++k)
+      for (hipEvent_t e : ev[k]) (void)hipEventDestroy(e);
+    if (hostpin) (void)hipHostFree(hostpin);
+  }
+};
+
+static inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    return fail(MH_HIP_ERROR, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what);
+  } catch (const std::bad_alloc&) {
+    return fail(MH_OOM, "device or host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(MH_INVALID_ARG, e.what());
+  } catch (...) {
+    return fail(MH_INVALID_ARG, "unknown error");
+  }
+}
+
+extern "C" const char* mh_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ mesh ----
+extern "C" int mh_mesh_create(const mh_mesh_desc* desc, mh_mesh** out) {
+  if (!desc || !out) return fail(MH_INVALID_ARG, "null argument");
+  if (desc->n_balls < 0 || (desc->n_balls > 0 && !desc->balls)) return fail(MH_INVALID_ARG, "bad balls");
+  return guarded([&]() -> int {
+    std::vector<Ball> balls;
+    for (int i = 0; i < desc->n_balls; ++i) {
+      Ball b;
+      for (int d = 0; d < 3; ++d) b.c[d] = desc->balls[i].center[d];
+      b.r = desc->balls[i].radius;
+      b.levels = desc->balls[i].levels;
+      balls.push_back(b);
+    }
+    auto m = std::make_unique<mh_mesh>();
+    bool unsup = false;
+    std::string err = build_mesh(desc->lo, desc->hi, desc->n_coarse, desc->p, balls, m->M, unsup);
+    if (!err.empty()) return fail(unsup ? MH_UNSUPPORTED : MH_INVALID_ARG, err);
+    *out = m.release();
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_mesh_info_get(const mh_mesh* mesh, mh_mesh_info* info) {
+  if (!mesh || !info) return fail(MH_INVALID_ARG, "null argument");
+  const Mesh& M = mesh->M;
+  std::memset(info, 0, sizeof(*info));
+  info->n_cells = M.n_cells;
+  info->n_full = M.nF;
+  info->n_dof = M.N;
+  info->n_hang = M.Nh;
+  info->n_bnd = M.Nb;
+  info->n_masters = (int64_t)M.masters.size();
+  info->hang_nnz = (int64_t)M.hang_col.size();
+  info->p = M.p;
+  info->max_level = M.Lmax;
+  for (int l = 0; l <= M.Lmax && l < 16; ++l) info->level_counts[l] = M.level_counts[l];
+  return MH_OK;
+}
+
+extern "C" int mh_mesh_node_coords(const mh_mesh* mesh, double* xyz) {
+  if (!mesh || !xyz) return fail(MH_INVALID_ARG, "null argument");
+  std::memcpy(xyz, mesh->M.xyz.data(), mesh->M.xyz.size() * sizeof(double));
+  return MH_OK;
+}
+
+extern "C" int mh_mesh_constraints(const mh_mesh* mesh, int64_t* ptr, int64_t* col, double* w) {
+  if (!mesh) return fail(MH_INVALID_ARG, "null argument");
+  const Mesh& M = mesh->M;
+  if (ptr) std::memcpy(ptr, M.hang_ptr.data(), M.hang_ptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, M.hang_col.data(), M.hang_col.size() * sizeof(int64_t));
+  if (w) std::memcpy(w, M.hang_w.data(), M.hang_w.size() * sizeof(double));
+  return MH_OK;
+}
+
+extern "C" int mh_mesh_destroy(mh_mesh* mesh) {
+  delete mesh;
+  return MH_OK;
+}
+
+// -------------------------------------------------------------- operator ----
+static int popcount32(uint32_t x) { return __builtin_popcount(x); }
+
+// a+_p a_q on string s: returns sign (0 if impossible) and the new string
+static int excite(uint32_t s, int p, int q, uint32_t* out) {
+  if (!((s >> q) & 1u)) return 0;
+  int sign = (popcount32(s & ((1u << q) - 1u)) & 1) ? -1 : 1;
+  uint32_t s2 = s & ~(1u << q);
+  if ((s2 >> p) & 1u) return 0;
+  if (popcount32(s2 & ((1u << p) - 1u)) & 1) sign = -sign;
+  *out = s2 | (1u << p);
+  return sign;
+}
+
+static std::vector<uint32_t> make_strings(int n, int k) {
+  std::vector<uint32_t> v;
+  for (uint32_t s = 0; s < (1u << n); ++s)
+    if (popcount32(s) == k) v.push_back(s);
+  return v;
+}
+
+// table[J][p*n+q] = I | (sign<0)<<30 with E_pq |I> = sign |J> (from E_qp |J>)
+static std::vector<int32_t> excitation_table(int n, const std::vector<uint32_t>& str) {
+  std::vector<int32_t> idx(1u << n, -1);
+  for (size_t i = 0; i < str.size(); ++i) idx[str[i]] = (int32_t)i;
+  std::vector<int32_t> t(str.size() * n * n, -1);
+  for (size_t J = 0; J < str.size(); ++J)
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        uint32_t I = 0;
+        int sg = excite(str[J], q, p, &I);
+        if (sg) t[J * n * n + p * n + q] = idx[I] | (sg < 0 ? (1 << 30) : 0);
+      }
+  return t;
+}
+
+static void krylov_alloc(mh_op* op, Krylov& K, int m_max, int nblk) {
+  K.m_max = m_max;
+  K.H = op->alloc<double>(2 * (m_max + 1) * m_max);
+  K.hcur = op->alloc<double>(2 * (m_max + 1));
+  K.scal = op->alloc<double>(8);
+  K.y = op->alloc<double>(2 * m_max);
+  K.nblk = nblk;
+  K.part = op->alloc<double>((size_t)nblk * (2 * (m_max + 1) + 1) + 64);
+}
+
+extern "C" int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* stream, mh_op** out) {
+  if (!mesh || !desc || !out) return fail(MH_INVALID_ARG, "null argument");
+  if (desc->n_orb < 1 || desc->n_orb > 8) return fail(MH_UNSUPPORTED, "n_orb must be 1..8");
+  if (desc->n_alpha < 0 || desc->n_beta < 0 || desc->n_alpha > desc->n_orb || desc->n_beta > desc->n_orb ||
+      desc->n_alpha + desc->n_beta < 1)
+    return fail(MH_INVALID_ARG, "electron counts");
+  if (desc->n_nuclei < 0 || (desc->n_nuclei > 0 && (!desc->charges || !desc->positions)))
+    return fail(MH_INVALID_ARG, "nuclei");
+  int lmax = desc->lmax_bc > 0 ? desc->lmax_bc : 12;
+  if (lmax > 12) return fail(MH_UNSUPPORTED, "lmax_bc must be <= 12");
+  const int n = desc->n_orb, ncol = n * n;
+  if ((lmax + 1) * (lmax + 1) * ncol > 48 * 256) return fail(MH_UNSUPPORTED, "multipole table too large");
+  return guarded([&]() -> int {
+    hipStream_t s = S(stream);
+    auto op = std::make_unique<mh_op>();
+    op->M = mesh->M;
+    const Mesh& M = op->M;
+    std::vector<Nucleus> nuc;
+    for (int i = 0; i < desc->n_nuclei; ++i) {
+      Nucleus a;
+      a.Z = desc->charges[i];
+      for (int d = 0; d < 3; ++d) a.R[d] = desc->positions[3 * i + d];
+      nuc.push_back(a);
+    }
+    double vnn = 0.0;
+    for (size_t a = 0; a < nuc.size(); ++a)
+      for (size_t b = a + 1; b < nuc.size(); ++b) {
+        double dx = nuc[a].R[0] - nuc[b].R[0], dy = nuc[a].R[1] - nuc[b].R[1], dz = nuc[a].R[2] - nuc[b].R[2];
+        vnn += nuc[a].Z * nuc[b].Z / std::sqrt(dx * dx + dy * dy + dz * dz);
+      }
+    op->vnn = vnn;
+    double pol[3] = {desc->polarization[0], desc->polarization[1], desc->polarization[2]};
+    build_operator(M, nuc, pol, lmax, op->H);
+    const OpHost& H = op->H;
+    op->n = n;
+    op->ncol = ncol;
+    op->lmax = lmax;
+    op->rtol = desc->poisson_rtol > 0 ? desc->poisson_rtol : 1e-12;
+    op->maxit = desc->poisson_maxit > 0 ? desc->poisson_maxit : 5000;
+    op->rdm_eps = desc->rdm_eps > 0 ? desc->rdm_eps : 1e-10;
+    const int64_t NE = M.N + M.Nh;
+
+    DevMesh& d = op->d;
+    d.P = M.P;
+    d.n = n;
+    d.nC = M.n_cells;
+    d.N = M.N;
+    d.NE = NE;
+    d.NF = M.nF;
+    d.Nh = M.Nh;
+    d.Nb = M.Nb;
+    d.nMa = (int64_t)M.masters.size();
+    d.cell_nodes = op->upload(M.cell_nodes, s);
+    std::vector<double> hh(M.n_cells);
+    for (int64_t e = 0; e < M.n_cells; ++e) hh[e] = 0.5 * M.cell_h[e];
+    d.cell_hh = op->upload(hh, s);
+    d.owner = op->upload(H.owner_mask, s);
+    d.m = op->upload(H.m, s);
+    d.v = op->upload(H.v, s);
+    d.mz = op->upload(H.mz, s);
+    std::vector<int32_t> hp(M.hang_ptr.begin(), M.hang_ptr.end()), hc(M.hang_col.begin(), M.hang_col.end());
+    d.hang_ptr = op->upload(hp, s);
+    d.hang_col = op->upload(hc, s);
+    d.hang_w = op->upload(M.hang_w, s);
+    d.ma_index = op->upload(H.ma_index, s);
+    d.ma_dof = op->upload(M.masters, s);
+    d.ma_ptr = op->upload(H.ma_ptr, s);
+    d.ma_col = op->upload(H.ma_col, s);
+    d.ma_val = op->upload(H.ma_val, s);
+    d.ma_dinv = op->upload(H.ma_dinv, s);
+    d.ct_ptr = op->upload(H.ct_ptr, s);
+    d.ct_row = op->upload(H.ct_row, s);
+    d.ct_w = op->upload(H.ct_w, s);
+    d.inv_mass = op->upload(H.inv_mass, s);
+    d.kdiag_inv = op->upload(H.kdiag_inv, s);
+    d.bnd_cells = op->upload(H.bnd_cells, s);
+    d.n_bnd_cells = (int64_t)H.bnd_cells.size();
+    for (int i = 0; i < 16; ++i) d.A[i] = 0.0;
+    for (int i = 0; i < 4; ++i) d.w[i] = 0.0;
+    for (int a = 0; a < M.P; ++a) {
+      d.w[a] = M.gll.w[a];
+      for (int b = 0; b < M.P; ++b) d.A[a * M.P + b] = M.gll.A[a * M.P + b];
+    }
+    op->xyz = op->upload(M.xyz, s);
+    // Poisson column layout
+    std::vector<int> colinfo, colmap(n * n, -1);
+    for (int r = 0; r < n; ++r)
+      for (int q = r; q < n; ++q) {
+        colmap[r * n + q] = (int)colinfo.size();
+        colinfo.push_back(r | (q << 8));
+        if (q != r) colinfo.push_back(r | (q << 8) | (1 << 16));
+      }
+    op->colinfo = op->upload(colinfo, s);
+    op->colmap = op->upload(colmap, s);
+    // orbital workspaces
+    op->acc = op->alloc<double>((size_t)2 * NE * n);
+    HIPCHK(hipMemsetAsync(op->acc, 0, (size_t)2 * NE * n * sizeof(double), s));
+    op->Upk = op->alloc<double>((size_t)NE * n * n);
+    op->ginv = op->alloc<double>(2 * n * n);
+    op->lam = op->alloc<double>(2 * n * n);
+    op->F = op->alloc<double>((size_t)2 * M.N * n);
+    size_t nma = std::max<size_t>(1, M.masters.size());
+    op->ma_b = op->alloc<double>(2 * nma * n);
+    op->ma_x = op->alloc<double>(2 * nma * n);
+    op->ma_r = op->alloc<double>(2 * nma * n);
+    op->ma_d0 = op->alloc<double>(2 * nma * n);
+    op->ma_d1 = op->alloc<double>(2 * nma * n);
+    op->gblk = std::max(gram_blocks(NE), gint_blocks(d));
+    op->gpart = op->alloc<double>((size_t)op->gblk * 2 * 4096 + 64);
+    op->Mr = op->alloc<double>(ncol * ncol);
+    op->Gtmp = op->alloc<double>(2 * ncol * ncol);
+    op->flag = op->alloc<int>(4);
+    op->gam = op->alloc<double>(2 * n * n);
+    op->Gam = op->alloc<double>(2 * ncol * ncol);
+    op->hmat = op->alloc<double>(2 * n * n);
+    op->gint = op->alloc<double>(2 * ncol * ncol);
+    op->S = op->alloc<double>(2 * n * n);
+    op->zmat = op->alloc<double>(2 * n * n);
+    op->obs = op->alloc<double>(8);
+    op->Rinv = op->alloc<double>(2 * n * n);
+    HIPCHK(hipHostMalloc((void**)&op->hostpin, 4096 * sizeof(double), hipHostMallocDefault));
+    // Poisson workspaces
+    PoissonWs& P = op->P;
+    P.ncol = ncol;
+    P.lmax = lmax;
+    P.nharm = (lmax + 1) * (lmax + 1);
+    P.acc = op->alloc<double>((size_t)NE * ncol);
+    HIPCHK(hipMemsetAsync(P.acc, 0, (size_t)NE * ncol * sizeof(double), s));
+    P.p = op->alloc<double>((size_t)NE * ncol);
+    HIPCHK(hipMemsetAsync(P.p, 0, (size_t)NE * ncol * sizeof(double), s));
+    P.r = op->alloc<double>((size_t)M.N * ncol);
+    P.q = op->alloc<double>((size_t)M.N * ncol);
+    P.sc = op->alloc<double>(8 * ncol);
+    P.part = op->alloc<double>((size_t)2048 * 2 * ncol);
+    P.Q = op->alloc<double>((size_t)P.nharm * ncol);
+    P.mblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (NE + 31) / 32));
+    P.mpart = op->alloc<double>((size_t)P.mblk * P.nharm * ncol);
+    P.table = op->upload(H.bnd_table, s);
+    P.center = 0.5 * (M.lo + M.hi);
+    // CI space
+    op->na = desc->n_alpha;
+    op->nb = desc->n_beta;
+    auto sa = make_strings(n, desc->n_alpha), sb = make_strings(n, desc->n_beta);
+    CIDev& c = op->ci;
+    c.n = n;
+    c.NA = (int)sa.size();
+    c.NB = (int)sb.size();
+    c.dim = c.NA * c.NB;
+    c.exa = op->upload(excitation_table(n, sa), s);
+    c.exb = op->upload(excitation_table(n, sb), s);
+    c.D = op->alloc<double>((size_t)2 * c.dim * ncol);
+    c.T = op->alloc<double>((size_t)2 * c.dim * ncol);
+    c.hp = op->alloc<double>(2 * ncol);
+    c.w = op->alloc<double>((size_t)2 * c.dim);
+    c.part = op->alloc<double>((size_t)gram_blocks(c.dim) * 2 * 4096 + 64);
+    int mci = std::min(12, c.dim);
+    for (int j = 0; j <= mci; ++j) op->Qh.push_back(op->alloc<double>((size_t)2 * c.dim));
+    op->Qdev = op->alloc<double*>(op->Qh.size());
+    HIPCHK(hipMemcpyAsync(op->Qdev, op->Qh.data(), op->Qh.size() * sizeof(double*), hipMemcpyHostToDevice, s));
+    krylov_alloc(op.get(), op->KC, 12, 1);
+    HIPCHK(hipStreamSynchronize(s));
+    *out = op.release();
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_op_destroy(mh_op* op) {
+  delete op;
+  return MH_OK;
+}
+
+extern "C" int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sz) {
+  if (!op || !sz) return fail(MH_INVALID_ARG, "null argument");
+  sz->n_dof = op->d.N;
+  sz->n_ext = op->d.NE;
+  sz->n_full = op->d.NF;
+  sz->n_ci = op->ci.dim;
+  sz->n_orb = op->n;
+  sz->n_pair_cols = op->ncol;
+  return MH_OK;
+}
+
+// ------------------------------------------------------- internal pieces ----
+static void cell_orb(mh_op* op, const double* u, double E, int diag_mode, hipStream_t s) {
+  const bool rec = op->timing && op->ev_used[0] + 2 <= (int)op->ev[0].size();
+  if (rec) HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0]], s));
+  launch_cell_orb(op->d, u, op->acc, E, diag_mode, op->Upk, op->ginv, s);
+  if (rec) {
+    HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0] + 1], s));
+    op->ev_used[0] += 2;
+  }
+}
+
+// out = F(u) load vector [N][n] (diag_mode 1: H1 only, 2: with mean field)
+static void load_vector(mh_op* op, const double* u, double E, int diag_mode, double* out, hipStream_t s) {
+  cell_orb(op, u, E, diag_mode, s);
+  launch_epi_orb(op->d, op->acc, 0, nullptr, nullptr, out, nullptr, s);
+  launch_zero(op->acc + 2 * op->d.N * op->n, 2 * op->d.Nh * op->n, s);
+}
+
+// out (extended) = G u  (or M^-1 F(u) when lam == nullptr)
+static void g_apply(mh_op* op, const double* u, double* out, int with_lam, hipStream_t s) {
+  const DevMesh& d = op->d;
+  cell_orb(op, u, op->E, 2, s);
+  launch_epi_orb(d, op->acc, with_lam ? 2 : 1, u, op->lam, out, op->ma_b, s);
+  launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
+                  op->H.cheb_iters, u, with_lam ? op->lam : nullptr, out, s);
+  launch_fill_orb(d, out, op->acc, s);
+}
+
+static int poisson_solve(mh_op* op, const double* phi, double* W, int warm, int* iters, hipStream_t s) {
+  const DevMesh& d = op->d;
+  PoissonWs& P = op->P;
+  const int ncol = P.ncol;
+  launch_poisson_pipeline_moments(d, phi, op->xyz, op->colinfo, P, s);
+  launch_bnd_eval(d, P, W, s);
+  launch_poisson_rhs_full(d, phi, W, op->colinfo, P.r, P, s);
+  launch_cg_start(d, W, P.r, P, warm, s);
+  int it = 0;
+  bool conv = false;
+  double* hs = op->hostpin;
+  const int check = 8;
+  while (it < op->maxit) {
+    int todo = std::min(check, op->maxit - it);
+    for (int k = 0; k < todo; ++k) launch_cg_step(d, W, P, s);
+    it += todo;
+    HIPCHK(hipMemcpyAsync(hs, P.sc, 8 * ncol * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    conv = true;
+    for (int c = 0; c < ncol; ++c) {
+      double rr = hs[SC_RR * ncol + c], bb = hs[SC_BB * ncol + c];
+      if (!std::isfinite(rr)) return fail(MH_NONFINITE, "non-finite Poisson residual");
+      if (rr > op->rtol * op->rtol * bb) conv = false;
+    }
+    if (conv) break;
+  }
+  launch_fill_real(d, W, ncol, 1, P.acc, s);
+  launch_zero(P.acc + d.N * ncol, d.Nh * ncol, s);
+  if (iters) *iters = it;
+  return conv ? MH_OK : MH_NOT_CONVERGED;
+}
+
+static int freeze(mh_op* op, const double* phi, const double* gamma, const double* Gamma, double E, const double* W,
+                  hipStream_t s) {
+  const DevMesh& d = op->d;
+  const int n = op->n;
+  op->E = E;
+  launch_build_U_full(d, W, Gamma, op->colmap, op->Mr, op->Upk, s);
+  launch_ginv(gamma, n, op->rdm_eps, op->ginv, op->flag, s);
+  load_vector(op, phi, E, 2, op->F, s);
+  launch_gram(phi, op->F, nullptr, d.N, n, op->gpart, gram_blocks(d.N), op->lam, s);
+  op->frozen = true;
+  return MH_OK;
+}
+
+static void ensure_krylov(mh_op* op, int m) {
+  if (op->m_alloc >= m) return;
+  for (double* p : op->V) {
+    auto it = std::find(op->allocs.begin(), op->allocs.end(), (void*)p);
+    if (it != op->allocs.end()) op->allocs.erase(it);
+    (void)hipFree(p);
+  }
+  op->V.clear();
+  const size_t len = (size_t)2 * op->d.NE * op->n;
+  for (int j = 0; j <= m; ++j) op->V.push_back(op->alloc<double>(len));
+  op->Vdev = op->alloc<double*>(m + 1);
+  HIPCHK(hipMemcpy(op->Vdev, op->V.data(), (m + 1) * sizeof(double*), hipMemcpyHostToDevice));
+  int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (op->d.NE * op->n + 255) / 256));
+  krylov_alloc(op, op->K, m, nblk);
+  op->m_alloc = m;
+}
+
+static int arnoldi(mh_op* op, double* phi, double tau_re, double tau_im, int m, hipStream_t s) {
+  const DevMesh& d = op->d;
+  ensure_krylov(op, m);
+  Krylov K = op->K;
+  K.m_max = op->m_alloc;
+  launch_norm_init(d, phi, K, m, s);
+  launch_krylov_scale(d, phi, op->V[0], K, 5, 0, s);
+  for (int k = 0; k < m; ++k) {
+    double* w = op->V[k + 1];
+    g_apply(op, op->V[k], w, 1, s);
+    launch_mdot(d, op->Vdev, k, w, K, 1, s);
+    launch_orth_update(d, op->Vdev, k, w, K, 1, s);
+    launch_mdot(d, op->Vdev, k, w, K, 2, s);
+    launch_orth_update(d, op->Vdev, k, w, K, 2, s);
+    launch_krylov_scale(d, w, w, K, 1, k, s);
+  }
+  launch_expm(K, m, tau_re, tau_im, s);
+  launch_combine(d, op->Vdev, m, phi, K, s);
+  return MH_OK;
+}
+
+// ------------------------------------------------------------ entry points ----
+extern "C" int mh_fill_hanging(mh_op* op, double* x, void* stream) {
+  if (!op || !x) return fail(MH_INVALID_ARG, "null argument");
+  return guarded([&]() -> int {
+    launch_fill_orb(op->d, x, nullptr, S(stream));
+    HIPCHK(hipGetLastError());
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream) {
+  if (!op || !f || !c) return fail(MH_INVALID_ARG, "null argument");
+  return guarded([&]() -> int {
+    hipStream_t s = S(stream);
+    const DevMesh& d = op->d;
+    // acc DoF rows <- f, then the plain epilogue (no constraints to add: hanging rows of acc are zero)
+    launch_copy(f, op->acc, 2 * d.N * op->n, s);
+    launch_epi_orb(d, op->acc, 1, nullptr, nullptr, c, op->ma_b, s);
+    launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
+                    op->H.cheb_iters, nullptr, nullptr, c, s);
+    launch_fill_orb(d, c, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_h1_apply(mh_op* op, const double* c, double E, double* f, void* stream) {
+  if (!op || !c || !f) return fail(MH_INVALID_ARG, "null argument");
+  return guarded([&]() -> int {
+    load_vector(op, c, E, 1, f, S(stream));
+    HIPCHK(hipGetLastError());
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_poisson_pairs(mh_op* op, const double* phi, double* W, int32_t warm, int32_t* iters,
+                                void* stream) {
+  if (!op || !phi || !W) return fail(MH_INVALID_ARG, "null argument");
+  return guarded([&]() -> int {
+    int it = 0;
+    int rc = poisson_solve(op, phi, W, warm, &it, S(stream));
+    HIPCHK(hipStreamSynchronize(S(stream)));
+    if (iters) *iters = it;
+    if (rc == MH_NOT_CONVERGED) g_err = "Poisson CG reached poisson_maxit";
+    return rc;
+  });
+}
+
+extern "C" int mh_ci_rdms(mh_op* op, const double* Ci, double* gamma, double* Gamma, void* stream) {
+  if (!op || !Ci || !gamma || !Gamma) return fail(MH_INVALID_ARG, "null argument");
+  return guarded([&]() -> int {
+    launch_ci_rdm_full(op->ci, Ci, gamma, Gamma, op->Gtmp, S(stream));
+    HIPCHK(hipGetLastError());
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_freeze(mh_op* op, const double* phi, const double* gamma, const double* Gamma, double E,
+                         const double* W, void* stream) {
+  if (!op || !phi || !gamma || !Gamma || !W) return fail(MH_INVALID_ARG, "null argument");
+  return guarded([&]() -> int {
+    hipStream_t s = S(stream);
+    freeze(op, phi, gamma, Gamma, E, W, s);
+    int* hf = (int*)op->hostpin;
+    HIPCHK(hipMemcpyAsync(hf, op->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hf[0]) {
+      op->frozen = false;
+      return fail(MH_SINGULAR_RDM, "1-RDM not positive after regularisation");
+    }
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_rhs_apply(mh_op* op, const double* v, double* Gv, void* stream) {
+  if (!op || !v || !Gv) return fail(MH_INVALID_ARG, "null argument");
+  if (!op->frozen) return fail(MH_INVALID_ARG, "mh_freeze has not been called");
+  return guarded([&]() -> int {
+    g_apply(op, v, Gv, 1, S(stream));
+    HIPCHK(hipGetLastError());
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_arnoldi_step(mh_op* op, double* phi, double tau_re, double tau_im, int32_t m, double* err_est,
+                               int32_t* m_used, void* stream) {
+  if (!op || !phi) return fail(MH_INVALID_ARG, "null argument");
+  if (m < 1 || m > 24) return fail(MH_INVALID_ARG, "Krylov dimension must be 1..24");
+  if (!op->frozen) return fail(MH_INVALID_ARG, "mh_freeze has not been called");
+  return guarded([&]() -> int {
+    hipStream_t s = S(stream);
+    arnoldi(op, phi, tau_re, tau_im, m, s);
+    HIPCHK(hipGetLastError());
+    if (err_est || m_used) {
+      HIPCHK(hipMemcpyAsync(op->hostpin, op->K.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (err_est) *err_est = op->hostpin[3];
+      if (m_used) *m_used = (int32_t)op->hostpin[4];
+    }
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const double* E_steps, int32_t n_steps,
+                            double dt, int32_t m, int32_t imaginary, mh_observables* obs, void* stream) {
+  if (!op || !phi || !Ci || !W || (n_steps > 0 && !E_steps)) return fail(MH_INVALID_ARG, "null argument");
+  if (n_steps < 0 || m < 1 || m > 24) return fail(MH_INVALID_ARG, "bad step count or Krylov dimension");
+  return guarded([&]() -> int {
+    hipStream_t s = S(stream);
+    const DevMesh& d = op->d;
+    const int n = op->n;
+    CIDev& c = op->ci;
+    const int mci = std::min(12, c.dim);
+    const double tre = imaginary ? 0.0 : dt, tim = imaginary ? -dt : 0.0;
+    int status = MH_OK;
+    for (int step = 0; step <= n_steps; ++step) {
+      const double E = (n_steps > 0 || E_steps) ? E_steps[step] : 0.0;
+      launch_ci_rdm_full(c, Ci, op->gam, op->Gam, op->Gtmp, s);
+      int it = 0;
+      int rc = poisson_solve(op, phi, W, 1, &it, s);
+      if (rc < 0) return rc;
+      if (rc == MH_NOT_CONVERGED) status = MH_NOT_CONVERGED;
+      freeze(op, phi, op->gam, op->Gam, E, W, s);
+      // integrals and observables at t_n
+      load_vector(op, phi, E, 1, op->F, s);
+      launch_gram(phi, op->F, nullptr, d.N, n, op->gpart, gram_blocks(d.N), op->hmat, s);
+      launch_gint_full(d, phi, W, op->colmap, op->gpart, gint_blocks(d), op->Gtmp, op->gint, s);
+      launch_gram(phi, phi, d.m, d.NE, n, op->gpart, gram_blocks(d.NE), op->S, s);
+      launch_gram(phi, phi, d.mz, d.NE, n, op->gpart, gram_blocks(d.NE), op->zmat, s);
+      launch_observe(op->gam, op->Gam, op->hmat, op->gint, op->zmat, op->S, n, op->vnn, op->obs, s);
+      double err = 0.0;
+      if (step < n_steps) {
+        arnoldi(op, phi, tre, tim, m, s);
+        launch_ci_hprime(c, op->hmat, op->gint, s);
+        launch_ci_lanczos(c, op->Qdev, op->Qh.data(), mci, op->gint, Ci, op->KC, tre, tim, imaginary ? 1 : 0, s);
+        if (imaginary) {
+          launch_gram(phi, phi, d.m, d.NE, n, op->gpart, gram_blocks(d.NE), op->S, s);
+          launch_orthonormalize_full(d, op->S, op->Rinv, phi, s);
+        }
+      }
+      // copy this step's scalars
+      double* hs = op->hostpin;
+      HIPCHK(hipMemcpyAsync(hs, op->obs, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hs + 8, op->K.scal ? op->K.scal : op->obs, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync((int*)(hs + 16), op->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (((int*)(hs + 16))[0]) return fail(MH_SINGULAR_RDM, "1-RDM not positive after regularisation");
+      if (!std::isfinite(hs[0]) || !std::isfinite(hs[1])) return fail(MH_NONFINITE, "non-finite observables");
+      err = (step < n_steps) ? hs[8 + 3] : 0.0;
+      if (obs) {
+        if (obs->dipole) obs->dipole[step] = hs[1];
+        if (obs->energy) obs->energy[step] = hs[0];
+        if (obs->ortho) obs->ortho[step] = hs[2];
+        if (obs->err_est) obs->err_est[step] = err;
+        if (obs->cg_iters) obs->cg_iters[step] = it;
+      }
+    }
+    return status;
+  });
+}
+
+extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, int64_t* count) {
+  if (!op || which < 0 || which > 1) return fail(MH_INVALID_ARG, "bad argument");
+  return guarded([&]() -> int {
+    HIPCHK(hipDeviceSynchronize());
+    const int cap = 8192;
+    for (int k = 0; k < 2; ++k)
+      while ((int)op->ev[k].size() < cap) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        op->ev[k].push_back(e);
+      }
+    op->ev_used[1] = op->P.ev_used;
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (int i = 0; i + 1 < op->ev_used[which]; i += 2) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, op->ev[which][i], op->ev[which][i + 1]));
+      tot += ms;
+      ++cnt;
+    }
+    if (avg_ms) *avg_ms = cnt ? tot / cnt : 0.0;
+    if (count) *count = cnt;
+    op->ev_used[which] = 0;
+    if (which == 1) op->P.ev_used = 0;
+    op->timing = enable != 0;
+    op->P.ev = op->timing ? op->ev[1].data() : nullptr;
+    op->P.ev_cap = cap;
+    return MH_OK;
+  });
+}

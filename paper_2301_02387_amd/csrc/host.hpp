@@ -1,0 +1,81 @@
+// Host-side data of the octree mesh and the operator set-up.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mh {
+
+// Gauss-Lobatto-Legendre nodes/weights on [-1,1] and the 1D stiffness
+// A_ab = sum_q w_q l_a'(x_q) l_b'(x_q) (Sec. III.A element basis/quadrature).
+struct Gll {
+  int p = 0;
+  std::vector<double> x, w, A;  // A row-major (p+1)^2
+};
+Gll make_gll(int p);
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);  // on [-1,1]
+double lagrange(const std::vector<double>& nodes, int a, double x);
+
+struct Ball {
+  double c[3];
+  double r;
+  int levels;
+};
+
+struct Mesh {
+  double lo = 0, hi = 0, H = 0;
+  int nc = 0, p = 0, P = 0, Lmax = 0;
+  int64_t n_cells = 0;
+  std::vector<int32_t> cell_level;
+  std::vector<int64_t> cell_ijk;     // 3 per cell
+  std::vector<double> cell_h;        // edge length
+  std::vector<double> cell_org;      // 3 per cell (lower corner)
+  std::vector<int32_t> cell_nodes;   // n_cells * P^3, library node index
+  int64_t nF = 0, N = 0, Nh = 0, Nb = 0;
+  std::vector<double> xyz;           // nF * 3
+  std::vector<int64_t> hang_ptr;     // Nh + 1 (row h <-> node N + h)
+  std::vector<int64_t> hang_col;     // library node index of master (DoF or boundary)
+  std::vector<double> hang_w;
+  std::vector<int32_t> masters;      // DoF masters, ascending
+  std::vector<int64_t> level_counts;
+  Gll gll;
+};
+
+// Returns "" on success, else an error message; `unsupported` set for
+// configurations the library refuses (hanging node on the boundary, ...).
+std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ball>& balls,
+                       Mesh& out, bool& unsupported);
+
+struct Nucleus {
+  double Z;
+  double R[3];
+};
+
+// Operator tables computed on the host at set-up.
+struct OpHost {
+  std::vector<double> m, v, mz;            // nF: mass, lumped nuclear potential, m*(e.x)
+  std::vector<uint64_t> owner_mask;        // per cell: local nodes whose diagonal terms it adds
+  // interface (hanging-master) block of the mass matrix, rows = masters
+  std::vector<int32_t> ma_index;           // N: index into masters or -1
+  std::vector<int32_t> ma_ptr, ma_col;     // CSR over masters (columns = master index)
+  std::vector<double> ma_val;
+  std::vector<double> ma_dinv;             // 1 / diagonal
+  double cheb_lo = 1, cheb_hi = 1;         // spectrum bounds of D^-1 A_Ma
+  int cheb_iters = 0;
+  std::vector<int32_t> ct_ptr, ct_row;     // per master: hanging rows (library index) constrained by it
+  std::vector<double> ct_w;
+  std::vector<double> inv_mass;            // N: 1/m_k for non-masters (0 for masters)
+  std::vector<double> kdiag_inv;           // N: 1/diag(C^T K_full C)
+  std::vector<int32_t> bnd_cells;          // cells touching boundary values
+  std::vector<double> bnd_table;           // Nb x nharm multipole evaluation table
+  int nharm = 0;
+};
+
+void build_operator(const Mesh& mesh, const std::vector<Nucleus>& nuc, const double pol[3],
+                    int lmax, OpHost& op);
+
+// Multipole harmonics shared by set-up and kernels: the order of the
+// (l, m, cos/sin) terms.  Term count for lmax: (lmax+1)^2.
+int multipole_terms(int lmax);
+
+}  // namespace mh

@@ -1,0 +1,220 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle on the
+same seeded inputs (small meshes spanning several cell tiles and a ragged
+tail, plus the full H2 mesh).
+
+Bar: operator applications (h1_apply, mass_solve, rhs_apply, arnoldi_step)
+max over orbitals of |y_gpu - y_oracle|_2 / |y_oracle|_2 <= 1e-10; Poisson
+potentials <= 1e-9 (CG driven to 1e-13 relative residual; the oracle uses a
+direct solve, so the gap is CG's round-off floor, about cond(K) eps);
+propagated dipoles and energies <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+from synth import random_orbitals, random_ci
+from tests.lib_cases import Pair, rel_err_cols
+
+pytestmark = pytest.mark.gpu
+
+SMALL = ["h_atom", "tiny_q3", "tiny_q1", "small_n3"]
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+_PAIRS = {}
+
+
+def pair(name, **kw):
+    key = (name, tuple(sorted(kw.items())))
+    if key not in _PAIRS:
+        _PAIRS[key] = Pair(name, **kw)
+    return _PAIRS[key]
+
+
+def dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    _torch().cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def orbitals(P, seed):
+    om = P.om
+    from oracle.mctdhf import orthonormalize
+    c = random_orbitals(om.xyz[om.dof_nodes], P.w["n_orb"], seed, spread=1.5)
+    return orthonormalize(P.ops, c)
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_fill_hanging_and_mass_solve(name):
+    torch = _torch()
+    P = pair(name)
+    n = P.w["n_orb"]
+    c = orbitals(P, 1)
+    x = dev(P.to_lib_orb(c))
+    y = x.clone()
+    y[P.N:] = 0
+    P.op.fill_hanging(y)
+    assert np.max(np.abs(host(y) - host(x))) < 1e-13 * np.abs(host(x)).max()
+    f_or = (P.ops.M @ c)
+    f = dev(np.ascontiguousarray(f_or[P.dof_or]))
+    out = torch.zeros((P.NE, n), dtype=torch.complex128, device="cuda")
+    P.op.mass_solve(f, out)
+    ref = P.ops.mass_solve(f_or)
+    o = host(out)
+    assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-12
+    assert rel_err_cols(o[P.N:], (P.om.C @ ref)[P.perm[P.N:P.NE]]) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL + ["h2"])
+def test_h1_apply(name):
+    torch = _torch()
+    P = pair(name)
+    n = P.w["n_orb"]
+    c = orbitals(P, 2)
+    E = 0.0317
+    f = torch.zeros((P.N, n), dtype=torch.complex128, device="cuda")
+    P.op.h1_apply(dev(P.to_lib_orb(c)), E, f)
+    ref = P.ops.H1(E) @ c
+    assert rel_err_cols(P.from_lib_dof(host(f)), ref) < 1e-10
+
+
+def _poisson(P, c, rtol=1e-13):
+    torch = _torch()
+    n = P.w["n_orb"]
+    W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+    it, rc = P.op.poisson_pairs(dev(P.to_lib_orb(c)), W)
+    return W, it, rc
+
+
+@pytest.mark.parametrize("name", SMALL + ["h2"])
+def test_poisson_pairs(name):
+    from oracle.poisson import PoissonSolver
+    P = pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
+    n = P.w["n_orb"]
+    c = orbitals(P, 3)
+    W, it, rc = _poisson(P, c)
+    assert rc == 0 and it > 0
+    ref = PoissonSolver(P.ops).pair_potentials(c)
+    got = P.W_from_lib(host(W), n)
+    for k in ref:
+        num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref[k]) ** 2))
+        den = np.sqrt(np.sum(P.ops.m * np.abs(ref[k]) ** 2))
+        assert num / den < 1e-9, (k, num / den, it)
+
+
+@pytest.mark.parametrize("name,nci", [("tiny_q3", 4), ("small_n3", 9)])
+def test_ci_rdms(name, nci):
+    torch = _torch()
+    from oracle.ci import CISpace
+    P = pair(name)
+    n = P.w["n_orb"]
+    cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
+    assert cs.dim == P.op.n_ci
+    C = random_ci(cs.dim, 4)
+    g = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    G = torch.zeros((n, n, n, n), dtype=torch.complex128, device="cuda")
+    P.op.ci_rdms(dev(C), g, G)
+    gr, Gr = cs.rdms(C)
+    assert np.max(np.abs(host(g) - gr)) < 1e-13
+    assert np.max(np.abs(host(G) - Gr)) < 1e-13
+
+
+def _frozen(P, c, C, E):
+    """Oracle frozen operator and the library frozen on the same inputs."""
+    from oracle.ci import CISpace
+    from oracle.mctdhf import Frozen
+    from oracle.poisson import PoissonSolver
+    torch = _torch()
+    n = P.w["n_orb"]
+    cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
+    gam, Gam = cs.rdms(C)
+    W = PoissonSolver(P.ops).pair_potentials(c)
+    fr = Frozen(P.ops, c, gam, Gam, E, W)
+    P.op.freeze(dev(P.to_lib_orb(c)), dev(gam), dev(Gam), E, dev(P.W_to_lib(W, n)))
+    return fr, cs
+
+
+@pytest.mark.parametrize("name", SMALL + ["h2"])
+def test_rhs_apply(name):
+    torch = _torch()
+    P = pair(name)
+    n = P.w["n_orb"]
+    c = orbitals(P, 5)
+    from oracle.ci import CISpace
+    dim = CISpace(n, P.w["n_alpha"], P.w["n_beta"]).dim
+    fr, _ = _frozen(P, c, random_ci(dim, 6), 0.021)
+    v = orbitals(P, 7)
+    out = torch.zeros((P.NE, n), dtype=torch.complex128, device="cuda")
+    P.op.rhs_apply(dev(P.to_lib_orb(v)), out)
+    ref = fr.G(v)
+    o = host(out)
+    assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-10
+    if P.Nh:
+        assert rel_err_cols(o[P.N:], (P.om.C @ ref)[P.perm[P.N:P.NE]]) < 1e-10
+
+
+@pytest.mark.parametrize("name,tau", [("tiny_q3", 0.02), ("small_n3", 0.05), ("h_atom", 0.02),
+                                      ("tiny_q3", -0.05j), ("h2", 0.02)])
+def test_arnoldi_step(name, tau):
+    from oracle.mctdhf import arnoldi_step
+    P = pair(name)
+    n = P.w["n_orb"]
+    c = orbitals(P, 8)
+    from oracle.ci import CISpace
+    dim = CISpace(n, P.w["n_alpha"], P.w["n_beta"]).dim
+    fr, _ = _frozen(P, c, random_ci(dim, 9), 0.013)
+    x = dev(P.to_lib_orb(c))
+    err, m_used = P.op.arnoldi_step(x, tau, 12)
+    ref, err_ref, m_ref, _ = arnoldi_step(P.ops, fr.G, c, tau, 12)
+    assert m_used == m_ref
+    o = host(x)
+    assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-10
+    assert abs(err - err_ref) <= 1e-6 * err_ref + 1e-14
+
+
+@pytest.mark.parametrize("name,steps,imag", [("h_atom", 4, False), ("tiny_q3", 4, False), ("small_n3", 3, False),
+                                             ("tiny_q3", 3, True)])
+def test_propagate_observables(name, steps, imag):
+    torch = _torch()
+    from oracle.ci import CISpace
+    from oracle.mctdhf import Propagator
+    P = pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
+    n = P.w["n_orb"]
+    cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
+    c = orbitals(P, 10)
+    C = random_ci(cs.dim, 11)
+    dt = 0.02
+    E_steps = [0.0 if imag else 0.05 * np.sin(0.3 * k) for k in range(steps + 1)]
+    x = dev(P.to_lib_orb(c))
+    Cd = dev(C)
+    W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+    rec = P.op.propagate(x, Cd, W, E_steps, dt, m=12, imaginary=imag)
+    pr = Propagator(P.ops, cs)
+    recs = []
+    cc, CC = c.copy(), C.copy()
+    for k in range(steps):
+        cc, CC, ob = pr.step(cc, CC, E_steps[k], dt, 12, imaginary=imag)
+        recs.append(ob)
+    recs.append(pr.final_observables(cc, CC, E_steps[-1]))
+    d_ref = np.array([r["dipole"] for r in recs])
+    e_ref = np.array([r["energy"] for r in recs])
+    assert np.max(np.abs(rec["dipole"] - d_ref)) <= 1e-8 * max(np.abs(d_ref).max(), 1e-3)
+    assert np.max(np.abs(rec["energy"] - e_ref)) <= 1e-8 * np.abs(e_ref).max()
+    assert rel_err_cols(P.from_lib_dof(host(x)), cc) < 1e-8
+    assert np.max(np.abs(host(Cd) - CC)) < 1e-8
+
+
+def test_poisson_not_converged_status():
+    torch = _torch()
+    P = pair("tiny_q3", poisson_maxit=1)
+    c = orbitals(P, 12)
+    W, it, rc = _poisson(P, c)
+    assert rc == 1 and it == 1
