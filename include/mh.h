@@ -88,8 +88,8 @@ typedef struct {
 /* Build the octree, nodes, hanging-node constraints (bridged basis of
  * Sec. III.A: a node is hanging iff the coarsest leaf containing it lacks it;
  * its value is that leaf's interpolant) and the node numbering above.
- * Host-only.  MH_UNSUPPORTED for p outside 1..3 or a hanging node on the box
- * boundary. */
+ * Host-only.  MH_UNSUPPORTED for p outside 1..3; MH_INVALID_ARG for an empty
+ * box or a refinement deeper than the 19-bit octree index allows. */
 int mh_mesh_create(const mh_mesh_desc* desc, mh_mesh** out);
 int mh_mesh_info_get(const mh_mesh* mesh, mh_mesh_info* info);
 /* Host double [N_F][3]: coordinates of every full node in library order. */
@@ -108,7 +108,8 @@ typedef struct {
   int32_t n_orb;              /* n spatial orbitals (1..8) */
   int32_t n_alpha, n_beta;    /* electrons per spin (full CAS over n orbitals) */
   double polarization[3];     /* unit field direction e (length gauge E(t) e.r) */
-  int32_t lmax_bc;            /* multipole order of the Poisson boundary values (<= 16) */
+  int32_t lmax_bc;            /* multipole order of the Poisson boundary values (1..12;
+                                 0 selects 12) */
   double poisson_rtol;        /* relative residual target of the pair Poisson CG */
   int32_t poisson_maxit;      /* CG iteration cap */
   double rdm_eps;             /* regularisation of the 1-RDM inverse */
@@ -197,15 +198,18 @@ typedef struct {
  * exponential, first order): at t_n freeze G and the CI Hamiltonian from t_n
  * data with field E_steps[n], then phi <- exp(-i dt G) phi by Arnoldi (m)
  * and C <- exp(-i dt H_CI) C by Lanczos with min(12, N_CI) vectors.
- * imaginary != 0: dt is an imaginary-time step; orbitals are then
- * Gram-Schmidt orthonormalised in M and C normalised after every step.
+ * flags: MH_PROP_IMAGINARY: dt is an imaginary-time step; orbitals are
+ * then Gram-Schmidt orthonormalised in M and C normalised after every step.
+ * MH_PROP_NO_FINAL: skip the final freeze at t_N (records [0, n_steps) only),
+ * so that n_steps calls of one step do exactly n_steps freezes.
  * phi: device c128 [N_E][n] in-out; Ci: device c128 [N_CI] in-out;
  * E_steps: host double [n_steps + 1] (the last value is used for the final
  * record).  obs: host arrays (any member may be NULL).  W_work: device double
  * [N_F][n*n] Poisson warm-start buffer (in-out, may hold zeros).
  * Synchronises `stream`. */
+enum { MH_PROP_IMAGINARY = 1, MH_PROP_NO_FINAL = 2 };
 int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const double* E_steps,
-                 int32_t n_steps, double dt, int32_t m, int32_t imaginary, mh_observables* obs,
+                 int32_t n_steps, double dt, int32_t m, int32_t flags, mh_observables* obs,
                  void* stream);
 
 /* Sizes the caller needs to allocate device arrays. */

@@ -110,7 +110,10 @@ class PoissonSolver:
 
     def factor(self):
         if self._lu is None:
-            self._lu = spla.splu(self.ops.K.tocsc())
+            # symmetric minimum-degree ordering: same exact factorisation,
+            # far less fill than the default column ordering on 3D meshes
+            self._lu = spla.splu(self.ops.K.tocsc(), permc_spec="MMD_AT_PLUS_A",
+                                 options=dict(SymmetricMode=True))
         return self._lu
 
     def _tables(self):

@@ -244,7 +244,7 @@ class Operator:
                                     _stream(stream)))
         return err.value, mu.value
 
-    def propagate(self, phi, Ci, W, E_steps, dt, m=12, imaginary=False, stream=None):
+    def propagate(self, phi, Ci, W, E_steps, dt, m=12, imaginary=False, final=True, stream=None):
         import torch
         self._need(phi, self.n_ext, self.n_orb, torch.complex128)
         self._need(W, self.n_full, self.n_pair_cols, torch.float64)
@@ -256,7 +256,8 @@ class Operator:
         obs = _Obs(dp(rec["dipole"]), dp(rec["energy"]), dp(rec["err_est"]), dp(rec["ortho"]),
                    rec["cg_iters"].ctypes.data_as(C.POINTER(C.c_int32)))
         rc = _check(_lib.mh_propagate(self._h, _ptr(phi), _ptr(Ci), _ptr(W), E.ctypes.data_as(C.c_void_p),
-                                      n_steps, float(dt), int(m), int(bool(imaginary)), C.byref(obs),
+                                      n_steps, float(dt), int(m),
+                                      (1 if imaginary else 0) | (0 if final else 2), C.byref(obs),
                                       _stream(stream)), allow_nc=True)
         rec["status"] = rc
         return rec

@@ -639,7 +639,9 @@ extern "C" int mh_arnoldi_step(mh_op* op, double* phi, double tau_re, double tau
 }
 
 extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const double* E_steps, int32_t n_steps,
-                            double dt, int32_t m, int32_t imaginary, mh_observables* obs, void* stream) {
+                            double dt, int32_t m, int32_t flags, mh_observables* obs, void* stream) {
+  const int imaginary = flags & MH_PROP_IMAGINARY;
+  const int last_step = (flags & MH_PROP_NO_FINAL) ? n_steps - 1 : n_steps;
   if (!op || !phi || !Ci || !W || (n_steps > 0 && !E_steps)) return fail(MH_INVALID_ARG, "null argument");
   if (n_steps < 0 || m < 1 || m > 24) return fail(MH_INVALID_ARG, "bad step count or Krylov dimension");
   return guarded([&]() -> int {
@@ -650,7 +652,7 @@ extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const
     const int mci = std::min(12, c.dim);
     const double tre = imaginary ? 0.0 : dt, tim = imaginary ? -dt : 0.0;
     int status = MH_OK;
-    for (int step = 0; step <= n_steps; ++step) {
+    for (int step = 0; step <= last_step; ++step) {
       const double E = (n_steps > 0 || E_steps) ? E_steps[step] : 0.0;
       launch_ci_rdm_full(c, Ci, op->gam, op->Gam, op->Gtmp, s);
       int it = 0;
