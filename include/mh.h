@@ -219,11 +219,22 @@ typedef struct {
 } mh_op_sizes;
 int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sizes);
 
-/* Timing hook for measurement: average duration (ms) of the dominant
- * kernel over the launches since the last reset, measured with HIP events
- * recorded on the launch stream.  which: 0 = orbital cell kernel,
- * 1 = Poisson cell kernel.  Synchronises the device. */
+/* Timing hook for measurement: average duration (ms) of an operator kernel
+ * over its launches since the last call, from HIP event pairs recorded on
+ * the launch stream around each launch (no synchronisation while
+ * recording; at most 4096 launches are recorded).  which: 0 = orbital
+ * operator kernel (one-body + mean field), 1 = Poisson operator kernel.
+ * enable: keep recording after this call.  Synchronises the device. */
 int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, int64_t* count);
+
+/* Launch schedule of an operator kernel, chosen by the autotuner.
+ * which: 0 = orbital operator, 1 = Poisson operator.  sched bit 0: 1 =
+ * XCD-contiguous sweep (XCD x of 8 owns a contiguous node range and its
+ * workgroups walk it side by side), 0 = plain grid-stride sweep.
+ * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
+ * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
+ * sums change order only). */
+int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap);
 
 const char* mh_last_error(void);
 

@@ -12,7 +12,7 @@ _NAMES = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP_ERROR", -4: "SINGULAR_RDM", -5:
 EXPORTS = ["mh_mesh_create", "mh_mesh_info_get", "mh_mesh_node_coords", "mh_mesh_constraints",
            "mh_mesh_destroy", "mh_op_create", "mh_op_destroy", "mh_fill_hanging", "mh_mass_solve",
            "mh_h1_apply", "mh_poisson_pairs", "mh_ci_rdms", "mh_freeze", "mh_rhs_apply",
-           "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_last_error"]
+           "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_tune", "mh_last_error"]
 
 
 class MHError(RuntimeError):
@@ -92,6 +92,7 @@ def load_library():
     lib.mh_propagate.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                  C.POINTER(_Obs), vp]
     lib.mh_kernel_timing.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.mh_tune.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     for name in EXPORTS:
         if name != "mh_last_error":
             getattr(lib, name).restype = C.c_int
@@ -267,3 +268,7 @@ class Operator:
         cnt = C.c_int64(0)
         _check(_lib.mh_kernel_timing(self._h, int(which), int(bool(enable)), C.byref(avg), C.byref(cnt)))
         return avg.value, cnt.value
+
+    def tune(self, which, sched, grid_cap):
+        """Select the launch schedule of operator kernel `which` (mh_tune)."""
+        _check(_lib.mh_tune(self._h, int(which), int(sched), int(grid_cap)))

@@ -317,6 +317,10 @@ extern "C" int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* s
     d.ct_w = op->upload(H.ct_w, s);
     d.inv_mass = op->upload(H.inv_mass, s);
     d.kdiag_inv = op->upload(H.kdiag_inv, s);
+    d.node_inc = op->upload(H.node_inc, s);
+    d.kt_ptr = op->upload(H.kt_ptr, s);
+    d.kt_col = op->upload(H.kt_col, s);
+    d.kt_val = op->upload(H.kt_val, s);
     d.bnd_cells = op->upload(H.bnd_cells, s);
     d.n_bnd_cells = (int64_t)H.bnd_cells.size();
     for (int i = 0; i < 16; ++i) d.A[i] = 0.0;
@@ -375,7 +379,8 @@ extern "C" int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* s
     P.r = op->alloc<double>((size_t)M.N * ncol);
     P.q = op->alloc<double>((size_t)M.N * ncol);
     P.sc = op->alloc<double>(8 * ncol);
-    P.part = op->alloc<double>((size_t)2048 * 2 * ncol);
+    P.part = op->alloc<double>((size_t)8192 * 2 * ncol);
+    P.part2 = op->alloc<double>((size_t)4096 * ncol);
     P.Q = op->alloc<double>((size_t)P.nharm * ncol);
     P.mblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (NE + 31) / 32));
     P.mpart = op->alloc<double>((size_t)P.mblk * P.nharm * ncol);
@@ -425,10 +430,12 @@ extern "C" int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sz) {
 }
 
 // ------------------------------------------------------- internal pieces ----
-static void cell_orb(mh_op* op, const double* u, double E, int diag_mode, hipStream_t s) {
+// Node-centric operator pass with optional event timing on the launch stream.
+static void stencil_orb(mh_op* op, const double* u, double E, int diag_mode, int mode, double* out,
+                        hipStream_t s) {
   const bool rec = op->timing && op->ev_used[0] + 2 <= (int)op->ev[0].size();
   if (rec) HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0]], s));
-  launch_cell_orb(op->d, u, op->acc, E, diag_mode, op->Upk, op->ginv, s);
+  launch_stencil_orb(op->d, u, E, diag_mode, op->Upk, op->ginv, mode, op->lam, out, op->acc, s);
   if (rec) {
     HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0] + 1], s));
     op->ev_used[0] += 2;
@@ -437,19 +444,18 @@ static void cell_orb(mh_op* op, const double* u, double E, int diag_mode, hipStr
 
 // out = F(u) load vector [N][n] (diag_mode 1: H1 only, 2: with mean field)
 static void load_vector(mh_op* op, const double* u, double E, int diag_mode, double* out, hipStream_t s) {
-  cell_orb(op, u, E, diag_mode, s);
-  launch_epi_orb(op->d, op->acc, 0, nullptr, nullptr, out, nullptr, s);
-  launch_zero(op->acc + 2 * op->d.N * op->n, 2 * op->d.Nh * op->n, s);
+  stencil_orb(op, u, E, diag_mode, 0, out, s);
+  launch_ma_gather_orb(op->d, op->acc, 0, out, nullptr, s);
 }
 
-// out (extended) = G u  (or M^-1 F(u) when lam == nullptr)
+// out (extended) = G u  (or M^-1 F(u) when with_lam == 0)
 static void g_apply(mh_op* op, const double* u, double* out, int with_lam, hipStream_t s) {
   const DevMesh& d = op->d;
-  cell_orb(op, u, op->E, 2, s);
-  launch_epi_orb(d, op->acc, with_lam ? 2 : 1, u, op->lam, out, op->ma_b, s);
+  stencil_orb(op, u, op->E, 2, with_lam ? 2 : 1, out, s);
+  launch_ma_gather_orb(d, op->acc, 1, out, op->ma_b, s);
   launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
                   op->H.cheb_iters, u, with_lam ? op->lam : nullptr, out, s);
-  launch_fill_orb(d, out, op->acc, s);
+  launch_fill_orb(d, out, nullptr, s);
 }
 
 static int poisson_solve(mh_op* op, const double* phi, double* W, int warm, int* iters, hipStream_t s) {
@@ -509,7 +515,7 @@ static void ensure_krylov(mh_op* op, int m) {
   for (int j = 0; j <= m; ++j) op->V.push_back(op->alloc<double>(len));
   op->Vdev = op->alloc<double*>(m + 1);
   HIPCHK(hipMemcpy(op->Vdev, op->V.data(), (m + 1) * sizeof(double*), hipMemcpyHostToDevice));
-  int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (op->d.NE * op->n + 255) / 256));
+  int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (op->d.NE * op->n + 255) / 256));
   krylov_alloc(op, op->K, m, nblk);
   op->m_alloc = m;
 }
@@ -550,9 +556,7 @@ extern "C" int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream
   return guarded([&]() -> int {
     hipStream_t s = S(stream);
     const DevMesh& d = op->d;
-    // acc DoF rows <- f, then the plain epilogue (no constraints to add: hanging rows of acc are zero)
-    launch_copy(f, op->acc, 2 * d.N * op->n, s);
-    launch_epi_orb(d, op->acc, 1, nullptr, nullptr, c, op->ma_b, s);
+    launch_mass_direct(d, f, c, op->ma_b, s);
     launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
                     op->H.cheb_iters, nullptr, nullptr, c, s);
     launch_fill_orb(d, c, nullptr, s);
@@ -727,4 +731,18 @@ extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double
     op->P.ev_cap = cap;
     return MH_OK;
   });
+}
+
+extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
+  if (!op || which < 0 || which > 1 || sched < 0 || sched > 1) return fail(MH_INVALID_ARG, "bad schedule");
+  const int cap_max = which == 0 ? 65536 : 8192;
+  if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");
+  if (which == 0) {
+    op->d.sched_orb = sched;
+    op->d.grid_orb = grid_cap;
+  } else {
+    op->d.sched_poi = sched;
+    op->d.grid_poi = grid_cap;
+  }
+  return MH_OK;
 }

@@ -55,6 +55,7 @@ struct Nucleus {
 struct OpHost {
   std::vector<double> m, v, mz;            // nF: mass, lumped nuclear potential, m*(e.x)
   std::vector<uint64_t> owner_mask;        // per cell: local nodes whose diagonal terms it adds
+  std::vector<int32_t> node_inc;           // NE x 8: cell*64 + local index of each incident cell, -1 padded
   // interface (hanging-master) block of the mass matrix, rows = masters
   std::vector<int32_t> ma_index;           // N: index into masters or -1
   std::vector<int32_t> ma_ptr, ma_col;     // CSR over masters (columns = master index)
@@ -65,6 +66,9 @@ struct OpHost {
   std::vector<int32_t> ct_ptr, ct_row;     // per master: hanging rows (library index) constrained by it
   std::vector<double> ct_w;
   std::vector<double> inv_mass;            // N: 1/m_k for non-masters (0 for masters)
+  // assembled Poisson operator C^T K_full C on the DoFs (homogeneous boundary), CSR
+  std::vector<int32_t> kt_ptr, kt_col;
+  std::vector<double> kt_val;
   std::vector<double> kdiag_inv;           // N: 1/diag(C^T K_full C)
   std::vector<int32_t> bnd_cells;          // cells touching boundary values
   std::vector<double> bnd_table;           // Nb x nharm multipole evaluation table

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <stdexcept>
 
 #include "host.hpp"
 
@@ -207,6 +208,19 @@ void build_operator(const Mesh& M, const std::vector<Nucleus>& nuc, const double
       }
   }
 
+  // ---- node -> incident cells (at most 8: one leaf per octant around a point)
+  op.node_inc.assign((size_t)NE * 8, -1);
+  {
+    std::vector<uint8_t> cnt(NE, 0);
+    for (int64_t e = 0; e < nC; ++e)
+      for (int t = 0; t < P3; ++t) {
+        int32_t nd = M.cell_nodes[e * P3 + t];
+        if (nd >= NE) continue;
+        if (cnt[nd] >= 8) throw std::runtime_error("a node lies in more than 8 cells");
+        op.node_inc[(size_t)nd * 8 + cnt[nd]++] = (int32_t)(e * 64 + t);
+      }
+  }
+
   // ---- interface block of the mass matrix ------------------------------------
   const int64_t nMa = (int64_t)M.masters.size();
   op.ma_index.assign(N, -1);
@@ -300,6 +314,66 @@ void build_operator(const Mesh& M, const std::vector<Nucleus>& nuc, const double
   op.inv_mass.assign(N, 0.0);
   for (int64_t k = 0; k < N; ++k)
     if (op.ma_index[k] < 0) op.inv_mass[k] = 1.0 / op.m[k];
+
+  // ---- assembled Poisson operator K~ = C^T K_full C on the DoFs --------------
+  // Row k of K_full is the sum over k's cells of its three line couplings
+  // (h/2) A (x) W (x) W etc.; rows of masters also collect c_hk times the
+  // rows of the hanging nodes they constrain; columns are expanded through
+  // C onto DoFs (boundary columns drop: the CG unknowns are homogeneous).
+  {
+    const std::vector<double>& A = M.gll.A;
+    op.kt_ptr.assign(N + 1, 0);
+    op.kt_col.clear();
+    op.kt_val.clear();
+    std::vector<std::pair<int32_t, double>> ent;
+    auto add_row = [&](int64_t nd, double s) {
+      for (int t = 0; t < 8; ++t) {
+        const int32_t code = op.node_inc[(size_t)nd * 8 + t];
+        if (code < 0) break;
+        const int64_t e = code >> 6;
+        const int loc = code & 63;
+        const int a = loc % P, b = (loc / P) % P, c = loc / (P * P);
+        const int32_t* cn = &M.cell_nodes[e * P3];
+        const double hh = 0.5 * M.cell_h[e];
+        for (int q = 0; q < P; ++q) {
+          const int32_t js[3] = {cn[(c * P + b) * P + q], cn[(c * P + q) * P + a], cn[(q * P + b) * P + a]};
+          const double cf[3] = {hh * A[a * P + q] * w[b] * w[c], hh * w[a] * A[b * P + q] * w[c],
+                                hh * w[a] * w[b] * A[c * P + q]};
+          for (int l = 0; l < 3; ++l) {
+            const int64_t j = js[l];
+            const double v = s * cf[l];
+            if (j < N) {
+              ent.push_back({(int32_t)j, v});
+            } else if (j < NE) {
+              for (int64_t r = M.hang_ptr[j - N]; r < M.hang_ptr[j - N + 1]; ++r)
+                if (M.hang_col[r] < N) ent.push_back({(int32_t)M.hang_col[r], v * M.hang_w[r]});
+            }
+          }
+        }
+      }
+    };
+    for (int64_t k = 0; k < N; ++k) {
+      ent.clear();
+      add_row(k, 1.0);
+      const int32_t mi = op.ma_index[k];
+      if (mi >= 0)
+        for (int32_t t = op.ct_ptr[mi]; t < op.ct_ptr[mi + 1]; ++t) add_row(op.ct_row[t], op.ct_w[t]);
+      std::sort(ent.begin(), ent.end(),
+                [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                  return x.first < y.first;
+                });
+      for (size_t t = 0; t < ent.size();) {
+        size_t u = t;
+        double v = 0.0;
+        while (u < ent.size() && ent[u].first == ent[t].first) v += ent[u++].second;
+        op.kt_col.push_back(ent[t].first);
+        op.kt_val.push_back(v);
+        t = u;
+      }
+      if (op.kt_col.size() >= (size_t)INT32_MAX) throw std::runtime_error("Poisson operator too large");
+      op.kt_ptr[k + 1] = (int32_t)op.kt_col.size();
+    }
+  }
 
   // ---- Jacobi diagonal of C^T K_full C --------------------------------------
   {

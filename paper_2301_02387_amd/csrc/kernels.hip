@@ -7,26 +7,11 @@
 
 #include <cmath>
 
+#include "devutil.hpp"
 #include "kernels.hpp"
 
 namespace mh {
 
-#define NT 256
-
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cjmul(double2 a, double2 b) {  // conj(a) * b
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
 // Sum over a 256-thread block; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* lds) {
   v = wave_sum(v);
@@ -39,12 +24,6 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return t;
 }
 
-static inline int nblocks(int64_t work, int per = NT, int cap = 1 << 20) {
-  int64_t b = (work + per - 1) / per;
-  if (b < 1) b = 1;
-  if (b > cap) b = cap;
-  return (int)b;
-}
 
 // =====================================================================
 // Orbital cell operator: acc += (K/2 + v + E mz + m gamma^-1 U) u
@@ -578,10 +557,11 @@ __global__ void __launch_bounds__(NT) k_mdot(DevMesh d, const double2* const* __
 // Finish the dots: pass 1 sets column k of H, pass 2 adds (re-orthogonalisation).
 __global__ void k_mdot_finish(const double* __restrict__ part, int nblk, int k, int m_max, int pass,
                               double2* __restrict__ H, double2* __restrict__ hcur, double* __restrict__ scal) {
+  __shared__ double lds4[4];
   const int nv = 2 * (k + 1) + 1;
-  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nv + v];
+  for (int v = 0; v < nv; ++v) {
+    const double s = sum_partials(part, nblk, nv, v, lds4);
+    if (threadIdx.x != 0) continue;
     if (v == nv - 1) {
       if (pass == 1) scal[2] = s;
       continue;
@@ -598,7 +578,7 @@ __global__ void k_mdot_finish(const double* __restrict__ part, int nblk, int k, 
 void launch_mdot(const DevMesh& d, double* const* V, int k, const double* w, Krylov& K, int pass, hipStream_t s) {
   hipLaunchKernelGGL(k_mdot, dim3(K.nblk), dim3(NT), 0, s, d, (const double2* const*)V, k, (const double2*)w,
                      pass == 1 ? 1 : 0, K.part);
-  hipLaunchKernelGGL(k_mdot_finish, dim3(1), dim3(64), 0, s, K.part, K.nblk, k, K.m_max, pass, (double2*)K.H,
+  hipLaunchKernelGGL(k_mdot_finish, dim3(1), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, pass, (double2*)K.H,
                      (double2*)K.hcur, K.scal);
 }
 
@@ -629,9 +609,9 @@ __global__ void __launch_bounds__(NT) k_orth_update(DevMesh d, const double2* co
 // h_{k+1,k} = |w|; happy breakdown when h <= 1e-14 |G v_k| (then scale 0).
 __global__ void k_norm_finish(const double* __restrict__ part, int nblk, int k, int m_max,
                               double2* __restrict__ H, double* __restrict__ scal) {
+  __shared__ double lds4[4];
+  const double s = sum_partials(part, nblk, 1, 0, lds4);
   if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[b];
   double h = sqrt(s);
   double wn = sqrt(scal[2]);
   H[(k + 1) + (int64_t)(m_max + 1) * k] = make_double2(h, 0.0);
@@ -647,7 +627,7 @@ void launch_orth_update(const DevMesh& d, double* const* V, int k, double* w, Kr
   hipLaunchKernelGGL(k_orth_update, dim3(K.nblk), dim3(NT), 0, s, d, (const double2* const*)V, k, (double2*)w,
                      (const double2*)K.hcur, pass == 2 ? 1 : 0, K.part);
   if (pass == 2)
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, K.part, K.nblk, k, K.m_max, (double2*)K.H, K.scal);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, (double2*)K.H, K.scal);
 }
 
 __global__ void k_scale_by(const double2* __restrict__ src, double2* __restrict__ dst, int64_t total,
@@ -679,9 +659,9 @@ __global__ void __launch_bounds__(NT) k_norm_part(DevMesh d, const double2* __re
 __global__ void k_beta_finish(const double* __restrict__ part, int nblk, int m, double* __restrict__ scal,
                               double2* __restrict__ H, int m_max) {
   for (int i = threadIdx.x; i < (m_max + 1) * m_max; i += blockDim.x) H[i] = make_double2(0.0, 0.0);
+  __shared__ double lds4[4];
+  const double s = sum_partials(part, nblk, 1, 0, lds4);
   if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[b];
   double beta = sqrt(s);
   scal[0] = beta;
   scal[5] = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -691,7 +671,7 @@ __global__ void k_beta_finish(const double* __restrict__ part, int nblk, int m, 
 
 void launch_norm_init(const DevMesh& d, const double* phi, Krylov& K, int m, hipStream_t s) {
   hipLaunchKernelGGL(k_norm_part, dim3(K.nblk), dim3(NT), 0, s, d, (const double2*)phi, K.part);
-  hipLaunchKernelGGL(k_beta_finish, dim3(1), dim3(64), 0, s, K.part, K.nblk, m, K.scal, (double2*)K.H, K.m_max);
+  hipLaunchKernelGGL(k_beta_finish, dim3(1), dim3(NT), 0, s, K.part, K.nblk, m, K.scal, (double2*)K.H, K.m_max);
 }
 
 // y = beta expm(A) e1, A = -i tau H_m (m = scal[4]); scaling and squaring
@@ -1157,7 +1137,7 @@ void launch_bnd_eval(const DevMesh& d, PoissonWs& P, double* W, hipStream_t s) {
 void launch_poisson_rhs_full(const DevMesh& d, const double* phi, double* W, const int* colinfo, double* rhs,
                              PoissonWs& P, hipStream_t s) {
   const int ncol = P.ncol;
-  launch_zero(P.acc + d.N * ncol, d.Nh * ncol, s);
+  launch_zero(P.acc, d.NE * ncol, s);  // the lift pass accumulates with atomics
   // boundary lift through the stiffness, then C^T and the density load
   launch_cell_poisson(d, W, P.acc, ncol, 1, s);
   int nb = col_blocks(d, ncol);
@@ -1169,7 +1149,7 @@ void launch_poisson_rhs_full(const DevMesh& d, const double* phi, double* W, con
 }
 
 // Operator apply q = K p (p DoF rows given; hanging rows filled here).
-static void cg_apply(const DevMesh& d, PoissonWs& P, double* pvec, double* qvec, hipStream_t s) {
+[[maybe_unused]] static void cg_apply_atomic(const DevMesh& d, PoissonWs& P, double* pvec, double* qvec, hipStream_t s) {
   const int ncol = P.ncol;
   launch_fill_real(d, pvec, ncol, 0, P.acc, s);
   const bool rec = P.ev && P.ev_used + 2 <= P.ev_cap;
@@ -1236,12 +1216,12 @@ __global__ void k_cg_start_finish(const double* __restrict__ part, int nblk, int
 }
 
 // Start: r = rhs - K x0 (warm) or rhs (cold, x0 = 0), p = z = D^-1 r.
-void launch_cg_start(const DevMesh& d, double* W, double* rhs_r, PoissonWs& P, int warm, hipStream_t s) {
+void launch_cg_start_atomic(const DevMesh& d, double* W, double* rhs_r, PoissonWs& P, int warm, hipStream_t s) {
   const int ncol = P.ncol;
   if (warm) {
     // q = K x0 using p as staging for x0 (DoF rows)
     hipLaunchKernelGGL(k_copy, dim3(nblocks(d.N * ncol, NT, 8192)), dim3(NT), 0, s, W, P.p, d.N * ncol);
-    cg_apply(d, P, P.p, P.q, s);
+    cg_apply_atomic(d, P, P.p, P.q, s);
   }
   hipLaunchKernelGGL(k_cg_start, dim3(nblocks(d.N * ncol, NT, 8192)), dim3(NT), 0, s, d, W, rhs_r, P.q, P.p, ncol,
                      warm);
@@ -1250,9 +1230,9 @@ void launch_cg_start(const DevMesh& d, double* W, double* rhs_r, PoissonWs& P, i
   hipLaunchKernelGGL(k_cg_start_finish, dim3(1), dim3(64), 0, s, P.part, nb, ncol, P.sc);
 }
 
-void launch_cg_step(const DevMesh& d, double* W, PoissonWs& P, hipStream_t s) {
+void launch_cg_step_atomic(const DevMesh& d, double* W, PoissonWs& P, hipStream_t s) {
   const int ncol = P.ncol;
-  cg_apply(d, P, P.p, P.q, s);
+  cg_apply_atomic(d, P, P.p, P.q, s);
   int nb = col_blocks(d, ncol);
   hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(NT), 0, s, d, W, P.r, P.p, P.q, ncol, P.sc, P.part);
   hipLaunchKernelGGL(k_cg_finish2, dim3(1), dim3(64), 0, s, P.part, nb, ncol, P.sc);

@@ -30,13 +30,30 @@ struct DevMesh {
   const double* ct_w = nullptr;
   const double* inv_mass = nullptr;     // [N] 1/m for non-masters
   const double* kdiag_inv = nullptr;    // [N]
+  const int32_t* node_inc = nullptr;    // [NE][8]: cell*64 + local index of each incident cell, -1 padded
+  const int32_t* kt_ptr = nullptr;      // assembled Poisson operator on DoFs (CSR)
+  const int32_t* kt_col = nullptr;
+  const double* kt_val = nullptr;
   const int32_t* bnd_cells = nullptr;
   int64_t n_bnd_cells = 0;
+  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; grid caps
+  int sched_orb = 1, sched_poi = 1, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights
 };
 
 // ---- orbital-space operator -------------------------------------------------
+// Node-centric operator (no atomics); diag_mode 0: K/2 only, 1: + v + E mz,
+// 2: + mean field.  mode 0: load vector F; 1: M^-1 F; 2: M^-1 F - v lam.
+// Non-master DoFs are final in out; masters and hanging nodes go to acc.
+void launch_stencil_orb(const DevMesh& d, const double* u, double E, int diag_mode, const double* Upk,
+                        const double* ginv, int mode, const double* lam, double* out, double* acc, hipStream_t s);
+// Masters: acc_k + sum_h c_hk acc_h -> out (mode 0) or the interface rhs ma_b.
+void launch_ma_gather_orb(const DevMesh& d, const double* acc, int mode, double* out, double* ma_b, hipStream_t s);
+void launch_mass_direct(const DevMesh& d, const double* f, double* out, double* ma_b, hipStream_t s);
+int launch_stencil_poisson(const DevMesh& d, const double* x, int ncol, double* q, double* acc, double* part,
+                           hipStream_t s);
+// Former scatter form (FP64 atomics), kept for the boundary-lift pass only.
 // acc[node] += (K/2 + diag) u; diag_mode 0: none, 1: v + E mz, 2: + mean field
 void launch_cell_orb(const DevMesh& d, const double* u, double* acc, double E, int diag_mode, const double* Upk,
                      const double* ginv, hipStream_t s);
@@ -91,6 +108,7 @@ struct PoissonWs {
   double* q = nullptr;     // [N][ncol]
   double* sc = nullptr;    // [8][ncol] scalars
   double* part = nullptr;  // partials
+  double* part2 = nullptr; // partials of the master gather
   double* Q = nullptr;     // moments [nharm][ncol]
   double* mpart = nullptr; // moment partials
   int mblk = 0;

@@ -1,0 +1,72 @@
+"""Autotuner for the launch schedules of the two operator kernels.
+
+Each candidate (sweep order, grid cap) is applied with ``Operator.tune`` and
+timed by the library's event-pair kernel timing on the caller's own inputs:
+the orbital operator through ``rhs_apply`` (the frozen operator must be set)
+and the Poisson operator through a warm-started ``poisson_pairs``.  The
+fastest candidate is kept.  Results are cached in memory (and optionally in
+a JSON file) per (mesh signature, degree, orbitals, device).
+"""
+import json
+import os
+
+ORB_CANDIDATES = [(s, g) for s in (1, 0) for g in (2048, 8192, 65536)]
+POI_CANDIDATES = [(s, g) for s in (1, 0) for g in (1024, 2048, 4096, 8192)]
+_CACHE = {}
+
+
+def _key(op):
+    import torch
+    info = op.mesh.info
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    return f"{info['n_cells']}-{info['n_dof']}-{info['n_hang']}-p{info['p']}-n{op.n_orb}-{dev}"
+
+
+def autotune(op, phi, W, reps=5, cache_file=None):
+    """Pick and apply the fastest schedule for both operator kernels.
+
+    phi: device orbitals [N_E][n] (consistent), W: device Poisson columns
+    [N_F][n^2] holding a converged (or good) solution for phi; mh_freeze must
+    have been called.  Returns {"orbital": (sched, grid), "poisson": (sched, grid),
+    "timings": {...}}.
+    """
+    import torch
+    key = _key(op)
+    if key not in _CACHE and cache_file and os.path.exists(cache_file):
+        with open(cache_file) as f:
+            _CACHE.update({k: {kk: tuple(vv) if isinstance(vv, list) else vv for kk, vv in v.items()}
+                           for k, v in json.load(f).items()})
+    if key in _CACHE:
+        best = _CACHE[key]
+        op.tune(0, *best["orbital"])
+        op.tune(1, *best["poisson"])
+        return best
+    out = torch.empty_like(phi)
+    times = {"orbital": {}, "poisson": {}}
+    for sched, grid in ORB_CANDIDATES:
+        op.tune(0, sched, grid)
+        op.rhs_apply(phi, out)
+        op.kernel_timing(0, True)
+        for _ in range(reps):
+            op.rhs_apply(phi, out)
+        times["orbital"][(sched, grid)] = op.kernel_timing(0, False)[0]
+    for sched, grid in POI_CANDIDATES:
+        op.tune(1, sched, grid)
+        op.kernel_timing(1, True)
+        op.poisson_pairs(phi, W, warm=True)
+        times["poisson"][(sched, grid)] = op.kernel_timing(1, False)[0]
+    best = {"orbital": min(times["orbital"], key=times["orbital"].get),
+            "poisson": min(times["poisson"], key=times["poisson"].get)}
+    op.tune(0, *best["orbital"])
+    op.tune(1, *best["poisson"])
+    best["timings_ms"] = {k: {f"{s}/{g}": v for (s, g), v in d.items()} for k, d in times.items()}
+    _CACHE[key] = best
+    if cache_file:
+        data = {}
+        if os.path.exists(cache_file):
+            with open(cache_file) as f:
+                data = json.load(f)
+        data[key] = {"orbital": list(best["orbital"]), "poisson": list(best["poisson"])}
+        with open(cache_file, "w") as f:
+            json.dump(data, f, indent=1)
+    return best
