@@ -55,8 +55,9 @@ def algorithmic_bytes(kind, info, op):
     P = info["p"] + 1
     nC, NE, N, n, ncol = info["n_cells"], op.n_ext, op.n_dof, op.n_orb, op.n_pair_cols
     meta = 32 * NE + 4 * P ** 3 * nC + 8 * nC + 4 * N          # node->cell table, cell maps, h/2, master index
-    if kind == "stencil_poisson":
-        return 16 * NE * ncol + meta
+    if kind == "poisson_spmv":
+        # x rows read and q rows written once; the assembled operator once (column int32 + value)
+        return 16 * N * ncol + 12 * op.n_poisson_nnz + 4 * (N + 1)
     return 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + meta   # u, out, U, (m, v, mz), 1/m
 
 
@@ -166,7 +167,7 @@ def main():
 
     evals = args.steps * m * op.n_dof * op.n_orb
     kern = {"stencil_orb": {"avg_ms": k_orb[0], "count": k_orb[1]},
-            "stencil_poisson": {"avg_ms": k_poi[0], "count": k_poi[1]}}
+            "poisson_spmv": {"avg_ms": k_poi[0], "count": k_poi[1]}}
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["count"])
     byts = algorithmic_bytes(dom, info, op)
     ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0

@@ -212,10 +212,34 @@ int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const doubl
                  int32_t n_steps, double dt, int32_t m, int32_t flags, mh_observables* obs,
                  void* stream);
 
+/* Exact discrete adjoint of mh_propagate's dipole record with respect to
+ * the field samples, for one orbital and one determinant (the one-electron
+ * case, where MCTDHF is the time-dependent Schroedinger equation and the
+ * frozen data reduce to a phase that cancels in the dipole; Sec. III.B
+ * frozen-operator exponential, first order).  Given g_n = dJ/dd_n for the
+ * record d_0..d_N of mh_propagate (real time, same phi0, Ci0, E_steps, dt,
+ * m), returns dJ/dE_k for k < N (E_N does not enter the dipoles).
+ * Backward recursion: nu_N = g_N M^-1 Z c_N, nu_k = exp(+i dt G_k) nu_{k+1}
+ * + g_k M^-1 Z c_k, with dJ/dE_k = 2 dt int_0^1 Im[a(s)^H Z b(s)] ds,
+ * a(s) = exp(+i (1-s) dt G_k) nu_{k+1}, b(s) = exp(-i s dt G_k) c_k
+ * (Frechet derivative of the exponential), the integral by n_quad-point
+ * Gauss-Legendre; every exponential is a short-iterative Arnoldi step.
+ * Orbitals are recomputed from checkpoints every ckpt_stride steps (<= 0:
+ * round(sqrt(N))).  phi0: device c128 [N_E][1]; Ci0: device c128 [1];
+ * W_work: device double [N_F][1] (overwritten); E_steps: host [N + 1];
+ * dJ_dd: host [N + 1]; dJ_dE: host out [N].  Allocates its checkpoint and
+ * work vectors per call.  MH_UNSUPPORTED for more than one orbital or
+ * determinant.  Synchronises `stream`. */
+int mh_propagate_adjoint(mh_op* op, const double* phi0, const double* Ci0, double* W_work,
+                         const double* E_steps, int32_t n_steps, double dt, int32_t m,
+                         const double* dJ_dd, double* dJ_dE, int32_t n_quad, int32_t ckpt_stride,
+                         void* stream);
+
 /* Sizes the caller needs to allocate device arrays. */
 typedef struct {
   int64_t n_dof, n_ext, n_full, n_ci;
   int32_t n_orb, n_pair_cols;
+  int64_t n_poisson_nnz;  /* entries of the assembled Poisson operator on the DoFs */
 } mh_op_sizes;
 int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sizes);
 
@@ -230,7 +254,9 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
 /* Launch schedule of an operator kernel, chosen by the autotuner.
  * which: 0 = orbital operator, 1 = Poisson operator.  sched bit 0: 1 =
  * XCD-contiguous sweep (XCD x of 8 owns a contiguous node range and its
- * workgroups walk it side by side), 0 = plain grid-stride sweep.
+ * workgroups walk it side by side), 0 = plain grid-stride sweep.  Poisson
+ * only, sched bit 1: column blocking (16 columns per XCD group) when the
+ * column count is 16, 32 or 64.
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
  * sums change order only). */

@@ -12,7 +12,8 @@ _NAMES = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP_ERROR", -4: "SINGULAR_RDM", -5:
 EXPORTS = ["mh_mesh_create", "mh_mesh_info_get", "mh_mesh_node_coords", "mh_mesh_constraints",
            "mh_mesh_destroy", "mh_op_create", "mh_op_destroy", "mh_fill_hanging", "mh_mass_solve",
            "mh_h1_apply", "mh_poisson_pairs", "mh_ci_rdms", "mh_freeze", "mh_rhs_apply",
-           "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_tune", "mh_last_error"]
+           "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_tune",
+           "mh_propagate_adjoint", "mh_last_error"]
 
 
 class MHError(RuntimeError):
@@ -51,7 +52,7 @@ class _Obs(C.Structure):
 
 class _Sizes(C.Structure):
     _fields_ = [("n_dof", C.c_int64), ("n_ext", C.c_int64), ("n_full", C.c_int64), ("n_ci", C.c_int64),
-                ("n_orb", C.c_int32), ("n_pair_cols", C.c_int32)]
+                ("n_orb", C.c_int32), ("n_pair_cols", C.c_int32), ("n_poisson_nnz", C.c_int64)]
 
 
 _lib = None
@@ -93,6 +94,8 @@ def load_library():
                                  C.POINTER(_Obs), vp]
     lib.mh_kernel_timing.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.mh_tune.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    lib.mh_propagate_adjoint.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_double, C.c_int32, vp, vp,
+                                         C.c_int32, C.c_int32, vp]
     for name in EXPORTS:
         if name != "mh_last_error":
             getattr(lib, name).restype = C.c_int
@@ -183,6 +186,7 @@ class Operator:
         _check(lib.mh_op_sizes_get(h, C.byref(sz)))
         self.n_dof, self.n_ext, self.n_full, self.n_ci = sz.n_dof, sz.n_ext, sz.n_full, sz.n_ci
         self.n_orb, self.n_pair_cols = sz.n_orb, sz.n_pair_cols
+        self.n_poisson_nnz = sz.n_poisson_nnz
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -272,3 +276,19 @@ class Operator:
     def tune(self, which, sched, grid_cap):
         """Select the launch schedule of operator kernel `which` (mh_tune)."""
         _check(_lib.mh_tune(self._h, int(which), int(sched), int(grid_cap)))
+
+    def propagate_adjoint(self, phi0, Ci0, W, E_steps, dt, dJ_dd, m=12, n_quad=6, ckpt_stride=0, stream=None):
+        """dJ/dE_k for the dipole record of propagate (mh_propagate_adjoint)."""
+        import torch
+        self._need(phi0, self.n_ext, self.n_orb, torch.complex128)
+        E = np.ascontiguousarray(E_steps, dtype=np.float64)
+        g = np.ascontiguousarray(dJ_dd, dtype=np.float64)
+        n_steps = len(E) - 1
+        if len(g) != n_steps + 1:
+            raise ValueError("dJ_dd must have one entry per dipole record")
+        out = np.zeros(n_steps)
+        _check(_lib.mh_propagate_adjoint(self._h, _ptr(phi0), _ptr(Ci0), _ptr(W), E.ctypes.data_as(C.c_void_p),
+                                         n_steps, float(dt), int(m), g.ctypes.data_as(C.c_void_p),
+                                         out.ctypes.data_as(C.c_void_p), int(n_quad), int(ckpt_stride),
+                                         _stream(stream)))
+        return out

@@ -426,6 +426,7 @@ extern "C" int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sz) {
   sz->n_ci = op->ci.dim;
   sz->n_orb = op->n;
   sz->n_pair_cols = op->ncol;
+  sz->n_poisson_nnz = (int64_t)op->H.kt_col.size();
   return MH_OK;
 }
 
@@ -734,7 +735,8 @@ extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double
 }
 
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || sched > 1) return fail(MH_INVALID_ARG, "bad schedule");
+  if (!op || which < 0 || which > 1 || sched < 0 || sched > (which == 1 ? 3 : 1))
+    return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");
   if (which == 0) {
@@ -745,4 +747,112 @@ extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap
     op->d.grid_poi = grid_cap;
   }
   return MH_OK;
+}
+
+// ------------------------------------------------------------------ adjoint ----
+// out = M^-1 Z u (dipole load vector through the mass solve), hanging rows filled
+static void mass_dipole(mh_op* op, const double* u, double* out, hipStream_t s) {
+  const DevMesh& d = op->d;
+  stencil_orb(op, u, 0.0, 3, 1, out, s);
+  launch_ma_gather_orb(d, op->acc, 1, out, op->ma_b, s);
+  launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
+                  op->H.cheb_iters, nullptr, nullptr, out, s);
+  launch_fill_orb(d, out, nullptr, s);
+}
+
+namespace {
+struct DevScratch {
+  std::vector<void*> p;
+  double* get(size_t nd) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(nd, 2) * sizeof(double)) != hipSuccess) throw std::bad_alloc();
+    p.push_back(q);
+    return (double*)q;
+  }
+  ~DevScratch() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+}  // namespace
+
+extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double* Ci0, double* W_work,
+                                    const double* E_steps, int32_t n_steps, double dt, int32_t m,
+                                    const double* dJ_dd, double* dJ_dE, int32_t n_quad, int32_t ckpt_stride,
+                                    void* stream) {
+  if (!op || !phi0 || !Ci0 || !W_work || !E_steps || !dJ_dd || !dJ_dE) return fail(MH_INVALID_ARG, "null argument");
+  if (op->n != 1 || op->ci.dim != 1)
+    return fail(MH_UNSUPPORTED, "the adjoint is implemented for one orbital and one determinant");
+  if (n_steps < 1 || m < 1 || m > 24 || n_quad < 1 || n_quad > 16) return fail(MH_INVALID_ARG, "bad sizes");
+  return guarded([&]() -> int {
+    hipStream_t s = S(stream);
+    const DevMesh& d = op->d;
+    const size_t len = (size_t)2 * d.NE * op->n;
+    const int S_ = ckpt_stride > 0 ? ckpt_stride : std::max(1, (int)std::lround(std::sqrt((double)n_steps)));
+    DevScratch mem;
+    const int nck = n_steps / S_ + 1;
+    std::vector<double*> ck(nck), seg(S_ + 1);
+    for (auto& v : ck) v = mem.get(len);
+    for (auto& v : seg) v = mem.get(len);
+    double* cur = mem.get(len);
+    double* nu = mem.get(len);
+    double* va = mem.get(len);
+    double* vb = mem.get(len);
+    double* tmp = mem.get(len);
+    double* zbuf = mem.get((size_t)2 * n_steps * n_quad);
+    // one orbital, one determinant: gamma = 1, Gamma = 0, so the mean field vanishes
+    launch_ci_rdm_full(op->ci, Ci0, op->gam, op->Gam, op->Gtmp, s);
+    launch_zero(W_work, d.NF * op->ncol, s);
+    auto step_forward = [&](double* c, int k) {
+      freeze(op, c, op->gam, op->Gam, E_steps[k], W_work, s);
+      arnoldi(op, c, dt, 0.0, m, s);
+    };
+    // forward sweep with checkpoints every S_ steps
+    launch_copy(phi0, cur, len, s);
+    for (int k = 0; k < n_steps; ++k) {
+      if (k % S_ == 0) launch_copy(cur, ck[k / S_], len, s);
+      step_forward(cur, k);
+    }
+    // nu_N = g_N M^-1 Z c_N
+    mass_dipole(op, cur, nu, s);
+    launch_axpby(len, 0.0, nu, dJ_dd[n_steps], nu, s);
+    // Gauss-Legendre nodes on [0, 1] for the Frechet integral of the exponential
+    std::vector<double> gx, gw;
+    gauss_legendre(n_quad, gx, gw);
+    for (int j = 0; j < n_quad; ++j) {
+      gx[j] = 0.5 * (gx[j] + 1.0);
+      gw[j] *= 0.5;
+    }
+    for (int s0 = ((n_steps - 1) / S_) * S_; s0 >= 0; s0 -= S_) {
+      const int s1 = std::min(s0 + S_, n_steps);
+      launch_copy(ck[s0 / S_], seg[0], len, s);
+      for (int k = s0; k + 1 < s1; ++k) {
+        launch_copy(seg[k - s0], seg[k - s0 + 1], len, s);
+        step_forward(seg[k - s0 + 1], k);
+      }
+      for (int k = s1 - 1; k >= s0; --k) {
+        double* ckk = seg[k - s0];
+        freeze(op, ckk, op->gam, op->Gam, E_steps[k], W_work, s);
+        for (int j = 0; j < n_quad; ++j) {
+          launch_copy(ckk, vb, len, s);
+          arnoldi(op, vb, gx[j] * dt, 0.0, m, s);          // b = exp(-i s dt G) c_k
+          launch_copy(nu, va, len, s);
+          arnoldi(op, va, -(1.0 - gx[j]) * dt, 0.0, m, s);  // a = exp(+i (1-s) dt G) nu_{k+1}
+          launch_gram(va, vb, d.mz, d.NE, 1, op->gpart, gram_blocks(d.NE),
+                      zbuf + 2 * ((size_t)k * n_quad + j), s);
+        }
+        arnoldi(op, nu, -dt, 0.0, m, s);                    // nu <- exp(+i dt G) nu
+        mass_dipole(op, ckk, tmp, s);
+        launch_axpby(len, dJ_dd[k], tmp, 1.0, nu, s);      // nu += g_k M^-1 Z c_k
+      }
+    }
+    std::vector<double> z((size_t)2 * n_steps * n_quad);
+    HIPCHK(hipMemcpyAsync(z.data(), zbuf, z.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < n_steps; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < n_quad; ++j) acc += gw[j] * z[2 * ((size_t)k * n_quad + j) + 1];
+      dJ_dE[k] = 2.0 * dt * acc;  // 2 Re[-i dt sum_j w_j a_j^H Z b_j]
+    }
+    return MH_OK;
+  });
 }

@@ -321,7 +321,80 @@ std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ba
           tmp_nodes[(e * P + c) * P * P + b * P + a] = id;
         }
   }
-  const int64_t nF = (int64_t)keys.size();
+  int64_t nF = (int64_t)keys.size();
+
+  // ---- breadth-first cell order (Cuthill-McKee on cells sharing a node) -------
+  // Starting from the first Morton cell (a box corner), cells are visited
+  // level set by level set, and nodes are renumbered by first touch in that
+  // order.  Every line neighbour of a node then lies within about one level
+  // set of it in index space, so operator passes that walk the nodes in order
+  // reuse each row from cache instead of re-fetching it (Morton order makes
+  // long jumps between octants).
+  {
+    const int P3 = P * P * P;
+    std::vector<int64_t> cptr(nF + 1, 0), cidx((size_t)nC * P3);
+    for (int64_t t = 0; t < nC * P3; ++t) cptr[tmp_nodes[t] + 1]++;
+    for (int64_t v = 0; v < nF; ++v) cptr[v + 1] += cptr[v];
+    {
+      std::vector<int64_t> fillp(cptr.begin(), cptr.end() - 1);
+      for (int64_t e = 0; e < nC; ++e)
+        for (int t = 0; t < P3; ++t) cidx[fillp[tmp_nodes[e * P3 + t]]++] = e;
+    }
+    std::vector<int64_t> order;
+    order.reserve(nC);
+    std::vector<char> seen(nC, 0);
+    for (int64_t s0 = 0; s0 < nC; ++s0) {
+      if (seen[s0]) continue;
+      seen[s0] = 1;
+      size_t head = order.size();
+      order.push_back(s0);
+      while (head < order.size()) {
+        const int64_t e = order[head++];
+        for (int t = 0; t < P3; ++t) {
+          const int64_t v = tmp_nodes[e * P3 + t];
+          for (int64_t k = cptr[v]; k < cptr[v + 1]; ++k) {
+            const int64_t f = cidx[k];
+            if (!seen[f]) {
+              seen[f] = 1;
+              order.push_back(f);
+            }
+          }
+        }
+      }
+    }
+    // permute cells and renumber nodes by first touch in the new order
+    std::vector<int32_t> lvl(nC);
+    std::vector<int64_t> ijk(3 * nC);
+    std::vector<double> ch(nC), co(3 * nC);
+    std::vector<int64_t> newid(nF, -1), tn2(tmp_nodes.size());
+    std::vector<Key3> keys2(nF);
+    int64_t next = 0;
+    for (int64_t e2 = 0; e2 < nC; ++e2) {
+      const int64_t e = order[e2];
+      lvl[e2] = M.cell_level[e];
+      ch[e2] = M.cell_h[e];
+      for (int d = 0; d < 3; ++d) {
+        ijk[3 * e2 + d] = M.cell_ijk[3 * e + d];
+        co[3 * e2 + d] = M.cell_org[3 * e + d];
+      }
+      for (int t = 0; t < P3; ++t) {
+        const int64_t v = tmp_nodes[e * P3 + t];
+        if (newid[v] < 0) {
+          newid[v] = next;
+          keys2[next] = keys[v];
+          ++next;
+        }
+        tn2[e2 * P3 + t] = newid[v];
+      }
+    }
+    M.cell_level.swap(lvl);
+    M.cell_ijk.swap(ijk);
+    M.cell_h.swap(ch);
+    M.cell_org.swap(co);
+    tmp_nodes.swap(tn2);
+    keys.swap(keys2);
+    nF = next;
+  }
 
   // ---- classification --------------------------------------------------------
   std::unordered_map<uint64_t, int64_t> leaf_id;

@@ -66,6 +66,7 @@ void launch_ma_solve(const DevMesh& d, const double* ma_b, double* x, double* r,
                      hipStream_t s);
 void launch_fill_orb(const DevMesh& d, double* x, double* acc, hipStream_t s);
 void launch_copy(const double* in, double* out, int64_t nd, hipStream_t s);
+void launch_axpby(int64_t nd, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_zero(double* out, int64_t nd, hipStream_t s);
 
 // ---- reductions ----------------------------------------------------------------

@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(DevMesh d, const double2* __
       if (act) ui = u[i * n + p];
       // the node's 8 incidence codes in two 16-byte loads (row of 32 bytes)
       const int4* inc4 = reinterpret_cast<const int4*>(d.node_inc + i * 8);
-      const int4 ca = inc4[0], cb = inc4[1];
+      int4 ca = inc4[0], cb = inc4[1];
+      if (diag_mode == 3) ca = cb = make_int4(-1, -1, -1, -1);  // dipole weights only: no stiffness
       const int codes[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(DevMesh d, const double2* __
         y.y += f0 * s0.y + f1 * s1.y + f2 * s2.y;
       }
       if (diag_mode >= 1 && act) {
-        const double dg = d.v[i] + E * d.mz[i];
+        const double dg = diag_mode == 3 ? d.mz[i] : d.v[i] + E * d.mz[i];
         y.x += dg * ui.x;
         y.y += dg * ui.y;
       }
@@ -364,9 +365,92 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson_v(DevMesh d, const double* 
   }
 }
 
+// Column-blocked form (ncol a multiple of 16, at most 4 blocks): the 8 XCDs
+// are split evenly over the 16-column blocks and each XCD sweeps a
+// contiguous share of the rows for its block only.  A row slice is then
+// 128 B, so the band of neighbour rows one XCD touches fits its L2; the
+// matrix is read once per column block.
+__global__ void __launch_bounds__(NT) k_spmv_poisson_cb(DevMesh d, const double* __restrict__ x, int ncol,
+                                                        double* __restrict__ q, double* __restrict__ part) {
+  constexpr int L = 4, V = 4, CB = 16;
+  __shared__ double lds[NT * V];
+  const int nblk_c = ncol / CB;
+  const int gpx = N_XCD / nblk_c;                 // XCDs per column block
+  const int xcd = blockIdx.x % N_XCD, lb = blockIdx.x / N_XCD, nbx = gridDim.x / N_XCD;
+  const int cblk = xcd / gpx, sub = xcd % gpx;
+  const int64_t R = (d.N + gpx - 1) / gpx;
+  const int64_t r0 = sub * R, r1 = (sub + 1) * R < d.N ? (sub + 1) * R : d.N;
+  const int lane = (int)(threadIdx.x & (L - 1));
+  const int c0 = cblk * CB + lane * V;
+  double pq[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) pq[v] = 0.0;
+  for (int64_t i = r0 + (int64_t)lb * (NT / L) + threadIdx.x / L; i < r1; i += (int64_t)nbx * (NT / L)) {
+    const int beg = d.kt_ptr[i], end = d.kt_ptr[i + 1];
+    double y[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) y[v] = 0.0;
+    int t = beg;
+    for (; t + 4 <= end; t += 4) {
+      double2 xv[4][2];
+      double av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = d.kt_col[t + u];
+        av[u] = d.kt_val[t + u];
+        const double2* row = reinterpret_cast<const double2*>(x + j * ncol + c0);
+        xv[u][0] = row[0];
+        xv[u][1] = row[1];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        y[0] += av[u] * xv[u][0].x;
+        y[1] += av[u] * xv[u][0].y;
+        y[2] += av[u] * xv[u][1].x;
+        y[3] += av[u] * xv[u][1].y;
+      }
+    }
+    for (; t < end; ++t) {
+      const double a = d.kt_val[t];
+      const double2* row = reinterpret_cast<const double2*>(x + (int64_t)d.kt_col[t] * ncol + c0);
+      const double2 r0v = row[0], r1v = row[1];
+      y[0] += a * r0v.x;
+      y[1] += a * r0v.y;
+      y[2] += a * r1v.x;
+      y[3] += a * r1v.y;
+    }
+    double2* qo = reinterpret_cast<double2*>(q + i * ncol + c0);
+    const double2* xo = reinterpret_cast<const double2*>(x + i * ncol + c0);
+    qo[0] = make_double2(y[0], y[1]);
+    qo[1] = make_double2(y[2], y[3]);
+    const double2 xa = xo[0], xb = xo[1];
+    pq[0] += y[0] * xa.x;
+    pq[1] += y[1] * xa.y;
+    pq[2] += y[2] * xb.x;
+    pq[3] += y[3] * xb.y;
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) lds[v * NT + threadIdx.x] = pq[v];
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += NT) {
+    double s = 0.0;
+    const int cc = c - cblk * CB;
+    if (cc >= 0 && cc < CB) {
+      const int cl = cc / V, cv = cc % V;
+      for (int g = 0; g < NT / L; ++g) s += lds[cv * NT + g * L + cl];
+    }
+    part[(int64_t)blockIdx.x * ncol + c] = s;
+  }
+}
+
 template <int L, int V>
 static int launch_spmv_poisson_v(const DevMesh& d, const double* x, int ncol, double* q, double* part,
                                  hipStream_t s) {
+  if ((d.sched_poi & 2) && ncol % 16 == 0 && (ncol == 16 || ncol == 32 || ncol == 64)) {
+    const int grid = xcd_grid(d.N * (ncol / 16), NT / 4, d.grid_poi);
+    hipLaunchKernelGGL(k_spmv_poisson_cb, dim3(grid), dim3(NT), 0, s, d, x, ncol, q, part);
+    return grid;
+  }
   const int grid = xcd_grid(d.N, NT / L, d.grid_poi);
   hipLaunchKernelGGL((k_spmv_poisson_v<L, V>), dim3(grid), dim3(NT), 0, s, d, x, ncol, q, part);
   return grid;
@@ -603,4 +687,16 @@ void launch_cg_step(const DevMesh& d, double* W, PoissonWs& P, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_p2, dim3(nblocks(d.N * ncol, NT, 8192)), dim3(NT), 0, s, d, P.r, P.p, ncol, P.sc);
 }
 
+}  // namespace mh
+
+namespace mh {
+// y = a x + b y over nd doubles (a, b real)
+__global__ void __launch_bounds__(NT) k_axpby(int64_t nd, double a, const double* __restrict__ x, double b,
+                                              double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nd; i += (int64_t)gridDim.x * NT)
+    y[i] = a * x[i] + b * y[i];
+}
+void launch_axpby(int64_t nd, double a, const double* x, double b, double* y, hipStream_t s) {
+  if (nd > 0) hipLaunchKernelGGL(k_axpby, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, nd, a, x, b, y);
+}
 }  // namespace mh

@@ -11,7 +11,7 @@ import json
 import os
 
 ORB_CANDIDATES = [(s, g) for s in (1, 0) for g in (2048, 8192, 65536)]
-POI_CANDIDATES = [(s, g) for s in (1, 0) for g in (1024, 2048, 4096, 8192)]
+POI_CANDIDATES = [(s, g) for s in (3, 2, 1, 0) for g in (2048, 4096, 8192)]
 _CACHE = {}
 
 
