@@ -12,6 +12,10 @@ Default workload: H2, Q3 elements, box [-30,30]^3, 12^3 coarse cells, three
 levels in 1.5-bohr balls at z = +-0.7 (66,635 DoF), 2 orbitals, 4
 determinants, sin^2 800 nm pulse of peak 0.0534 au, dt = 0.02, Krylov 12.
 `--workload h2o` runs the 1,517,876-DoF CAS(10e,8o) H2O mesh.
+`--workload h2x64` runs 64 H2 instances of uneven meshes (bond ~ U[1,2],
+refinement depth in {2,3,4}, E0 ~ U[0.02,0.06], seeded) as one batch in the
+same kernel launches, and times 64 sequential single-instance runs of the
+same instances on a bounded sample for the batched/sequential ratio.
 """
 import argparse
 import json
@@ -23,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def _workload(name):
@@ -102,7 +110,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="h2", choices=["h2", "h2o", "h_atom"])
+    ap.add_argument("--workload", default="h2", choices=["h2", "h2o", "h_atom", "h2x64"])
+    ap.add_argument("--batch", type=int, default=64, help="instances of the h2x64 workload")
+    ap.add_argument("--seq-steps", type=int, default=2, help="timed steps per instance of the sequential runs")
+    ap.add_argument("--graph", action="store_true", help="replay each step's fixed part as a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -110,6 +121,8 @@ def main():
         print("this build runs on one GPU only: the whole mesh lives on one MI355X; "
               "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "h2x64":
+        return run_batch(args)
     import numpy as np
     import torch
     import paper_2301_02387_amd as mh
@@ -140,7 +153,7 @@ def main():
     op.kernel_timing(1, True)
     torch.cuda.synchronize()
     t_a = time.perf_counter()
-    rec = op.propagate(phi, Ci, W, E, dt, m=m, final=False)
+    rec = op.propagate(phi, Ci, W, E, dt, m=m, final=False, graph=args.graph)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_a
     k_orb = op.kernel_timing(0, False)
@@ -200,6 +213,123 @@ def main():
     }
     if not args.no_cpu_baseline and args.workload == "h2":
         line["cpu_baseline"] = cpu_baseline(args.workload, w, args.cpu_budget)
+    print(json.dumps(line))
+
+
+def run_batch(args):
+    """64 uneven H2 instances in one batch against 64 sequential plain runs."""
+    import numpy as np
+    import torch
+    import paper_2301_02387_amd as mh
+    from synth import batch_instances, h2_guess, h2_ci_guess, pulse
+    from paper_2301_02387_amd.tune import autotune
+
+    ws = batch_instances(args.batch, seed=2301)
+    w0 = ws[0]
+    t_setup = time.perf_counter()
+    meshes = [mh.Mesh.from_workload(w) for w in ws]
+    op = mh.Operator.batch(meshes, [w["nuclei"] for w in ws], w0["n_orb"], w0["n_alpha"], w0["n_beta"],
+                           field_scale=[w["E0"] for w in ws], poisson_rtol=1e-12, poisson_maxit=20000)
+    t_setup = time.perf_counter() - t_setup
+    lay = op.layout()
+    log(f"batch of {op.n_inst} set up in {t_setup:.1f} s: {op.n_dof} DoF in total")
+
+    def guess(i, mesh):
+        xyz = mesh.coords()[:lay[i, 1]]
+        half = abs(ws[i]["nuclei"][0][1][2])
+        return h2_guess(xyz, half)
+
+    phi = torch.from_numpy(np.ascontiguousarray(np.concatenate([guess(i, m) for i, m in enumerate(meshes)]))).cuda()
+    op.fill_hanging(phi)
+    Ci = torch.from_numpy(np.stack([h2_ci_guess()] * op.n_inst)).cuda()
+    W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
+    dt, m, cycles = w0["dt"], w0["krylov"], w0["cycles"]
+    Tp = cycles * 2 * np.pi / 0.0569542
+    if args.warmup > 0:
+        op.propagate(phi, Ci, W, [0.0] * (args.warmup + 1), 0.05, m=m, imaginary=True, final=False)
+    t0 = Tp / 2
+    shape = [float(pulse(t0 + k * dt, 1.0, cycles)) for k in range(args.steps + 1)]
+    op.propagate(phi, Ci, W, shape[:2], dt, m=m, final=False)
+    sched = autotune(op, phi, W)
+    log(f"warm-up and tuning done: {sched['orbital']} {sched['poisson']}")
+    op.kernel_timing(0, True)
+    op.kernel_timing(1, True)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    rec = op.propagate(phi, Ci, W, shape, dt, m=m, final=False, graph=args.graph)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_a
+    k_orb = op.kernel_timing(0, False)
+    k_poi = op.kernel_timing(1, False)
+    log(f"batched: {wall / args.steps * 1e3:.1f} ms per step")
+    # sequential baseline: each instance alone (plain operator, default schedule),
+    # from this batch's current state, `seq_steps` timed steps after one untimed step
+    seq_step_s = 0.0
+    seq_iters = []
+    ph_all = phi.clone()
+    C_all = Ci.clone()
+    for i, mesh in enumerate(meshes):
+        w = ws[i]
+        one = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_rtol=1e-12,
+                          poisson_maxit=20000)
+        a, b = lay[i, 3], lay[i, 3] + lay[i, 1]
+        ph = ph_all[a:b].clone()
+        C1 = C_all[i:i + 1].clone()
+        W1 = torch.zeros((one.n_full, one.n_pair_cols), dtype=torch.float64, device="cuda")
+        Ei = [w["E0"] * v for v in shape[:args.seq_steps + 2]]
+        one.propagate(ph, C1, W1, Ei[:2], dt, m=m, final=False)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        r1 = one.propagate(ph, C1, W1, Ei[1:args.seq_steps + 2], dt, m=m, final=False)
+        torch.cuda.synchronize()
+        seq_step_s += (time.perf_counter() - ts) / args.seq_steps
+        seq_iters.append(float(np.mean(r1["cg_iters"][:args.seq_steps])))
+        del one
+        if i % 8 == 7:
+            log(f"sequential: {i + 1} instances, {seq_step_s * 1e3:.1f} ms per step so far")
+    evals = args.steps * m * op.n_dof * op.n_orb
+    n_cells = sum(mm.info["n_cells"] for mm in meshes)
+    ncol = op.n_pair_cols
+    spmv_bytes = 16 * op.n_dof * ncol + 12 * op.n_poisson_nnz + 4 * (op.n_dof + op.n_inst)
+    P3 = (w0["p"] + 1) ** 3
+    NE, N, n = op.n_ext, op.n_dof, op.n_orb
+    orb_bytes = 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + 32 * NE + 4 * P3 * n_cells + 8 * n_cells + 4 * N
+    kern = {"stencil_orb": {"avg_ms": k_orb[0], "count": k_orb[1], "algorithmic_bytes": orb_bytes},
+            "poisson_spmv": {"avg_ms": k_poi[0], "count": k_poi[1], "algorithmic_bytes": spmv_bytes}}
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["count"])
+    byts = kern[dom]["algorithmic_bytes"]
+    ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0
+    ms_step = wall / args.steps * 1e3
+    line = {
+        "metric": "orbital-RHS evals/s (DoF x orbitals/s)",
+        "value": evals / wall,
+        "unit": "DoF*orbitals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"h2x{op.n_inst}_q3_{op.n_dof}dof_{op.n_orb}orb", "n_inst": op.n_inst,
+                   "n_dof_total": op.n_dof, "n_dof_min": int(lay[:, 0].min()), "n_dof_max": int(lay[:, 0].max()),
+                   "n_cells_total": n_cells, "krylov": m, "dt": dt, "graph": bool(args.graph),
+                   "parallelism": "none (one GPU, batch of instances)"},
+        "batched_vs_sequential": seq_step_s * 1e3 / ms_step,
+        "sequential_ms_per_step": seq_step_s * 1e3,
+        "sequential_sample": f"each of the {op.n_inst} instances alone, {args.seq_steps} timed step(s) after one "
+                             f"untimed step, default schedules",
+        "poisson_cg_iters_per_step": float(np.mean(rec["cg_iters"][:args.steps])),
+        "sequential_cg_iters_per_step_mean": float(np.mean(seq_iters)),
+        "setup_s": t_setup,
+        "schedule": {"orbital": list(sched["orbital"]), "poisson": list(sched["poisson"]),
+                     "tuning_ms": sched.get("timings_ms")},
+        "kernels": kern,
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byts},
+    }
     print(json.dumps(line))
 
 

@@ -30,6 +30,17 @@
  *    Handles (mh_mesh, mh_op) are owned by the library and freed by their
  *    destroy call.  Internal device workspaces are allocated by the library
  *    at mh_op_create.
+ *  - Batches: an operator handle holds one or more independent instances
+ *    (mh_op_create: one; mh_batch_create: several meshes and molecules of
+ *    one orbital/electron space).  Every call then acts on all instances at
+ *    once (one kernel launch covers them all).  A batch array is the
+ *    per-instance arrays laid end to end: instance i owns rows
+ *    [oE_i, oE_i + N_E,i) of every array over extended rows (orbitals, load
+ *    vectors) and rows [oF_i, oF_i + N_F,i) of every array over full rows
+ *    (pair potentials W); mh_batch_layout gives the offsets.  Small
+ *    per-instance arrays (CI vectors, RDMs) are [n_inst][...].  Arrays
+ *    documented below as [N][n] hold, for a batch, [sum N_E][n] with the
+ *    extended-row offsets.  For a single instance every offset is 0.
  *  - Streams: every device call is enqueued on the hipStream_t given as
  *    `stream` (NULL = the default stream) and returns without synchronising,
  *    except where a call returns host results (noted per call), which
@@ -184,13 +195,14 @@ int mh_rhs_apply(mh_op* op, const double* v, double* Gv, void* stream);
 int mh_arnoldi_step(mh_op* op, double* phi, double tau_re, double tau_im, int32_t m,
                     double* err_est, int32_t* m_used, void* stream);
 
-/* Per-step observables written by mh_propagate, host arrays [n_steps + 1]. */
+/* Per-step observables written by mh_propagate, host arrays [n_steps + 1]
+ * (dipole, energy, err_est, ortho: [n_steps + 1][n_inst], instance fastest). */
 typedef struct {
   double* dipole;     /* sum_pq gamma_pq <phi_p|e.r|phi_q> */
   double* energy;     /* sum h gamma + 1/2 sum g Gamma + nuclear repulsion */
   double* err_est;    /* Arnoldi error estimate (0 for the final record) */
   double* ortho;      /* max |S - I|, S_pq = <phi_p|phi_q> */
-  int32_t* cg_iters;  /* Poisson CG iterations */
+  int32_t* cg_iters;  /* Poisson CG iterations (all instances iterate together) */
 } mh_observables;
 
 /* Propagate orbitals and CI vector together for n_steps steps of size dt
@@ -202,12 +214,18 @@ typedef struct {
  * then Gram-Schmidt orthonormalised in M and C normalised after every step.
  * MH_PROP_NO_FINAL: skip the final freeze at t_N (records [0, n_steps) only),
  * so that n_steps calls of one step do exactly n_steps freezes.
- * phi: device c128 [N_E][n] in-out; Ci: device c128 [N_CI] in-out;
+ * MH_PROP_GRAPH: capture the fixed launch sequence of a step that follows
+ * the Poisson solve (freeze, integrals, observables, Arnoldi and CI steps)
+ * once as a HIP graph on a stream of the library and replay it every step;
+ * the Poisson CG, whose length depends on the data, stays eager.  Results
+ * are those of the eager path.
+ * phi: device c128 [N_E][n] in-out; Ci: device c128 [n_inst][N_CI] in-out;
  * E_steps: host double [n_steps + 1] (the last value is used for the final
- * record).  obs: host arrays (any member may be NULL).  W_work: device double
- * [N_F][n*n] Poisson warm-start buffer (in-out, may hold zeros).
+ * record); instance i sees the field E0_i E_steps[k] (E0 = 1 for
+ * mh_op_create).  obs: host arrays (any member may be NULL).  W_work: device
+ * double [N_F][n*n] Poisson warm-start buffer (in-out, may hold zeros).
  * Synchronises `stream`. */
-enum { MH_PROP_IMAGINARY = 1, MH_PROP_NO_FINAL = 2 };
+enum { MH_PROP_IMAGINARY = 1, MH_PROP_NO_FINAL = 2, MH_PROP_GRAPH = 4 };
 int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const double* E_steps,
                  int32_t n_steps, double dt, int32_t m, int32_t flags, mh_observables* obs,
                  void* stream);
@@ -228,7 +246,8 @@ int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const doubl
  * round(sqrt(N))).  phi0: device c128 [N_E][1]; Ci0: device c128 [1];
  * W_work: device double [N_F][1] (overwritten); E_steps: host [N + 1];
  * dJ_dd: host [N + 1]; dJ_dE: host out [N].  Allocates its checkpoint and
- * work vectors per call.  MH_UNSUPPORTED for more than one orbital or
+ * work vectors per call.  MH_UNSUPPORTED for a batch of several instances,
+ * or for more than one orbital or
  * determinant.  Synchronises `stream`. */
 int mh_propagate_adjoint(mh_op* op, const double* phi0, const double* Ci0, double* W_work,
                          const double* E_steps, int32_t n_steps, double dt, int32_t m,
@@ -240,15 +259,36 @@ typedef struct {
   int64_t n_dof, n_ext, n_full, n_ci;
   int32_t n_orb, n_pair_cols;
   int64_t n_poisson_nnz;  /* entries of the assembled Poisson operator on the DoFs */
+  int32_t n_inst;         /* instances in the handle (sizes above are batch totals) */
 } mh_op_sizes;
 int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sizes);
+
+/* Batch of independent instances sharing n_orb, n_alpha, n_beta, lmax_bc
+ * and p (the many-molecule workload: one mesh and molecule per instance,
+ * uneven sizes allowed).  meshes[i], descs[i]: as for mh_op_create;
+ * field_scale: host [n_inst] (may be NULL = all 1): instance i sees the
+ * field E0_i E.  Poisson tolerances and the RDM regularisation come from
+ * descs[0].  The host set-up of the instances runs on several threads.
+ * Every later call acts on all instances in the same kernel launches;
+ * reductions are segmented per instance, and the CG, Arnoldi and Lanczos
+ * scalars are per instance, so each instance evolves as it would alone
+ * (up to the Chebyshev count of the interface mass solve, taken as the
+ * largest over the batch, and the Poisson CG, which iterates until every
+ * instance has converged).  Synchronises `stream`. */
+int mh_batch_create(const mh_mesh* const* meshes, const mh_op_desc* descs, const double* field_scale,
+                    int32_t n_inst, void* stream, mh_op** out);
+
+/* Batch layout, host int64 [n_inst][6]: N, N_E, N_F, oE, oF, nnz of the
+ * instance's assembled Poisson operator. */
+int mh_batch_layout(const mh_op* op, int64_t* layout);
 
 /* Timing hook for measurement: average duration (ms) of an operator kernel
  * over its launches since the last call, from HIP event pairs recorded on
  * the launch stream around each launch (no synchronisation while
  * recording; at most 4096 launches are recorded).  which: 0 = orbital
  * operator kernel (one-body + mean field), 1 = Poisson operator kernel.
- * enable: keep recording after this call.  Synchronises the device. */
+ * enable: keep recording after this call.  Launches inside a captured
+ * graph are not recorded.  Synchronises the device. */
 int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, int64_t* count);
 
 /* Launch schedule of an operator kernel, chosen by the autotuner.

@@ -13,7 +13,7 @@ EXPORTS = ["mh_mesh_create", "mh_mesh_info_get", "mh_mesh_node_coords", "mh_mesh
            "mh_mesh_destroy", "mh_op_create", "mh_op_destroy", "mh_fill_hanging", "mh_mass_solve",
            "mh_h1_apply", "mh_poisson_pairs", "mh_ci_rdms", "mh_freeze", "mh_rhs_apply",
            "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_tune",
-           "mh_propagate_adjoint", "mh_last_error"]
+           "mh_propagate_adjoint", "mh_batch_create", "mh_batch_layout", "mh_last_error"]
 
 
 class MHError(RuntimeError):
@@ -52,7 +52,8 @@ class _Obs(C.Structure):
 
 class _Sizes(C.Structure):
     _fields_ = [("n_dof", C.c_int64), ("n_ext", C.c_int64), ("n_full", C.c_int64), ("n_ci", C.c_int64),
-                ("n_orb", C.c_int32), ("n_pair_cols", C.c_int32), ("n_poisson_nnz", C.c_int64)]
+                ("n_orb", C.c_int32), ("n_pair_cols", C.c_int32), ("n_poisson_nnz", C.c_int64),
+                ("n_inst", C.c_int32)]
 
 
 _lib = None
@@ -70,6 +71,11 @@ def load_library():
     path = lib_path()
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2301_02387_amd.build`")
+    # PyTorch carries its own HIP runtime (soname libamdhip64.so.7).  Loading
+    # torch first makes libmh.so bind to that same runtime, so that torch's
+    # device pointers and streams are valid in the library; loading libmh.so
+    # first would bring a second runtime into the process.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp = C.c_void_p
     lib.mh_last_error.restype = C.c_char_p
@@ -96,6 +102,8 @@ def load_library():
     lib.mh_tune.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     lib.mh_propagate_adjoint.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_double, C.c_int32, vp, vp,
                                          C.c_int32, C.c_int32, vp]
+    lib.mh_batch_create.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(vp)]
+    lib.mh_batch_layout.argtypes = [vp, vp]
     for name in EXPORTS:
         if name != "mh_last_error":
             getattr(lib, name).restype = C.c_int
@@ -165,28 +173,70 @@ class Mesh:
             self._h = None
 
 
+def _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit, rdm_eps):
+    Z = np.array([z for z, _ in nuclei], dtype=np.float64)
+    R = np.ascontiguousarray(np.array([r for _, r in nuclei], dtype=np.float64).reshape(-1, 3))
+    desc = _OpDesc(len(nuclei), Z.ctypes.data_as(C.POINTER(C.c_double)), R.ctypes.data_as(C.POINTER(C.c_double)),
+                   int(n_orb), int(n_alpha), int(n_beta), (C.c_double * 3)(*polarization), int(lmax_bc),
+                   float(poisson_rtol), int(poisson_maxit), float(rdm_eps))
+    return desc, (Z, R)
+
+
 class Operator:
     """Operator set-up and device entry points (see include/mh.h)."""
 
     def __init__(self, mesh, nuclei, n_orb, n_alpha, n_beta, polarization=(0.0, 0.0, 1.0), lmax_bc=12,
                  poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, stream=None):
         lib = load_library()
-        Z = np.array([z for z, _ in nuclei], dtype=np.float64)
-        R = np.array([r for _, r in nuclei], dtype=np.float64).reshape(-1, 3)
-        self._keep = (Z, R)
-        desc = _OpDesc(len(nuclei), Z.ctypes.data_as(C.POINTER(C.c_double)),
-                       R.ctypes.data_as(C.POINTER(C.c_double)), int(n_orb), int(n_alpha), int(n_beta),
-                       (C.c_double * 3)(*polarization), int(lmax_bc), float(poisson_rtol), int(poisson_maxit),
-                       float(rdm_eps))
+        desc, keep = _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol,
+                              poisson_maxit, rdm_eps)
         h = C.c_void_p()
         _check(lib.mh_op_create(mesh._h, C.byref(desc), _stream(stream), C.byref(h)))
+        self._attach(h, [mesh])
+
+    @classmethod
+    def batch(cls, meshes, nuclei_list, n_orb, n_alpha, n_beta, field_scale=None, polarization=(0.0, 0.0, 1.0),
+              lmax_bc=12, poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, stream=None):
+        """Batch of independent instances (mh_batch_create): one mesh and one
+        molecule per instance, one shared orbital/electron space."""
+        lib = load_library()
+        ni = len(meshes)
+        if len(nuclei_list) != ni:
+            raise ValueError("one nuclei list per mesh")
+        descs = (_OpDesc * ni)()
+        keep = []
+        for i, nuc in enumerate(nuclei_list):
+            d, k = _op_desc(nuc, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit,
+                            rdm_eps)
+            descs[i] = d
+            keep.append(k)
+        hs = (C.c_void_p * ni)(*[m._h.value for m in meshes])
+        fs = np.ascontiguousarray(np.ones(ni) if field_scale is None else field_scale, dtype=np.float64)
+        if fs.shape != (ni,):
+            raise ValueError("field_scale must have one entry per instance")
+        h = C.c_void_p()
+        _check(lib.mh_batch_create(C.cast(hs, C.c_void_p), C.cast(descs, C.c_void_p),
+                                   fs.ctypes.data_as(C.c_void_p), ni, _stream(stream), C.byref(h)))
+        self = cls.__new__(cls)
+        self._attach(h, list(meshes))
+        return self
+
+    def _attach(self, h, meshes):
         self._h = h
-        self.mesh = mesh
+        self.meshes = meshes
+        self.mesh = meshes[0]
         sz = _Sizes()
-        _check(lib.mh_op_sizes_get(h, C.byref(sz)))
+        _check(_lib.mh_op_sizes_get(h, C.byref(sz)))
         self.n_dof, self.n_ext, self.n_full, self.n_ci = sz.n_dof, sz.n_ext, sz.n_full, sz.n_ci
         self.n_orb, self.n_pair_cols = sz.n_orb, sz.n_pair_cols
         self.n_poisson_nnz = sz.n_poisson_nnz
+        self.n_inst = sz.n_inst
+
+    def layout(self):
+        """Per instance: N, N_E, N_F, oE, oF, Poisson nnz (mh_batch_layout)."""
+        out = np.zeros((self.n_inst, 6), dtype=np.int64)
+        _check(_lib.mh_batch_layout(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -215,7 +265,7 @@ class Operator:
     def h1_apply(self, c, E, f, stream=None):
         import torch
         self._need(c, self.n_ext, self.n_orb, torch.complex128)
-        self._need(f, self.n_dof, self.n_orb, torch.complex128)
+        self._need(f, self.n_dof if self.n_inst == 1 else self.n_ext, self.n_orb, torch.complex128)
         _check(_lib.mh_h1_apply(self._h, _ptr(c), float(E), _ptr(f), _stream(stream)))
 
     def poisson_pairs(self, phi, W, warm=False, stream=None):
@@ -249,20 +299,24 @@ class Operator:
                                     _stream(stream)))
         return err.value, mu.value
 
-    def propagate(self, phi, Ci, W, E_steps, dt, m=12, imaginary=False, final=True, stream=None):
+    def propagate(self, phi, Ci, W, E_steps, dt, m=12, imaginary=False, final=True, graph=False, stream=None):
+        """Records are [n_steps + 1] for one instance, [n_steps + 1][n_inst] for a batch."""
         import torch
         self._need(phi, self.n_ext, self.n_orb, torch.complex128)
         self._need(W, self.n_full, self.n_pair_cols, torch.float64)
+        self._need(Ci, self.n_inst, self.n_ci, torch.complex128)
         E = np.ascontiguousarray(E_steps, dtype=np.float64)
         n_steps = len(E) - 1
-        rec = {k: np.zeros(n_steps + 1) for k in ("dipole", "energy", "err_est", "ortho")}
+        shape = (n_steps + 1,) if self.n_inst == 1 else (n_steps + 1, self.n_inst)
+        rec = {k: np.zeros(shape) for k in ("dipole", "energy", "err_est", "ortho")}
         rec["cg_iters"] = np.zeros(n_steps + 1, dtype=np.int32)
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
         obs = _Obs(dp(rec["dipole"]), dp(rec["energy"]), dp(rec["err_est"]), dp(rec["ortho"]),
                    rec["cg_iters"].ctypes.data_as(C.POINTER(C.c_int32)))
         rc = _check(_lib.mh_propagate(self._h, _ptr(phi), _ptr(Ci), _ptr(W), E.ctypes.data_as(C.c_void_p),
                                       n_steps, float(dt), int(m),
-                                      (1 if imaginary else 0) | (0 if final else 2), C.byref(obs),
+                                      (1 if imaginary else 0) | (0 if final else 2) | (4 if graph else 0),
+                                      C.byref(obs),
                                       _stream(stream)), allow_nc=True)
         rec["status"] = rc
         return rec

@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmh.so")
 SOURCES = ["host_mesh.cpp", "host_setup.cpp", "kernels.hip", "stencil.hip", "api.hip"]
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
+    "-O3", "-std=c++17", "-fPIC", "-pthread", "--offload-arch=gfx950", "-munsafe-fp-atomics",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

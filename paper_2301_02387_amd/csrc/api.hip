@@ -1,5 +1,7 @@
 // C ABI of the hot path: handles, device memory, and the orchestration of
-// the kernels for each entry point declared in include/mh.h.
+// the kernels for each entry point declared in include/mh.h.  An operator
+// handle holds a batch of instances (a plain operator is a batch of one);
+// every kernel launch covers all of them (kernels.hpp).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +10,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mh.h"
@@ -19,6 +22,7 @@ using namespace mh;
 namespace {
 
 thread_local std::string g_err;
+thread_local std::string g_alloc_detail;  // what the last failed allocation asked for
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -36,11 +40,6 @@ struct HipError {
     if (_e != hipSuccess) throw HipError{_e, #x};  \
   } while (0)
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
 }  // namespace
 
 struct mh_mesh {
@@ -48,30 +47,31 @@ struct mh_mesh {
 };
 
 struct mh_op {
-  Mesh M;
-  OpHost H;
-  DevMesh d;
+  int ni = 1;                  // instances
+  std::vector<Mesh> Ms;        // per instance
+  std::vector<OpHost> Hs;
+  std::vector<DevMesh> dh;     // host copies of the device instance records
+  DevMesh* dm = nullptr;       // device [ni]
+  Batch B;
   std::vector<void*> allocs;
   int n = 0, ncol = 0, lmax = 12;
-  double rtol = 1e-12, rdm_eps = 1e-10, vnn = 0.0;
+  double rtol = 1e-12, rdm_eps = 1e-10;
   int maxit = 5000;
   // device data
-  double* xyz = nullptr;
   int* colinfo = nullptr;  // per real Poisson column: r | s<<8 | part<<16
   int* colmap = nullptr;   // [n*n]: first column of pair (r<=s)
-  // orbital workspaces
-  double* acc = nullptr;    // [NE][n] c128
-  double* Upk = nullptr;    // [NE][n*n]
-  double* ginv = nullptr;   // [n][n] c128
-  double* lam = nullptr;    // [n][n] c128
-  double* F = nullptr;      // [N][n] c128
-  double* ma_b = nullptr, *ma_x = nullptr, *ma_r = nullptr, *ma_d0 = nullptr, *ma_d1 = nullptr;
+  double* Ebuf = nullptr;  // [2]: field value of the frozen operator, field value of a load-vector call
+  // orbital workspaces (batch arrays over extended rows, or [ni][...] small blocks)
+  double* acc = nullptr;    // [tE][n] c128
+  double* Upk = nullptr;    // [tE][n*n]
+  double* ginv = nullptr;   // [ni][n][n] c128
+  double* lam = nullptr;    // [ni][n][n] c128
+  double* F = nullptr;      // [tE][n] c128
+  double* ma_b = nullptr, *ma_x = nullptr, *ma_r = nullptr, *ma_d0 = nullptr, *ma_d1 = nullptr;  // [tMa][n]
   double* gpart = nullptr;  // reduction partials
-  int gblk = 0;
-  double* Mr = nullptr;     // [n^2][n^2]
-  double* Gtmp = nullptr;   // [n^2][n^2] c128
-  int* flag = nullptr;
-  double E = 0.0;
+  double* Mr = nullptr;     // [ni][n^2][n^2]
+  double* Gtmp = nullptr;   // [ni][n^2][n^2] c128
+  int* flag = nullptr;      // [ni]
   bool frozen = false;
   // Krylov
   int m_alloc = 0;
@@ -87,9 +87,11 @@ struct mh_op {
   double** Qdev = nullptr;
   Krylov KC;
   double* gam = nullptr, *Gam = nullptr, *hmat = nullptr, *gint = nullptr, *S = nullptr, *zmat = nullptr;
-  double* obs = nullptr;    // [4]
+  double* obs = nullptr;    // [ni][8]
   double* Rinv = nullptr;
   double* hostpin = nullptr;
+  size_t hostpin_len = 0;
+  hipStream_t gstream = nullptr;  // stream for graph capture and replay
   // timing of the dominant kernels: pools of event pairs recorded on the
   // launch stream around each launch (no synchronisation while recording)
   std::vector<hipEvent_t> ev[2];
@@ -100,7 +102,11 @@ struct mh_op {
   T* alloc(size_t count) {
     void* p = nullptr;
     size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-    if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      g_alloc_detail = "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e);
+      throw std::bad_alloc();
+    }
     allocs.push_back(p);
     return (T*)p;
   }
@@ -115,6 +121,7 @@ struct mh_op {
     for (int k = 0; k < 2; ++k)
       for (hipEvent_t e : ev[k]) (void)hipEventDestroy(e);
     if (hostpin) (void)hipHostFree(hostpin);
+    if (gstream) (void)hipStreamDestroy(gstream);
   }
 };
 
@@ -127,7 +134,9 @@ static int guarded(F&& f) {
   } catch (const HipError& e) {
     return fail(MH_HIP_ERROR, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what);
   } catch (const std::bad_alloc&) {
-    return fail(MH_OOM, "device or host allocation failed");
+    std::string d = g_alloc_detail;
+    g_alloc_detail.clear();
+    return fail(MH_OOM, "device or host allocation failed" + (d.empty() ? std::string() : ": " + d));
   } catch (const std::exception& e) {
     return fail(MH_INVALID_ARG, e.what());
   } catch (...) {
@@ -233,75 +242,134 @@ static std::vector<int32_t> excitation_table(int n, const std::vector<uint32_t>&
 }
 
 static void krylov_alloc(mh_op* op, Krylov& K, int m_max, int nblk) {
+  const size_t ni = op->ni;
   K.m_max = m_max;
-  K.H = op->alloc<double>(2 * (m_max + 1) * m_max);
-  K.hcur = op->alloc<double>(2 * (m_max + 1));
-  K.scal = op->alloc<double>(8);
-  K.y = op->alloc<double>(2 * m_max);
+  K.H = op->alloc<double>(ni * 2 * (m_max + 1) * m_max);
+  K.hcur = op->alloc<double>(ni * 2 * (m_max + 1));
+  K.scal = op->alloc<double>(ni * 8);
+  K.y = op->alloc<double>(ni * 2 * m_max);
   K.nblk = nblk;
-  K.part = op->alloc<double>((size_t)nblk * (2 * (m_max + 1) + 1) + 64);
+  K.part = op->alloc<double>(ni * (size_t)nblk * (2 * (m_max + 1) + 1) + 64);
 }
 
-extern "C" int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* stream, mh_op** out) {
-  if (!mesh || !desc || !out) return fail(MH_INVALID_ARG, "null argument");
-  if (desc->n_orb < 1 || desc->n_orb > 8) return fail(MH_UNSUPPORTED, "n_orb must be 1..8");
-  if (desc->n_alpha < 0 || desc->n_beta < 0 || desc->n_alpha > desc->n_orb || desc->n_beta > desc->n_orb ||
-      desc->n_alpha + desc->n_beta < 1)
-    return fail(MH_INVALID_ARG, "electron counts");
-  if (desc->n_nuclei < 0 || (desc->n_nuclei > 0 && (!desc->charges || !desc->positions)))
-    return fail(MH_INVALID_ARG, "nuclei");
-  int lmax = desc->lmax_bc > 0 ? desc->lmax_bc : 12;
-  if (lmax > 12) return fail(MH_UNSUPPORTED, "lmax_bc must be <= 12");
-  const int n = desc->n_orb, ncol = n * n;
-  if ((lmax + 1) * (lmax + 1) * ncol > 48 * 256) return fail(MH_UNSUPPORTED, "multipole table too large");
-  return guarded([&]() -> int {
-    hipStream_t s = S(stream);
-    auto op = std::make_unique<mh_op>();
-    op->M = mesh->M;
-    const Mesh& M = op->M;
-    std::vector<Nucleus> nuc;
-    for (int i = 0; i < desc->n_nuclei; ++i) {
-      Nucleus a;
-      a.Z = desc->charges[i];
-      for (int d = 0; d < 3; ++d) a.R[d] = desc->positions[3 * i + d];
-      nuc.push_back(a);
-    }
-    double vnn = 0.0;
-    for (size_t a = 0; a < nuc.size(); ++a)
-      for (size_t b = a + 1; b < nuc.size(); ++b) {
-        double dx = nuc[a].R[0] - nuc[b].R[0], dy = nuc[a].R[1] - nuc[b].R[1], dz = nuc[a].R[2] - nuc[b].R[2];
-        vnn += nuc[a].Z * nuc[b].Z / std::sqrt(dx * dx + dy * dy + dz * dz);
-      }
-    op->vnn = vnn;
-    double pol[3] = {desc->polarization[0], desc->polarization[1], desc->polarization[2]};
-    build_operator(M, nuc, pol, lmax, op->H);
-    const OpHost& H = op->H;
-    op->n = n;
-    op->ncol = ncol;
-    op->lmax = lmax;
-    op->rtol = desc->poisson_rtol > 0 ? desc->poisson_rtol : 1e-12;
-    op->maxit = desc->poisson_maxit > 0 ? desc->poisson_maxit : 5000;
-    op->rdm_eps = desc->rdm_eps > 0 ? desc->rdm_eps : 1e-10;
-    const int64_t NE = M.N + M.Nh;
+// Per-instance Chebyshev coefficients for `iters` iterations from that
+// instance's spectrum bounds: 1/theta, then (rho_{k+1} rho_k, 2 rho_{k+1}/delta).
+static std::vector<double> cheb_table(double lo, double hi, int iters, bool used) {
+  std::vector<double> t(1 + 2 * (size_t)iters, 0.0);
+  if (!used) return t;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  t[0] = 1.0 / theta;
+  double rho = 1.0 / sigma;
+  for (int k = 0; k < iters; ++k) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    t[1 + 2 * k] = rho1 * rho;
+    t[2 + 2 * k] = 2.0 * rho1 / delta;
+    rho = rho1;
+  }
+  return t;
+}
 
-    DevMesh& d = op->d;
+struct InstanceSpec {
+  const Mesh* mesh;
+  std::vector<Nucleus> nuc;
+  double pol[3];
+  double E0;
+};
+
+static double nuclear_repulsion(const std::vector<Nucleus>& nuc) {
+  double vnn = 0.0;
+  for (size_t a = 0; a < nuc.size(); ++a)
+    for (size_t b = a + 1; b < nuc.size(); ++b) {
+      double dx = nuc[a].R[0] - nuc[b].R[0], dy = nuc[a].R[1] - nuc[b].R[1], dz = nuc[a].R[2] - nuc[b].R[2];
+      vnn += nuc[a].Z * nuc[b].Z / std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  return vnn;
+}
+
+static void upload_instances(mh_op* op, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(op->dm, op->dh.data(), op->dh.size() * sizeof(DevMesh), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  op->B.mx.sched_orb = op->dh[0].sched_orb;
+  op->B.mx.sched_poi = op->dh[0].sched_poi;
+  op->B.mx.grid_orb = op->dh[0].grid_orb;
+  op->B.mx.grid_poi = op->dh[0].grid_poi;
+}
+
+// Build the host operators of all instances (in parallel), upload them and
+// allocate the batch workspaces.
+static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_desc& desc, hipStream_t s) {
+  const int ni = (int)spec.size();
+  const int n = desc.n_orb, ncol = n * n;
+  const int lmax = desc.lmax_bc > 0 ? desc.lmax_bc : 12;
+  // Bring up the HIP runtime (device discovery and its address reservations)
+  // before the set-up threads start.
+  HIPCHK(hipFree(nullptr));
+  auto op = std::make_unique<mh_op>();
+  op->ni = ni;
+  op->Ms.resize(ni);
+  op->Hs.resize(ni);
+  {
+    const int nthr = std::max(1, std::min<int>(ni, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::vector<std::thread> pool;
+    std::vector<std::string> errs(nthr);
+    for (int t = 0; t < nthr; ++t)
+      pool.emplace_back([&, t]() {
+        try {
+          for (int i = t; i < ni; i += nthr) {
+            op->Ms[i] = *spec[i].mesh;
+            build_operator(op->Ms[i], spec[i].nuc, spec[i].pol, lmax, op->Hs[i]);
+          }
+        } catch (const std::exception& e) {
+          errs[t] = e.what();
+        }
+      });
+    for (auto& th : pool) th.join();
+    for (auto& e : errs)
+      if (!e.empty()) throw std::runtime_error(e);
+  }
+  op->n = n;
+  op->ncol = ncol;
+  op->lmax = lmax;
+  op->rtol = desc.poisson_rtol > 0 ? desc.poisson_rtol : 1e-12;
+  op->maxit = desc.poisson_maxit > 0 ? desc.poisson_maxit : 5000;
+  op->rdm_eps = desc.rdm_eps > 0 ? desc.rdm_eps : 1e-10;
+  Batch& B = op->B;
+  B.ni = ni;
+  int iters = 0;
+  for (int i = 0; i < ni; ++i)
+    if (!op->Ms[i].masters.empty()) iters = std::max(iters, op->Hs[i].cheb_iters);
+  B.cheb_iters = iters;
+  op->dh.resize(ni);
+  DevMesh& mx = B.mx;
+  int64_t oE = 0, oF = 0, oMa = 0;
+  for (int i = 0; i < ni; ++i) {
+    const Mesh& M = op->Ms[i];
+    const OpHost& H = op->Hs[i];
+    DevMesh& d = op->dh[i];
     d.P = M.P;
     d.n = n;
+    d.inst = i;
     d.nC = M.n_cells;
     d.N = M.N;
-    d.NE = NE;
+    d.NE = M.N + M.Nh;
     d.NF = M.nF;
     d.Nh = M.Nh;
     d.Nb = M.Nb;
     d.nMa = (int64_t)M.masters.size();
+    d.oE = oE;
+    d.oF = oF;
+    d.oMa = oMa;
+    oE += d.NE;
+    oF += d.NF;
+    oMa += d.nMa;
     d.cell_nodes = op->upload(M.cell_nodes, s);
     std::vector<double> hh(M.n_cells);
     for (int64_t e = 0; e < M.n_cells; ++e) hh[e] = 0.5 * M.cell_h[e];
     d.cell_hh = op->upload(hh, s);
-    d.owner = op->upload(H.owner_mask, s);
     d.m = op->upload(H.m, s);
     d.v = op->upload(H.v, s);
     d.mz = op->upload(H.mz, s);
+    d.xyz = op->upload(M.xyz, s);
     std::vector<int32_t> hp(M.hang_ptr.begin(), M.hang_ptr.end()), hc(M.hang_col.begin(), M.hang_col.end());
     d.hang_ptr = op->upload(hp, s);
     d.hang_col = op->upload(hc, s);
@@ -312,6 +380,7 @@ extern "C" int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* s
     d.ma_col = op->upload(H.ma_col, s);
     d.ma_val = op->upload(H.ma_val, s);
     d.ma_dinv = op->upload(H.ma_dinv, s);
+    d.cheb = op->upload(cheb_table(H.cheb_lo, H.cheb_hi, iters, d.nMa > 0), s);
     d.ct_ptr = op->upload(H.ct_ptr, s);
     d.ct_row = op->upload(H.ct_row, s);
     d.ct_w = op->upload(H.ct_w, s);
@@ -323,92 +392,173 @@ extern "C" int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* s
     d.kt_val = op->upload(H.kt_val, s);
     d.bnd_cells = op->upload(H.bnd_cells, s);
     d.n_bnd_cells = (int64_t)H.bnd_cells.size();
-    for (int i = 0; i < 16; ++i) d.A[i] = 0.0;
-    for (int i = 0; i < 4; ++i) d.w[i] = 0.0;
+    d.bnd_table = op->upload(H.bnd_table, s);
+    for (int k = 0; k < 3; ++k) d.center[k] = 0.5 * (M.lo + M.hi);
+    d.E0 = spec[i].E0;
+    d.vnn = nuclear_repulsion(spec[i].nuc);
+    for (int k = 0; k < 16; ++k) d.A[k] = 0.0;
+    for (int k = 0; k < 4; ++k) d.w[k] = 0.0;
     for (int a = 0; a < M.P; ++a) {
       d.w[a] = M.gll.w[a];
       for (int b = 0; b < M.P; ++b) d.A[a * M.P + b] = M.gll.A[a * M.P + b];
     }
-    op->xyz = op->upload(M.xyz, s);
-    // Poisson column layout
-    std::vector<int> colinfo, colmap(n * n, -1);
-    for (int r = 0; r < n; ++r)
-      for (int q = r; q < n; ++q) {
-        colmap[r * n + q] = (int)colinfo.size();
-        colinfo.push_back(r | (q << 8));
-        if (q != r) colinfo.push_back(r | (q << 8) | (1 << 16));
-      }
-    op->colinfo = op->upload(colinfo, s);
-    op->colmap = op->upload(colmap, s);
-    // orbital workspaces
-    op->acc = op->alloc<double>((size_t)2 * NE * n);
-    HIPCHK(hipMemsetAsync(op->acc, 0, (size_t)2 * NE * n * sizeof(double), s));
-    op->Upk = op->alloc<double>((size_t)NE * n * n);
-    op->ginv = op->alloc<double>(2 * n * n);
-    op->lam = op->alloc<double>(2 * n * n);
-    op->F = op->alloc<double>((size_t)2 * M.N * n);
-    size_t nma = std::max<size_t>(1, M.masters.size());
-    op->ma_b = op->alloc<double>(2 * nma * n);
-    op->ma_x = op->alloc<double>(2 * nma * n);
-    op->ma_r = op->alloc<double>(2 * nma * n);
-    op->ma_d0 = op->alloc<double>(2 * nma * n);
-    op->ma_d1 = op->alloc<double>(2 * nma * n);
-    op->gblk = std::max(gram_blocks(NE), gint_blocks(d));
-    op->gpart = op->alloc<double>((size_t)op->gblk * 2 * 4096 + 64);
-    op->Mr = op->alloc<double>(ncol * ncol);
-    op->Gtmp = op->alloc<double>(2 * ncol * ncol);
-    op->flag = op->alloc<int>(4);
-    op->gam = op->alloc<double>(2 * n * n);
-    op->Gam = op->alloc<double>(2 * ncol * ncol);
-    op->hmat = op->alloc<double>(2 * n * n);
-    op->gint = op->alloc<double>(2 * ncol * ncol);
-    op->S = op->alloc<double>(2 * n * n);
-    op->zmat = op->alloc<double>(2 * n * n);
-    op->obs = op->alloc<double>(8);
-    op->Rinv = op->alloc<double>(2 * n * n);
-    HIPCHK(hipHostMalloc((void**)&op->hostpin, 4096 * sizeof(double), hipHostMallocDefault));
-    // Poisson workspaces
-    PoissonWs& P = op->P;
-    P.ncol = ncol;
-    P.lmax = lmax;
-    P.nharm = (lmax + 1) * (lmax + 1);
-    P.acc = op->alloc<double>((size_t)NE * ncol);
-    HIPCHK(hipMemsetAsync(P.acc, 0, (size_t)NE * ncol * sizeof(double), s));
-    P.p = op->alloc<double>((size_t)NE * ncol);
-    HIPCHK(hipMemsetAsync(P.p, 0, (size_t)NE * ncol * sizeof(double), s));
-    P.r = op->alloc<double>((size_t)M.N * ncol);
-    P.q = op->alloc<double>((size_t)M.N * ncol);
-    P.sc = op->alloc<double>(8 * ncol);
-    P.part = op->alloc<double>((size_t)8192 * 2 * ncol);
-    P.part2 = op->alloc<double>((size_t)4096 * ncol);
-    P.Q = op->alloc<double>((size_t)P.nharm * ncol);
-    P.mblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (NE + 31) / 32));
-    P.mpart = op->alloc<double>((size_t)P.mblk * P.nharm * ncol);
-    P.table = op->upload(H.bnd_table, s);
-    P.center = 0.5 * (M.lo + M.hi);
-    // CI space
-    op->na = desc->n_alpha;
-    op->nb = desc->n_beta;
-    auto sa = make_strings(n, desc->n_alpha), sb = make_strings(n, desc->n_beta);
-    CIDev& c = op->ci;
-    c.n = n;
-    c.NA = (int)sa.size();
-    c.NB = (int)sb.size();
-    c.dim = c.NA * c.NB;
-    c.exa = op->upload(excitation_table(n, sa), s);
-    c.exb = op->upload(excitation_table(n, sb), s);
-    c.D = op->alloc<double>((size_t)2 * c.dim * ncol);
-    c.T = op->alloc<double>((size_t)2 * c.dim * ncol);
-    c.hp = op->alloc<double>(2 * ncol);
-    c.w = op->alloc<double>((size_t)2 * c.dim);
-    c.part = op->alloc<double>((size_t)gram_blocks(c.dim) * 2 * 4096 + 64);
-    int mci = std::min(12, c.dim);
-    for (int j = 0; j <= mci; ++j) op->Qh.push_back(op->alloc<double>((size_t)2 * c.dim));
-    op->Qdev = op->alloc<double*>(op->Qh.size());
-    HIPCHK(hipMemcpyAsync(op->Qdev, op->Qh.data(), op->Qh.size() * sizeof(double*), hipMemcpyHostToDevice, s));
-    krylov_alloc(op.get(), op->KC, 12, 1);
-    HIPCHK(hipStreamSynchronize(s));
-    *out = op.release();
+    if (i == 0) mx = d;
+    mx.nC = std::max(mx.nC, d.nC);
+    mx.N = std::max(mx.N, d.N);
+    mx.NE = std::max(mx.NE, d.NE);
+    mx.NF = std::max(mx.NF, d.NF);
+    mx.Nh = std::max(mx.Nh, d.Nh);
+    mx.Nb = std::max(mx.Nb, d.Nb);
+    mx.nMa = std::max(mx.nMa, d.nMa);
+    mx.n_bnd_cells = std::max(mx.n_bnd_cells, d.n_bnd_cells);
+    if (d.P != mx.P) throw std::runtime_error("all instances of a batch must use the same degree p");
+  }
+  B.tE = oE;
+  B.tF = oF;
+  B.tMa = oMa;
+  op->dm = op->alloc<DevMesh>(ni);
+  B.dm = op->dm;
+  upload_instances(op.get(), s);
+  // Poisson column layout
+  std::vector<int> colinfo, colmap(n * n, -1);
+  for (int r = 0; r < n; ++r)
+    for (int q = r; q < n; ++q) {
+      colmap[r * n + q] = (int)colinfo.size();
+      colinfo.push_back(r | (q << 8));
+      if (q != r) colinfo.push_back(r | (q << 8) | (1 << 16));
+    }
+  op->colinfo = op->upload(colinfo, s);
+  op->colmap = op->upload(colmap, s);
+  op->Ebuf = op->alloc<double>(2);
+  launch_zero(op->Ebuf, 2, s);
+  // orbital workspaces
+  const size_t tE = B.tE, nn = (size_t)n * n, n4 = nn * nn;
+  op->acc = op->alloc<double>(2 * tE * n);
+  launch_zero(op->acc, 2 * tE * n, s);
+  op->Upk = op->alloc<double>(tE * nn);
+  op->ginv = op->alloc<double>(ni * 2 * nn);
+  op->lam = op->alloc<double>(ni * 2 * nn);
+  op->F = op->alloc<double>(2 * tE * n);
+  const size_t nma = std::max<size_t>(1, B.tMa);
+  op->ma_b = op->alloc<double>(2 * nma * n);
+  op->ma_x = op->alloc<double>(2 * nma * n);
+  op->ma_r = op->alloc<double>(2 * nma * n);
+  op->ma_d0 = op->alloc<double>(2 * nma * n);
+  op->ma_d1 = op->alloc<double>(2 * nma * n);
+  const int gblk = std::max(gram_blocks(mx.NE), gint_blocks(B));
+  op->gpart = op->alloc<double>((size_t)ni * gblk * 2 * std::max(nn, n4) + 64);
+  op->Mr = op->alloc<double>(ni * n4);
+  op->Gtmp = op->alloc<double>(ni * 2 * n4);
+  op->flag = op->alloc<int>(ni);
+  op->gam = op->alloc<double>(ni * 2 * nn);
+  op->Gam = op->alloc<double>(ni * 2 * n4);
+  op->hmat = op->alloc<double>(ni * 2 * nn);
+  op->gint = op->alloc<double>(ni * 2 * n4);
+  op->S = op->alloc<double>(ni * 2 * nn);
+  op->zmat = op->alloc<double>(ni * 2 * nn);
+  op->obs = op->alloc<double>(ni * 8);
+  op->Rinv = op->alloc<double>(ni * 2 * nn);
+  op->hostpin_len = (size_t)ni * std::max(8 * ncol, 64) + 4096;
+  HIPCHK(hipHostMalloc((void**)&op->hostpin, op->hostpin_len * sizeof(double), hipHostMallocDefault));
+  // Poisson workspaces
+  PoissonWs& P = op->P;
+  P.ncol = ncol;
+  P.lmax = lmax;
+  P.nharm = (lmax + 1) * (lmax + 1);
+  P.acc = op->alloc<double>(tE * ncol);
+  launch_zero(P.acc, tE * ncol, s);
+  P.p = op->alloc<double>(tE * ncol);
+  launch_zero(P.p, tE * ncol, s);
+  P.r = op->alloc<double>(tE * ncol);
+  P.q = op->alloc<double>(tE * ncol);
+  P.sc = op->alloc<double>((size_t)ni * 8 * ncol);
+  P.part_stride = (int64_t)8192 * 2 * ncol;
+  P.part = op->alloc<double>((size_t)ni * P.part_stride);
+  P.Q = op->alloc<double>((size_t)ni * P.nharm * ncol);
+  P.mblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (mx.NE + 31) / 32));
+  P.mpart = op->alloc<double>((size_t)ni * P.mblk * P.nharm * ncol);
+  // CI space
+  op->na = desc.n_alpha;
+  op->nb = desc.n_beta;
+  auto sa = make_strings(n, desc.n_alpha), sb = make_strings(n, desc.n_beta);
+  CIDev& c = op->ci;
+  c.n = n;
+  c.NA = (int)sa.size();
+  c.NB = (int)sb.size();
+  c.dim = c.NA * c.NB;
+  c.exa = op->upload(excitation_table(n, sa), s);
+  c.exb = op->upload(excitation_table(n, sb), s);
+  c.D = op->alloc<double>((size_t)ni * 2 * c.dim * ncol);
+  c.T = op->alloc<double>((size_t)ni * 2 * c.dim * ncol);
+  c.hp = op->alloc<double>((size_t)ni * 2 * ncol);
+  c.w = op->alloc<double>((size_t)ni * 2 * c.dim);
+  c.part = op->alloc<double>((size_t)ni * gram_blocks(c.dim) * 2 * 4096 + 64);
+  int mci = std::min(12, c.dim);
+  for (int j = 0; j <= mci; ++j) op->Qh.push_back(op->alloc<double>((size_t)ni * 2 * c.dim));
+  op->Qdev = op->alloc<double*>(op->Qh.size());
+  HIPCHK(hipMemcpyAsync(op->Qdev, op->Qh.data(), op->Qh.size() * sizeof(double*), hipMemcpyHostToDevice, s));
+  krylov_alloc(op.get(), op->KC, 12, 1);
+  HIPCHK(hipStreamSynchronize(s));
+  return op.release();
+}
+
+static int check_desc(const mh_op_desc* desc) {
+  if (desc->n_orb < 1 || desc->n_orb > 8) return fail(MH_UNSUPPORTED, "n_orb must be 1..8");
+  if (desc->n_alpha < 0 || desc->n_beta < 0 || desc->n_alpha > desc->n_orb || desc->n_beta > desc->n_orb ||
+      desc->n_alpha + desc->n_beta < 1)
+    return fail(MH_INVALID_ARG, "electron counts");
+  if (desc->n_nuclei < 0 || (desc->n_nuclei > 0 && (!desc->charges || !desc->positions)))
+    return fail(MH_INVALID_ARG, "nuclei");
+  const int lmax = desc->lmax_bc > 0 ? desc->lmax_bc : 12;
+  if (lmax > 12) return fail(MH_UNSUPPORTED, "lmax_bc must be <= 12");
+  if ((lmax + 1) * (lmax + 1) * desc->n_orb * desc->n_orb > 48 * 256)
+    return fail(MH_UNSUPPORTED, "multipole table too large");
+  return MH_OK;
+}
+
+static InstanceSpec make_spec(const mh_mesh* mesh, const mh_op_desc* desc, double E0) {
+  InstanceSpec sp;
+  sp.mesh = &mesh->M;
+  for (int i = 0; i < desc->n_nuclei; ++i) {
+    Nucleus a;
+    a.Z = desc->charges[i];
+    for (int k = 0; k < 3; ++k) a.R[k] = desc->positions[3 * i + k];
+    sp.nuc.push_back(a);
+  }
+  for (int k = 0; k < 3; ++k) sp.pol[k] = desc->polarization[k];
+  sp.E0 = E0;
+  return sp;
+}
+
+extern "C" int mh_op_create(const mh_mesh* mesh, const mh_op_desc* desc, void* stream, mh_op** out) {
+  if (!mesh || !desc || !out) return fail(MH_INVALID_ARG, "null argument");
+  int rc = check_desc(desc);
+  if (rc != MH_OK) return rc;
+  return guarded([&]() -> int {
+    std::vector<InstanceSpec> spec{make_spec(mesh, desc, 1.0)};
+    *out = create_batch(spec, *desc, S(stream));
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_batch_create(const mh_mesh* const* meshes, const mh_op_desc* descs, const double* field_scale,
+                               int32_t n_inst, void* stream, mh_op** out) {
+  if (!meshes || !descs || !out || n_inst < 1) return fail(MH_INVALID_ARG, "null argument or empty batch");
+  if (n_inst > 4096) return fail(MH_UNSUPPORTED, "at most 4096 instances per batch");
+  for (int i = 0; i < n_inst; ++i) {
+    if (!meshes[i]) return fail(MH_INVALID_ARG, "null mesh");
+    int rc = check_desc(&descs[i]);
+    if (rc != MH_OK) return rc;
+    const mh_op_desc& a = descs[0];
+    const mh_op_desc& b = descs[i];
+    if (a.n_orb != b.n_orb || a.n_alpha != b.n_alpha || a.n_beta != b.n_beta || a.lmax_bc != b.lmax_bc)
+      return fail(MH_INVALID_ARG, "instances of a batch must share n_orb, electron counts and lmax_bc");
+    if (meshes[i]->M.P != meshes[0]->M.P) return fail(MH_INVALID_ARG, "instances of a batch must share p");
+  }
+  return guarded([&]() -> int {
+    std::vector<InstanceSpec> spec;
+    for (int i = 0; i < n_inst; ++i) spec.push_back(make_spec(meshes[i], &descs[i], field_scale ? field_scale[i] : 1.0));
+    *out = create_batch(spec, descs[0], S(stream));
     return MH_OK;
   });
 }
@@ -420,87 +570,129 @@ extern "C" int mh_op_destroy(mh_op* op) {
 
 extern "C" int mh_op_sizes_get(const mh_op* op, mh_op_sizes* sz) {
   if (!op || !sz) return fail(MH_INVALID_ARG, "null argument");
-  sz->n_dof = op->d.N;
-  sz->n_ext = op->d.NE;
-  sz->n_full = op->d.NF;
+  int64_t N = 0, nnz = 0;
+  for (int i = 0; i < op->ni; ++i) {
+    N += op->dh[i].N;
+    nnz += (int64_t)op->Hs[i].kt_col.size();
+  }
+  sz->n_dof = N;
+  sz->n_ext = op->B.tE;
+  sz->n_full = op->B.tF;
   sz->n_ci = op->ci.dim;
   sz->n_orb = op->n;
   sz->n_pair_cols = op->ncol;
-  sz->n_poisson_nnz = (int64_t)op->H.kt_col.size();
+  sz->n_poisson_nnz = nnz;
+  sz->n_inst = op->ni;
+  return MH_OK;
+}
+
+extern "C" int mh_batch_layout(const mh_op* op, int64_t* layout) {
+  if (!op || !layout) return fail(MH_INVALID_ARG, "null argument");
+  for (int i = 0; i < op->ni; ++i) {
+    const DevMesh& d = op->dh[i];
+    int64_t* r = layout + 6 * (size_t)i;
+    r[0] = d.N;
+    r[1] = d.NE;
+    r[2] = d.NF;
+    r[3] = d.oE;
+    r[4] = d.oF;
+    r[5] = (int64_t)op->Hs[i].kt_col.size();
+  }
   return MH_OK;
 }
 
 // ------------------------------------------------------- internal pieces ----
 // Node-centric operator pass with optional event timing on the launch stream.
-static void stencil_orb(mh_op* op, const double* u, double E, int diag_mode, int mode, double* out,
+static void stencil_orb(mh_op* op, const double* u, const double* Ef, int diag_mode, int mode, double* out,
                         hipStream_t s) {
   const bool rec = op->timing && op->ev_used[0] + 2 <= (int)op->ev[0].size();
   if (rec) HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0]], s));
-  launch_stencil_orb(op->d, u, E, diag_mode, op->Upk, op->ginv, mode, op->lam, out, op->acc, s);
+  launch_stencil_orb(op->B, u, Ef, diag_mode, op->Upk, op->ginv, mode, op->lam, out, op->acc, s);
   if (rec) {
     HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0] + 1], s));
     op->ev_used[0] += 2;
   }
 }
 
-// out = F(u) load vector [N][n] (diag_mode 1: H1 only, 2: with mean field)
-static void load_vector(mh_op* op, const double* u, double E, int diag_mode, double* out, hipStream_t s) {
-  stencil_orb(op, u, E, diag_mode, 0, out, s);
-  launch_ma_gather_orb(op->d, op->acc, 0, out, nullptr, s);
+// out = F(u) load vector over DoF rows (diag_mode 1: H1 only, 2: with mean
+// field) at the field value held in the device scalar *Ef.
+static void load_vector(mh_op* op, const double* u, const double* Ef, int diag_mode, double* out, hipStream_t s) {
+  stencil_orb(op, u, Ef, diag_mode, 0, out, s);
+  launch_ma_gather_orb(op->B, op->acc, 0, out, nullptr, s);
 }
 
 // out (extended) = G u  (or M^-1 F(u) when with_lam == 0)
 static void g_apply(mh_op* op, const double* u, double* out, int with_lam, hipStream_t s) {
-  const DevMesh& d = op->d;
-  stencil_orb(op, u, op->E, 2, with_lam ? 2 : 1, out, s);
-  launch_ma_gather_orb(d, op->acc, 1, out, op->ma_b, s);
-  launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
-                  op->H.cheb_iters, u, with_lam ? op->lam : nullptr, out, s);
-  launch_fill_orb(d, out, nullptr, s);
+  const Batch& B = op->B;
+  stencil_orb(op, u, op->Ebuf, 2, with_lam ? 2 : 1, out, s);
+  launch_ma_gather_orb(B, op->acc, 1, out, op->ma_b, s);
+  launch_ma_solve(B, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, u, with_lam ? op->lam : nullptr, out, s);
+  launch_fill_orb(B, out, nullptr, s);
+}
+
+// Poisson set-up of one solve: moments, boundary values, right-hand side, CG start.
+static void poisson_begin(mh_op* op, const double* phi, double* W, int warm, hipStream_t s) {
+  const Batch& B = op->B;
+  PoissonWs& P = op->P;
+  launch_poisson_pipeline_moments(B, phi, op->colinfo, P, s);
+  launch_bnd_eval(B, P, W, s);
+  launch_poisson_rhs_full(B, phi, W, op->colinfo, P.r, P, s);
+  launch_cg_start(B, W, P.r, P, warm, s);
+}
+
+// 1 when every column of every instance meets the residual target, -1 on a
+// non-finite residual, else 0 (reads the CG scalars after a stream sync).
+static int poisson_converged(mh_op* op, hipStream_t s) {
+  const int ncol = op->ncol, ni = op->ni;
+  double* hs = op->hostpin;
+  HIPCHK(hipMemcpyAsync(hs, op->P.sc, (size_t)ni * 8 * ncol * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int conv = 1;
+  for (int i = 0; i < ni; ++i)
+    for (int c = 0; c < ncol; ++c) {
+      const double* sc = hs + (size_t)i * 8 * ncol;
+      double rr = sc[SC_RR * ncol + c], bb = sc[SC_BB * ncol + c];
+      if (!std::isfinite(rr)) return -1;
+      if (rr > op->rtol * op->rtol * bb) conv = 0;
+    }
+  return conv;
 }
 
 static int poisson_solve(mh_op* op, const double* phi, double* W, int warm, int* iters, hipStream_t s) {
-  const DevMesh& d = op->d;
+  const Batch& B = op->B;
   PoissonWs& P = op->P;
-  const int ncol = P.ncol;
-  launch_poisson_pipeline_moments(d, phi, op->xyz, op->colinfo, P, s);
-  launch_bnd_eval(d, P, W, s);
-  launch_poisson_rhs_full(d, phi, W, op->colinfo, P.r, P, s);
-  launch_cg_start(d, W, P.r, P, warm, s);
-  int it = 0;
-  bool conv = false;
-  double* hs = op->hostpin;
+  poisson_begin(op, phi, W, warm, s);
+  int it = 0, conv = 0;
   const int check = 8;
   while (it < op->maxit) {
     int todo = std::min(check, op->maxit - it);
-    for (int k = 0; k < todo; ++k) launch_cg_step(d, W, P, s);
+    for (int k = 0; k < todo; ++k) launch_cg_step(B, W, P, s);
     it += todo;
-    HIPCHK(hipMemcpyAsync(hs, P.sc, 8 * ncol * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    conv = true;
-    for (int c = 0; c < ncol; ++c) {
-      double rr = hs[SC_RR * ncol + c], bb = hs[SC_BB * ncol + c];
-      if (!std::isfinite(rr)) return fail(MH_NONFINITE, "non-finite Poisson residual");
-      if (rr > op->rtol * op->rtol * bb) conv = false;
-    }
+    conv = poisson_converged(op, s);
+    if (conv < 0) return fail(MH_NONFINITE, "non-finite Poisson residual");
     if (conv) break;
   }
-  launch_fill_real(d, W, ncol, 1, P.acc, s);
-  launch_zero(P.acc + d.N * ncol, d.Nh * ncol, s);
+  launch_fill_real(B, W, 1, op->ncol, 1, P.acc, s);
   if (iters) *iters = it;
   return conv ? MH_OK : MH_NOT_CONVERGED;
 }
 
+// Frozen data of G at the current orbitals (field value already in Ebuf[0]):
+// U from W and Gamma, gamma^-1, lambda = c^H F(c).
+static void freeze_body(mh_op* op, const double* phi, const double* gamma, const double* Gamma, const double* W,
+                        hipStream_t s) {
+  const Batch& B = op->B;
+  launch_build_U_full(B, W, Gamma, op->colmap, op->Mr, op->Upk, s);
+  launch_ginv(op->ni, gamma, op->n, op->rdm_eps, op->ginv, op->flag, s);
+  load_vector(op, phi, op->Ebuf, 2, op->F, s);
+  launch_gram(B, phi, op->F, WT_NONE, ROWS_DOF, op->gpart, gram_blocks(B.mx.N), op->lam, s);
+  op->frozen = true;
+}
+
 static int freeze(mh_op* op, const double* phi, const double* gamma, const double* Gamma, double E, const double* W,
                   hipStream_t s) {
-  const DevMesh& d = op->d;
-  const int n = op->n;
-  op->E = E;
-  launch_build_U_full(d, W, Gamma, op->colmap, op->Mr, op->Upk, s);
-  launch_ginv(gamma, n, op->rdm_eps, op->ginv, op->flag, s);
-  load_vector(op, phi, E, 2, op->F, s);
-  launch_gram(phi, op->F, nullptr, d.N, n, op->gpart, gram_blocks(d.N), op->lam, s);
-  op->frozen = true;
+  launch_set(op->Ebuf, E, s);
+  freeze_body(op, phi, gamma, Gamma, W, s);
   return MH_OK;
 }
 
@@ -512,33 +704,33 @@ static void ensure_krylov(mh_op* op, int m) {
     (void)hipFree(p);
   }
   op->V.clear();
-  const size_t len = (size_t)2 * op->d.NE * op->n;
+  const size_t len = (size_t)2 * op->B.tE * op->n;
   for (int j = 0; j <= m; ++j) op->V.push_back(op->alloc<double>(len));
   op->Vdev = op->alloc<double*>(m + 1);
   HIPCHK(hipMemcpy(op->Vdev, op->V.data(), (m + 1) * sizeof(double*), hipMemcpyHostToDevice));
-  int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (op->d.NE * op->n + 255) / 256));
+  int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (op->B.mx.NE * op->n + 255) / 256));
   krylov_alloc(op, op->K, m, nblk);
   op->m_alloc = m;
 }
 
 static int arnoldi(mh_op* op, double* phi, double tau_re, double tau_im, int m, hipStream_t s) {
-  const DevMesh& d = op->d;
+  const Batch& B = op->B;
   ensure_krylov(op, m);
   Krylov K = op->K;
   K.m_max = op->m_alloc;
-  launch_norm_init(d, phi, K, m, s);
-  launch_krylov_scale(d, phi, op->V[0], K, 5, 0, s);
+  launch_norm_init(B, phi, K, m, s);
+  launch_krylov_scale(B, phi, op->V[0], K, 5, s);
   for (int k = 0; k < m; ++k) {
     double* w = op->V[k + 1];
     g_apply(op, op->V[k], w, 1, s);
-    launch_mdot(d, op->Vdev, k, w, K, 1, s);
-    launch_orth_update(d, op->Vdev, k, w, K, 1, s);
-    launch_mdot(d, op->Vdev, k, w, K, 2, s);
-    launch_orth_update(d, op->Vdev, k, w, K, 2, s);
-    launch_krylov_scale(d, w, w, K, 1, k, s);
+    launch_mdot(B, op->Vdev, k, w, K, 1, s);
+    launch_orth_update(B, op->Vdev, k, w, K, 1, s);
+    launch_mdot(B, op->Vdev, k, w, K, 2, s);
+    launch_orth_update(B, op->Vdev, k, w, K, 2, s);
+    launch_krylov_scale(B, w, w, K, 1, s);
   }
-  launch_expm(K, m, tau_re, tau_im, s);
-  launch_combine(d, op->Vdev, m, phi, K, s);
+  launch_expm(op->ni, K, tau_re, tau_im, s);
+  launch_combine(B, op->Vdev, m, phi, K, s);
   return MH_OK;
 }
 
@@ -546,7 +738,7 @@ static int arnoldi(mh_op* op, double* phi, double tau_re, double tau_im, int m, 
 extern "C" int mh_fill_hanging(mh_op* op, double* x, void* stream) {
   if (!op || !x) return fail(MH_INVALID_ARG, "null argument");
   return guarded([&]() -> int {
-    launch_fill_orb(op->d, x, nullptr, S(stream));
+    launch_fill_orb(op->B, x, nullptr, S(stream));
     HIPCHK(hipGetLastError());
     return MH_OK;
   });
@@ -556,11 +748,10 @@ extern "C" int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream
   if (!op || !f || !c) return fail(MH_INVALID_ARG, "null argument");
   return guarded([&]() -> int {
     hipStream_t s = S(stream);
-    const DevMesh& d = op->d;
-    launch_mass_direct(d, f, c, op->ma_b, s);
-    launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
-                    op->H.cheb_iters, nullptr, nullptr, c, s);
-    launch_fill_orb(d, c, nullptr, s);
+    const Batch& B = op->B;
+    launch_mass_direct(B, f, c, op->ma_b, s);
+    launch_ma_solve(B, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, nullptr, nullptr, c, s);
+    launch_fill_orb(B, c, nullptr, s);
     HIPCHK(hipGetLastError());
     return MH_OK;
   });
@@ -569,7 +760,9 @@ extern "C" int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream
 extern "C" int mh_h1_apply(mh_op* op, const double* c, double E, double* f, void* stream) {
   if (!op || !c || !f) return fail(MH_INVALID_ARG, "null argument");
   return guarded([&]() -> int {
-    load_vector(op, c, E, 1, f, S(stream));
+    hipStream_t s = S(stream);
+    launch_set(op->Ebuf + 1, E, s);
+    load_vector(op, c, op->Ebuf + 1, 1, f, s);
     HIPCHK(hipGetLastError());
     return MH_OK;
   });
@@ -591,10 +784,19 @@ extern "C" int mh_poisson_pairs(mh_op* op, const double* phi, double* W, int32_t
 extern "C" int mh_ci_rdms(mh_op* op, const double* Ci, double* gamma, double* Gamma, void* stream) {
   if (!op || !Ci || !gamma || !Gamma) return fail(MH_INVALID_ARG, "null argument");
   return guarded([&]() -> int {
-    launch_ci_rdm_full(op->ci, Ci, gamma, Gamma, op->Gtmp, S(stream));
+    launch_ci_rdm_full(op->ni, op->ci, Ci, gamma, Gamma, op->Gtmp, S(stream));
     HIPCHK(hipGetLastError());
     return MH_OK;
   });
+}
+
+static bool any_flag(mh_op* op, hipStream_t s) {
+  int* hf = (int*)op->hostpin;
+  HIPCHK(hipMemcpyAsync(hf, op->flag, op->ni * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < op->ni; ++i)
+    if (hf[i]) return true;
+  return false;
 }
 
 extern "C" int mh_freeze(mh_op* op, const double* phi, const double* gamma, const double* Gamma, double E,
@@ -603,10 +805,7 @@ extern "C" int mh_freeze(mh_op* op, const double* phi, const double* gamma, cons
   return guarded([&]() -> int {
     hipStream_t s = S(stream);
     freeze(op, phi, gamma, Gamma, E, W, s);
-    int* hf = (int*)op->hostpin;
-    HIPCHK(hipMemcpyAsync(hf, op->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hf[0]) {
+    if (any_flag(op, s)) {
       op->frozen = false;
       return fail(MH_SINGULAR_RDM, "1-RDM not positive after regularisation");
     }
@@ -634,68 +833,136 @@ extern "C" int mh_arnoldi_step(mh_op* op, double* phi, double tau_re, double tau
     arnoldi(op, phi, tau_re, tau_im, m, s);
     HIPCHK(hipGetLastError());
     if (err_est || m_used) {
-      HIPCHK(hipMemcpyAsync(op->hostpin, op->K.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(op->hostpin, op->K.scal, (size_t)op->ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (err_est) *err_est = op->hostpin[3];
-      if (m_used) *m_used = (int32_t)op->hostpin[4];
+      double err = 0.0;
+      int mu = m;
+      for (int i = 0; i < op->ni; ++i) {
+        err = std::max(err, op->hostpin[8 * i + 3]);
+        mu = std::min(mu, (int)op->hostpin[8 * i + 4]);
+      }
+      if (err_est) *err_est = err;
+      if (m_used) *m_used = mu;
     }
     return MH_OK;
   });
 }
 
+// Everything of one time step after the Poisson solve, with the step's field
+// value already in Ebuf[0]: freeze, one- and two-electron integrals and
+// observables at t_n, then (advance) the orbital Arnoldi step and the CI
+// Lanczos step.  A fixed launch sequence, so it can be captured as a graph.
+static void step_after_poisson(mh_op* op, double* phi, double* Ci, const double* W, int advance, double tre,
+                               double tim, int m, int imaginary, hipStream_t s) {
+  const Batch& B = op->B;
+  const int mci = std::min(12, op->ci.dim);
+  freeze_body(op, phi, op->gam, op->Gam, W, s);
+  load_vector(op, phi, op->Ebuf, 1, op->F, s);
+  launch_gram(B, phi, op->F, WT_NONE, ROWS_DOF, op->gpart, gram_blocks(B.mx.N), op->hmat, s);
+  launch_gint_full(B, phi, W, op->colmap, op->gpart, gint_blocks(B), op->Gtmp, op->gint, s);
+  launch_gram(B, phi, phi, WT_MASS, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), op->S, s);
+  launch_gram(B, phi, phi, WT_DIPOLE, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), op->zmat, s);
+  launch_observe(B, op->gam, op->Gam, op->hmat, op->gint, op->zmat, op->S, op->obs, s);
+  if (!advance) return;
+  arnoldi(op, phi, tre, tim, m, s);
+  launch_ci_hprime(op->ni, op->ci, op->hmat, op->gint, s);
+  launch_ci_lanczos(op->ni, op->ci, op->Qdev, op->Qh.data(), mci, op->gint, Ci, op->KC, tre, tim, imaginary ? 1 : 0,
+                    s);
+  if (imaginary) {
+    launch_gram(B, phi, phi, WT_MASS, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), op->S, s);
+    launch_orthonormalize_full(B, op->S, op->Rinv, phi, s);
+  }
+}
+
+namespace {
+struct GraphHolder {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  ~GraphHolder() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+struct EventHolder {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~EventHolder() {
+    for (hipEvent_t v : e)
+      if (v) (void)hipEventDestroy(v);
+  }
+};
+}  // namespace
+
 extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const double* E_steps, int32_t n_steps,
                             double dt, int32_t m, int32_t flags, mh_observables* obs, void* stream) {
   const int imaginary = flags & MH_PROP_IMAGINARY;
+  const bool use_graph = (flags & MH_PROP_GRAPH) != 0;
   const int last_step = (flags & MH_PROP_NO_FINAL) ? n_steps - 1 : n_steps;
   if (!op || !phi || !Ci || !W || (n_steps > 0 && !E_steps)) return fail(MH_INVALID_ARG, "null argument");
   if (n_steps < 0 || m < 1 || m > 24) return fail(MH_INVALID_ARG, "bad step count or Krylov dimension");
   return guarded([&]() -> int {
     hipStream_t s = S(stream);
-    const DevMesh& d = op->d;
-    const int n = op->n;
-    CIDev& c = op->ci;
-    const int mci = std::min(12, c.dim);
+    const int ni = op->ni;
     const double tre = imaginary ? 0.0 : dt, tim = imaginary ? -dt : 0.0;
     int status = MH_OK;
+    GraphHolder gh;
+    EventHolder evh;
+    const bool saved_timing = op->timing;
+    if (use_graph) {
+      ensure_krylov(op, m);
+      if (!op->gstream) HIPCHK(hipStreamCreateWithFlags(&op->gstream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&evh.e[0], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&evh.e[1], hipEventDisableTiming));
+    }
     for (int step = 0; step <= last_step; ++step) {
       const double E = (n_steps > 0 || E_steps) ? E_steps[step] : 0.0;
-      launch_ci_rdm_full(c, Ci, op->gam, op->Gam, op->Gtmp, s);
+      launch_ci_rdm_full(ni, op->ci, Ci, op->gam, op->Gam, op->Gtmp, s);
       int it = 0;
       int rc = poisson_solve(op, phi, W, 1, &it, s);
       if (rc < 0) return rc;
       if (rc == MH_NOT_CONVERGED) status = MH_NOT_CONVERGED;
-      freeze(op, phi, op->gam, op->Gam, E, W, s);
-      // integrals and observables at t_n
-      load_vector(op, phi, E, 1, op->F, s);
-      launch_gram(phi, op->F, nullptr, d.N, n, op->gpart, gram_blocks(d.N), op->hmat, s);
-      launch_gint_full(d, phi, W, op->colmap, op->gpart, gint_blocks(d), op->Gtmp, op->gint, s);
-      launch_gram(phi, phi, d.m, d.NE, n, op->gpart, gram_blocks(d.NE), op->S, s);
-      launch_gram(phi, phi, d.mz, d.NE, n, op->gpart, gram_blocks(d.NE), op->zmat, s);
-      launch_observe(op->gam, op->Gam, op->hmat, op->gint, op->zmat, op->S, n, op->vnn, op->obs, s);
-      double err = 0.0;
-      if (step < n_steps) {
-        arnoldi(op, phi, tre, tim, m, s);
-        launch_ci_hprime(c, op->hmat, op->gint, s);
-        launch_ci_lanczos(c, op->Qdev, op->Qh.data(), mci, op->gint, Ci, op->KC, tre, tim, imaginary ? 1 : 0, s);
-        if (imaginary) {
-          launch_gram(phi, phi, d.m, d.NE, n, op->gpart, gram_blocks(d.NE), op->S, s);
-          launch_orthonormalize_full(d, op->S, op->Rinv, phi, s);
+      launch_set(op->Ebuf, E, s);
+      const int advance = step < n_steps;
+      if (use_graph && advance) {
+        hipStream_t g = op->gstream;
+        if (!gh.x) {
+          op->timing = false;
+          HIPCHK(hipEventRecord(evh.e[0], s));
+          HIPCHK(hipStreamWaitEvent(g, evh.e[0], 0));
+          HIPCHK(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
+          step_after_poisson(op, phi, Ci, W, 1, tre, tim, m, imaginary, g);
+          HIPCHK(hipStreamEndCapture(g, &gh.g));
+          HIPCHK(hipGraphInstantiate(&gh.x, gh.g, nullptr, nullptr, 0));
+          op->timing = saved_timing;
         }
+        HIPCHK(hipEventRecord(evh.e[0], s));
+        HIPCHK(hipStreamWaitEvent(g, evh.e[0], 0));
+        HIPCHK(hipGraphLaunch(gh.x, g));
+        HIPCHK(hipEventRecord(evh.e[1], g));
+        HIPCHK(hipStreamWaitEvent(s, evh.e[1], 0));
+      } else {
+        step_after_poisson(op, phi, Ci, W, advance, tre, tim, m, imaginary, s);
       }
       // copy this step's scalars
       double* hs = op->hostpin;
-      HIPCHK(hipMemcpyAsync(hs, op->obs, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hs + 8, op->K.scal ? op->K.scal : op->obs, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync((int*)(hs + 16), op->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      double* hk = hs + 8 * (size_t)ni;
+      int* hf = (int*)(hs + 16 * (size_t)ni);
+      HIPCHK(hipMemcpyAsync(hs, op->obs, (size_t)ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      if (advance)
+        HIPCHK(hipMemcpyAsync(hk, op->K.scal, (size_t)ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hf, op->flag, ni * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (((int*)(hs + 16))[0]) return fail(MH_SINGULAR_RDM, "1-RDM not positive after regularisation");
-      if (!std::isfinite(hs[0]) || !std::isfinite(hs[1])) return fail(MH_NONFINITE, "non-finite observables");
-      err = (step < n_steps) ? hs[8 + 3] : 0.0;
+      for (int i = 0; i < ni; ++i) {
+        if (hf[i]) return fail(MH_SINGULAR_RDM, "1-RDM not positive after regularisation");
+        if (!std::isfinite(hs[8 * i]) || !std::isfinite(hs[8 * i + 1])) return fail(MH_NONFINITE, "non-finite observables");
+      }
       if (obs) {
-        if (obs->dipole) obs->dipole[step] = hs[1];
-        if (obs->energy) obs->energy[step] = hs[0];
-        if (obs->ortho) obs->ortho[step] = hs[2];
-        if (obs->err_est) obs->err_est[step] = err;
+        for (int i = 0; i < ni; ++i) {
+          const size_t o = (size_t)step * ni + i;
+          if (obs->dipole) obs->dipole[o] = hs[8 * i + 1];
+          if (obs->energy) obs->energy[o] = hs[8 * i];
+          if (obs->ortho) obs->ortho[o] = hs[8 * i + 2];
+          if (obs->err_est) obs->err_est[o] = advance ? hk[8 * i + 3] : 0.0;
+        }
         if (obs->cg_iters) obs->cg_iters[step] = it;
       }
     }
@@ -739,25 +1006,30 @@ extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");
-  if (which == 0) {
-    op->d.sched_orb = sched;
-    op->d.grid_orb = grid_cap;
-  } else {
-    op->d.sched_poi = sched;
-    op->d.grid_poi = grid_cap;
-  }
-  return MH_OK;
+  return guarded([&]() -> int {
+    HIPCHK(hipDeviceSynchronize());
+    for (DevMesh& d : op->dh) {
+      if (which == 0) {
+        d.sched_orb = sched;
+        d.grid_orb = grid_cap;
+      } else {
+        d.sched_poi = sched;
+        d.grid_poi = grid_cap;
+      }
+    }
+    upload_instances(op, nullptr);
+    return MH_OK;
+  });
 }
 
 // ------------------------------------------------------------------ adjoint ----
 // out = M^-1 Z u (dipole load vector through the mass solve), hanging rows filled
 static void mass_dipole(mh_op* op, const double* u, double* out, hipStream_t s) {
-  const DevMesh& d = op->d;
-  stencil_orb(op, u, 0.0, 3, 1, out, s);
-  launch_ma_gather_orb(d, op->acc, 1, out, op->ma_b, s);
-  launch_ma_solve(d, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, op->H.cheb_lo, op->H.cheb_hi,
-                  op->H.cheb_iters, nullptr, nullptr, out, s);
-  launch_fill_orb(d, out, nullptr, s);
+  const Batch& B = op->B;
+  stencil_orb(op, u, op->Ebuf, 3, 1, out, s);
+  launch_ma_gather_orb(B, op->acc, 1, out, op->ma_b, s);
+  launch_ma_solve(B, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, nullptr, nullptr, out, s);
+  launch_fill_orb(B, out, nullptr, s);
 }
 
 namespace {
@@ -780,13 +1052,14 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
                                     const double* dJ_dd, double* dJ_dE, int32_t n_quad, int32_t ckpt_stride,
                                     void* stream) {
   if (!op || !phi0 || !Ci0 || !W_work || !E_steps || !dJ_dd || !dJ_dE) return fail(MH_INVALID_ARG, "null argument");
+  if (op->ni != 1) return fail(MH_UNSUPPORTED, "the adjoint takes a single instance");
   if (op->n != 1 || op->ci.dim != 1)
     return fail(MH_UNSUPPORTED, "the adjoint is implemented for one orbital and one determinant");
   if (n_steps < 1 || m < 1 || m > 24 || n_quad < 1 || n_quad > 16) return fail(MH_INVALID_ARG, "bad sizes");
   return guarded([&]() -> int {
     hipStream_t s = S(stream);
-    const DevMesh& d = op->d;
-    const size_t len = (size_t)2 * d.NE * op->n;
+    const Batch& B = op->B;
+    const size_t len = (size_t)2 * B.tE * op->n;
     const int S_ = ckpt_stride > 0 ? ckpt_stride : std::max(1, (int)std::lround(std::sqrt((double)n_steps)));
     DevScratch mem;
     const int nck = n_steps / S_ + 1;
@@ -800,8 +1073,8 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
     double* tmp = mem.get(len);
     double* zbuf = mem.get((size_t)2 * n_steps * n_quad);
     // one orbital, one determinant: gamma = 1, Gamma = 0, so the mean field vanishes
-    launch_ci_rdm_full(op->ci, Ci0, op->gam, op->Gam, op->Gtmp, s);
-    launch_zero(W_work, d.NF * op->ncol, s);
+    launch_ci_rdm_full(1, op->ci, Ci0, op->gam, op->Gam, op->Gtmp, s);
+    launch_zero(W_work, B.tF * op->ncol, s);
     auto step_forward = [&](double* c, int k) {
       freeze(op, c, op->gam, op->Gam, E_steps[k], W_work, s);
       arnoldi(op, c, dt, 0.0, m, s);
@@ -837,7 +1110,7 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
           arnoldi(op, vb, gx[j] * dt, 0.0, m, s);          // b = exp(-i s dt G) c_k
           launch_copy(nu, va, len, s);
           arnoldi(op, va, -(1.0 - gx[j]) * dt, 0.0, m, s);  // a = exp(+i (1-s) dt G) nu_{k+1}
-          launch_gram(va, vb, d.mz, d.NE, 1, op->gpart, gram_blocks(d.NE),
+          launch_gram(B, va, vb, WT_DIPOLE, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE),
                       zbuf + 2 * ((size_t)k * n_quad + j), s);
         }
         arnoldi(op, nu, -dt, 0.0, m, s);                    // nu <- exp(+i dt G) nu

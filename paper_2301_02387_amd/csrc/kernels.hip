@@ -1,8 +1,12 @@
-// HIP kernels of the MCTDHF-on-octree-FEM hot path for gfx950 (wave64).
+// HIP kernels of the MCTDHF-on-octree-FEM hot path for gfx950 (wave64):
+// interface mass solve, constraint fill, reductions, mean-field build,
+// Krylov (Arnoldi) pieces, Poisson right-hand side and multipole boundary
+// values, small dense work and the CI space.
 //
 // Orbital arrays are complex128 [rows][n] (orbital fastest); Poisson arrays
-// are real [rows][ncol].  Row space: [0,N) DoFs, [N,NE) hanging nodes,
-// [NE,NF) box-boundary nodes.
+// are real [rows][ncol].  Row space of one instance: [0,N) DoFs, [N,NE)
+// hanging nodes, [NE,NF) box-boundary nodes.  Batched launches: instance
+// blockIdx.y, batch row offsets from its DevMesh (kernels.hpp).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,238 +28,102 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return t;
 }
 
+#define INSTANCE const DevMesh& d = dm[blockIdx.y]
 
 // =====================================================================
-// Orbital cell operator: acc += (K/2 + v + E mz + m gamma^-1 U) u
-// Sum-factorised per cell (Sec. III.A tensor-product basis): the element
-// stiffness (h/2)(A x W x W + W x A x W + W x W x A) is applied line by
-// line from LDS; node-diagonal terms are added once per node by its owner
-// cell; results are scattered with FP64 atomics (boundary rows skipped).
-// =====================================================================
-template <int P>
-__global__ void __launch_bounds__(NT) k_cell_orb(DevMesh d, const double2* __restrict__ u, double* __restrict__ acc,
-                                                 double E, int diag_mode, const double* __restrict__ Upk,
-                                                 const double2* __restrict__ ginv) {
-  constexpr int P3 = P * P * P;
-  constexpr int CPB = (NT / P3) > 0 ? NT / P3 : 1;
-  __shared__ double2 su[CPB * 8 * P3];
-  const int n = d.n;
-  const int tid = threadIdx.x;
-  const int ci = tid / P3, t = tid - ci * P3;
-  const int64_t e = (int64_t)blockIdx.x * CPB + ci;
-  const bool active = (ci < CPB) && (e < d.nC);
-  const int node = active ? d.cell_nodes[e * P3 + t] : (int)d.NE;
-  double2* my = su + ci * 8 * P3;
-  if (ci < CPB) {
-    for (int o = 0; o < n; ++o)
-      my[o * P3 + t] = (active && node < d.NE) ? u[(int64_t)node * n + o] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  if (!active || node >= d.NE) return;
-  const int a = t % P, b = (t / P) % P, c = t / (P * P);
-  const double hh = d.cell_hh[e];
-  const double wa = d.w[a], wb = d.w[b], wc = d.w[c];
-  const double f0 = 0.5 * hh * wb * wc, f1 = 0.5 * hh * wa * wc, f2 = 0.5 * hh * wa * wb;
-  double2 y[8];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) y[o] = make_double2(0.0, 0.0);
-  for (int o = 0; o < n; ++o) {
-    const double2* uo = my + o * P3;
-    double2 s0 = make_double2(0, 0), s1 = make_double2(0, 0), s2 = make_double2(0, 0);
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      double2 v0 = uo[(c * P + b) * P + q], v1 = uo[(c * P + q) * P + a], v2 = uo[(q * P + b) * P + a];
-      double A0 = d.A[a * P + q], A1 = d.A[b * P + q], A2 = d.A[c * P + q];
-      s0.x += A0 * v0.x; s0.y += A0 * v0.y;
-      s1.x += A1 * v1.x; s1.y += A1 * v1.y;
-      s2.x += A2 * v2.x; s2.y += A2 * v2.y;
-    }
-    y[o] = make_double2(f0 * s0.x + f1 * s1.x + f2 * s2.x, f0 * s0.y + f1 * s1.y + f2 * s2.y);
-  }
-  if (diag_mode >= 1 && ((d.owner[e] >> t) & 1ull)) {
-    const double dg = d.v[node] + E * d.mz[node];
-    for (int o = 0; o < n; ++o) {
-      double2 uo = my[o * P3 + t];
-      y[o].x += dg * uo.x;
-      y[o].y += dg * uo.y;
-    }
-    if (diag_mode == 2) {
-      // z = U u with U Hermitian packed: U_oo = Up[o][o], U_oq = Up[o][q] + i Up[q][o] (o < q)
-      const double* Up = Upk + (int64_t)node * n * n;
-      double2 z[8];
-      for (int o = 0; o < n; ++o) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int q = 0; q < n; ++q) {
-          double2 Uoq;
-          if (o == q) Uoq = make_double2(Up[o * n + o], 0.0);
-          else if (o < q) Uoq = make_double2(Up[o * n + q], Up[q * n + o]);
-          else Uoq = make_double2(Up[q * n + o], -Up[o * n + q]);
-          s = cadd(s, cmul(Uoq, my[q * P3 + t]));
-        }
-        z[o] = s;
-      }
-      const double mi = d.m[node];
-      for (int p = 0; p < n; ++p) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int o = 0; o < n; ++o) s = cadd(s, cmul(ginv[p * n + o], z[o]));
-        y[p].x += mi * s.x;
-        y[p].y += mi * s.y;
-      }
-    }
-  }
-  double* dst = acc + (int64_t)node * n * 2;
-  for (int o = 0; o < n; ++o) {
-    atomicAdd(dst + 2 * o, y[o].x);
-    atomicAdd(dst + 2 * o + 1, y[o].y);
-  }
-}
-
-void launch_cell_orb(const DevMesh& d, const double* u, double* acc, double E, int diag_mode, const double* Upk,
-                     const double* ginv, hipStream_t s) {
-  switch (d.P) {
-    case 2: {
-      constexpr int CPB = NT / 8;
-      hipLaunchKernelGGL(k_cell_orb<2>, dim3(nblocks(d.nC, CPB)), dim3(NT), 0, s, d, (const double2*)u, acc, E,
-                         diag_mode, Upk, (const double2*)ginv);
-      break;
-    }
-    case 3: {
-      constexpr int CPB = NT / 27;
-      hipLaunchKernelGGL(k_cell_orb<3>, dim3(nblocks(d.nC, CPB)), dim3(NT), 0, s, d, (const double2*)u, acc, E,
-                         diag_mode, Upk, (const double2*)ginv);
-      break;
-    }
-    default: {
-      constexpr int CPB = NT / 64;
-      hipLaunchKernelGGL(k_cell_orb<4>, dim3(nblocks(d.nC, CPB)), dim3(NT), 0, s, d, (const double2*)u, acc, E,
-                         diag_mode, Upk, (const double2*)ginv);
-    }
-  }
-}
-
-// DoF epilogue: C^T (transposed constraints), then mass solve / projector.
-__global__ void __launch_bounds__(NT) k_epi_orb(DevMesh d, double2* __restrict__ acc, int mode,
-                                                const double2* __restrict__ v, const double2* __restrict__ lam,
-                                                double2* __restrict__ out, double2* __restrict__ ma_b) {
-  const int n = d.n;
-  const int64_t total = d.N * n;
-  for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
-    const int64_t k = idx / n;
-    const int p = (int)(idx - k * n);
-    double2 f = acc[idx];
-    acc[idx] = make_double2(0.0, 0.0);
-    const int mi = d.ma_index[k];
-    if (mi >= 0)
-      for (int t = d.ct_ptr[mi]; t < d.ct_ptr[mi + 1]; ++t) {
-        double2 a = acc[(int64_t)d.ct_row[t] * n + p];
-        f.x += d.ct_w[t] * a.x;
-        f.y += d.ct_w[t] * a.y;
-      }
-    if (mode == 0) {
-      out[idx] = f;
-      continue;
-    }
-    if (mi >= 0) {
-      ma_b[(int64_t)mi * n + p] = f;
-      continue;
-    }
-    double2 x = cscale(d.inv_mass[k], f);
-    if (mode == 2)
-      for (int q = 0; q < n; ++q) x = csub(x, cmul(lam[q * n + p], v[k * n + q]));
-    out[idx] = x;
-  }
-}
-
-void launch_epi_orb(const DevMesh& d, double* acc, int mode, const double* v, const double* lam, double* out,
-                    double* ma_b, hipStream_t s) {
-  hipLaunchKernelGGL(k_epi_orb, dim3(nblocks(d.N * d.n, NT, 8192)), dim3(NT), 0, s, d, (double2*)acc, mode,
-                     (const double2*)v, (const double2*)lam, (double2*)out, (double2*)ma_b);
-}
-
 // Chebyshev iteration on the interface block A_Ma (Jacobi-preconditioned,
 // spectrum bounds from set-up): x_{k+1} = x_k + d_k, r_{k+1} = r_k - A d_k,
-// d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) D^-1 r_{k+1}.
-__global__ void __launch_bounds__(NT) k_cheb_init(DevMesh d, const double2* __restrict__ b, double2* __restrict__ x,
-                                                  double2* __restrict__ r, double2* __restrict__ d0, double inv_theta) {
+// d_{k+1} = c1_k d_k + c2_k D^-1 r_{k+1}; the per-instance coefficients
+// (from that instance's bounds) are tabulated in d.cheb.
+// =====================================================================
+__global__ void __launch_bounds__(NT) k_cheb_init(const DevMesh* __restrict__ dm, const double2* __restrict__ b,
+                                                  double2* __restrict__ x, double2* __restrict__ r,
+                                                  double2* __restrict__ d0) {
+  INSTANCE;
   const int n = d.n;
-  const int64_t total = d.nMa * n;
+  const int64_t total = d.nMa * n, o = d.oMa * n;
+  if (total == 0) return;
+  const double inv_theta = d.cheb[0];
   for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
     const int64_t i = idx / n;
-    double2 bi = b[idx];
-    x[idx] = make_double2(0.0, 0.0);
-    r[idx] = bi;
-    d0[idx] = cscale(d.ma_dinv[i] * inv_theta, bi);
+    double2 bi = b[o + idx];
+    x[o + idx] = make_double2(0.0, 0.0);
+    r[o + idx] = bi;
+    d0[o + idx] = cscale(d.ma_dinv[i] * inv_theta, bi);
   }
 }
 
-__global__ void __launch_bounds__(NT) k_cheb_iter(DevMesh d, double2* __restrict__ x, double2* __restrict__ r,
-                                                  const double2* __restrict__ din, double2* __restrict__ dout,
-                                                  double c1, double c2) {
+__global__ void __launch_bounds__(NT) k_cheb_iter(const DevMesh* __restrict__ dm, double2* __restrict__ x,
+                                                  double2* __restrict__ r, const double2* __restrict__ din,
+                                                  double2* __restrict__ dout, int k) {
+  INSTANCE;
   const int n = d.n;
-  const int64_t total = d.nMa * n;
+  const int64_t total = d.nMa * n, o = d.oMa * n;
+  if (total == 0) return;
+  const double c1 = d.cheb[1 + 2 * k], c2 = d.cheb[2 + 2 * k];
+  const double2* dI = din + o;
   for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
     const int64_t i = idx / n;
     const int p = (int)(idx - i * n);
     double2 s = make_double2(0.0, 0.0);
     for (int t = d.ma_ptr[i]; t < d.ma_ptr[i + 1]; ++t) {
-      double2 v = din[(int64_t)d.ma_col[t] * n + p];
+      double2 v = dI[(int64_t)d.ma_col[t] * n + p];
       s.x += d.ma_val[t] * v.x;
       s.y += d.ma_val[t] * v.y;
     }
-    double2 dk = din[idx];
-    x[idx] = cadd(x[idx], dk);
-    double2 rn = csub(r[idx], s);
-    r[idx] = rn;
+    double2 dk = dI[idx];
+    x[o + idx] = cadd(x[o + idx], dk);
+    double2 rn = csub(r[o + idx], s);
+    r[o + idx] = rn;
     double g = c2 * d.ma_dinv[i];
-    dout[idx] = make_double2(c1 * dk.x + g * rn.x, c1 * dk.y + g * rn.y);
+    dout[o + idx] = make_double2(c1 * dk.x + g * rn.x, c1 * dk.y + g * rn.y);
   }
 }
 
-__global__ void __launch_bounds__(NT) k_cheb_finish(DevMesh d, const double2* __restrict__ x,
+__global__ void __launch_bounds__(NT) k_cheb_finish(const DevMesh* __restrict__ dm, const double2* __restrict__ x,
                                                     const double2* __restrict__ dk, const double2* __restrict__ v,
                                                     const double2* __restrict__ lam, double2* __restrict__ out) {
+  INSTANCE;
   const int n = d.n;
-  const int64_t total = d.nMa * n;
+  const int64_t total = d.nMa * n, o = d.oMa * n, oe = d.oE * n;
+  const double2* L = lam ? lam + (int64_t)blockIdx.y * n * n : nullptr;
   for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
     const int64_t i = idx / n;
     const int p = (int)(idx - i * n);
     const int64_t k = d.ma_dof[i];
-    double2 xf = cadd(x[idx], dk[idx]);
-    if (lam)
-      for (int q = 0; q < n; ++q) xf = csub(xf, cmul(lam[q * n + p], v[k * n + q]));
-    out[k * n + p] = xf;
+    double2 xf = cadd(x[o + idx], dk[o + idx]);
+    if (L)
+      for (int q = 0; q < n; ++q) xf = csub(xf, cmul(L[q * n + p], v[oe + k * n + q]));
+    out[oe + k * n + p] = xf;
   }
 }
 
-void launch_ma_solve(const DevMesh& d, const double* ma_b, double* x, double* r, double* dbuf0, double* dbuf1,
-                     double lo, double hi, int iters, const double* v, const double* lam, double* out,
-                     hipStream_t s) {
-  if (d.nMa == 0) return;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  const int nb = nblocks(d.nMa * d.n);
-  hipLaunchKernelGGL(k_cheb_init, dim3(nb), dim3(NT), 0, s, d, (const double2*)ma_b, (double2*)x, (double2*)r,
-                     (double2*)dbuf0, 1.0 / theta);
-  double rho = 1.0 / sigma;
+void launch_ma_solve(const Batch& b, const double* ma_b, double* x, double* r, double* dbuf0, double* dbuf1,
+                     const double* v, const double* lam, double* out, hipStream_t s) {
+  if (b.mx.nMa == 0) return;
+  const dim3 g(nblocks(b.mx.nMa * b.mx.n), b.ni);
+  hipLaunchKernelGGL(k_cheb_init, g, dim3(NT), 0, s, b.dm, (const double2*)ma_b, (double2*)x, (double2*)r,
+                     (double2*)dbuf0);
   double* din = dbuf0;
   double* dout = dbuf1;
-  for (int k = 0; k < iters; ++k) {
-    double rho1 = 1.0 / (2.0 * sigma - rho);
-    hipLaunchKernelGGL(k_cheb_iter, dim3(nb), dim3(NT), 0, s, d, (double2*)x, (double2*)r, (const double2*)din,
-                       (double2*)dout, rho1 * rho, 2.0 * rho1 / delta);
-    rho = rho1;
+  for (int k = 0; k < b.cheb_iters; ++k) {
+    hipLaunchKernelGGL(k_cheb_iter, g, dim3(NT), 0, s, b.dm, (double2*)x, (double2*)r, (const double2*)din,
+                       (double2*)dout, k);
     double* t = din;
     din = dout;
     dout = t;
   }
-  hipLaunchKernelGGL(k_cheb_finish, dim3(nb), dim3(NT), 0, s, d, (const double2*)x, (const double2*)din,
+  hipLaunchKernelGGL(k_cheb_finish, g, dim3(NT), 0, s, b.dm, (const double2*)x, (const double2*)din,
                      (const double2*)v, (const double2*)lam, (double2*)out);
 }
 
 // Hanging rows: x[h] = sum_k c_hk x[k] over DoF masters (boundary values of
 // orbitals vanish); optionally zero the hanging rows of acc.
-__global__ void __launch_bounds__(NT) k_fill_orb(DevMesh d, double2* __restrict__ x, double2* __restrict__ acc) {
+__global__ void __launch_bounds__(NT) k_fill_orb(const DevMesh* __restrict__ dm, double2* __restrict__ x,
+                                                 double2* __restrict__ acc) {
+  INSTANCE;
   const int n = d.n;
-  const int64_t total = d.Nh * n;
+  const int64_t total = d.Nh * n, o = d.oE * n;
   for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
     const int64_t h = idx / n;
     const int p = (int)(idx - h * n);
@@ -263,19 +131,20 @@ __global__ void __launch_bounds__(NT) k_fill_orb(DevMesh d, double2* __restrict_
     for (int t = d.hang_ptr[h]; t < d.hang_ptr[h + 1]; ++t) {
       int col = d.hang_col[t];
       if (col < d.N) {
-        double2 v = x[(int64_t)col * n + p];
+        double2 v = x[o + (int64_t)col * n + p];
         s.x += d.hang_w[t] * v.x;
         s.y += d.hang_w[t] * v.y;
       }
     }
-    x[(d.N + h) * n + p] = s;
-    if (acc) acc[(d.N + h) * n + p] = make_double2(0.0, 0.0);
+    x[o + (d.N + h) * n + p] = s;
+    if (acc) acc[o + (d.N + h) * n + p] = make_double2(0.0, 0.0);
   }
 }
 
-void launch_fill_orb(const DevMesh& d, double* x, double* acc, hipStream_t s) {
-  if (d.Nh == 0) return;
-  hipLaunchKernelGGL(k_fill_orb, dim3(nblocks(d.Nh * d.n)), dim3(NT), 0, s, d, (double2*)x, (double2*)acc);
+void launch_fill_orb(const Batch& b, double* x, double* acc, hipStream_t s) {
+  if (b.mx.Nh == 0) return;
+  hipLaunchKernelGGL(k_fill_orb, dim3(nblocks(b.mx.Nh * b.mx.n), b.ni), dim3(NT), 0, s, b.dm, (double2*)x,
+                     (double2*)acc);
 }
 
 __global__ void k_copy(const double* __restrict__ in, double* __restrict__ out, int64_t nd) {
@@ -284,24 +153,47 @@ __global__ void k_copy(const double* __restrict__ in, double* __restrict__ out, 
 __global__ void k_zero(double* __restrict__ out, int64_t nd) {
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nd; i += (int64_t)gridDim.x * NT) out[i] = 0.0;
 }
+__global__ void k_set(double* __restrict__ out, double value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = value;
+}
 void launch_copy(const double* in, double* out, int64_t nd, hipStream_t s) {
   if (nd > 0) hipLaunchKernelGGL(k_copy, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, in, out, nd);
 }
 void launch_zero(double* out, int64_t nd, hipStream_t s) {
   if (nd > 0) hipLaunchKernelGGL(k_zero, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, out, nd);
 }
+void launch_set(double* out, double value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, out, value);
+}
 
 // =====================================================================
-// Generic tiled reduction: out[a][b] = sum_i wt_i conj(X[i][a]) Y[i][b]
-// X complex [rows][na]; Y complex or real [rows][nb].  Partials per block,
-// then one finishing block.  Deterministic.
+// Generic tiled reduction: out[a][b] = sum_i wt_i conj(X[i][a]) Y[i][b],
+// one output set per instance.  Mesh mode (dm != null): X, Y are batch
+// orbital arrays with na, nb columns, rows N or NE of the instance, weight
+// none / m / m z.  Flat mode: X [ni][rows][na], Y [ni][rows][nb].
+// Partials per block, then a finishing pass.  Deterministic.
 // =====================================================================
 constexpr int XG_CH = 16;
-__global__ void __launch_bounds__(NT) k_xgram(const double2* __restrict__ X, int na, const double* __restrict__ Y,
-                                              int nb, int yreal, const double* __restrict__ wt, int64_t rows,
-                                              double2* __restrict__ part) {
+__global__ void __launch_bounds__(NT) k_xgram(const DevMesh* __restrict__ dm, int wsel, int rsel,
+                                              const double2* __restrict__ X, int na, const double2* __restrict__ Y,
+                                              int nb, int64_t frows, double2* __restrict__ part) {
   __shared__ double2 sx[XG_CH * 64];
   __shared__ double2 sy[XG_CH * 64];
+  int64_t rows, xo, yo;
+  const double* wt = nullptr;
+  if (dm) {
+    const DevMesh& d = dm[blockIdx.y];
+    rows = rsel == ROWS_EXT ? d.NE : d.N;
+    xo = d.oE * na;
+    yo = d.oE * nb;
+    wt = wsel == WT_MASS ? d.m : (wsel == WT_DIPOLE ? d.mz : nullptr);
+  } else {
+    rows = frows;
+    xo = (int64_t)blockIdx.y * frows * na;
+    yo = (int64_t)blockIdx.y * frows * nb;
+  }
+  X += xo;
+  Y += yo;
   const int nout = na * nb;
   constexpr int MAXO = 16;  // outputs per thread (na*nb <= 4096)
   double2 accv[MAXO];
@@ -321,9 +213,7 @@ __global__ void __launch_bounds__(NT) k_xgram(const double2* __restrict__ X, int
     }
     for (int e = threadIdx.x; e < XG_CH * nb; e += NT) {
       int r = e / nb, bb = e - r * nb;
-      double2 v = make_double2(0.0, 0.0);
-      if (r < cnt) v = yreal ? make_double2(Y[(base + r) * nb + bb], 0.0) : ((const double2*)Y)[(base + r) * nb + bb];
-      sy[r * nb + bb] = v;
+      sy[r * nb + bb] = (r < cnt) ? Y[(base + r) * nb + bb] : make_double2(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll
@@ -340,43 +230,53 @@ __global__ void __launch_bounds__(NT) k_xgram(const double2* __restrict__ X, int
       accv[j] = s;
     }
   }
+  double2* pb = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout;
 #pragma unroll
   for (int j = 0; j < MAXO; ++j) {
     int o = threadIdx.x + j * NT;
-    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = accv[j];
+    if (o < nout) pb[o] = accv[j];
   }
 }
 
+// out[i][o] = sum_b part[i][b][o]
 __global__ void k_sum_parts(const double2* __restrict__ part, int nblk, int nout, double2* __restrict__ out) {
+  const double2* pi = part + (int64_t)blockIdx.y * nblk * nout;
   for (int o = blockIdx.x * NT + threadIdx.x; o < nout; o += gridDim.x * NT) {
     double2 s = make_double2(0.0, 0.0);
-    for (int b = 0; b < nblk; ++b) s = cadd(s, part[(int64_t)b * nout + o]);
-    out[o] = s;
+    for (int b = 0; b < nblk; ++b) s = cadd(s, pi[(int64_t)b * nout + o]);
+    out[(int64_t)blockIdx.y * nout + o] = s;
   }
 }
 
 int gram_blocks(int64_t rows) { return nblocks(rows, XG_CH, 512); }
 
-void launch_xgram(const double* X, int na, const double* Y, int nb, int yreal, const double* wt, int64_t rows,
-                  double* part, int nblk, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_xgram, dim3(nblk), dim3(NT), 0, s, (const double2*)X, na, Y, nb, yreal, wt, rows,
-                     (double2*)part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(na * nb)), dim3(NT), 0, s, (const double2*)part, nblk, na * nb,
-                     (double2*)out);
+void launch_gram(const Batch& b, const double* A, const double* B, int wsel, int rows, double* part, int nblk,
+                 double* G, hipStream_t s) {
+  const int n = b.mx.n;
+  hipLaunchKernelGGL(k_xgram, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, wsel, rows, (const double2*)A, n,
+                     (const double2*)B, n, (int64_t)0, (double2*)part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(n * n), b.ni), dim3(NT), 0, s, (const double2*)part, nblk, n * n,
+                     (double2*)G);
 }
 
-void launch_gram(const double* a, const double* b, const double* wt, int64_t rows, int n, double* part, int nblk,
-                 double* G, hipStream_t s) {
-  launch_xgram(a, n, b, n, 0, wt, rows, part, nblk, G, s);
+void launch_xgram_flat(int ni, const double* X, int na, const double* Y, int nb, int64_t rows, double* part,
+                       int nblk, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_xgram, dim3(nblk, ni), dim3(NT), 0, s, (const DevMesh*)nullptr, 0, 0, (const double2*)X, na,
+                     (const double2*)Y, nb, rows, (double2*)part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(na * nb), ni), dim3(NT), 0, s, (const double2*)part, nblk, na * nb,
+                     (double2*)out);
 }
 
 // Pair-product integrals: G[(p,q)][col] = sum_i m_i conj(phi_p) phi_q Wcol_i
 // (X built on the fly as phi_p conj(phi_q) so that conj(X) = conj(phi_p) phi_q).
-__global__ void __launch_bounds__(NT) k_gint(DevMesh d, const double2* __restrict__ phi,
+__global__ void __launch_bounds__(NT) k_gint(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
                                              const double* __restrict__ W, int ncol, double2* __restrict__ part) {
+  INSTANCE;
   __shared__ double2 sx[XG_CH * 64];
   __shared__ double sw[XG_CH * 64];
   const int n = d.n, na = n * n, nout = na * ncol;
+  phi += d.oE * n;
+  W += d.oF * ncol;
   constexpr int MAXO = 16;
   double2 accv[MAXO];
 #pragma unroll
@@ -417,18 +317,21 @@ __global__ void __launch_bounds__(NT) k_gint(DevMesh d, const double2* __restric
       accv[j] = s;
     }
   }
+  double2* pb = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout;
 #pragma unroll
   for (int j = 0; j < MAXO; ++j) {
     int o = threadIdx.x + j * NT;
-    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = accv[j];
+    if (o < nout) pb[o] = accv[j];
   }
 }
 
 // Assemble g_pqrs from the pair-column integrals G[(p,q)][col].
 __global__ void k_gint_assemble(const double2* __restrict__ G, int n, const int* __restrict__ colmap,
                                 double2* __restrict__ g) {
-  const int ncol = n * n;
-  for (int o = blockIdx.x * NT + threadIdx.x; o < n * n * n * n; o += gridDim.x * NT) {
+  const int ncol = n * n, n4 = ncol * ncol;
+  G += (int64_t)blockIdx.y * n4;
+  g += (int64_t)blockIdx.y * n4;
+  for (int o = blockIdx.x * NT + threadIdx.x; o < n4; o += gridDim.x * NT) {
     int s = o % n, r = (o / n) % n, pq = o / (n * n);
     int rr = r < s ? r : s, ss = r < s ? s : r;
     int cre = colmap[rr * n + ss];
@@ -442,16 +345,16 @@ __global__ void k_gint_assemble(const double2* __restrict__ G, int n, const int*
   }
 }
 
-int gint_blocks(const DevMesh& d) { return nblocks(d.NE, XG_CH, 512); }
+int gint_blocks(const Batch& b) { return nblocks(b.mx.NE, XG_CH, 512); }
 
-void launch_gint_full(const DevMesh& d, const double* phi, const double* W, const int* colmap, double* part,
-                      int nblk, double* Gtmp, double* g, hipStream_t s) {
-  const int n = d.n, ncol = n * n;
-  hipLaunchKernelGGL(k_gint, dim3(nblk), dim3(NT), 0, s, d, (const double2*)phi, W, ncol, (double2*)part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(ncol * ncol)), dim3(NT), 0, s, (const double2*)part, nblk,
+void launch_gint_full(const Batch& b, const double* phi, const double* W, const int* colmap, double* part, int nblk,
+                      double* Gtmp, double* g, hipStream_t s) {
+  const int n = b.mx.n, ncol = n * n;
+  hipLaunchKernelGGL(k_gint, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol, (double2*)part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(ncol * ncol), b.ni), dim3(NT), 0, s, (const double2*)part, nblk,
                      ncol * ncol, (double2*)Gtmp);
-  hipLaunchKernelGGL(k_gint_assemble, dim3(nblocks(ncol * ncol)), dim3(NT), 0, s, (const double2*)Gtmp, n, colmap,
-                     (double2*)g);
+  hipLaunchKernelGGL(k_gint_assemble, dim3(nblocks(ncol * ncol), b.ni), dim3(NT), 0, s, (const double2*)Gtmp, n,
+                     colmap, (double2*)g);
 }
 
 // =====================================================================
@@ -461,11 +364,13 @@ void launch_gint_full(const DevMesh& d, const double* phi, const double* W, cons
 __global__ void k_build_Mreal(const double2* __restrict__ Gamma, int n, const int* __restrict__ colmap,
                               double* __restrict__ Mr) {
   const int nn = n * n;
+  Gamma += (int64_t)blockIdx.y * nn * nn;
+  Mr += (int64_t)blockIdx.y * nn * nn;
   for (int o = blockIdx.x * NT + threadIdx.x; o < nn * nn; o += gridDim.x * NT) {
     int out = o / nn, col = o - out * nn;
     int oi = out / n, qi = out - oi * n;  // packed position
     int ro = oi < qi ? oi : qi, co = oi < qi ? qi : oi;
-    bool want_im = oi > qi;               // lower triangle holds Im U_{co? }
+    bool want_im = oi > qi;               // lower triangle holds the imaginary part
     // locate (r, s, part) of col
     int rr = 0, ss = 0, part = 0;
     for (int r = 0; r < n; ++r)
@@ -485,10 +390,14 @@ __global__ void k_build_Mreal(const double2* __restrict__ Gamma, int n, const in
   }
 }
 
-__global__ void __launch_bounds__(NT) k_build_U(DevMesh d, const double* __restrict__ W, const double* __restrict__ Mr,
-                                                double* __restrict__ Upk) {
+__global__ void __launch_bounds__(NT) k_build_U(const DevMesh* __restrict__ dm, const double* __restrict__ W,
+                                                const double* __restrict__ Mr, double* __restrict__ Upk) {
+  INSTANCE;
   __shared__ double sM[64 * 64];
   const int nn = d.n * d.n;
+  Mr += (int64_t)blockIdx.y * nn * nn;
+  W += d.oF * nn;
+  Upk += d.oE * nn;
   for (int e = threadIdx.x; e < nn * nn; e += NT) sM[e] = Mr[e];
   __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < d.NE; i += (int64_t)gridDim.x * NT) {
@@ -505,35 +414,42 @@ __global__ void __launch_bounds__(NT) k_build_U(DevMesh d, const double* __restr
   }
 }
 
-void launch_build_U_full(const DevMesh& d, const double* W, const double* Gamma, const int* colmap, double* Mr,
+void launch_build_U_full(const Batch& b, const double* W, const double* Gamma, const int* colmap, double* Mr,
                          double* Upk, hipStream_t s) {
-  const int nn = d.n * d.n;
-  hipLaunchKernelGGL(k_build_Mreal, dim3(nblocks(nn * nn)), dim3(NT), 0, s, (const double2*)Gamma, d.n, colmap, Mr);
-  hipLaunchKernelGGL(k_build_U, dim3(nblocks(d.NE, NT, 4096)), dim3(NT), 0, s, d, W, Mr, Upk);
+  const int nn = b.mx.n * b.mx.n;
+  hipLaunchKernelGGL(k_build_Mreal, dim3(nblocks(nn * nn), b.ni), dim3(NT), 0, s, (const double2*)Gamma, b.mx.n,
+                     colmap, Mr);
+  hipLaunchKernelGGL(k_build_U, dim3(nblocks(b.mx.NE, NT, 4096), b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
 }
 
 // =====================================================================
 // Krylov (Arnoldi) pieces.  M-inner product over the packed orbital vector:
-// <u,v> = sum_i m_i sum_p conj(u_ip) v_ip on rows [0, NE).
+// <u,v> = sum_i m_i sum_p conj(u_ip) v_ip on rows [0, NE) of each instance.
+// Per-instance strides: H (m_max+1) m_max, hcur m_max+1, y m_max, scal 8,
+// partials nblk (2 (m_max+1) + 1).
 // =====================================================================
 constexpr int KMAX = 25;
 
-__global__ void __launch_bounds__(NT) k_mdot(DevMesh d, const double2* const* __restrict__ V, int k,
-                                             const double2* __restrict__ w, int with_norm, double* __restrict__ part) {
+__device__ __forceinline__ int64_t kpart_stride(int nblk, int m_max) { return (int64_t)nblk * (2 * (m_max + 1) + 1); }
+
+__global__ void __launch_bounds__(NT) k_mdot(const DevMesh* __restrict__ dm, const double2* const* __restrict__ V,
+                                             int k, const double2* __restrict__ w, int with_norm, int m_max,
+                                             double* __restrict__ part) {
+  INSTANCE;
   __shared__ double lds[8];
   const int n = d.n;
-  const int64_t total = d.NE * n;
+  const int64_t total = d.NE * n, o = d.oE * n;
   double hr[KMAX], hi[KMAX], nrm = 0.0;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) { hr[j] = 0.0; hi[j] = 0.0; }
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const double mi = d.m[e / n];
-    const double2 w0 = w[e];
+    const double2 w0 = w[o + e];
     const double2 we = make_double2(mi * w0.x, mi * w0.y);
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
       if (j <= k) {
-        double2 vj = V[j][e];
+        double2 vj = V[j][o + e];
         hr[j] += vj.x * we.x + vj.y * we.y;
         hi[j] += vj.x * we.y - vj.y * we.x;
       }
@@ -541,23 +457,29 @@ __global__ void __launch_bounds__(NT) k_mdot(DevMesh d, const double2* const* __
     if (with_norm) nrm += we.x * w0.x + we.y * w0.y;
   }
   const int nv = 2 * (k + 1) + 1;
+  double* pb = part + blockIdx.y * kpart_stride(gridDim.x, m_max) + (int64_t)blockIdx.x * nv;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j <= k) {
       double a = block_sum(hr[j], lds);
-      if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nv + 2 * j] = a;
+      if (threadIdx.x == 0) pb[2 * j] = a;
       double b = block_sum(hi[j], lds);
-      if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nv + 2 * j + 1] = b;
+      if (threadIdx.x == 0) pb[2 * j + 1] = b;
     }
   }
   double c = block_sum(nrm, lds);
-  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nv + nv - 1] = c;
+  if (threadIdx.x == 0) pb[nv - 1] = c;
 }
 
 // Finish the dots: pass 1 sets column k of H, pass 2 adds (re-orthogonalisation).
 __global__ void k_mdot_finish(const double* __restrict__ part, int nblk, int k, int m_max, int pass,
                               double2* __restrict__ H, double2* __restrict__ hcur, double* __restrict__ scal) {
   __shared__ double lds4[4];
+  const int i = blockIdx.y;
+  part += i * kpart_stride(nblk, m_max);
+  H += (int64_t)i * (m_max + 1) * m_max;
+  hcur += (int64_t)i * (m_max + 1);
+  scal += 8 * i;
   const int nv = 2 * (k + 1) + 1;
   for (int v = 0; v < nv; ++v) {
     const double s = sum_partials(part, nblk, nv, v, lds4);
@@ -575,41 +497,48 @@ __global__ void k_mdot_finish(const double* __restrict__ part, int nblk, int k, 
   }
 }
 
-void launch_mdot(const DevMesh& d, double* const* V, int k, const double* w, Krylov& K, int pass, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot, dim3(K.nblk), dim3(NT), 0, s, d, (const double2* const*)V, k, (const double2*)w,
-                     pass == 1 ? 1 : 0, K.part);
-  hipLaunchKernelGGL(k_mdot_finish, dim3(1), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, pass, (double2*)K.H,
+void launch_mdot(const Batch& b, double* const* V, int k, const double* w, Krylov& K, int pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot, dim3(K.nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2* const*)V, k,
+                     (const double2*)w, pass == 1 ? 1 : 0, K.m_max, K.part);
+  hipLaunchKernelGGL(k_mdot_finish, dim3(1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, pass, (double2*)K.H,
                      (double2*)K.hcur, K.scal);
 }
 
-__global__ void __launch_bounds__(NT) k_orth_update(DevMesh d, const double2* const* __restrict__ V, int k,
+__global__ void __launch_bounds__(NT) k_orth_update(const DevMesh* __restrict__ dm,
+                                                    const double2* const* __restrict__ V, int k,
                                                     double2* __restrict__ w, const double2* __restrict__ hcur,
-                                                    int with_norm, double* __restrict__ part) {
+                                                    int with_norm, int m_max, double* __restrict__ part) {
+  INSTANCE;
   __shared__ double lds[8];
   const int n = d.n;
-  const int64_t total = d.NE * n;
+  const int64_t total = d.NE * n, o = d.oE * n;
+  hcur += (int64_t)blockIdx.y * (m_max + 1);
   double2 h[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) h[j] = (j <= k) ? hcur[j] : make_double2(0.0, 0.0);
   double nrm = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    double2 we = w[e];
+    double2 we = w[o + e];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
-      if (j <= k) we = csub(we, cmul(h[j], V[j][e]));
-    w[e] = we;
+      if (j <= k) we = csub(we, cmul(h[j], V[j][o + e]));
+    w[o + e] = we;
     if (with_norm) nrm += d.m[e / n] * (we.x * we.x + we.y * we.y);
   }
   if (with_norm) {
     double c = block_sum(nrm, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = c;
+    if (threadIdx.x == 0) part[blockIdx.y * kpart_stride(gridDim.x, m_max) + blockIdx.x] = c;
   }
 }
 
 // h_{k+1,k} = |w|; happy breakdown when h <= 1e-14 |G v_k| (then scale 0).
-__global__ void k_norm_finish(const double* __restrict__ part, int nblk, int k, int m_max,
-                              double2* __restrict__ H, double* __restrict__ scal) {
+__global__ void k_norm_finish(const double* __restrict__ part, int nblk, int k, int m_max, double2* __restrict__ H,
+                              double* __restrict__ scal) {
   __shared__ double lds4[4];
+  const int i = blockIdx.y;
+  part += i * kpart_stride(nblk, m_max);
+  H += (int64_t)i * (m_max + 1) * m_max;
+  scal += 8 * i;
   const double s = sum_partials(part, nblk, 1, 0, lds4);
   if (threadIdx.x != 0) return;
   double h = sqrt(s);
@@ -623,42 +552,50 @@ __global__ void k_norm_finish(const double* __restrict__ part, int nblk, int k, 
   }
 }
 
-void launch_orth_update(const DevMesh& d, double* const* V, int k, double* w, Krylov& K, int pass, hipStream_t s) {
-  hipLaunchKernelGGL(k_orth_update, dim3(K.nblk), dim3(NT), 0, s, d, (const double2* const*)V, k, (double2*)w,
-                     (const double2*)K.hcur, pass == 2 ? 1 : 0, K.part);
+void launch_orth_update(const Batch& b, double* const* V, int k, double* w, Krylov& K, int pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_orth_update, dim3(K.nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2* const*)V, k,
+                     (double2*)w, (const double2*)K.hcur, pass == 2 ? 1 : 0, K.m_max, K.part);
   if (pass == 2)
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, (double2*)K.H, K.scal);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, (double2*)K.H,
+                       K.scal);
 }
 
-__global__ void k_scale_by(const double2* __restrict__ src, double2* __restrict__ dst, int64_t total,
-                           const double* __restrict__ scal, int which) {
-  const double f = scal[which];
+__global__ void k_scale_by(const DevMesh* __restrict__ dm, const double2* __restrict__ src,
+                           double2* __restrict__ dst, const double* __restrict__ scal, int which) {
+  INSTANCE;
+  const int64_t total = d.NE * d.n, o = d.oE * d.n;
+  const double f = scal[8 * blockIdx.y + which];
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT)
-    dst[e] = cscale(f, src[e]);
+    dst[o + e] = cscale(f, src[o + e]);
 }
 
-void launch_krylov_scale(const DevMesh& d, const double* src, double* dst, Krylov& K, int which, int,
-                         hipStream_t s) {
-  const int64_t total = d.NE * d.n;
-  hipLaunchKernelGGL(k_scale_by, dim3(nblocks(total, NT, 8192)), dim3(NT), 0, s, (const double2*)src,
-                     (double2*)dst, total, K.scal, which);
+void launch_krylov_scale(const Batch& b, const double* src, double* dst, Krylov& K, int which, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_by, dim3(nblocks(b.mx.NE * b.mx.n, NT, 8192), b.ni), dim3(NT), 0, s, b.dm,
+                     (const double2*)src, (double2*)dst, K.scal, which);
 }
 
-__global__ void __launch_bounds__(NT) k_norm_part(DevMesh d, const double2* __restrict__ x,
-                                                  double* __restrict__ part) {
+__global__ void __launch_bounds__(NT) k_norm_part(const DevMesh* __restrict__ dm, const double2* __restrict__ x,
+                                                  int m_max, double* __restrict__ part) {
+  INSTANCE;
   __shared__ double lds[8];
   const int n = d.n;
-  const int64_t total = d.NE * n;
+  const int64_t total = d.NE * n, o = d.oE * n;
   double s = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT)
-    s += d.m[e / n] * (x[e].x * x[e].x + x[e].y * x[e].y);
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const double2 v = x[o + e];
+    s += d.m[e / n] * (v.x * v.x + v.y * v.y);
+  }
   double c = block_sum(s, lds);
-  if (threadIdx.x == 0) part[blockIdx.x] = c;
+  if (threadIdx.x == 0) part[blockIdx.y * kpart_stride(gridDim.x, m_max) + blockIdx.x] = c;
 }
 
 __global__ void k_beta_finish(const double* __restrict__ part, int nblk, int m, double* __restrict__ scal,
                               double2* __restrict__ H, int m_max) {
-  for (int i = threadIdx.x; i < (m_max + 1) * m_max; i += blockDim.x) H[i] = make_double2(0.0, 0.0);
+  const int i = blockIdx.y;
+  part += i * kpart_stride(nblk, m_max);
+  H += (int64_t)i * (m_max + 1) * m_max;
+  scal += 8 * i;
+  for (int t = threadIdx.x; t < (m_max + 1) * m_max; t += blockDim.x) H[t] = make_double2(0.0, 0.0);
   __shared__ double lds4[4];
   const double s = sum_partials(part, nblk, 1, 0, lds4);
   if (threadIdx.x != 0) return;
@@ -669,19 +606,24 @@ __global__ void k_beta_finish(const double* __restrict__ part, int nblk, int m, 
   scal[3] = 0.0;
 }
 
-void launch_norm_init(const DevMesh& d, const double* phi, Krylov& K, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_part, dim3(K.nblk), dim3(NT), 0, s, d, (const double2*)phi, K.part);
-  hipLaunchKernelGGL(k_beta_finish, dim3(1), dim3(NT), 0, s, K.part, K.nblk, m, K.scal, (double2*)K.H, K.m_max);
+void launch_norm_init(const Batch& b, const double* phi, Krylov& K, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_part, dim3(K.nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, K.m_max, K.part);
+  hipLaunchKernelGGL(k_beta_finish, dim3(1, b.ni), dim3(NT), 0, s, K.part, K.nblk, m, K.scal, (double2*)K.H,
+                     K.m_max);
 }
 
 // y = beta expm(A) e1, A = -i tau H_m (m = scal[4]); scaling and squaring
 // with a degree-18 Taylor polynomial at |A/2^s|_1 <= 1/2 (remainder below
-// 1e-22).  One workgroup; matrices in LDS.
+// 1e-22).  One workgroup per instance; matrices in LDS.
 __global__ void __launch_bounds__(NT) k_expm(const double2* __restrict__ H, int m_max, double tau_re, double tau_im,
                                              double* __restrict__ scal, double2* __restrict__ y) {
   __shared__ double2 A[KMAX * KMAX], T[KMAX * KMAX], S[KMAX * KMAX];
   __shared__ int sh_s;
   __shared__ double sh_norm;
+  const int inst = blockIdx.y;
+  H += (int64_t)inst * (m_max + 1) * m_max;
+  scal += 8 * inst;
+  y += (int64_t)inst * m_max;
   const int m = (int)scal[4];
   const int mm = m * m;
   // A = -i tau H = (tau_im - i tau_re) H
@@ -746,14 +688,17 @@ __global__ void __launch_bounds__(NT) k_expm(const double2* __restrict__ H, int 
   }
 }
 
-void launch_expm(Krylov& K, int, double tau_re, double tau_im, hipStream_t s) {
-  hipLaunchKernelGGL(k_expm, dim3(1), dim3(NT), 0, s, (const double2*)K.H, K.m_max, tau_re, tau_im, K.scal,
+void launch_expm(int ni, Krylov& K, double tau_re, double tau_im, hipStream_t s) {
+  hipLaunchKernelGGL(k_expm, dim3(1, ni), dim3(NT), 0, s, (const double2*)K.H, K.m_max, tau_re, tau_im, K.scal,
                      (double2*)K.y);
 }
 
-__global__ void __launch_bounds__(NT) k_combine(DevMesh d, const double2* const* __restrict__ V, int m,
-                                                double2* __restrict__ phi, const double2* __restrict__ y) {
-  const int64_t total = d.NE * d.n;
+__global__ void __launch_bounds__(NT) k_combine(const DevMesh* __restrict__ dm, const double2* const* __restrict__ V,
+                                                int m, int m_max, double2* __restrict__ phi,
+                                                const double2* __restrict__ y) {
+  INSTANCE;
+  const int64_t total = d.NE * d.n, o = d.oE * d.n;
+  y += (int64_t)blockIdx.y * m_max;
   double2 yy[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) yy[j] = (j < m) ? y[j] : make_double2(0.0, 0.0);
@@ -761,19 +706,19 @@ __global__ void __launch_bounds__(NT) k_combine(DevMesh d, const double2* const*
     double2 s = make_double2(0.0, 0.0);
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
-      if (j < m) s = cadd(s, cmul(yy[j], V[j][e]));
-    phi[e] = s;
+      if (j < m) s = cadd(s, cmul(yy[j], V[j][o + e]));
+    phi[o + e] = s;
   }
 }
 
-void launch_combine(const DevMesh& d, double* const* V, int m, double* phi, Krylov& K, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(nblocks(d.NE * d.n, NT, 8192)), dim3(NT), 0, s, d, (const double2* const*)V, m,
-                     (double2*)phi, (const double2*)K.y);
+void launch_combine(const Batch& b, double* const* V, int m, double* phi, Krylov& K, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(nblocks(b.mx.NE * b.mx.n, NT, 8192), b.ni), dim3(NT), 0, s, b.dm,
+                     (const double2* const*)V, m, K.m_max, (double2*)phi, (const double2*)K.y);
 }
 
 // =====================================================================
-// Poisson: moments, boundary values, right-hand side, Jacobi PCG.
-// Column c of the n^2 real columns is (r, s, part) = colinfo[c].
+// Poisson: moments, boundary values, right-hand side.  Column c of the n^2
+// real columns is (r, s, part) = colinfo[c].
 // =====================================================================
 constexpr int MP_CH = 32;
 constexpr int MP_MAXH = 169;  // (lmax+1)^2 for lmax <= 12
@@ -813,14 +758,17 @@ __device__ __forceinline__ double pair_density(const double2* phi, int n, int64_
   return part == 0 ? (a.x * b.x + a.y * b.y) : (a.x * b.y - a.y * b.x);
 }
 
-__global__ void __launch_bounds__(NT) k_moments(DevMesh d, const double2* __restrict__ phi, const double* __restrict__ xyz,
-                                                double center, int lmax, int ncol, const int* __restrict__ colinfo,
+__global__ void __launch_bounds__(NT) k_moments(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
+                                                int lmax, int ncol, const int* __restrict__ colinfo,
                                                 double* __restrict__ part) {
+  INSTANCE;
   __shared__ double sR[MP_CH * MP_MAXH];
   __shared__ double sW[MP_CH * 64];
   const int nh = (lmax + 1) * (lmax + 1);
   const int nout = nh * ncol;
   const int n = d.n;
+  phi += d.oE * n;
+  const double cx = d.center[0], cy = d.center[1], cz = d.center[2];
   constexpr int MAXO = 48;
   double accv[MAXO];
 #pragma unroll
@@ -833,7 +781,7 @@ __global__ void __launch_bounds__(NT) k_moments(DevMesh d, const double2* __rest
       double* R = sR + threadIdx.x * nh;
       if ((int)threadIdx.x < cnt) {
         int64_t i = base + threadIdx.x;
-        solid_regular(xyz[3 * i] - center, xyz[3 * i + 1] - center, xyz[3 * i + 2] - center, lmax, R);
+        solid_regular(d.xyz[3 * i] - cx, d.xyz[3 * i + 1] - cy, d.xyz[3 * i + 2] - cz, lmax, R);
       } else {
         for (int t = 0; t < nh; ++t) R[t] = 0.0;
       }
@@ -859,46 +807,54 @@ __global__ void __launch_bounds__(NT) k_moments(DevMesh d, const double2* __rest
       accv[j] = s;
     }
   }
+  double* pb = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout;
 #pragma unroll
   for (int j = 0; j < MAXO; ++j) {
     int o = threadIdx.x + j * NT;
-    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = accv[j];
+    if (o < nout) pb[o] = accv[j];
   }
 }
 
 __global__ void k_sum_parts_real(const double* __restrict__ part, int nblk, int nout, double* __restrict__ out) {
+  const double* pi = part + (int64_t)blockIdx.y * nblk * nout;
   for (int o = blockIdx.x * NT + threadIdx.x; o < nout; o += gridDim.x * NT) {
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nout + o];
-    out[o] = s;
+    for (int b = 0; b < nblk; ++b) s += pi[(int64_t)b * nout + o];
+    out[(int64_t)blockIdx.y * nout + o] = s;
   }
 }
 
 // W[NE + b][c] = sum_t table[b][t] Q[t][c]
-__global__ void k_bnd_eval(DevMesh d, const double* __restrict__ table, int nh, const double* __restrict__ Q, int ncol,
+__global__ void k_bnd_eval(const DevMesh* __restrict__ dm, int nh, const double* __restrict__ Q, int ncol,
                            double* __restrict__ W) {
+  INSTANCE;
   const int64_t total = d.Nb * ncol;
+  Q += (int64_t)blockIdx.y * nh * ncol;
+  W += d.oF * ncol;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     int64_t b = e / ncol;
     int c = (int)(e - b * ncol);
     double s = 0.0;
-    for (int t = 0; t < nh; ++t) s += table[b * nh + t] * Q[t * ncol + c];
+    for (int t = 0; t < nh; ++t) s += d.bnd_table[b * nh + t] * Q[t * ncol + c];
     W[(d.NE + b) * ncol + c] = s;
   }
 }
 
-// Poisson cell operator on real columns: acc += K_full x.  lift = 1: only the
-// listed boundary cells, with x taken as the boundary lift (boundary rows and
-// the boundary-master share of hanging rows; DoF rows read as zero).
+// Boundary lift through the element stiffness: acc += K_full x over the
+// listed boundary cells, with x the lift (boundary rows and the boundary-
+// master share of hanging rows; DoF rows read as zero).  x over full rows,
+// acc over extended rows; boundary rows of acc are skipped.
 template <int P>
-__global__ void __launch_bounds__(NT) k_cell_poisson(DevMesh d, const double* __restrict__ x, double* __restrict__ acc,
-                                                     int ncol, int lift) {
+__global__ void __launch_bounds__(NT) k_lift_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
+                                                     double* __restrict__ acc, int ncol) {
+  INSTANCE;
   constexpr int P3 = P * P * P;
   __shared__ double sx[P3 * 64];
   __shared__ int snode[P3];
-  const int64_t ncell = lift ? d.n_bnd_cells : d.nC;
-  for (int64_t cb = blockIdx.x; cb < ncell; cb += gridDim.x) {
-    const int64_t e = lift ? d.bnd_cells[cb] : cb;
+  x += d.oF * ncol;
+  acc += d.oE * ncol;
+  for (int64_t cb = blockIdx.x; cb < d.n_bnd_cells; cb += gridDim.x) {
+    const int64_t e = d.bnd_cells[cb];
     __syncthreads();
     for (int t = threadIdx.x; t < P3; t += NT) snode[t] = d.cell_nodes[e * P3 + t];
     __syncthreads();
@@ -906,9 +862,7 @@ __global__ void __launch_bounds__(NT) k_cell_poisson(DevMesh d, const double* __
       int t = idx / ncol, c = idx - t * ncol;
       int node = snode[t];
       double v = 0.0;
-      if (!lift) {
-        if (node < d.NE) v = x[(int64_t)node * ncol + c];
-      } else if (node >= d.NE) {
+      if (node >= d.NE) {
         v = x[(int64_t)node * ncol + c];
       } else if (node >= d.N) {
         int64_t h = node - d.N;
@@ -938,20 +892,24 @@ __global__ void __launch_bounds__(NT) k_cell_poisson(DevMesh d, const double* __
   }
 }
 
-void launch_cell_poisson(const DevMesh& d, const double* x, double* acc, int ncol, int lift, hipStream_t s) {
-  int64_t ncell = lift ? d.n_bnd_cells : d.nC;
+static void launch_lift_poisson(const Batch& b, const double* x, double* acc, int ncol, hipStream_t s) {
+  const int64_t ncell = b.mx.n_bnd_cells;
   if (ncell == 0) return;
-  int nb = (int)(ncell < 65536 ? ncell : 65536);
-  switch (d.P) {
-    case 2: hipLaunchKernelGGL(k_cell_poisson<2>, dim3(nb), dim3(NT), 0, s, d, x, acc, ncol, lift); break;
-    case 3: hipLaunchKernelGGL(k_cell_poisson<3>, dim3(nb), dim3(NT), 0, s, d, x, acc, ncol, lift); break;
-    default: hipLaunchKernelGGL(k_cell_poisson<4>, dim3(nb), dim3(NT), 0, s, d, x, acc, ncol, lift);
+  const dim3 g((unsigned)(ncell < 65536 ? ncell : 65536), b.ni);
+  switch (b.mx.P) {
+    case 2: hipLaunchKernelGGL(k_lift_poisson<2>, g, dim3(NT), 0, s, b.dm, x, acc, ncol); break;
+    case 3: hipLaunchKernelGGL(k_lift_poisson<3>, g, dim3(NT), 0, s, b.dm, x, acc, ncol); break;
+    default: hipLaunchKernelGGL(k_lift_poisson<4>, g, dim3(NT), 0, s, b.dm, x, acc, ncol);
   }
 }
 
 // Hanging rows of a real column array; with_bnd includes boundary masters.
-__global__ void k_fill_real(DevMesh d, double* __restrict__ x, int ncol, int with_bnd, double* __restrict__ acc) {
+__global__ void k_fill_real(const DevMesh* __restrict__ dm, double* __restrict__ x, int xfull, int ncol,
+                            int with_bnd, double* __restrict__ acc) {
+  INSTANCE;
   const int64_t total = d.Nh * ncol;
+  x += (xfull ? d.oF : d.oE) * ncol;
+  if (acc) acc += d.oE * ncol;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     int64_t h = e / ncol;
     int c = (int)(e - h * ncol);
@@ -965,26 +923,36 @@ __global__ void k_fill_real(DevMesh d, double* __restrict__ x, int ncol, int wit
   }
 }
 
-void launch_fill_real(const DevMesh& d, double* x, int ncol, int with_bnd, double* acc, hipStream_t s) {
-  if (d.Nh == 0) return;
-  hipLaunchKernelGGL(k_fill_real, dim3(nblocks(d.Nh * ncol)), dim3(NT), 0, s, d, x, ncol, with_bnd, acc);
+void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s) {
+  if (b.mx.Nh == 0) return;
+  hipLaunchKernelGGL(k_fill_real, dim3(nblocks(b.mx.Nh * ncol), b.ni), dim3(NT), 0, s, b.dm, x, xfull, ncol,
+                     with_bnd, acc);
 }
 
-// Column-wise partial sums over rows with thread layout (row group, column).
-struct ColLayout {
-  int ncol, groups;
-};
+// Zero rows [lo, hi) (lo, hi: 0 = 0, 1 = N, 2 = NE) of a real column array over extended rows.
+__global__ void k_zero_rows(const DevMesh* __restrict__ dm, double* __restrict__ x, int ncol, int lo, int hi) {
+  INSTANCE;
+  const int64_t r0 = lo == 0 ? 0 : (lo == 1 ? d.N : d.NE), r1 = hi == 0 ? 0 : (hi == 1 ? d.N : d.NE);
+  x += (d.oE + r0) * ncol;
+  const int64_t total = (r1 - r0) * ncol;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) x[e] = 0.0;
+}
 
-// RHS: b = 4 pi C^T (m rho) - C^T acc;  r = b (cold start);  partial |b|^2.
-__global__ void __launch_bounds__(NT) k_poisson_rhs(DevMesh d, const double2* __restrict__ phi, double* __restrict__ acc,
-                                                    int ncol, const int* __restrict__ colinfo, double* __restrict__ rhs,
-                                                    double* __restrict__ part) {
+// RHS: b = 4 pi C^T (m rho) - C^T acc;  partial |b|^2 (acc DoF rows zeroed).
+__global__ void __launch_bounds__(NT) k_poisson_rhs(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
+                                                    double* __restrict__ acc, int ncol,
+                                                    const int* __restrict__ colinfo, double* __restrict__ rhs,
+                                                    int64_t part_stride, double* __restrict__ part) {
+  INSTANCE;
   __shared__ double lds[NT];
   const int groups = NT / ncol;
   const int g = threadIdx.x / ncol, c = threadIdx.x - g * ncol;
   const bool act = g < groups;
   double bb = 0.0;
   const int n = d.n;
+  phi += d.oE * n;
+  acc += d.oE * ncol;
+  rhs += d.oE * ncol;
   const int ci = colinfo[act ? c : 0];
   const int r = ci & 255, s = (ci >> 8) & 255, pr = ci >> 16;
   if (act)
@@ -1005,250 +973,64 @@ __global__ void __launch_bounds__(NT) k_poisson_rhs(DevMesh d, const double2* __
   if (threadIdx.x < ncol) {
     double t = 0.0;
     for (int q = 0; q < groups; ++q) t += lds[q * ncol + threadIdx.x];
-    part[(int64_t)blockIdx.x * ncol + threadIdx.x] = t;
+    part[blockIdx.y * part_stride + (int64_t)blockIdx.x * ncol + threadIdx.x] = t;
   }
 }
 
-// q = C^T acc (zeroing acc DoF rows); partial p.q
-__global__ void __launch_bounds__(NT) k_cg_epi(DevMesh d, double* __restrict__ acc, const double* __restrict__ p,
-                                               double* __restrict__ q, int ncol, double* __restrict__ part) {
-  __shared__ double lds[NT];
-  const int groups = NT / ncol;
-  const int g = threadIdx.x / ncol, c = threadIdx.x - g * ncol;
-  const bool act = g < groups;
-  double pq = 0.0;
-  if (act)
-    for (int64_t k = (int64_t)blockIdx.x * groups + g; k < d.N; k += (int64_t)gridDim.x * groups) {
-      double f = acc[k * ncol + c];
-      acc[k * ncol + c] = 0.0;
-      int mi = d.ma_index[k];
-      if (mi >= 0)
-        for (int t = d.ct_ptr[mi]; t < d.ct_ptr[mi + 1]; ++t) f += d.ct_w[t] * acc[(int64_t)d.ct_row[t] * ncol + c];
-      q[k * ncol + c] = f;
-      pq += f * p[k * ncol + c];
-    }
-  lds[threadIdx.x] = act ? pq : 0.0;
-  __syncthreads();
-  if (threadIdx.x < ncol) {
-    double t = 0.0;
-    for (int qq = 0; qq < groups; ++qq) t += lds[qq * ncol + threadIdx.x];
-    part[(int64_t)blockIdx.x * ncol + threadIdx.x] = t;
-  }
-}
-
-// scalar slots in sc[slot * ncol + c] (SC_* in kernels.hpp)
-
-__global__ void k_col_finish(const double* __restrict__ part, int nblk, int ncol, double* __restrict__ sc, int slot,
-                             int mode) {
+// sc[i][slot][c] = sum_b part[i][b][c]
+__global__ void k_col_sum(const double* __restrict__ part, int64_t part_stride, int nblk, int ncol,
+                          double* __restrict__ sc, int slot) {
+  part += blockIdx.y * part_stride;
   for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ncol + c];
-    if (mode == 0) {
-      sc[slot * ncol + c] = s;
-    } else if (mode == 1) {  // alpha = rz / pq
-      sc[SC_PQ * ncol + c] = s;
-      double rz = sc[SC_RZ * ncol + c];
-      sc[SC_ALPHA * ncol + c] = (s != 0.0 && rz != 0.0) ? rz / s : 0.0;
-    } else if (mode == 2) {  // beta = rz_new / rz (and rr from second half)
-      double rz = sc[SC_RZ * ncol + c];
-      sc[SC_BETA * ncol + c] = (rz != 0.0) ? s / rz : 0.0;
-      sc[SC_RZ * ncol + c] = s;
-    }
+    sc[(int64_t)blockIdx.y * 8 * ncol + slot * ncol + c] = s;
   }
 }
 
-// x += alpha p; r -= alpha q; z = D^-1 r; partials (r.z, r.r)
-__global__ void __launch_bounds__(NT) k_cg_update(DevMesh d, double* __restrict__ x, double* __restrict__ r,
-                                                  const double* __restrict__ p, const double* __restrict__ q, int ncol,
-                                                  const double* __restrict__ sc, double* __restrict__ part) {
-  __shared__ double lds[2 * NT];
-  const int groups = NT / ncol;
-  const int g = threadIdx.x / ncol, c = threadIdx.x - g * ncol;
-  const bool act = g < groups;
-  double rz = 0.0, rr = 0.0;
-  if (act) {
-    const double al = sc[SC_ALPHA * ncol + c];
-    for (int64_t k = (int64_t)blockIdx.x * groups + g; k < d.N; k += (int64_t)gridDim.x * groups) {
-      int64_t e = k * ncol + c;
-      x[e] += al * p[e];
-      double rn = r[e] - al * q[e];
-      r[e] = rn;
-      rz += rn * rn * d.kdiag_inv[k];
-      rr += rn * rn;
-    }
-  }
-  lds[threadIdx.x] = act ? rz : 0.0;
-  lds[NT + threadIdx.x] = act ? rr : 0.0;
-  __syncthreads();
-  if (threadIdx.x < ncol) {
-    double t = 0.0, u = 0.0;
-    for (int qq = 0; qq < groups; ++qq) {
-      t += lds[qq * ncol + threadIdx.x];
-      u += lds[NT + qq * ncol + threadIdx.x];
-    }
-    part[(int64_t)blockIdx.x * 2 * ncol + threadIdx.x] = t;
-    part[(int64_t)blockIdx.x * 2 * ncol + ncol + threadIdx.x] = u;
-  }
-}
+static int rhs_blocks(const Batch& b, int ncol) { return nblocks(b.mx.N, NT / ncol, 1024); }
 
-__global__ void k_cg_finish2(const double* __restrict__ part, int nblk, int ncol, double* __restrict__ sc) {
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    double s = 0.0, u = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      s += part[(int64_t)b * 2 * ncol + c];
-      u += part[(int64_t)b * 2 * ncol + ncol + c];
-    }
-    double rz = sc[SC_RZ * ncol + c];
-    sc[SC_BETA * ncol + c] = (rz != 0.0) ? s / rz : 0.0;
-    sc[SC_RZ * ncol + c] = s;
-    sc[SC_RR * ncol + c] = u;
-  }
-}
-
-// p = D^-1 r + beta p (DoF rows)
-__global__ void k_cg_p(DevMesh d, const double* __restrict__ r, double* __restrict__ p, int ncol,
-                       const double* __restrict__ sc) {
-  const int64_t total = d.N * ncol;
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    int64_t k = e / ncol;
-    int c = (int)(e - k * ncol);
-    p[e] = d.kdiag_inv[k] * r[e] + sc[SC_BETA * ncol + c] * p[e];
-  }
-}
-
-static int col_blocks(const DevMesh& d, int ncol) {
-  int groups = NT / ncol;
-  return nblocks(d.N, groups, 1024);
-}
-
-void launch_poisson_pipeline_moments(const DevMesh& d, const double* phi, const double* xyz, const int* colinfo,
-                                     PoissonWs& P, hipStream_t s) {
+void launch_poisson_pipeline_moments(const Batch& b, const double* phi, const int* colinfo, PoissonWs& P,
+                                     hipStream_t s) {
   const int nout = P.nharm * P.ncol;
-  hipLaunchKernelGGL(k_moments, dim3(P.mblk), dim3(NT), 0, s, d, (const double2*)phi, xyz, P.center, P.lmax, P.ncol,
+  hipLaunchKernelGGL(k_moments, dim3(P.mblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, P.lmax, P.ncol,
                      colinfo, P.mpart);
-  hipLaunchKernelGGL(k_sum_parts_real, dim3(nblocks(nout)), dim3(NT), 0, s, P.mpart, P.mblk, nout, P.Q);
+  hipLaunchKernelGGL(k_sum_parts_real, dim3(nblocks(nout), b.ni), dim3(NT), 0, s, P.mpart, P.mblk, nout, P.Q);
 }
 
-void launch_bnd_eval(const DevMesh& d, PoissonWs& P, double* W, hipStream_t s) {
-  if (d.Nb == 0) return;
-  hipLaunchKernelGGL(k_bnd_eval, dim3(nblocks(d.Nb * P.ncol)), dim3(NT), 0, s, d, P.table, P.nharm, P.Q, P.ncol, W);
+void launch_bnd_eval(const Batch& b, PoissonWs& P, double* W, hipStream_t s) {
+  if (b.mx.Nb == 0) return;
+  hipLaunchKernelGGL(k_bnd_eval, dim3(nblocks(b.mx.Nb * P.ncol), b.ni), dim3(NT), 0, s, b.dm, P.nharm, P.Q, P.ncol,
+                     W);
 }
 
-void launch_poisson_rhs_full(const DevMesh& d, const double* phi, double* W, const int* colinfo, double* rhs,
+void launch_poisson_rhs_full(const Batch& b, const double* phi, double* W, const int* colinfo, double* rhs,
                              PoissonWs& P, hipStream_t s) {
   const int ncol = P.ncol;
-  launch_zero(P.acc, d.NE * ncol, s);  // the lift pass accumulates with atomics
-  // boundary lift through the stiffness, then C^T and the density load
-  launch_cell_poisson(d, W, P.acc, ncol, 1, s);
-  int nb = col_blocks(d, ncol);
-  hipLaunchKernelGGL(k_poisson_rhs, dim3(nb), dim3(NT), 0, s, d, (const double2*)phi, P.acc, ncol, colinfo, rhs,
-                     P.part);
-  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(64), 0, s, P.part, nb, ncol, P.sc, (int)SC_BB, 0);
+  launch_zero(P.acc, b.tE * ncol, s);  // the lift pass accumulates with atomics
+  launch_lift_poisson(b, W, P.acc, ncol, s);
+  const int nb = rhs_blocks(b, ncol);
+  hipLaunchKernelGGL(k_poisson_rhs, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, P.acc, ncol, colinfo,
+                     rhs, P.part_stride, P.part);
+  hipLaunchKernelGGL(k_col_sum, dim3(1, b.ni), dim3(64), 0, s, P.part, P.part_stride, nb, ncol, P.sc, (int)SC_BB);
   // hanging rows of acc back to zero
-  launch_zero(P.acc + d.N * ncol, d.Nh * ncol, s);
+  if (b.mx.Nh > 0)
+    hipLaunchKernelGGL(k_zero_rows, dim3(nblocks(b.mx.Nh * ncol, NT, 4096), b.ni), dim3(NT), 0, s, b.dm, P.acc,
+                       ncol, 1, 2);
 }
-
-// Operator apply q = K p (p DoF rows given; hanging rows filled here).
-[[maybe_unused]] static void cg_apply_atomic(const DevMesh& d, PoissonWs& P, double* pvec, double* qvec, hipStream_t s) {
-  const int ncol = P.ncol;
-  launch_fill_real(d, pvec, ncol, 0, P.acc, s);
-  const bool rec = P.ev && P.ev_used + 2 <= P.ev_cap;
-  if (rec) (void)hipEventRecord(P.ev[P.ev_used], s);
-  launch_cell_poisson(d, pvec, P.acc, ncol, 0, s);
-  if (rec) {
-    (void)hipEventRecord(P.ev[P.ev_used + 1], s);
-    P.ev_used += 2;
-  }
-  int nb = col_blocks(d, ncol);
-  hipLaunchKernelGGL(k_cg_epi, dim3(nb), dim3(NT), 0, s, d, P.acc, pvec, qvec, ncol, P.part);
-  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(64), 0, s, P.part, nb, ncol, P.sc, (int)SC_PQ, 1);
-}
-
-__global__ void k_cg_start(DevMesh d, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ q,
-                           double* __restrict__ p, int ncol, int warm) {
-  const int64_t total = d.N * ncol;
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    int64_t k = e / ncol;
-    double rn = warm ? r[e] - q[e] : r[e];
-    if (!warm) x[e] = 0.0;
-    r[e] = rn;
-    p[e] = d.kdiag_inv[k] * rn;
-  }
-}
-
-__global__ void __launch_bounds__(NT) k_rz_part(DevMesh d, const double* __restrict__ r, int ncol,
-                                                double* __restrict__ part) {
-  __shared__ double lds[2 * NT];
-  const int groups = NT / ncol;
-  const int g = threadIdx.x / ncol, c = threadIdx.x - g * ncol;
-  const bool act = g < groups;
-  double rz = 0.0, rr = 0.0;
-  if (act)
-    for (int64_t k = (int64_t)blockIdx.x * groups + g; k < d.N; k += (int64_t)gridDim.x * groups) {
-      double rn = r[k * ncol + c];
-      rz += rn * rn * d.kdiag_inv[k];
-      rr += rn * rn;
-    }
-  lds[threadIdx.x] = act ? rz : 0.0;
-  lds[NT + threadIdx.x] = act ? rr : 0.0;
-  __syncthreads();
-  if (threadIdx.x < ncol) {
-    double t = 0.0, u = 0.0;
-    for (int qq = 0; qq < groups; ++qq) {
-      t += lds[qq * ncol + threadIdx.x];
-      u += lds[NT + qq * ncol + threadIdx.x];
-    }
-    part[(int64_t)blockIdx.x * 2 * ncol + threadIdx.x] = t;
-    part[(int64_t)blockIdx.x * 2 * ncol + ncol + threadIdx.x] = u;
-  }
-}
-
-__global__ void k_cg_start_finish(const double* __restrict__ part, int nblk, int ncol, double* __restrict__ sc) {
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    double s = 0.0, u = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      s += part[(int64_t)b * 2 * ncol + c];
-      u += part[(int64_t)b * 2 * ncol + ncol + c];
-    }
-    sc[SC_RZ * ncol + c] = s;
-    sc[SC_RR * ncol + c] = u;
-  }
-}
-
-// Start: r = rhs - K x0 (warm) or rhs (cold, x0 = 0), p = z = D^-1 r.
-void launch_cg_start_atomic(const DevMesh& d, double* W, double* rhs_r, PoissonWs& P, int warm, hipStream_t s) {
-  const int ncol = P.ncol;
-  if (warm) {
-    // q = K x0 using p as staging for x0 (DoF rows)
-    hipLaunchKernelGGL(k_copy, dim3(nblocks(d.N * ncol, NT, 8192)), dim3(NT), 0, s, W, P.p, d.N * ncol);
-    cg_apply_atomic(d, P, P.p, P.q, s);
-  }
-  hipLaunchKernelGGL(k_cg_start, dim3(nblocks(d.N * ncol, NT, 8192)), dim3(NT), 0, s, d, W, rhs_r, P.q, P.p, ncol,
-                     warm);
-  int nb = col_blocks(d, ncol);
-  hipLaunchKernelGGL(k_rz_part, dim3(nb), dim3(NT), 0, s, d, rhs_r, ncol, P.part);
-  hipLaunchKernelGGL(k_cg_start_finish, dim3(1), dim3(64), 0, s, P.part, nb, ncol, P.sc);
-}
-
-void launch_cg_step_atomic(const DevMesh& d, double* W, PoissonWs& P, hipStream_t s) {
-  const int ncol = P.ncol;
-  cg_apply_atomic(d, P, P.p, P.q, s);
-  int nb = col_blocks(d, ncol);
-  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(NT), 0, s, d, W, P.r, P.p, P.q, ncol, P.sc, P.part);
-  hipLaunchKernelGGL(k_cg_finish2, dim3(1), dim3(64), 0, s, P.part, nb, ncol, P.sc);
-  hipLaunchKernelGGL(k_cg_p, dim3(nblocks(d.N * ncol, NT, 8192)), dim3(NT), 0, s, d, P.r, P.p, ncol, P.sc);
-}
-
 
 // =====================================================================
-// Small dense kernels (one workgroup / one thread).
+// Small dense kernels (one workgroup per instance, work on thread 0).
 // =====================================================================
 // Regularised inverse of the Hermitian 1-RDM: eigen-decomposition of the
 // real 2n x 2n embedding [[Re, -Im], [Im, Re]] by cyclic Jacobi, d -> d +
 // eps exp(-d/eps), inverse from the eigenpairs.
 __global__ void k_ginv(const double2* __restrict__ gamma, int n, double eps, double2* __restrict__ ginv,
                        int* __restrict__ flag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (threadIdx.x != 0) return;
+  const int inst = blockIdx.x;
+  gamma += (int64_t)inst * n * n;
+  ginv += (int64_t)inst * n * n;
   const int N2 = 2 * n;
   double a[16 * 16], V[16 * 16];
   for (int i = 0; i < n; ++i)
@@ -1312,48 +1094,61 @@ __global__ void k_ginv(const double2* __restrict__ gamma, int n, double eps, dou
       }
       ginv[i * n + j] = make_double2(re, im);
     }
-  *flag = bad;
+  flag[inst] = bad;
 }
 
-void launch_ginv(const double* gamma, int n, double eps, double* ginv, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_ginv, dim3(1), dim3(64), 0, s, (const double2*)gamma, n, eps, (double2*)ginv, flag);
+void launch_ginv(int ni, const double* gamma, int n, double eps, double* ginv, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_ginv, dim3(ni), dim3(64), 0, s, (const double2*)gamma, n, eps, (double2*)ginv, flag);
 }
 
-// out: [0] energy, [1] dipole, [2] max |S - I|, [3] sum |C|^2 (unused here)
-__global__ void k_observe(const double2* __restrict__ gamma, const double2* __restrict__ Gamma,
-                          const double2* __restrict__ h, const double2* __restrict__ g, const double2* __restrict__ z,
-                          const double2* __restrict__ S, int n, double vnn, double* __restrict__ out) {
+// out[i]: [0] energy, [1] dipole, [2] max |S - I|
+__global__ void k_observe(const DevMesh* __restrict__ dm, const double2* __restrict__ gamma,
+                          const double2* __restrict__ Gamma, const double2* __restrict__ h,
+                          const double2* __restrict__ g, const double2* __restrict__ z, const double2* __restrict__ S,
+                          double* __restrict__ out) {
   if (threadIdx.x != 0) return;
+  const int inst = blockIdx.x;
+  const DevMesh& d = dm[inst];
+  const int n = d.n, nn = n * n;
+  gamma += (int64_t)inst * nn;
+  Gamma += (int64_t)inst * nn * nn;
+  h += (int64_t)inst * nn;
+  g += (int64_t)inst * nn * nn;
+  z += (int64_t)inst * nn;
+  S += (int64_t)inst * nn;
+  out += 8 * inst;
   double e1 = 0.0, e2 = 0.0, dip = 0.0, orth = 0.0;
-  for (int i = 0; i < n * n; ++i) {
+  for (int i = 0; i < nn; ++i) {
     e1 += h[i].x * gamma[i].x - h[i].y * gamma[i].y;
     dip += gamma[i].x * z[i].x - gamma[i].y * z[i].y;
     int p = i / n, q = i % n;
     double dx = S[i].x - (p == q ? 1.0 : 0.0);
     orth = fmax(orth, hypot(dx, S[i].y));
   }
-  for (int i = 0; i < n * n * n * n; ++i) e2 += g[i].x * Gamma[i].x - g[i].y * Gamma[i].y;
-  out[0] = e1 + 0.5 * e2 + vnn;
+  for (int i = 0; i < nn * nn; ++i) e2 += g[i].x * Gamma[i].x - g[i].y * Gamma[i].y;
+  out[0] = e1 + 0.5 * e2 + d.vnn;
   out[1] = dip;
   out[2] = orth;
 }
 
-void launch_observe(const double* gamma, const double* Gamma, const double* h, const double* g, const double* zmat,
-                    const double* S, int n, double vnn, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_observe, dim3(1), dim3(64), 0, s, (const double2*)gamma, (const double2*)Gamma,
-                     (const double2*)h, (const double2*)g, (const double2*)zmat, (const double2*)S, n, vnn, out);
+void launch_observe(const Batch& b, const double* gamma, const double* Gamma, const double* h, const double* g,
+                    const double* zmat, const double* S, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_observe, dim3(b.ni), dim3(64), 0, s, b.dm, (const double2*)gamma, (const double2*)Gamma,
+                     (const double2*)h, (const double2*)g, (const double2*)zmat, (const double2*)S, out);
 }
 
 // Gram-Schmidt in M as x <- x R^-1 with S = R^H R (Cholesky), R upper.
 __global__ void k_chol_inv(const double2* __restrict__ S, int n, double2* __restrict__ Rinv) {
   if (threadIdx.x != 0) return;
+  S += (int64_t)blockIdx.x * n * n;
+  Rinv += (int64_t)blockIdx.x * n * n;
   double2 R[64], Ri[64];
   for (int i = 0; i < n * n; ++i) { R[i] = make_double2(0, 0); Ri[i] = make_double2(0, 0); }
   for (int j = 0; j < n; ++j) {
     // R_jj = sqrt(S_jj - sum_k |R_kj|^2); R_ji = (S_ji - sum_k conj(R_kj) R_ki) / R_jj
-    double d = S[j * n + j].x;
-    for (int k = 0; k < j; ++k) d -= R[k * n + j].x * R[k * n + j].x + R[k * n + j].y * R[k * n + j].y;
-    double rjj = sqrt(fmax(d, 1e-300));
+    double dd = S[j * n + j].x;
+    for (int k = 0; k < j; ++k) dd -= R[k * n + j].x * R[k * n + j].x + R[k * n + j].y * R[k * n + j].y;
+    double rjj = sqrt(fmax(dd, 1e-300));
     R[j * n + j] = make_double2(rjj, 0.0);
     for (int i = j + 1; i < n; ++i) {
       double2 s = S[j * n + i];
@@ -1373,8 +1168,11 @@ __global__ void k_chol_inv(const double2* __restrict__ S, int n, double2* __rest
   for (int i = 0; i < n * n; ++i) Rinv[i] = Ri[i];
 }
 
-__global__ void k_right_mul(DevMesh d, double2* __restrict__ x, const double2* __restrict__ Ri) {
+__global__ void k_right_mul(const DevMesh* __restrict__ dm, double2* __restrict__ x, const double2* __restrict__ Ri) {
+  INSTANCE;
   const int n = d.n;
+  x += d.oE * n;
+  Ri += (int64_t)blockIdx.y * n * n;
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < d.NE; i += (int64_t)gridDim.x * NT) {
     double2 row[8], out[8];
     for (int p = 0; p < n; ++p) row[p] = x[i * n + p];
@@ -1387,19 +1185,22 @@ __global__ void k_right_mul(DevMesh d, double2* __restrict__ x, const double2* _
   }
 }
 
-void launch_orthonormalize_full(const DevMesh& d, const double* S, double* Rinv, double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, s, (const double2*)S, d.n, (double2*)Rinv);
-  hipLaunchKernelGGL(k_right_mul, dim3(nblocks(d.NE, NT, 4096)), dim3(NT), 0, s, d, (double2*)x,
+void launch_orthonormalize_full(const Batch& b, const double* S, double* Rinv, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(b.ni), dim3(64), 0, s, (const double2*)S, b.mx.n, (double2*)Rinv);
+  hipLaunchKernelGGL(k_right_mul, dim3(nblocks(b.mx.NE, NT, 4096), b.ni), dim3(NT), 0, s, b.dm, (double2*)x,
                      (const double2*)Rinv);
 }
 
 // =====================================================================
-// CI: excitation-table sigma vector, RDMs, Lanczos in one workgroup.
-// Tables: ex[J][p*n+q] = I | (sign<0) << 30 with E_pq |I> = sign |J>, or -1.
+// CI: excitation-table sigma vector, RDMs, Lanczos in one workgroup per
+// instance.  Tables: ex[J][p*n+q] = I | (sign<0) << 30 with E_pq |I> =
+// sign |J>, or -1.  Vectors of instance i at offset i * dim.
 // =====================================================================
 __global__ void k_ci_D(CIDev c, const double2* __restrict__ C, double2* __restrict__ D) {
   const int nn = c.n * c.n;
   const int64_t total = (int64_t)c.dim * nn;
+  C += (int64_t)blockIdx.y * c.dim;
+  D += (int64_t)blockIdx.y * total;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     int J = (int)(e / nn), pq = (int)(e - (int64_t)J * nn);
     int Ja = J / c.NB, Jb = J - Ja * c.NB;
@@ -1418,8 +1219,8 @@ __global__ void k_ci_D(CIDev c, const double2* __restrict__ C, double2* __restri
   }
 }
 
-void launch_ci_D(const CIDev& c, const double* C, hipStream_t s) {
-  hipLaunchKernelGGL(k_ci_D, dim3(nblocks((int64_t)c.dim * c.n * c.n)), dim3(NT), 0, s, c, (const double2*)C,
+static void launch_ci_D(int ni, const CIDev& c, const double* C, hipStream_t s) {
+  hipLaunchKernelGGL(k_ci_D, dim3(nblocks((int64_t)c.dim * c.n * c.n), ni), dim3(NT), 0, s, c, (const double2*)C,
                      (double2*)c.D);
 }
 
@@ -1427,6 +1228,9 @@ void launch_ci_D(const CIDev& c, const double* C, hipStream_t s) {
 __global__ void k_ci_gamma2(const double2* __restrict__ G, const double2* __restrict__ gamma, int n,
                             double2* __restrict__ Gamma) {
   const int nn = n * n;
+  G += (int64_t)blockIdx.y * nn * nn;
+  gamma += (int64_t)blockIdx.y * nn;
+  Gamma += (int64_t)blockIdx.y * nn * nn;
   for (int o = blockIdx.x * NT + threadIdx.x; o < nn * nn; o += gridDim.x * NT) {
     int s = o % n, r = (o / n) % n, q = (o / nn) % n, p = o / (nn * n);
     double2 v = G[(q * n + p) * nn + (r * n + s)];
@@ -1435,37 +1239,46 @@ __global__ void k_ci_gamma2(const double2* __restrict__ G, const double2* __rest
   }
 }
 
-void launch_ci_rdm_full(const CIDev& c, const double* C, double* gamma, double* Gamma, double* Gtmp, hipStream_t s) {
+void launch_ci_rdm_full(int ni, const CIDev& c, const double* C, double* gamma, double* Gamma, double* Gtmp,
+                        hipStream_t s) {
   const int nn = c.n * c.n;
-  launch_ci_D(c, C, s);
+  launch_ci_D(ni, c, C, s);
   int nb = gram_blocks(c.dim);
-  launch_xgram(C, 1, c.D, nn, 0, nullptr, c.dim, c.part, nb, gamma, s);   // gamma[pq] = C^H D_pq
-  launch_xgram(c.D, nn, c.D, nn, 0, nullptr, c.dim, c.part, nb, Gtmp, s);
-  hipLaunchKernelGGL(k_ci_gamma2, dim3(nblocks(nn * nn)), dim3(NT), 0, s, (const double2*)Gtmp,
+  launch_xgram_flat(ni, C, 1, c.D, nn, c.dim, c.part, nb, gamma, s);   // gamma[pq] = C^H D_pq
+  launch_xgram_flat(ni, c.D, nn, c.D, nn, c.dim, c.part, nb, Gtmp, s);
+  hipLaunchKernelGGL(k_ci_gamma2, dim3(nblocks(nn * nn), ni), dim3(NT), 0, s, (const double2*)Gtmp,
                      (const double2*)gamma, c.n, (double2*)Gamma);
 }
 
 // h'_pq = h_pq - 1/2 sum_q' g_pq'q'q
 __global__ void k_ci_hprime(const double2* __restrict__ h, const double2* __restrict__ g, int n,
                             double2* __restrict__ hp) {
-  for (int o = threadIdx.x; o < n * n; o += blockDim.x) {
+  const int nn = n * n;
+  h += (int64_t)blockIdx.x * nn;
+  g += (int64_t)blockIdx.x * nn * nn;
+  hp += (int64_t)blockIdx.x * nn;
+  for (int o = threadIdx.x; o < nn; o += blockDim.x) {
     int p = o / n, q = o % n;
     double2 s = h[o];
     for (int k = 0; k < n; ++k) s = csub(s, cscale(0.5, g[((p * n + k) * n + k) * n + q]));
     hp[o] = s;
   }
 }
-void launch_ci_hprime(const CIDev& c, const double* h, const double* g, hipStream_t s) {
-  hipLaunchKernelGGL(k_ci_hprime, dim3(1), dim3(64), 0, s, (const double2*)h, (const double2*)g, c.n, (double2*)c.hp);
+void launch_ci_hprime(int ni, const CIDev& c, const double* h, const double* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_ci_hprime, dim3(ni), dim3(64), 0, s, (const double2*)h, (const double2*)g, c.n,
+                     (double2*)c.hp);
 }
 
 // T[J][pq] = h'_pq C[J] + 1/2 sum_rs g_pqrs D[J][rs]
 __global__ void k_ci_T(CIDev c, const double2* __restrict__ C, const double2* __restrict__ g) {
   const int nn = c.n * c.n;
   const int64_t total = (int64_t)c.dim * nn;
-  const double2* D = (const double2*)c.D;
-  const double2* hp = (const double2*)c.hp;
-  double2* T = (double2*)c.T;
+  const int inst = blockIdx.y;
+  C += (int64_t)inst * c.dim;
+  g += (int64_t)inst * nn * nn;
+  const double2* D = (const double2*)c.D + inst * total;
+  const double2* hp = (const double2*)c.hp + (int64_t)inst * nn;
+  double2* T = (double2*)c.T + inst * total;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     int J = (int)(e / nn), pq = (int)(e - (int64_t)J * nn);
     double2 s = cmul(hp[pq], C[J]);
@@ -1480,7 +1293,9 @@ __global__ void k_ci_T(CIDev c, const double2* __restrict__ C, const double2* __
 // sigma[J] = sum_pq (E_pq T_pq)(J)
 __global__ void k_ci_sigma(CIDev c, double2* __restrict__ sigma) {
   const int nn = c.n * c.n;
-  const double2* T = (const double2*)c.T;
+  const int inst = blockIdx.y;
+  const double2* T = (const double2*)c.T + (int64_t)inst * c.dim * nn;
+  sigma += (int64_t)inst * c.dim;
   for (int J = blockIdx.x * NT + threadIdx.x; J < c.dim; J += gridDim.x * NT) {
     int Ja = J / c.NB, Jb = J - Ja * c.NB;
     double2 s = make_double2(0.0, 0.0);
@@ -1500,12 +1315,12 @@ __global__ void k_ci_sigma(CIDev c, double2* __restrict__ sigma) {
   }
 }
 
-void launch_ci_sigma(const CIDev& c, const double* C, const double* g, double* sigma, hipStream_t s) {
+static void launch_ci_sigma(int ni, const CIDev& c, const double* C, const double* g, double* sigma, hipStream_t s) {
   const int nn = c.n * c.n;
-  launch_ci_D(c, C, s);
-  hipLaunchKernelGGL(k_ci_T, dim3(nblocks((int64_t)c.dim * nn)), dim3(NT), 0, s, c, (const double2*)C,
+  launch_ci_D(ni, c, C, s);
+  hipLaunchKernelGGL(k_ci_T, dim3(nblocks((int64_t)c.dim * nn), ni), dim3(NT), 0, s, c, (const double2*)C,
                      (const double2*)g);
-  hipLaunchKernelGGL(k_ci_sigma, dim3(nblocks(c.dim)), dim3(NT), 0, s, c, (double2*)sigma);
+  hipLaunchKernelGGL(k_ci_sigma, dim3(nblocks(c.dim), ni), dim3(NT), 0, s, c, (double2*)sigma);
 }
 
 // One Lanczos/Arnoldi step on the CI space inside one workgroup: w is
@@ -1517,6 +1332,11 @@ __global__ void __launch_bounds__(1024) k_ci_lanczos_step(int dim, double2* cons
                                                           double* __restrict__ scal, int last) {
   __shared__ double red[32];
   __shared__ double2 hs[KMAX];
+  const int inst = blockIdx.x;
+  const int64_t vo = (int64_t)inst * dim;
+  w += vo;
+  H += (int64_t)inst * (m_max + 1) * m_max;
+  scal += 8 * inst;
   auto bsum = [&](double v) -> double {
     v = wave_sum(v);
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1528,14 +1348,11 @@ __global__ void __launch_bounds__(1024) k_ci_lanczos_step(int dim, double2* cons
     __syncthreads();
     return t;
   };
-  double wn2 = 0.0;
-  for (int i = threadIdx.x; i < dim; i += blockDim.x) wn2 += w[i].x * w[i].x + w[i].y * w[i].y;
-  wn2 = bsum(wn2);
   for (int pass = 0; pass < 2; ++pass) {
     for (int j = 0; j <= k; ++j) {
       double re = 0.0, im = 0.0;
       for (int i = threadIdx.x; i < dim; i += blockDim.x) {
-        double2 q = Q[j][i], x = w[i];
+        double2 q = Q[j][vo + i], x = w[i];
         re += q.x * x.x + q.y * x.y;
         im += q.x * x.y - q.y * x.x;
       }
@@ -1551,7 +1368,7 @@ __global__ void __launch_bounds__(1024) k_ci_lanczos_step(int dim, double2* cons
     }
     for (int i = threadIdx.x; i < dim; i += blockDim.x) {
       double2 x = w[i];
-      for (int j = 0; j <= k; ++j) x = csub(x, cmul(hs[j], Q[j][i]));
+      for (int j = 0; j <= k; ++j) x = csub(x, cmul(hs[j], Q[j][vo + i]));
       w[i] = x;
     }
     __syncthreads();
@@ -1562,8 +1379,8 @@ __global__ void __launch_bounds__(1024) k_ci_lanczos_step(int dim, double2* cons
   if (last) return;
   double hkk = 0.0;
   {
-    double2 d = H[k + (int64_t)(m_max + 1) * k];
-    hkk = hypot(d.x, d.y);
+    double2 dd = H[k + (int64_t)(m_max + 1) * k];
+    hkk = hypot(dd.x, dd.y);
   }
   bool brk = !(nrm > 1e-14 * fmax(1.0, hkk));
   double sc = brk ? 0.0 : 1.0 / nrm;
@@ -1571,14 +1388,18 @@ __global__ void __launch_bounds__(1024) k_ci_lanczos_step(int dim, double2* cons
     H[(k + 1) + (int64_t)(m_max + 1) * k] = make_double2(brk ? 0.0 : nrm, 0.0);
     if (brk && scal[4] > k + 1) scal[4] = k + 1;
   }
-  for (int i = threadIdx.x; i < dim; i += blockDim.x) Q[k + 1][i] = cscale(sc, w[i]);
-  (void)wn2;
+  for (int i = threadIdx.x; i < dim; i += blockDim.x) Q[k + 1][vo + i] = cscale(sc, w[i]);
 }
 
 __global__ void __launch_bounds__(1024) k_ci_start(int dim, const double2* __restrict__ C, double2* __restrict__ Q0,
                                                    double* __restrict__ scal, int m, double2* __restrict__ H,
                                                    int m_max) {
   __shared__ double red[32];
+  const int inst = blockIdx.x;
+  C += (int64_t)inst * dim;
+  Q0 += (int64_t)inst * dim;
+  H += (int64_t)inst * (m_max + 1) * m_max;
+  scal += 8 * inst;
   double s = 0.0;
   for (int i = threadIdx.x; i < dim; i += blockDim.x) s += C[i].x * C[i].x + C[i].y * C[i].y;
   s = wave_sum(s);
@@ -1597,14 +1418,18 @@ __global__ void __launch_bounds__(1024) k_ci_start(int dim, const double2* __res
   }
 }
 
-__global__ void __launch_bounds__(1024) k_ci_combine(int dim, double2* const* __restrict__ Q, int m,
+__global__ void __launch_bounds__(1024) k_ci_combine(int dim, double2* const* __restrict__ Q, int m, int m_max,
                                                      const double2* __restrict__ y, double2* __restrict__ C,
                                                      int normalize) {
   __shared__ double red[32];
+  const int inst = blockIdx.x;
+  const int64_t vo = (int64_t)inst * dim;
+  y += (int64_t)inst * m_max;
+  C += vo;
   double s2 = 0.0;
   for (int i = threadIdx.x; i < dim; i += blockDim.x) {
     double2 s = make_double2(0.0, 0.0);
-    for (int j = 0; j < m; ++j) s = cadd(s, cmul(y[j], Q[j][i]));
+    for (int j = 0; j < m; ++j) s = cadd(s, cmul(y[j], Q[j][vo + i]));
     C[i] = s;
     s2 += s.x * s.x + s.y * s.y;
   }
@@ -1619,20 +1444,19 @@ __global__ void __launch_bounds__(1024) k_ci_combine(int dim, double2* const* __
   for (int i = threadIdx.x; i < dim; i += blockDim.x) C[i] = cscale(f, C[i]);
 }
 
-void launch_ci_lanczos(const CIDev& c, double* const* Qdev, double* const* Qhost, int m, const double* g,
+void launch_ci_lanczos(int ni, const CIDev& c, double* const* Qdev, double* const* Qhost, int m, const double* g,
                        double* Cvec, Krylov& K, double tau_re, double tau_im, int normalize, hipStream_t s) {
-  hipLaunchKernelGGL(k_ci_start, dim3(1), dim3(1024), 0, s, c.dim, (const double2*)Cvec, (double2*)Qhost[0], K.scal,
+  hipLaunchKernelGGL(k_ci_start, dim3(ni), dim3(1024), 0, s, c.dim, (const double2*)Cvec, (double2*)Qhost[0], K.scal,
                      m, (double2*)K.H, K.m_max);
   for (int k = 0; k < m; ++k) {
-    launch_ci_sigma(c, Qhost[k], g, c.w, s);
-    hipLaunchKernelGGL(k_ci_lanczos_step, dim3(1), dim3(1024), 0, s, c.dim, (double2* const*)Qdev, k, (double2*)c.w,
+    launch_ci_sigma(ni, c, Qhost[k], g, c.w, s);
+    hipLaunchKernelGGL(k_ci_lanczos_step, dim3(ni), dim3(1024), 0, s, c.dim, (double2* const*)Qdev, k, (double2*)c.w,
                        (double2*)K.H, K.m_max, K.scal, (k == m - 1) ? 1 : 0);
   }
-  hipLaunchKernelGGL(k_expm, dim3(1), dim3(NT), 0, s, (const double2*)K.H, K.m_max, tau_re, tau_im, K.scal,
+  hipLaunchKernelGGL(k_expm, dim3(1, ni), dim3(NT), 0, s, (const double2*)K.H, K.m_max, tau_re, tau_im, K.scal,
                      (double2*)K.y);
-  hipLaunchKernelGGL(k_ci_combine, dim3(1), dim3(1024), 0, s, c.dim, (double2* const*)Qdev, m, (const double2*)K.y,
-                     (double2*)Cvec, normalize);
+  hipLaunchKernelGGL(k_ci_combine, dim3(ni), dim3(1024), 0, s, c.dim, (double2* const*)Qdev, m, K.m_max,
+                     (const double2*)K.y, (double2*)Cvec, normalize);
 }
-
 
 }  // namespace mh

@@ -1,4 +1,15 @@
 // Device kernels of the hot path and their host launchers (gfx950, wave64).
+//
+// Every launch covers a batch of independent instances (one molecule and
+// mesh each; a plain operator is a batch of one).  Instance i runs in the
+// workgroups with blockIdx.y == i and finds its mesh and operator data in
+// DevMesh dm[i].  Batch arrays are the per-instance arrays laid end to end:
+// instance i owns rows [oE, oE + NE) of every array over extended rows,
+// [oF, oF + NF) of arrays over full rows and [oMa, oMa + nMa) of arrays over
+// interface masters.  Small per-instance results (Krylov matrices, CG
+// scalars, moments, RDMs, integrals) are stored instance-major with a fixed
+// stride, and every reduction is segmented: its partial sums never mix
+// instances.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -6,16 +17,18 @@
 
 namespace mh {
 
-// Read-only mesh/operator data resident in HBM.
+// Read-only mesh/operator data of one instance, resident in HBM.
 struct DevMesh {
   int P = 0, n = 0;                // nodes per cell edge, orbitals
+  int inst = 0;                    // instance index (== blockIdx.y of its workgroups)
   int64_t nC = 0, N = 0, NE = 0, NF = 0, Nh = 0, Nb = 0, nMa = 0;
+  int64_t oE = 0, oF = 0, oMa = 0;      // first row in batch arrays (extended / full / master rows)
   const int32_t* cell_nodes = nullptr;  // [nC][P^3]
   const double* cell_hh = nullptr;      // [nC] h/2
-  const uint64_t* owner = nullptr;      // [nC] bit mask of owned local nodes
   const double* m = nullptr;            // [NF] Gauss-Lobatto full-node mass
   const double* v = nullptr;            // [NF] lumped nuclear potential
   const double* mz = nullptr;           // [NF] m (e.x)
+  const double* xyz = nullptr;          // [NF][3]
   const int32_t* hang_ptr = nullptr;    // [Nh+1]
   const int32_t* hang_col = nullptr;    // library node index (DoF < N or boundary >= NE)
   const double* hang_w = nullptr;
@@ -25,6 +38,7 @@ struct DevMesh {
   const int32_t* ma_col = nullptr;
   const double* ma_val = nullptr;
   const double* ma_dinv = nullptr;
+  const double* cheb = nullptr;         // 1/theta, then (c1, c2) per Chebyshev iteration
   const int32_t* ct_ptr = nullptr;      // per master: hanging rows it constrains
   const int32_t* ct_row = nullptr;
   const double* ct_w = nullptr;
@@ -36,123 +50,131 @@ struct DevMesh {
   const double* kt_val = nullptr;
   const int32_t* bnd_cells = nullptr;
   int64_t n_bnd_cells = 0;
-  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; grid caps
+  const double* bnd_table = nullptr;    // [Nb][nharm] multipole boundary table
+  double center[3] = {0.0, 0.0, 0.0};   // multipole expansion centre
+  double E0 = 1.0;                      // field amplitude of this instance (E = E0 x the step's field value)
+  double vnn = 0.0;                     // nuclear repulsion
+  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; grid caps (per instance)
   int sched_orb = 1, sched_poi = 1, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights
 };
 
+// A batch as seen by the launchers: the device array of instances, and a host
+// record with the shared parameters and the largest per-instance sizes (grid
+// shapes are taken from these; workgroups beyond an instance's size idle).
+struct Batch {
+  const DevMesh* dm = nullptr;  // device [ni]
+  int ni = 1;
+  DevMesh mx;                   // host: shared fields, per-class maximum sizes
+  int64_t tE = 0, tF = 0, tMa = 0;  // batch totals of extended, full and master rows
+  int cheb_iters = 0;           // Chebyshev iterations (the largest instance count)
+};
+
 // ---- orbital-space operator -------------------------------------------------
 // Node-centric operator (no atomics); diag_mode 0: K/2 only, 1: + v + E mz,
-// 2: + mean field.  mode 0: load vector F; 1: M^-1 F; 2: M^-1 F - v lam.
-// Non-master DoFs are final in out; masters and hanging nodes go to acc.
-void launch_stencil_orb(const DevMesh& d, const double* u, double E, int diag_mode, const double* Upk,
+// 2: + mean field, 3: mz only.  mode 0: load vector F; 1: M^-1 F; 2: M^-1 F
+// - v lam.  Non-master DoFs are final in out; masters and hanging nodes go to
+// acc.  E is read from the device scalar *Ef (times each instance's E0).
+void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
                         const double* ginv, int mode, const double* lam, double* out, double* acc, hipStream_t s);
 // Masters: acc_k + sum_h c_hk acc_h -> out (mode 0) or the interface rhs ma_b.
-void launch_ma_gather_orb(const DevMesh& d, const double* acc, int mode, double* out, double* ma_b, hipStream_t s);
-void launch_mass_direct(const DevMesh& d, const double* f, double* out, double* ma_b, hipStream_t s);
-int launch_stencil_poisson(const DevMesh& d, const double* x, int ncol, double* q, double* acc, double* part,
-                           hipStream_t s);
-// Former scatter form (FP64 atomics), kept for the boundary-lift pass only.
-// acc[node] += (K/2 + diag) u; diag_mode 0: none, 1: v + E mz, 2: + mean field
-void launch_cell_orb(const DevMesh& d, const double* u, double* acc, double E, int diag_mode, const double* Upk,
-                     const double* ginv, hipStream_t s);
-// DoF epilogue.  mode 0: out = C^T acc (load vector); 1: out = M^-1 (C^T acc)
-// on non-masters and master rhs into ma_b; 2: as 1 minus sum_q lam_qp v_q.
-void launch_epi_orb(const DevMesh& d, double* acc, int mode, const double* v, const double* lam, double* out,
-                    double* ma_b, hipStream_t s);
-void launch_ma_solve(const DevMesh& d, const double* ma_b, double* x, double* r, double* dbuf0, double* dbuf1,
-                     double lo, double hi, int iters, const double* v, const double* lam, double* out,
-                     hipStream_t s);
-void launch_fill_orb(const DevMesh& d, double* x, double* acc, hipStream_t s);
+void launch_ma_gather_orb(const Batch& b, const double* acc, int mode, double* out, double* ma_b, hipStream_t s);
+void launch_mass_direct(const Batch& b, const double* f, double* out, double* ma_b, hipStream_t s);
+void launch_ma_solve(const Batch& b, const double* ma_b, double* x, double* r, double* dbuf0, double* dbuf1,
+                     const double* v, const double* lam, double* out, hipStream_t s);
+void launch_fill_orb(const Batch& b, double* x, double* acc, hipStream_t s);
 void launch_copy(const double* in, double* out, int64_t nd, hipStream_t s);
 void launch_axpby(int64_t nd, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_zero(double* out, int64_t nd, hipStream_t s);
+void launch_set(double* out, double value, hipStream_t s);
 
-// ---- reductions ----------------------------------------------------------------
+// ---- reductions (segmented per instance) -----------------------------------------
+enum { ROWS_DOF = 0, ROWS_EXT = 1 };
+enum { WT_NONE = 0, WT_MASS = 1, WT_DIPOLE = 2 };
 int gram_blocks(int64_t rows);
-void launch_xgram(const double* X, int na, const double* Y, int nb, int yreal, const double* wt, int64_t rows,
-                  double* part, int nblk, double* out, hipStream_t s);
-void launch_gram(const double* a, const double* b, const double* wt, int64_t rows, int n, double* part,
-                 int nblk, double* G, hipStream_t s);
-int gint_blocks(const DevMesh& d);
-void launch_gint_full(const DevMesh& d, const double* phi, const double* W, const int* colmap, double* part,
-                      int nblk, double* Gtmp, double* g, hipStream_t s);
-void launch_build_U_full(const DevMesh& d, const double* W, const double* Gamma, const int* colmap, double* Mr,
+// G_i[a][b] = sum over rows of instance i of wt conj(A[row][a]) B[row][b]
+// (A, B batch orbital arrays [tE][n]); G instance stride n*n.
+void launch_gram(const Batch& b, const double* A, const double* B, int wsel, int rows, double* part, int nblk,
+                 double* G, hipStream_t s);
+// Same on flat per-instance arrays of `rows` rows: X [ni][rows][na], Y [ni][rows][nb].
+void launch_xgram_flat(int ni, const double* X, int na, const double* Y, int nb, int64_t rows, double* part,
+                       int nblk, double* out, hipStream_t s);
+int gint_blocks(const Batch& b);
+void launch_gint_full(const Batch& b, const double* phi, const double* W, const int* colmap, double* part, int nblk,
+                      double* Gtmp, double* g, hipStream_t s);
+void launch_build_U_full(const Batch& b, const double* W, const double* Gamma, const int* colmap, double* Mr,
                          double* Upk, hipStream_t s);
 
 // ---- Krylov ---------------------------------------------------------------------
 struct Krylov {
   int m_max = 0;
-  double* H = nullptr;       // device c128 [(m_max+1) x m_max], H[i + (m_max+1) j]
-  double* hcur = nullptr;    // device c128 [m_max+1]
-  double* scal = nullptr;    // [0]=beta [1]=next scale [2]=|w|^2 [3]=err [4]=m_eff [5]=1/beta
-  double* y = nullptr;       // device c128 [m_max]
-  double* part = nullptr;    // partial sums
+  double* H = nullptr;       // device c128 [ni][(m_max+1) x m_max], H[i + (m_max+1) j]
+  double* hcur = nullptr;    // device c128 [ni][m_max+1]
+  double* scal = nullptr;    // [ni][8]: [0]=beta [1]=next scale [2]=|w|^2 [3]=err [4]=m_eff [5]=1/beta
+  double* y = nullptr;       // device c128 [ni][m_max]
+  double* part = nullptr;    // partial sums [ni][nblk][...]
   int nblk = 0;
 };
-void launch_norm_init(const DevMesh& d, const double* phi, Krylov& K, int m, hipStream_t s);
-void launch_mdot(const DevMesh& d, double* const* V, int k, const double* w, Krylov& K, int pass, hipStream_t s);
-void launch_orth_update(const DevMesh& d, double* const* V, int k, double* w, Krylov& K, int pass,
-                        hipStream_t s);
-void launch_krylov_scale(const DevMesh& d, const double* src, double* dst, Krylov& K, int which, int k,
-                         hipStream_t s);
-void launch_expm(Krylov& K, int m, double tau_re, double tau_im, hipStream_t s);
-void launch_combine(const DevMesh& d, double* const* V, int m, double* phi, Krylov& K, hipStream_t s);
+void launch_norm_init(const Batch& b, const double* phi, Krylov& K, int m, hipStream_t s);
+void launch_mdot(const Batch& b, double* const* V, int k, const double* w, Krylov& K, int pass, hipStream_t s);
+void launch_orth_update(const Batch& b, double* const* V, int k, double* w, Krylov& K, int pass, hipStream_t s);
+void launch_krylov_scale(const Batch& b, const double* src, double* dst, Krylov& K, int which, hipStream_t s);
+void launch_expm(int ni, Krylov& K, double tau_re, double tau_im, hipStream_t s);
+void launch_combine(const Batch& b, double* const* V, int m, double* phi, Krylov& K, hipStream_t s);
 
 // ---- Poisson ---------------------------------------------------------------------
+// Column arrays are real [rows][ncol]: acc, p, r, q over extended rows (batch
+// offset oE), the potentials W over full rows (offset oF).
 struct PoissonWs {
   int ncol = 0, nharm = 0, lmax = 0;
-  double* acc = nullptr;   // [NE][ncol]
-  double* p = nullptr;     // [NE][ncol]
-  double* r = nullptr;     // [N][ncol]
-  double* q = nullptr;     // [N][ncol]
-  double* sc = nullptr;    // [8][ncol] scalars
-  double* part = nullptr;  // partials
-  double* part2 = nullptr; // partials of the master gather
-  double* Q = nullptr;     // moments [nharm][ncol]
-  double* mpart = nullptr; // moment partials
+  double* acc = nullptr;   // [tE][ncol]
+  double* p = nullptr;     // [tE][ncol]
+  double* r = nullptr;     // [tE][ncol]
+  double* q = nullptr;     // [tE][ncol]
+  double* sc = nullptr;    // [ni][8][ncol] scalars
+  double* part = nullptr;  // partials [ni][grid][2 ncol]
+  int64_t part_stride = 0;
+  double* Q = nullptr;     // moments [ni][nharm][ncol]
+  double* mpart = nullptr; // moment partials [ni][mblk][nharm ncol]
   int mblk = 0;
-  const double* table = nullptr;  // [Nb][nharm]
-  double center = 0;
-  // optional timing of the stiffness (cell) kernel: event pairs recorded on
-  // the launch stream around each launch, read after the timed region
+  // optional timing of the operator kernel: event pairs recorded on the
+  // launch stream around each launch, read after the timed region
   hipEvent_t* ev = nullptr;
   int ev_cap = 0, ev_used = 0;
 };
 enum { SC_RZ = 0, SC_PQ = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RR = 4, SC_BB = 5, SC_RZN = 6 };
-void launch_poisson_pipeline_moments(const DevMesh& d, const double* phi, const double* xyz, const int* colinfo,
-                                     PoissonWs& P, hipStream_t s);
-void launch_bnd_eval(const DevMesh& d, PoissonWs& P, double* W, hipStream_t s);
-void launch_poisson_rhs_full(const DevMesh& d, const double* phi, double* W, const int* colinfo, double* rhs,
+void launch_poisson_pipeline_moments(const Batch& b, const double* phi, const int* colinfo, PoissonWs& P,
+                                     hipStream_t s);
+void launch_bnd_eval(const Batch& b, PoissonWs& P, double* W, hipStream_t s);
+void launch_poisson_rhs_full(const Batch& b, const double* phi, double* W, const int* colinfo, double* rhs,
                              PoissonWs& P, hipStream_t s);
-void launch_cg_start(const DevMesh& d, double* W, double* rhs_r, PoissonWs& P, int warm, hipStream_t s);
-void launch_cg_step(const DevMesh& d, double* W, PoissonWs& P, hipStream_t s);
-void launch_fill_real(const DevMesh& d, double* x, int ncol, int with_bnd, double* acc, hipStream_t s);
-void launch_cell_poisson(const DevMesh& d, const double* x, double* acc, int ncol, int lift, hipStream_t s);
+void launch_cg_start(const Batch& b, double* W, double* rhs_r, PoissonWs& P, int warm, hipStream_t s);
+void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s);
+// Hanging rows of a real column array (xfull: x is over full rows, else extended).
+void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s);
 
-// ---- small dense work ----------------------------------------------------------------
-void launch_ginv(const double* gamma, int n, double eps, double* ginv, int* flag, hipStream_t s);
-void launch_observe(const double* gamma, const double* Gamma, const double* h, const double* g,
-                    const double* zmat, const double* S, int n, double vnn, double* out, hipStream_t s);
-void launch_orthonormalize_full(const DevMesh& d, const double* S, double* Rinv, double* x, hipStream_t s);
+// ---- small dense work (one workgroup per instance) ------------------------------------
+void launch_ginv(int ni, const double* gamma, int n, double eps, double* ginv, int* flag, hipStream_t s);
+void launch_observe(const Batch& b, const double* gamma, const double* Gamma, const double* h, const double* g,
+                    const double* zmat, const double* S, double* out, hipStream_t s);
+void launch_orthonormalize_full(const Batch& b, const double* S, double* Rinv, double* x, hipStream_t s);
 
-// ---- CI --------------------------------------------------------------------------------
+// ---- CI (one space shared by the instances; vectors [ni][dim]) ---------------------------
 struct CIDev {
   int n = 0, NA = 0, NB = 0, dim = 0;
   const int32_t* exa = nullptr;  // [NA][n*n]: I | (sign<0)<<30 with E_pq|I> = sign|J>, or -1
   const int32_t* exb = nullptr;  // [NB][n*n]
-  double* D = nullptr;           // [dim][n*n] c128
-  double* T = nullptr;           // [dim][n*n] c128
-  double* hp = nullptr;          // h' [n*n] c128
+  double* D = nullptr;           // [ni][dim][n*n] c128
+  double* T = nullptr;           // [ni][dim][n*n] c128
+  double* hp = nullptr;          // h' [ni][n*n] c128
   double* part = nullptr;
-  double* w = nullptr;           // [dim] c128
+  double* w = nullptr;           // [ni][dim] c128
 };
-void launch_ci_D(const CIDev& c, const double* C, hipStream_t s);
-void launch_ci_rdm_full(const CIDev& c, const double* C, double* gamma, double* Gamma, double* Gtmp, hipStream_t s);
-void launch_ci_hprime(const CIDev& c, const double* h, const double* g, hipStream_t s);
-void launch_ci_sigma(const CIDev& c, const double* C, const double* g, double* sigma, hipStream_t s);
-void launch_ci_lanczos(const CIDev& c, double* const* Qdev, double* const* Qhost, int m, const double* g,
+void launch_ci_rdm_full(int ni, const CIDev& c, const double* C, double* gamma, double* Gamma, double* Gtmp,
+                        hipStream_t s);
+void launch_ci_hprime(int ni, const CIDev& c, const double* h, const double* g, hipStream_t s);
+void launch_ci_lanczos(int ni, const CIDev& c, double* const* Qdev, double* const* Qhost, int m, const double* g,
                        double* Cvec, Krylov& K, double tau_re, double tau_im, int normalize, hipStream_t s);
 
 }  // namespace mh

@@ -12,6 +12,9 @@ import os
 
 ORB_CANDIDATES = [(s, g) for s in (1, 0) for g in (2048, 8192, 65536)]
 POI_CANDIDATES = [(s, g) for s in (3, 2, 1, 0) for g in (2048, 4096, 8192)]
+# grid caps are per instance: a batch fills the chip with fewer workgroups each
+ORB_CANDIDATES_BATCH = [(s, g) for s in (1, 0) for g in (256, 1024, 65536)]
+POI_CANDIDATES_BATCH = [(s, g) for s in (1, 0) for g in (256, 1024, 8192)]
 _CACHE = {}
 
 
@@ -19,7 +22,8 @@ def _key(op):
     import torch
     info = op.mesh.info
     dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
-    return f"{info['n_cells']}-{info['n_dof']}-{info['n_hang']}-p{info['p']}-n{op.n_orb}-{dev}"
+    return (f"{info['n_cells']}-{info['n_dof']}-{info['n_hang']}-p{info['p']}-n{op.n_orb}"
+            f"-i{op.n_inst}-{op.n_dof}-{dev}")
 
 
 def autotune(op, phi, W, reps=5, cache_file=None):
@@ -43,14 +47,15 @@ def autotune(op, phi, W, reps=5, cache_file=None):
         return best
     out = torch.empty_like(phi)
     times = {"orbital": {}, "poisson": {}}
-    for sched, grid in ORB_CANDIDATES:
+    batched = op.n_inst > 1
+    for sched, grid in (ORB_CANDIDATES_BATCH if batched else ORB_CANDIDATES):
         op.tune(0, sched, grid)
         op.rhs_apply(phi, out)
         op.kernel_timing(0, True)
         for _ in range(reps):
             op.rhs_apply(phi, out)
         times["orbital"][(sched, grid)] = op.kernel_timing(0, False)[0]
-    for sched, grid in POI_CANDIDATES:
+    for sched, grid in (POI_CANDIDATES_BATCH if batched else POI_CANDIDATES):
         op.tune(1, sched, grid)
         op.kernel_timing(1, True)
         op.poisson_pairs(phi, W, warm=True)
