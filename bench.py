@@ -114,6 +114,11 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="instances of the h2x64 workload")
     ap.add_argument("--seq-steps", type=int, default=2, help="timed steps per instance of the sequential runs")
     ap.add_argument("--graph", action="store_true", help="replay each step's fixed part as a HIP graph")
+    ap.add_argument("--no-sequential", action="store_true", help="h2x64: skip the sequential runs")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware-counter passes: CG iterations and RHS applications on the "
+                         "workload's mesh, then a 1 GiB elementwise multiply for calibration; prints no JSON")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint vs plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -121,6 +126,8 @@ def main():
         print("this build runs on one GPU only: the whole mesh lives on one MI355X; "
               "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.counters:
+        return run_counters(args)
     if args.workload == "h2x64":
         return run_batch(args)
     import numpy as np
@@ -209,11 +216,107 @@ def main():
                      "tuning_ms": sched.get("timings_ms")},
         "kernels": kern,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byts},
+                     "frac": ach / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, f"{args.workload}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb"),
+                     "algorithmic_bytes_per_launch": byts},
     }
+    if not args.no_adjoint:
+        line["fwd_adjoint_vs_plain"] = adjoint_ratio()
     if not args.no_cpu_baseline and args.workload == "h2":
         line["cpu_baseline"] = cpu_baseline(args.workload, w, args.cpu_budget)
     print(json.dumps(line))
+
+
+def measured_traffic(kernel, workload, profiles_dir=None, source=None):
+    """HBM bytes per launch of `kernel` on `workload` from the counter summaries
+    under profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated), or None
+    when none was taken or the kernel's source has changed since."""
+    import glob
+    import hashlib
+    src = source or os.path.join(ROOT, "paper_2301_02387_amd", "csrc", "stencil.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(profiles_dir or os.path.join(ROOT, "profiles"), "*.md"))):
+        for ln in open(path):
+            if not ln.startswith("traffic:"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in ln.split()[1:])
+            if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha1") == sha:
+                return float(kv["bytes_per_launch"])
+    return None
+
+
+def adjoint_ratio(steps=40):
+    """Forward + checkpointed recomputation + adjoint against the plain forward
+    propagation, one-electron workload (H atom, Q2, 1 orbital)."""
+    import numpy as np
+    import torch
+    import paper_2301_02387_amd as mh
+    from synth import initial_guess
+    w = _workload("h_atom")
+    mesh = mh.Mesh.from_workload(w)
+    op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"])
+    phi = torch.from_numpy(np.ascontiguousarray(initial_guess("h_atom", mesh.coords()[:op.n_ext]))).cuda()
+    op.fill_hanging(phi)
+    C = torch.ones(1, dtype=torch.complex128, device="cuda")
+    W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
+    op.propagate(phi, C, W, [0.0] * 3, 0.05, m=12, imaginary=True, final=False)
+    E = 0.02 * np.sin(0.3 * np.arange(steps + 1))
+    g = np.random.default_rng(5).standard_normal(steps + 1)
+    phi0 = phi.clone()
+
+    def plain():
+        p = phi0.clone()
+        op.propagate(p, C.clone(), W, E, w["dt"], m=w["krylov"])
+
+    def adjoint():
+        plain()   # the forward pass that produced the dipoles
+        op.propagate_adjoint(phi0, C, W, E, w["dt"], g, m=w["krylov"], n_quad=6)
+
+    out = {}
+    for name, fn in (("plain", plain), ("fwd_adjoint", adjoint)):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = (time.perf_counter() - t) * 1e3
+    out["ratio"] = out["fwd_adjoint_ms"] / out["plain_ms"]
+    out["workload"] = f"h_atom_q{w['p']}_{op.n_dof}dof_1orb, {steps} steps, 6-point Frechet quadrature, " \
+                      f"checkpoints every round(sqrt(N)) steps"
+    return out
+
+
+def run_counters(args):
+    import numpy as np
+    import torch
+    import paper_2301_02387_amd as mh
+    from synth import h2_guess, h2o_guess, random_ci
+    w = _workload(args.workload)
+    mesh = mh.Mesh.from_workload(w)
+    op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_maxit=24)
+    xyz = mesh.coords()[:op.n_ext]
+    c = h2o_guess(xyz) if args.workload == "h2o" else h2_guess(xyz, 0.7)
+    phi = torch.from_numpy(np.ascontiguousarray(c)).cuda()
+    op.fill_hanging(phi)
+    W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
+    it, _ = op.poisson_pairs(phi, W)
+    log(f"cg iterations {it}")
+    n = op.n_orb
+    C = torch.from_numpy(random_ci(op.n_ci, 3)).cuda()
+    g = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    G = torch.zeros((n,) * 4, dtype=torch.complex128, device="cuda")
+    op.ci_rdms(C, g, G)
+    op.freeze(phi, g, G, 0.01, W)
+    out = torch.empty_like(phi)
+    for _ in range(10):
+        op.rhs_apply(phi, out)
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 2.0, out=b)   # calibration: 1 GiB read and 1 GiB written per launch
+    torch.cuda.synchronize()
+    log("counters run done")
 
 
 def run_batch(args):
@@ -269,6 +372,8 @@ def run_batch(args):
     ph_all = phi.clone()
     C_all = Ci.clone()
     for i, mesh in enumerate(meshes):
+        if args.no_sequential:
+            break
         w = ws[i]
         one = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_rtol=1e-12,
                           poisson_maxit=20000)
@@ -317,12 +422,12 @@ def run_batch(args):
                    "n_dof_total": op.n_dof, "n_dof_min": int(lay[:, 0].min()), "n_dof_max": int(lay[:, 0].max()),
                    "n_cells_total": n_cells, "krylov": m, "dt": dt, "graph": bool(args.graph),
                    "parallelism": "none (one GPU, batch of instances)"},
-        "batched_vs_sequential": seq_step_s * 1e3 / ms_step,
+        "batched_vs_sequential": (seq_step_s * 1e3 / ms_step) if not args.no_sequential else None,
         "sequential_ms_per_step": seq_step_s * 1e3,
         "sequential_sample": f"each of the {op.n_inst} instances alone, {args.seq_steps} timed step(s) after one "
                              f"untimed step, default schedules",
         "poisson_cg_iters_per_step": float(np.mean(rec["cg_iters"][:args.steps])),
-        "sequential_cg_iters_per_step_mean": float(np.mean(seq_iters)),
+        "sequential_cg_iters_per_step_mean": float(np.mean(seq_iters)) if seq_iters else None,
         "setup_s": t_setup,
         "schedule": {"orbital": list(sched["orbital"]), "poisson": list(sched["poisson"]),
                      "tuning_ms": sched.get("timings_ms")},

@@ -223,7 +223,9 @@ typedef struct {
  * E_steps: host double [n_steps + 1] (the last value is used for the final
  * record); instance i sees the field E0_i E_steps[k] (E0 = 1 for
  * mh_op_create).  obs: host arrays (any member may be NULL).  W_work: device
- * double [N_F][n*n] Poisson warm-start buffer (in-out, may hold zeros).
+ * double [N_F][n*n] Poisson warm-start buffer (in-out, may hold zeros); the
+ * first step of a call starts CG from it, later steps from the linear
+ * extrapolation 2 W_n - W_{n-1} of the two previous solutions.
  * Synchronises `stream`. */
 enum { MH_PROP_IMAGINARY = 1, MH_PROP_NO_FINAL = 2, MH_PROP_GRAPH = 4 };
 int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const double* E_steps,
@@ -295,8 +297,12 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * which: 0 = orbital operator, 1 = Poisson operator.  sched bit 0: 1 =
  * XCD-contiguous sweep (XCD x of 8 owns a contiguous node range and its
  * workgroups walk it side by side), 0 = plain grid-stride sweep.  Poisson
- * only, sched bit 1: column blocking (16 columns per XCD group) when the
- * column count is 16, 32 or 64.
+ * only, sched bit 2: rows of the assembled operator with more than 48
+ * entries (hanging-node masters) taken by whole waves in reserved workgroups
+ * of the same launch; bit 3: the CG direction formed inside the operator
+ * pass (two launches per CG iteration instead of three; fewer launches, more
+ * loads per entry).  Default sched 13.  Allowed values: 0, 1 (orbital); any
+ * combination of bits 0, 2, 3 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
  * sums change order only). */

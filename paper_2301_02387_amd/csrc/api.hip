@@ -89,6 +89,7 @@ struct mh_op {
   double* gam = nullptr, *Gam = nullptr, *hmat = nullptr, *gint = nullptr, *S = nullptr, *zmat = nullptr;
   double* obs = nullptr;    // [ni][8]
   double* Rinv = nullptr;
+  double* Wprev = nullptr;  // [tF][n*n] potentials of the previous step (start extrapolation)
   double* hostpin = nullptr;
   size_t hostpin_len = 0;
   hipStream_t gstream = nullptr;  // stream for graph capture and replay
@@ -390,6 +391,13 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
     d.kt_ptr = op->upload(H.kt_ptr, s);
     d.kt_col = op->upload(H.kt_col, s);
     d.kt_val = op->upload(H.kt_val, s);
+    {
+      std::vector<int32_t> lr;
+      for (int64_t r = 0; r < d.N; ++r)
+        if (H.kt_ptr[r + 1] - H.kt_ptr[r] > KT_LONG) lr.push_back((int32_t)r);
+      d.kt_long = op->upload(lr, s);
+      d.n_long = (int64_t)lr.size();
+    }
     d.bnd_cells = op->upload(H.bnd_cells, s);
     d.n_bnd_cells = (int64_t)H.bnd_cells.size();
     d.bnd_table = op->upload(H.bnd_table, s);
@@ -411,6 +419,7 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
     mx.Nb = std::max(mx.Nb, d.Nb);
     mx.nMa = std::max(mx.nMa, d.nMa);
     mx.n_bnd_cells = std::max(mx.n_bnd_cells, d.n_bnd_cells);
+    mx.n_long = std::max(mx.n_long, d.n_long);
     if (d.P != mx.P) throw std::runtime_error("all instances of a batch must use the same degree p");
   }
   B.tE = oE;
@@ -458,7 +467,7 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   op->zmat = op->alloc<double>(ni * 2 * nn);
   op->obs = op->alloc<double>(ni * 8);
   op->Rinv = op->alloc<double>(ni * 2 * nn);
-  op->hostpin_len = (size_t)ni * std::max(8 * ncol, 64) + 4096;
+  op->hostpin_len = (size_t)ni * std::max((8 + RED_SLOTS) * ncol, 64) + 4096;
   HIPCHK(hipHostMalloc((void**)&op->hostpin, op->hostpin_len * sizeof(double), hipHostMallocDefault));
   // Poisson workspaces
   PoissonWs& P = op->P;
@@ -469,9 +478,14 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   launch_zero(P.acc, tE * ncol, s);
   P.p = op->alloc<double>(tE * ncol);
   launch_zero(P.p, tE * ncol, s);
+  P.p2 = op->alloc<double>(tE * ncol);
+  launch_zero(P.p2, tE * ncol, s);
   P.r = op->alloc<double>(tE * ncol);
   P.q = op->alloc<double>(tE * ncol);
   P.sc = op->alloc<double>((size_t)ni * 8 * ncol);
+  launch_zero(P.sc, (size_t)ni * 8 * ncol, s);
+  P.red = op->alloc<double>((size_t)ni * RED_SLOTS * ncol);
+  launch_zero(P.red, (size_t)ni * RED_SLOTS * ncol, s);
   P.part_stride = (int64_t)8192 * 2 * ncol;
   P.part = op->alloc<double>((size_t)ni * P.part_stride);
   P.Q = op->alloc<double>((size_t)ni * P.nharm * ncol);
@@ -645,13 +659,17 @@ static void poisson_begin(mh_op* op, const double* phi, double* W, int warm, hip
 static int poisson_converged(mh_op* op, hipStream_t s) {
   const int ncol = op->ncol, ni = op->ni;
   double* hs = op->hostpin;
+  double* hr = hs + (size_t)ni * 8 * ncol;
   HIPCHK(hipMemcpyAsync(hs, op->P.sc, (size_t)ni * 8 * ncol * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hr, op->P.red, (size_t)ni * RED_SLOTS * ncol * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  const int rr_slot = op->P.it > 0 ? red_rr_slot(op->P.it) : -1;
   int conv = 1;
   for (int i = 0; i < ni; ++i)
     for (int c = 0; c < ncol; ++c) {
       const double* sc = hs + (size_t)i * 8 * ncol;
-      double rr = sc[SC_RR * ncol + c], bb = sc[SC_BB * ncol + c];
+      const double* rd = hr + (size_t)i * RED_SLOTS * ncol;
+      double rr = rr_slot >= 0 ? rd[rr_slot * ncol + c] : sc[SC_RR * ncol + c], bb = sc[SC_BB * ncol + c];
       if (!std::isfinite(rr)) return -1;
       if (rr > op->rtol * op->rtol * bb) conv = 0;
     }
@@ -917,7 +935,13 @@ extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const
       const double E = (n_steps > 0 || E_steps) ? E_steps[step] : 0.0;
       launch_ci_rdm_full(ni, op->ci, Ci, op->gam, op->Gam, op->Gtmp, s);
       int it = 0;
+      // CG start: the previous solution, then (from the third step of the call)
+      // the linear extrapolation 2 W_{n-1} - W_{n-2}; Wprev keeps W_{n-1}
+      const int64_t wlen = (int64_t)op->B.tF * op->ncol;
+      if (step == 0 && !op->Wprev) op->Wprev = op->alloc<double>((size_t)wlen);
+      if (step >= 2) launch_extrapolate(W, op->Wprev, wlen, s);
       int rc = poisson_solve(op, phi, W, 1, &it, s);
+      if (step == 0) launch_copy(W, op->Wprev, wlen, s);  // W_0; step 1 starts from W_0 and keeps it
       if (rc < 0) return rc;
       if (rc == MH_NOT_CONVERGED) status = MH_NOT_CONVERGED;
       launch_set(op->Ebuf, E, s);
@@ -1002,7 +1026,7 @@ extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double
 }
 
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || sched > (which == 1 ? 3 : 1))
+  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 13 : 1)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");

@@ -10,6 +10,30 @@ namespace mh {
 #define NT 256
 #endif
 
+// Array pointers read from an instance record in memory are generic to the
+// compiler, which then emits flat loads (tracked by both wait counters, so
+// dependent loads serialise).  They all point to device global memory; this
+// cast lets the compiler emit global loads instead.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gbl(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gblw(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// 16-byte global load of element i of a double2 array (double2 is a class
+// type that does not copy from another address space; the native vector type does).
+typedef double dvec2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldg2(const double2* p, int64_t i) {
+  const dvec2_t v = ((const __attribute__((address_space(1))) dvec2_t*)p)[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ldg2(const double* p, int64_t i) {
+  return ldg2(reinterpret_cast<const double2*>(p), i);
+}
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -60,23 +84,29 @@ constexpr int N_XCD = 8;
 struct XcdSweep {
   int64_t start, end, step;
 };
-__device__ __forceinline__ XcdSweep xcd_sweep(int64_t total, int per_block, bool xcd = true) {
+// (bx, gx): this workgroup's index and the number of workgroups taking part
+// (a launch may reserve its first workgroups for other work; the reserved
+// count is a multiple of 8, so bx % 8 is still the XCD).
+__device__ __forceinline__ XcdSweep xcd_sweep(int64_t total, int per_block, bool xcd, int bx, int gx) {
   if (!xcd) {  // plain grid-stride sweep
     XcdSweep s;
-    s.start = (int64_t)blockIdx.x * per_block;
+    s.start = (int64_t)bx * per_block;
     s.end = total;
-    s.step = (int64_t)gridDim.x * per_block;
+    s.step = (int64_t)gx * per_block;
     return s;
   }
-  const int x = blockIdx.x % N_XCD;
-  const int lb = blockIdx.x / N_XCD;
-  const int nbx = gridDim.x / N_XCD;
+  const int x = bx % N_XCD;
+  const int lb = bx / N_XCD;
+  const int nbx = gx / N_XCD;
   const int64_t R = (total + N_XCD - 1) / N_XCD;
   XcdSweep s;
   s.start = x * R + (int64_t)lb * per_block;
   s.end = (x + 1) * R < total ? (x + 1) * R : total;
   s.step = (int64_t)nbx * per_block;
   return s;
+}
+__device__ __forceinline__ XcdSweep xcd_sweep(int64_t total, int per_block, bool xcd = true) {
+  return xcd_sweep(total, per_block, xcd, (int)blockIdx.x, (int)gridDim.x);
 }
 static inline int xcd_grid(int64_t items, int per_block, int cap) {
   int64_t b = (items + per_block - 1) / per_block;

@@ -53,30 +53,56 @@ __global__ void __launch_bounds__(NT) k_cheb_init(const DevMesh* __restrict__ dm
   }
 }
 
+// One row of the interface block per group of CHEB_G lanes: the lanes split
+// the row's entries (tens per row) and combine by shuffles, all n orbitals
+// at once.
+constexpr int CHEB_G = 8;
 __global__ void __launch_bounds__(NT) k_cheb_iter(const DevMesh* __restrict__ dm, double2* __restrict__ x,
                                                   double2* __restrict__ r, const double2* __restrict__ din,
                                                   double2* __restrict__ dout, int k) {
   INSTANCE;
   const int n = d.n;
-  const int64_t total = d.nMa * n, o = d.oMa * n;
-  if (total == 0) return;
+  if (d.nMa == 0) return;
+  const int64_t o = d.oMa * n;
   const double c1 = d.cheb[1 + 2 * k], c2 = d.cheb[2 + 2 * k];
   const double2* dI = din + o;
-  for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
-    const int64_t i = idx / n;
-    const int p = (int)(idx - i * n);
-    double2 s = make_double2(0.0, 0.0);
-    for (int t = d.ma_ptr[i]; t < d.ma_ptr[i + 1]; ++t) {
-      double2 v = dI[(int64_t)d.ma_col[t] * n + p];
-      s.x += d.ma_val[t] * v.x;
-      s.y += d.ma_val[t] * v.y;
+  const int g = (int)(threadIdx.x & (CHEB_G - 1));
+  const int64_t groups = (int64_t)gridDim.x * (NT / CHEB_G);
+  for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) / CHEB_G; i < d.nMa; i += groups) {
+    double sx[8], sy[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) { sx[p] = 0.0; sy[p] = 0.0; }
+    const auto* mp = gbl(d.ma_ptr);
+    for (int t = mp[i] + g; t < mp[i + 1]; t += CHEB_G) {
+      const double a = gbl(d.ma_val)[t];
+      const double2* row = dI + (int64_t)gbl(d.ma_col)[t] * n;
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < n) {
+          const double2 v = row[p];
+          sx[p] += a * v.x;
+          sy[p] += a * v.y;
+        }
     }
-    double2 dk = dI[idx];
-    x[o + idx] = cadd(x[o + idx], dk);
-    double2 rn = csub(r[o + idx], s);
-    r[o + idx] = rn;
-    double g = c2 * d.ma_dinv[i];
-    dout[o + idx] = make_double2(c1 * dk.x + g * rn.x, c1 * dk.y + g * rn.y);
+#pragma unroll
+    for (int off = CHEB_G / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < n) {
+          sx[p] += __shfl_xor(sx[p], off, CHEB_G);
+          sy[p] += __shfl_xor(sy[p], off, CHEB_G);
+        }
+    const double gi = c2 * gbl(d.ma_dinv)[i];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < n && p % CHEB_G == g) {
+        const int64_t idx = o + i * n + p;
+        const double2 dk = din[idx];
+        x[idx] = cadd(x[idx], dk);
+        const double2 rn = csub(r[idx], make_double2(sx[p], sy[p]));
+        r[idx] = rn;
+        dout[idx] = make_double2(c1 * dk.x + gi * rn.x, c1 * dk.y + gi * rn.y);
+      }
   }
 }
 
@@ -106,8 +132,9 @@ void launch_ma_solve(const Batch& b, const double* ma_b, double* x, double* r, d
                      (double2*)dbuf0);
   double* din = dbuf0;
   double* dout = dbuf1;
+  const dim3 gi(nblocks(b.mx.nMa * CHEB_G), b.ni);
   for (int k = 0; k < b.cheb_iters; ++k) {
-    hipLaunchKernelGGL(k_cheb_iter, g, dim3(NT), 0, s, b.dm, (double2*)x, (double2*)r, (const double2*)din,
+    hipLaunchKernelGGL(k_cheb_iter, gi, dim3(NT), 0, s, b.dm, (double2*)x, (double2*)r, (const double2*)din,
                        (double2*)dout, k);
     double* t = din;
     din = dout;
@@ -128,12 +155,14 @@ __global__ void __launch_bounds__(NT) k_fill_orb(const DevMesh* __restrict__ dm,
     const int64_t h = idx / n;
     const int p = (int)(idx - h * n);
     double2 s = make_double2(0.0, 0.0);
-    for (int t = d.hang_ptr[h]; t < d.hang_ptr[h + 1]; ++t) {
-      int col = d.hang_col[t];
+    const auto* hp = gbl(d.hang_ptr);
+    for (int t = hp[h]; t < hp[h + 1]; ++t) {
+      int col = gbl(d.hang_col)[t];
       if (col < d.N) {
+        const double w = gbl(d.hang_w)[t];
         double2 v = x[o + (int64_t)col * n + p];
-        s.x += d.hang_w[t] * v.x;
-        s.y += d.hang_w[t] * v.y;
+        s.x += w * v.x;
+        s.y += w * v.y;
       }
     }
     x[o + (d.N + h) * n + p] = s;
@@ -161,6 +190,17 @@ void launch_copy(const double* in, double* out, int64_t nd, hipStream_t s) {
 }
 void launch_zero(double* out, int64_t nd, hipStream_t s) {
   if (nd > 0) hipLaunchKernelGGL(k_zero, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, out, nd);
+}
+// x <- 2 x - xp and xp <- the old x (linear extrapolation in time, history shifted)
+__global__ void k_extrapolate(double* __restrict__ x, double* __restrict__ xp, int64_t nd) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nd; i += (int64_t)gridDim.x * NT) {
+    const double xi = x[i];
+    x[i] = 2.0 * xi - xp[i];
+    xp[i] = xi;
+  }
+}
+void launch_extrapolate(double* x, double* xprev, int64_t nd, hipStream_t s) {
+  if (nd > 0) hipLaunchKernelGGL(k_extrapolate, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, x, xprev, nd);
 }
 void launch_set(double* out, double value, hipStream_t s) {
   hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, out, value);
@@ -207,7 +247,7 @@ __global__ void __launch_bounds__(NT) k_xgram(const DevMesh* __restrict__ dm, in
       double2 v = make_double2(0.0, 0.0);
       if (r < cnt) {
         v = X[(base + r) * na + a];
-        if (wt) v = cscale(wt[base + r], v);
+        if (wt) v = cscale(gbl(wt)[base + r], v);
       }
       sx[r * na + a] = v;
     }
@@ -238,14 +278,15 @@ __global__ void __launch_bounds__(NT) k_xgram(const DevMesh* __restrict__ dm, in
   }
 }
 
-// out[i][o] = sum_b part[i][b][o]
-__global__ void k_sum_parts(const double2* __restrict__ part, int nblk, int nout, double2* __restrict__ out) {
-  const double2* pi = part + (int64_t)blockIdx.y * nblk * nout;
-  for (int o = blockIdx.x * NT + threadIdx.x; o < nout; o += gridDim.x * NT) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int b = 0; b < nblk; ++b) s = cadd(s, pi[(int64_t)b * nout + o]);
-    out[(int64_t)blockIdx.y * nout + o] = s;
-  }
+// out[i][o] = sum_b part[i][b][o]; one workgroup per (output, instance)
+__global__ void __launch_bounds__(NT) k_sum_parts(const double2* __restrict__ part, int nblk, int nout,
+                                                  double2* __restrict__ out) {
+  __shared__ double lds4[4];
+  const double* pi = (const double*)(part + (int64_t)blockIdx.y * nblk * nout);
+  const int o = blockIdx.x;
+  const double sx = sum_partials(pi, nblk, 2 * nout, 2 * o, lds4);
+  const double sy = sum_partials(pi, nblk, 2 * nout, 2 * o + 1, lds4);
+  if (threadIdx.x == 0) out[(int64_t)blockIdx.y * nout + o] = make_double2(sx, sy);
 }
 
 int gram_blocks(int64_t rows) { return nblocks(rows, XG_CH, 512); }
@@ -255,7 +296,7 @@ void launch_gram(const Batch& b, const double* A, const double* B, int wsel, int
   const int n = b.mx.n;
   hipLaunchKernelGGL(k_xgram, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, wsel, rows, (const double2*)A, n,
                      (const double2*)B, n, (int64_t)0, (double2*)part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(n * n), b.ni), dim3(NT), 0, s, (const double2*)part, nblk, n * n,
+  hipLaunchKernelGGL(k_sum_parts, dim3(n * n, b.ni), dim3(NT), 0, s, (const double2*)part, nblk, n * n,
                      (double2*)G);
 }
 
@@ -263,7 +304,7 @@ void launch_xgram_flat(int ni, const double* X, int na, const double* Y, int nb,
                        int nblk, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_xgram, dim3(nblk, ni), dim3(NT), 0, s, (const DevMesh*)nullptr, 0, 0, (const double2*)X, na,
                      (const double2*)Y, nb, rows, (double2*)part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(na * nb), ni), dim3(NT), 0, s, (const double2*)part, nblk, na * nb,
+  hipLaunchKernelGGL(k_sum_parts, dim3(na * nb, ni), dim3(NT), 0, s, (const double2*)part, nblk, na * nb,
                      (double2*)out);
 }
 
@@ -351,8 +392,8 @@ void launch_gint_full(const Batch& b, const double* phi, const double* W, const 
                       double* Gtmp, double* g, hipStream_t s) {
   const int n = b.mx.n, ncol = n * n;
   hipLaunchKernelGGL(k_gint, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol, (double2*)part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(ncol * ncol), b.ni), dim3(NT), 0, s, (const double2*)part, nblk,
-                     ncol * ncol, (double2*)Gtmp);
+  hipLaunchKernelGGL(k_sum_parts, dim3(ncol * ncol, b.ni), dim3(NT), 0, s, (const double2*)part, nblk, ncol * ncol,
+                     (double2*)Gtmp);
   hipLaunchKernelGGL(k_gint_assemble, dim3(nblocks(ncol * ncol), b.ni), dim3(NT), 0, s, (const double2*)Gtmp, n,
                      colmap, (double2*)g);
 }
@@ -401,14 +442,12 @@ __global__ void __launch_bounds__(NT) k_build_U(const DevMesh* __restrict__ dm, 
   for (int e = threadIdx.x; e < nn * nn; e += NT) sM[e] = Mr[e];
   __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < d.NE; i += (int64_t)gridDim.x * NT) {
-    double wv[64];
     const double* wr = W + i * nn;
-    for (int c = 0; c < nn; ++c) wv[c] = wr[c];
     double* ur = Upk + i * nn;
     for (int o = 0; o < nn; ++o) {
       double s = 0.0;
       const double* mrow = sM + o * nn;
-      for (int c = 0; c < nn; ++c) s += mrow[c] * wv[c];
+      for (int c = 0; c < nn; ++c) s += mrow[c] * wr[c];
       ur[o] = s;
     }
   }
@@ -443,13 +482,13 @@ __global__ void __launch_bounds__(NT) k_mdot(const DevMesh* __restrict__ dm, con
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) { hr[j] = 0.0; hi[j] = 0.0; }
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const double mi = d.m[e / n];
+    const double mi = gbl(d.m)[e / n];
     const double2 w0 = w[o + e];
     const double2 we = make_double2(mi * w0.x, mi * w0.y);
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
       if (j <= k) {
-        double2 vj = V[j][o + e];
+        double2 vj = ldg2(V[j], o + e);
         hr[j] += vj.x * we.x + vj.y * we.y;
         hi[j] += vj.x * we.y - vj.y * we.x;
       }
@@ -521,9 +560,9 @@ __global__ void __launch_bounds__(NT) k_orth_update(const DevMesh* __restrict__ 
     double2 we = w[o + e];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
-      if (j <= k) we = csub(we, cmul(h[j], V[j][o + e]));
+      if (j <= k) we = csub(we, cmul(h[j], ldg2(V[j], o + e)));
     w[o + e] = we;
-    if (with_norm) nrm += d.m[e / n] * (we.x * we.x + we.y * we.y);
+    if (with_norm) nrm += gbl(d.m)[e / n] * (we.x * we.x + we.y * we.y);
   }
   if (with_norm) {
     double c = block_sum(nrm, lds);
@@ -583,7 +622,7 @@ __global__ void __launch_bounds__(NT) k_norm_part(const DevMesh* __restrict__ dm
   double s = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const double2 v = x[o + e];
-    s += d.m[e / n] * (v.x * v.x + v.y * v.y);
+    s += gbl(d.m)[e / n] * (v.x * v.x + v.y * v.y);
   }
   double c = block_sum(s, lds);
   if (threadIdx.x == 0) part[blockIdx.y * kpart_stride(gridDim.x, m_max) + blockIdx.x] = c;
@@ -706,7 +745,7 @@ __global__ void __launch_bounds__(NT) k_combine(const DevMesh* __restrict__ dm, 
     double2 s = make_double2(0.0, 0.0);
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
-      if (j < m) s = cadd(s, cmul(yy[j], V[j][o + e]));
+      if (j < m) s = cadd(s, cmul(yy[j], ldg2(V[j], o + e)));
     phi[o + e] = s;
   }
 }
@@ -758,6 +797,9 @@ __device__ __forceinline__ double pair_density(const double2* phi, int n, int64_
   return part == 0 ? (a.x * b.x + a.y * b.y) : (a.x * b.y - a.y * b.x);
 }
 
+// MAXO: outputs (harmonic x column) per thread, at least ceil(nout / NT);
+// compile-time, so the accumulators stay in registers.
+template <int MAXO>
 __global__ void __launch_bounds__(NT) k_moments(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
                                                 int lmax, int ncol, const int* __restrict__ colinfo,
                                                 double* __restrict__ part) {
@@ -769,7 +811,7 @@ __global__ void __launch_bounds__(NT) k_moments(const DevMesh* __restrict__ dm, 
   const int n = d.n;
   phi += d.oE * n;
   const double cx = d.center[0], cy = d.center[1], cz = d.center[2];
-  constexpr int MAXO = 48;
+  const int o0 = blockIdx.z * MAXO * NT;  // this workgroup's slice of the outputs
   double accv[MAXO];
 #pragma unroll
   for (int j = 0; j < MAXO; ++j) accv[j] = 0.0;
@@ -799,29 +841,29 @@ __global__ void __launch_bounds__(NT) k_moments(const DevMesh* __restrict__ dm, 
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < MAXO; ++j) {
-      int o = threadIdx.x + j * NT;
-      if (o >= nout) break;
-      int t = o / ncol, c = o - t * ncol;
-      double s = accv[j];
-      for (int r = 0; r < cnt; ++r) s += sR[r * nh + t] * sW[r * ncol + c];
-      accv[j] = s;
+      const int o = o0 + threadIdx.x + j * NT;
+      if (o < nout) {
+        const int t = o / ncol, c = o - t * ncol;
+        double s = accv[j];
+        for (int r = 0; r < cnt; ++r) s += sR[r * nh + t] * sW[r * ncol + c];
+        accv[j] = s;
+      }
     }
   }
   double* pb = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout;
 #pragma unroll
   for (int j = 0; j < MAXO; ++j) {
-    int o = threadIdx.x + j * NT;
+    const int o = o0 + threadIdx.x + j * NT;
     if (o < nout) pb[o] = accv[j];
   }
 }
 
-__global__ void k_sum_parts_real(const double* __restrict__ part, int nblk, int nout, double* __restrict__ out) {
-  const double* pi = part + (int64_t)blockIdx.y * nblk * nout;
-  for (int o = blockIdx.x * NT + threadIdx.x; o < nout; o += gridDim.x * NT) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += pi[(int64_t)b * nout + o];
-    out[(int64_t)blockIdx.y * nout + o] = s;
-  }
+// out[i][o] = sum_b part[i][b][o]; one workgroup per (output, instance)
+__global__ void __launch_bounds__(NT) k_sum_parts_real(const double* __restrict__ part, int nblk, int nout,
+                                                       double* __restrict__ out) {
+  __shared__ double lds4[4];
+  const double s = sum_partials(part + (int64_t)blockIdx.y * nblk * nout, nblk, nout, blockIdx.x, lds4);
+  if (threadIdx.x == 0) out[(int64_t)blockIdx.y * nout + blockIdx.x] = s;
 }
 
 // W[NE + b][c] = sum_t table[b][t] Q[t][c]
@@ -977,15 +1019,13 @@ __global__ void __launch_bounds__(NT) k_poisson_rhs(const DevMesh* __restrict__ 
   }
 }
 
-// sc[i][slot][c] = sum_b part[i][b][c]
-__global__ void k_col_sum(const double* __restrict__ part, int64_t part_stride, int nblk, int ncol,
-                          double* __restrict__ sc, int slot) {
-  part += blockIdx.y * part_stride;
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ncol + c];
-    sc[(int64_t)blockIdx.y * 8 * ncol + slot * ncol + c] = s;
-  }
+// sc[i][slot][c] = sum_b part[i][b][c]; one workgroup per (column, instance)
+__global__ void __launch_bounds__(NT) k_col_sum(const double* __restrict__ part, int64_t part_stride, int nblk,
+                                                int ncol, double* __restrict__ sc, int slot) {
+  __shared__ double lds4[4];
+  const int c = blockIdx.x;
+  const double s = sum_partials(part + blockIdx.y * part_stride, nblk, ncol, c, lds4);
+  if (threadIdx.x == 0) sc[(int64_t)blockIdx.y * 8 * ncol + slot * ncol + c] = s;
 }
 
 static int rhs_blocks(const Batch& b, int ncol) { return nblocks(b.mx.N, NT / ncol, 1024); }
@@ -993,9 +1033,21 @@ static int rhs_blocks(const Batch& b, int ncol) { return nblocks(b.mx.N, NT / nc
 void launch_poisson_pipeline_moments(const Batch& b, const double* phi, const int* colinfo, PoissonWs& P,
                                      hipStream_t s) {
   const int nout = P.nharm * P.ncol;
-  hipLaunchKernelGGL(k_moments, dim3(P.mblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, P.lmax, P.ncol,
-                     colinfo, P.mpart);
-  hipLaunchKernelGGL(k_sum_parts_real, dim3(nblocks(nout), b.ni), dim3(NT), 0, s, P.mpart, P.mblk, nout, P.Q);
+  // outputs per thread: at most 16 (registers); larger sets split over grid.z
+  const int per = (nout + NT - 1) / NT;
+  const double2* ph = (const double2*)phi;
+  if (per <= 4) {
+    hipLaunchKernelGGL(k_moments<4>, dim3(P.mblk, b.ni, 1), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
+                       P.mpart);
+  } else if (per <= 8) {
+    hipLaunchKernelGGL(k_moments<8>, dim3(P.mblk, b.ni, 1), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
+                       P.mpart);
+  } else {
+    const unsigned nz = (unsigned)((nout + 16 * NT - 1) / (16 * NT));
+    hipLaunchKernelGGL(k_moments<16>, dim3(P.mblk, b.ni, nz), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
+                       P.mpart);
+  }
+  hipLaunchKernelGGL(k_sum_parts_real, dim3(nout, b.ni), dim3(NT), 0, s, P.mpart, P.mblk, nout, P.Q);
 }
 
 void launch_bnd_eval(const Batch& b, PoissonWs& P, double* W, hipStream_t s) {
@@ -1012,7 +1064,7 @@ void launch_poisson_rhs_full(const Batch& b, const double* phi, double* W, const
   const int nb = rhs_blocks(b, ncol);
   hipLaunchKernelGGL(k_poisson_rhs, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, P.acc, ncol, colinfo,
                      rhs, P.part_stride, P.part);
-  hipLaunchKernelGGL(k_col_sum, dim3(1, b.ni), dim3(64), 0, s, P.part, P.part_stride, nb, ncol, P.sc, (int)SC_BB);
+  hipLaunchKernelGGL(k_col_sum, dim3(ncol, b.ni), dim3(NT), 0, s, P.part, P.part_stride, nb, ncol, P.sc, (int)SC_BB);
   // hanging rows of acc back to zero
   if (b.mx.Nh > 0)
     hipLaunchKernelGGL(k_zero_rows, dim3(nblocks(b.mx.Nh * ncol, NT, 4096), b.ni), dim3(NT), 0, s, b.dm, P.acc,

@@ -48,17 +48,25 @@ struct DevMesh {
   const int32_t* kt_ptr = nullptr;      // assembled Poisson operator on DoFs (CSR)
   const int32_t* kt_col = nullptr;
   const double* kt_val = nullptr;
+  const int32_t* kt_long = nullptr;      // rows of the assembled operator with more than KT_LONG entries
+  int64_t n_long = 0;
   const int32_t* bnd_cells = nullptr;
   int64_t n_bnd_cells = 0;
   const double* bnd_table = nullptr;    // [Nb][nharm] multipole boundary table
   double center[3] = {0.0, 0.0, 0.0};   // multipole expansion centre
   double E0 = 1.0;                      // field amplitude of this instance (E = E0 x the step's field value)
   double vnn = 0.0;                     // nuclear repulsion
-  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; grid caps (per instance)
-  int sched_orb = 1, sched_poi = 1, grid_orb = 65536, grid_poi = 8192;
+  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; Poisson bit 2 =
+  // long rows by whole waves, bit 3 = CG direction formed inside the operator pass;
+  // grid caps (per instance)
+  int sched_orb = 1, sched_poi = 13, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights
 };
+
+// Rows of the assembled Poisson operator longer than this are handled by whole
+// workgroups (the masters of hanging nodes: tens to hundreds of entries).
+constexpr int KT_LONG = 48;
 
 // A batch as seen by the launchers: the device array of instances, and a host
 // record with the shared parameters and the largest per-instance sizes (grid
@@ -88,6 +96,8 @@ void launch_copy(const double* in, double* out, int64_t nd, hipStream_t s);
 void launch_axpby(int64_t nd, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_zero(double* out, int64_t nd, hipStream_t s);
 void launch_set(double* out, double value, hipStream_t s);
+// x <- 2 x - xprev and xprev <- the old x (linear extrapolation in time) over nd doubles
+void launch_extrapolate(double* x, double* xprev, int64_t nd, hipStream_t s);
 
 // ---- reductions (segmented per instance) -----------------------------------------
 enum { ROWS_DOF = 0, ROWS_EXT = 1 };
@@ -129,10 +139,13 @@ void launch_combine(const Batch& b, double* const* V, int m, double* phi, Krylov
 struct PoissonWs {
   int ncol = 0, nharm = 0, lmax = 0;
   double* acc = nullptr;   // [tE][ncol]
-  double* p = nullptr;     // [tE][ncol]
+  double* p = nullptr;     // [tE][ncol] search direction (two buffers, alternating by iteration)
+  double* p2 = nullptr;
   double* r = nullptr;     // [tE][ncol]
   double* q = nullptr;     // [tE][ncol]
   double* sc = nullptr;    // [ni][8][ncol] scalars
+  double* red = nullptr;   // [ni][RED_SLOTS][ncol] atomic accumulators (rz x3, pq x2, rr x2; see stencil.hip)
+  int it = 0;              // CG iteration within the running solve
   double* part = nullptr;  // partials [ni][grid][2 ncol]
   int64_t part_stride = 0;
   double* Q = nullptr;     // moments [ni][nharm][ncol]
@@ -144,6 +157,11 @@ struct PoissonWs {
   int ev_cap = 0, ev_used = 0;
 };
 enum { SC_RZ = 0, SC_PQ = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RR = 4, SC_BB = 5, SC_RZN = 6 };
+// accumulator slots: r.D^-1 r of iteration k in RED_RZ + k % 3, p.q in RED_PQ + k % 2,
+// r.r after iteration k in RED_RR + k % 2
+enum { RED_RZ = 0, RED_PQ = 3, RED_RR = 5, RED_SLOTS = 8 };
+// slot of r.r after the last iteration of a solve that took `it` iterations (it >= 1)
+inline int red_rr_slot(int it) { return RED_RR + (it - 1) % 2; }
 void launch_poisson_pipeline_moments(const Batch& b, const double* phi, const int* colinfo, PoissonWs& P,
                                      hipStream_t s);
 void launch_bnd_eval(const Batch& b, PoissonWs& P, double* W, hipStream_t s);

@@ -22,6 +22,8 @@
 // Batched launches: instance blockIdx.y (kernels.hpp).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "devutil.hpp"
 #include "kernels.hpp"
 
@@ -59,9 +61,10 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
     double2 y = make_double2(0.0, 0.0), ui = make_double2(0.0, 0.0);
     if (act) ui = u[i * n + p];
     // the node's 8 incidence codes in two 16-byte loads (row of 32 bytes)
-    const int4* inc4 = reinterpret_cast<const int4*>(d.node_inc + i * 8);
-    int4 ca = inc4[0], cb = inc4[1];
-    if (diag_mode == 3) ca = cb = make_int4(-1, -1, -1, -1);  // dipole weights only: no stiffness
+    typedef int ivec4_t __attribute__((ext_vector_type(4)));
+    const auto* inc4 = reinterpret_cast<const __attribute__((address_space(1))) ivec4_t*>(gbl(d.node_inc) + i * 8);
+    ivec4_t ca = inc4[0], cb = inc4[1];
+    if (diag_mode == 3) ca = cb = ivec4_t{-1, -1, -1, -1};  // dipole weights only: no stiffness
     const int codes[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -70,7 +73,7 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
       const int64_t K = code >> 6;
       const int loc = code & 63;
       const int a = loc % P, b = (loc / P) % P, c = loc / (P * P);
-      const int32_t* cn = d.cell_nodes + K * P3;
+      const auto* cn = gbl(d.cell_nodes) + K * P3;
       double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
@@ -82,13 +85,13 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
           if (j2 < d.NE) { const double2 v = u[(int64_t)j2 * n + p]; s2.x += A2 * v.x; s2.y += A2 * v.y; }
         }
       }
-      const double hh = 0.5 * d.cell_hh[K];  // (1/2) K with K_cell = (h/2)(...)
+      const double hh = 0.5 * gbl(d.cell_hh)[K];  // (1/2) K with K_cell = (h/2)(...)
       const double f0 = hh * d.w[b] * d.w[c], f1 = hh * d.w[a] * d.w[c], f2 = hh * d.w[a] * d.w[b];
       y.x += f0 * s0.x + f1 * s1.x + f2 * s2.x;
       y.y += f0 * s0.y + f1 * s1.y + f2 * s2.y;
     }
     if (diag_mode >= 1 && act) {
-      const double dg = diag_mode == 3 ? d.mz[i] : d.v[i] + E * d.mz[i];
+      const double dg = diag_mode == 3 ? gbl(d.mz)[i] : gbl(d.v)[i] + E * gbl(d.mz)[i];
       y.x += dg * ui.x;
       y.y += dg * ui.y;
     }
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
         if (act) wv = cadd(wv, cmul(ginv[p * n + oo], zo));
       }
       if (act) {
-        const double mi = d.m[i];
+        const double mi = gbl(d.m)[i];
         y.x += mi * wv.x;
         y.y += mi * wv.y;
       }
@@ -125,10 +128,10 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
       }
     if (!act) continue;
     const bool dof = i < d.N;
-    const int mi = dof ? d.ma_index[i] : -1;
+    const int mi = dof ? gbl(d.ma_index)[i] : -1;
     if (dof && mi < 0) {
       if (mode == 0) out[i * n + p] = y;
-      else out[i * n + p] = csub(cscale(d.inv_mass[i], y), lm);
+      else out[i * n + p] = csub(cscale(gbl(d.inv_mass)[i], y), lm);
     } else {
       acc[i * n + p] = y;
     }
@@ -136,24 +139,58 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
 }
 
 // Masters: load value = acc_k + sum_h c_hk acc_h (transposed constraints).
+// One master per group of GATHER_G lanes splitting its hanging rows (about
+// fifty), combined by shuffles; all n orbitals at once.
+constexpr int GATHER_G = 16;
 __global__ void __launch_bounds__(NT) k_ma_gather_orb(const DevMesh* __restrict__ dm, const double2* __restrict__ acc,
                                                       int mode, double2* __restrict__ out,
                                                       double2* __restrict__ ma_b) {
   INSTANCE;
   const int n = d.n;
-  const int64_t total = d.nMa * n, o = d.oE * n, om = d.oMa * n;
-  for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
-    const int64_t i = idx / n;
-    const int p = (int)(idx - i * n);
-    const int64_t k = d.ma_dof[i];
-    double2 f = acc[o + k * n + p];
-    for (int t = d.ct_ptr[i]; t < d.ct_ptr[i + 1]; ++t) {
-      const double2 a = acc[o + (int64_t)d.ct_row[t] * n + p];
-      f.x += d.ct_w[t] * a.x;
-      f.y += d.ct_w[t] * a.y;
+  const int64_t o = d.oE * n, om = d.oMa * n;
+  const int g = (int)(threadIdx.x & (GATHER_G - 1));
+  const int64_t groups = (int64_t)gridDim.x * (NT / GATHER_G);
+  for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) / GATHER_G; i < d.nMa; i += groups) {
+    const int64_t k = gbl(d.ma_dof)[i];
+    double fx[8], fy[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) { fx[p] = 0.0; fy[p] = 0.0; }
+    if (g == 0) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < n) {
+          const double2 a = acc[o + k * n + p];
+          fx[p] = a.x;
+          fy[p] = a.y;
+        }
     }
-    if (mode == 0) out[o + k * n + p] = f;
-    else ma_b[om + idx] = f;
+    const auto* ctp = gbl(d.ct_ptr);
+    for (int t = ctp[i] + g; t < ctp[i + 1]; t += GATHER_G) {
+      const double w = gbl(d.ct_w)[t];
+      const double2* row = acc + o + (int64_t)gbl(d.ct_row)[t] * n;
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < n) {
+          const double2 a = row[p];
+          fx[p] += w * a.x;
+          fy[p] += w * a.y;
+        }
+    }
+#pragma unroll
+    for (int off = GATHER_G / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < n) {
+          fx[p] += __shfl_xor(fx[p], off, GATHER_G);
+          fy[p] += __shfl_xor(fy[p], off, GATHER_G);
+        }
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < n && p % GATHER_G == g) {
+        const double2 f = make_double2(fx[p], fy[p]);
+        if (mode == 0) out[o + k * n + p] = f;
+        else ma_b[om + i * n + p] = f;
+      }
   }
 }
 
@@ -165,8 +202,8 @@ __global__ void __launch_bounds__(NT) k_mass_direct(const DevMesh* __restrict__ 
   const int64_t total = d.N * n, o = d.oE * n, om = d.oMa * n;
   for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NT) {
     const int64_t k = idx / n;
-    const int mi = d.ma_index[k];
-    if (mi < 0) out[o + idx] = cscale(d.inv_mass[k], f[o + idx]);
+    const int mi = gbl(d.ma_index)[k];
+    if (mi < 0) out[o + idx] = cscale(gbl(d.inv_mass)[k], f[o + idx]);
     else ma_b[om + (int64_t)mi * n + (idx - k * n)] = f[o + idx];
   }
 }
@@ -202,7 +239,7 @@ void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int d
 
 void launch_ma_gather_orb(const Batch& b, const double* acc, int mode, double* out, double* ma_b, hipStream_t s) {
   if (b.mx.nMa == 0) return;
-  hipLaunchKernelGGL(k_ma_gather_orb, dim3(nblocks(b.mx.nMa * b.mx.n), b.ni), dim3(NT), 0, s, b.dm,
+  hipLaunchKernelGGL(k_ma_gather_orb, dim3(nblocks(b.mx.nMa * GATHER_G), b.ni), dim3(NT), 0, s, b.dm,
                      (const double2*)acc, mode, (double2*)out, (double2*)ma_b);
 }
 
@@ -215,289 +252,269 @@ void launch_mass_direct(const Batch& b, const double* f, double* out, double* ma
 // Assembled Poisson operator on the DoFs, K~ = C^T K_full C (CSR, built at
 // set-up from the element line couplings): one dependent level per row
 // (column index -> row of x), the hanging fill and the master gather folded
-// into the matrix.  The matrix (about 12 B per entry, ~14 entries per row)
-// is shared by all n^2 real columns, so it costs ~150 B per row against
-// 8 n^2 B of x per row.  L lanes per row (lane = column); fused p.q
-// partials.  x, q over extended rows (batch offset oE).
+// into the matrix.  The matrix (about 12 B per entry, ~22 entries per row)
+// is shared by all n^2 real columns.  L lanes per row, each owning V
+// adjacent columns (16-byte loads for V >= 2); fused p.q partials.  x, q
+// over extended rows (batch offset oE).
+//
+// Row lengths are very uneven: the masters of hanging nodes carry the
+// constrained neighbourhood (up to several hundred entries against a median
+// near 13).  Left to L lanes, such a row would keep its workgroup waiting
+// for hundreds of dependent loads.  So the first `nlb` workgroups take the
+// rows longer than KT_LONG, one row at a time per workgroup with all its
+// NT / L lane groups splitting the entries and an LDS reduction; the other
+// workgroups sweep the remaining rows.
 // --------------------------------------------------------------------------
-template <int L>
-__global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
-                                                     int ncol, double* __restrict__ q, int64_t part_stride,
-                                                     double* __restrict__ part) {
-  INSTANCE;
-  __shared__ double lds[NT];
-  x += d.oE * ncol;
-  q += d.oE * ncol;
-  const int c = (int)(threadIdx.x & (L - 1));
-  const bool col_ok = c < ncol;
-  double pq = 0.0;
-  const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1);
-  for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
-    if (!col_ok) continue;
-    const int beg = d.kt_ptr[i], end = d.kt_ptr[i + 1];
-    double y0 = 0.0, y1 = 0.0;
-    int t = beg;
-    for (; t + 4 <= end; t += 4) {
-      const int j0 = d.kt_col[t], j1 = d.kt_col[t + 1], j2 = d.kt_col[t + 2], j3 = d.kt_col[t + 3];
-      const double x0 = x[(int64_t)j0 * ncol + c], x1 = x[(int64_t)j1 * ncol + c];
-      const double x2 = x[(int64_t)j2 * ncol + c], x3 = x[(int64_t)j3 * ncol + c];
-      y0 += d.kt_val[t] * x0 + d.kt_val[t + 2] * x2;
-      y1 += d.kt_val[t + 1] * x1 + d.kt_val[t + 3] * x3;
+// Value of the operand at row j, columns c0 .. c0+V: x itself, or (FUSE) the CG
+// direction p_j = D^-1_j r_j + beta p_prev,j formed on the fly (x = r then).
+template <int V, bool FUSE>
+__device__ __forceinline__ void operand_row(const __attribute__((address_space(1))) double* xg,
+                                            const __attribute__((address_space(1))) double* pg,
+                                            const __attribute__((address_space(1))) double* dinv, const double* beta,
+                                            int64_t j, int ncol, int c0, double* out) {
+  const auto* row = xg + j * ncol + c0;
+  if constexpr (V == 1) {
+    out[0] = row[0];
+  } else {
+#pragma unroll
+    for (int v = 0; v < V / 2; ++v) {
+      const double2 r2 = ldg2((const double*)row, v);  // 16-byte aligned (ncol, c0 even)
+      out[2 * v] = r2.x;
+      out[2 * v + 1] = r2.y;
     }
-    for (; t < end; ++t) y0 += d.kt_val[t] * x[(int64_t)d.kt_col[t] * ncol + c];
-    const double y = y0 + y1;
-    q[i * ncol + c] = y;
-    pq += y * x[i * ncol + c];
   }
-  lds[threadIdx.x] = pq;
-  __syncthreads();
-  if (threadIdx.x < (unsigned)ncol) {
-    double s = 0.0;
-    for (int g = 0; g < NT / L; ++g) s += lds[g * L + threadIdx.x];
-    part[blockIdx.y * part_stride + (int64_t)blockIdx.x * ncol + threadIdx.x] = s;
+  if constexpr (FUSE) {
+    const double dj = dinv[j];
+    double pv[V];
+    const auto* prow = pg + j * ncol + c0;
+    if constexpr (V == 1) {
+      pv[0] = prow[0];
+    } else {
+#pragma unroll
+      for (int v = 0; v < V / 2; ++v) {
+        const double2 r2 = ldg2((const double*)prow, v);
+        pv[2 * v] = r2.x;
+        pv[2 * v + 1] = r2.y;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = dj * out[v] + (beta[v] != 0.0 ? beta[v] * pv[v] : 0.0);
   }
 }
 
-// Same operator for an even number of columns: each lane owns V = 2 or 4
-// adjacent columns (16-byte loads), so a wave keeps 64 V / ncol rows and
-// their column loads in flight at once (the single-column form is bound by
-// the latency of one row per wave).
-template <int L, int V>
-__global__ void __launch_bounds__(NT) k_spmv_poisson_v(const DevMesh* __restrict__ dm, const double* __restrict__ x,
-                                                       int ncol, double* __restrict__ q, int64_t part_stride,
-                                                       double* __restrict__ part) {
+// y += sum over entries t = beg, beg + stride, ... < end of val[t] operand(col[t]);
+// four entries per round with all their loads issued together.  Past the end
+// the index is clamped to the row's last entry (every row holds its diagonal)
+// and the coefficient zeroed, so the loads need no branch.
+template <int V, bool FUSE>
+__device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __restrict__ x,
+                                              const double* __restrict__ pprev, const double* beta, int ncol, int c0,
+                                              int beg, int end, int stride, double* y) {
+  const auto* kcol = gbl(d.kt_col);
+  const auto* kval = gbl(d.kt_val);
+  const auto* xg = gbl(x);
+  const auto* pg = gbl(pprev);
+  const auto* dinv = gbl(d.kdiag_inv);
+  for (int t = beg; t < end; t += 4 * stride) {
+    double av[4];
+    double xv[4][V];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tt = t + u * stride;
+      const int tc = tt < end ? tt : end - 1;
+      const int64_t j = kcol[tc];
+      const double a = kval[tc];
+      av[u] = tt < end ? a : 0.0;
+      operand_row<V, FUSE>(xg, pg, dinv, beta, j, ncol, c0, xv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < V; ++v) y[v] += av[u] * xv[u][v];
+  }
+}
+
+// Row i done: q_i = y, (FUSE) p_i = the operand of row i, and the p.q partial.
+template <int V, bool FUSE>
+__device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict__ q, double* __restrict__ pout,
+                                           const double* __restrict__ x, const double* __restrict__ pprev,
+                                           const double* beta, int64_t i, int ncol, int c0, const double* y,
+                                           double* pq) {
+  double pi[V];
+  operand_row<V, FUSE>(gbl(x), gbl(pprev), gbl(d.kdiag_inv), beta, i, ncol, c0, pi);
+  double* qo = q + i * ncol + c0;
+  double* po = pout + i * ncol + c0;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    qo[v] = y[v];
+    if constexpr (FUSE) po[v] = pi[v];
+    pq[v] += y[v] * pi[v];
+  }
+}
+
+template <int L, int V, bool FUSE>
+__global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
+                                                     const double* __restrict__ pprev, double* __restrict__ pout,
+                                                     int ncol, double* __restrict__ q, int nlb,
+                                                     double* __restrict__ red, int k) {
   INSTANCE;
   __shared__ double lds[NT * V];
   x += d.oE * ncol;
   q += d.oE * ncol;
+  pprev += d.oE * ncol;
+  pout += d.oE * ncol;
+  red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
   const int lane = (int)(threadIdx.x & (L - 1));
   const int c0 = lane * V;
   const bool col_ok = c0 < ncol;
+  // beta_k = rz_k / rz_{k-1} per column (0 at the first iteration)
+  double beta[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    beta[v] = 0.0;
+    if (FUSE && k > 0 && c0 + v < ncol) {
+      const double rzk = red[(RED_RZ + k % 3) * ncol + c0 + v], rzp = red[(RED_RZ + (k + 2) % 3) * ncol + c0 + v];
+      beta[v] = rzp != 0.0 ? rzk / rzp : 0.0;
+    }
+  }
   double pq[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) pq[v] = 0.0;
-  const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1);
-  for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
-    if (!col_ok) continue;
-    const int beg = d.kt_ptr[i], end = d.kt_ptr[i + 1];
-    double y[V];
+  if ((int)blockIdx.x < nlb) {
+    // long rows: one per wave at a time, its 64 / L lane groups splitting the
+    // entries, combined by shuffles (no workgroup barrier)
+    constexpr int SEG = 64 / L;
+    const int wave = threadIdx.x >> 6, seg = (threadIdx.x & 63) / L;
+    for (int64_t lr = (int64_t)blockIdx.x * (NT / 64) + wave; lr < d.n_long; lr += (int64_t)nlb * (NT / 64)) {
+      const int64_t i = gbl(d.kt_long)[lr];
+      const int beg = gbl(d.kt_ptr)[i], end = gbl(d.kt_ptr)[i + 1];
+      double y[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) y[v] = 0.0;
-    int t = beg;
-    for (; t + 4 <= end; t += 4) {
-      double2 xv[4][V / 2];
-      double av[4];
+      for (int v = 0; v < V; ++v) y[v] = 0.0;
+      if (col_ok) spmv_row_part<V, FUSE>(d, x, pprev, beta, ncol, c0, beg + seg, end, SEG, y);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t j = d.kt_col[t + u];
-        av[u] = d.kt_val[t + u];
-        const double2* row = reinterpret_cast<const double2*>(x + j * ncol + c0);
+      for (int off = L; off < 64; off <<= 1)
 #pragma unroll
-        for (int v = 0; v < V / 2; ++v) xv[u][v] = row[v];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < V / 2; ++v) {
-          y[2 * v] += av[u] * xv[u][v].x;
-          y[2 * v + 1] += av[u] * xv[u][v].y;
-        }
+        for (int v = 0; v < V; ++v) y[v] += __shfl_xor(y[v], off, 64);
+      if (seg == 0 && col_ok) spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ncol, c0, y, pq);
     }
-    for (; t < end; ++t) {
-      const double a = d.kt_val[t];
-      const double2* row = reinterpret_cast<const double2*>(x + (int64_t)d.kt_col[t] * ncol + c0);
+  } else {
+    const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
+    for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
+      if (!col_ok) continue;
+      const int beg = gbl(d.kt_ptr)[i], end = gbl(d.kt_ptr)[i + 1];
+      if (nlb > 0 && end - beg > KT_LONG) continue;  // taken by the long-row workgroups
+      double y[V];
 #pragma unroll
-      for (int v = 0; v < V / 2; ++v) {
-        const double2 r = row[v];
-        y[2 * v] += a * r.x;
-        y[2 * v + 1] += a * r.y;
-      }
-    }
-    double2* qo = reinterpret_cast<double2*>(q + i * ncol + c0);
-    const double2* xo = reinterpret_cast<const double2*>(x + i * ncol + c0);
-#pragma unroll
-    for (int v = 0; v < V / 2; ++v) {
-      qo[v] = make_double2(y[2 * v], y[2 * v + 1]);
-      const double2 xi = xo[v];
-      pq[2 * v] += y[2 * v] * xi.x;
-      pq[2 * v + 1] += y[2 * v + 1] * xi.y;
+      for (int v = 0; v < V; ++v) y[v] = 0.0;
+      spmv_row_part<V, FUSE>(d, x, pprev, beta, ncol, c0, beg, end, 1, y);
+      spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ncol, c0, y, pq);
     }
   }
+  // p.q of the workgroup: shuffles over the rows of each wave, then 4 waves
 #pragma unroll
-  for (int v = 0; v < V; ++v) lds[v * NT + threadIdx.x] = col_ok ? pq[v] : 0.0;
+  for (int off = L; off < 64; off <<= 1)
+#pragma unroll
+    for (int v = 0; v < V; ++v) pq[v] += __shfl_xor(pq[v], off, 64);
+  if ((threadIdx.x & 63) < (unsigned)L)
+#pragma unroll
+    for (int v = 0; v < V; ++v) lds[(threadIdx.x >> 6) * (L * V) + lane * V + v] = col_ok ? pq[v] : 0.0;
   __syncthreads();
   if (threadIdx.x < (unsigned)ncol) {
-    const int cl = threadIdx.x / V, cv = threadIdx.x % V;
-    double s = 0.0;
-    for (int g = 0; g < NT / L; ++g) s += lds[cv * NT + g * L + cl];
-    part[blockIdx.y * part_stride + (int64_t)blockIdx.x * ncol + threadIdx.x] = s;
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) sum += lds[w * (L * V) + threadIdx.x];
+    // iteration of this pass: k (fused), -2 - k (plain pass of a CG iteration), 0 (k = -1: start)
+    const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
+    atomicAdd(red + (RED_PQ + kk % 2) * ncol + threadIdx.x, sum);  // p.q of this instance and column
+    if (FUSE && blockIdx.x == 0) {  // clear what the update pass of this iteration accumulates into
+      red[(RED_RZ + (k + 1) % 3) * ncol + threadIdx.x] = 0.0;
+      red[(RED_RR + k % 2) * ncol + threadIdx.x] = 0.0;
+    }
   }
 }
 
-// Column-blocked form (ncol a multiple of 16, at most 4 blocks): the 8 XCDs
-// are split evenly over the 16-column blocks and each XCD sweeps a
-// contiguous share of the rows for its block only.  A row slice is then
-// 128 B, so the band of neighbour rows one XCD touches fits its L2; the
-// matrix is read once per column block.
-__global__ void __launch_bounds__(NT) k_spmv_poisson_cb(const DevMesh* __restrict__ dm, const double* __restrict__ x,
-                                                        int ncol, double* __restrict__ q, int64_t part_stride,
-                                                        double* __restrict__ part) {
-  INSTANCE;
-  constexpr int L = 4, V = 4, CB = 16;
-  __shared__ double lds[NT * V];
-  x += d.oE * ncol;
-  q += d.oE * ncol;
-  const int nblk_c = ncol / CB;
-  const int gpx = N_XCD / nblk_c;                 // XCDs per column block
-  const int xcd = blockIdx.x % N_XCD, lb = blockIdx.x / N_XCD, nbx = gridDim.x / N_XCD;
-  const int cblk = xcd / gpx, sub = xcd % gpx;
-  const int64_t R = (d.N + gpx - 1) / gpx;
-  const int64_t r0 = sub * R, r1 = (sub + 1) * R < d.N ? (sub + 1) * R : d.N;
-  const int lane = (int)(threadIdx.x & (L - 1));
-  const int c0 = cblk * CB + lane * V;
-  double pq[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) pq[v] = 0.0;
-  for (int64_t i = r0 + (int64_t)lb * (NT / L) + threadIdx.x / L; i < r1; i += (int64_t)nbx * (NT / L)) {
-    const int beg = d.kt_ptr[i], end = d.kt_ptr[i + 1];
-    double y[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) y[v] = 0.0;
-    int t = beg;
-    for (; t + 4 <= end; t += 4) {
-      double2 xv[4][2];
-      double av[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t j = d.kt_col[t + u];
-        av[u] = d.kt_val[t + u];
-        const double2* row = reinterpret_cast<const double2*>(x + j * ncol + c0);
-        xv[u][0] = row[0];
-        xv[u][1] = row[1];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        y[0] += av[u] * xv[u][0].x;
-        y[1] += av[u] * xv[u][0].y;
-        y[2] += av[u] * xv[u][1].x;
-        y[3] += av[u] * xv[u][1].y;
-      }
-    }
-    for (; t < end; ++t) {
-      const double a = d.kt_val[t];
-      const double2* row = reinterpret_cast<const double2*>(x + (int64_t)d.kt_col[t] * ncol + c0);
-      const double2 r0v = row[0], r1v = row[1];
-      y[0] += a * r0v.x;
-      y[1] += a * r0v.y;
-      y[2] += a * r1v.x;
-      y[3] += a * r1v.y;
-    }
-    double2* qo = reinterpret_cast<double2*>(q + i * ncol + c0);
-    const double2* xo = reinterpret_cast<const double2*>(x + i * ncol + c0);
-    qo[0] = make_double2(y[0], y[1]);
-    qo[1] = make_double2(y[2], y[3]);
-    const double2 xa = xo[0], xb = xo[1];
-    pq[0] += y[0] * xa.x;
-    pq[1] += y[1] * xa.y;
-    pq[2] += y[2] * xb.x;
-    pq[3] += y[3] * xb.y;
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) lds[v * NT + threadIdx.x] = pq[v];
-  __syncthreads();
-  for (int c = threadIdx.x; c < ncol; c += NT) {
-    double s = 0.0;
-    const int cc = c - cblk * CB;
-    if (cc >= 0 && cc < CB) {
-      const int cl = cc / V, cv = cc % V;
-      for (int g = 0; g < NT / L; ++g) s += lds[cv * NT + g * L + cl];
-    }
-    part[blockIdx.y * part_stride + (int64_t)blockIdx.x * ncol + c] = s;
-  }
+// Workgroups reserved for the long rows when schedule bit 2 is set: about
+// two rows per wave, a multiple of 8 (so the XCD of the sweeping workgroups is
+// unchanged).
+static int long_row_blocks(const Batch& b) {
+  if (b.mx.n_long == 0 || !(b.mx.sched_poi & 4)) return 0;
+  const int64_t nb = std::min<int64_t>((b.mx.n_long + 2 * (NT / 64) - 1) / (2 * (NT / 64)), 2048);
+  return (int)((nb + N_XCD - 1) / N_XCD * N_XCD);
 }
 
 template <int L, int V>
-static int launch_spmv_poisson_v(const Batch& b, const double* x, int ncol, double* q, const PoissonWs& P,
-                                 hipStream_t s) {
-  if ((b.mx.sched_poi & 2) && ncol % 16 == 0 && (ncol == 16 || ncol == 32 || ncol == 64)) {
-    const int grid = xcd_grid(b.mx.N * (ncol / 16), NT / 4, b.mx.grid_poi);
-    hipLaunchKernelGGL(k_spmv_poisson_cb, dim3(grid, b.ni), dim3(NT), 0, s, b.dm, x, ncol, q, P.part_stride, P.part);
-    return grid;
-  }
-  const int grid = xcd_grid(b.mx.N, NT / L, b.mx.grid_poi);
-  hipLaunchKernelGGL((k_spmv_poisson_v<L, V>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, x, ncol, q, P.part_stride,
-                     P.part);
-  return grid;
+static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, double* pout, int ncol, double* q,
+                          const PoissonWs& P, int k, hipStream_t s) {
+  const int nlb = long_row_blocks(b);
+  const int grid = nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi);
+  if (k >= 0)
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, x, pprev, pout, ncol, q,
+                       nlb, P.red, k);
+  else
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, x, pprev, pout, ncol,
+                       q, nlb, P.red, k);
 }
 
-template <int L>
-static int launch_spmv_poisson_t(const Batch& b, const double* x, int ncol, double* q, const PoissonWs& P,
-                                 hipStream_t s) {
-  const int grid = xcd_grid(b.mx.N, NT / L, b.mx.grid_poi);
-  hipLaunchKernelGGL((k_spmv_poisson<L>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, x, ncol, q, P.part_stride, P.part);
-  return grid;
-}
-
-static int launch_spmv_poisson(const Batch& b, const double* x, int ncol, double* q, const PoissonWs& P,
-                               hipStream_t s) {
+// q = K x (k < 0: k = -1 at the CG start, -2 - j for the plain pass of iteration j),
+// or for CG iteration k >= 0: p_k = D^-1 r + beta_k p_{k-1} formed on the fly from
+// x = r and pprev, written to pout, and q = K p_k.
+static void launch_spmv_poisson(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
+                                double* q, const PoissonWs& P, int k, hipStream_t s) {
   if (ncol % 2 == 0) {  // 16-byte column pairs
-    if (ncol <= 4) return launch_spmv_poisson_v<2, 2>(b, x, ncol, q, P, s);
-    if (ncol <= 16) return launch_spmv_poisson_v<4, 4>(b, x, ncol, q, P, s);
-    if (ncol <= 32) return launch_spmv_poisson_v<8, 4>(b, x, ncol, q, P, s);
-    return launch_spmv_poisson_v<16, 4>(b, x, ncol, q, P, s);
+    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, q, P, k, s);
+    if (ncol <= 16) return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, q, P, k, s);
+    if (ncol <= 32) return launch_spmv_t<8, 4>(b, x, pprev, pout, ncol, q, P, k, s);
+    return launch_spmv_t<16, 4>(b, x, pprev, pout, ncol, q, P, k, s);
   }
-  if (ncol <= 1) return launch_spmv_poisson_t<1>(b, x, ncol, q, P, s);
-  if (ncol <= 2) return launch_spmv_poisson_t<2>(b, x, ncol, q, P, s);
-  if (ncol <= 4) return launch_spmv_poisson_t<4>(b, x, ncol, q, P, s);
-  if (ncol <= 8) return launch_spmv_poisson_t<8>(b, x, ncol, q, P, s);
-  if (ncol <= 16) return launch_spmv_poisson_t<16>(b, x, ncol, q, P, s);
-  if (ncol <= 32) return launch_spmv_poisson_t<32>(b, x, ncol, q, P, s);
-  return launch_spmv_poisson_t<64>(b, x, ncol, q, P, s);
+  if (ncol <= 1) return launch_spmv_t<1, 1>(b, x, pprev, pout, ncol, q, P, k, s);
+  if (ncol <= 2) return launch_spmv_t<2, 1>(b, x, pprev, pout, ncol, q, P, k, s);
+  if (ncol <= 4) return launch_spmv_t<4, 1>(b, x, pprev, pout, ncol, q, P, k, s);
+  if (ncol <= 8) return launch_spmv_t<8, 1>(b, x, pprev, pout, ncol, q, P, k, s);
+  if (ncol <= 16) return launch_spmv_t<16, 1>(b, x, pprev, pout, ncol, q, P, k, s);
+  if (ncol <= 32) return launch_spmv_t<32, 1>(b, x, pprev, pout, ncol, q, P, k, s);
+  return launch_spmv_t<64, 1>(b, x, pprev, pout, ncol, q, P, k, s);
 }
 
 // --------------------------------------------------------------------------
 // Jacobi-preconditioned CG, all columns of all instances at once with their
 // own alpha and beta.  Scalars sc[i][slot][c] (SC_* in kernels.hpp).
 // --------------------------------------------------------------------------
-// alpha = rz / (p.q); one block per (column, instance)
-__global__ void __launch_bounds__(NT) k_alpha_finish(const double* __restrict__ part, int64_t part_stride, int nb,
-                                                     int ncol, double* __restrict__ sc) {
-  __shared__ double lds4[4];
-  const int c = blockIdx.x;
-  part += blockIdx.y * part_stride;
-  sc += (int64_t)blockIdx.y * 8 * ncol;
-  const double s = sum_partials(part, nb, ncol, c, lds4);
-  if (threadIdx.x == 0) {
-    sc[SC_PQ * ncol + c] = s;
-    const double rz = sc[SC_RZ * ncol + c];
-    sc[SC_ALPHA * ncol + c] = (s != 0.0 && rz != 0.0) ? rz / s : 0.0;
-  }
-}
+// One CG iteration is two launches.  The operator pass forms the direction
+// p_k = D^-1 r_k + beta_k p_{k-1} on the fly for every row it reads (beta_k =
+// rz_k / rz_{k-1} from the accumulators), writes p_k to the other direction
+// buffer, and accumulates p.q with FP64 atomics per instance and column.  The
+// update pass takes alpha_k = rz_k / p.q, updates x and r, and accumulates
+// rz_{k+1} and r.r.  The accumulators rotate (rz over three slots, p.q and
+// r.r over two), and each pass clears only slots that no workgroup of the
+// same launch reads, so no launch overwrites a value its own workgroups use.
 
-// x += alpha p; r -= alpha q; partial (r.D^-1 r, r.r).  x over full rows.
+// x += alpha p; r -= alpha q; accumulate (r.D^-1 r, r.r).  x over full rows.
 __global__ void __launch_bounds__(NT) k_cg_update2(const DevMesh* __restrict__ dm, double* __restrict__ x,
                                                    double* __restrict__ r, const double* __restrict__ p,
-                                                   const double* __restrict__ q, int ncol,
-                                                   const double* __restrict__ sc, int64_t part_stride,
-                                                   double* __restrict__ part) {
+                                                   const double* __restrict__ q, int ncol, double* __restrict__ red,
+                                                   int k) {
   INSTANCE;
   __shared__ double lds[2 * NT];
   x += d.oF * ncol;
   r += d.oE * ncol;
   p += d.oE * ncol;
   q += d.oE * ncol;
+  red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
   const int groups = NT / ncol;
   const int g = threadIdx.x / ncol, c = threadIdx.x - g * ncol;
   const bool act = g < groups;
+  const auto* dinv = gbl(d.kdiag_inv);
   double rz = 0.0, rr = 0.0;
   if (act) {
-    const double al = sc[(int64_t)blockIdx.y * 8 * ncol + SC_ALPHA * ncol + c];
-    for (int64_t k = (int64_t)blockIdx.x * groups + g; k < d.N; k += (int64_t)gridDim.x * groups) {
-      const int64_t e = k * ncol + c;
+    const double pq = red[(RED_PQ + k % 2) * ncol + c], rz0 = red[(RED_RZ + k % 3) * ncol + c];
+    const double al = (pq != 0.0 && rz0 != 0.0) ? rz0 / pq : 0.0;
+    for (int64_t kk = (int64_t)blockIdx.x * groups + g; kk < d.N; kk += (int64_t)gridDim.x * groups) {
+      const int64_t e = kk * ncol + c;
       x[e] += al * p[e];
       const double rn = r[e] - al * q[e];
       r[e] = rn;
-      rz += rn * rn * d.kdiag_inv[k];
+      rz += rn * rn * dinv[kk];
       rr += rn * rn;
     }
   }
@@ -510,57 +527,75 @@ __global__ void __launch_bounds__(NT) k_cg_update2(const DevMesh* __restrict__ d
       t += lds[gg * ncol + threadIdx.x];
       u += lds[NT + gg * ncol + threadIdx.x];
     }
-    double* pb = part + blockIdx.y * part_stride + (int64_t)blockIdx.x * 2 * ncol;
-    pb[threadIdx.x] = t;
-    pb[ncol + threadIdx.x] = u;
+    atomicAdd(red + (RED_RZ + (k + 1) % 3) * ncol + threadIdx.x, t);
+    atomicAdd(red + (RED_RR + k % 2) * ncol + threadIdx.x, u);
+    if (blockIdx.x == 0) red[(RED_PQ + (k + 1) % 2) * ncol + threadIdx.x] = 0.0;  // for the next operator pass
   }
 }
 
-// beta = rz_new / rz (mode 1) or initial rz (mode 0); rr.  One block per (column, instance).
-__global__ void __launch_bounds__(NT) k_rz_finish(const double* __restrict__ part, int64_t part_stride, int nblk,
-                                                  int ncol, double* __restrict__ sc, int mode) {
+// Direction pass for schedules without bit 3: p_k = D^-1 r_k + beta_k p_{k-1}
+// into pcur; workgroup 0 clears the slots the update pass of iteration k
+// accumulates into (the operator pass does this when it forms p_k itself).
+__global__ void __launch_bounds__(NT) k_cg_dir(const DevMesh* __restrict__ dm, const double* __restrict__ r,
+                                               const double* __restrict__ pprev, double* __restrict__ pcur, int ncol,
+                                               double* __restrict__ red, int k) {
+  INSTANCE;
+  __shared__ double beta[64];
+  const int64_t total = d.N * ncol;
+  r += d.oE * ncol;
+  pprev += d.oE * ncol;
+  pcur += d.oE * ncol;
+  red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
+  if (threadIdx.x < (unsigned)ncol) {
+    double bt = 0.0;
+    if (k > 0) {
+      const double rzk = red[(RED_RZ + k % 3) * ncol + threadIdx.x], rzp = red[(RED_RZ + (k + 2) % 3) * ncol + threadIdx.x];
+      bt = rzp != 0.0 ? rzk / rzp : 0.0;
+    }
+    beta[threadIdx.x] = bt;
+  }
+  __syncthreads();
+  const auto* dinv = gbl(d.kdiag_inv);
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int64_t kk = e / ncol;
+    const int c = (int)(e - kk * ncol);
+    const double bt = beta[c];
+    pcur[e] = dinv[kk] * r[e] + (bt != 0.0 ? bt * pprev[e] : 0.0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (unsigned)ncol) {
+    red[(RED_RZ + (k + 1) % 3) * ncol + threadIdx.x] = 0.0;
+    red[(RED_RR + k % 2) * ncol + threadIdx.x] = 0.0;
+  }
+}
+
+// Initial rz, rr from the start partials (rz_0 into slot RED_RZ, r.r also
+// into SC_RR); the other accumulators cleared.
+__global__ void __launch_bounds__(NT) k_rz_start(const double* __restrict__ part, int64_t part_stride, int nblk,
+                                                 int ncol, double* __restrict__ sc, double* __restrict__ red) {
   __shared__ double lds4[4];
   const int c = blockIdx.x;
   part += blockIdx.y * part_stride;
   sc += (int64_t)blockIdx.y * 8 * ncol;
+  red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
   const double s = sum_partials(part, nblk, 2 * ncol, c, lds4);
   const double u = sum_partials(part, nblk, 2 * ncol, ncol + c, lds4);
   if (threadIdx.x == 0) {
-    if (mode == 1) {
-      const double rz = sc[SC_RZ * ncol + c];
-      sc[SC_BETA * ncol + c] = (rz != 0.0) ? s / rz : 0.0;
-    }
+    for (int slot = 0; slot < RED_SLOTS; ++slot) red[slot * ncol + c] = 0.0;
+    red[RED_RZ * ncol + c] = s;
     sc[SC_RZ * ncol + c] = s;
     sc[SC_RR * ncol + c] = u;
   }
 }
 
-// p = D^-1 r + beta p
-__global__ void __launch_bounds__(NT) k_cg_p2(const DevMesh* __restrict__ dm, const double* __restrict__ r,
-                                              double* __restrict__ p, int ncol, const double* __restrict__ sc) {
-  INSTANCE;
-  const int64_t total = d.N * ncol;
-  r += d.oE * ncol;
-  p += d.oE * ncol;
-  const double* beta = sc + (int64_t)blockIdx.y * 8 * ncol + SC_BETA * ncol;
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int64_t k = e / ncol;
-    const int c = (int)(e - k * ncol);
-    p[e] = d.kdiag_inv[k] * r[e] + beta[c] * p[e];
-  }
-}
-
-// start: r = rhs - q (warm) or rhs (cold, x = 0); p = D^-1 r; partial rz, rr.  x over full rows.
+// start: r = rhs - q (warm) or rhs (cold, x = 0); partial rz, rr.  x over full rows.
 __global__ void __launch_bounds__(NT) k_cg_start2(const DevMesh* __restrict__ dm, double* __restrict__ x,
-                                                  double* __restrict__ r, const double* __restrict__ q,
-                                                  double* __restrict__ p, int ncol, int warm, int64_t part_stride,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ r, const double* __restrict__ q, int ncol,
+                                                  int warm, int64_t part_stride, double* __restrict__ part) {
   INSTANCE;
   __shared__ double lds[2 * NT];
   x += d.oF * ncol;
   r += d.oE * ncol;
   q += d.oE * ncol;
-  p += d.oE * ncol;
   const int groups = NT / ncol;
   const int g = threadIdx.x / ncol, c = threadIdx.x - g * ncol;
   const bool act = g < groups;
@@ -571,8 +606,8 @@ __global__ void __launch_bounds__(NT) k_cg_start2(const DevMesh* __restrict__ dm
       const double rn = warm ? r[e] - q[e] : r[e];
       if (!warm) x[e] = 0.0;
       r[e] = rn;
-      p[e] = d.kdiag_inv[k] * rn;
-      rz += rn * rn * d.kdiag_inv[k];
+      const double di = gbl(d.kdiag_inv)[k];
+      rz += rn * rn * di;
       rr += rn * rn;
     }
   lds[threadIdx.x] = act ? rz : 0.0;
@@ -602,40 +637,45 @@ __global__ void __launch_bounds__(NT) k_copy_dofs(const DevMesh* __restrict__ dm
 
 static int cg_blocks(const Batch& b, int ncol) { return nblocks(b.mx.N, NT / ncol, RED_BLOCKS); }
 
-// q = K p, alpha from p.q
-static void cg_apply2(const Batch& b, PoissonWs& P, double* pvec, double* qvec, hipStream_t s) {
-  const int ncol = P.ncol;
+// the operator pass with optional event timing on the launch stream
+static void cg_apply2(const Batch& b, PoissonWs& P, const double* x, const double* pprev, double* pout, double* q,
+                      int k, hipStream_t s) {
   const bool rec = P.ev && P.ev_used + 2 <= P.ev_cap;
   if (rec) (void)hipEventRecord(P.ev[P.ev_used], s);
-  const int nb1 = launch_spmv_poisson(b, pvec, ncol, qvec, P, s);
+  launch_spmv_poisson(b, x, pprev, pout, P.ncol, q, P, k, s);
   if (rec) {
     (void)hipEventRecord(P.ev[P.ev_used + 1], s);
     P.ev_used += 2;
   }
-  hipLaunchKernelGGL(k_alpha_finish, dim3(ncol, b.ni), dim3(NT), 0, s, P.part, P.part_stride, nb1, ncol, P.sc);
 }
 
 void launch_cg_start(const Batch& b, double* W, double* rhs_r, PoissonWs& P, int warm, hipStream_t s) {
   const int ncol = P.ncol;
-  if (warm) {
+  if (warm) {  // q = K x0, x0 = the DoF rows of W (staged in the first direction buffer)
     hipLaunchKernelGGL(k_copy_dofs, dim3(nblocks(b.mx.N * ncol, NT, 8192), b.ni), dim3(NT), 0, s, b.dm, W, P.p, ncol);
-    cg_apply2(b, P, P.p, P.q, s);
+    cg_apply2(b, P, P.p, P.p2, P.p2, P.q, -1, s);
   }
   const int nb = cg_blocks(b, ncol);
-  hipLaunchKernelGGL(k_cg_start2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, rhs_r, P.q, P.p, ncol, warm, P.part_stride,
+  hipLaunchKernelGGL(k_cg_start2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, rhs_r, P.q, ncol, warm, P.part_stride,
                      P.part);
-  hipLaunchKernelGGL(k_rz_finish, dim3(ncol, b.ni), dim3(NT), 0, s, P.part, P.part_stride, nb, ncol, P.sc, 0);
+  hipLaunchKernelGGL(k_rz_start, dim3(ncol, b.ni), dim3(NT), 0, s, P.part, P.part_stride, nb, ncol, P.sc, P.red);
+  P.it = 0;
 }
 
 void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s) {
-  const int ncol = P.ncol;
-  cg_apply2(b, P, P.p, P.q, s);
+  const int ncol = P.ncol, k = P.it;
+  double* pcur = (k % 2) ? P.p2 : P.p;
+  double* pprev = (k % 2) ? P.p : P.p2;
+  if (b.mx.sched_poi & 8) {
+    cg_apply2(b, P, P.r, pprev, pcur, P.q, k, s);  // direction formed inside the operator pass
+  } else {
+    hipLaunchKernelGGL(k_cg_dir, dim3(nblocks(b.mx.N * ncol, NT, 8192), b.ni), dim3(NT), 0, s, b.dm, P.r, pprev, pcur,
+                       ncol, P.red, k);
+    cg_apply2(b, P, pcur, pprev, pcur, P.q, -2 - k, s);  // plain operator pass of iteration k
+  }
   const int nb = cg_blocks(b, ncol);
-  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, P.p, P.q, ncol, P.sc, P.part_stride,
-                     P.part);
-  hipLaunchKernelGGL(k_rz_finish, dim3(ncol, b.ni), dim3(NT), 0, s, P.part, P.part_stride, nb, ncol, P.sc, 1);
-  hipLaunchKernelGGL(k_cg_p2, dim3(nblocks(b.mx.N * ncol, NT, 8192), b.ni), dim3(NT), 0, s, b.dm, P.r, P.p, ncol,
-                     P.sc);
+  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, pcur, P.q, ncol, P.red, k);
+  P.it = k + 1;
 }
 
 // y = a x + b y over nd doubles (a, b real)

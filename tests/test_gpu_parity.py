@@ -110,6 +110,31 @@ def test_poisson_pairs(name):
         assert num / den < 1e-9, (k, num / den, it)
 
 
+@pytest.mark.parametrize("name", ["tiny_q3", "small_n3"])
+def test_poisson_every_schedule(name):
+    """Each Poisson launch schedule (sweep order, long rows by waves, direction
+    fused into the operator pass) gives the oracle's potentials, cold and warm."""
+    from oracle.poisson import PoissonSolver
+    P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
+    n = P.w["n_orb"]
+    c = orbitals(P, 4)
+    ref = PoissonSolver(P.ops).pair_potentials(c)
+    torch = _torch()
+    x = dev(P.to_lib_orb(c))
+    for sched in (13, 12, 9, 8, 5, 4, 1, 0):
+        for grid in (8, 2048):
+            P.op.tune(1, sched, grid)
+            W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+            it, rc = P.op.poisson_pairs(x, W)
+            it2, rc2 = P.op.poisson_pairs(x, W, warm=True)
+            assert rc == 0 and rc2 == 0 and it2 <= it
+            got = P.W_from_lib(host(W), n)
+            for k in ref:
+                num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref[k]) ** 2))
+                den = np.sqrt(np.sum(P.ops.m * np.abs(ref[k]) ** 2))
+                assert num / den < 1e-9, (sched, grid, k, num / den)
+
+
 @pytest.mark.parametrize("name,nci", [("tiny_q3", 4), ("small_n3", 9)])
 def test_ci_rdms(name, nci):
     torch = _torch()
