@@ -57,15 +57,25 @@ def initial_state(name, w, mesh, op, torch):
     return phi, torch.from_numpy(np.ascontiguousarray(C)).cuda()
 
 
-def algorithmic_bytes(kind, info, op):
-    """Compulsory HBM bytes of one launch of the node-centric operator kernel:
+def spmv_bytes(N, ncol, nnz, n_inst, fused):
+    """Compulsory HBM bytes of one Poisson operator launch: x rows read and q rows
+    written once, the assembled operator once (column int32 + value), row
+    pointers; with the direction fused in (schedule bit 3) also r and the
+    previous direction read, the new direction written and D^-1 read."""
+    b = 16 * N * ncol + 12 * nnz + 4 * (N + n_inst)
+    if fused:
+        b += 16 * N * ncol + 8 * N   # x is r then; + p_prev read, p written (8 ncol each), D^-1
+    return b
+
+
+def algorithmic_bytes(kind, info, op, sched_poi=0):
+    """Compulsory HBM bytes of one launch of the dominant operator kernels:
     every input row read once, every output row written once, index data once."""
     P = info["p"] + 1
     nC, NE, N, n, ncol = info["n_cells"], op.n_ext, op.n_dof, op.n_orb, op.n_pair_cols
     meta = 32 * NE + 4 * P ** 3 * nC + 8 * nC + 4 * N          # node->cell table, cell maps, h/2, master index
     if kind == "poisson_spmv":
-        # x rows read and q rows written once; the assembled operator once (column int32 + value)
-        return 16 * N * ncol + 12 * op.n_poisson_nnz + 4 * (N + 1)
+        return spmv_bytes(N, ncol, op.n_poisson_nnz, op.n_inst, bool(sched_poi & 8))
     return 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + meta   # u, out, U, (m, v, mz), 1/m
 
 
@@ -119,6 +129,8 @@ def main():
                     help="short run for hardware-counter passes: CG iterations and RHS applications on the "
                          "workload's mesh, then a 1 GiB elementwise multiply for calibration; prints no JSON")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint vs plain comparison")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned schedules: read if it holds this workload, else written after tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -154,7 +166,7 @@ def main():
     op.propagate(phi, Ci, W, E[:2], dt, m=m, final=False)
     # schedules of the two operator kernels picked by the autotuner (untimed)
     from paper_2301_02387_amd.tune import autotune
-    sched = autotune(op, phi, W)
+    sched = autotune(op, phi, W, cache_file=args.tune_cache)
     # timed region: exactly `steps` steps
     op.kernel_timing(0, True)
     op.kernel_timing(1, True)
@@ -189,7 +201,8 @@ def main():
     kern = {"stencil_orb": {"avg_ms": k_orb[0], "count": k_orb[1]},
             "poisson_spmv": {"avg_ms": k_poi[0], "count": k_poi[1]}}
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["count"])
-    byts = algorithmic_bytes(dom, info, op)
+    byts = algorithmic_bytes(dom, info, op, sched["poisson"][0])
+    sched_tag = "/".join(map(str, sched["poisson"] if dom == "poisson_spmv" else sched["orbital"]))
     ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0
     line = {
         "metric": "orbital-RHS evals/s (DoF x orbitals/s)",
@@ -217,7 +230,9 @@ def main():
         "kernels": kern,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, f"{args.workload}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb"),
+                     "traffic": measured_traffic(dom, f"{args.workload}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb",
+                                                 schedule=sched_tag),
+                     "schedule": sched_tag,
                      "algorithmic_bytes_per_launch": byts},
     }
     if not args.no_adjoint:
@@ -227,10 +242,11 @@ def main():
     print(json.dumps(line))
 
 
-def measured_traffic(kernel, workload, profiles_dir=None, source=None):
-    """HBM bytes per launch of `kernel` on `workload` from the counter summaries
-    under profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated), or None
-    when none was taken or the kernel's source has changed since."""
+def measured_traffic(kernel, workload, profiles_dir=None, source=None, schedule=None):
+    """HBM bytes per launch of `kernel` on `workload` (under `schedule`) from the
+    counter summaries under profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
+    calibrated), or None when none was taken or the kernel's source has changed
+    since."""
     import glob
     import hashlib
     src = source or os.path.join(ROOT, "paper_2301_02387_amd", "csrc", "stencil.hip")
@@ -240,7 +256,8 @@ def measured_traffic(kernel, workload, profiles_dir=None, source=None):
             if not ln.startswith("traffic:"):
                 continue
             kv = dict(tok.split("=", 1) for tok in ln.split()[1:])
-            if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha1") == sha:
+            if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha1") == sha \
+                    and (schedule is None or kv.get("schedule", schedule) == schedule):
                 return float(kv["bytes_per_launch"])
     return None
 
@@ -298,6 +315,9 @@ def run_counters(args):
     c = h2o_guess(xyz) if args.workload == "h2o" else h2_guess(xyz, 0.7)
     phi = torch.from_numpy(np.ascontiguousarray(c)).cuda()
     op.fill_hanging(phi)
+    if args.tune_cache:   # the schedules the bench run tuned for this workload
+        from paper_2301_02387_amd.tune import apply_cached
+        log(f"schedules from the cache: {apply_cached(op, args.tune_cache)}")
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     it, _ = op.poisson_pairs(phi, W)
     log(f"cg iterations {it}")
@@ -353,7 +373,7 @@ def run_batch(args):
     t0 = Tp / 2
     shape = [float(pulse(t0 + k * dt, 1.0, cycles)) for k in range(args.steps + 1)]
     op.propagate(phi, Ci, W, shape[:2], dt, m=m, final=False)
-    sched = autotune(op, phi, W)
+    sched = autotune(op, phi, W, cache_file=args.tune_cache)
     log(f"warm-up and tuning done: {sched['orbital']} {sched['poisson']}")
     op.kernel_timing(0, True)
     op.kernel_timing(1, True)
@@ -395,12 +415,12 @@ def run_batch(args):
     evals = args.steps * m * op.n_dof * op.n_orb
     n_cells = sum(mm.info["n_cells"] for mm in meshes)
     ncol = op.n_pair_cols
-    spmv_bytes = 16 * op.n_dof * ncol + 12 * op.n_poisson_nnz + 4 * (op.n_dof + op.n_inst)
+    spmv_b = spmv_bytes(op.n_dof, ncol, op.n_poisson_nnz, op.n_inst, bool(sched["poisson"][0] & 8))
     P3 = (w0["p"] + 1) ** 3
     NE, N, n = op.n_ext, op.n_dof, op.n_orb
     orb_bytes = 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + 32 * NE + 4 * P3 * n_cells + 8 * n_cells + 4 * N
     kern = {"stencil_orb": {"avg_ms": k_orb[0], "count": k_orb[1], "algorithmic_bytes": orb_bytes},
-            "poisson_spmv": {"avg_ms": k_poi[0], "count": k_poi[1], "algorithmic_bytes": spmv_bytes}}
+            "poisson_spmv": {"avg_ms": k_poi[0], "count": k_poi[1], "algorithmic_bytes": spmv_b}}
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["count"])
     byts = kern[dom]["algorithmic_bytes"]
     ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0

@@ -6,7 +6,7 @@ caller's own inputs: the orbital operator by the library's event-pair kernel
 timing through ``rhs_apply`` (the frozen operator must be set), the Poisson
 solve by the wall time per CG iteration of a ``poisson_pairs`` solve from zero.  The
 fastest candidate is kept.  Results are cached in memory (and optionally in
-a JSON file) per (mesh signature, degree, orbitals, device).
+a JSON file) per (mesh signature, degree, orbitals, instances).
 """
 import json
 import os
@@ -20,11 +20,29 @@ _CACHE = {}
 
 
 def _key(op):
-    import torch
     info = op.mesh.info
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
     return (f"{info['n_cells']}-{info['n_dof']}-{info['n_hang']}-p{info['p']}-n{op.n_orb}"
-            f"-i{op.n_inst}-{op.n_dof}-{dev}")
+            f"-i{op.n_inst}-{op.n_dof}")
+
+
+def _load(cache_file):
+    if cache_file and os.path.exists(cache_file):
+        with open(cache_file) as f:
+            _CACHE.update({k: {kk: tuple(vv) if isinstance(vv, list) else vv for kk, vv in v.items()}
+                           for k, v in json.load(f).items()})
+
+
+def apply_cached(op, cache_file=None):
+    """Apply the tuned schedules of this operator from the cache, if present."""
+    key = _key(op)
+    if key not in _CACHE:
+        _load(cache_file)
+    if key not in _CACHE:
+        return None
+    best = _CACHE[key]
+    op.tune(0, *best["orbital"])
+    op.tune(1, *best["poisson"])
+    return best
 
 
 def autotune(op, phi, W, reps=5, cache_file=None):
@@ -37,14 +55,8 @@ def autotune(op, phi, W, reps=5, cache_file=None):
     """
     import torch
     key = _key(op)
-    if key not in _CACHE and cache_file and os.path.exists(cache_file):
-        with open(cache_file) as f:
-            _CACHE.update({k: {kk: tuple(vv) if isinstance(vv, list) else vv for kk, vv in v.items()}
-                           for k, v in json.load(f).items()})
-    if key in _CACHE:
-        best = _CACHE[key]
-        op.tune(0, *best["orbital"])
-        op.tune(1, *best["poisson"])
+    best = apply_cached(op, cache_file)
+    if best is not None:
         return best
     out = torch.empty_like(phi)
     times = {"orbital": {}, "poisson": {}}
