@@ -38,6 +38,7 @@ struct Mesh {
   std::vector<double> hang_w;
   std::vector<int32_t> masters;      // DoF masters, ascending
   std::vector<int64_t> level_counts;
+  std::vector<Ball> balls;           // the refinement request the mesh was built from
   Gll gll;
 };
 
@@ -77,6 +78,30 @@ struct OpHost {
 
 void build_operator(const Mesh& mesh, const std::vector<Nucleus>& nuc, const double pol[3],
                     int lmax, OpHost& op);
+
+// Geometric multigrid hierarchy for the assembled pair Poisson operator
+// (homogeneous Dirichlet problem on the DoFs).  Level 0 is the operator's own
+// mesh; level 1 is Q1 on the same leaves; then Q1 with every ball one level
+// shallower, down to the uniform base grid; then base grids of half the cells
+// per edge while the interior is larger than `max_coarse`.  The spaces are
+// nested, so the prolongation is nodal interpolation of the coarse function at
+// the fine DoF nodes (coarse hanging nodes expanded through their constraints,
+// coarse boundary nodes zero) and the restriction its transpose.
+struct MgLevel {
+  int64_t N = 0;                           // DoFs
+  std::vector<int32_t> k_ptr, k_col;       // operator (CSR over DoFs)
+  std::vector<double> k_val, dinv;         // values, 1 / diagonal
+  double lmax = 0;                         // largest eigenvalue of D^-1 K (power iteration, x 1.05)
+  std::vector<int32_t> p_ptr, p_col;       // prolongation from level l+1: rows = DoFs of l
+  std::vector<double> p_val;
+  std::vector<int32_t> r_ptr, r_col;       // restriction to level l+1 (transpose): rows = DoFs of l+1
+  std::vector<double> r_val;
+};
+struct MgHost {
+  std::vector<MgLevel> lv;                 // lv[0] finest ... lv.back() coarsest
+  std::vector<double> coarse_inv;          // dense inverse of the coarsest operator, row-major
+};
+void build_multigrid(const Mesh& fine, const OpHost& fop, MgHost& mg, int max_coarse = 1500);
 
 // Multipole harmonics shared by set-up and kernels: the order of the
 // (l, m, cos/sin) terms.  Term count for lmax: (lmax+1)^2.

@@ -163,6 +163,7 @@ std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ba
   if (!(hi > lo) || nc < 1) return "invalid box";
   const int P = p + 1;
   M.lo = lo; M.hi = hi; M.nc = nc; M.p = p; M.P = P;
+  M.balls = balls;
   M.H = (hi - lo) / nc;
   M.gll = make_gll(p);
   const double H = M.H;

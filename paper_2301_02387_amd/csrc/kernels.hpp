@@ -56,9 +56,9 @@ struct DevMesh {
   double center[3] = {0.0, 0.0, 0.0};   // multipole expansion centre
   double E0 = 1.0;                      // field amplitude of this instance (E = E0 x the step's field value)
   double vnn = 0.0;                     // nuclear repulsion
-  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; Poisson bit 2 =
-  // long rows by whole waves, bit 3 = CG direction formed inside the operator pass;
-  // grid caps (per instance)
+  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; Poisson bit 1 =
+  // column blocks of 16, bit 2 = long rows by whole waves, bit 3 = CG direction formed
+  // inside the operator pass; grid caps (per instance)
   int sched_orb = 1, sched_poi = 13, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights

@@ -271,8 +271,8 @@ template <int V, bool FUSE>
 __device__ __forceinline__ void operand_row(const __attribute__((address_space(1))) double* xg,
                                             const __attribute__((address_space(1))) double* pg,
                                             const __attribute__((address_space(1))) double* dinv, const double* beta,
-                                            int64_t j, int ncol, int c0, double* out) {
-  const auto* row = xg + j * ncol + c0;
+                                            int64_t j, int ld, int c0, double* out) {
+  const auto* row = xg + j * ld + c0;
   if constexpr (V == 1) {
     out[0] = row[0];
   } else {
@@ -286,7 +286,7 @@ __device__ __forceinline__ void operand_row(const __attribute__((address_space(1
   if constexpr (FUSE) {
     const double dj = dinv[j];
     double pv[V];
-    const auto* prow = pg + j * ncol + c0;
+    const auto* prow = pg + j * ld + c0;
     if constexpr (V == 1) {
       pv[0] = prow[0];
     } else {
@@ -308,7 +308,7 @@ __device__ __forceinline__ void operand_row(const __attribute__((address_space(1
 // and the coefficient zeroed, so the loads need no branch.
 template <int V, bool FUSE>
 __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __restrict__ x,
-                                              const double* __restrict__ pprev, const double* beta, int ncol, int c0,
+                                              const double* __restrict__ pprev, const double* beta, int ld, int c0,
                                               int beg, int end, int stride, double* y) {
   const auto* kcol = gbl(d.kt_col);
   const auto* kval = gbl(d.kt_val);
@@ -325,7 +325,7 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __
       const int64_t j = kcol[tc];
       const double a = kval[tc];
       av[u] = tt < end ? a : 0.0;
-      operand_row<V, FUSE>(xg, pg, dinv, beta, j, ncol, c0, xv[u]);
+      operand_row<V, FUSE>(xg, pg, dinv, beta, j, ld, c0, xv[u]);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -338,12 +338,12 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __
 template <int V, bool FUSE>
 __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict__ q, double* __restrict__ pout,
                                            const double* __restrict__ x, const double* __restrict__ pprev,
-                                           const double* beta, int64_t i, int ncol, int c0, const double* y,
+                                           const double* beta, int64_t i, int ld, int c0, const double* y,
                                            double* pq) {
   double pi[V];
-  operand_row<V, FUSE>(gbl(x), gbl(pprev), gbl(d.kdiag_inv), beta, i, ncol, c0, pi);
-  double* qo = q + i * ncol + c0;
-  double* po = pout + i * ncol + c0;
+  operand_row<V, FUSE>(gbl(x), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, pi);
+  double* qo = q + i * ld + c0;
+  double* po = pout + i * ld + c0;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     qo[v] = y[v];
@@ -352,28 +352,31 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict_
   }
 }
 
+// Columns [col0, col0 + nc) of arrays with ld columns per row, col0 = blockIdx.z * nc
+// (nc = ld without column blocking).
 template <int L, int V, bool FUSE>
 __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
                                                      const double* __restrict__ pprev, double* __restrict__ pout,
-                                                     int ncol, double* __restrict__ q, int nlb,
+                                                     int ld, int nc, double* __restrict__ q, int nlb,
                                                      double* __restrict__ red, int k) {
   INSTANCE;
   __shared__ double lds[NT * V];
-  x += d.oE * ncol;
-  q += d.oE * ncol;
-  pprev += d.oE * ncol;
-  pout += d.oE * ncol;
-  red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
+  const int col0 = blockIdx.z * nc;
+  x += d.oE * ld + col0;
+  q += d.oE * ld + col0;
+  pprev += d.oE * ld + col0;
+  pout += d.oE * ld + col0;
+  red += (int64_t)blockIdx.y * RED_SLOTS * ld + col0;
   const int lane = (int)(threadIdx.x & (L - 1));
   const int c0 = lane * V;
-  const bool col_ok = c0 < ncol;
+  const bool col_ok = c0 < nc;
   // beta_k = rz_k / rz_{k-1} per column (0 at the first iteration)
   double beta[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     beta[v] = 0.0;
-    if (FUSE && k > 0 && c0 + v < ncol) {
-      const double rzk = red[(RED_RZ + k % 3) * ncol + c0 + v], rzp = red[(RED_RZ + (k + 2) % 3) * ncol + c0 + v];
+    if (FUSE && k > 0 && c0 + v < nc) {
+      const double rzk = red[(RED_RZ + k % 3) * ld + c0 + v], rzp = red[(RED_RZ + (k + 2) % 3) * ld + c0 + v];
       beta[v] = rzp != 0.0 ? rzk / rzp : 0.0;
     }
   }
@@ -391,12 +394,12 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       double y[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) y[v] = 0.0;
-      if (col_ok) spmv_row_part<V, FUSE>(d, x, pprev, beta, ncol, c0, beg + seg, end, SEG, y);
+      if (col_ok) spmv_row_part<V, FUSE>(d, x, pprev, beta, ld, c0, beg + seg, end, SEG, y);
 #pragma unroll
       for (int off = L; off < 64; off <<= 1)
 #pragma unroll
         for (int v = 0; v < V; ++v) y[v] += __shfl_xor(y[v], off, 64);
-      if (seg == 0 && col_ok) spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ncol, c0, y, pq);
+      if (seg == 0 && col_ok) spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq);
     }
   } else {
     const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
@@ -407,8 +410,8 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       double y[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) y[v] = 0.0;
-      spmv_row_part<V, FUSE>(d, x, pprev, beta, ncol, c0, beg, end, 1, y);
-      spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ncol, c0, y, pq);
+      spmv_row_part<V, FUSE>(d, x, pprev, beta, ld, c0, beg, end, 1, y);
+      spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq);
     }
   }
   // p.q of the workgroup: shuffles over the rows of each wave, then 4 waves
@@ -420,16 +423,16 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
 #pragma unroll
     for (int v = 0; v < V; ++v) lds[(threadIdx.x >> 6) * (L * V) + lane * V + v] = col_ok ? pq[v] : 0.0;
   __syncthreads();
-  if (threadIdx.x < (unsigned)ncol) {
+  if (threadIdx.x < (unsigned)nc) {
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) sum += lds[w * (L * V) + threadIdx.x];
     // iteration of this pass: k (fused), -2 - k (plain pass of a CG iteration), 0 (k = -1: start)
     const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
-    atomicAdd(red + (RED_PQ + kk % 2) * ncol + threadIdx.x, sum);  // p.q of this instance and column
+    atomicAdd(red + (RED_PQ + kk % 2) * ld + threadIdx.x, sum);  // p.q of this instance and column
     if (FUSE && blockIdx.x == 0) {  // clear what the update pass of this iteration accumulates into
-      red[(RED_RZ + (k + 1) % 3) * ncol + threadIdx.x] = 0.0;
-      red[(RED_RR + k % 2) * ncol + threadIdx.x] = 0.0;
+      red[(RED_RZ + (k + 1) % 3) * ld + threadIdx.x] = 0.0;
+      red[(RED_RR + k % 2) * ld + threadIdx.x] = 0.0;
     }
   }
 }
@@ -444,36 +447,41 @@ static int long_row_blocks(const Batch& b) {
 }
 
 template <int L, int V>
-static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, double* pout, int ncol, double* q,
-                          const PoissonWs& P, int k, hipStream_t s) {
+static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, double* pout, int ld, int nc,
+                          double* q, const PoissonWs& P, int k, hipStream_t s) {
   const int nlb = long_row_blocks(b);
-  const int grid = nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi);
+  const dim3 g(nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi), b.ni, ld / nc);
   if (k >= 0)
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, x, pprev, pout, ncol, q,
-                       nlb, P.red, k);
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb, P.red,
+                       k);
   else
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, x, pprev, pout, ncol,
-                       q, nlb, P.red, k);
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
+                       P.red, k);
 }
 
 // q = K x (k < 0: k = -1 at the CG start, -2 - j for the plain pass of iteration j),
 // or for CG iteration k >= 0: p_k = D^-1 r + beta_k p_{k-1} formed on the fly from
 // x = r and pprev, written to pout, and q = K p_k.
+// Schedule bit 1 (column blocking): with 32 or more columns in multiples of 16,
+// grid.z runs over blocks of 16 columns, so a row slice is 128 B and the band of
+// neighbour rows a sweep touches stays in L2 (the matrix is read once per block).
 static void launch_spmv_poisson(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
                                 double* q, const PoissonWs& P, int k, hipStream_t s) {
+  if ((b.mx.sched_poi & 2) && ncol >= 32 && ncol % 16 == 0)
+    return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, 16, q, P, k, s);
   if (ncol % 2 == 0) {  // 16-byte column pairs
-    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, q, P, k, s);
-    if (ncol <= 16) return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, q, P, k, s);
-    if (ncol <= 32) return launch_spmv_t<8, 4>(b, x, pprev, pout, ncol, q, P, k, s);
-    return launch_spmv_t<16, 4>(b, x, pprev, pout, ncol, q, P, k, s);
+    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    if (ncol <= 16) return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    if (ncol <= 32) return launch_spmv_t<8, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    return launch_spmv_t<16, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
   }
-  if (ncol <= 1) return launch_spmv_t<1, 1>(b, x, pprev, pout, ncol, q, P, k, s);
-  if (ncol <= 2) return launch_spmv_t<2, 1>(b, x, pprev, pout, ncol, q, P, k, s);
-  if (ncol <= 4) return launch_spmv_t<4, 1>(b, x, pprev, pout, ncol, q, P, k, s);
-  if (ncol <= 8) return launch_spmv_t<8, 1>(b, x, pprev, pout, ncol, q, P, k, s);
-  if (ncol <= 16) return launch_spmv_t<16, 1>(b, x, pprev, pout, ncol, q, P, k, s);
-  if (ncol <= 32) return launch_spmv_t<32, 1>(b, x, pprev, pout, ncol, q, P, k, s);
-  return launch_spmv_t<64, 1>(b, x, pprev, pout, ncol, q, P, k, s);
+  if (ncol <= 1) return launch_spmv_t<1, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  if (ncol <= 2) return launch_spmv_t<2, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  if (ncol <= 4) return launch_spmv_t<4, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  if (ncol <= 8) return launch_spmv_t<8, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  if (ncol <= 16) return launch_spmv_t<16, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  if (ncol <= 32) return launch_spmv_t<32, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  return launch_spmv_t<64, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
 }
 
 // --------------------------------------------------------------------------

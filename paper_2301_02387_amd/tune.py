@@ -13,6 +13,8 @@ import os
 
 ORB_CANDIDATES = [(s, g) for s in (1, 0) for g in (2048, 8192, 65536)]
 POI_CANDIDATES = [(s, g) for s in (13, 12, 5, 4, 9, 1) for g in (2048, 8192)]
+# column blocking only changes anything at 32 or more columns (n >= 6 orbitals)
+POI_CANDIDATES_WIDE = [(s, g) for s in (15, 14, 7, 6, 13, 5, 4) for g in (2048, 8192)]
 # grid caps are per instance: a batch fills the chip with fewer workgroups each
 ORB_CANDIDATES_BATCH = [(s, g) for s in (1, 0) for g in (256, 1024, 65536)]
 POI_CANDIDATES_BATCH = [(s, g) for s in (13, 12, 5, 4, 1) for g in (256, 1024)]
@@ -73,7 +75,8 @@ def autotune(op, phi, W, reps=5, cache_file=None):
     # only in the operator kernel; every schedule takes the same iterations)
     import time
     Wt = torch.zeros_like(W)
-    for sched, grid in (POI_CANDIDATES_BATCH if batched else POI_CANDIDATES):
+    wide = op.n_pair_cols >= 32 and op.n_pair_cols % 16 == 0
+    for sched, grid in (POI_CANDIDATES_BATCH if batched else (POI_CANDIDATES_WIDE if wide else POI_CANDIDATES)):
         op.tune(1, sched, grid)
         Wt.zero_()
         torch.cuda.synchronize()

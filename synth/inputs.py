@@ -70,6 +70,10 @@ def small_workload(name, seed=0):
         return dict(name=name, lo=-5.0, hi=5.0, n_coarse=4, p=1,
                     balls=[_ball(rng.uniform(-0.5, 0.5, 3), 1.5, 2)],
                     nuclei=[(1.0, (0.3, -0.2, 0.1))], n_orb=2, n_alpha=1, n_beta=1)
+    if name == "tiny_n8":   # eight orbitals: 64 real pair columns (column-blocked Poisson schedules)
+        return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                    balls=[_ball(rng.uniform(-1, 1, 3), 1.0, 1)],
+                    nuclei=[(3.0, (0.0, 0.0, 0.0))], n_orb=8, n_alpha=1, n_beta=1)
     if name == "small_n3":
         return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
                     balls=[_ball((0.2, -0.3, 0.1), 1.5, 2)],

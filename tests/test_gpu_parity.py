@@ -110,10 +110,11 @@ def test_poisson_pairs(name):
         assert num / den < 1e-9, (k, num / den, it)
 
 
-@pytest.mark.parametrize("name", ["tiny_q3", "small_n3"])
+@pytest.mark.parametrize("name", ["tiny_q3", "small_n3", "tiny_n8"])
 def test_poisson_every_schedule(name):
-    """Each Poisson launch schedule (sweep order, long rows by waves, direction
-    fused into the operator pass) gives the oracle's potentials, cold and warm."""
+    """Each Poisson launch schedule (sweep order, column blocks, long rows by
+    waves, direction fused into the operator pass) gives the oracle's
+    potentials, cold and warm."""
     from oracle.poisson import PoissonSolver
     P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     n = P.w["n_orb"]
@@ -121,7 +122,7 @@ def test_poisson_every_schedule(name):
     ref = PoissonSolver(P.ops).pair_potentials(c)
     torch = _torch()
     x = dev(P.to_lib_orb(c))
-    for sched in (13, 12, 9, 8, 5, 4, 1, 0):
+    for sched in (15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
         for grid in (8, 2048):
             P.op.tune(1, sched, grid)
             W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
