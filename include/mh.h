@@ -233,24 +233,31 @@ int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const doubl
                  void* stream);
 
 /* Exact discrete adjoint of mh_propagate's dipole record with respect to
- * the field samples, for one orbital and one determinant (the one-electron
- * case, where MCTDHF is the time-dependent Schroedinger equation and the
- * frozen data reduce to a phase that cancels in the dipole; Sec. III.B
- * frozen-operator exponential, first order).  Given g_n = dJ/dd_n for the
- * record d_0..d_N of mh_propagate (real time, same phi0, Ci0, E_steps, dt,
- * m), returns dJ/dE_k for k < N (E_N does not enter the dipoles).
- * Backward recursion: nu_N = g_N M^-1 Z c_N, nu_k = exp(+i dt G_k) nu_{k+1}
- * + g_k M^-1 Z c_k, with dJ/dE_k = 2 dt int_0^1 Im[a(s)^H Z b(s)] ds,
- * a(s) = exp(+i (1-s) dt G_k) nu_{k+1}, b(s) = exp(-i s dt G_k) c_k
- * (Frechet derivative of the exponential), the integral by n_quad-point
- * Gauss-Legendre; every exponential is a short-iterative Arnoldi step.
- * Orbitals are recomputed from checkpoints every ckpt_stride steps (<= 0:
- * round(sqrt(N))).  phi0: device c128 [N_E][1]; Ci0: device c128 [1];
- * W_work: device double [N_F][1] (overwritten); E_steps: host [N + 1];
- * dJ_dd: host [N + 1]; dJ_dE: host out [N].  Allocates its checkpoint and
- * work vectors per call.  MH_UNSUPPORTED for a batch of several instances,
- * or for more than one orbital or
- * determinant.  Synchronises `stream`. */
+ * the field samples (reverse mode through the coupled orbital / CI steps of
+ * Sec. II, Eqs. ci_eom and orb_eom with X = 0, and the first-order frozen
+ * operator exponential of Sec. III.B).  Given g_n = dJ/dd_n for the record
+ * d_0..d_N of mh_propagate (real time, same phi0, Ci0, E_steps, dt, m),
+ * returns dJ/dE_k for k < N (E_N does not enter the dipoles).
+ * Per step, backwards: the orbital adjoint nu (M-weighted, dJ = Re <nu, dc>_M)
+ * is carried by exp(+i dt G^H), applied as the forward Arnoldi step of G with
+ * its orbital mixing replaced and the orbitals conjugated by the regularised
+ * 1-RDM; the CI adjoint kappa by exp(+i dt H_CI).  The Frechet derivatives
+ * of both exponentials (n_quad-point Gauss-Legendre in s of
+ * exp(-i(1-s)dt A) dA exp(-i s dt A)) give the sensitivities of the field,
+ * of lambda, of the mean field V = gamma^-1 U and of the CI integrals h and g;
+ * these are pushed back through U = Gamma W, through the pair Poisson solves
+ * (one adjoint CG solve per step on all pair columns, with the transposed
+ * multipole boundary lift) and the pair densities to the orbitals, and
+ * through the RDMs to the CI vector.  Orbitals, CI vectors and pair
+ * potentials are recomputed from checkpoints every ckpt_stride steps (<= 0:
+ * round(sqrt(N))).  phi0: device c128 [N_E][n]; Ci0: device c128 [N_CI];
+ * W_work: device double [N_F][n*n] warm-start buffer (overwritten);
+ * E_steps: host [N + 1]; dJ_dd: host [N + 1]; dJ_dE: host out [N].
+ * Allocates its checkpoint and work vectors per call.  MH_UNSUPPORTED for a
+ * batch of several instances, more than 4 orbitals or more than 12
+ * determinants (the CI exponential must be exact); MH_NOT_CONVERGED when a
+ * Poisson solve stopped at the iteration cap (the gradient is still
+ * returned).  Synchronises `stream`. */
 int mh_propagate_adjoint(mh_op* op, const double* phi0, const double* Ci0, double* W_work,
                          const double* E_steps, int32_t n_steps, double dt, int32_t m,
                          const double* dJ_dd, double* dJ_dE, int32_t n_quad, int32_t ckpt_stride,

@@ -1,6 +1,7 @@
 """Differentiable dipole record: a ``torch.autograd.Function`` over
 ``Operator.propagate`` whose backward is the library's hand-written adjoint
-(``mh_propagate_adjoint``, one orbital and one determinant).
+(``mh_propagate_adjoint``: orbitals, mean field and CI vector, up to 4
+orbitals and 12 determinants).
 
 Forward: propagate from (phi0, C0) with the step fields E_steps and return
 the dipole record d_0..d_N (CPU float64).  Backward: dJ/dE_k from the

@@ -15,6 +15,7 @@
 
 #include "../../include/mh.h"
 #include "host.hpp"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace mh;
@@ -1056,6 +1057,24 @@ static void mass_dipole(mh_op* op, const double* u, double* out, hipStream_t s) 
   launch_fill_orb(B, out, nullptr, s);
 }
 
+// out = M^-1 H1(E) u at the field value in Ebuf[0], hanging rows filled
+static void mass_h1(mh_op* op, const double* u, double* out, hipStream_t s) {
+  const Batch& B = op->B;
+  stencil_orb(op, u, op->Ebuf, 1, 1, out, s);
+  launch_ma_gather_orb(B, op->acc, 1, out, op->ma_b, s);
+  launch_ma_solve(B, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, nullptr, nullptr, out, s);
+  launch_fill_orb(B, out, nullptr, s);
+}
+
+// out = M^-1 C^T f for a full-node load f given at the extended rows
+static void mass_load(mh_op* op, const double* f, double* out, hipStream_t s) {
+  const Batch& B = op->B;
+  launch_load_split(B, f, out, op->acc, s);
+  launch_ma_gather_orb(B, op->acc, 1, out, op->ma_b, s);
+  launch_ma_solve(B, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, nullptr, nullptr, out, s);
+  launch_fill_orb(B, out, nullptr, s);
+}
+
 namespace {
 struct DevScratch {
   std::vector<void*> p;
@@ -1071,48 +1090,115 @@ struct DevScratch {
 };
 }  // namespace
 
+// CG on the assembled Poisson operator for the right-hand side already in
+// P.r (with |rhs|^2 in the SC_BB scalars), cold start, solution in the DoF
+// rows of the full-row array Z.
+static int cg_solve_rhs(mh_op* op, double* Z, int* iters, hipStream_t s) {
+  const Batch& B = op->B;
+  PoissonWs& P = op->P;
+  launch_cg_start(B, Z, P.r, P, 0, s);
+  int it = 0, conv = 0;
+  while (it < op->maxit) {
+    const int todo = std::min(8, op->maxit - it);
+    for (int k = 0; k < todo; ++k) launch_cg_step(B, Z, P, s);
+    it += todo;
+    conv = poisson_converged(op, s);
+    if (conv < 0) return fail(MH_NONFINITE, "non-finite adjoint Poisson residual");
+    if (conv) break;
+  }
+  if (iters) *iters = it;
+  return conv ? MH_OK : MH_NOT_CONVERGED;
+}
+
 extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double* Ci0, double* W_work,
                                     const double* E_steps, int32_t n_steps, double dt, int32_t m,
                                     const double* dJ_dd, double* dJ_dE, int32_t n_quad, int32_t ckpt_stride,
                                     void* stream) {
   if (!op || !phi0 || !Ci0 || !W_work || !E_steps || !dJ_dd || !dJ_dE) return fail(MH_INVALID_ARG, "null argument");
   if (op->ni != 1) return fail(MH_UNSUPPORTED, "the adjoint takes a single instance");
-  if (op->n != 1 || op->ci.dim != 1)
-    return fail(MH_UNSUPPORTED, "the adjoint is implemented for one orbital and one determinant");
+  if (op->n > 4) return fail(MH_UNSUPPORTED, "the adjoint is implemented for at most 4 orbitals");
+  if (op->ci.dim > 12) return fail(MH_UNSUPPORTED, "the adjoint needs an exact CI exponential (at most 12 determinants)");
   if (n_steps < 1 || m < 1 || m > 24 || n_quad < 1 || n_quad > 16) return fail(MH_INVALID_ARG, "bad sizes");
   return guarded([&]() -> int {
     hipStream_t s = S(stream);
     const Batch& B = op->B;
-    const size_t len = (size_t)2 * B.tE * op->n;
+    const int n = op->n, nn = n * n, ncol = op->ncol, dim = op->ci.dim;
+    const int mci = std::min(12, dim);
+    const size_t len = (size_t)2 * B.tE * n, clen = (size_t)2 * dim, wlen = (size_t)B.tF * ncol;
     const int S_ = ckpt_stride > 0 ? ckpt_stride : std::max(1, (int)std::lround(std::sqrt((double)n_steps)));
+    int status = MH_OK;
     DevScratch mem;
     const int nck = n_steps / S_ + 1;
-    std::vector<double*> ck(nck), seg(S_ + 1);
-    for (auto& v : ck) v = mem.get(len);
-    for (auto& v : seg) v = mem.get(len);
-    double* cur = mem.get(len);
-    double* nu = mem.get(len);
-    double* va = mem.get(len);
-    double* vb = mem.get(len);
-    double* tmp = mem.get(len);
-    double* zbuf = mem.get((size_t)2 * n_steps * n_quad);
-    // one orbital, one determinant: gamma = 1, Gamma = 0, so the mean field vanishes
-    launch_ci_rdm_full(1, op->ci, Ci0, op->gam, op->Gam, op->Gtmp, s);
-    launch_zero(W_work, B.tF * op->ncol, s);
-    auto step_forward = [&](double* c, int k) {
-      freeze(op, c, op->gam, op->Gam, E_steps[k], W_work, s);
-      arnoldi(op, c, dt, 0.0, m, s);
+    std::vector<double*> ck(nck), ckC(nck), seg(S_ + 1), segC(S_ + 1), segW(S_);
+    for (int i = 0; i < nck; ++i) { ck[i] = mem.get(len); ckC[i] = mem.get(clen); }
+    for (int i = 0; i <= S_; ++i) { seg[i] = mem.get(len); segC[i] = mem.get(clen); }
+    for (int i = 0; i < S_; ++i) segW[i] = mem.get(wlen);
+    double* cur = mem.get(len), *curC = mem.get(clen);
+    double* nu = mem.get(len), *va = mem.get(len), *vb = mem.get(len), *t1 = mem.get(len), *t2 = mem.get(len);
+    double* Fc = mem.get(len), *Phib = mem.get(len);
+    double* Q = mem.get((size_t)2 * B.tE * nn);
+    double* Kw = mem.get(wlen), *Zb = mem.get(wlen);
+    double* tb = mem.get((size_t)std::max<int64_t>(1, B.mx.Nb) * ncol);
+    double* qlm = mem.get((size_t)op->P.nharm * ncol);
+    double* qwpart = mem.get((size_t)qw_part_doubles(B));
+    double* sm = mem.get((size_t)2 * ADJ_NBLK * nn);
+    double* Kg = mem.get((size_t)2 * nn * nn), *KGam = mem.get((size_t)2 * nn * nn), *G2 = mem.get((size_t)2 * nn * nn);
+    double* tgam = mem.get((size_t)2 * nn), *tGam = mem.get((size_t)2 * nn * nn);
+    double* th = mem.get((size_t)2 * nn), *tg2 = mem.get((size_t)2 * nn * nn);
+    double* Gz = mem.get((size_t)2 * nn), *Sm = mem.get((size_t)2 * nn);
+    double* kap = mem.get(clen), *ca = mem.get(clen), *cb = mem.get(clen), *sig = mem.get(clen);
+    double* DA = mem.get((size_t)2 * dim * nn), *DB = mem.get((size_t)2 * dim * nn);
+    double* ebar = mem.get((size_t)n_steps + 1);
+    launch_zero(ebar, n_steps + 1, s);
+    double* XG = sm + 2 * ADJ_XG * nn, *XR = sm + 2 * ADJ_XR * nn, *L2 = sm + 2 * ADJ_LAM2 * nn;
+    double* XL1 = sm + 2 * ADJ_XL1 * nn, *XL2 = sm + 2 * ADJ_XL2 * nn, *XH = sm + 2 * ADJ_XH * nn;
+    double* XD = sm + 2 * ADJ_XD * nn, *KH = sm + 2 * ADJ_KH * nn;
+    ensure_krylov(op, m);
+
+    // one forward step of mh_propagate (real time), W warm-started from its contents
+    auto fwd_step = [&](double* c, double* Cv, double* W, int k) -> int {
+      launch_ci_rdm_full(1, op->ci, Cv, op->gam, op->Gam, op->Gtmp, s);
+      int it = 0;
+      const int rc = poisson_solve(op, c, W, 1, &it, s);
+      if (rc < 0) return rc;
+      if (rc == MH_NOT_CONVERGED) status = MH_NOT_CONVERGED;
+      launch_set(op->Ebuf, E_steps[k], s);
+      step_after_poisson(op, c, Cv, W, 1, dt, 0.0, m, 0, s);
+      return MH_OK;
     };
+    // x <- exp(+i tau G^H) x in the M inner product: G^H = R(gr^T) G'' R(ginv^T),
+    // G'' = M^-1 H_F - R(lam2) (the forward operator with the mixing lam2)
+    auto adj_exp = [&](double* x, double tau) {
+      launch_mix(B, x, XG, 0.0, t2, s);
+      double* lam_alt = L2;
+      std::swap(op->lam, lam_alt);
+      arnoldi(op, t2, -tau, 0.0, m, s);
+      std::swap(op->lam, lam_alt);
+      launch_mix(B, t2, XR, 0.0, x, s);
+    };
+
     // forward sweep with checkpoints every S_ steps
     launch_copy(phi0, cur, len, s);
+    launch_copy(Ci0, curC, clen, s);
     for (int k = 0; k < n_steps; ++k) {
-      if (k % S_ == 0) launch_copy(cur, ck[k / S_], len, s);
-      step_forward(cur, k);
+      if (k % S_ == 0) {
+        launch_copy(cur, ck[k / S_], len, s);
+        launch_copy(curC, ckC[k / S_], clen, s);
+      }
+      const int rc = fwd_step(cur, curC, W_work, k);
+      if (rc < 0) return rc;
     }
-    // nu_N = g_N M^-1 Z c_N
-    mass_dipole(op, cur, nu, s);
-    launch_axpby(len, 0.0, nu, dJ_dd[n_steps], nu, s);
-    // Gauss-Legendre nodes on [0, 1] for the Frechet integral of the exponential
+    // terminal adjoint state from d_N
+    launch_ci_rdm_full(1, op->ci, curC, op->gam, op->Gam, op->Gtmp, s);
+    launch_gram(B, cur, cur, WT_DIPOLE, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), op->zmat, s);
+    launch_zero(sm, 2 * ADJ_NBLK * nn, s);
+    launch_zero(KGam, 2 * nn * nn, s);
+    launch_adj_terms(op->zmat, op->gam, dJ_dd[n_steps], n, ebar + n_steps, sm, s);
+    launch_mix(B, cur, XD, 0.0, t1, s);
+    mass_dipole(op, t1, nu, s);
+    launch_adj_ciprep(sm, KGam, n, th, tg2, s);
+    launch_ci_apply(1, op->ci, th, tg2, curC, kap, s);
+
     std::vector<double> gx, gw;
     gauss_legendre(n_quad, gx, gw);
     for (int j = 0; j < n_quad; ++j) {
@@ -1121,35 +1207,112 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
     }
     for (int s0 = ((n_steps - 1) / S_) * S_; s0 >= 0; s0 -= S_) {
       const int s1 = std::min(s0 + S_, n_steps);
+      // recompute the segment: states and pair potentials of steps s0 .. s1-1
       launch_copy(ck[s0 / S_], seg[0], len, s);
-      for (int k = s0; k + 1 < s1; ++k) {
-        launch_copy(seg[k - s0], seg[k - s0 + 1], len, s);
-        step_forward(seg[k - s0 + 1], k);
+      launch_copy(ckC[s0 / S_], segC[0], clen, s);
+      for (int k = s0; k < s1; ++k) {
+        const int j = k - s0;
+        launch_copy(j == 0 ? W_work : segW[j - 1], segW[j], wlen, s);
+        launch_ci_rdm_full(1, op->ci, segC[j], op->gam, op->Gam, op->Gtmp, s);
+        int it = 0;
+        const int rc = poisson_solve(op, seg[j], segW[j], 1, &it, s);
+        if (rc < 0) return rc;
+        if (rc == MH_NOT_CONVERGED) status = MH_NOT_CONVERGED;
+        if (k + 1 < s1) {
+          launch_copy(seg[j], seg[j + 1], len, s);
+          launch_copy(segC[j], segC[j + 1], clen, s);
+          launch_set(op->Ebuf, E_steps[k], s);
+          step_after_poisson(op, seg[j + 1], segC[j + 1], segW[j], 1, dt, 0.0, m, 0, s);
+        }
       }
       for (int k = s1 - 1; k >= s0; --k) {
-        double* ckk = seg[k - s0];
-        freeze(op, ckk, op->gam, op->Gam, E_steps[k], W_work, s);
+        double* c = seg[k - s0];
+        double* Cv = segC[k - s0];
+        double* W = segW[k - s0];
+        const double g = dJ_dd[k];
+        launch_zero(sm, 2 * ADJ_NBLK * nn, s);
+        launch_zero(Kg, 2 * nn * nn, s);
+        launch_zero(Q, 2 * B.tE * nn, s);
+        // frozen data, integrals and observables of step k
+        launch_ci_rdm_full(1, op->ci, Cv, op->gam, op->Gam, op->Gtmp, s);
+        launch_set(op->Ebuf, E_steps[k], s);
+        freeze_body(op, c, op->gam, op->Gam, W, s);
+        load_vector(op, c, op->Ebuf, 1, op->F, s);
+        launch_gram(B, c, op->F, WT_NONE, ROWS_DOF, op->gpart, gram_blocks(B.mx.N), op->hmat, s);
+        launch_gint_full(B, c, W, op->colmap, op->gpart, gint_blocks(B), op->Gtmp, op->gint, s);
+        launch_gram(B, c, c, WT_DIPOLE, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), op->zmat, s);
+        launch_ci_hprime(1, op->ci, op->hmat, op->gint, s);
+        g_apply(op, c, Fc, 0, s);
+        launch_adj_prep(op->ginv, op->lam, n, sm, s);
+        // orbital exponential: Frechet quadrature, then nu_k = exp(+i dt G^H) nu_{k+1}
         for (int j = 0; j < n_quad; ++j) {
-          launch_copy(ckk, vb, len, s);
-          arnoldi(op, vb, gx[j] * dt, 0.0, m, s);          // b = exp(-i s dt G) c_k
+          const double wi = -dt * gw[j];  // omega_j = -i dt w_j
+          launch_copy(c, vb, len, s);
+          arnoldi(op, vb, gx[j] * dt, 0.0, m, s);
           launch_copy(nu, va, len, s);
-          arnoldi(op, va, -(1.0 - gx[j]) * dt, 0.0, m, s);  // a = exp(+i (1-s) dt G) nu_{k+1}
-          launch_gram(B, va, vb, WT_DIPOLE, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE),
-                      zbuf + 2 * ((size_t)k * n_quad + j), s);
+          adj_exp(va, (1.0 - gx[j]) * dt);
+          launch_gram(B, va, vb, WT_DIPOLE, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), Gz, s);
+          launch_gram(B, va, vb, WT_MASS, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), Sm, s);
+          launch_adj_quad(Gz, Sm, 0.0, wi, n, ebar + k, sm, s);
+          launch_q_accum(B, va, vb, 0.0, wi, Q, s);
         }
-        arnoldi(op, nu, -dt, 0.0, m, s);                    // nu <- exp(+i dt G) nu
-        mass_dipole(op, ckk, tmp, s);
-        launch_axpby(len, dJ_dd[k], tmp, 1.0, nu, s);      // nu += g_k M^-1 Z c_k
+        adj_exp(nu, dt);
+        // CI exponential: the same quadrature, then kappa_k = exp(+i dt H) kappa_{k+1}
+        for (int j = 0; j < n_quad; ++j) {
+          const double wi = -dt * gw[j];
+          launch_copy(kap, ca, clen, s);
+          launch_ci_lanczos(1, op->ci, op->Qdev, op->Qh.data(), mci, op->gint, ca, op->KC, -(1.0 - gx[j]) * dt, 0.0,
+                            0, s);
+          launch_copy(Cv, cb, clen, s);
+          launch_ci_lanczos(1, op->ci, op->Qdev, op->Qh.data(), mci, op->gint, cb, op->KC, gx[j] * dt, 0.0, 0, s);
+          launch_ci_trdm(1, op->ci, ca, cb, DA, DB, tgam, tGam, op->Gtmp, s);
+          launch_caxpy(nn, 0.0, wi, tgam, KH, s);
+          launch_caxpy((int64_t)nn * nn, 0.0, 0.5 * wi, tGam, Kg, s);
+        }
+        launch_ci_lanczos(1, op->ci, op->Qdev, op->Qh.data(), mci, op->gint, kap, op->KC, -dt, 0.0, 0, s);
+        // lambda, h and dipole terms
+        launch_adj_terms(op->zmat, op->gam, g, n, ebar + k, sm, s);
+        launch_mix(B, Fc, XL1, 1.0, nu, s);             // nu += (M^-1 F(c)) Lbar^T
+        launch_mix(B, c, XL2, 0.0, t1, s);              // Y = c conj(Lbar)
+        launch_q_accum(B, t1, c, 1.0, 0.0, Q, s);
+        launch_mix(B, t1, XG, 0.0, t2, s);
+        g_apply(op, t2, va, 0, s);
+        launch_mix(B, va, XR, 1.0, nu, s);              // nu += M^-1 H_F^H Y
+        launch_mix(B, c, XH, 0.0, t1, s);
+        mass_h1(op, t1, va, s);
+        launch_axpby(len, 1.0, va, 1.0, nu, s);
+        launch_mix(B, c, XD, 0.0, t1, s);
+        mass_dipole(op, t1, va, s);
+        launch_axpby(len, 1.0, va, 1.0, nu, s);
+        // mean field: sensitivities of the pair potentials, gamma^-1 and Gamma
+        launch_zero(Kw, wlen, s);
+        launch_adj_mf(B, Q, W, c, op->ginv, op->Mr, Kg, op->colmap, Kw, Phib, s);
+        launch_qw_gram(B, Q, W, qwpart, G2, s);
+        launch_adj_mf_small(G2, op->Mr, op->ginv, op->colmap, n, sm, KGam, s);
+        // pair Poisson solves, reversed
+        launch_adj_poisson_rhs(B, Kw, ncol, op->P.r, op->P.sc, s);
+        launch_zero(Zb, wlen, s);
+        int it = 0;
+        const int rc = cg_solve_rhs(op, Zb, &it, s);
+        if (rc < 0) return rc;
+        if (rc == MH_NOT_CONVERGED) status = MH_NOT_CONVERGED;
+        launch_fill_real(B, Zb, 1, ncol, 1, nullptr, s);
+        launch_zero(tb, (int64_t)std::max<int64_t>(1, B.mx.Nb) * ncol, s);
+        launch_adj_bnd(B, Kw, Zb, ncol, op->P.nharm, tb, qlm, s);
+        launch_krho(B, Zb, qlm, op->P.lmax, ncol, op->colmap, c, Phib, s);
+        mass_load(op, Phib, va, s);
+        launch_axpby(len, 1.0, va, 1.0, nu, s);
+        // CI: the RDM sensitivities as an operator on C_k
+        launch_adj_ciprep(sm, KGam, n, th, tg2, s);
+        launch_ci_apply(1, op->ci, th, tg2, Cv, sig, s);
+        launch_axpby(clen, 1.0, sig, 1.0, kap, s);
       }
     }
-    std::vector<double> z((size_t)2 * n_steps * n_quad);
-    HIPCHK(hipMemcpyAsync(z.data(), zbuf, z.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> eb((size_t)n_steps + 1);
+    HIPCHK(hipMemcpyAsync(eb.data(), ebar, eb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (int k = 0; k < n_steps; ++k) {
-      double acc = 0.0;
-      for (int j = 0; j < n_quad; ++j) acc += gw[j] * z[2 * ((size_t)k * n_quad + j) + 1];
-      dJ_dE[k] = 2.0 * dt * acc;  // 2 Re[-i dt sum_j w_j a_j^H Z b_j]
-    }
-    return MH_OK;
+    const double E0 = op->dh[0].E0;
+    for (int k = 0; k < n_steps; ++k) dJ_dE[k] = E0 * eb[k];
+    return status;
   });
 }

@@ -67,6 +67,37 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return block_sum_all(s, lds4);
 }
 
+// Regular solid harmonics R_lm(x) of the multipole expansion, (lmax+1)^2 values:
+// index l*l + m holds the cos part, l*l + l + m (m > 0) the sin part.
+__device__ inline void solid_regular(double x, double y, double z, int lmax, double* R) {
+  // R_lm = r^l P_l^m e^{i m phi} (no Condon-Shortley phase), cos then sin parts
+  const double r2 = x * x + y * y + z * z;
+  double pre = 1.0, pim = 0.0, dfact = 1.0;
+  for (int m = 0; m <= lmax; ++m) {
+    if (m > 0) {
+      double t = pre * x - pim * y;
+      pim = pre * y + pim * x;
+      pre = t;
+      dfact *= (2.0 * m - 1.0);
+    }
+    double a_re = dfact * pre, a_im = dfact * pim, b_re = 0.0, b_im = 0.0;  // a = R_{l-1}, b = R_{l-2}
+    for (int l = m; l <= lmax; ++l) {
+      double re, im;
+      if (l == m) { re = a_re; im = a_im; }
+      else if (l == m + 1) {
+        re = (2.0 * m + 1.0) * z * a_re; im = (2.0 * m + 1.0) * z * a_im;
+        b_re = a_re; b_im = a_im; a_re = re; a_im = im;
+      } else {
+        re = ((2.0 * l - 1.0) * z * a_re - (l + m - 1.0) * r2 * b_re) / (l - m);
+        im = ((2.0 * l - 1.0) * z * a_im - (l + m - 1.0) * r2 * b_im) / (l - m);
+        b_re = a_re; b_im = a_im; a_re = re; a_im = im;
+      }
+      R[l * l + m] = re;
+      if (m > 0) R[l * l + l + m] = im;
+    }
+  }
+}
+
 static inline int nblocks(int64_t work, int per = NT, int cap = 1 << 20) {
   int64_t b = (work + per - 1) / per;
   if (b < 1) b = 1;

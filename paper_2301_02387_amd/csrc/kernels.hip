@@ -762,35 +762,6 @@ void launch_combine(const Batch& b, double* const* V, int m, double* phi, Krylov
 constexpr int MP_CH = 32;
 constexpr int MP_MAXH = 169;  // (lmax+1)^2 for lmax <= 12
 
-__device__ void solid_regular(double x, double y, double z, int lmax, double* R) {
-  // R_lm = r^l P_l^m e^{i m phi} (no Condon-Shortley phase), cos then sin parts
-  const double r2 = x * x + y * y + z * z;
-  double pre = 1.0, pim = 0.0, dfact = 1.0;
-  for (int m = 0; m <= lmax; ++m) {
-    if (m > 0) {
-      double t = pre * x - pim * y;
-      pim = pre * y + pim * x;
-      pre = t;
-      dfact *= (2.0 * m - 1.0);
-    }
-    double a_re = dfact * pre, a_im = dfact * pim, b_re = 0.0, b_im = 0.0;  // a = R_{l-1}, b = R_{l-2}
-    for (int l = m; l <= lmax; ++l) {
-      double re, im;
-      if (l == m) { re = a_re; im = a_im; }
-      else if (l == m + 1) {
-        re = (2.0 * m + 1.0) * z * a_re; im = (2.0 * m + 1.0) * z * a_im;
-        b_re = a_re; b_im = a_im; a_re = re; a_im = im;
-      } else {
-        re = ((2.0 * l - 1.0) * z * a_re - (l + m - 1.0) * r2 * b_re) / (l - m);
-        im = ((2.0 * l - 1.0) * z * a_im - (l + m - 1.0) * r2 * b_im) / (l - m);
-        b_re = a_re; b_im = a_im; a_re = re; a_im = im;
-      }
-      R[l * l + m] = re;
-      if (m > 0) R[l * l + l + m] = im;
-    }
-  }
-}
-
 __device__ __forceinline__ double pair_density(const double2* phi, int n, int64_t i, int r, int s, int part) {
   double2 a = phi[i * n + r], b = phi[i * n + s];
   // conj(a) b
@@ -1375,6 +1346,31 @@ static void launch_ci_sigma(int ni, const CIDev& c, const double* C, const doubl
   hipLaunchKernelGGL(k_ci_sigma, dim3(nblocks(c.dim), ni), dim3(NT), 0, s, c, (double2*)sigma);
 }
 
+// Transition RDMs <A|E_pq|B> and <A|E_pq E_rs|B> - delta_qr <A|E_ps|B> (the
+// RDMs above with different bra and ket), D tables in DA and DB.
+void launch_ci_trdm(int ni, const CIDev& c, const double* A, const double* Bv, double* DA, double* DB,
+                    double* gamma, double* Gamma, double* Gtmp, hipStream_t s) {
+  const int nn = c.n * c.n;
+  CIDev ca = c, cb = c;
+  ca.D = DA;
+  cb.D = DB;
+  launch_ci_D(ni, ca, A, s);
+  launch_ci_D(ni, cb, Bv, s);
+  int nb = gram_blocks(c.dim);
+  launch_xgram_flat(ni, A, 1, DB, nn, c.dim, c.part, nb, gamma, s);
+  launch_xgram_flat(ni, DA, nn, DB, nn, c.dim, c.part, nb, Gtmp, s);
+  hipLaunchKernelGGL(k_ci_gamma2, dim3(nblocks(nn * nn), ni), dim3(NT), 0, s, (const double2*)Gtmp,
+                     (const double2*)gamma, c.n, (double2*)Gamma);
+}
+
+// sigma = (sum h_pq E_pq + 1/2 sum g_pqrs (E_pq E_rs - delta_qr E_ps)) C for
+// general h and g; overwrites the shared h' of the CI space.
+void launch_ci_apply(int ni, const CIDev& c, const double* h, const double* g, const double* C, double* sigma,
+                     hipStream_t s) {
+  launch_ci_hprime(ni, c, h, g, s);
+  launch_ci_sigma(ni, c, C, g, sigma, s);
+}
+
 // One Lanczos/Arnoldi step on the CI space inside one workgroup: w is
 // orthogonalised twice against Q_0..Q_k (full re-orthogonalisation),
 // H column k filled, h_{k+1,k} = |w| (breakdown: scale 0, m_eff = k+1),
@@ -1461,7 +1457,8 @@ __global__ void __launch_bounds__(1024) k_ci_start(int dim, const double2* __res
   double t = 0.0;
   for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
   double beta = sqrt(t);
-  for (int i = threadIdx.x; i < dim; i += blockDim.x) Q0[i] = cscale(1.0 / beta, C[i]);
+  const double ib = beta > 0.0 ? 1.0 / beta : 0.0;  // a zero vector stays zero
+  for (int i = threadIdx.x; i < dim; i += blockDim.x) Q0[i] = cscale(ib, C[i]);
   for (int i = threadIdx.x; i < (m_max + 1) * m_max; i += blockDim.x) H[i] = make_double2(0.0, 0.0);
   if (threadIdx.x == 0) {
     scal[0] = beta;

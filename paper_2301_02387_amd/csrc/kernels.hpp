@@ -194,5 +194,9 @@ void launch_ci_rdm_full(int ni, const CIDev& c, const double* C, double* gamma, 
 void launch_ci_hprime(int ni, const CIDev& c, const double* h, const double* g, hipStream_t s);
 void launch_ci_lanczos(int ni, const CIDev& c, double* const* Qdev, double* const* Qhost, int m, const double* g,
                        double* Cvec, Krylov& K, double tau_re, double tau_im, int normalize, hipStream_t s);
+void launch_ci_trdm(int ni, const CIDev& c, const double* A, const double* Bv, double* DA, double* DB,
+                    double* gamma, double* Gamma, double* Gtmp, hipStream_t s);
+void launch_ci_apply(int ni, const CIDev& c, const double* h, const double* g, const double* C, double* sigma,
+                     hipStream_t s);
 
 }  // namespace mh

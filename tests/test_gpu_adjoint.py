@@ -1,8 +1,8 @@
-"""GPU checks of the hand-written adjoint (one orbital, one determinant):
-central finite differences of the propagated dipole objective along seeded
-directions, and reverse-mode autodiff of a dense torch-CPU re-expression of
-the oracle's discrete propagation (exact matrix exponentials of the oracle's
-M^-1 H1(E) on the same mesh)."""
+"""GPU checks of the hand-written adjoint of the dipole record: central
+finite differences of the propagated dipole objective along seeded
+directions, and reverse-mode autodiff of dense torch-CPU re-expressions of
+the oracle's discrete propagation (one orbital: exact matrix exponentials of
+M^-1 H1(E); several orbitals with mean field and CI: oracle/adjoint.py)."""
 import numpy as np
 import pytest
 import torch
@@ -108,3 +108,58 @@ def test_autograd_function_harmonic_objective():
         fd = (float(J_of(samples + eps * torch.from_numpy(delta)))
               - float(J_of(samples - eps * torch.from_numpy(delta)))) / (2 * eps)
     assert abs(fd - g @ delta) <= 1e-6 * max(abs(fd), 1e-3 * np.linalg.norm(g))
+
+
+def _mctdhf_setup(name, seed, steps, **kw):
+    from oracle.ci import CISpace
+    from oracle.mctdhf import orthonormalize
+    from synth import random_ci
+    P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000, **kw)
+    w, om, ops = P.w, P.om, P.ops
+    n = w["n_orb"]
+    cs = CISpace(n, w["n_alpha"], w["n_beta"])
+    c = orthonormalize(ops, random_orbitals(om.xyz[om.dof_nodes], n, seed, spread=1.2))
+    C = random_ci(cs.dim, seed + 1)
+    phi0 = torch.from_numpy(np.ascontiguousarray(P.to_lib_orb(c))).cuda()
+    C0 = torch.from_numpy(C).cuda()
+    E = 0.04 * np.cos(0.5 * np.arange(steps + 1)) + 0.01 * np.random.default_rng(seed).standard_normal(steps + 1)
+    return P, cs, c, C, phi0, C0, E
+
+
+@pytest.mark.parametrize("name,steps", [("tiny_q1", 5), ("small_n3", 3)])
+def test_mctdhf_adjoint_matches_oracle_autodiff(name, steps):
+    """Several orbitals, mean field, CI: the GPU adjoint against reverse-mode
+    autodiff of the oracle's propagation (same start, fields and dt)."""
+    from oracle.adjoint import dipole_gradient
+    P, cs, c, C, phi0, C0, E = _mctdhf_setup(name, 6, steps)
+    wts = np.random.default_rng(3).standard_normal(len(E))
+    d_ref, g_ref = dipole_gradient(P.ops, cs, c, C, E, DT, wts, m=12)
+    d = _dipoles(P, phi0, C0, E)
+    assert np.max(np.abs(d - d_ref)) <= 1e-9 * max(1.0, np.abs(d_ref).max()), (d, d_ref)
+    W = torch.zeros((P.op.n_full, P.op.n_pair_cols), dtype=torch.float64, device="cuda")
+    g = P.op.propagate_adjoint(phi0, C0, W, E, DT, wts, m=12, n_quad=8, ckpt_stride=2)
+    print(name, "gpu", g, "oracle", g_ref, flush=True)
+    assert np.max(np.abs(g - g_ref)) <= 1e-7 * np.abs(g_ref).max(), (g, g_ref)
+
+
+def test_mctdhf_adjoint_matches_central_differences():
+    """Q3 mesh, two orbitals and four determinants: the adjoint against
+    central differences of the GPU propagation along seeded directions."""
+    P, cs, c, C, phi0, C0, E = _mctdhf_setup("tiny_q3", 8, 6)
+    n = len(E)
+    rng = np.random.default_rng(11)
+    w, v = rng.standard_normal(n), rng.standard_normal(n)
+    d = _dipoles(P, phi0, C0, E)
+    W = torch.zeros((P.op.n_full, P.op.n_pair_cols), dtype=torch.float64, device="cuda")
+    grad = P.op.propagate_adjoint(phi0, C0, W, E, DT, w + 2 * v * d, m=12, n_quad=8, ckpt_stride=3)
+    eps = 1e-4
+    for k in range(4):
+        delta = rng.standard_normal(n)
+        delta[-1] = 0.0
+        delta /= np.linalg.norm(delta)
+        jp = _objective(_dipoles(P, phi0, C0, E + eps * delta), w, v)
+        jm = _objective(_dipoles(P, phi0, C0, E - eps * delta), w, v)
+        fd = (jp - jm) / (2 * eps)
+        ad = float(grad @ delta[:-1])
+        print("fd", fd, "adjoint", ad, flush=True)
+        assert abs(fd - ad) <= 1e-6 * max(abs(fd), 1e-3 * np.linalg.norm(grad)), (k, fd, ad)
