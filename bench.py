@@ -235,8 +235,8 @@ def main():
                      "schedule": sched_tag,
                      "algorithmic_bytes_per_launch": byts},
     }
-    if not args.no_adjoint:
-        line["fwd_adjoint_vs_plain"] = adjoint_ratio()
+    if not args.no_adjoint and args.workload == "h2":
+        line["fwd_adjoint_vs_plain"] = adjoint_ratio(op, phi, Ci, w)
     if not args.no_cpu_baseline and args.workload == "h2":
         line["cpu_baseline"] = cpu_baseline(args.workload, w, args.cpu_budget)
     print(json.dumps(line))
@@ -262,32 +262,29 @@ def measured_traffic(kernel, workload, profiles_dir=None, source=None, schedule=
     return None
 
 
-def adjoint_ratio(steps=40):
-    """Forward + checkpointed recomputation + adjoint against the plain forward
-    propagation, one-electron workload (H atom, Q2, 1 orbital)."""
+def adjoint_ratio(op, phi, Ci, w, steps=20, n_quad=6):
+    """Forward + checkpointed recomputation + adjoint against the plain
+    forward propagation on the differentiation workload's molecule and mesh
+    (H2, Q3, 2 orbitals, 4 determinants): a window of `steps` real-time steps
+    at the pulse peak, from the bench's current state."""
     import numpy as np
     import torch
-    import paper_2301_02387_amd as mh
-    from synth import initial_guess
-    w = _workload("h_atom")
-    mesh = mh.Mesh.from_workload(w)
-    op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"])
-    phi = torch.from_numpy(np.ascontiguousarray(initial_guess("h_atom", mesh.coords()[:op.n_ext]))).cuda()
-    op.fill_hanging(phi)
-    C = torch.ones(1, dtype=torch.complex128, device="cuda")
-    W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
-    op.propagate(phi, C, W, [0.0] * 3, 0.05, m=12, imaginary=True, final=False)
-    E = 0.02 * np.sin(0.3 * np.arange(steps + 1))
+    from synth import pulse
+    dt, m = w["dt"], w["krylov"]
+    Tp = w["cycles"] * 2 * np.pi / 0.0569542
+    E = pulse(Tp / 2 + dt * np.arange(steps + 1), w["E0"], w["cycles"])
     g = np.random.default_rng(5).standard_normal(steps + 1)
-    phi0 = phi.clone()
+    phi0, C0 = phi.clone(), Ci.clone()
+    W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
 
     def plain():
-        p = phi0.clone()
-        op.propagate(p, C.clone(), W, E, w["dt"], m=w["krylov"])
+        W.zero_()
+        op.propagate(phi0.clone(), C0.clone(), W, E, dt, m=m)
 
     def adjoint():
         plain()   # the forward pass that produced the dipoles
-        op.propagate_adjoint(phi0, C, W, E, w["dt"], g, m=w["krylov"], n_quad=6)
+        W.zero_()
+        op.propagate_adjoint(phi0, C0, W, E, dt, g, m=m, n_quad=n_quad)
 
     out = {}
     for name, fn in (("plain", plain), ("fwd_adjoint", adjoint)):
@@ -298,8 +295,9 @@ def adjoint_ratio(steps=40):
         torch.cuda.synchronize()
         out[name + "_ms"] = (time.perf_counter() - t) * 1e3
     out["ratio"] = out["fwd_adjoint_ms"] / out["plain_ms"]
-    out["workload"] = f"h_atom_q{w['p']}_{op.n_dof}dof_1orb, {steps} steps, 6-point Frechet quadrature, " \
-                      f"checkpoints every round(sqrt(N)) steps"
+    out["workload"] = (f"h2_q3_{op.n_dof}dof_2orb_4det (differentiation workload's molecule and mesh), "
+                       f"{steps}-step window at the pulse peak, {n_quad}-point Frechet quadrature, "
+                       f"checkpoints every round(sqrt(N)) steps")
     return out
 
 

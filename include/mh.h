@@ -121,7 +121,8 @@ typedef struct {
   double polarization[3];     /* unit field direction e (length gauge E(t) e.r) */
   int32_t lmax_bc;            /* multipole order of the Poisson boundary values (1..12;
                                  0 selects 12) */
-  double poisson_rtol;        /* relative residual target of the pair Poisson CG */
+  double poisson_rtol;        /* residual target of the pair Poisson CG: each column of an
+                                 instance to |r| <= rtol x the largest |rhs| of its columns */
   int32_t poisson_maxit;      /* CG iteration cap */
   double rdm_eps;             /* regularisation of the 1-RDM inverse */
 } mh_op_desc;

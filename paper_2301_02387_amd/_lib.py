@@ -341,8 +341,11 @@ class Operator:
         if len(g) != n_steps + 1:
             raise ValueError("dJ_dd must have one entry per dipole record")
         out = np.zeros(n_steps)
-        _check(_lib.mh_propagate_adjoint(self._h, _ptr(phi0), _ptr(Ci0), _ptr(W), E.ctypes.data_as(C.c_void_p),
-                                         n_steps, float(dt), int(m), g.ctypes.data_as(C.c_void_p),
-                                         out.ctypes.data_as(C.c_void_p), int(n_quad), int(ckpt_stride),
-                                         _stream(stream)))
+        rc = _check(_lib.mh_propagate_adjoint(self._h, _ptr(phi0), _ptr(Ci0), _ptr(W), E.ctypes.data_as(C.c_void_p),
+                                              n_steps, float(dt), int(m), g.ctypes.data_as(C.c_void_p),
+                                              out.ctypes.data_as(C.c_void_p), int(n_quad), int(ckpt_stride),
+                                              _stream(stream)), allow_nc=True)
+        if rc == MH_NOT_CONVERGED:
+            import warnings
+            warnings.warn("a Poisson solve of the adjoint stopped at the iteration cap")
         return out

@@ -657,6 +657,11 @@ static void poisson_begin(mh_op* op, const double* phi, double* W, int warm, hip
 
 // 1 when every column of every instance meets the residual target, -1 on a
 // non-finite residual, else 0 (reads the CG scalars after a stream sync).
+// The target is relative to the largest right-hand side of the instance's
+// columns, so a column whose right-hand side is rounding noise (the
+// imaginary part of a real pair density) is held to the same absolute
+// accuracy as the others; a warm start far from its solution could not reach
+// a target relative to the noise itself.
 static int poisson_converged(mh_op* op, hipStream_t s) {
   const int ncol = op->ncol, ni = op->ni;
   double* hs = op->hostpin;
@@ -666,14 +671,17 @@ static int poisson_converged(mh_op* op, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
   const int rr_slot = op->P.it > 0 ? red_rr_slot(op->P.it) : -1;
   int conv = 1;
-  for (int i = 0; i < ni; ++i)
+  for (int i = 0; i < ni; ++i) {
+    const double* sc = hs + (size_t)i * 8 * ncol;
+    const double* rd = hr + (size_t)i * RED_SLOTS * ncol;
+    double bb = 0.0;
+    for (int c = 0; c < ncol; ++c) bb = std::max(bb, sc[SC_BB * ncol + c]);
     for (int c = 0; c < ncol; ++c) {
-      const double* sc = hs + (size_t)i * 8 * ncol;
-      const double* rd = hr + (size_t)i * RED_SLOTS * ncol;
-      double rr = rr_slot >= 0 ? rd[rr_slot * ncol + c] : sc[SC_RR * ncol + c], bb = sc[SC_BB * ncol + c];
+      const double rr = rr_slot >= 0 ? rd[rr_slot * ncol + c] : sc[SC_RR * ncol + c];
       if (!std::isfinite(rr)) return -1;
       if (rr > op->rtol * op->rtol * bb) conv = 0;
     }
+  }
   return conv;
 }
 
@@ -1091,12 +1099,12 @@ struct DevScratch {
 }  // namespace
 
 // CG on the assembled Poisson operator for the right-hand side already in
-// P.r (with |rhs|^2 in the SC_BB scalars), cold start, solution in the DoF
-// rows of the full-row array Z.
+// P.r (with the convergence targets in the SC_BB scalars), started from the
+// DoF rows of the full-row array Z, which receive the solution.
 static int cg_solve_rhs(mh_op* op, double* Z, int* iters, hipStream_t s) {
   const Batch& B = op->B;
   PoissonWs& P = op->P;
-  launch_cg_start(B, Z, P.r, P, 0, s);
+  launch_cg_start(B, Z, P.r, P, 1, s);
   int it = 0, conv = 0;
   while (it < op->maxit) {
     const int todo = std::min(8, op->maxit - it);
@@ -1150,6 +1158,7 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
     double* DA = mem.get((size_t)2 * dim * nn), *DB = mem.get((size_t)2 * dim * nn);
     double* ebar = mem.get((size_t)n_steps + 1);
     launch_zero(ebar, n_steps + 1, s);
+    launch_zero(Zb, wlen, s);
     double* XG = sm + 2 * ADJ_XG * nn, *XR = sm + 2 * ADJ_XR * nn, *L2 = sm + 2 * ADJ_LAM2 * nn;
     double* XL1 = sm + 2 * ADJ_XL1 * nn, *XL2 = sm + 2 * ADJ_XL2 * nn, *XH = sm + 2 * ADJ_XH * nn;
     double* XD = sm + 2 * ADJ_XD * nn, *KH = sm + 2 * ADJ_KH * nn;
@@ -1291,8 +1300,7 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
         launch_adj_mf_small(G2, op->Mr, op->ginv, op->colmap, n, sm, KGam, s);
         // pair Poisson solves, reversed
         launch_adj_poisson_rhs(B, Kw, ncol, op->P.r, op->P.sc, s);
-        launch_zero(Zb, wlen, s);
-        int it = 0;
+        int it = 0;  // started from the previous step's solution (zero at the first)
         const int rc = cg_solve_rhs(op, Zb, &it, s);
         if (rc < 0) return rc;
         if (rc == MH_NOT_CONVERGED) status = MH_NOT_CONVERGED;

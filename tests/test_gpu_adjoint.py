@@ -163,3 +163,87 @@ def test_mctdhf_adjoint_matches_central_differences():
         ad = float(grad @ delta[:-1])
         print("fd", fd, "adjoint", ad, flush=True)
         assert abs(fd - ad) <= 1e-6 * max(abs(fd), 1e-3 * np.linalg.norm(grad)), (k, fd, ad)
+
+
+def _h2_start(P):
+    """sigma_g / sigma_u guess and the every-orbital-occupied CI start, made
+    M-orthonormal by the oracle (same start on both sides)."""
+    from oracle.mctdhf import orthonormalize
+    from synth import h2_guess, h2_ci_guess
+    om = P.om
+    c = orthonormalize(P.ops, h2_guess(om.xyz[om.dof_nodes], 0.7))
+    C = h2_ci_guess()
+    return c, C, torch.from_numpy(np.ascontiguousarray(P.to_lib_orb(c))).cuda(), torch.from_numpy(C).cuda()
+
+
+def test_h2_adjoint_on_h_atom_mesh_matches_oracle_autodiff():
+    """H2 (two orbitals, four determinants) on the H-atom workload's Q2 mesh
+    (4,007 DoF): the GPU adjoint against reverse-mode autodiff of the
+    oracle's propagation over a window of pulse steps."""
+    from oracle.adjoint import dipole_gradient
+    from oracle.ci import CISpace
+    from synth import pulse
+    P = Pair("h2_hmesh", poisson_rtol=1e-12, poisson_maxit=20000)
+    c, C, phi0, C0 = _h2_start(P)
+    cs = CISpace(2, 1, 1)
+    dt, steps = 0.02, 4
+    Tp = 4 * 2 * np.pi / 0.0569542
+    E = pulse(Tp / 2 + dt * np.arange(steps + 1), 0.0534, 4)
+    wts = np.random.default_rng(4).standard_normal(steps + 1)
+    d_ref, g_ref = dipole_gradient(P.ops, cs, c, C, E, dt, wts, m=12)
+    phi, Cd = phi0.clone(), C0.clone()
+    W = torch.zeros((P.op.n_full, P.op.n_pair_cols), dtype=torch.float64, device="cuda")
+    d = P.op.propagate(phi, Cd, W, E, dt, m=12)["dipole"]
+    # the field-induced dipole of the symmetric start is ~1e-7 (sums of O(1) terms)
+    assert np.max(np.abs(d - d_ref)) <= 1e-12, (d, d_ref)
+    W.zero_()
+    g = P.op.propagate_adjoint(phi0, C0, W, E, dt, wts, m=12, n_quad=8)
+    print("gpu", g, "oracle", g_ref, flush=True)
+    assert np.max(np.abs(g - g_ref)) <= 1e-7 * np.abs(g_ref).max(), (g, g_ref)
+
+
+def test_h2_differentiation_workload_central_differences():
+    """The differentiation workload on the full H2 mesh (66,635 DoF): the
+    field sampled at 4000 points on the pulse, piecewise linear between
+    them; a harmonic-band |FFT|^2 objective of the dipole record over a window
+    of steps at the pulse peak; dJ/d(samples) through the autograd Function
+    against central differences along 8 seeded unit directions in sample
+    space (default_rng(1)).  The step is 1e-3 in sample space (about 2e-5
+    per sample inside the window) so that the Poisson solves' tolerance
+    stays far below the difference quotient."""
+    import paper_2301_02387_amd as mh
+    from paper_2301_02387_amd.autodiff import dipole_history, harmonic_band_power, field_at_steps
+    from synth import workload, pulse, h2_guess, h2_ci_guess
+    w = workload("h2")
+    mesh = mh.Mesh.from_workload(w)
+    op = mh.Operator(mesh, w["nuclei"], 2, 1, 1, poisson_rtol=1e-12, poisson_maxit=20000)
+    phi = torch.from_numpy(np.ascontiguousarray(h2_guess(mesh.coords()[:op.n_ext], 0.7))).cuda()
+    op.fill_hanging(phi)
+    C0 = torch.from_numpy(h2_ci_guess()).cuda()
+    W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
+    op.propagate(phi, C0, W, [0.0] * 4, 0.05, m=12, imaginary=True, final=False)
+    dt, steps = w["dt"], 8
+    Tp = w["cycles"] * 2 * np.pi / 0.0569542
+    t_samp = np.linspace(0.0, Tp, 4000)
+    samples = torch.tensor(pulse(t_samp, w["E0"], w["cycles"]), dtype=torch.float64, requires_grad=True)
+    t_steps = Tp / 2 + dt * np.arange(steps + 1)
+    omega0 = 2 * np.pi / ((steps + 1) * dt)
+
+    def J_of(s):
+        d = dipole_history(field_at_steps(s, t_samp, t_steps), op, phi, C0, dt, m=12, n_quad=8)
+        return harmonic_band_power(d, dt, omega0, lo=1.0, hi=3.0)
+    J = J_of(samples)
+    J.backward()
+    g = samples.grad.numpy()
+    assert np.count_nonzero(g) > 0
+    rng = np.random.default_rng(1)
+    eps = 1e-3
+    for k in range(8):
+        delta = rng.standard_normal(4000)
+        delta /= np.linalg.norm(delta)
+        with torch.no_grad():
+            fd = (float(J_of(samples + eps * torch.from_numpy(delta)))
+                  - float(J_of(samples - eps * torch.from_numpy(delta)))) / (2 * eps)
+        ad = float(g @ delta)
+        print("fd", fd, "adjoint", ad, flush=True)
+        assert abs(fd - ad) <= 1e-6 * max(abs(fd), 1e-3 * np.linalg.norm(g)), (k, fd, ad)
