@@ -128,6 +128,8 @@ struct mh_op {
 };
 
 static inline hipStream_t S(void* s) { return (hipStream_t)s; }
+// largest interface block held as a dense inverse (doubles: MA_DENSE_MAX^2 x 8 B = 128 MiB)
+constexpr int64_t MA_DENSE_MAX = 4096;
 
 template <class F>
 static int guarded(F&& f) {
@@ -426,6 +428,21 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   B.tE = oE;
   B.tF = oF;
   B.tMa = oMa;
+  // one instance with a small interface block: its dense inverse (SPD,
+  // Gauss-Jordan on the device), so each interface solve is one matrix-vector
+  // pass instead of a chain of Chebyshev launches
+  if (ni == 1 && op->dh[0].nMa > 0 && op->dh[0].nMa <= MA_DENSE_MAX) {
+    const OpHost& H = op->Hs[0];
+    const int64_t nm = op->dh[0].nMa;
+    std::vector<double> A((size_t)(nm * nm), 0.0);
+    for (int64_t i = 0; i < nm; ++i)
+      for (int32_t t = H.ma_ptr[i]; t < H.ma_ptr[i + 1]; ++t) A[(size_t)(i * nm + H.ma_col[t])] += H.ma_val[t];
+    double* Ad = op->upload(A, s);
+    HIPCHK(hipStreamSynchronize(s));  // A is a host temporary
+    launch_dense_inverse(Ad, nm, s);
+    op->dh[0].ma_inv = Ad;
+    mx.ma_inv = Ad;
+  }
   op->dm = op->alloc<DevMesh>(ni);
   B.dm = op->dm;
   upload_instances(op.get(), s);
@@ -1035,7 +1052,7 @@ extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double
 }
 
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 15 : 1)) != 0)
+  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 15 : 3)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");

@@ -124,9 +124,94 @@ __global__ void __launch_bounds__(NT) k_cheb_finish(const DevMesh* __restrict__ 
   }
 }
 
+// Interface solve by the dense inverse (one instance): x = A^-1 b, one wave per
+// row, the lanes splitting the row's columns; then the final value of each
+// master DoF as in k_cheb_finish.
+__global__ void __launch_bounds__(NT) k_ma_dense(const DevMesh* __restrict__ dm, const double2* __restrict__ b,
+                                                 const double2* __restrict__ v, const double2* __restrict__ lam,
+                                                 double2* __restrict__ out) {
+  INSTANCE;
+  const int n = d.n;
+  const int64_t nMa = d.nMa, o = d.oMa * n, oe = d.oE * n;
+  const auto* Ai = gbl(d.ma_inv);
+  const int lane = threadIdx.x & 63;
+  const double2* L = lam ? lam + (int64_t)blockIdx.y * n * n : nullptr;
+  for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6; i < nMa; i += ((int64_t)gridDim.x * NT) >> 6) {
+    double sx[8], sy[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) { sx[p] = 0.0; sy[p] = 0.0; }
+    const auto* row = Ai + i * nMa;
+    for (int64_t j = lane; j < nMa; j += 64) {
+      const double a = row[j];
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < n) {
+          const double2 bj = ldg2(b, o + j * n + p);
+          sx[p] += a * bj.x;
+          sy[p] += a * bj.y;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p < n) {
+          sx[p] += __shfl_xor(sx[p], off, 64);
+          sy[p] += __shfl_xor(sy[p], off, 64);
+        }
+    if (lane < n) {
+      double2 xf = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        if (p == lane) xf = make_double2(sx[p], sy[p]);
+      const int64_t k = d.ma_dof[i];
+      if (L)
+        for (int q = 0; q < n; ++q) xf = csub(xf, cmul(L[q * n + lane], v[oe + k * n + q]));
+      out[oe + k * n + lane] = xf;
+    }
+  }
+}
+
+// Gauss-Jordan step k on a dense SPD matrix: entries off row and column k
+// (reading row and column k, which this launch does not write) ...
+__global__ void __launch_bounds__(NT) k_gj_update(double* __restrict__ A, int64_t n, int64_t k) {
+  const double inv = 1.0 / A[k * n + k];
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n * n; e += (int64_t)gridDim.x * NT) {
+    const int64_t i = e / n, j = e - i * n;
+    if (i == k || j == k) continue;
+    A[e] -= A[i * n + k] * A[k * n + j] * inv;
+  }
+}
+// ... then row and column k (reading the pivot, written by the next launch) ...
+__global__ void __launch_bounds__(NT) k_gj_rowcol(double* __restrict__ A, int64_t n, int64_t k) {
+  const double inv = 1.0 / A[k * n + k];
+  for (int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x; t < n; t += (int64_t)gridDim.x * NT) {
+    if (t == k) continue;
+    A[k * n + t] *= inv;
+    A[t * n + k] *= -inv;
+  }
+}
+// ... then the pivot itself.
+__global__ void k_gj_pivot(double* __restrict__ A, int64_t n, int64_t k) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) A[k * n + k] = 1.0 / A[k * n + k];
+}
+void launch_dense_inverse(double* A, int64_t n, hipStream_t s) {
+  const int g = nblocks(n * n, NT, 8192), g2 = nblocks(n, NT, 256);
+  for (int64_t k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_gj_update, dim3(g), dim3(NT), 0, s, A, n, k);
+    hipLaunchKernelGGL(k_gj_rowcol, dim3(g2), dim3(NT), 0, s, A, n, k);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(64), 0, s, A, n, k);
+  }
+}
+
 void launch_ma_solve(const Batch& b, const double* ma_b, double* x, double* r, double* dbuf0, double* dbuf1,
                      const double* v, const double* lam, double* out, hipStream_t s) {
   if (b.mx.nMa == 0) return;
+  if (b.ni == 1 && b.mx.ma_inv && !(b.mx.sched_orb & 2)) {
+    hipLaunchKernelGGL(k_ma_dense, dim3(nblocks(b.mx.nMa * 64, NT, 8192), 1), dim3(NT), 0, s, b.dm,
+                       (const double2*)ma_b, (const double2*)v, (const double2*)lam, (double2*)out);
+    return;
+  }
   const dim3 g(nblocks(b.mx.nMa * b.mx.n), b.ni);
   hipLaunchKernelGGL(k_cheb_init, g, dim3(NT), 0, s, b.dm, (const double2*)ma_b, (double2*)x, (double2*)r,
                      (double2*)dbuf0);

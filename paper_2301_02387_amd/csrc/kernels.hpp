@@ -39,6 +39,7 @@ struct DevMesh {
   const double* ma_val = nullptr;
   const double* ma_dinv = nullptr;
   const double* cheb = nullptr;         // 1/theta, then (c1, c2) per Chebyshev iteration
+  const double* ma_inv = nullptr;       // dense inverse of the interface block [nMa][nMa] (single small instances)
   const int32_t* ct_ptr = nullptr;      // per master: hanging rows it constrains
   const int32_t* ct_row = nullptr;
   const double* ct_w = nullptr;
@@ -56,7 +57,8 @@ struct DevMesh {
   double center[3] = {0.0, 0.0, 0.0};   // multipole expansion centre
   double E0 = 1.0;                      // field amplitude of this instance (E = E0 x the step's field value)
   double vnn = 0.0;                     // nuclear repulsion
-  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; Poisson bit 1 =
+  // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; orbital bit 1 = interface
+  // solve by Chebyshev even where a dense inverse is held; Poisson bit 1 =
   // column blocks of 16, bit 2 = long rows by whole waves, bit 3 = CG direction formed
   // inside the operator pass; grid caps (per instance)
   int sched_orb = 1, sched_poi = 13, grid_orb = 65536, grid_poi = 8192;
@@ -92,6 +94,8 @@ void launch_mass_direct(const Batch& b, const double* f, double* out, double* ma
 void launch_ma_solve(const Batch& b, const double* ma_b, double* x, double* r, double* dbuf0, double* dbuf1,
                      const double* v, const double* lam, double* out, hipStream_t s);
 void launch_fill_orb(const Batch& b, double* x, double* acc, hipStream_t s);
+// In-place Gauss-Jordan inverse of a dense SPD matrix [n][n] (no pivoting), 3 n launches.
+void launch_dense_inverse(double* A, int64_t n, hipStream_t s);
 void launch_copy(const double* in, double* out, int64_t nd, hipStream_t s);
 void launch_axpby(int64_t nd, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_zero(double* out, int64_t nd, hipStream_t s);

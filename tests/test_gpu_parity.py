@@ -170,8 +170,17 @@ def _frozen(P, c, C, E):
 
 @pytest.mark.parametrize("name", SMALL + ["h2"])
 def test_rhs_apply(name):
+    """G applied to a random packed vector, interface mass block solved both by
+    the dense inverse (the default for one small instance) and by Chebyshev."""
     torch = _torch()
     P = pair(name)
+    for orb_sched in (1, 3):
+        P.op.tune(0, orb_sched, 65536)
+        _rhs_apply_case(P, name, torch)
+    P.op.tune(0, 1, 65536)
+
+
+def _rhs_apply_case(P, name, torch):
     n = P.w["n_orb"]
     c = orbitals(P, 5)
     from oracle.ci import CISpace
