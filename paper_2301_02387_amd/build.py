@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmh.so")
-SOURCES = ["host_mesh.cpp", "host_setup.cpp", "kernels.hip", "stencil.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["host_mesh.cpp", "host_setup.cpp", "host_mg.cpp", "kernels.hip", "stencil.hip", "adjoint.hip", "mg.hip", "api.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-pthread", "--offload-arch=gfx950", "-munsafe-fp-atomics",
     # no packed FP32 instructions anywhere in the device code

@@ -17,6 +17,7 @@
 #include "host.hpp"
 #include "adjoint.hpp"
 #include "kernels.hpp"
+#include "mg.hpp"
 
 using namespace mh;
 
@@ -73,6 +74,11 @@ struct mh_op {
   double* Mr = nullptr;     // [ni][n^2][n^2]
   double* Gtmp = nullptr;   // [ni][n^2][n^2] c128
   int* flag = nullptr;      // [ni]
+  // multigrid preconditioner of the Poisson solves (built on first use)
+  std::unique_ptr<MgDev> mg;
+  double* mg_red = nullptr;   // scratch accumulators of the level-0 operator passes
+  double* mg_part = nullptr;  // r.z partials
+  int mg_levels = 0;
   bool frozen = false;
   // Krylov
   int m_alloc = 0;
@@ -702,10 +708,109 @@ static int poisson_converged(mh_op* op, hipStream_t s) {
   return conv;
 }
 
-static int poisson_solve(mh_op* op, const double* phi, double* W, int warm, int* iters, hipStream_t s) {
+// The multigrid hierarchy of instance 0 (Poisson schedule bit 4): host set-up
+// of the coarse spaces, their operators and transfers, then upload.  Level 0
+// reuses the operator's own assembled matrix and diagonal on the device.
+static void ensure_mg(mh_op* op, hipStream_t s) {
+  if (op->mg) return;
+  MgHost H;
+  build_multigrid(op->Ms[0], op->Hs[0], H);
+  auto mg = std::make_unique<MgDev>();
+  const int ncol = op->ncol;
+  const DevMesh& d0 = op->dh[0];
+  const int nl = (int)H.lv.size();
+  for (int l = 0; l < nl; ++l) {
+    const MgLevel& h = H.lv[l];
+    MgLevelDev L;
+    L.N = h.N;
+    if (l == 0) {
+      L.a_ptr = d0.kt_ptr;
+      L.a_col = d0.kt_col;
+      L.a_val = d0.kt_val;
+      L.dinv = d0.kdiag_inv;
+    } else {
+      L.a_ptr = op->upload(h.k_ptr, s);
+      L.a_col = op->upload(h.k_col, s);
+      L.a_val = op->upload(h.k_val, s);
+      L.dinv = op->upload(h.dinv, s);
+    }
+    L.lmax = h.lmax;
+    if (l + 1 < nl) {
+      L.p_ptr = op->upload(h.p_ptr, s);
+      L.p_col = op->upload(h.p_col, s);
+      L.p_val = op->upload(h.p_val, s);
+      L.r_ptr = op->upload(h.r_ptr, s);
+      L.r_col = op->upload(h.r_col, s);
+      L.r_val = op->upload(h.r_val, s);
+    }
+    const size_t len = (size_t)std::max<int64_t>(1, h.N) * ncol;
+    if (l > 0) L.r = op->alloc<double>(len);
+    L.z = op->alloc<double>(len);
+    L.d = op->alloc<double>(len);
+    L.t = op->alloc<double>(len);
+    mg->lv.push_back(L);
+  }
+  mg->cinv = op->upload(H.coarse_inv, s);
+  op->mg_red = op->alloc<double>((size_t)RED_SLOTS * ncol);
+  op->mg_part = op->alloc<double>((size_t)MG_RZ_BLOCKS * ncol);
+  HIPCHK(hipStreamSynchronize(s));  // the host tables are temporaries
+  op->mg_levels = nl;
+  op->mg = std::move(mg);
+}
+
+// CG preconditioned by one multigrid V-cycle per iteration, after
+// launch_cg_start (r_0 in P.r, accumulators initialised): z = B r, rz = r.z,
+// p = z + beta p, then the same operator and update passes as the Jacobi CG
+// (alpha = r.z / p.q).  Converged (1), not (0) or non-finite (-1); the check
+// runs after every iteration.
+static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
   const Batch& B = op->B;
   PoissonWs& P = op->P;
-  poisson_begin(op, phi, W, warm, s);
+  const MgDev& mg = *op->mg;
+  const int ncol = op->ncol;
+  const int64_t N = B.mx.N;
+  const MgSpmv spmv = [&](int lev, const double* x, double* y, hipStream_t st) {
+    if (lev == 0) launch_poisson_apply(B, x, y, ncol, op->mg_red, P, st);
+    else mg_level_spmv(mg.lv[lev], ncol, x, y, st);
+  };
+  double* z = mg.lv[0].z;
+  P.it = 0;
+  int conv = poisson_converged(op, s);
+  int k = 0;
+  if (conv == 0) {
+    mg_vcycle(mg, ncol, P.r, z, spmv, s);
+    mg_rz(N, ncol, P.r, z, op->mg_part, P.red, RED_RZ, s);
+    mg_dir(N, ncol, z, P.p2, P.p, P.red, RED_RZ, -1, RED_RR, s);
+  }
+  while (conv == 0 && k < op->maxit) {
+    double* pcur = (k % 2) ? P.p2 : P.p;
+    launch_cg_apply_plain(B, P, pcur, k, s);
+    launch_cg_update(B, W, P, pcur, k, s);
+    ++k;
+    P.it = k;
+    conv = poisson_converged(op, s);
+    if (conv != 0) break;
+    mg_vcycle(mg, ncol, P.r, z, spmv, s);
+    mg_rz(N, ncol, P.r, z, op->mg_part, P.red, RED_RZ + k % 3, s);
+    double* pnext = (k % 2) ? P.p2 : P.p;
+    double* pold = (k % 2) ? P.p : P.p2;
+    mg_dir(N, ncol, z, pold, pnext, P.red, RED_RZ + k % 3, RED_RZ + (k - 1) % 3, RED_RR + k % 2, s);
+  }
+  if (iters) *iters = k;
+  return conv;
+}
+
+// CG iterations after launch_cg_start, to the residual target or the cap:
+// multigrid-preconditioned (Poisson schedule bit 4, one instance), else
+// Jacobi launch by launch with a convergence check every 8 iterations.
+// 1 converged, 0 not, -1 non-finite residual.
+static int cg_iterate(mh_op* op, double* W, int* iters, hipStream_t s) {
+  const Batch& B = op->B;
+  PoissonWs& P = op->P;
+  if ((B.mx.sched_poi & 16) && op->ni == 1) {
+    ensure_mg(op, s);
+    return mg_pcg(op, W, iters, s);
+  }
   int it = 0, conv = 0;
   const int check = 8;
   while (it < op->maxit) {
@@ -713,11 +818,19 @@ static int poisson_solve(mh_op* op, const double* phi, double* W, int warm, int*
     for (int k = 0; k < todo; ++k) launch_cg_step(B, W, P, s);
     it += todo;
     conv = poisson_converged(op, s);
-    if (conv < 0) return fail(MH_NONFINITE, "non-finite Poisson residual");
-    if (conv) break;
+    if (conv != 0) break;
   }
-  launch_fill_real(B, W, 1, op->ncol, 1, P.acc, s);
   if (iters) *iters = it;
+  return conv;
+}
+
+static int poisson_solve(mh_op* op, const double* phi, double* W, int warm, int* iters, hipStream_t s) {
+  const Batch& B = op->B;
+  PoissonWs& P = op->P;
+  poisson_begin(op, phi, W, warm, s);
+  const int conv = cg_iterate(op, W, iters, s);
+  if (conv < 0) return fail(MH_NONFINITE, "non-finite Poisson residual");
+  launch_fill_real(B, W, 1, op->ncol, 1, P.acc, s);
   return conv ? MH_OK : MH_NOT_CONVERGED;
 }
 
@@ -1052,7 +1165,7 @@ extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double
 }
 
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 15 : 3)) != 0)
+  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 31 : 3)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");
@@ -1122,16 +1235,8 @@ static int cg_solve_rhs(mh_op* op, double* Z, int* iters, hipStream_t s) {
   const Batch& B = op->B;
   PoissonWs& P = op->P;
   launch_cg_start(B, Z, P.r, P, 1, s);
-  int it = 0, conv = 0;
-  while (it < op->maxit) {
-    const int todo = std::min(8, op->maxit - it);
-    for (int k = 0; k < todo; ++k) launch_cg_step(B, Z, P, s);
-    it += todo;
-    conv = poisson_converged(op, s);
-    if (conv < 0) return fail(MH_NONFINITE, "non-finite adjoint Poisson residual");
-    if (conv) break;
-  }
-  if (iters) *iters = it;
+  const int conv = cg_iterate(op, Z, iters, s);
+  if (conv < 0) return fail(MH_NONFINITE, "non-finite adjoint Poisson residual");
   return conv ? MH_OK : MH_NOT_CONVERGED;
 }
 

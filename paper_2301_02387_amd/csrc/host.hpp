@@ -101,7 +101,7 @@ struct MgHost {
   std::vector<MgLevel> lv;                 // lv[0] finest ... lv.back() coarsest
   std::vector<double> coarse_inv;          // dense inverse of the coarsest operator, row-major
 };
-void build_multigrid(const Mesh& fine, const OpHost& fop, MgHost& mg, int max_coarse = 1500);
+void build_multigrid(const Mesh& fine, const OpHost& fop, MgHost& mg, int max_coarse = 400);
 
 // Multipole harmonics shared by set-up and kernels: the order of the
 // (l, m, cos/sin) terms.  Term count for lmax: (lmax+1)^2.

@@ -60,7 +60,8 @@ struct DevMesh {
   // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; orbital bit 1 = interface
   // solve by Chebyshev even where a dense inverse is held; Poisson bit 1 =
   // column blocks of 16, bit 2 = long rows by whole waves, bit 3 = CG direction formed
-  // inside the operator pass; grid caps (per instance)
+  // inside the operator pass, bit 4 = geometric multigrid preconditioner (one
+  // instance); grid caps (per instance)
   int sched_orb = 1, sched_poi = 13, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights
@@ -173,6 +174,13 @@ void launch_poisson_rhs_full(const Batch& b, const double* phi, double* W, const
                              PoissonWs& P, hipStream_t s);
 void launch_cg_start(const Batch& b, double* W, double* rhs_r, PoissonWs& P, int warm, hipStream_t s);
 void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s);
+// Pieces of a CG iteration with another preconditioner: q = K p with p.q into
+// slot RED_PQ + k % 2, and the update pass (alpha_k = red[RED_RZ + k % 3] / p.q).
+void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k, hipStream_t s);
+void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s);
+// q = K x on the DoF rows with the tuned operator kernel, p.q partials into red_scratch
+void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch,
+                          const PoissonWs& P, hipStream_t s);
 // Hanging rows of a real column array (xfull: x is over full rows, else extended).
 void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s);
 

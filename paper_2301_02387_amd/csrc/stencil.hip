@@ -686,6 +686,25 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s) {
   P.it = k + 1;
 }
 
+// q = K x on the DoF rows (one instance or a batch), p.q partials into the
+// caller's scratch accumulators red_scratch ([ni][RED_SLOTS][ncol]).
+void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch,
+                          const PoissonWs& P, hipStream_t s) {
+  PoissonWs Ps = P;
+  Ps.red = red_scratch;
+  launch_spmv_poisson(b, x, x, q, ncol, q, Ps, -1, s);
+}
+
+// The plain operator pass of CG iteration k on the direction p (q = K p, p.q
+// accumulated for the update pass), and the update pass itself.
+void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k, hipStream_t s) {
+  cg_apply2(b, P, p, p, const_cast<double*>(p), P.q, -2 - k, s);
+}
+void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s) {
+  const int nb = cg_blocks(b, P.ncol);
+  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, p, P.q, P.ncol, P.red, k);
+}
+
 // y = a x + b y over nd doubles (a, b real)
 __global__ void __launch_bounds__(NT) k_axpby(int64_t nd, double a, const double* __restrict__ x, double b,
                                               double* __restrict__ y) {

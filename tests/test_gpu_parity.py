@@ -113,8 +113,8 @@ def test_poisson_pairs(name):
 @pytest.mark.parametrize("name", ["tiny_q3", "small_n3", "tiny_n8"])
 def test_poisson_every_schedule(name):
     """Each Poisson launch schedule (sweep order, column blocks, long rows by
-    waves, direction fused into the operator pass) gives the oracle's
-    potentials, cold and warm."""
+    waves, direction fused into the operator pass, multigrid preconditioner)
+    gives the oracle's potentials, cold and warm."""
     from oracle.poisson import PoissonSolver
     P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     n = P.w["n_orb"]
@@ -122,7 +122,7 @@ def test_poisson_every_schedule(name):
     ref = PoissonSolver(P.ops).pair_potentials(c)
     torch = _torch()
     x = dev(P.to_lib_orb(c))
-    for sched in (15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
+    for sched in (31, 29, 22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
         for grid in (8, 2048):
             P.op.tune(1, sched, grid)
             W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
@@ -215,13 +215,18 @@ def test_arnoldi_step(name, tau):
     assert abs(err - err_ref) <= 1e-6 * err_ref + 1e-14
 
 
-@pytest.mark.parametrize("name,steps,imag", [("h_atom", 4, False), ("tiny_q3", 4, False), ("small_n3", 3, False),
-                                             ("tiny_q3", 3, True)])
-def test_propagate_observables(name, steps, imag):
+@pytest.mark.parametrize("name,steps,imag,sched", [("h_atom", 4, False, 13), ("tiny_q3", 4, False, 13),
+                                                   ("small_n3", 3, False, 13), ("tiny_q3", 3, True, 13),
+                                                   ("tiny_q3", 4, False, 21), ("small_n3", 3, False, 20)])
+def test_propagate_observables(name, steps, imag, sched):
+    """Propagated dipoles, energies, orbitals and CI vectors against the
+    oracle, with the default Poisson schedule (13) and with the multigrid
+    preconditioner (20, 21)."""
     torch = _torch()
     from oracle.ci import CISpace
     from oracle.mctdhf import Propagator
     P = pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
+    P.op.tune(1, sched, 8192)
     n = P.w["n_orb"]
     cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
     c = orbitals(P, 10)
@@ -253,3 +258,30 @@ def test_poisson_not_converged_status():
     c = orbitals(P, 12)
     W, it, rc = _poisson(P, c)
     assert rc == 1 and it == 1
+
+
+@pytest.mark.parametrize("name", ["tiny_q3", "small_n3", "h2"])
+def test_multigrid_poisson(name):
+    """The multigrid-preconditioned CG gives the oracle's potentials in a few
+    tens of iterations, far fewer than the Jacobi-preconditioned one."""
+    torch = _torch()
+    from oracle.poisson import PoissonSolver
+    P = Pair(name, poisson_rtol=1e-12, poisson_maxit=20000)
+    n = P.w["n_orb"]
+    c = orbitals(P, 4)
+    ref = PoissonSolver(P.ops).pair_potentials(c)
+    x = dev(P.to_lib_orb(c))
+    its = {}
+    for sched in (13, 21):
+        P.op.tune(1, sched, 8192)
+        W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+        it, rc = P.op.poisson_pairs(x, W)
+        assert rc == 0
+        its[sched] = it
+        got = P.W_from_lib(host(W), n)
+        for k in ref:
+            num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref[k]) ** 2))
+            den = np.sqrt(np.sum(P.ops.m * np.abs(ref[k]) ** 2))
+            assert num / den < 1e-9, (sched, k, num / den)
+    print(name, "CG iterations jacobi / multigrid", its, flush=True)
+    assert its[21] <= 60 and its[21] * 4 < its[13], its
