@@ -158,6 +158,9 @@ def main():
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     dt, m = w["dt"], w["krylov"]
     Tp = (w["cycles"] * 2 * np.pi / 0.0569542) if w["cycles"] else 1.0
+    if args.tune_cache:   # schedules tuned by an earlier run on this workload, before the warm-up
+        from paper_2301_02387_amd.tune import apply_cached
+        apply_cached(op, args.tune_cache)
     # warm-up: imaginary-time relaxation steps, then one real-time step
     if args.warmup > 0:
         op.propagate(phi, Ci, W, [0.0] * (args.warmup + 1), 0.05, m=m, imaginary=True, final=False)

@@ -516,25 +516,33 @@ __global__ void k_build_Mreal(const double2* __restrict__ Gamma, int n, const in
   }
 }
 
+// Upk[i][o] = sum_c Mr[o][c] W[i][c]: G lanes per node (G = n^2 rounded up
+// to a power of two), lane o owning output o; the node's W row is read once,
+// coalesced, and broadcast by shuffles; Mr is held transposed in LDS so the
+// lanes of a group read consecutive words.
+template <int G>
 __global__ void __launch_bounds__(NT) k_build_U(const DevMesh* __restrict__ dm, const double* __restrict__ W,
                                                 const double* __restrict__ Mr, double* __restrict__ Upk) {
   INSTANCE;
-  __shared__ double sM[64 * 64];
+  __shared__ double sMT[64 * 64];
   const int nn = d.n * d.n;
   Mr += (int64_t)blockIdx.y * nn * nn;
   W += d.oF * nn;
   Upk += d.oE * nn;
-  for (int e = threadIdx.x; e < nn * nn; e += NT) sM[e] = Mr[e];
+  for (int e = threadIdx.x; e < nn * nn; e += NT) {
+    const int o = e / nn, c = e - o * nn;
+    sMT[c * nn + o] = Mr[e];
+  }
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < d.NE; i += (int64_t)gridDim.x * NT) {
-    const double* wr = W + i * nn;
-    double* ur = Upk + i * nn;
-    for (int o = 0; o < nn; ++o) {
-      double s = 0.0;
-      const double* mrow = sM + o * nn;
-      for (int c = 0; c < nn; ++c) s += mrow[c] * wr[c];
-      ur[o] = s;
+  const int o = (int)(threadIdx.x & (G - 1));
+  for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) / G; i < d.NE; i += ((int64_t)gridDim.x * NT) / G) {
+    const double w = o < nn ? W[i * nn + o] : 0.0;
+    double acc = 0.0;
+    for (int c = 0; c < nn; ++c) {
+      const double wc = __shfl(w, c, G);
+      if (o < nn) acc += sMT[c * nn + o] * wc;
     }
+    if (o < nn) Upk[i * nn + o] = acc;
   }
 }
 
@@ -543,7 +551,11 @@ void launch_build_U_full(const Batch& b, const double* W, const double* Gamma, c
   const int nn = b.mx.n * b.mx.n;
   hipLaunchKernelGGL(k_build_Mreal, dim3(nblocks(nn * nn), b.ni), dim3(NT), 0, s, (const double2*)Gamma, b.mx.n,
                      colmap, Mr);
-  hipLaunchKernelGGL(k_build_U, dim3(nblocks(b.mx.NE, NT, 4096), b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
+  const int g = nblocks(b.mx.NE * 64, NT, 8192);
+  if (nn <= 1) hipLaunchKernelGGL(k_build_U<1>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
+  else if (nn <= 4) hipLaunchKernelGGL(k_build_U<4>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
+  else if (nn <= 16) hipLaunchKernelGGL(k_build_U<16>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
+  else hipLaunchKernelGGL(k_build_U<64>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
 }
 
 // =====================================================================

@@ -179,8 +179,8 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s);
 void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k, hipStream_t s);
 void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s);
 // q = K x on the DoF rows with the tuned operator kernel, p.q partials into red_scratch
-void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch,
-                          const PoissonWs& P, hipStream_t s);
+void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch, PoissonWs& P,
+                          hipStream_t s);
 // Hanging rows of a real column array (xfull: x is over full rows, else extended).
 void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s);
 

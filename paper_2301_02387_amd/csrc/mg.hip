@@ -155,13 +155,20 @@ void mg_level_spmv(const MgLevelDev& L, int ncol, const double* x, double* y, hi
 // direction pass also clears the r.r slot the update pass of iteration k fills.
 __global__ void __launch_bounds__(NT) k_rz_parts(int64_t n, int ncol, const double* __restrict__ r,
                                                  const double* __restrict__ z, double* __restrict__ part) {
-  __shared__ double lds4[4];
-  for (int c = 0; c < ncol; ++c) {
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+  // ncol consecutive threads take one row (coalesced), NT / ncol rows per pass
+  __shared__ double lds[NT];
+  const int groups = NT / ncol;
+  const int g = threadIdx.x / ncol, c = threadIdx.x - g * ncol;
+  double acc = 0.0;
+  if (g < groups)
+    for (int64_t i = (int64_t)blockIdx.x * groups + g; i < n; i += (int64_t)gridDim.x * groups)
       acc += r[i * ncol + c] * z[i * ncol + c];
-    acc = block_sum_all(acc, lds4);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ncol + c] = acc;
+  lds[threadIdx.x] = g < groups ? acc : 0.0;
+  __syncthreads();
+  if (threadIdx.x < (unsigned)ncol) {
+    double t = 0.0;
+    for (int q = 0; q < groups; ++q) t += lds[q * ncol + threadIdx.x];
+    part[(int64_t)blockIdx.x * ncol + threadIdx.x] = t;
   }
 }
 __global__ void __launch_bounds__(NT) k_rz_finish(const double* __restrict__ part, int nblk, int ncol,

@@ -688,11 +688,17 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s) {
 
 // q = K x on the DoF rows (one instance or a batch), p.q partials into the
 // caller's scratch accumulators red_scratch ([ni][RED_SLOTS][ncol]).
-void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch,
-                          const PoissonWs& P, hipStream_t s) {
+void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch, PoissonWs& P,
+                          hipStream_t s) {
   PoissonWs Ps = P;
   Ps.red = red_scratch;
+  const bool rec = P.ev && P.ev_used + 2 <= P.ev_cap;  // timed like the CG's own operator passes
+  if (rec) (void)hipEventRecord(P.ev[P.ev_used], s);
   launch_spmv_poisson(b, x, x, q, ncol, q, Ps, -1, s);
+  if (rec) {
+    (void)hipEventRecord(P.ev[P.ev_used + 1], s);
+    P.ev_used += 2;
+  }
 }
 
 // The plain operator pass of CG iteration k on the direction p (q = K p, p.q
