@@ -307,14 +307,18 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * workgroups walk it side by side), 0 = plain grid-stride sweep.  Orbital
  * only, sched bit 1: solve the interface block of the mass matrix by the
  * Chebyshev iteration even where the operator holds its dense inverse (a
- * single instance with at most 4096 interface unknowns holds one).  Poisson
+ * single instance with at most 4096 interface unknowns holds one); bit 2:
+ * the stiffness part of the orbital operator by the assembled Poisson
+ * operator K~ applied to the 2n real columns of the orbitals (one sparse
+ * pass with the Poisson schedule's long-row and sweep options), the node pass
+ * adding only the diagonal and mean-field terms.  Poisson
  * only, sched bit 1: column blocking (16 columns per block on grid.z) when
  * the column count is a multiple of 16 and at least 32; bit 2: rows of the
  * assembled operator with more than 48
  * entries (hanging-node masters) taken by whole waves in reserved workgroups
  * of the same launch; bit 3: the CG direction formed inside the operator
  * pass (two launches per CG iteration instead of three; fewer launches, more
- * loads per entry).  Default sched 13.  Allowed values: 0 to 3 (orbital); any
+ * loads per entry).  Default sched 13.  Allowed values: 0 to 7 (orbital); any
  * combination of bits 0 to 3 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial

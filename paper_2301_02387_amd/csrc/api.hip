@@ -69,6 +69,8 @@ struct mh_op {
   double* ginv = nullptr;   // [ni][n][n] c128
   double* lam = nullptr;    // [ni][n][n] c128
   double* F = nullptr;      // [tE][n] c128
+  double* kq = nullptr;     // [tE][n] c128: assembled stiffness times the orbitals (orbital schedule bit 2)
+  double* kred = nullptr;   // [ni][RED_SLOTS][2n] scratch accumulators of that operator pass
   double* ma_b = nullptr, *ma_x = nullptr, *ma_r = nullptr, *ma_d0 = nullptr, *ma_d1 = nullptr;  // [tMa][n]
   double* gpart = nullptr;  // reduction partials
   double* Mr = nullptr;     // [ni][n^2][n^2]
@@ -472,6 +474,8 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   op->ginv = op->alloc<double>(ni * 2 * nn);
   op->lam = op->alloc<double>(ni * 2 * nn);
   op->F = op->alloc<double>(2 * tE * n);
+  op->kq = op->alloc<double>(2 * tE * n);
+  op->kred = op->alloc<double>((size_t)ni * RED_SLOTS * 2 * n);
   const size_t nma = std::max<size_t>(1, B.tMa);
   op->ma_b = op->alloc<double>(2 * nma * n);
   op->ma_x = op->alloc<double>(2 * nma * n);
@@ -645,7 +649,7 @@ static void stencil_orb(mh_op* op, const double* u, const double* Ef, int diag_m
                         hipStream_t s) {
   const bool rec = op->timing && op->ev_used[0] + 2 <= (int)op->ev[0].size();
   if (rec) HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0]], s));
-  launch_stencil_orb(op->B, u, Ef, diag_mode, op->Upk, op->ginv, mode, op->lam, out, op->acc, s);
+  launch_stencil_orb(op->B, u, Ef, diag_mode, op->Upk, op->ginv, mode, op->lam, out, op->acc, op->kq, op->kred, s);
   if (rec) {
     HIPCHK(hipEventRecord(op->ev[0][op->ev_used[0] + 1], s));
     op->ev_used[0] += 2;
@@ -1166,7 +1170,7 @@ extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double
 }
 
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 31 : 3)) != 0)
+  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 31 : 7)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");

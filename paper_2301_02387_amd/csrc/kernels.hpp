@@ -58,7 +58,8 @@ struct DevMesh {
   double E0 = 1.0;                      // field amplitude of this instance (E = E0 x the step's field value)
   double vnn = 0.0;                     // nuclear repulsion
   // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; orbital bit 1 = interface
-  // solve by Chebyshev even where a dense inverse is held; Poisson bit 1 =
+  // solve by Chebyshev even where a dense inverse is held, bit 2 = stiffness part by the
+  // assembled operator; Poisson bit 1 =
   // column blocks of 16, bit 2 = long rows by whole waves, bit 3 = CG direction formed
   // inside the operator pass, bit 4 = geometric multigrid preconditioner (one
   // instance); grid caps (per instance)
@@ -87,8 +88,10 @@ struct Batch {
 // 2: + mean field, 3: mz only.  mode 0: load vector F; 1: M^-1 F; 2: M^-1 F
 // - v lam.  Non-master DoFs are final in out; masters and hanging nodes go to
 // acc.  E is read from the device scalar *Ef (times each instance's E0).
+// Orbital schedule bit 2: the stiffness part by the assembled K~ (kq, kred scratch).
 void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
-                        const double* ginv, int mode, const double* lam, double* out, double* acc, hipStream_t s);
+                        const double* ginv, int mode, const double* lam, double* out, double* acc, double* kq,
+                        double* kred, hipStream_t s);
 // Masters: acc_k + sum_h c_hk acc_h -> out (mode 0) or the interface rhs ma_b.
 void launch_ma_gather_orb(const Batch& b, const double* acc, int mode, double* out, double* ma_b, hipStream_t s);
 void launch_mass_direct(const Batch& b, const double* f, double* out, double* ma_b, hipStream_t s);

@@ -36,12 +36,17 @@ namespace mh {
 // Non-master DoFs get their final value in `out`; masters and hanging nodes
 // store the load value in `acc`.
 // --------------------------------------------------------------------------
-template <int P, int L>
+// ASM: the stiffness part is taken from kq, the assembled K~ u on the DoF
+// rows (constraints folded in, so hanging rows carry no stiffness and the
+// masters already hold their hanging neighbours' share); the node then only
+// adds its diagonal and mean-field terms.
+template <int P, int L, bool ASM>
 __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ dm, const double2* __restrict__ u,
                                                     const double* __restrict__ Ef, int diag_mode,
                                                     const double* __restrict__ Upk, const double2* __restrict__ ginv,
                                                     int mode, const double2* __restrict__ lam,
-                                                    double2* __restrict__ out, double2* __restrict__ acc) {
+                                                    double2* __restrict__ out, double2* __restrict__ acc,
+                                                    const double2* __restrict__ kq) {
   INSTANCE;
   constexpr int P3 = P * P * P;
   const int n = d.n;
@@ -49,6 +54,7 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
   u += o;
   out += o;
   acc += o;
+  if (ASM) kq += o;
   Upk += d.oE * n * n;
   ginv += (int64_t)blockIdx.y * n * n;
   if (lam) lam += (int64_t)blockIdx.y * n * n;
@@ -63,7 +69,13 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
     // the node's 8 incidence codes in two 16-byte loads (row of 32 bytes)
     typedef int ivec4_t __attribute__((ext_vector_type(4)));
     const auto* inc4 = reinterpret_cast<const __attribute__((address_space(1))) ivec4_t*>(gbl(d.node_inc) + i * 8);
-    ivec4_t ca = inc4[0], cb = inc4[1];
+    ivec4_t ca = ivec4_t{-1, -1, -1, -1}, cb = ca;
+    if (!ASM) {
+      ca = inc4[0];
+      cb = inc4[1];
+    } else if (diag_mode != 3 && i < d.N && act) {
+      y = cscale(0.5, kq[i * n + p]);  // (1/2) K~ u
+    }
     if (diag_mode == 3) ca = cb = ivec4_t{-1, -1, -1, -1};  // dipole weights only: no stiffness
     const int codes[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
@@ -208,32 +220,54 @@ __global__ void __launch_bounds__(NT) k_mass_direct(const DevMesh* __restrict__ 
   }
 }
 
+static void launch_spmv_poisson(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
+                                double* q, const PoissonWs& P, int k, hipStream_t s);
+
 template <int P, int L>
 static void launch_stencil_orb_t(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
                                  const double* ginv, int mode, const double* lam, double* out, double* acc,
-                                 hipStream_t s) {
+                                 const double* kq, hipStream_t s) {
   const int grid = xcd_grid(b.mx.NE, NT / L, b.mx.grid_orb);
-  hipLaunchKernelGGL((k_stencil_orb<P, L>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u, Ef, diag_mode,
-                     Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out, (double2*)acc);
+  if (kq)
+    hipLaunchKernelGGL((k_stencil_orb<P, L, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u, Ef,
+                       diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out, (double2*)acc,
+                       (const double2*)kq);
+  else
+    hipLaunchKernelGGL((k_stencil_orb<P, L, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u, Ef,
+                       diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out, (double2*)acc,
+                       (const double2*)nullptr);
 }
 
 template <int P>
 static void launch_stencil_orb_p(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
                                  const double* ginv, int mode, const double* lam, double* out, double* acc,
-                                 hipStream_t s) {
+                                 const double* kq, hipStream_t s) {
   const int n = b.mx.n;
-  if (n <= 1) launch_stencil_orb_t<P, 1>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, s);
-  else if (n <= 2) launch_stencil_orb_t<P, 2>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, s);
-  else if (n <= 4) launch_stencil_orb_t<P, 4>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, s);
-  else launch_stencil_orb_t<P, 8>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, s);
+  if (n <= 1) launch_stencil_orb_t<P, 1>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, kq, s);
+  else if (n <= 2) launch_stencil_orb_t<P, 2>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, kq, s);
+  else if (n <= 4) launch_stencil_orb_t<P, 4>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, kq, s);
+  else launch_stencil_orb_t<P, 8>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, kq, s);
 }
 
+// Orbital schedule bit 2: the stiffness part by the assembled Poisson
+// operator K~ applied to the 2n real columns of the orbital array (the tuned
+// SpMV, long rows by waves), then the node pass adds the diagonal and
+// mean-field terms; kq [tE][n] and kred (RED_SLOTS x 2n per instance) are
+// scratch.
 void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
-                        const double* ginv, int mode, const double* lam, double* out, double* acc, hipStream_t s) {
+                        const double* ginv, int mode, const double* lam, double* out, double* acc, double* kq,
+                        double* kred, hipStream_t s) {
+  const bool asm_k = (b.mx.sched_orb & 4) && kq && kred;
+  if (asm_k && diag_mode != 3) {
+    PoissonWs Pk;
+    Pk.red = kred;
+    launch_spmv_poisson(b, u, u, kq, 2 * b.mx.n, kq, Pk, -1, s);
+  }
+  const double* q = asm_k ? kq : nullptr;
   switch (b.mx.P) {
-    case 2: launch_stencil_orb_p<2>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, s); break;
-    case 3: launch_stencil_orb_p<3>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, s); break;
-    default: launch_stencil_orb_p<4>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, s);
+    case 2: launch_stencil_orb_p<2>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, q, s); break;
+    case 3: launch_stencil_orb_p<3>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, q, s); break;
+    default: launch_stencil_orb_p<4>(b, u, Ef, diag_mode, Upk, ginv, mode, lam, out, acc, q, s);
   }
 }
 
@@ -469,11 +503,17 @@ static void launch_spmv_poisson(const Batch& b, const double* x, const double* p
                                 double* q, const PoissonWs& P, int k, hipStream_t s) {
   if ((b.mx.sched_poi & 2) && ncol >= 32 && ncol % 16 == 0)
     return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, 16, q, P, k, s);
-  if (ncol % 2 == 0) {  // 16-byte column pairs
-    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  if (ncol % 4 == 0 && ncol > 4) {  // 4 columns per lane (two 16-byte loads)
     if (ncol <= 16) return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
     if (ncol <= 32) return launch_spmv_t<8, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
     return launch_spmv_t<16, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  }
+  if (ncol % 2 == 0) {  // 16-byte column pairs
+    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    if (ncol <= 8) return launch_spmv_t<4, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    if (ncol <= 16) return launch_spmv_t<8, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    if (ncol <= 32) return launch_spmv_t<16, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    return launch_spmv_t<32, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
   }
   if (ncol <= 1) return launch_spmv_t<1, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
   if (ncol <= 2) return launch_spmv_t<2, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);

@@ -170,11 +170,12 @@ def _frozen(P, c, C, E):
 
 @pytest.mark.parametrize("name", SMALL + ["h2"])
 def test_rhs_apply(name):
-    """G applied to a random packed vector, interface mass block solved both by
-    the dense inverse (the default for one small instance) and by Chebyshev."""
+    """G applied to a random packed vector: interface mass block solved by the
+    dense inverse (the default for one small instance) and by Chebyshev, the
+    stiffness part node by node and by the assembled operator."""
     torch = _torch()
     P = pair(name)
-    for orb_sched in (1, 3):
+    for orb_sched in (1, 3, 5, 7):   # bit 1: Chebyshev interface solve, bit 2: assembled stiffness
         P.op.tune(0, orb_sched, 65536)
         _rhs_apply_case(P, name, torch)
     P.op.tune(0, 1, 65536)
@@ -220,13 +221,14 @@ def test_arnoldi_step(name, tau):
                                                    ("tiny_q3", 4, False, 21), ("small_n3", 3, False, 20)])
 def test_propagate_observables(name, steps, imag, sched):
     """Propagated dipoles, energies, orbitals and CI vectors against the
-    oracle, with the default Poisson schedule (13) and with the multigrid
-    preconditioner (20, 21)."""
+    oracle, with the default schedules (Poisson 13) and with the multigrid
+    preconditioner (Poisson 20, 21) and the assembled orbital stiffness."""
     torch = _torch()
     from oracle.ci import CISpace
     from oracle.mctdhf import Propagator
     P = pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     P.op.tune(1, sched, 8192)
+    P.op.tune(0, 1 if sched == 13 else 5, 65536)   # with multigrid: the assembled orbital stiffness too
     n = P.w["n_orb"]
     cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
     c = orbitals(P, 10)
