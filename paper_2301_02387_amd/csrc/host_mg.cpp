@@ -158,13 +158,17 @@ void build_multigrid(const Mesh& fine, const OpHost& fop, MgHost& mg, int max_co
     plan.push_back({nc, {}});
   }
   const double pol[3] = {0.0, 0.0, 1.0};
-  for (const auto& pl : plan) {
+  for (size_t pi = 0; pi < plan.size(); ++pi) {
+    const auto& pl = plan[pi];
     Mesh C;
     bool uns = false;
     std::string err = build_mesh(fine.lo, fine.hi, pl.first, 1, pl.second, C, uns);
     if (!err.empty()) throw std::runtime_error("multigrid coarse mesh: " + err);
     const Mesh& F = meshes.back();
     if (F.p == 1 && C.n_cells == F.n_cells && C.nc == F.nc) continue;  // same mesh as the level above
+    // a level that removes less than 40 % of the unknowns costs launches without
+    // coarsening much; skip it (the meshes are nested, so the next one still is)
+    if (pi + 1 < plan.size() && (double)C.N > 0.6 * (double)mg.lv.back().N) continue;
     if (C.N == 0) break;
     OpHost HC;
     build_operator(C, {}, pol, 0, HC);
