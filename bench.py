@@ -386,8 +386,10 @@ def run_batch(args):
     k_orb = op.kernel_timing(0, False)
     k_poi = op.kernel_timing(1, False)
     log(f"batched: {wall / args.steps * 1e3:.1f} ms per step")
-    # sequential baseline: each instance alone (plain operator, default schedule),
-    # from this batch's current state, `seq_steps` timed steps after one untimed step
+    # sequential baseline: each instance alone (plain operator, with the
+    # schedules tuned on the first instance alone), from this batch's current
+    # state, `seq_steps` timed steps after one untimed step
+    seq_sched = None
     seq_step_s = 0.0
     seq_iters = []
     ph_all = phi.clone()
@@ -404,6 +406,12 @@ def run_batch(args):
         W1 = torch.zeros((one.n_full, one.n_pair_cols), dtype=torch.float64, device="cuda")
         Ei = [w["E0"] * v for v in shape[:args.seq_steps + 2]]
         one.propagate(ph, C1, W1, Ei[:2], dt, m=m, final=False)
+        if seq_sched is None:
+            seq_sched = autotune(one, ph, W1)
+            log(f"sequential schedules (tuned on instance 0): {seq_sched['orbital']} {seq_sched['poisson']}")
+        else:
+            one.tune(0, *seq_sched["orbital"])
+            one.tune(1, *seq_sched["poisson"])
         torch.cuda.synchronize()
         ts = time.perf_counter()
         r1 = one.propagate(ph, C1, W1, Ei[1:args.seq_steps + 2], dt, m=m, final=False)
@@ -446,7 +454,9 @@ def run_batch(args):
         "batched_vs_sequential": (seq_step_s * 1e3 / ms_step) if not args.no_sequential else None,
         "sequential_ms_per_step": seq_step_s * 1e3,
         "sequential_sample": f"each of the {op.n_inst} instances alone, {args.seq_steps} timed step(s) after one "
-                             f"untimed step, default schedules",
+                             f"untimed step, schedules tuned on instance 0 alone",
+        "sequential_schedule": ({"orbital": list(seq_sched["orbital"]), "poisson": list(seq_sched["poisson"])}
+                                if seq_sched else None),
         "poisson_cg_iters_per_step": float(np.mean(rec["cg_iters"][:args.steps])),
         "sequential_cg_iters_per_step_mean": float(np.mean(seq_iters)) if seq_iters else None,
         "setup_s": t_setup,

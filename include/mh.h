@@ -319,8 +319,8 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * of the same launch; bit 3: the CG direction formed inside the operator
  * pass (two launches per CG iteration instead of three; fewer launches, more
  * loads per entry); bit 4: CG preconditioned by the geometric multigrid
- * V-cycle instead of the diagonal (one instance; the hierarchy is built on
- * first use).  Default sched 13.  Allowed values: 0 to 7 (orbital); any
+ * V-cycle instead of the diagonal (a hierarchy per instance, built on first
+ * use; the V-cycles of a batch run level by level in shared launches).  Default sched 13.  Allowed values: 0 to 7 (orbital); any
  * combination of bits 0 to 4 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial

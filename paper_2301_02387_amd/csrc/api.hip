@@ -712,79 +712,123 @@ static int poisson_converged(mh_op* op, hipStream_t s) {
   return conv;
 }
 
-// The multigrid hierarchy of instance 0 (Poisson schedule bit 4): host set-up
-// of the coarse spaces, their operators and transfers, then upload.  Level 0
-// reuses the operator's own assembled matrix and diagonal on the device.
+// The multigrid hierarchies of all instances (Poisson schedule bit 4): host
+// set-up of the coarse spaces, their operators and transfers (instances in
+// parallel), then upload and the per-level instance records.  Level 0 reuses
+// each instance's assembled matrix and diagonal on the device, and its
+// vectors live in batch arrays with the instances' extended-row offsets (the
+// right-hand side is the CG residual itself).
 static void ensure_mg(mh_op* op, hipStream_t s) {
   if (op->mg) return;
-  MgHost H;
-  build_multigrid(op->Ms[0], op->Hs[0], H);
-  auto mg = std::make_unique<MgDev>();
-  const int ncol = op->ncol;
-  const DevMesh& d0 = op->dh[0];
-  const int nl = (int)H.lv.size();
-  for (int l = 0; l < nl; ++l) {
-    const MgLevel& h = H.lv[l];
-    MgLevelDev L;
-    L.N = h.N;
-    if (l == 0) {
-      L.a_ptr = d0.kt_ptr;
-      L.a_col = d0.kt_col;
-      L.a_val = d0.kt_val;
-      L.dinv = d0.kdiag_inv;
-    } else {
-      L.a_ptr = op->upload(h.k_ptr, s);
-      L.a_col = op->upload(h.k_col, s);
-      L.a_val = op->upload(h.k_val, s);
-      L.dinv = op->upload(h.dinv, s);
-    }
-    L.lmax = h.lmax;
-    if (l + 1 < nl) {
-      L.p_ptr = op->upload(h.p_ptr, s);
-      L.p_col = op->upload(h.p_col, s);
-      L.p_val = op->upload(h.p_val, s);
-      L.r_ptr = op->upload(h.r_ptr, s);
-      L.r_col = op->upload(h.r_col, s);
-      L.r_val = op->upload(h.r_val, s);
-    }
-    const size_t len = (size_t)std::max<int64_t>(1, h.N) * ncol;
-    if (l > 0) L.r = op->alloc<double>(len);
-    L.z = op->alloc<double>(len);
-    L.d = op->alloc<double>(len);
-    L.t = op->alloc<double>(len);
-    mg->lv.push_back(L);
+  const int ni = op->ni, ncol = op->ncol;
+  std::vector<MgHost> H(ni);
+  {
+    const int nthr = std::max(1, std::min<int>(ni, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::vector<std::thread> pool;
+    std::vector<std::string> errs(nthr);
+    for (int t = 0; t < nthr; ++t)
+      pool.emplace_back([&, t]() {
+        try {
+          for (int i = t; i < ni; i += nthr) build_multigrid(op->Ms[i], op->Hs[i], H[i]);
+        } catch (const std::exception& e) {
+          errs[t] = e.what();
+        }
+      });
+    for (auto& th : pool) th.join();
+    for (auto& e : errs)
+      if (!e.empty()) throw std::runtime_error(e);
   }
-  mg->cinv = op->upload(H.coarse_inv, s);
-  op->mg_red = op->alloc<double>((size_t)RED_SLOTS * ncol);
-  op->mg_part = op->alloc<double>((size_t)MG_RZ_BLOCKS * ncol);
+  auto mg = std::make_unique<MgDev>();
+  int nlev = 0;
+  for (const MgHost& h : H) nlev = std::max(nlev, (int)h.lv.size());
+  if (nlev < 1 || nlev > 32) throw std::runtime_error("multigrid hierarchy depth out of range");
+  const size_t tlen = (size_t)op->B.tE * ncol;
+  mg->z0 = op->alloc<double>(tlen);
+  mg->t0 = op->alloc<double>(tlen);
+  double* d0 = op->alloc<double>(tlen);
+  HIPCHK(hipMemsetAsync(mg->z0, 0, tlen * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(mg->t0, 0, tlen * sizeof(double), s));
+  std::vector<std::vector<MgLevelDev>> rec(nlev, std::vector<MgLevelDev>(ni));
+  std::vector<MgLevelDev> co(ni);
+  for (int i = 0; i < ni; ++i) {
+    const DevMesh& dh = op->dh[i];
+    const int nl = (int)H[i].lv.size();
+    const size_t off = (size_t)dh.oE * ncol;
+    for (int l = 0; l < nl; ++l) {
+      const MgLevel& h = H[i].lv[l];
+      MgLevelDev& L = rec[l][i];
+      L.N = h.N;
+      L.active = l + 1 < nl;
+      L.coarse = l + 1 == nl;
+      if (l == 0) {
+        L.a_ptr = dh.kt_ptr;
+        L.a_col = dh.kt_col;
+        L.a_val = dh.kt_val;
+        L.dinv = dh.kdiag_inv;
+        L.r = op->P.r + off;
+        L.z = mg->z0 + off;
+        L.t = mg->t0 + off;
+        L.d = d0 + off;
+      } else {
+        L.a_ptr = op->upload(h.k_ptr, s);
+        L.a_col = op->upload(h.k_col, s);
+        L.a_val = op->upload(h.k_val, s);
+        L.dinv = op->upload(h.dinv, s);
+        const size_t len = (size_t)std::max<int64_t>(1, h.N) * ncol;
+        L.r = op->alloc<double>(len);
+        L.z = op->alloc<double>(len);
+        L.d = op->alloc<double>(len);
+        L.t = op->alloc<double>(len);
+      }
+      L.lmax = h.lmax;
+      if (L.active) {
+        L.p_ptr = op->upload(h.p_ptr, s);
+        L.p_col = op->upload(h.p_col, s);
+        L.p_val = op->upload(h.p_val, s);
+        L.r_ptr = op->upload(h.r_ptr, s);
+        L.r_col = op->upload(h.r_col, s);
+        L.r_val = op->upload(h.r_val, s);
+      } else {
+        L.cinv = op->upload(H[i].coarse_inv, s);
+        co[i] = L;
+        mg->max_coarse = std::max(mg->max_coarse, h.N);
+      }
+      mg->max_n[l] = std::max(mg->max_n[l], h.N);
+    }
+  }
+  mg->nlev = nlev;
+  for (int l = 0; l < nlev; ++l) mg->lv.push_back(op->upload(rec[l], s));
+  mg->coarse = op->upload(co, s);
+  op->mg_red = op->alloc<double>((size_t)ni * RED_SLOTS * ncol);
+  op->mg_part = op->alloc<double>((size_t)ni * MG_RZ_BLOCKS * ncol);
   HIPCHK(hipStreamSynchronize(s));  // the host tables are temporaries
-  op->mg_levels = nl;
+  op->mg_levels = nlev;
   op->mg = std::move(mg);
 }
 
-// CG preconditioned by one multigrid V-cycle per iteration, after
-// launch_cg_start (r_0 in P.r, accumulators initialised): z = B r, rz = r.z,
-// p = z + beta p, then the same operator and update passes as the Jacobi CG
-// (alpha = r.z / p.q).  Converged (1), not (0) or non-finite (-1); the check
-// runs after every iteration.
+// CG preconditioned by one multigrid V-cycle per instance and iteration,
+// after launch_cg_start (r_0 in P.r, accumulators initialised): z = B r,
+// rz = r.z, p = z + beta p, then the same operator and update passes as the
+// Jacobi CG (alpha = r.z / p.q), with every instance's own scalars.
+// Converged (1), not (0) or non-finite (-1); the check runs after every
+// iteration.
 static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
   const Batch& B = op->B;
   PoissonWs& P = op->P;
   const MgDev& mg = *op->mg;
-  const int ncol = op->ncol;
+  const int ncol = op->ncol, ni = op->ni;
   const int64_t N = B.mx.N;
-  const MgSpmv spmv = [&](int lev, const double* x, double* y, hipStream_t st) {
-    if (lev == 0) launch_poisson_apply(B, x, y, ncol, op->mg_red, P, st);
-    else mg_level_spmv(mg.lv[lev], ncol, x, y, st);
+  const MgSpmv0 spmv0 = [&](const double* x, double* y, hipStream_t st) {
+    launch_poisson_apply(B, x, y, ncol, op->mg_red, P, st);
   };
-  double* z = mg.lv[0].z;
+  double* z = mg.z0;
   P.it = 0;
   int conv = poisson_converged(op, s);
   int k = 0;
   if (conv == 0) {
-    mg_vcycle(mg, ncol, P.r, z, spmv, s);
-    mg_rz(N, ncol, P.r, z, op->mg_part, P.red, RED_RZ, s);
-    mg_dir(N, ncol, z, P.p2, P.p, P.red, RED_RZ, -1, RED_RR, s);
+    mg_vcycle(mg, ni, ncol, spmv0, s);
+    mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ, s);
+    mg_dir(B.dm, ni, N, ncol, z, P.p2, P.p, P.red, RED_RZ, -1, RED_RR, s);
   }
   while (conv == 0 && k < op->maxit) {
     double* pcur = (k % 2) ? P.p2 : P.p;
@@ -794,24 +838,24 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
     P.it = k;
     conv = poisson_converged(op, s);
     if (conv != 0) break;
-    mg_vcycle(mg, ncol, P.r, z, spmv, s);
-    mg_rz(N, ncol, P.r, z, op->mg_part, P.red, RED_RZ + k % 3, s);
+    mg_vcycle(mg, ni, ncol, spmv0, s);
+    mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ + k % 3, s);
     double* pnext = (k % 2) ? P.p2 : P.p;
     double* pold = (k % 2) ? P.p : P.p2;
-    mg_dir(N, ncol, z, pold, pnext, P.red, RED_RZ + k % 3, RED_RZ + (k - 1) % 3, RED_RR + k % 2, s);
+    mg_dir(B.dm, ni, N, ncol, z, pold, pnext, P.red, RED_RZ + k % 3, RED_RZ + (k - 1) % 3, RED_RR + k % 2, s);
   }
   if (iters) *iters = k;
   return conv;
 }
 
 // CG iterations after launch_cg_start, to the residual target or the cap:
-// multigrid-preconditioned (Poisson schedule bit 4, one instance), else
+// multigrid-preconditioned (Poisson schedule bit 4), else
 // Jacobi launch by launch with a convergence check every 8 iterations.
 // 1 converged, 0 not, -1 non-finite residual.
 static int cg_iterate(mh_op* op, double* W, int* iters, hipStream_t s) {
   const Batch& B = op->B;
   PoissonWs& P = op->P;
-  if ((B.mx.sched_poi & 16) && op->ni == 1) {
+  if (B.mx.sched_poi & 16) {
     ensure_mg(op, s);
     return mg_pcg(op, W, iters, s);
   }

@@ -61,8 +61,8 @@ struct DevMesh {
   // solve by Chebyshev even where a dense inverse is held, bit 2 = stiffness part by the
   // assembled operator; Poisson bit 1 =
   // column blocks of 16, bit 2 = long rows by whole waves, bit 3 = CG direction formed
-  // inside the operator pass, bit 4 = geometric multigrid preconditioner (one
-  // instance); grid caps (per instance)
+  // inside the operator pass, bit 4 = geometric multigrid preconditioner (a
+  // hierarchy per instance); grid caps (per instance)
   int sched_orb = 1, sched_poi = 13, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights

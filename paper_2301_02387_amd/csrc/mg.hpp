@@ -1,5 +1,7 @@
 // Geometric multigrid preconditioner of the pair Poisson solves (mg.hip):
-// device levels and the V-cycle.  One instance; real [rows][ncol] arrays.
+// per-instance hierarchies and the V-cycle over a whole batch.  Every pass over
+// a level covers all instances in one launch (instance blockIdx.y); real
+// [rows][ncol] arrays.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -13,8 +15,12 @@ namespace mh {
 constexpr double MG_RANGE = 8.0;
 constexpr int MG_RZ_BLOCKS = 256;
 
+// One level of one instance.  `active`: smoothing and transfers run on this
+// level (it is not the instance's coarsest); `coarse`: the level is the
+// instance's coarsest, solved with the dense inverse cinv.
 struct MgLevelDev {
   int64_t N = 0;                                                   // unknowns of the level
+  int active = 0, coarse = 0;
   const int32_t* a_ptr = nullptr; const int32_t* a_col = nullptr;   // operator (CSR)
   const double* a_val = nullptr;
   const double* dinv = nullptr;                                    // 1 / diagonal
@@ -23,27 +29,40 @@ struct MgLevelDev {
   const double* p_val = nullptr;
   const int32_t* r_ptr = nullptr; const int32_t* r_col = nullptr;   // restriction to level + 1 (its rows)
   const double* r_val = nullptr;
-  double* r = nullptr;   // right-hand side (levels >= 1) [N][ncol]
-  double* z = nullptr;   // correction (levels >= 1)
+  const double* cinv = nullptr;                                    // dense inverse (coarse levels)
+  double* r = nullptr;   // right-hand side [N][ncol] (level 0: the batch residual at this instance)
+  double* z = nullptr;   // correction
   double* d = nullptr;   // Chebyshev direction
   double* t = nullptr;   // operator product scratch
 };
-struct MgDev {
-  std::vector<MgLevelDev> lv;   // lv[0] = the operator's own DoF space
-  const double* cinv = nullptr; // dense inverse of the coarsest operator
-  int nu = 2;                   // smoothing steps before and after the coarse correction
-};
-// y = A_lev x (level 0 may use the tuned Poisson operator kernel)
-using MgSpmv = std::function<void(int lev, const double* x, double* y, hipStream_t s)>;
 
-// z0 = B r0 for one symmetric V-cycle B (Chebyshev pre- and post-smoothing)
-void mg_vcycle(const MgDev& mg, int ncol, const double* r0, double* z0, const MgSpmv& spmv, hipStream_t s);
-void mg_level_spmv(const MgLevelDev& L, int ncol, const double* x, double* y, hipStream_t s);
-// red[slot][c] = sum_i r[i][c] z[i][c] (part: MG_RZ_BLOCKS * ncol doubles)
-void mg_rz(int64_t n, int ncol, const double* r, const double* z, double* part, double* red, int slot, hipStream_t s);
-// pcur = z + beta pprev, beta = red[rz_cur] / red[rz_prev] per column (rz_prev < 0: beta = 0);
-// clears red[rr_clear]
-void mg_dir(int64_t n, int ncol, const double* z, const double* pprev, double* pcur, double* red, int rz_cur,
-            int rz_prev, int rr_clear, hipStream_t s);
+// The batch hierarchy: lv[l] = device array [ni] of level-l records (an
+// instance with fewer levels has inactive records there); coarse = device
+// array [ni] of each instance's coarsest level.  z0, t0: batch arrays of level
+// 0 (extended-row layout, instance offsets as every Poisson array).
+struct MgDev {
+  int nlev = 0;
+  std::vector<MgLevelDev*> lv;
+  MgLevelDev* coarse = nullptr;
+  int64_t max_n[32] = {};   // largest N of each level over the instances (grid shapes)
+  int64_t max_coarse = 0;
+  double* z0 = nullptr;
+  double* t0 = nullptr;
+  int nu = 2;               // smoothing steps before and after the coarse correction
+};
+// level-0 operator pass over the batch: y = A x (batch arrays)
+using MgSpmv0 = std::function<void(const double* x, double* y, hipStream_t s)>;
+
+// z0 = B r0 for one symmetric V-cycle per instance (r0: the batch residual)
+void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgSpmv0& spmv0, hipStream_t s);
+// red[i][slot][c] = sum over instance i's DoF rows of r[][c] z[][c] (part:
+// ni * MG_RZ_BLOCKS * ncol doubles); dm: the batch instance records
+struct DevMesh;
+void mg_rz(const DevMesh* dm, int ni, int ncol, const double* r, const double* z, double* part, double* red,
+           int slot, hipStream_t s);
+// pcur = z + beta pprev per instance and column, beta = red[rz_cur] / red[rz_prev]
+// (rz_prev < 0: beta = 0); clears red[rr_clear]
+void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const double* z, const double* pprev, double* pcur,
+            double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s);
 
 }  // namespace mh
