@@ -369,6 +369,9 @@ def run_batch(args):
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     dt, m, cycles = w0["dt"], w0["krylov"], w0["cycles"]
     Tp = cycles * 2 * np.pi / 0.0569542
+    if args.tune_cache:  # cached schedules already for the warm-up
+        from paper_2301_02387_amd.tune import apply_cached
+        log(f"schedules from the cache: {apply_cached(op, args.tune_cache)}")
     if args.warmup > 0:
         op.propagate(phi, Ci, W, [0.0] * (args.warmup + 1), 0.05, m=m, imaginary=True, final=False)
     t0 = Tp / 2

@@ -320,8 +320,13 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * pass (two launches per CG iteration instead of three; fewer launches, more
  * loads per entry); bit 4: CG preconditioned by the geometric multigrid
  * V-cycle instead of the diagonal (a hierarchy per instance, built on first
- * use; the V-cycles of a batch run level by level in shared launches).  Default sched 13.  Allowed values: 0 to 7 (orbital); any
- * combination of bits 0 to 4 (Poisson).
+ * use; the V-cycles of a batch run level by level in shared launches); bit 5:
+ * the rows of at most 48 entries read from a sliced-ELL copy of the operator
+ * (built when the bit is first set: rows sorted by length within windows of
+ * 4096, slices of 64 rows stored entry-major, so the lanes of a wave read
+ * consecutive words), the longer rows by whole waves as with bit 2.
+ * Default sched 13.  Allowed values: 0 to 7 (orbital); any combination of
+ * bits 0 to 5 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
  * sums change order only). */

@@ -1213,13 +1213,70 @@ extern "C" int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double
   });
 }
 
+// Sliced-ELL copy of the short rows of an instance's assembled Poisson
+// operator: within each window of SELL_WINDOW rows the short rows are sorted
+// by length (longest first, stable) and cut into slices of SELL_H slots; a
+// slice is as wide as its longest row, rounded up to a multiple of 4, and its
+// entries are stored slot-fastest so that the lanes of a wave, one row each,
+// read consecutive words.  Padding entries repeat the slot's own row as the
+// column (empty slots: row 0) with coefficient 0.
+static void build_sell(mh_op* op, int i, hipStream_t s) {
+  DevMesh& d = op->dh[i];
+  const OpHost& H = op->Hs[i];
+  const int64_t N = d.N;
+  std::vector<int32_t> ptr{0}, row, col;
+  std::vector<double> val;
+  std::vector<int32_t> win;
+  for (int64_t w0 = 0; w0 < N; w0 += SELL_WINDOW) {
+    win.clear();
+    const int64_t w1 = std::min<int64_t>(N, w0 + SELL_WINDOW);
+    for (int64_t r = w0; r < w1; ++r)
+      if (H.kt_ptr[r + 1] - H.kt_ptr[r] <= KT_LONG) win.push_back((int32_t)r);
+    std::stable_sort(win.begin(), win.end(), [&](int32_t a, int32_t b) {
+      return H.kt_ptr[a + 1] - H.kt_ptr[a] > H.kt_ptr[b + 1] - H.kt_ptr[b];
+    });
+    for (size_t a = 0; a < win.size(); a += SELL_H) {
+      const size_t nr = std::min<size_t>(SELL_H, win.size() - a);
+      int width = 0;
+      for (size_t q = 0; q < nr; ++q) width = std::max(width, H.kt_ptr[win[a + q] + 1] - H.kt_ptr[win[a + q]]);
+      width = (width + 3) / 4 * 4;
+      const size_t base = col.size();
+      if (base + (size_t)width * SELL_H >= (size_t)INT32_MAX) throw std::runtime_error("Poisson operator too large");
+      col.resize(base + (size_t)width * SELL_H);
+      val.resize(base + (size_t)width * SELL_H, 0.0);
+      for (int q = 0; q < SELL_H; ++q) {
+        const int32_t r = q < (int)nr ? win[a + q] : -1;
+        row.push_back(r);
+        const int beg = r >= 0 ? H.kt_ptr[r] : 0, len = r >= 0 ? H.kt_ptr[r + 1] - beg : 0;
+        for (int t = 0; t < width; ++t) {
+          const size_t e = base + (size_t)t * SELL_H + q;
+          col[e] = t < len ? H.kt_col[beg + t] : std::max<int32_t>(r, 0);
+          val[e] = t < len ? H.kt_val[beg + t] : 0.0;
+        }
+      }
+      ptr.push_back((int32_t)col.size());
+    }
+  }
+  d.sell_ptr = op->upload(ptr, s);
+  d.sell_row = op->upload(row, s);
+  d.sell_col = op->upload(col, s);
+  d.sell_val = op->upload(val, s);
+  d.n_slices = (int64_t)ptr.size() - 1;
+  HIPCHK(hipStreamSynchronize(s));  // the host tables are temporaries
+}
+
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 31 : 7)) != 0)
+  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 63 : 7)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");
   return guarded([&]() -> int {
     HIPCHK(hipDeviceSynchronize());
+    if (which == 1 && (sched & 32) && !op->dh[0].sell_ptr) {
+      for (int i = 0; i < op->ni; ++i) build_sell(op, i, nullptr);
+      op->B.mx.n_slices = 0;
+      for (const DevMesh& d : op->dh) op->B.mx.n_slices = std::max(op->B.mx.n_slices, d.n_slices);
+    }
     for (DevMesh& d : op->dh) {
       if (which == 0) {
         d.sched_orb = sched;

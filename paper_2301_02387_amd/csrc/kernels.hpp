@@ -51,6 +51,15 @@ struct DevMesh {
   const double* kt_val = nullptr;
   const int32_t* kt_long = nullptr;      // rows of the assembled operator with more than KT_LONG entries
   int64_t n_long = 0;
+  // sliced-ELL copy of the other rows (Poisson schedule bit 5, built on first use):
+  // slices of SELL_H row slots, rows sorted by length within windows of SELL_WINDOW;
+  // entry t of slot r of slice s at sell_ptr[s] + SELL_H t + r (widths are
+  // multiples of 4; padding entries hold coefficient 0 and a valid column)
+  const int32_t* sell_ptr = nullptr;    // [n_slices + 1]
+  const int32_t* sell_row = nullptr;    // [n_slices][SELL_H] row of each slot, -1 for none
+  const int32_t* sell_col = nullptr;
+  const double* sell_val = nullptr;
+  int64_t n_slices = 0;
   const int32_t* bnd_cells = nullptr;
   int64_t n_bnd_cells = 0;
   const double* bnd_table = nullptr;    // [Nb][nharm] multipole boundary table
@@ -62,7 +71,8 @@ struct DevMesh {
   // assembled operator; Poisson bit 1 =
   // column blocks of 16, bit 2 = long rows by whole waves, bit 3 = CG direction formed
   // inside the operator pass, bit 4 = geometric multigrid preconditioner (a
-  // hierarchy per instance); grid caps (per instance)
+  // hierarchy per instance), bit 5 = short rows from the sliced-ELL copy (long
+  // rows by waves); grid caps (per instance)
   int sched_orb = 1, sched_poi = 13, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights
@@ -71,6 +81,8 @@ struct DevMesh {
 // Rows of the assembled Poisson operator longer than this are handled by whole
 // workgroups (the masters of hanging nodes: tens to hundreds of entries).
 constexpr int KT_LONG = 48;
+constexpr int SELL_H = 64;
+constexpr int SELL_WINDOW = 4096;
 
 // A batch as seen by the launchers: the device array of instances, and a host
 // record with the shared parameters and the largest per-instance sizes (grid

@@ -38,29 +38,36 @@ __global__ void __launch_bounds__(NT) k_mg_spmv(const MgLevelDev* __restrict__ l
   }
 }
 
-// coarse.r = R (fine.r - fine.t) for each instance whose fine record is active
+// coarse.r = R (fine.r - fine.t) for each instance whose fine record is
+// active.  A restriction row gathers every fine node in the support of a
+// coarse basis function (up to 343 entries from Q3 to Q1), so one wave takes
+// a row: groups of cw lanes (a power of two >= ncol) split its entries, lane c
+// of a group holds column c, and the groups are combined by shuffles.
 __global__ void __launch_bounds__(NT) k_mg_restrict(const MgLevelDev* __restrict__ fine,
-                                                    const MgLevelDev* __restrict__ coarse, int ncol) {
+                                                    const MgLevelDev* __restrict__ coarse, int ncol, int cw) {
   const MgLevelDev& F = fine[blockIdx.y];
   if (!F.active) return;
   const MgLevelDev& C = coarse[blockIdx.y];
-  const int64_t total = C.N * ncol;
   const auto* ptr = gbl(F.r_ptr);
   const auto* col = gbl(F.r_col);
   const auto* val = gbl(F.r_val);
   const auto* r = gbl((const double*)F.r);
   const auto* t = gbl((const double*)F.t);
   auto* y = gblw(C.r);
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int64_t i = e / ncol;
-    const int c = (int)(e - i * ncol);
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / cw, c = lane - grp * cw, ngrp = 64 / cw;
+  const int64_t nrow = C.N;
+  for (int64_t w = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6; w < nrow; w += ((int64_t)gridDim.x * NT) >> 6) {
     double s = 0.0;
-    const int beg = ptr[i], end = ptr[i + 1];
-    for (int q = beg; q < end; ++q) {
-      const int64_t j = (int64_t)col[q] * ncol + c;
-      s += val[q] * (r[j] - t[j]);
+    if (c < ncol) {
+      const int beg = ptr[w], end = ptr[w + 1];
+      for (int q = beg + grp; q < end; q += ngrp) {
+        const int64_t j = (int64_t)col[q] * ncol + c;
+        s += val[q] * (r[j] - t[j]);
+      }
     }
-    y[e] = s;
+    for (int off = 32; off >= cw; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (grp == 0 && c < ncol) y[w * ncol + c] = s;
   }
 }
 
@@ -177,8 +184,10 @@ void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgSpmv0& spmv0, hipStrea
   for (int l = 0; l + 1 < nl; ++l) {
     smooth(mg, l, ni, ncol, true, spmv0, s);
     level_spmv(mg, l, ni, ncol, spmv0, s);
-    hipLaunchKernelGGL(k_mg_restrict, level_grid(mg.max_n[l + 1], ncol, ni), dim3(NT), 0, s, mg.lv[l], mg.lv[l + 1],
-                       ncol);
+    int cw = 1;
+    while (cw < ncol) cw *= 2;
+    hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(mg.max_n[l + 1] * 64, NT, 16384), ni), dim3(NT), 0, s, mg.lv[l],
+                       mg.lv[l + 1], ncol, cw);
   }
   hipLaunchKernelGGL(k_mg_coarse, dim3(nblocks(mg.max_coarse * ((ncol + 7) / 8) * 64, NT, 4096), ni), dim3(NT), 0, s,
                      mg.coarse, ncol);

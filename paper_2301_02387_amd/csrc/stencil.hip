@@ -387,8 +387,10 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict_
 }
 
 // Columns [col0, col0 + nc) of arrays with ld columns per row, col0 = blockIdx.z * nc
-// (nc = ld without column blocking).
-template <int L, int V, bool FUSE>
+// (nc = ld without column blocking).  SELL: the short rows come from the
+// sliced-ELL copy, a wave taking 64 / L slots of one slice (one width for all
+// its rows), so each round of entries is read as consecutive words.
+template <int L, int V, bool FUSE, bool SELL>
 __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
                                                      const double* __restrict__ pprev, double* __restrict__ pout,
                                                      int ld, int nc, double* __restrict__ q, int nlb,
@@ -435,6 +437,43 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
         for (int v = 0; v < V; ++v) y[v] += __shfl_xor(y[v], off, 64);
       if (seg == 0 && col_ok) spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq);
     }
+  } else if constexpr (SELL) {
+    constexpr int R = 64 / L;  // slots per wave
+    const int wave = threadIdx.x >> 6, slot_in = (threadIdx.x & 63) / L;
+    const XcdSweep sw =
+        xcd_sweep(d.n_slices * L, NT / 64, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
+    const auto* sptr = gbl(d.sell_ptr);
+    const auto* srow = gbl(d.sell_row);
+    const auto* scol = gbl(d.sell_col);
+    const auto* sval = gbl(d.sell_val);
+    const auto* xg = gbl(x);
+    const auto* pg = gbl(pprev);
+    const auto* dinv = gbl(d.kdiag_inv);
+    for (int64_t u = sw.start + wave; u < sw.end; u += sw.step) {
+      const int64_t sl = u / L;
+      const int slot = (int)(u - sl * L) * R + slot_in;
+      const int i = srow[sl * SELL_H + slot];
+      if (i < 0 || !col_ok) continue;
+      const int base = sptr[sl], width = (sptr[sl + 1] - base) / SELL_H;
+      double y[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) y[v] = 0.0;
+      for (int t = 0; t < width; t += 4) {
+        double av[4];
+        double xv[4][V];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int e = base + (t + h) * SELL_H + slot;
+          av[h] = sval[e];
+          operand_row<V, FUSE>(xg, pg, dinv, beta, (int64_t)scol[e], ld, c0, xv[h]);
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+          for (int v = 0; v < V; ++v) y[v] += av[h] * xv[h][v];
+      }
+      spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq);
+    }
   } else {
     const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
     for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
@@ -471,11 +510,11 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
   }
 }
 
-// Workgroups reserved for the long rows when schedule bit 2 is set: about
-// two rows per wave, a multiple of 8 (so the XCD of the sweeping workgroups is
-// unchanged).
+// Workgroups reserved for the long rows when schedule bit 2 or 5 is set:
+// about two rows per wave, a multiple of 8 (so the XCD of the sweeping
+// workgroups is unchanged).
 static int long_row_blocks(const Batch& b) {
-  if (b.mx.n_long == 0 || !(b.mx.sched_poi & 4)) return 0;
+  if (b.mx.n_long == 0 || !(b.mx.sched_poi & (4 | 32))) return 0;
   const int64_t nb = std::min<int64_t>((b.mx.n_long + 2 * (NT / 64) - 1) / (2 * (NT / 64)), 2048);
   return (int)((nb + N_XCD - 1) / N_XCD * N_XCD);
 }
@@ -484,12 +523,22 @@ template <int L, int V>
 static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, double* pout, int ld, int nc,
                           double* q, const PoissonWs& P, int k, hipStream_t s) {
   const int nlb = long_row_blocks(b);
+  if (b.mx.sched_poi & 32) {
+    const dim3 g(nlb + xcd_grid(b.mx.n_slices * L, NT / 64, b.mx.grid_poi), b.ni, ld / nc);
+    if (k >= 0)
+      hipLaunchKernelGGL((k_spmv_poisson<L, V, true, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
+                         P.red, k);
+    else
+      hipLaunchKernelGGL((k_spmv_poisson<L, V, false, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
+                         nlb, P.red, k);
+    return;
+  }
   const dim3 g(nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi), b.ni, ld / nc);
   if (k >= 0)
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb, P.red,
-                       k);
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, true, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
+                       P.red, k);
   else
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, false, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
                        P.red, k);
 }
 

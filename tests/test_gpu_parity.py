@@ -113,8 +113,8 @@ def test_poisson_pairs(name):
 @pytest.mark.parametrize("name", ["tiny_q3", "small_n3", "tiny_n8"])
 def test_poisson_every_schedule(name):
     """Each Poisson launch schedule (sweep order, column blocks, long rows by
-    waves, direction fused into the operator pass, multigrid preconditioner)
-    gives the oracle's potentials, cold and warm."""
+    waves, direction fused into the operator pass, multigrid preconditioner,
+    sliced-ELL short rows) gives the oracle's potentials, cold and warm."""
     from oracle.poisson import PoissonSolver
     P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     n = P.w["n_orb"]
@@ -122,7 +122,8 @@ def test_poisson_every_schedule(name):
     ref = PoissonSolver(P.ops).pair_potentials(c)
     torch = _torch()
     x = dev(P.to_lib_orb(c))
-    for sched in (31, 29, 22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
+    for sched in (63, 61, 53, 45, 44, 39, 37, 36, 33, 32, 31, 29, 22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2,
+                  1, 0):
         for grid in (8, 2048):
             P.op.tune(1, sched, grid)
             W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
@@ -172,12 +173,18 @@ def _frozen(P, c, C, E):
 def test_rhs_apply(name):
     """G applied to a random packed vector: interface mass block solved by the
     dense inverse (the default for one small instance) and by Chebyshev, the
-    stiffness part node by node and by the assembled operator."""
+    stiffness part node by node and by the assembled operator (from its CSR
+    rows and from its sliced-ELL copy)."""
     torch = _torch()
     P = pair(name)
     for orb_sched in (1, 3, 5, 7):   # bit 1: Chebyshev interface solve, bit 2: assembled stiffness
         P.op.tune(0, orb_sched, 65536)
         _rhs_apply_case(P, name, torch)
+    P.op.tune(1, 45, 8192)           # the assembled stiffness through the sliced-ELL rows
+    for orb_sched in (5, 4):
+        P.op.tune(0, orb_sched, 65536)
+        _rhs_apply_case(P, name, torch)
+    P.op.tune(1, 13, 8192)
     P.op.tune(0, 1, 65536)
 
 
