@@ -913,8 +913,11 @@ static void ensure_krylov(mh_op* op, int m) {
   for (int j = 0; j <= m; ++j) op->V.push_back(op->alloc<double>(len));
   op->Vdev = op->alloc<double*>(m + 1);
   HIPCHK(hipMemcpy(op->Vdev, op->V.data(), (m + 1) * sizeof(double*), hipMemcpyHostToDevice));
-  // enough workgroups to keep the memory system busy (the dot and update passes stream whole vectors)
-  int nblk = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (op->B.mx.NE * op->n + 255) / 256));
+  // enough workgroups to keep the memory system busy (the dot and update passes
+  // stream whole vectors), about 8192 over a batch (grid.y = instance)
+  int64_t nb = std::min<int64_t>(2048, std::max<int64_t>(1, (op->B.mx.NE * op->n + 255) / 256));
+  if (op->ni > 1) nb = std::min<int64_t>(nb, std::max<int64_t>(8, 8192 / op->ni));
+  const int nblk = (int)nb;
   krylov_alloc(op, op->K, m, nblk);
   op->m_alloc = m;
 }

@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(NT) k_mdot(const DevMesh* __restrict__ dm, con
                                              int k, const double2* __restrict__ w, int with_norm, int m_max,
                                              double* __restrict__ part) {
   INSTANCE;
-  __shared__ double lds[8];
+  __shared__ double lw[NT / 64][2 * KMAX + 1];
   const int n = d.n;
   const int64_t total = d.NE * n, o = d.oE * n;
   double hr[KMAX], hi[KMAX], nrm = 0.0;
@@ -592,52 +592,58 @@ __global__ void __launch_bounds__(NT) k_mdot(const DevMesh* __restrict__ dm, con
     }
     if (with_norm) nrm += we.x * w0.x + we.y * w0.y;
   }
+  // every value reduced over its wave by shuffles, then the four waves
+  // combined after one barrier
   const int nv = 2 * (k + 1) + 1;
   double* pb = part + blockIdx.y * kpart_stride(gridDim.x, m_max) + (int64_t)blockIdx.x * nv;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j <= k) {
-      double a = block_sum(hr[j], lds);
-      if (threadIdx.x == 0) pb[2 * j] = a;
-      double b = block_sum(hi[j], lds);
-      if (threadIdx.x == 0) pb[2 * j + 1] = b;
+      const double a = wave_sum(hr[j]), b = wave_sum(hi[j]);
+      if (lane == 0) {
+        lw[wid][2 * j] = a;
+        lw[wid][2 * j + 1] = b;
+      }
     }
   }
-  double c = block_sum(nrm, lds);
-  if (threadIdx.x == 0) pb[nv - 1] = c;
+  const double c = wave_sum(nrm);
+  if (lane == 0) lw[wid][nv - 1] = c;
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nv) pb[threadIdx.x] = lw[0][threadIdx.x] + lw[1][threadIdx.x] + lw[2][threadIdx.x] + lw[3][threadIdx.x];
 }
 
-// Finish the dots: pass 1 sets column k of H, pass 2 adds (re-orthogonalisation).
-__global__ void k_mdot_finish(const double* __restrict__ part, int nblk, int k, int m_max, int pass,
-                              double2* __restrict__ H, double2* __restrict__ hcur, double* __restrict__ scal) {
+// Finish the dots, one workgroup per value: pass 1 sets column k of H, pass 2
+// adds (re-orthogonalisation).
+__global__ void __launch_bounds__(NT) k_mdot_finish(const double* __restrict__ part, int nblk, int k, int m_max,
+                                                    int pass, double2* __restrict__ H, double2* __restrict__ hcur,
+                                                    double* __restrict__ scal) {
   __shared__ double lds4[4];
-  const int i = blockIdx.y;
+  const int i = blockIdx.y, v = blockIdx.x;
   part += i * kpart_stride(nblk, m_max);
   H += (int64_t)i * (m_max + 1) * m_max;
   hcur += (int64_t)i * (m_max + 1);
   scal += 8 * i;
   const int nv = 2 * (k + 1) + 1;
-  for (int v = 0; v < nv; ++v) {
-    const double s = sum_partials(part, nblk, nv, v, lds4);
-    if (threadIdx.x != 0) continue;
-    if (v == nv - 1) {
-      if (pass == 1) scal[2] = s;
-      continue;
-    }
-    int j = v >> 1;
-    double* hc = (double*)&hcur[j];
-    hc[v & 1] = s;
-    double* hp = (double*)&H[j + (int64_t)(m_max + 1) * k];
-    if (pass == 1) hp[v & 1] = s;
-    else hp[v & 1] += s;
+  const double s = sum_partials(part, nblk, nv, v, lds4);
+  if (threadIdx.x != 0) return;
+  if (v == nv - 1) {
+    if (pass == 1) scal[2] = s;
+    return;
   }
+  const int j = v >> 1;
+  double* hc = (double*)&hcur[j];
+  hc[v & 1] = s;
+  double* hp = (double*)&H[j + (int64_t)(m_max + 1) * k];
+  if (pass == 1) hp[v & 1] = s;
+  else hp[v & 1] += s;
 }
 
 void launch_mdot(const Batch& b, double* const* V, int k, const double* w, Krylov& K, int pass, hipStream_t s) {
   hipLaunchKernelGGL(k_mdot, dim3(K.nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2* const*)V, k,
                      (const double2*)w, pass == 1 ? 1 : 0, K.m_max, K.part);
-  hipLaunchKernelGGL(k_mdot_finish, dim3(1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, pass, (double2*)K.H,
-                     (double2*)K.hcur, K.scal);
+  hipLaunchKernelGGL(k_mdot_finish, dim3(2 * (k + 1) + 1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, pass,
+                     (double2*)K.H, (double2*)K.hcur, K.scal);
 }
 
 __global__ void __launch_bounds__(NT) k_orth_update(const DevMesh* __restrict__ dm,

@@ -18,6 +18,50 @@ namespace mh {
 
 #define INSTANCE const DevMesh& d = dm[blockIdx.y]
 
+// sum of val[t] (x[col[t] ncol + c] - xm[col[t] ncol + c]) (SUB; else x alone)
+// over t = beg, beg + stride, ... < end, for end > beg.  Rounds of 8 entries:
+// the indices and coefficients of the next round are requested before this
+// round's gathers, so each round waits for one memory latency.  Entries past
+// the end repeat the last one with coefficient 0 (in-bounds loads, no branch).
+template <bool SUB, class IP, class DP>
+__device__ __forceinline__ double row_gather_dot(IP col, DP val, int beg, int end, int stride, DP x, DP xm, int ncol,
+                                                 int c) {
+  double s = 0.0;
+  int jn[8];
+  double an[8];
+#pragma unroll
+  for (int h = 0; h < 8; ++h) {
+    const int tt = beg + h * stride;
+    const int tc = tt < end ? tt : end - 1;
+    jn[h] = col[tc];
+    an[h] = tt < end ? val[tc] : 0.0;
+  }
+  for (int t = beg; t < end; t += 8 * stride) {
+    int jc[8];
+    double ac[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      jc[h] = jn[h];
+      ac[h] = an[h];
+    }
+    if (t + 8 * stride < end) {
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int tt = t + (8 + h) * stride;
+        const int tc = tt < end ? tt : end - 1;
+        jn[h] = col[tc];
+        an[h] = tt < end ? val[tc] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int64_t j = (int64_t)jc[h] * ncol + c;
+      s += ac[h] * (SUB ? x[j] - xm[j] : x[j]);
+    }
+  }
+  return s;
+}
+
 // t = A z on each active record
 __global__ void __launch_bounds__(NT) k_mg_spmv(const MgLevelDev* __restrict__ lv, int ncol) {
   const MgLevelDev& L = lv[blockIdx.y];
@@ -31,10 +75,8 @@ __global__ void __launch_bounds__(NT) k_mg_spmv(const MgLevelDev* __restrict__ l
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int64_t i = e / ncol;
     const int c = (int)(e - i * ncol);
-    double s = 0.0;
     const int beg = ptr[i], end = ptr[i + 1];
-    for (int t = beg; t < end; ++t) s += val[t] * x[(int64_t)col[t] * ncol + c];
-    y[e] = s;
+    y[e] = end > beg ? row_gather_dot<false>(col, val, beg, end, 1, x, x, ncol, c) : 0.0;
   }
 }
 
@@ -60,11 +102,8 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(const MgLevelDev* __restrict
   for (int64_t w = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6; w < nrow; w += ((int64_t)gridDim.x * NT) >> 6) {
     double s = 0.0;
     if (c < ncol) {
-      const int beg = ptr[w], end = ptr[w + 1];
-      for (int q = beg + grp; q < end; q += ngrp) {
-        const int64_t j = (int64_t)col[q] * ncol + c;
-        s += val[q] * (r[j] - t[j]);
-      }
+      const int beg = ptr[w] + grp, end = ptr[w + 1];
+      if (end > beg) s = row_gather_dot<true>(col, val, beg, end, ngrp, r, t, ncol, c);
     }
     for (int off = 32; off >= cw; off >>= 1) s += __shfl_xor(s, off, 64);
     if (grp == 0 && c < ncol) y[w * ncol + c] = s;
@@ -86,10 +125,8 @@ __global__ void __launch_bounds__(NT) k_mg_prolong(const MgLevelDev* __restrict_
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int64_t i = e / ncol;
     const int c = (int)(e - i * ncol);
-    double s = 0.0;
     const int beg = ptr[i], end = ptr[i + 1];
-    for (int q = beg; q < end; ++q) s += val[q] * x[(int64_t)col[q] * ncol + c];
-    z[e] += s;
+    if (end > beg) z[e] += row_gather_dot<false>(col, val, beg, end, 1, x, x, ncol, c);
   }
 }
 
