@@ -714,13 +714,20 @@ static int poisson_converged(mh_op* op, hipStream_t s) {
 
 // The multigrid hierarchies of all instances (Poisson schedule bit 4): host
 // set-up of the coarse spaces, their operators and transfers (instances in
-// parallel), then upload and the per-level instance records.  Level 0 reuses
+// parallel), then upload, the dense inverses of the coarsest operators on the
+// device, and the per-level instance records.  Level 0 reuses
 // each instance's assembled matrix and diagonal on the device, and its
 // vectors live in batch arrays with the instances' extended-row offsets (the
 // right-hand side is the CG residual itself).
 static void ensure_mg(mh_op* op, hipStream_t s) {
   if (op->mg) return;
   const int ni = op->ni, ncol = op->ncol;
+  // The coarsest level is solved by its dense inverse.  One instance takes
+  // the first level with at most 2048 unknowns (one launch instead of the
+  // smoothing and transfers of further levels, which cost more in launch
+  // latency than the dense matrix costs in bytes); a batch stops at 400
+  // unknowns, where the dense matrices of all instances are read every cycle.
+  const int max_coarse = ni == 1 ? 2048 : 400;
   std::vector<MgHost> H(ni);
   {
     const int nthr = std::max(1, std::min<int>(ni, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
@@ -729,7 +736,7 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
     for (int t = 0; t < nthr; ++t)
       pool.emplace_back([&, t]() {
         try {
-          for (int i = t; i < ni; i += nthr) build_multigrid(op->Ms[i], op->Hs[i], H[i]);
+          for (int i = t; i < ni; i += nthr) build_multigrid(op->Ms[i], op->Hs[i], H[i], max_coarse);
         } catch (const std::exception& e) {
           errs[t] = e.what();
         }
@@ -789,7 +796,9 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
         L.r_col = op->upload(h.r_col, s);
         L.r_val = op->upload(h.r_val, s);
       } else {
-        L.cinv = op->upload(H[i].coarse_inv, s);
+        double* ci = op->upload(H[i].coarse_dense, s);
+        launch_dense_inverse(ci, h.N, s);  // Gauss-Jordan (the operator is SPD)
+        L.cinv = ci;
         co[i] = L;
         mg->max_coarse = std::max(mg->max_coarse, h.N);
       }

@@ -99,8 +99,10 @@ struct MgLevel {
 };
 struct MgHost {
   std::vector<MgLevel> lv;                 // lv[0] finest ... lv.back() coarsest
-  std::vector<double> coarse_inv;          // dense inverse of the coarsest operator, row-major
+  std::vector<double> coarse_dense;        // the coarsest operator, dense row-major
 };
+// Levels stop at the first with at most max_coarse unknowns (or at the
+// coarsest base grid of the plan).
 void build_multigrid(const Mesh& fine, const OpHost& fop, MgHost& mg, int max_coarse = 400);
 
 // Multipole harmonics shared by set-up and kernels: the order of the

@@ -177,41 +177,15 @@ void build_multigrid(const Mesh& fine, const OpHost& fop, MgHost& mg, int max_co
     take_operator(HC, C.N, LC);
     mg.lv.push_back(std::move(LC));
     meshes.push_back(std::move(C));
+    if (mg.lv.back().N <= max_coarse) break;  // small enough for the dense solve
   }
   for (MgLevel& L : mg.lv) L.lmax = 1.05 * lambda_max(L);
-  // dense inverse of the coarsest operator (Cholesky, then inverse from the factor)
+  // the coarsest operator as a dense row-major matrix (inverted on the device)
   const MgLevel& Lc = mg.lv.back();
   const int64_t n = Lc.N;
-  std::vector<double> A(n * n, 0.0);
+  mg.coarse_dense.assign(n * n, 0.0);
   for (int64_t i = 0; i < n; ++i)
-    for (int32_t t = Lc.k_ptr[i]; t < Lc.k_ptr[i + 1]; ++t) A[i * n + Lc.k_col[t]] = Lc.k_val[t];
-  for (int64_t j = 0; j < n; ++j) {  // A = L L^T in the lower triangle
-    double d = A[j * n + j];
-    for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
-    if (!(d > 0.0)) throw std::runtime_error("multigrid: coarsest operator not positive definite");
-    d = std::sqrt(d);
-    A[j * n + j] = d;
-    for (int64_t i = j + 1; i < n; ++i) {
-      double s = A[i * n + j];
-      for (int64_t k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
-      A[i * n + j] = s / d;
-    }
-  }
-  mg.coarse_inv.assign(n * n, 0.0);
-  std::vector<double> col(n);
-  for (int64_t c = 0; c < n; ++c) {  // solve L L^T x = e_c
-    for (int64_t i = 0; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int64_t k = 0; k < i; ++k) s -= A[i * n + k] * col[k];
-      col[i] = s / A[i * n + i];
-    }
-    for (int64_t i = n - 1; i >= 0; --i) {
-      double s = col[i];
-      for (int64_t k = i + 1; k < n; ++k) s -= A[k * n + i] * col[k];
-      col[i] = s / A[i * n + i];
-    }
-    for (int64_t i = 0; i < n; ++i) mg.coarse_inv[i * n + c] = col[i];
-  }
+    for (int32_t t = Lc.k_ptr[i]; t < Lc.k_ptr[i + 1]; ++t) mg.coarse_dense[i * n + Lc.k_col[t]] = Lc.k_val[t];
 }
 
 }  // namespace mh
