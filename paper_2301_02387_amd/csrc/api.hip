@@ -751,10 +751,26 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
   if (nlev < 1 || nlev > 32) throw std::runtime_error("multigrid hierarchy depth out of range");
   const size_t tlen = (size_t)op->B.tE * ncol;
   mg->z0 = op->alloc<double>(tlen);
+  mg->z0b = op->alloc<double>(tlen);
   mg->t0 = op->alloc<double>(tlen);
   double* d0 = op->alloc<double>(tlen);
+  mg->d0 = d0;
   HIPCHK(hipMemsetAsync(mg->z0, 0, tlen * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(mg->z0b, 0, tlen * sizeof(double), s));
   HIPCHK(hipMemsetAsync(mg->t0, 0, tlen * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(d0, 0, tlen * sizeof(double), s));
+  // level-0 Chebyshev coefficients of the fused smoothing passes: s0 = 1/theta
+  // (first step), then c1, c2 of the second step of the three-term recurrence
+  std::vector<double> coef((size_t)ni * 8, 0.0);
+  for (int i = 0; i < ni; ++i) {
+    const double b = H[i].lv[0].lmax, a = b / MG_RANGE;
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+    const double rho0 = 1.0 / sigma, rn = 1.0 / (2.0 * sigma - rho0);
+    coef[(size_t)i * 8 + 0] = 1.0 / theta;
+    coef[(size_t)i * 8 + 1] = rn * rho0;
+    coef[(size_t)i * 8 + 2] = 2.0 * rn / delta;
+  }
+  mg->coef0 = op->upload(coef, s);
   std::vector<std::vector<MgLevelDev>> rec(nlev, std::vector<MgLevelDev>(ni));
   std::vector<MgLevelDev> co(ni);
   for (int i = 0; i < ni; ++i) {
@@ -827,15 +843,20 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
   const MgDev& mg = *op->mg;
   const int ncol = op->ncol, ni = op->ni;
   const int64_t N = B.mx.N;
-  const MgSpmv0 spmv0 = [&](const double* x, double* y, hipStream_t st) {
+  MgLevel0Ops ops;
+  ops.spmv = [&](const double* x, double* y, hipStream_t st) {
     launch_poisson_apply(B, x, y, ncol, op->mg_red, P, st);
+  };
+  ops.cheb0 = [&](double* z, double* d, hipStream_t st) { launch_mg_cheb0(B, P.r, z, d, mg.coef0, ncol, st); };
+  ops.cheb = [&](const double* zin, double* zout, double* d, int k, hipStream_t st) {
+    launch_mg_cheb_step(B, zin, P.r, zout, d, mg.coef0, ncol, k, st);
   };
   double* z = mg.z0;
   P.it = 0;
   int conv = poisson_converged(op, s);
   int k = 0;
   if (conv == 0) {
-    mg_vcycle(mg, ni, ncol, spmv0, s);
+    mg_vcycle(mg, ni, ncol, ops, s);
     mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ, s);
     mg_dir(B.dm, ni, N, ncol, z, P.p2, P.p, P.red, RED_RZ, -1, RED_RR, s);
   }
@@ -847,7 +868,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
     P.it = k;
     conv = poisson_converged(op, s);
     if (conv != 0) break;
-    mg_vcycle(mg, ni, ncol, spmv0, s);
+    mg_vcycle(mg, ni, ncol, ops, s);
     mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ + k % 3, s);
     double* pnext = (k % 2) ? P.p2 : P.p;
     double* pold = (k % 2) ? P.p : P.p2;

@@ -1150,77 +1150,93 @@ void launch_poisson_rhs_full(const Batch& b, const double* phi, double* W, const
 // =====================================================================
 // Regularised inverse of the Hermitian 1-RDM: eigen-decomposition of the
 // real 2n x 2n embedding [[Re, -Im], [Im, Re]] by cyclic Jacobi, d -> d +
-// eps exp(-d/eps), inverse from the eigenpairs.
-__global__ void k_ginv(const double2* __restrict__ gamma, int n, double eps, double2* __restrict__ ginv,
-                       int* __restrict__ flag) {
-  if (threadIdx.x != 0) return;
-  const int inst = blockIdx.x;
+// eps exp(-d/eps), inverse from the eigenpairs.  One wave per instance with
+// the matrices in LDS: the rotations are applied in order, the lanes taking
+// the row (or column) index of each one's updates.
+__device__ __forceinline__ double wave_sum_xor(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);  // every lane gets the same total
+  return v;
+}
+__global__ void __launch_bounds__(64) k_ginv(const double2* __restrict__ gamma, int n, double eps,
+                                             double2* __restrict__ ginv, int* __restrict__ flag) {
+  __shared__ double a[16 * 16], V[16 * 16], dinv[16];
+  __shared__ int badk[16];
+  const int inst = blockIdx.x, lane = threadIdx.x;
   gamma += (int64_t)inst * n * n;
   ginv += (int64_t)inst * n * n;
   const int N2 = 2 * n;
-  double a[16 * 16], V[16 * 16];
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      // Hermitian part
-      double re = 0.5 * (gamma[i * n + j].x + gamma[j * n + i].x);
-      double im = 0.5 * (gamma[i * n + j].y - gamma[j * n + i].y);
-      a[i * N2 + j] = re;
-      a[(i + n) * N2 + (j + n)] = re;
-      a[i * N2 + (j + n)] = -im;
-      a[(i + n) * N2 + j] = im;
-    }
-  for (int i = 0; i < N2; ++i)
-    for (int j = 0; j < N2; ++j) V[i * N2 + j] = (i == j) ? 1.0 : 0.0;
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, j = e - i * n;
+    // Hermitian part
+    const double re = 0.5 * (gamma[i * n + j].x + gamma[j * n + i].x);
+    const double im = 0.5 * (gamma[i * n + j].y - gamma[j * n + i].y);
+    a[i * N2 + j] = re;
+    a[(i + n) * N2 + (j + n)] = re;
+    a[i * N2 + (j + n)] = -im;
+    a[(i + n) * N2 + j] = im;
+  }
+  for (int e = lane; e < N2 * N2; e += 64) V[e] = (e / N2 == e % N2) ? 1.0 : 0.0;
+  __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int i = 0; i < N2; ++i)
-      for (int j = 0; j < N2; ++j) {
-        tot += a[i * N2 + j] * a[i * N2 + j];
-        if (i != j) off += a[i * N2 + j] * a[i * N2 + j];
-      }
+    for (int e = lane; e < N2 * N2; e += 64) {
+      const double v = a[e];
+      tot += v * v;
+      if (e / N2 != e % N2) off += v * v;
+    }
+    off = wave_sum_xor(off);
+    tot = wave_sum_xor(tot);
     if (off <= 1e-32 * tot) break;
     for (int p = 0; p < N2; ++p)
       for (int q = p + 1; q < N2; ++q) {
-        double apq = a[p * N2 + q];
+        const double apq = a[p * N2 + q];
         if (fabs(apq) < 1e-300) continue;
-        double theta = (a[q * N2 + q] - a[p * N2 + p]) / (2.0 * apq);
-        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < N2; ++k) {
-          double akp = a[k * N2 + p], akq = a[k * N2 + q];
-          a[k * N2 + p] = c * akp - s * akq;
-          a[k * N2 + q] = s * akp + c * akq;
+        const double theta = (a[q * N2 + q] - a[p * N2 + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        __syncthreads();  // every lane has read the pivot entries
+        if (lane < N2) {  // columns p, q of a
+          const int k = lane;
+          const double akp = a[k * N2 + p], akq = a[k * N2 + q];
+          a[k * N2 + p] = c * akp - sn * akq;
+          a[k * N2 + q] = sn * akp + c * akq;
+        } else if (lane >= 32 && lane < 32 + N2) {  // columns p, q of V
+          const int k = lane - 32;
+          const double vkp = V[k * N2 + p], vkq = V[k * N2 + q];
+          V[k * N2 + p] = c * vkp - sn * vkq;
+          V[k * N2 + q] = sn * vkp + c * vkq;
         }
-        for (int k = 0; k < N2; ++k) {
-          double apk = a[p * N2 + k], aqk = a[q * N2 + k];
-          a[p * N2 + k] = c * apk - s * aqk;
-          a[q * N2 + k] = s * apk + c * aqk;
+        __syncthreads();
+        if (lane < N2) {  // rows p, q of a
+          const int k = lane;
+          const double apk = a[p * N2 + k], aqk = a[q * N2 + k];
+          a[p * N2 + k] = c * apk - sn * aqk;
+          a[q * N2 + k] = sn * apk + c * aqk;
         }
-        for (int k = 0; k < N2; ++k) {
-          double vkp = V[k * N2 + p], vkq = V[k * N2 + q];
-          V[k * N2 + p] = c * vkp - s * vkq;
-          V[k * N2 + q] = s * vkp + c * vkq;
-        }
+        __syncthreads();
       }
   }
-  int bad = 0;
-  double dinv[16];
-  for (int k = 0; k < N2; ++k) {
-    double dk = a[k * N2 + k];
-    double dr = dk + eps * exp(-dk / eps);
-    if (!(dr > 0.0) || !isfinite(dr)) bad = 1;
-    dinv[k] = 1.0 / dr;
+  if (lane < N2) {
+    const double dk = a[lane * N2 + lane];
+    const double dr = dk + eps * exp(-dk / eps);
+    badk[lane] = (!(dr > 0.0) || !isfinite(dr)) ? 1 : 0;
+    dinv[lane] = 1.0 / dr;
   }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double re = 0.0, im = 0.0;
-      for (int k = 0; k < N2; ++k) {
-        re += V[i * N2 + k] * dinv[k] * V[j * N2 + k];
-        im += V[(i + n) * N2 + k] * dinv[k] * V[j * N2 + k];
-      }
-      ginv[i * n + j] = make_double2(re, im);
+  __syncthreads();
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, j = e - i * n;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < N2; ++k) {
+      re += V[i * N2 + k] * dinv[k] * V[j * N2 + k];
+      im += V[(i + n) * N2 + k] * dinv[k] * V[j * N2 + k];
     }
-  flag[inst] = bad;
+    ginv[i * n + j] = make_double2(re, im);
+  }
+  if (lane == 0) {
+    int bad = 0;
+    for (int k = 0; k < N2; ++k) bad |= badk[k];
+    flag[inst] = bad;
+  }
 }
 
 void launch_ginv(int ni, const double* gamma, int n, double eps, double* ginv, int* flag, hipStream_t s) {

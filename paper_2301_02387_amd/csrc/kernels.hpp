@@ -196,6 +196,13 @@ void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, 
 // q = K x on the DoF rows with the tuned operator kernel, p.q partials into red_scratch
 void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch, PoissonWs& P,
                           hipStream_t s);
+// Chebyshev smoothing of the multigrid cycle on the finest level, fused into
+// the operator pass (coef: [ni][8] with s0 = 1/theta, then c1, c2 of the
+// second step): the first two steps from z = 0 (z and d from r), and step k
+// (0 or 1) from zin into zout (d updated in place).
+void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* coef, int ncol, hipStream_t s);
+void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* coef,
+                         int ncol, int k, hipStream_t s);
 // Hanging rows of a real column array (xfull: x is over full rows, else extended).
 void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s);
 

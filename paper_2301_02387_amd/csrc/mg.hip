@@ -203,24 +203,33 @@ __global__ void __launch_bounds__(NT) k_mg_coarse(const MgLevelDev* __restrict__
 static dim3 level_grid(int64_t n, int ncol, int ni) { return dim3(nblocks(n * ncol, NT, 16384), ni); }
 
 // A z -> t on level l of every instance
-static void level_spmv(const MgDev& mg, int l, int ni, int ncol, const MgSpmv0& spmv0, hipStream_t s) {
-  if (l == 0) spmv0(mg.z0, mg.t0, s);
+static void level_spmv(const MgDev& mg, int l, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s) {
+  if (l == 0) ops.spmv(mg.z0, mg.t0, s);
   else hipLaunchKernelGGL(k_mg_spmv, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], ncol);
 }
 
-static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, const MgSpmv0& spmv0, hipStream_t s) {
+static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, const MgLevel0Ops& ops, hipStream_t s) {
+  if (l == 0 && ops.cheb0 && mg.nu == 2) {  // fused into the level-0 operator passes
+    if (from_zero) {
+      ops.cheb0(mg.z0, mg.d0, s);
+    } else {
+      ops.cheb(mg.z0, mg.z0b, mg.d0, 0, s);
+      ops.cheb(mg.z0b, mg.z0, mg.d0, 1, s);
+    }
+    return;
+  }
   for (int k = 0; k < mg.nu; ++k) {
-    if (!(from_zero && k == 0)) level_spmv(mg, l, ni, ncol, spmv0, s);
+    if (!(from_zero && k == 0)) level_spmv(mg, l, ni, ncol, ops, s);
     hipLaunchKernelGGL(k_mg_cheb, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], ncol, k,
                        from_zero ? 1 : 0);
   }
 }
 
-void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgSpmv0& spmv0, hipStream_t s) {
+void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s) {
   const int nl = mg.nlev;
   for (int l = 0; l + 1 < nl; ++l) {
-    smooth(mg, l, ni, ncol, true, spmv0, s);
-    level_spmv(mg, l, ni, ncol, spmv0, s);
+    smooth(mg, l, ni, ncol, true, ops, s);
+    level_spmv(mg, l, ni, ncol, ops, s);
     int cw = 1;
     while (cw < ncol) cw *= 2;
     hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(mg.max_n[l + 1] * 64, NT, 16384), ni), dim3(NT), 0, s, mg.lv[l],
@@ -230,7 +239,7 @@ void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgSpmv0& spmv0, hipStrea
                      mg.coarse, ncol);
   for (int l = nl - 2; l >= 0; --l) {
     hipLaunchKernelGGL(k_mg_prolong, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], mg.lv[l + 1], ncol);
-    smooth(mg, l, ni, ncol, false, spmv0, s);
+    smooth(mg, l, ni, ncol, false, ops, s);
   }
 }
 

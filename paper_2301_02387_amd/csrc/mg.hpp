@@ -47,14 +47,23 @@ struct MgDev {
   int64_t max_n[32] = {};   // largest N of each level over the instances (grid shapes)
   int64_t max_coarse = 0;
   double* z0 = nullptr;
+  double* z0b = nullptr;    // second level-0 correction array (the fused smoothing steps alternate)
   double* t0 = nullptr;
+  double* d0 = nullptr;
+  double* coef0 = nullptr;  // [ni][8]: level-0 Chebyshev coefficients s0, c1, c2
   int nu = 2;               // smoothing steps before and after the coarse correction
 };
-// level-0 operator pass over the batch: y = A x (batch arrays)
-using MgSpmv0 = std::function<void(const double* x, double* y, hipStream_t s)>;
+// Level-0 passes over the batch (batch arrays): y = A x; and, when set, the
+// smoothing steps fused into the operator pass (nu = 2): the two steps from
+// zero (z, d from r0), and step k from zin into zout.
+struct MgLevel0Ops {
+  std::function<void(const double* x, double* y, hipStream_t s)> spmv;
+  std::function<void(double* z, double* d, hipStream_t s)> cheb0;
+  std::function<void(const double* zin, double* zout, double* d, int k, hipStream_t s)> cheb;
+};
 
 // z0 = B r0 for one symmetric V-cycle per instance (r0: the batch residual)
-void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgSpmv0& spmv0, hipStream_t s);
+void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s);
 // red[i][slot][c] = sum over instance i's DoF rows of r[][c] z[][c] (part:
 // ni * MG_RZ_BLOCKS * ncol doubles); dm: the batch instance records
 struct DevMesh;

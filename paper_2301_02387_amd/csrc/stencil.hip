@@ -299,9 +299,17 @@ void launch_mass_direct(const Batch& b, const double* f, double* out, double* ma
 // NT / L lane groups splitting the entries and an LDS reduction; the other
 // workgroups sweep the remaining rows.
 // --------------------------------------------------------------------------
-// Value of the operand at row j, columns c0 .. c0+V: x itself, or (FUSE) the CG
-// direction p_j = D^-1_j r_j + beta p_prev,j formed on the fly (x = r then).
-template <int V, bool FUSE>
+// Operator pass modes: plain q = K x (SP_PLAIN); the CG direction formed on
+// the fly (SP_CG); and the two Chebyshev smoothing passes of the multigrid
+// cycle on the finest level, which replace q by the smoother's update:
+// SP_CHEB0 runs the first two steps from z = 0 (its operand s0 D^-1 r is
+// formed on the fly), SP_CHEB runs one step on a given z into another array.
+enum { SP_PLAIN = 0, SP_CG = 1, SP_CHEB0 = 2, SP_CHEB = 3 };
+
+// Value of the operand at row j, columns c0 .. c0+V: x itself; (SP_CG) the CG
+// direction p_j = D^-1_j r_j + beta p_prev,j formed on the fly (x = r then);
+// (SP_CHEB0) beta D^-1_j x_j (x = r, beta = s0).
+template <int V, int MODE>
 __device__ __forceinline__ void operand_row(const __attribute__((address_space(1))) double* xg,
                                             const __attribute__((address_space(1))) double* pg,
                                             const __attribute__((address_space(1))) double* dinv, const double* beta,
@@ -317,7 +325,12 @@ __device__ __forceinline__ void operand_row(const __attribute__((address_space(1
       out[2 * v + 1] = r2.y;
     }
   }
-  if constexpr (FUSE) {
+  if constexpr (MODE == SP_CHEB0) {
+    const double dj = dinv[j];
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = beta[v] * dj * out[v];
+  }
+  if constexpr (MODE == SP_CG) {
     const double dj = dinv[j];
     double pv[V];
     const auto* prow = pg + j * ld + c0;
@@ -340,7 +353,7 @@ __device__ __forceinline__ void operand_row(const __attribute__((address_space(1
 // four entries per round with all their loads issued together.  Past the end
 // the index is clamped to the row's last entry (every row holds its diagonal)
 // and the coefficient zeroed, so the loads need no branch.
-template <int V, bool FUSE>
+template <int V, int MODE>
 __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __restrict__ x,
                                               const double* __restrict__ pprev, const double* beta, int ld, int c0,
                                               int beg, int end, int stride, double* y) {
@@ -359,7 +372,7 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __
       const int64_t j = kcol[tc];
       const double a = kval[tc];
       av[u] = tt < end ? a : 0.0;
-      operand_row<V, FUSE>(xg, pg, dinv, beta, j, ld, c0, xv[u]);
+      operand_row<V, MODE>(xg, pg, dinv, beta, j, ld, c0, xv[u]);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -368,21 +381,52 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __
   }
 }
 
-// Row i done: q_i = y, (FUSE) p_i = the operand of row i, and the p.q partial.
-template <int V, bool FUSE>
+// Row i done, y = (K operand)_i.  SP_PLAIN / SP_CG: q_i = y, (SP_CG) p_i = the
+// operand of row i, and the p.q partial.  Chebyshev passes (x: the operand's
+// source, pprev = r, pout = z out, q = d, cf = the instance's coefficients
+// s0, c1, c2 with step k of SP_CHEB):
+//   SP_CHEB0: d0 = s0 D^-1 r, d = c1 d0 + c2 D^-1 (r - y), z = d0 + d;
+//   SP_CHEB:  d = c1 d + c D^-1 (r - y) (k = 0: c1 d dropped, c = s0; else
+//             c = c2), z = x + d.
+template <int V, int MODE>
 __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict__ q, double* __restrict__ pout,
                                            const double* __restrict__ x, const double* __restrict__ pprev,
                                            const double* beta, int64_t i, int ld, int c0, const double* y,
-                                           double* pq) {
-  double pi[V];
-  operand_row<V, FUSE>(gbl(x), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, pi);
-  double* qo = q + i * ld + c0;
-  double* po = pout + i * ld + c0;
+                                           double* pq, const double* cf, int k) {
+  if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB) {
+    const double di = gbl(d.kdiag_inv)[i];
+    double rv[V], xv[V], dv[V];
+    operand_row<V, SP_PLAIN>(gbl(pprev), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, rv);
+    if constexpr (MODE == SP_CHEB) {
+      operand_row<V, SP_PLAIN>(gbl(x), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, xv);
+      if (k > 0) operand_row<V, SP_PLAIN>(gbl((const double*)q), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, dv);
+    }
+    double* qo = q + i * ld + c0;
+    double* po = pout + i * ld + c0;
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-    qo[v] = y[v];
-    if constexpr (FUSE) po[v] = pi[v];
-    pq[v] += y[v] * pi[v];
+    for (int v = 0; v < V; ++v) {
+      if constexpr (MODE == SP_CHEB0) {
+        const double d0 = cf[0] * di * rv[v];
+        const double dn = cf[1] * d0 + cf[2] * di * (rv[v] - y[v]);
+        qo[v] = dn;
+        po[v] = d0 + dn;
+      } else {
+        const double dn = (k > 0 ? cf[1] * dv[v] + cf[2] * di * (rv[v] - y[v]) : cf[0] * di * (rv[v] - y[v]));
+        qo[v] = dn;
+        po[v] = xv[v] + dn;
+      }
+    }
+  } else {
+    double pi[V];
+    operand_row<V, MODE>(gbl(x), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, pi);
+    double* qo = q + i * ld + c0;
+    double* po = pout + i * ld + c0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      qo[v] = y[v];
+      if constexpr (MODE == SP_CG) po[v] = pi[v];
+      pq[v] += y[v] * pi[v];
+    }
   }
 }
 
@@ -390,11 +434,15 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict_
 // (nc = ld without column blocking).  SELL: the short rows come from the
 // sliced-ELL copy, a wave taking 64 / L slots of one slice (one width for all
 // its rows), so each round of entries is read as consecutive words.
-template <int L, int V, bool FUSE, bool SELL>
+// MODE: SP_*; red: the p.q accumulators ([ni][RED_SLOTS][ld]), or for the
+// Chebyshev passes the coefficients ([ni][8]: s0, c1, c2).
+template <int L, int V, int MODE, bool SELL>
 __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
                                                      const double* __restrict__ pprev, double* __restrict__ pout,
                                                      int ld, int nc, double* __restrict__ q, int nlb,
                                                      double* __restrict__ red, int k) {
+  constexpr bool FUSE = MODE == SP_CG;
+  constexpr bool CHEB = MODE == SP_CHEB0 || MODE == SP_CHEB;
   INSTANCE;
   __shared__ double lds[NT * V];
   const int col0 = blockIdx.z * nc;
@@ -402,15 +450,16 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
   q += d.oE * ld + col0;
   pprev += d.oE * ld + col0;
   pout += d.oE * ld + col0;
-  red += (int64_t)blockIdx.y * RED_SLOTS * ld + col0;
+  const double* cf = red + (int64_t)blockIdx.y * 8;
+  if constexpr (!CHEB) red += (int64_t)blockIdx.y * RED_SLOTS * ld + col0;
   const int lane = (int)(threadIdx.x & (L - 1));
   const int c0 = lane * V;
   const bool col_ok = c0 < nc;
-  // beta_k = rz_k / rz_{k-1} per column (0 at the first iteration)
+  // beta_k = rz_k / rz_{k-1} per column (0 at the first iteration); s0 for SP_CHEB0
   double beta[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    beta[v] = 0.0;
+    beta[v] = MODE == SP_CHEB0 ? cf[0] : 0.0;
     if (FUSE && k > 0 && c0 + v < nc) {
       const double rzk = red[(RED_RZ + k % 3) * ld + c0 + v], rzp = red[(RED_RZ + (k + 2) % 3) * ld + c0 + v];
       beta[v] = rzp != 0.0 ? rzk / rzp : 0.0;
@@ -430,12 +479,12 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       double y[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) y[v] = 0.0;
-      if (col_ok) spmv_row_part<V, FUSE>(d, x, pprev, beta, ld, c0, beg + seg, end, SEG, y);
+      if (col_ok) spmv_row_part<V, MODE>(d, x, pprev, beta, ld, c0, beg + seg, end, SEG, y);
 #pragma unroll
       for (int off = L; off < 64; off <<= 1)
 #pragma unroll
         for (int v = 0; v < V; ++v) y[v] += __shfl_xor(y[v], off, 64);
-      if (seg == 0 && col_ok) spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq);
+      if (seg == 0 && col_ok) spmv_store<V, MODE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   } else if constexpr (SELL) {
     constexpr int R = 64 / L;  // slots per wave
@@ -465,14 +514,14 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
         for (int h = 0; h < 4; ++h) {
           const int e = base + (t + h) * SELL_H + slot;
           av[h] = sval[e];
-          operand_row<V, FUSE>(xg, pg, dinv, beta, (int64_t)scol[e], ld, c0, xv[h]);
+          operand_row<V, MODE>(xg, pg, dinv, beta, (int64_t)scol[e], ld, c0, xv[h]);
         }
 #pragma unroll
         for (int h = 0; h < 4; ++h)
 #pragma unroll
           for (int v = 0; v < V; ++v) y[v] += av[h] * xv[h][v];
       }
-      spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq);
+      spmv_store<V, MODE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   } else {
     const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
@@ -483,10 +532,11 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       double y[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) y[v] = 0.0;
-      spmv_row_part<V, FUSE>(d, x, pprev, beta, ld, c0, beg, end, 1, y);
-      spmv_store<V, FUSE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq);
+      spmv_row_part<V, MODE>(d, x, pprev, beta, ld, c0, beg, end, 1, y);
+      spmv_store<V, MODE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   }
+  if constexpr (CHEB) return;
   // p.q of the workgroup: shuffles over the rows of each wave, then 4 waves
 #pragma unroll
   for (int off = L; off < 64; off <<= 1)
@@ -519,27 +569,29 @@ static int long_row_blocks(const Batch& b) {
   return (int)((nb + N_XCD - 1) / N_XCD * N_XCD);
 }
 
-template <int L, int V>
-static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, double* pout, int ld, int nc,
-                          double* q, const PoissonWs& P, int k, hipStream_t s) {
+template <int L, int V, int MODE>
+static void launch_spmv_m(const Batch& b, const double* x, const double* pprev, double* pout, int ld, int nc,
+                          double* q, double* red, int k, hipStream_t s) {
   const int nlb = long_row_blocks(b);
   if (b.mx.sched_poi & 32) {
     const dim3 g(nlb + xcd_grid(b.mx.n_slices * L, NT / 64, b.mx.grid_poi), b.ni, ld / nc);
-    if (k >= 0)
-      hipLaunchKernelGGL((k_spmv_poisson<L, V, true, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
-                         P.red, k);
-    else
-      hipLaunchKernelGGL((k_spmv_poisson<L, V, false, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
-                         nlb, P.red, k);
-    return;
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
+                       red, k);
+  } else {
+    const dim3 g(nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi), b.ni, ld / nc);
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
+                       red, k);
   }
-  const dim3 g(nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi), b.ni, ld / nc);
-  if (k >= 0)
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, true, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
-                       P.red, k);
-  else
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, false, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
-                       P.red, k);
+}
+template <int L, int V>
+static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, double* pout, int ld, int nc,
+                          double* q, double* red, int mode, int k, hipStream_t s) {
+  switch (mode) {
+    case SP_PLAIN: return launch_spmv_m<L, V, SP_PLAIN>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    case SP_CG: return launch_spmv_m<L, V, SP_CG>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    case SP_CHEB0: return launch_spmv_m<L, V, SP_CHEB0>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    default: return launch_spmv_m<L, V, SP_CHEB>(b, x, pprev, pout, ld, nc, q, red, k, s);
+  }
 }
 
 // q = K x (k < 0: k = -1 at the CG start, -2 - j for the plain pass of iteration j),
@@ -548,29 +600,35 @@ static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, 
 // Schedule bit 1 (column blocking): with 32 or more columns in multiples of 16,
 // grid.z runs over blocks of 16 columns, so a row slice is 128 B and the band of
 // neighbour rows a sweep touches stays in L2 (the matrix is read once per block).
+static void launch_spmv_mode(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
+                             double* q, double* red, int mode, int k, hipStream_t s);
 static void launch_spmv_poisson(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
                                 double* q, const PoissonWs& P, int k, hipStream_t s) {
+  launch_spmv_mode(b, x, pprev, pout, ncol, q, P.red, k >= 0 ? SP_CG : SP_PLAIN, k, s);
+}
+static void launch_spmv_mode(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
+                             double* q, double* red, int mode, int k, hipStream_t s) {
   if ((b.mx.sched_poi & 2) && ncol >= 32 && ncol % 16 == 0)
-    return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, 16, q, P, k, s);
+    return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, 16, q, red, mode, k, s);
   if (ncol % 4 == 0 && ncol > 4) {  // 4 columns per lane (two 16-byte loads)
-    if (ncol <= 16) return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-    if (ncol <= 32) return launch_spmv_t<8, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-    return launch_spmv_t<16, 4>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    if (ncol <= 16) return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 32) return launch_spmv_t<8, 4>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    return launch_spmv_t<16, 4>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
   }
   if (ncol % 2 == 0) {  // 16-byte column pairs
-    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-    if (ncol <= 8) return launch_spmv_t<4, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-    if (ncol <= 16) return launch_spmv_t<8, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-    if (ncol <= 32) return launch_spmv_t<16, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-    return launch_spmv_t<32, 2>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 8) return launch_spmv_t<4, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 16) return launch_spmv_t<8, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 32) return launch_spmv_t<16, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    return launch_spmv_t<32, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
   }
-  if (ncol <= 1) return launch_spmv_t<1, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-  if (ncol <= 2) return launch_spmv_t<2, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-  if (ncol <= 4) return launch_spmv_t<4, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-  if (ncol <= 8) return launch_spmv_t<8, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-  if (ncol <= 16) return launch_spmv_t<16, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-  if (ncol <= 32) return launch_spmv_t<32, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
-  return launch_spmv_t<64, 1>(b, x, pprev, pout, ncol, ncol, q, P, k, s);
+  if (ncol <= 1) return launch_spmv_t<1, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 2) return launch_spmv_t<2, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 4) return launch_spmv_t<4, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 8) return launch_spmv_t<8, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 16) return launch_spmv_t<16, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 32) return launch_spmv_t<32, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  return launch_spmv_t<64, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
 }
 
 // --------------------------------------------------------------------------
@@ -788,6 +846,17 @@ void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, 
     (void)hipEventRecord(P.ev[P.ev_used + 1], s);
     P.ev_used += 2;
   }
+}
+
+// Chebyshev smoothing on the finest multigrid level fused into the operator
+// pass (the spmv_store comment gives the updates): the first two steps from
+// zero (z, d from r), and one further step from zin into zout.
+void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* coef, int ncol, hipStream_t s) {
+  launch_spmv_mode(b, r, r, z, ncol, d, coef, SP_CHEB0, 0, s);
+}
+void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* coef,
+                         int ncol, int k, hipStream_t s) {
+  launch_spmv_mode(b, zin, r, zout, ncol, d, coef, SP_CHEB, k, s);
 }
 
 // The plain operator pass of CG iteration k on the direction p (q = K p, p.q
