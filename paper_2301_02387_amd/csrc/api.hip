@@ -81,6 +81,7 @@ struct mh_op {
   double* mg_red = nullptr;   // scratch accumulators of the level-0 operator passes
   double* mg_part = nullptr;  // r.z partials
   int mg_levels = 0;
+  int cg_hint = 0;            // iterations of the last multigrid-preconditioned solve
   bool frozen = false;
   // Krylov
   int m_alloc = 0;
@@ -835,8 +836,10 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
 // after launch_cg_start (r_0 in P.r, accumulators initialised): z = B r,
 // rz = r.z, p = z + beta p, then the same operator and update passes as the
 // Jacobi CG (alpha = r.z / p.q), with every instance's own scalars.
-// Converged (1), not (0) or non-finite (-1); the check runs after every
-// iteration.
+// Converged (1), not (0) or non-finite (-1).  The check (a host round trip)
+// runs before the first iteration and after every iteration from two before
+// the previous solve's count on (successive solves of a propagation take
+// nearly the same count; an unchecked iteration only lowers the residual).
 static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
   const Batch& B = op->B;
   PoissonWs& P = op->P;
@@ -855,6 +858,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
   P.it = 0;
   int conv = poisson_converged(op, s);
   int k = 0;
+  const int check_from = op->cg_hint - 2;
   if (conv == 0) {
     mg_vcycle(mg, ni, ncol, ops, s);
     mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ, s);
@@ -866,7 +870,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
     launch_cg_update(B, W, P, pcur, k, s);
     ++k;
     P.it = k;
-    conv = poisson_converged(op, s);
+    if (k >= check_from || k == op->maxit) conv = poisson_converged(op, s);
     if (conv != 0) break;
     mg_vcycle(mg, ni, ncol, ops, s);
     mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ + k % 3, s);
@@ -875,6 +879,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
     mg_dir(B.dm, ni, N, ncol, z, pold, pnext, P.red, RED_RZ + k % 3, RED_RZ + (k - 1) % 3, RED_RR + k % 2, s);
   }
   if (iters) *iters = k;
+  op->cg_hint = k;
   return conv;
 }
 

@@ -125,8 +125,10 @@ __global__ void __launch_bounds__(NT) k_cheb_finish(const DevMesh* __restrict__ 
 }
 
 // Interface solve by the dense inverse (one instance): x = A^-1 b, one wave per
-// row, the lanes splitting the row's columns; then the final value of each
-// master DoF as in k_cheb_finish.
+// row, the lanes splitting the row's columns (four strides of 64 per round,
+// their loads in flight together); then the final value of each master DoF
+// as in k_cheb_finish.  NP: the orbital count rounded up (2, 4 or 8).
+template <int NP>
 __global__ void __launch_bounds__(NT) k_ma_dense(const DevMesh* __restrict__ dm, const double2* __restrict__ b,
                                                  const double2* __restrict__ v, const double2* __restrict__ lam,
                                                  double2* __restrict__ out) {
@@ -137,14 +139,34 @@ __global__ void __launch_bounds__(NT) k_ma_dense(const DevMesh* __restrict__ dm,
   const int lane = threadIdx.x & 63;
   const double2* L = lam ? lam + (int64_t)blockIdx.y * n * n : nullptr;
   for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) >> 6; i < nMa; i += ((int64_t)gridDim.x * NT) >> 6) {
-    double sx[8], sy[8];
+    double sx[NP], sy[NP];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) { sx[p] = 0.0; sy[p] = 0.0; }
+    for (int p = 0; p < NP; ++p) { sx[p] = 0.0; sy[p] = 0.0; }
     const auto* row = Ai + i * nMa;
-    for (int64_t j = lane; j < nMa; j += 64) {
+    int64_t j = lane;
+    for (; j + 192 < nMa; j += 256) {
+      double a[4];
+      double2 bj[4][NP];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = row[j + 64 * u];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          if (p < n) bj[u][p] = ldg2(b, o + (j + 64 * u) * n + p);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          if (p < n) {
+            sx[p] += a[u] * bj[u][p].x;
+            sy[p] += a[u] * bj[u][p].y;
+          }
+    }
+    for (; j < nMa; j += 64) {
       const double a = row[j];
 #pragma unroll
-      for (int p = 0; p < 8; ++p)
+      for (int p = 0; p < NP; ++p)
         if (p < n) {
           const double2 bj = ldg2(b, o + j * n + p);
           sx[p] += a * bj.x;
@@ -154,7 +176,7 @@ __global__ void __launch_bounds__(NT) k_ma_dense(const DevMesh* __restrict__ dm,
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-      for (int p = 0; p < 8; ++p)
+      for (int p = 0; p < NP; ++p)
         if (p < n) {
           sx[p] += __shfl_xor(sx[p], off, 64);
           sy[p] += __shfl_xor(sy[p], off, 64);
@@ -162,7 +184,7 @@ __global__ void __launch_bounds__(NT) k_ma_dense(const DevMesh* __restrict__ dm,
     if (lane < n) {
       double2 xf = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int p = 0; p < 8; ++p)
+      for (int p = 0; p < NP; ++p)
         if (p == lane) xf = make_double2(sx[p], sy[p]);
       const int64_t k = d.ma_dof[i];
       if (L)
@@ -208,8 +230,16 @@ void launch_ma_solve(const Batch& b, const double* ma_b, double* x, double* r, d
                      const double* v, const double* lam, double* out, hipStream_t s) {
   if (b.mx.nMa == 0) return;
   if (b.ni == 1 && b.mx.ma_inv && !(b.mx.sched_orb & 2)) {
-    hipLaunchKernelGGL(k_ma_dense, dim3(nblocks(b.mx.nMa * 64, NT, 8192), 1), dim3(NT), 0, s, b.dm,
-                       (const double2*)ma_b, (const double2*)v, (const double2*)lam, (double2*)out);
+    const dim3 g(nblocks(b.mx.nMa * 64, NT, 8192), 1);
+    if (b.mx.n <= 2)
+      hipLaunchKernelGGL(k_ma_dense<2>, g, dim3(NT), 0, s, b.dm, (const double2*)ma_b, (const double2*)v,
+                         (const double2*)lam, (double2*)out);
+    else if (b.mx.n <= 4)
+      hipLaunchKernelGGL(k_ma_dense<4>, g, dim3(NT), 0, s, b.dm, (const double2*)ma_b, (const double2*)v,
+                         (const double2*)lam, (double2*)out);
+    else
+      hipLaunchKernelGGL(k_ma_dense<8>, g, dim3(NT), 0, s, b.dm, (const double2*)ma_b, (const double2*)v,
+                         (const double2*)lam, (double2*)out);
     return;
   }
   const dim3 g(nblocks(b.mx.nMa * b.mx.n), b.ni);

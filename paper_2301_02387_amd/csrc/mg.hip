@@ -180,7 +180,22 @@ __global__ void __launch_bounds__(NT) k_mg_coarse(const MgLevelDev* __restrict__
     double acc[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) acc[v] = 0.0;
-    for (int64_t j = lane; j < n; j += 64) {
+    // four strides of 64 per round, their loads in flight together
+    int64_t j = lane;
+    for (; j + 192 < n; j += 256) {
+      double a[4], rv[4][8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Ainv[i * n + j + 64 * u];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) rv[u][v] = c0 + v < ncol ? r[(j + 64 * u) * ncol + c0 + v] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[v] += a[u] * rv[u][v];
+    }
+    for (; j < n; j += 64) {
       const double a = Ainv[i * n + j];
 #pragma unroll
       for (int v = 0; v < 8; ++v)
