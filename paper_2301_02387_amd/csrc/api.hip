@@ -762,16 +762,15 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
   HIPCHK(hipMemsetAsync(d0, 0, tlen * sizeof(double), s));
   // level-0 Chebyshev coefficients of the fused smoothing passes: s0 = 1/theta
   // (first step), then c1, c2 of the second step of the three-term recurrence
-  std::vector<double> coef((size_t)ni * 8, 0.0);
   for (int i = 0; i < ni; ++i) {
     const double b = H[i].lv[0].lmax, a = b / MG_RANGE;
     const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
     const double rho0 = 1.0 / sigma, rn = 1.0 / (2.0 * sigma - rho0);
-    coef[(size_t)i * 8 + 0] = 1.0 / theta;
-    coef[(size_t)i * 8 + 1] = rn * rho0;
-    coef[(size_t)i * 8 + 2] = 2.0 * rn / delta;
+    op->dh[i].mgc[0] = 1.0 / theta;
+    op->dh[i].mgc[1] = rn * rho0;
+    op->dh[i].mgc[2] = 2.0 * rn / delta;
   }
-  mg->coef0 = op->upload(coef, s);
+  upload_instances(op, s);
   std::vector<std::vector<MgLevelDev>> rec(nlev, std::vector<MgLevelDev>(ni));
   std::vector<MgLevelDev> co(ni);
   for (int i = 0; i < ni; ++i) {
@@ -835,7 +834,9 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
 // CG preconditioned by one multigrid V-cycle per instance and iteration,
 // after launch_cg_start (r_0 in P.r, accumulators initialised): z = B r,
 // rz = r.z, p = z + beta p, then the same operator and update passes as the
-// Jacobi CG (alpha = r.z / p.q), with every instance's own scalars.
+// Jacobi CG (alpha = r.z / p.q), with every instance's own scalars.  With a
+// smoothed finest level, r.z is accumulated by the cycle's last smoothing
+// pass; else it takes passes of its own.
 // Converged (1), not (0) or non-finite (-1).  The check (a host round trip)
 // runs before the first iteration and after every iteration from two before
 // the previous solve's count on (successive solves of a propagation take
@@ -846,37 +847,41 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
   const MgDev& mg = *op->mg;
   const int ncol = op->ncol, ni = op->ni;
   const int64_t N = B.mx.N;
+  const bool fused = mg.nlev > 1 && mg.nu == 2;
+  int rz_slot = RED_RZ;
   MgLevel0Ops ops;
   ops.spmv = [&](const double* x, double* y, hipStream_t st) {
     launch_poisson_apply(B, x, y, ncol, op->mg_red, P, st);
   };
-  ops.cheb0 = [&](double* z, double* d, hipStream_t st) { launch_mg_cheb0(B, P.r, z, d, mg.coef0, ncol, st); };
+  ops.cheb0 = [&](double* z, double* d, hipStream_t st) {
+    launch_mg_cheb0(B, P.r, z, d, P.red, rz_slot, ncol, st);
+  };
   ops.cheb = [&](const double* zin, double* zout, double* d, int k, hipStream_t st) {
-    launch_mg_cheb_step(B, zin, P.r, zout, d, mg.coef0, ncol, k, st);
+    launch_mg_cheb_step(B, zin, P.r, zout, d, P.red, ncol, k, k == 1 ? rz_slot : -1, st);
   };
   double* z = mg.z0;
+  auto precondition = [&](int it) {  // z = B r with r.z in slot RED_RZ + it % 3
+    rz_slot = RED_RZ + it % 3;
+    mg_vcycle(mg, ni, ncol, ops, s);
+    if (!fused) mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, rz_slot, s);
+  };
   P.it = 0;
   int conv = poisson_converged(op, s);
   int k = 0;
   const int check_from = op->cg_hint - 2;
-  if (conv == 0) {
-    mg_vcycle(mg, ni, ncol, ops, s);
-    mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ, s);
-    mg_dir(B.dm, ni, N, ncol, z, P.p2, P.p, P.red, RED_RZ, -1, RED_RR, s);
-  }
+  if (conv == 0) precondition(0);
   while (conv == 0 && k < op->maxit) {
     double* pcur = (k % 2) ? P.p2 : P.p;
+    double* pold = (k % 2) ? P.p : P.p2;
+    mg_dir(B.dm, ni, N, ncol, z, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1, RED_RR + k % 2,
+           s);
     launch_cg_apply_plain(B, P, pcur, k, s);
     launch_cg_update(B, W, P, pcur, k, s);
     ++k;
     P.it = k;
     if (k >= check_from || k == op->maxit) conv = poisson_converged(op, s);
     if (conv != 0) break;
-    mg_vcycle(mg, ni, ncol, ops, s);
-    mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, RED_RZ + k % 3, s);
-    double* pnext = (k % 2) ? P.p2 : P.p;
-    double* pold = (k % 2) ? P.p : P.p2;
-    mg_dir(B.dm, ni, N, ncol, z, pold, pnext, P.red, RED_RZ + k % 3, RED_RZ + (k - 1) % 3, RED_RR + k % 2, s);
+    precondition(k);
   }
   if (iters) *iters = k;
   op->cg_hint = k;

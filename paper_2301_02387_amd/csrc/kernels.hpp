@@ -65,6 +65,7 @@ struct DevMesh {
   const double* bnd_table = nullptr;    // [Nb][nharm] multipole boundary table
   double center[3] = {0.0, 0.0, 0.0};   // multipole expansion centre
   double E0 = 1.0;                      // field amplitude of this instance (E = E0 x the step's field value)
+  double mgc[3] = {0.0, 0.0, 0.0};      // multigrid level-0 Chebyshev coefficients: s0 = 1/theta, c1, c2
   double vnn = 0.0;                     // nuclear repulsion
   // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; orbital bit 1 = interface
   // solve by Chebyshev even where a dense inverse is held, bit 2 = stiffness part by the
@@ -196,13 +197,16 @@ void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, 
 // q = K x on the DoF rows with the tuned operator kernel, p.q partials into red_scratch
 void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch, PoissonWs& P,
                           hipStream_t s);
-// Chebyshev smoothing of the multigrid cycle on the finest level, fused into
-// the operator pass (coef: [ni][8] with s0 = 1/theta, then c1, c2 of the
-// second step): the first two steps from z = 0 (z and d from r), and step k
-// (0 or 1) from zin into zout (d updated in place).
-void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* coef, int ncol, hipStream_t s);
-void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* coef,
-                         int ncol, int k, hipStream_t s);
+// Multigrid-preconditioned CG on the finest level, in operator passes (the
+// Chebyshev coefficients are each instance's DevMesh::mgc; red: the CG
+// accumulators [ni][RED_SLOTS][ncol]):
+//  - the first two smoothing steps from z = 0 (z and d from r); clears red slot rz_slot;
+//  - smoothing step k (0 or 1) from zin into zout (d updated in place); with
+//    rz_slot >= 0 (step 1 only) it also accumulates r.zout into that slot.
+void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* red, int rz_slot, int ncol,
+                     hipStream_t s);
+void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* red,
+                         int ncol, int k, int rz_slot, hipStream_t s);
 // Hanging rows of a real column array (xfull: x is over full rows, else extended).
 void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s);
 

@@ -50,7 +50,6 @@ struct MgDev {
   double* z0b = nullptr;    // second level-0 correction array (the fused smoothing steps alternate)
   double* t0 = nullptr;
   double* d0 = nullptr;
-  double* coef0 = nullptr;  // [ni][8]: level-0 Chebyshev coefficients s0, c1, c2
   int nu = 2;               // smoothing steps before and after the coarse correction
 };
 // Level-0 passes over the batch (batch arrays): y = A x; and, when set, the

@@ -304,7 +304,9 @@ void launch_mass_direct(const Batch& b, const double* f, double* out, double* ma
 // cycle on the finest level, which replace q by the smoother's update:
 // SP_CHEB0 runs the first two steps from z = 0 (its operand s0 D^-1 r is
 // formed on the fly), SP_CHEB runs one step on a given z into another array.
-enum { SP_PLAIN = 0, SP_CG = 1, SP_CHEB0 = 2, SP_CHEB = 3 };
+// SP_CHEB_RZ is the second SP_CHEB step with r.z accumulated for the
+// multigrid-preconditioned CG.
+enum { SP_PLAIN = 0, SP_CG = 1, SP_CHEB0 = 2, SP_CHEB = 3, SP_CHEB_RZ = 4 };
 
 // Value of the operand at row j, columns c0 .. c0+V: x itself; (SP_CG) the CG
 // direction p_j = D^-1_j r_j + beta p_prev,j formed on the fly (x = r then);
@@ -381,25 +383,27 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __
   }
 }
 
-// Row i done, y = (K operand)_i.  SP_PLAIN / SP_CG: q_i = y, (SP_CG) p_i = the
-// operand of row i, and the p.q partial.  Chebyshev passes (x: the operand's
-// source, pprev = r, pout = z out, q = d, cf = the instance's coefficients
-// s0, c1, c2 with step k of SP_CHEB):
+// Row i done, y = (K operand)_i.  SP_PLAIN / SP_CG: q_i = y, (SP_CG) p_i =
+// the operand of row i, and the p.q partial.
+// Chebyshev passes (x: the operand's source, pprev = r, pout = z out, q = d,
+// cf = the instance's coefficients s0, c1, c2; step k of SP_CHEB, step 1 for
+// SP_CHEB_RZ):
 //   SP_CHEB0: d0 = s0 D^-1 r, d = c1 d0 + c2 D^-1 (r - y), z = d0 + d;
 //   SP_CHEB:  d = c1 d + c D^-1 (r - y) (k = 0: c1 d dropped, c = s0; else
-//             c = c2), z = x + d.
+//             c = c2), z = x + d; SP_CHEB_RZ also the r.z partial (in pq).
 template <int V, int MODE>
 __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict__ q, double* __restrict__ pout,
                                            const double* __restrict__ x, const double* __restrict__ pprev,
                                            const double* beta, int64_t i, int ld, int c0, const double* y,
                                            double* pq, const double* cf, int k) {
-  if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB) {
+  if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_CHEB_RZ) {
+    const int step = MODE == SP_CHEB_RZ ? 1 : k;
     const double di = gbl(d.kdiag_inv)[i];
     double rv[V], xv[V], dv[V];
     operand_row<V, SP_PLAIN>(gbl(pprev), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, rv);
-    if constexpr (MODE == SP_CHEB) {
+    if constexpr (MODE != SP_CHEB0) {
       operand_row<V, SP_PLAIN>(gbl(x), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, xv);
-      if (k > 0) operand_row<V, SP_PLAIN>(gbl((const double*)q), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, dv);
+      if (step > 0) operand_row<V, SP_PLAIN>(gbl((const double*)q), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, dv);
     }
     double* qo = q + i * ld + c0;
     double* po = pout + i * ld + c0;
@@ -411,9 +415,11 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict_
         qo[v] = dn;
         po[v] = d0 + dn;
       } else {
-        const double dn = (k > 0 ? cf[1] * dv[v] + cf[2] * di * (rv[v] - y[v]) : cf[0] * di * (rv[v] - y[v]));
+        const double dn = (step > 0 ? cf[1] * dv[v] + cf[2] * di * (rv[v] - y[v]) : cf[0] * di * (rv[v] - y[v]));
+        const double zn = xv[v] + dn;
         qo[v] = dn;
-        po[v] = xv[v] + dn;
+        po[v] = zn;
+        if constexpr (MODE == SP_CHEB_RZ) pq[v] += rv[v] * zn;
       }
     }
   } else {
@@ -434,15 +440,16 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict_
 // (nc = ld without column blocking).  SELL: the short rows come from the
 // sliced-ELL copy, a wave taking 64 / L slots of one slice (one width for all
 // its rows), so each round of entries is read as consecutive words.
-// MODE: SP_*; red: the p.q accumulators ([ni][RED_SLOTS][ld]), or for the
-// Chebyshev passes the coefficients ([ni][8]: s0, c1, c2).
+// MODE: SP_*; red: the CG accumulators ([ni][RED_SLOTS][ld]); k: the CG
+// iteration (SP_CG; see launch_spmv_poisson for SP_PLAIN), the
+// smoothing step (SP_CHEB) or the r.z slot (SP_CHEB0 clears it, SP_CHEB_RZ
+// accumulates into it).
 template <int L, int V, int MODE, bool SELL>
 __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
                                                      const double* __restrict__ pprev, double* __restrict__ pout,
                                                      int ld, int nc, double* __restrict__ q, int nlb,
                                                      double* __restrict__ red, int k) {
   constexpr bool FUSE = MODE == SP_CG;
-  constexpr bool CHEB = MODE == SP_CHEB0 || MODE == SP_CHEB;
   INSTANCE;
   __shared__ double lds[NT * V];
   const int col0 = blockIdx.z * nc;
@@ -450,8 +457,8 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
   q += d.oE * ld + col0;
   pprev += d.oE * ld + col0;
   pout += d.oE * ld + col0;
-  const double* cf = red + (int64_t)blockIdx.y * 8;
-  if constexpr (!CHEB) red += (int64_t)blockIdx.y * RED_SLOTS * ld + col0;
+  const double cf[3] = {d.mgc[0], d.mgc[1], d.mgc[2]};
+  red += (int64_t)blockIdx.y * RED_SLOTS * ld + col0;
   const int lane = (int)(threadIdx.x & (L - 1));
   const int c0 = lane * V;
   const bool col_ok = c0 < nc;
@@ -536,8 +543,11 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       spmv_store<V, MODE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   }
-  if constexpr (CHEB) return;
-  // p.q of the workgroup: shuffles over the rows of each wave, then 4 waves
+  if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB) {
+    if (MODE == SP_CHEB0 && blockIdx.x == 0 && threadIdx.x < (unsigned)nc) red[k * ld + threadIdx.x] = 0.0;
+    return;
+  }
+  // p.q (r.z for SP_CHEB_RZ) of the workgroup: shuffles over the rows of each wave, then 4 waves
 #pragma unroll
   for (int off = L; off < 64; off <<= 1)
 #pragma unroll
@@ -550,12 +560,16 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) sum += lds[w * (L * V) + threadIdx.x];
-    // iteration of this pass: k (fused), -2 - k (plain pass of a CG iteration), 0 (k = -1: start)
-    const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
-    atomicAdd(red + (RED_PQ + kk % 2) * ld + threadIdx.x, sum);  // p.q of this instance and column
-    if (FUSE && blockIdx.x == 0) {  // clear what the update pass of this iteration accumulates into
-      red[(RED_RZ + (k + 1) % 3) * ld + threadIdx.x] = 0.0;
-      red[(RED_RR + k % 2) * ld + threadIdx.x] = 0.0;
+    if constexpr (MODE == SP_CHEB_RZ) {
+      atomicAdd(red + k * ld + threadIdx.x, sum);  // r.z of this instance and column
+    } else {
+      // iteration of this pass: k (fused), -2 - k (plain pass of a CG iteration), 0 (k = -1: start)
+      const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
+      atomicAdd(red + (RED_PQ + kk % 2) * ld + threadIdx.x, sum);  // p.q of this instance and column
+      if (FUSE && blockIdx.x == 0) {  // clear what the update pass of this iteration accumulates into
+        red[(RED_RZ + (k + 1) % 3) * ld + threadIdx.x] = 0.0;
+        red[(RED_RR + k % 2) * ld + threadIdx.x] = 0.0;
+      }
     }
   }
 }
@@ -590,7 +604,8 @@ static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, 
     case SP_PLAIN: return launch_spmv_m<L, V, SP_PLAIN>(b, x, pprev, pout, ld, nc, q, red, k, s);
     case SP_CG: return launch_spmv_m<L, V, SP_CG>(b, x, pprev, pout, ld, nc, q, red, k, s);
     case SP_CHEB0: return launch_spmv_m<L, V, SP_CHEB0>(b, x, pprev, pout, ld, nc, q, red, k, s);
-    default: return launch_spmv_m<L, V, SP_CHEB>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    case SP_CHEB: return launch_spmv_m<L, V, SP_CHEB>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    default: return launch_spmv_m<L, V, SP_CHEB_RZ>(b, x, pprev, pout, ld, nc, q, red, k, s);
   }
 }
 
@@ -851,12 +866,14 @@ void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, 
 // Chebyshev smoothing on the finest multigrid level fused into the operator
 // pass (the spmv_store comment gives the updates): the first two steps from
 // zero (z, d from r), and one further step from zin into zout.
-void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* coef, int ncol, hipStream_t s) {
-  launch_spmv_mode(b, r, r, z, ncol, d, coef, SP_CHEB0, 0, s);
+void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* red, int rz_slot, int ncol,
+                     hipStream_t s) {
+  launch_spmv_mode(b, r, r, z, ncol, d, red, SP_CHEB0, rz_slot, s);
 }
-void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* coef,
-                         int ncol, int k, hipStream_t s) {
-  launch_spmv_mode(b, zin, r, zout, ncol, d, coef, SP_CHEB, k, s);
+void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* red,
+                         int ncol, int k, int rz_slot, hipStream_t s) {
+  if (rz_slot >= 0) launch_spmv_mode(b, zin, r, zout, ncol, d, red, SP_CHEB_RZ, rz_slot, s);
+  else launch_spmv_mode(b, zin, r, zout, ncol, d, red, SP_CHEB, k, s);
 }
 
 // The plain operator pass of CG iteration k on the direction p (q = K p, p.q
