@@ -98,6 +98,35 @@ __device__ inline void solid_regular(double x, double y, double z, int lmax, dou
   }
 }
 
+// The order-m terms of solid_regular alone (l = m .. lmax), with the same
+// arithmetic: (x + i y)^m and (2m - 1)!! by the same recurrence, then the
+// recurrence in l.
+__device__ inline void solid_regular_m(double x, double y, double z, int lmax, int m, double* R) {
+  const double r2 = x * x + y * y + z * z;
+  double pre = 1.0, pim = 0.0, dfact = 1.0;
+  for (int k = 1; k <= m; ++k) {
+    double t = pre * x - pim * y;
+    pim = pre * y + pim * x;
+    pre = t;
+    dfact *= (2.0 * k - 1.0);
+  }
+  double a_re = dfact * pre, a_im = dfact * pim, b_re = 0.0, b_im = 0.0;
+  for (int l = m; l <= lmax; ++l) {
+    double re, im;
+    if (l == m) { re = a_re; im = a_im; }
+    else if (l == m + 1) {
+      re = (2.0 * m + 1.0) * z * a_re; im = (2.0 * m + 1.0) * z * a_im;
+      b_re = a_re; b_im = a_im; a_re = re; a_im = im;
+    } else {
+      re = ((2.0 * l - 1.0) * z * a_re - (l + m - 1.0) * r2 * b_re) / (l - m);
+      im = ((2.0 * l - 1.0) * z * a_im - (l + m - 1.0) * r2 * b_im) / (l - m);
+      b_re = a_re; b_im = a_im; a_re = re; a_im = im;
+    }
+    R[l * l + m] = re;
+    if (m > 0) R[l * l + l + m] = im;
+  }
+}
+
 static inline int nblocks(int64_t work, int per = NT, int cap = 1 << 20) {
   int64_t b = (work + per - 1) / per;
   if (b < 1) b = 1;

@@ -393,6 +393,59 @@ __global__ void __launch_bounds__(NT) k_xgram(const DevMesh* __restrict__ dm, in
   }
 }
 
+// The same for small output sets (na nb <= 16): every thread accumulates all
+// outputs over a grid-stride set of rows (no staging, no barrier per chunk),
+// then one reduction per workgroup (shuffles, then the four waves).
+__global__ void __launch_bounds__(NT) k_xgram_small(const DevMesh* __restrict__ dm, int wsel, int rsel,
+                                                    const double2* __restrict__ X, int na,
+                                                    const double2* __restrict__ Y, int nb, int64_t frows,
+                                                    double2* __restrict__ part) {
+  __shared__ double2 lw[NT / 64][16];
+  int64_t rows, xo, yo;
+  const double* wt = nullptr;
+  if (dm) {
+    const DevMesh& d = dm[blockIdx.y];
+    rows = rsel == ROWS_EXT ? d.NE : d.N;
+    xo = d.oE * na;
+    yo = d.oE * nb;
+    wt = wsel == WT_MASS ? d.m : (wsel == WT_DIPOLE ? d.mz : nullptr);
+  } else {
+    rows = frows;
+    xo = (int64_t)blockIdx.y * frows * na;
+    yo = (int64_t)blockIdx.y * frows * nb;
+  }
+  X += xo;
+  Y += yo;
+  const int nout = na * nb;
+  double2 acc[16];
+#pragma unroll
+  for (int o = 0; o < 16; ++o) acc[o] = make_double2(0.0, 0.0);
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < rows; i += (int64_t)gridDim.x * NT) {
+    const double w = wt ? gbl(wt)[i] : 1.0;
+#pragma unroll
+    for (int o = 0; o < 16; ++o)
+      if (o < nout) {
+        const int a = o / nb, bb = o - a * nb;
+        const double2 xv = cscale(w, X[i * na + a]), yv = Y[i * nb + bb];
+        acc[o].x += xv.x * yv.x + xv.y * yv.y;
+        acc[o].y += xv.x * yv.y - xv.y * yv.x;
+      }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 0; o < 16; ++o)
+    if (o < nout) {
+      const double sx = wave_sum(acc[o].x), sy = wave_sum(acc[o].y);
+      if (lane == 0) lw[wid][o] = make_double2(sx, sy);
+    }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nout) {
+    double2 t = lw[0][threadIdx.x];
+    for (int w = 1; w < NT / 64; ++w) t = cadd(t, lw[w][threadIdx.x]);
+    part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout + threadIdx.x] = t;
+  }
+}
+
 // out[i][o] = sum_b part[i][b][o]; one workgroup per (output, instance)
 __global__ void __launch_bounds__(NT) k_sum_parts(const double2* __restrict__ part, int nblk, int nout,
                                                   double2* __restrict__ out) {
@@ -409,16 +462,24 @@ int gram_blocks(int64_t rows) { return nblocks(rows, XG_CH, 512); }
 void launch_gram(const Batch& b, const double* A, const double* B, int wsel, int rows, double* part, int nblk,
                  double* G, hipStream_t s) {
   const int n = b.mx.n;
-  hipLaunchKernelGGL(k_xgram, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, wsel, rows, (const double2*)A, n,
-                     (const double2*)B, n, (int64_t)0, (double2*)part);
+  if (n * n <= 16)
+    hipLaunchKernelGGL(k_xgram_small, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, wsel, rows, (const double2*)A, n,
+                       (const double2*)B, n, (int64_t)0, (double2*)part);
+  else
+    hipLaunchKernelGGL(k_xgram, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, wsel, rows, (const double2*)A, n,
+                       (const double2*)B, n, (int64_t)0, (double2*)part);
   hipLaunchKernelGGL(k_sum_parts, dim3(n * n, b.ni), dim3(NT), 0, s, (const double2*)part, nblk, n * n,
                      (double2*)G);
 }
 
 void launch_xgram_flat(int ni, const double* X, int na, const double* Y, int nb, int64_t rows, double* part,
                        int nblk, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_xgram, dim3(nblk, ni), dim3(NT), 0, s, (const DevMesh*)nullptr, 0, 0, (const double2*)X, na,
-                     (const double2*)Y, nb, rows, (double2*)part);
+  if (na * nb <= 16)
+    hipLaunchKernelGGL(k_xgram_small, dim3(nblk, ni), dim3(NT), 0, s, (const DevMesh*)nullptr, 0, 0,
+                       (const double2*)X, na, (const double2*)Y, nb, rows, (double2*)part);
+  else
+    hipLaunchKernelGGL(k_xgram, dim3(nblk, ni), dim3(NT), 0, s, (const DevMesh*)nullptr, 0, 0, (const double2*)X, na,
+                       (const double2*)Y, nb, rows, (double2*)part);
   hipLaunchKernelGGL(k_sum_parts, dim3(na * nb, ni), dim3(NT), 0, s, (const double2*)part, nblk, na * nb,
                      (double2*)out);
 }
@@ -481,6 +542,50 @@ __global__ void __launch_bounds__(NT) k_gint(const DevMesh* __restrict__ dm, con
   }
 }
 
+// The same for n^2 x ncol <= 16 outputs (two orbitals): every thread
+// accumulates all outputs over a grid-stride set of rows, then one reduction
+// per workgroup.
+__global__ void __launch_bounds__(NT) k_gint_small(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
+                                                   const double* __restrict__ W, int ncol,
+                                                   double2* __restrict__ part) {
+  INSTANCE;
+  __shared__ double2 lw[NT / 64][16];
+  const int n = d.n, na = n * n, nout = na * ncol;
+  phi += d.oE * n;
+  W += d.oF * ncol;
+  double2 acc[16];
+#pragma unroll
+  for (int o = 0; o < 16; ++o) acc[o] = make_double2(0.0, 0.0);
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < d.NE; i += (int64_t)gridDim.x * NT) {
+    const double mi = gbl(d.m)[i];
+#pragma unroll
+    for (int o = 0; o < 16; ++o)
+      if (o < nout) {
+        const int a = o / ncol, c = o - a * ncol;
+        const int p = a / n, q = a - p * n;
+        const double2 fp = phi[i * n + p], fq = phi[i * n + q];
+        // phi_p conj(phi_q) m_i, conjugated
+        const double2 xv = cscale(mi, make_double2(fp.x * fq.x + fp.y * fq.y, fp.y * fq.x - fp.x * fq.y));
+        const double yv = W[i * ncol + c];
+        acc[o].x += xv.x * yv;
+        acc[o].y -= xv.y * yv;
+      }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 0; o < 16; ++o)
+    if (o < nout) {
+      const double sx = wave_sum(acc[o].x), sy = wave_sum(acc[o].y);
+      if (lane == 0) lw[wid][o] = make_double2(sx, sy);
+    }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nout) {
+    double2 t = lw[0][threadIdx.x];
+    for (int w = 1; w < NT / 64; ++w) t = cadd(t, lw[w][threadIdx.x]);
+    part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout + threadIdx.x] = t;
+  }
+}
+
 // Assemble g_pqrs from the pair-column integrals G[(p,q)][col].
 __global__ void k_gint_assemble(const double2* __restrict__ G, int n, const int* __restrict__ colmap,
                                 double2* __restrict__ g) {
@@ -506,7 +611,12 @@ int gint_blocks(const Batch& b) { return nblocks(b.mx.NE, XG_CH, 512); }
 void launch_gint_full(const Batch& b, const double* phi, const double* W, const int* colmap, double* part, int nblk,
                       double* Gtmp, double* g, hipStream_t s) {
   const int n = b.mx.n, ncol = n * n;
-  hipLaunchKernelGGL(k_gint, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol, (double2*)part);
+  if (ncol * ncol <= 16)
+    hipLaunchKernelGGL(k_gint_small, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol,
+                       (double2*)part);
+  else
+    hipLaunchKernelGGL(k_gint, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol,
+                       (double2*)part);
   hipLaunchKernelGGL(k_sum_parts, dim3(ncol * ncol, b.ni), dim3(NT), 0, s, (const double2*)part, nblk, ncol * ncol,
                      (double2*)Gtmp);
   hipLaunchKernelGGL(k_gint_assemble, dim3(nblocks(ncol * ncol), b.ni), dim3(NT), 0, s, (const double2*)Gtmp, n,
@@ -923,13 +1033,18 @@ __global__ void __launch_bounds__(NT) k_moments(const DevMesh* __restrict__ dm, 
   for (int64_t base = (int64_t)blockIdx.x * MP_CH; base < rows; base += (int64_t)gridDim.x * MP_CH) {
     const int cnt = (int)((rows - base) < MP_CH ? (rows - base) : MP_CH);
     __syncthreads();
-    if (threadIdx.x < MP_CH) {
-      double* R = sR + threadIdx.x * nh;
-      if ((int)threadIdx.x < cnt) {
-        int64_t i = base + threadIdx.x;
-        solid_regular(d.xyz[3 * i] - cx, d.xyz[3 * i + 1] - cy, d.xyz[3 * i + 2] - cz, lmax, R);
+    // harmonics of the chunk's rows, one (row, order m) per thread
+    for (int w = threadIdx.x; w < MP_CH * (lmax + 1); w += NT) {
+      const int r = w / (lmax + 1), m = w - r * (lmax + 1);
+      double* R = sR + r * nh;
+      if (r < cnt) {
+        const int64_t i = base + r;
+        solid_regular_m(d.xyz[3 * i] - cx, d.xyz[3 * i + 1] - cy, d.xyz[3 * i + 2] - cz, lmax, m, R);
       } else {
-        for (int t = 0; t < nh; ++t) R[t] = 0.0;
+        for (int l = m; l <= lmax; ++l) {
+          R[l * l + m] = 0.0;
+          if (m > 0) R[l * l + l + m] = 0.0;
+        }
       }
     }
     for (int e = threadIdx.x; e < MP_CH * ncol; e += NT) {
