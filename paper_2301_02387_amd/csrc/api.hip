@@ -973,8 +973,7 @@ static int arnoldi(mh_op* op, double* phi, double tau_re, double tau_im, int m, 
     double* w = op->V[k + 1];
     g_apply(op, op->V[k], w, 1, s);
     launch_mdot(B, op->Vdev, k, w, K, 1, s);
-    launch_orth_update(B, op->Vdev, k, w, K, 1, s);
-    launch_mdot(B, op->Vdev, k, w, K, 2, s);
+    launch_orth_dot(B, op->Vdev, k, w, K, s);
     launch_orth_update(B, op->Vdev, k, w, K, 2, s);
     launch_krylov_scale(B, w, w, K, 1, s);
   }

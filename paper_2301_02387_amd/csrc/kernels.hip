@@ -813,6 +813,63 @@ __global__ void __launch_bounds__(NT) k_orth_update(const DevMesh* __restrict__ 
   }
 }
 
+// The first update of CGS2 fused with the second pass's dot products:
+// w -= sum_j V_j hcur_j, then the partials of V_j^H M w (layout of k_mdot,
+// norm slot 0).  KM >= k + 1 sizes the register arrays.
+template <int KM>
+__global__ void __launch_bounds__(NT) k_orth_dot(const DevMesh* __restrict__ dm, const double2* const* __restrict__ V,
+                                                 int k, double2* __restrict__ w, const double2* __restrict__ hcur,
+                                                 int m_max, double* __restrict__ part) {
+  INSTANCE;
+  __shared__ double lw[NT / 64][2 * KM + 1];
+  const int n = d.n;
+  const int64_t total = d.NE * n, o = d.oE * n;
+  hcur += (int64_t)blockIdx.y * (m_max + 1);
+  double2 h[KM];
+  double hr[KM], hi[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    h[j] = (j <= k) ? hcur[j] : make_double2(0.0, 0.0);
+    hr[j] = 0.0;
+    hi[j] = 0.0;
+  }
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    double2 we = w[o + e];
+    double2 vj[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j <= k) {
+        vj[j] = ldg2(V[j], o + e);
+        we = csub(we, cmul(h[j], vj[j]));
+      }
+    w[o + e] = we;
+    const double mi = gbl(d.m)[e / n];
+    const double2 wm = make_double2(mi * we.x, mi * we.y);
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j <= k) {
+        hr[j] += vj[j].x * wm.x + vj[j].y * wm.y;
+        hi[j] += vj[j].x * wm.y - vj[j].y * wm.x;
+      }
+  }
+  const int nv = 2 * (k + 1) + 1;
+  double* pb = part + blockIdx.y * kpart_stride(gridDim.x, m_max) + (int64_t)blockIdx.x * nv;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < KM; ++j)
+    if (j <= k) {
+      const double a = wave_sum(hr[j]), b = wave_sum(hi[j]);
+      if (lane == 0) {
+        lw[wid][2 * j] = a;
+        lw[wid][2 * j + 1] = b;
+      }
+    }
+  if (lane == 0) lw[wid][nv - 1] = 0.0;
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nv)
+    pb[threadIdx.x] = lw[0][threadIdx.x] + lw[1][threadIdx.x] + lw[2][threadIdx.x] + lw[3][threadIdx.x];
+}
+
 // h_{k+1,k} = |w|; happy breakdown when h <= 1e-14 |G v_k| (then scale 0).
 __global__ void k_norm_finish(const double* __restrict__ part, int nblk, int k, int m_max, double2* __restrict__ H,
                               double* __restrict__ scal) {
@@ -840,6 +897,25 @@ void launch_orth_update(const Batch& b, double* const* V, int k, double* w, Kryl
   if (pass == 2)
     hipLaunchKernelGGL(k_norm_finish, dim3(1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, (double2*)K.H,
                        K.scal);
+}
+
+void launch_orth_dot(const Batch& b, double* const* V, int k, double* w, Krylov& K, hipStream_t s) {
+  const dim3 g(K.nblk, b.ni);
+  const auto* Vc = (const double2* const*)V;
+  if (k + 1 <= 4)
+    hipLaunchKernelGGL(k_orth_dot<4>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur, K.m_max,
+                       K.part);
+  else if (k + 1 <= 8)
+    hipLaunchKernelGGL(k_orth_dot<8>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur, K.m_max,
+                       K.part);
+  else if (k + 1 <= 13)
+    hipLaunchKernelGGL(k_orth_dot<13>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur, K.m_max,
+                       K.part);
+  else
+    hipLaunchKernelGGL(k_orth_dot<KMAX>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur,
+                       K.m_max, K.part);
+  hipLaunchKernelGGL(k_mdot_finish, dim3(2 * (k + 1) + 1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, 2,
+                     (double2*)K.H, (double2*)K.hcur, K.scal);
 }
 
 __global__ void k_scale_by(const DevMesh* __restrict__ dm, const double2* __restrict__ src,

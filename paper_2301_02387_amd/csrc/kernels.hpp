@@ -150,6 +150,9 @@ struct Krylov {
 void launch_norm_init(const Batch& b, const double* phi, Krylov& K, int m, hipStream_t s);
 void launch_mdot(const Batch& b, double* const* V, int k, const double* w, Krylov& K, int pass, hipStream_t s);
 void launch_orth_update(const Batch& b, double* const* V, int k, double* w, Krylov& K, int pass, hipStream_t s);
+// The first CGS2 update fused with the second pass's dots (w -= V hcur, then
+// V^H M w finished into H and hcur as the second pass of launch_mdot).
+void launch_orth_dot(const Batch& b, double* const* V, int k, double* w, Krylov& K, hipStream_t s);
 void launch_krylov_scale(const Batch& b, const double* src, double* dst, Krylov& K, int which, hipStream_t s);
 void launch_expm(int ni, Krylov& K, double tau_re, double tau_im, hipStream_t s);
 void launch_combine(const Batch& b, double* const* V, int m, double* phi, Krylov& K, hipStream_t s);
