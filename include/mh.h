@@ -334,6 +334,23 @@ int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap);
 
 const char* mh_last_error(void);
 
+/* Device workspace allocator.  The library's own device buffers (operator
+ * tables, Krylov bases, CG and multigrid workspaces, adjoint scratch) come
+ * from hipMalloc / hipFree unless an allocator is registered, e.g. a
+ * framework's caching allocator, so that the library shares its memory pool.
+ * alloc_fn(bytes, ctx) returns device memory of at least `bytes` bytes,
+ * aligned to 256 bytes, or NULL on failure (the call that needed it then
+ * returns MH_OOM); free_fn(ptr, bytes, ctx) returns it.  The registration is
+ * process-wide and applies to allocations made after it; every buffer
+ * records the pair that made it and is returned to that pair (on *_destroy,
+ * or when a workspace is regrown), so the functions and ctx must stay valid
+ * until every handle created while they were registered is destroyed.  Both
+ * NULL restores hipMalloc / hipFree; exactly one NULL is MH_INVALID_ARG.  Not
+ * to be called while another thread creates or runs a handle. */
+typedef void* (*mh_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*mh_free_fn)(void* ptr, size_t bytes, void* ctx);
+int mh_set_allocator(mh_alloc_fn alloc_fn, mh_free_fn free_fn, void* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,7 +7,7 @@ every computation runs in the library's HIP kernels.  There is no CPU
 fallback: importing works without a GPU, but every call needs the built
 library and a GPU.
 """
-from ._lib import (Mesh, Operator, MHError, lib_path, load_library,  # noqa: F401
+from ._lib import (Mesh, Operator, MHError, lib_path, load_library, set_allocator,  # noqa: F401
                    MH_OK, MH_NOT_CONVERGED)
 
-__all__ = ["Mesh", "Operator", "MHError", "lib_path", "load_library"]
+__all__ = ["Mesh", "Operator", "MHError", "lib_path", "load_library", "set_allocator"]

@@ -13,7 +13,7 @@ EXPORTS = ["mh_mesh_create", "mh_mesh_info_get", "mh_mesh_node_coords", "mh_mesh
            "mh_mesh_destroy", "mh_op_create", "mh_op_destroy", "mh_fill_hanging", "mh_mass_solve",
            "mh_h1_apply", "mh_poisson_pairs", "mh_ci_rdms", "mh_freeze", "mh_rhs_apply",
            "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_tune",
-           "mh_propagate_adjoint", "mh_batch_create", "mh_batch_layout", "mh_last_error"]
+           "mh_propagate_adjoint", "mh_batch_create", "mh_batch_layout", "mh_set_allocator", "mh_last_error"]
 
 
 class MHError(RuntimeError):
@@ -104,11 +104,54 @@ def load_library():
                                          C.c_int32, C.c_int32, vp]
     lib.mh_batch_create.argtypes = [vp, vp, vp, C.c_int32, vp, C.POINTER(vp)]
     lib.mh_batch_layout.argtypes = [vp, vp]
+    lib.mh_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     for name in EXPORTS:
         if name != "mh_last_error":
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+_ALLOCATORS = []    # every registered pair of callbacks, kept alive for the handles that use them
+
+
+def set_allocator(alloc=None, free=None):
+    """Register the device allocator of the library's own workspaces
+    (mh_set_allocator): alloc(nbytes) -> int device address (0 on failure),
+    free(address, nbytes).  alloc="torch" takes torch's caching allocator on
+    the current device and stream.  No arguments restore hipMalloc/hipFree.
+    Handles return their buffers to the functions that made them, so every
+    pair registered stays referenced for the life of the process."""
+    lib = load_library()
+    if alloc is None and free is None:
+        _check(lib.mh_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        return
+    if alloc == "torch":
+        import torch
+
+        def alloc(nbytes):
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+        def free(ptr, nbytes):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+    def _a(nbytes, ctx):
+        try:
+            return int(alloc(nbytes)) or None
+        except Exception:   # reported to the library as a failed allocation
+            return None
+
+    def _f(ptr, nbytes, ctx):
+        try:
+            free(ptr, nbytes)
+        except Exception:   # nothing to report from a release
+            pass
+
+    cbs = (_ALLOC_FN(_a), _FREE_FN(_f))
+    _ALLOCATORS.append(cbs)
+    _check(lib.mh_set_allocator(cbs[0], cbs[1], None))
 
 
 def _check(rc, allow_nc=False):

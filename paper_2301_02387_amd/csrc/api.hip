@@ -31,6 +31,44 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// Device buffers: from the registered allocator (mh_set_allocator) or
+// hipMalloc; each remembers the pair that made it.
+struct AllocHook {
+  mh_alloc_fn alloc = nullptr;
+  mh_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+AllocHook g_hook;
+struct DevBlock {
+  void* p = nullptr;
+  size_t bytes = 0;
+  AllocHook hook;
+};
+DevBlock dev_alloc(size_t bytes) {
+  DevBlock b;
+  b.bytes = bytes;
+  b.hook = g_hook;
+  if (b.hook.alloc) {
+    b.p = b.hook.alloc(bytes, b.hook.ctx);
+    if (!b.p) {
+      g_alloc_detail = "registered allocator (" + std::to_string(bytes) + " bytes)";
+      throw std::bad_alloc();
+    }
+  } else {
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      g_alloc_detail = "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e);
+      throw std::bad_alloc();
+    }
+  }
+  return b;
+}
+void dev_free(const DevBlock& b) {
+  if (!b.p) return;
+  if (b.hook.free) b.hook.free(b.p, b.bytes, b.hook.ctx);
+  else (void)hipFree(b.p);
+}
+
 struct HipError {
   hipError_t e;
   const char* what;
@@ -55,7 +93,7 @@ struct mh_op {
   std::vector<DevMesh> dh;     // host copies of the device instance records
   DevMesh* dm = nullptr;       // device [ni]
   Batch B;
-  std::vector<void*> allocs;
+  std::vector<DevBlock> allocs;
   int n = 0, ncol = 0, lmax = 12;
   double rtol = 1e-12, rdm_eps = 1e-10;
   int maxit = 5000;
@@ -111,15 +149,17 @@ struct mh_op {
 
   template <class T>
   T* alloc(size_t count) {
-    void* p = nullptr;
-    size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      g_alloc_detail = "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e);
-      throw std::bad_alloc();
-    }
-    allocs.push_back(p);
-    return (T*)p;
+    const DevBlock b = dev_alloc(std::max<size_t>(count * sizeof(T), 16));
+    allocs.push_back(b);
+    return (T*)b.p;
+  }
+  void release(void* p) {  // one buffer back to the allocator that made it
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i].p == p) {
+        dev_free(allocs[i]);
+        allocs.erase(allocs.begin() + i);
+        return;
+      }
   }
   template <class T>
   T* upload(const std::vector<T>& v, hipStream_t s) {
@@ -128,7 +168,8 @@ struct mh_op {
     return p;
   }
   ~mh_op() {
-    for (void* p : allocs) (void)hipFree(p);
+    (void)hipDeviceSynchronize();  // no kernel still uses a buffer handed back
+    for (const DevBlock& b : allocs) dev_free(b);
     for (int k = 0; k < 2; ++k)
       for (hipEvent_t e : ev[k]) (void)hipEventDestroy(e);
     if (hostpin) (void)hipHostFree(hostpin);
@@ -158,6 +199,14 @@ static int guarded(F&& f) {
 }
 
 extern "C" const char* mh_last_error(void) { return g_err.c_str(); }
+
+extern "C" int mh_set_allocator(mh_alloc_fn alloc_fn, mh_free_fn free_fn, void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) return fail(MH_INVALID_ARG, "give both allocator functions or neither");
+  g_hook.alloc = alloc_fn;
+  g_hook.free = free_fn;
+  g_hook.ctx = alloc_fn ? ctx : nullptr;
+  return MH_OK;
+}
 
 // ------------------------------------------------------------------ mesh ----
 extern "C" int mh_mesh_create(const mh_mesh_desc* desc, mh_mesh** out) {
@@ -944,9 +993,7 @@ static int freeze(mh_op* op, const double* phi, const double* gamma, const doubl
 static void ensure_krylov(mh_op* op, int m) {
   if (op->m_alloc >= m) return;
   for (double* p : op->V) {
-    auto it = std::find(op->allocs.begin(), op->allocs.end(), (void*)p);
-    if (it != op->allocs.end()) op->allocs.erase(it);
-    (void)hipFree(p);
+    op->release(p);
   }
   op->V.clear();
   const size_t len = (size_t)2 * op->B.tE * op->n;
@@ -1363,15 +1410,14 @@ static void mass_load(mh_op* op, const double* f, double* out, hipStream_t s) {
 
 namespace {
 struct DevScratch {
-  std::vector<void*> p;
+  std::vector<DevBlock> p;
   double* get(size_t nd) {
-    void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(nd, 2) * sizeof(double)) != hipSuccess) throw std::bad_alloc();
-    p.push_back(q);
-    return (double*)q;
+    p.push_back(dev_alloc(std::max<size_t>(nd, 2) * sizeof(double)));
+    return (double*)p.back().p;
   }
   ~DevScratch() {
-    for (void* q : p) (void)hipFree(q);
+    (void)hipDeviceSynchronize();
+    for (const DevBlock& b : p) dev_free(b);
   }
 };
 }  // namespace

@@ -61,6 +61,16 @@ def test_h2o_mesh_counts():
     assert M.info["n_dof"] == 1517876
 
 
+def test_allocator_registration_arguments():
+    """mh_set_allocator takes both functions or neither (no GPU work)."""
+    mh, lib = _lib()
+    from paper_2301_02387_amd._lib import _ALLOC_FN, _FREE_FN
+    keep = _ALLOC_FN(lambda nbytes, ctx: None)
+    assert lib.mh_set_allocator(keep, _FREE_FN(), None) == -1
+    assert "both" in lib.mh_last_error().decode()
+    assert lib.mh_set_allocator(_ALLOC_FN(), _FREE_FN(), None) == 0
+
+
 def test_error_paths():
     mh, _ = _lib()
     with pytest.raises(mh.MHError) as e:
