@@ -65,12 +65,17 @@ def test_layout_is_concatenation():
     assert len(set(lay[:, 0])) == len(SEEDS)  # uneven sizes
 
 
-@pytest.mark.parametrize("imag,steps", [(False, 3), (True, 2)])
-def test_batch_propagate_matches_oracle(imag, steps):
+@pytest.mark.parametrize("imag,steps,orb,poi", [(False, 3, 1, 13), (True, 2, 1, 13), (False, 3, 4, 53)])
+def test_batch_propagate_matches_oracle(imag, steps, orb, poi):
+    """Each instance of the batch against the oracle on its own mesh, with the
+    default schedules and with those the batch bench tunes to (assembled
+    orbital stiffness; multigrid CG with sliced-ELL rows)."""
     torch = _torch()
     from oracle.ci import CISpace
     from oracle.mctdhf import Propagator
     pairs, op = batch_case()
+    op.tune(0, orb, 65536)
+    op.tune(1, poi, 8192 if poi == 13 else 1024)
     w = pairs[0].w
     n = w["n_orb"]
     cs_space = CISpace(n, w["n_alpha"], w["n_beta"])
@@ -99,6 +104,8 @@ def test_batch_propagate_matches_oracle(imag, steps):
         oE, NE = lay[i, 3], lay[i, 1]
         assert rel_err_cols(P.from_lib_dof(xh[oE:oE + NE]), cc) < 1e-8, i
         assert np.max(np.abs(Ch[i] - CC)) < 1e-8, i
+    op.tune(0, 1, 65536)
+    op.tune(1, 13, 8192)
 
 
 def test_batch_multigrid_poisson():

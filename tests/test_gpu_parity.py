@@ -225,11 +225,13 @@ def test_arnoldi_step(name, tau):
 
 @pytest.mark.parametrize("name,steps,imag,sched", [("h_atom", 4, False, 13), ("tiny_q3", 4, False, 13),
                                                    ("small_n3", 3, False, 13), ("tiny_q3", 3, True, 13),
-                                                   ("tiny_q3", 4, False, 21), ("small_n3", 3, False, 20)])
+                                                   ("tiny_q3", 4, False, 21), ("small_n3", 3, False, 20),
+                                                   ("tiny_q3", 4, False, 53), ("small_n3", 3, False, 52)])
 def test_propagate_observables(name, steps, imag, sched):
     """Propagated dipoles, energies, orbitals and CI vectors against the
     oracle, with the default schedules (Poisson 13) and with the multigrid
-    preconditioner (Poisson 20, 21) and the assembled orbital stiffness."""
+    preconditioner (Poisson 20, 21; with the sliced-ELL rows 52, 53) and the
+    assembled orbital stiffness."""
     torch = _torch()
     from oracle.ci import CISpace
     from oracle.mctdhf import Propagator
