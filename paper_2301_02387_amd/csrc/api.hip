@@ -138,6 +138,7 @@ struct mh_op {
   double* obs = nullptr;    // [ni][8]
   double* Rinv = nullptr;
   double* Wprev = nullptr;  // [tF][n*n] potentials of the previous step (start extrapolation)
+  double* Wprev2 = nullptr; // [tF][n*n] and of the step before
   double* hostpin = nullptr;
   size_t hostpin_len = 0;
   hipStream_t gstream = nullptr;  // stream for graph capture and replay
@@ -1212,11 +1213,18 @@ extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const
       const double E = (n_steps > 0 || E_steps) ? E_steps[step] : 0.0;
       launch_ci_rdm_full(ni, op->ci, Ci, op->gam, op->Gam, op->Gtmp, s);
       int it = 0;
-      // CG start: the previous solution, then (from the third step of the call)
-      // the linear extrapolation 2 W_{n-1} - W_{n-2}; Wprev keeps W_{n-1}
+      // CG start: the previous solution; at the third step of the call the
+      // linear extrapolation 2 W_{n-1} - W_{n-2}, from the fourth the quadratic
+      // 3 W_{n-1} - 3 W_{n-2} + W_{n-3} (Wprev, Wprev2 keep W_{n-2}, W_{n-3})
       const int64_t wlen = (int64_t)op->B.tF * op->ncol;
       if (step == 0 && !op->Wprev) op->Wprev = op->alloc<double>((size_t)wlen);
-      if (step >= 2) launch_extrapolate(W, op->Wprev, wlen, s);
+      if (step == 0 && !op->Wprev2) op->Wprev2 = op->alloc<double>((size_t)wlen);
+      if (step == 2) {
+        launch_copy(op->Wprev, op->Wprev2, wlen, s);
+        launch_extrapolate(W, op->Wprev, wlen, s);
+      } else if (step >= 3) {
+        launch_extrapolate2(W, op->Wprev, op->Wprev2, wlen, s);
+      }
       int rc = poisson_solve(op, phi, W, 1, &it, s);
       if (step == 0) launch_copy(W, op->Wprev, wlen, s);  // W_0; step 1 starts from W_0 and keeps it
       if (rc < 0) return rc;

@@ -317,6 +317,18 @@ __global__ void k_extrapolate(double* __restrict__ x, double* __restrict__ xp, i
 void launch_extrapolate(double* x, double* xprev, int64_t nd, hipStream_t s) {
   if (nd > 0) hipLaunchKernelGGL(k_extrapolate, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, x, xprev, nd);
 }
+// x <- 3 x - 3 p1 + p2 (quadratic extrapolation in time), then p2 <- p1, p1 <- the old x
+__global__ void k_extrapolate2(double* __restrict__ x, double* __restrict__ p1, double* __restrict__ p2, int64_t nd) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nd; i += (int64_t)gridDim.x * NT) {
+    const double xi = x[i], a = p1[i];
+    x[i] = 3.0 * (xi - a) + p2[i];
+    p2[i] = a;
+    p1[i] = xi;
+  }
+}
+void launch_extrapolate2(double* x, double* p1, double* p2, int64_t nd, hipStream_t s) {
+  if (nd > 0) hipLaunchKernelGGL(k_extrapolate2, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, x, p1, p2, nd);
+}
 void launch_set(double* out, double value, hipStream_t s) {
   hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, out, value);
 }

@@ -119,6 +119,8 @@ void launch_zero(double* out, int64_t nd, hipStream_t s);
 void launch_set(double* out, double value, hipStream_t s);
 // x <- 2 x - xprev and xprev <- the old x (linear extrapolation in time) over nd doubles
 void launch_extrapolate(double* x, double* xprev, int64_t nd, hipStream_t s);
+// x <- 3 x - 3 p1 + p2 (quadratic extrapolation in time), then p2 <- p1 and p1 <- the old x
+void launch_extrapolate2(double* x, double* p1, double* p2, int64_t nd, hipStream_t s);
 
 // ---- reductions (segmented per instance) -----------------------------------------
 enum { ROWS_DOF = 0, ROWS_EXT = 1 };
