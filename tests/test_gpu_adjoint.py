@@ -126,12 +126,17 @@ def _mctdhf_setup(name, seed, steps, **kw):
     return P, cs, c, C, phi0, C0, E
 
 
-@pytest.mark.parametrize("name,steps", [("tiny_q1", 5), ("small_n3", 3)])
-def test_mctdhf_adjoint_matches_oracle_autodiff(name, steps):
+@pytest.mark.parametrize("name,steps,sched", [("tiny_q1", 5, None), ("small_n3", 3, None), ("small_n3", 3, (4, 53))])
+def test_mctdhf_adjoint_matches_oracle_autodiff(name, steps, sched):
     """Several orbitals, mean field, CI: the GPU adjoint against reverse-mode
-    autodiff of the oracle's propagation (same start, fields and dt)."""
+    autodiff of the oracle's propagation (same start, fields and dt); with the
+    default schedules, and with the assembled orbital stiffness and the
+    multigrid CG on sliced-ELL rows (forward and adjoint Poisson solves)."""
     from oracle.adjoint import dipole_gradient
     P, cs, c, C, phi0, C0, E = _mctdhf_setup(name, 6, steps)
+    if sched:
+        P.op.tune(0, sched[0], 65536)
+        P.op.tune(1, sched[1], 8192)
     wts = np.random.default_rng(3).standard_normal(len(E))
     d_ref, g_ref = dipole_gradient(P.ops, cs, c, C, E, DT, wts, m=12)
     d = _dipoles(P, phi0, C0, E)
