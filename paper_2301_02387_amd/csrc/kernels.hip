@@ -1382,10 +1382,13 @@ void launch_poisson_rhs_full(const Batch& b, const double* phi, double* W, const
 // Small dense kernels (one workgroup per instance, work on thread 0).
 // =====================================================================
 // Regularised inverse of the Hermitian 1-RDM: eigen-decomposition of the
-// real 2n x 2n embedding [[Re, -Im], [Im, Re]] by cyclic Jacobi, d -> d +
+// real 2n x 2n embedding [[Re, -Im], [Im, Re]] by Jacobi rotations, d -> d +
 // eps exp(-d/eps), inverse from the eigenpairs.  One wave per instance with
-// the matrices in LDS: the rotations are applied in order, the lanes taking
-// the row (or column) index of each one's updates.
+// the matrices in LDS.  Each sweep runs 2n - 1 rounds of n disjoint pivot
+// pairs (the round-robin ordering): the pairs' angles come from the entries
+// at the start of the round, then all column rotations (of A and of the
+// eigenvector matrix) and all row rotations are applied at once.  Disjoint
+// rotations commute, so a round is the same as those rotations in sequence.
 __device__ __forceinline__ double wave_sum_xor(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);  // every lane gets the same total
   return v;
@@ -1393,11 +1396,13 @@ __device__ __forceinline__ double wave_sum_xor(double v) {
 __global__ void __launch_bounds__(64) k_ginv(const double2* __restrict__ gamma, int n, double eps,
                                              double2* __restrict__ ginv, int* __restrict__ flag) {
   __shared__ double a[16 * 16], V[16 * 16], dinv[16];
+  __shared__ double rc[8], rs[8];
+  __shared__ int rp[8], rq[8];
   __shared__ int badk[16];
   const int inst = blockIdx.x, lane = threadIdx.x;
   gamma += (int64_t)inst * n * n;
   ginv += (int64_t)inst * n * n;
-  const int N2 = 2 * n;
+  const int N2 = 2 * n, npair = n, m = N2 - 1;
   for (int e = lane; e < n * n; e += 64) {
     const int i = e / n, j = e - i * n;
     // Hermitian part
@@ -1420,34 +1425,47 @@ __global__ void __launch_bounds__(64) k_ginv(const double2* __restrict__ gamma, 
     off = wave_sum_xor(off);
     tot = wave_sum_xor(tot);
     if (off <= 1e-32 * tot) break;
-    for (int p = 0; p < N2; ++p)
-      for (int q = p + 1; q < N2; ++q) {
+    for (int r = 0; r < m; ++r) {
+      if (lane < npair) {
+        // pair `lane` of round r: (N2 - 1, r) for lane 0, else (r + lane, r - lane) mod m
+        int p = lane == 0 ? r : (r + lane) % m, q = lane == 0 ? N2 - 1 : (r - lane + m) % m;
+        if (p > q) { const int t = p; p = q; q = t; }
         const double apq = a[p * N2 + q];
-        if (fabs(apq) < 1e-300) continue;
-        const double theta = (a[q * N2 + q] - a[p * N2 + p]) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
-        __syncthreads();  // every lane has read the pivot entries
-        if (lane < N2) {  // columns p, q of a
-          const int k = lane;
-          const double akp = a[k * N2 + p], akq = a[k * N2 + q];
-          a[k * N2 + p] = c * akp - sn * akq;
-          a[k * N2 + q] = sn * akp + c * akq;
-        } else if (lane >= 32 && lane < 32 + N2) {  // columns p, q of V
-          const int k = lane - 32;
-          const double vkp = V[k * N2 + p], vkq = V[k * N2 + q];
-          V[k * N2 + p] = c * vkp - sn * vkq;
-          V[k * N2 + q] = sn * vkp + c * vkq;
+        double c = 1.0, sn = 0.0;
+        if (fabs(apq) >= 1e-300) {
+          const double theta = (a[q * N2 + q] - a[p * N2 + p]) / (2.0 * apq);
+          const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sn = t * c;
         }
-        __syncthreads();
-        if (lane < N2) {  // rows p, q of a
-          const int k = lane;
-          const double apk = a[p * N2 + k], aqk = a[q * N2 + k];
-          a[p * N2 + k] = c * apk - sn * aqk;
-          a[q * N2 + k] = sn * apk + c * aqk;
-        }
-        __syncthreads();
+        rp[lane] = p;
+        rq[lane] = q;
+        rc[lane] = c;
+        rs[lane] = sn;
       }
+      __syncthreads();
+      for (int w = lane; w < npair * N2; w += 64) {  // columns p, q of a and V
+        const int k = w / N2, i = w - k * N2;
+        const int p = rp[k], q = rq[k];
+        const double c = rc[k], sn = rs[k];
+        const double aip = a[i * N2 + p], aiq = a[i * N2 + q];
+        a[i * N2 + p] = c * aip - sn * aiq;
+        a[i * N2 + q] = sn * aip + c * aiq;
+        const double vip = V[i * N2 + p], viq = V[i * N2 + q];
+        V[i * N2 + p] = c * vip - sn * viq;
+        V[i * N2 + q] = sn * vip + c * viq;
+      }
+      __syncthreads();
+      for (int w = lane; w < npair * N2; w += 64) {  // rows p, q of a
+        const int k = w / N2, j = w - k * N2;
+        const int p = rp[k], q = rq[k];
+        const double c = rc[k], sn = rs[k];
+        const double apj = a[p * N2 + j], aqj = a[q * N2 + j];
+        a[p * N2 + j] = c * apj - sn * aqj;
+        a[q * N2 + j] = sn * apj + c * aqj;
+      }
+      __syncthreads();
+    }
   }
   if (lane < N2) {
     const double dk = a[lane * N2 + lane];
