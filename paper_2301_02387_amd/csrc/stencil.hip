@@ -49,6 +49,8 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
                                                     const double2* __restrict__ kq) {
   INSTANCE;
   constexpr int P3 = P * P * P;
+  // per wave: the packed mean-field matrices of its 64 / L nodes (at most 64 doubles each)
+  __shared__ double sU[NT / 64][512];
   const int n = d.n;
   const int64_t o = d.oE * n;
   u += o;
@@ -108,8 +110,18 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
       y.y += dg * ui.y;
     }
     if (diag_mode == 2) {
-      // z_p = sum_q U_pq u_q (U Hermitian, packed: Up[o][q] = Re U_oq, Up[q][o] = Im U_oq for o < q)
-      const double* Up = Upk + i * n * n;
+      // z_p = sum_q U_pq u_q (U Hermitian, packed: Up[o][q] = Re U_oq, Up[q][o] = Im U_oq for o < q).
+      // The node's n^2 packed values are read by its L lanes in consecutive
+      // words and staged in the wave's LDS slice, where each lane then finds
+      // the entries of its row and column.
+      double* Up = &sU[threadIdx.x >> 6][((threadIdx.x & 63) / L) * (n * n)];
+      {
+        const auto* Ug = gbl(Upk) + i * n * n;
+        for (int f = (int)(threadIdx.x & (L - 1)); f < n * n; f += L) Up[f] = Ug[f];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       double2 z = make_double2(0.0, 0.0);
       for (int q = 0; q < n; ++q) {
         const double2 uq = make_double2(__shfl(ui.x, q, L), __shfl(ui.y, q, L));
@@ -121,6 +133,7 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
           z = cadd(z, cmul(Upq, uq));
         }
       }
+      __builtin_amdgcn_wave_barrier();  // the slice is rewritten for the wave's next nodes
       double2 wv = make_double2(0.0, 0.0);
       for (int oo = 0; oo < n; ++oo) {
         const double2 zo = make_double2(__shfl(z.x, oo, L), __shfl(z.y, oo, L));

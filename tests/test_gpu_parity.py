@@ -169,7 +169,7 @@ def _frozen(P, c, C, E):
     return fr, cs
 
 
-@pytest.mark.parametrize("name", SMALL + ["h2"])
+@pytest.mark.parametrize("name", SMALL + ["h2", "tiny_n8"])
 def test_rhs_apply(name):
     """G applied to a random packed vector: interface mass block solved by the
     dense inverse (the default for one small instance) and by Chebyshev, the
