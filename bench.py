@@ -135,7 +135,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: the whole mesh lives on one MI355X; "
+        print("bench.py runs on one GPU only: the whole mesh lives on one MI355X; "
               "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
     if args.counters:
