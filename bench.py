@@ -315,23 +315,26 @@ def run_counters(args):
     import torch
     import paper_2301_02387_amd as mh
     from synth import h2_guess, h2o_guess, random_ci
-    w = _workload(args.workload)
-    mesh = mh.Mesh.from_workload(w)
-    op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_maxit=24)
-    xyz = mesh.coords()[:op.n_ext]
-    c = h2o_guess(xyz) if args.workload == "h2o" else h2_guess(xyz, 0.7)
-    phi = torch.from_numpy(np.ascontiguousarray(c)).cuda()
-    op.fill_hanging(phi)
+    if args.workload == "h2x64":
+        _, _, op, _, phi, _ = batch_setup(args, maxit=24)
+    else:
+        w = _workload(args.workload)
+        mesh = mh.Mesh.from_workload(w)
+        op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_maxit=24)
+        xyz = mesh.coords()[:op.n_ext]
+        c = h2o_guess(xyz) if args.workload == "h2o" else h2_guess(xyz, 0.7)
+        phi = torch.from_numpy(np.ascontiguousarray(c)).cuda()
+        op.fill_hanging(phi)
     if args.tune_cache:   # the schedules the bench run tuned for this workload
         from paper_2301_02387_amd.tune import apply_cached
         log(f"schedules from the cache: {apply_cached(op, args.tune_cache)}")
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     it, _ = op.poisson_pairs(phi, W)
     log(f"cg iterations {it}")
-    n = op.n_orb
-    C = torch.from_numpy(random_ci(op.n_ci, 3)).cuda()
-    g = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
-    G = torch.zeros((n,) * 4, dtype=torch.complex128, device="cuda")
+    n, ni = op.n_orb, op.n_inst
+    C = torch.from_numpy(np.stack([random_ci(op.n_ci, 3)] * ni)).cuda()
+    g = torch.zeros((ni, n, n), dtype=torch.complex128, device="cuda")
+    G = torch.zeros((ni,) + (n,) * 4, dtype=torch.complex128, device="cuda")
     op.ci_rdms(C, g, G)
     op.freeze(phi, g, G, 0.01, W)
     out = torch.empty_like(phi)
@@ -346,20 +349,19 @@ def run_counters(args):
     log("counters run done")
 
 
-def run_batch(args):
-    """64 uneven H2 instances in one batch against 64 sequential plain runs."""
+def batch_setup(args, maxit=20000):
+    """The uneven H2 instances of the batch workload, their batched operator
+    and the sigma_g / sigma_u start of every instance."""
     import numpy as np
     import torch
     import paper_2301_02387_amd as mh
-    from synth import batch_instances, h2_guess, h2_ci_guess, pulse
-    from paper_2301_02387_amd.tune import autotune
-
+    from synth import batch_instances, h2_guess
     ws = batch_instances(args.batch, seed=2301)
     w0 = ws[0]
     t_setup = time.perf_counter()
     meshes = [mh.Mesh.from_workload(w) for w in ws]
     op = mh.Operator.batch(meshes, [w["nuclei"] for w in ws], w0["n_orb"], w0["n_alpha"], w0["n_beta"],
-                           field_scale=[w["E0"] for w in ws], poisson_rtol=1e-12, poisson_maxit=20000)
+                           field_scale=[w["E0"] for w in ws], poisson_rtol=1e-12, poisson_maxit=maxit)
     t_setup = time.perf_counter() - t_setup
     lay = op.layout()
     log(f"batch of {op.n_inst} set up in {t_setup:.1f} s: {op.n_dof} DoF in total")
@@ -371,6 +373,19 @@ def run_batch(args):
 
     phi = torch.from_numpy(np.ascontiguousarray(np.concatenate([guess(i, m) for i, m in enumerate(meshes)]))).cuda()
     op.fill_hanging(phi)
+    return ws, meshes, op, lay, phi, t_setup
+
+
+def run_batch(args):
+    """64 uneven H2 instances in one batch against 64 sequential plain runs."""
+    import numpy as np
+    import torch
+    import paper_2301_02387_amd as mh
+    from synth import h2_ci_guess, pulse
+    from paper_2301_02387_amd.tune import autotune
+
+    ws, meshes, op, lay, phi, t_setup = batch_setup(args)
+    w0 = ws[0]
     Ci = torch.from_numpy(np.stack([h2_ci_guess()] * op.n_inst)).cuda()
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     dt, m, cycles = w0["dt"], w0["krylov"], w0["cycles"]
@@ -478,7 +493,10 @@ def run_batch(args):
                      "tuning_ms": sched.get("timings_ms")},
         "kernels": kern,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": byts},
+                     "frac": ach / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, f"h2x{op.n_inst}_q3_{op.n_dof}dof_{op.n_orb}orb",
+                                                 schedule="/".join(map(str, sched["poisson"]))),
+                     "schedule": "/".join(map(str, sched["poisson"])), "algorithmic_bytes_per_launch": byts},
         "roofline_orbital": {"kernel": "stencil_orb", "bound": "hbm",
                              "achieved": (orb_bytes / (k_orb[0] * 1e-3) / 1e9) if k_orb[0] > 0 else 0.0,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -167,12 +167,14 @@ int mh_poisson_pairs(mh_op* op, const double* phi, double* W, int32_t warm, int3
 /* Reduced density matrices of a CI vector (Sec. II, spin-summed):
  * gamma_pq = <E_pq>, Gamma_pq,rs = <E_pq E_rs> - delta_qr gamma_ps.
  * Ci: device c128 [N_CI] (alpha-string major, strings ordered by bit mask);
- * gamma: device c128 [n][n]; Gamma: device c128 [n][n][n][n]. */
+ * gamma: device c128 [n][n]; Gamma: device c128 [n][n][n][n].  On a batch
+ * handle each is one such block per instance ([n_inst][...]). */
 int mh_ci_rdms(mh_op* op, const double* Ci, double* gamma, double* Gamma, void* stream);
 
 /* Freeze G at t_n (Eqs. orb_eom, discretized_eom, packed_orb_eom with X = 0):
- * takes orbitals phi (device c128 [N_E][n]), RDMs (device c128, as above),
- * the field value E and pair potentials W (device, layout of
+ * takes orbitals phi (device c128 [N_E][n]), RDMs (device c128, as above,
+ * one block per instance on a batch handle), the field value E (times each
+ * instance's field scale) and pair potentials W (device, layout of
  * mh_poisson_pairs); builds U_oq(x) = sum_rs Gamma_oq,rs W_rs(x), the
  * regularised gamma^{-1} and lam_qp = phi_q^H F_p(phi).  The frozen operator
  * is held by `op` until the next freeze.  MH_SINGULAR_RDM if gamma is not
