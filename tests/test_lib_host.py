@@ -79,3 +79,80 @@ def test_error_paths():
     with pytest.raises(mh.MHError) as e:
         mh.Mesh(1, -1, 2, 2, [])
     assert e.value.code == -1
+
+
+def test_argument_errors_before_device_work():
+    """Every entry point rejects a missing handle or a bad descriptor with its
+    documented status before any device call (so this runs without a GPU):
+    null handles give MH_INVALID_ARG (-1), out-of-range orbital counts and
+    boundary orders MH_UNSUPPORTED (-6), inconsistent batches MH_INVALID_ARG."""
+    import ctypes as C
+    from synth import small_workload
+    from paper_2301_02387_amd._lib import _OpDesc, _op_desc, _Sizes
+    mh, lib = _lib()
+    INVALID, UNSUP = -1, -6
+    d = C.c_double(0.0)
+    i32 = C.c_int32(0)
+    i64 = C.c_int64(0)
+    # op entry points with no handle
+    assert lib.mh_fill_hanging(None, None, None) == INVALID
+    assert lib.mh_mass_solve(None, None, None, None) == INVALID
+    assert lib.mh_h1_apply(None, None, 0.0, None, None) == INVALID
+    assert lib.mh_poisson_pairs(None, None, None, 0, C.byref(i32), None) == INVALID
+    assert lib.mh_ci_rdms(None, None, None, None, None) == INVALID
+    assert lib.mh_freeze(None, None, None, None, 0.0, None, None) == INVALID
+    assert lib.mh_rhs_apply(None, None, None, None) == INVALID
+    assert lib.mh_arnoldi_step(None, None, 0.01, 0.0, 8, C.byref(d), C.byref(i32), None) == INVALID
+    assert lib.mh_propagate(None, None, None, None, None, 1, 0.01, 8, 0, None, None) == INVALID
+    assert lib.mh_propagate_adjoint(None, None, None, None, None, 1, 0.01, 8, None, None, 2, 0, None) == INVALID
+    assert lib.mh_op_sizes_get(None, C.byref(_Sizes())) == INVALID
+    assert lib.mh_batch_layout(None, None) == INVALID
+    assert lib.mh_kernel_timing(None, 0, 1, C.byref(d), C.byref(i64)) == INVALID
+    assert lib.mh_tune(None, 1, 13, 8192) == INVALID
+    assert lib.mh_op_destroy(None) == 0
+    # mesh entry points with no handle
+    assert lib.mh_mesh_info_get(None, None) == INVALID
+    assert lib.mh_mesh_node_coords(None, None) == INVALID
+    assert lib.mh_mesh_constraints(None, None, None, None) == INVALID
+    assert lib.mh_mesh_destroy(None) == 0
+    # descriptors rejected before the operator is built
+    w = small_workload("tiny_q3", 0)
+    M = mh.Mesh.from_workload(w)
+    h = C.c_void_p()
+
+    def desc(**kw):
+        args = dict(nuclei=w["nuclei"], n_orb=w["n_orb"], n_alpha=w["n_alpha"], n_beta=w["n_beta"],
+                    polarization=(0.0, 0.0, 1.0), lmax_bc=12, poisson_rtol=1e-12, poisson_maxit=100, rdm_eps=1e-10)
+        args.update(kw)
+        return _op_desc(**args)
+
+    assert lib.mh_op_create(None, C.byref(desc()[0]), None, C.byref(h)) == INVALID
+    for kw, code in [(dict(n_orb=9), UNSUP), (dict(n_orb=0), UNSUP), (dict(lmax_bc=13), UNSUP),
+                     (dict(n_alpha=w["n_orb"] + 1), INVALID), (dict(n_alpha=0, n_beta=0), INVALID),
+                     (dict(n_beta=-1), INVALID)]:
+        dd, keep = desc(**kw)
+        assert lib.mh_op_create(M._h, C.byref(dd), None, C.byref(h)) == code, kw
+        assert lib.mh_last_error()
+    dd, keep = desc()
+    dd.charges = C.POINTER(C.c_double)()  # nuclei announced, charges missing
+    assert lib.mh_op_create(M._h, C.byref(dd), None, C.byref(h)) == INVALID
+    # batches: empty, too many, a null mesh, instances that disagree
+    w1 = small_workload("tiny_q1", 0)
+    M1 = mh.Mesh.from_workload(w1)
+    d0, k0 = desc()
+    d9, k9 = desc(n_orb=w["n_orb"] + 1, n_alpha=w["n_alpha"], n_beta=w["n_beta"])
+    d1, k1 = desc()
+
+    def batch(meshes, descs, n=None):
+        hs = (C.c_void_p * len(meshes))(*[m._h.value if m is not None else None for m in meshes])
+        ds = (_OpDesc * len(descs))(*descs)
+        return lib.mh_batch_create(C.cast(hs, C.c_void_p), C.cast(ds, C.c_void_p), None,
+                                   len(meshes) if n is None else n, None, C.byref(h))
+
+    assert batch([M], [d0], n=0) == INVALID
+    assert batch([M], [d0], n=5000) == UNSUP
+    assert batch([M, None], [d0, d1]) == INVALID
+    assert batch([M, M], [d0, d9]) == INVALID
+    assert w1["p"] != w["p"]
+    assert batch([M, M1], [d0, d1]) == INVALID
+    assert "share p" in lib.mh_last_error().decode()
