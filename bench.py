@@ -18,6 +18,7 @@ same kernel launches, and times 64 sequential single-instance runs of the
 same instances on a bounded sample for the batched/sequential ratio.
 """
 import argparse
+import glob
 import json
 import os
 import sys
@@ -251,21 +252,35 @@ def main():
     print(json.dumps(line))
 
 
-def measured_traffic(kernel, workload, profiles_dir=None, source=None, schedule=None):
+def sources_sha1(root=None):
+    """SHA-1 over the library sources and the workload generators (every file
+    of paper_2301_02387_amd/csrc/ and synth/*.py, in name order, each as its
+    relative path then its bytes): what fixes both the kernels and the data
+    layout they stream (node numbering, operator copies, meshes)."""
+    import hashlib
+    root = root or ROOT
+    files = (sorted(glob.glob(os.path.join(root, "paper_2301_02387_amd", "csrc", "*")))
+             + sorted(glob.glob(os.path.join(root, "synth", "*.py"))))
+    h = hashlib.sha1()
+    for f in files:
+        if os.path.isfile(f):
+            h.update(os.path.relpath(f, root).encode() + b"\0")
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, profiles_dir=None, root=None, schedule=None):
     """HBM bytes per launch of `kernel` on `workload` (under `schedule`) from the
     counter summaries under profiles/ (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
-    calibrated), or None when none was taken or the kernel's source has changed
-    since."""
-    import glob
-    import hashlib
-    src = source or os.path.join(ROOT, "paper_2301_02387_amd", "csrc", "stencil.hip")
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    calibrated), or None when none was taken or the library sources or
+    workload generators have changed since (sources_sha1)."""
+    sha = sources_sha1(root)
     for path in sorted(glob.glob(os.path.join(profiles_dir or os.path.join(ROOT, "profiles"), "*.md"))):
         for ln in open(path):
             if not ln.startswith("traffic:"):
                 continue
             kv = dict(tok.split("=", 1) for tok in ln.split()[1:])
-            if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_sha1") == sha \
+            if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("sources_sha1") == sha \
                     and (schedule is None or kv.get("schedule", schedule) == schedule):
                 return float(kv["bytes_per_launch"])
     return None

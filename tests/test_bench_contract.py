@@ -1,6 +1,5 @@
 """Host-side checks of the benchmark contract (no GPU): the single-GPU guard
-and the rule that counter traffic is reported only for an unchanged kernel."""
-import hashlib
+and the rule that counter traffic is reported only for unchanged sources."""
 import os
 import subprocess
 import sys
@@ -15,18 +14,43 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_only_for_unchanged_source(tmp_path):
+def test_traffic_only_for_unchanged_sources(tmp_path):
+    """A stored traffic line counts only while every library source and
+    workload generator is byte-for-byte the one it was measured on: a change
+    to a kernel, to host code that lays out the data, or to a workload's mesh
+    recipe each void it."""
     sys.path.insert(0, ROOT)
     import bench
-    src = tmp_path / "kernel.hip"
-    src.write_text("kernel v1\n")
-    sha = hashlib.sha1(src.read_bytes()).hexdigest()
+    csrc = tmp_path / "paper_2301_02387_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (tmp_path / "synth").mkdir()
+    (csrc / "stencil.hip").write_text("kernel v1\n")
+    (csrc / "host_mesh.cpp").write_text("numbering v1\n")
+    (tmp_path / "synth" / "inputs.py").write_text("mesh recipe v1\n")
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "x.md").write_text("text\ntraffic: kernel=poisson_spmv workload=w1 bytes_per_launch=1234 "
-                               f"source_sha1={sha}\n")
-    assert bench.measured_traffic("poisson_spmv", "w1", str(prof), str(src)) == 1234.0
-    assert bench.measured_traffic("poisson_spmv", "w2", str(prof), str(src)) is None
-    assert bench.measured_traffic("stencil_orb", "w1", str(prof), str(src)) is None
-    src.write_text("kernel v2\n")
-    assert bench.measured_traffic("poisson_spmv", "w1", str(prof), str(src)) is None
+
+    def store():
+        sha = bench.sources_sha1(str(tmp_path))
+        (prof / "x.md").write_text("text\ntraffic: kernel=poisson_spmv workload=w1 schedule=53/8192 "
+                                   f"bytes_per_launch=1234 sources_sha1={sha}\n")
+
+    def traffic(kernel="poisson_spmv", workload="w1", schedule=None):
+        return bench.measured_traffic(kernel, workload, str(prof), str(tmp_path), schedule)
+
+    store()
+    assert traffic() == 1234.0
+    assert traffic(schedule="53/8192") == 1234.0
+    assert traffic(schedule="52/8192") is None
+    assert traffic(workload="w2") is None
+    assert traffic(kernel="stencil_orb") is None
+    for f, text in [(csrc / "stencil.hip", "kernel v2\n"), (csrc / "host_mesh.cpp", "numbering v2\n"),
+                    (tmp_path / "synth" / "inputs.py", "mesh recipe v2\n")]:
+        store()
+        assert traffic() == 1234.0
+        f.write_text(text)
+        assert traffic() is None, f
+    store()
+    (csrc / "api.hip").write_text("a new source file\n")
+    assert traffic() is None
+
