@@ -12,12 +12,27 @@ def desc_of(w):
     return MeshDesc(w["lo"], w["hi"], w["n_coarse"], w["p"], [Ball(**b) for b in w["balls"]])
 
 
+# Degenerate meshes for the tests only: no refinement, so no hanging nodes and
+# no interface block of the mass matrix.  On the odd Q1 grid the multigrid
+# hierarchy has a single level (nothing coarser nests in it), solved by the
+# dense inverse of the whole operator.
+TEST_WORKLOADS = {
+    "uniform_q2": dict(name="uniform_q2", lo=-5.0, hi=5.0, n_coarse=4, p=2, balls=[],
+                       nuclei=[(1.0, (0.0, 0.0, 0.6)), (1.0, (0.0, 0.0, -0.6))], n_orb=2, n_alpha=1, n_beta=1),
+    "uniform_q1_odd": dict(name="uniform_q1_odd", lo=-5.0, hi=5.0, n_coarse=5, p=1, balls=[],
+                           nuclei=[(1.0, (0.3, -0.2, 0.1))], n_orb=2, n_alpha=1, n_beta=1),
+}
+
+
 @functools.lru_cache(maxsize=None)
 def case(name, seed=0):
-    try:
-        w = workload(name)
-    except KeyError:
-        w = small_workload(name, seed)
+    if name in TEST_WORKLOADS:
+        w = TEST_WORKLOADS[name]
+    else:
+        try:
+            w = workload(name)
+        except KeyError:
+            w = small_workload(name, seed)
     mesh = Mesh(desc_of(w))
     ops = Operators(mesh, w["nuclei"])
     return w, mesh, ops

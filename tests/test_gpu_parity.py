@@ -17,6 +17,9 @@ from tests.lib_cases import Pair, rel_err_cols
 pytestmark = pytest.mark.gpu
 
 SMALL = ["h_atom", "tiny_q3", "tiny_q1", "small_n3"]
+# unrefined meshes: no hanging nodes, no interface mass block; on the odd Q1
+# grid the multigrid hierarchy is the operator alone (dense inverse)
+UNIFORM = ["uniform_q2", "uniform_q1_odd"]
 
 
 def _torch():
@@ -52,7 +55,7 @@ def orbitals(P, seed):
     return orthonormalize(P.ops, c)
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL + UNIFORM)
 def test_fill_hanging_and_mass_solve(name):
     torch = _torch()
     P = pair(name)
@@ -70,10 +73,11 @@ def test_fill_hanging_and_mass_solve(name):
     ref = P.ops.mass_solve(f_or)
     o = host(out)
     assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-12
-    assert rel_err_cols(o[P.N:], (P.om.C @ ref)[P.perm[P.N:P.NE]]) < 1e-12
+    if P.Nh:
+        assert rel_err_cols(o[P.N:], (P.om.C @ ref)[P.perm[P.N:P.NE]]) < 1e-12
 
 
-@pytest.mark.parametrize("name", SMALL + ["h2"])
+@pytest.mark.parametrize("name", SMALL + UNIFORM + ["h2"])
 def test_h1_apply(name):
     torch = _torch()
     P = pair(name)
@@ -94,7 +98,7 @@ def _poisson(P, c, rtol=1e-13):
     return W, it, rc
 
 
-@pytest.mark.parametrize("name", SMALL + ["h2"])
+@pytest.mark.parametrize("name", SMALL + UNIFORM + ["h2"])
 def test_poisson_pairs(name):
     from oracle.poisson import PoissonSolver
     P = pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
@@ -169,7 +173,7 @@ def _frozen(P, c, C, E):
     return fr, cs
 
 
-@pytest.mark.parametrize("name", SMALL + ["h2", "tiny_n8"])
+@pytest.mark.parametrize("name", SMALL + UNIFORM + ["h2", "tiny_n8"])
 def test_rhs_apply(name):
     """G applied to a random packed vector: interface mass block solved by the
     dense inverse (the default for one small instance) and by Chebyshev, the
@@ -204,9 +208,10 @@ def _rhs_apply_case(P, name, torch):
         assert rel_err_cols(o[P.N:], (P.om.C @ ref)[P.perm[P.N:P.NE]]) < 1e-10
 
 
-@pytest.mark.parametrize("name,tau", [("tiny_q3", 0.02), ("small_n3", 0.05), ("h_atom", 0.02),
-                                      ("tiny_q3", -0.05j), ("h2", 0.02)])
-def test_arnoldi_step(name, tau):
+@pytest.mark.parametrize("name,tau,m", [("tiny_q3", 0.02, 12), ("small_n3", 0.05, 12), ("h_atom", 0.02, 12),
+                                        ("tiny_q3", -0.05j, 12), ("h2", 0.02, 12), ("tiny_q3", 0.02, 1),
+                                        ("uniform_q2", 0.02, 2), ("uniform_q1_odd", 0.05, 12)])
+def test_arnoldi_step(name, tau, m):
     from oracle.mctdhf import arnoldi_step
     P = pair(name)
     n = P.w["n_orb"]
@@ -215,8 +220,8 @@ def test_arnoldi_step(name, tau):
     dim = CISpace(n, P.w["n_alpha"], P.w["n_beta"]).dim
     fr, _ = _frozen(P, c, random_ci(dim, 9), 0.013)
     x = dev(P.to_lib_orb(c))
-    err, m_used = P.op.arnoldi_step(x, tau, 12)
-    ref, err_ref, m_ref, _ = arnoldi_step(P.ops, fr.G, c, tau, 12)
+    err, m_used = P.op.arnoldi_step(x, tau, m)
+    ref, err_ref, m_ref, _ = arnoldi_step(P.ops, fr.G, c, tau, m)
     assert m_used == m_ref
     o = host(x)
     assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-10
@@ -226,7 +231,8 @@ def test_arnoldi_step(name, tau):
 @pytest.mark.parametrize("name,steps,imag,sched", [("h_atom", 4, False, 13), ("tiny_q3", 4, False, 13),
                                                    ("small_n3", 3, False, 13), ("tiny_q3", 3, True, 13),
                                                    ("tiny_q3", 4, False, 21), ("small_n3", 3, False, 20),
-                                                   ("tiny_q3", 4, False, 53), ("small_n3", 3, False, 52)])
+                                                   ("tiny_q3", 4, False, 53), ("small_n3", 3, False, 52),
+                                                   ("uniform_q2", 3, False, 13), ("uniform_q1_odd", 3, False, 53)])
 def test_propagate_observables(name, steps, imag, sched):
     """Propagated dipoles, energies, orbitals and CI vectors against the
     oracle, with the default schedules (Poisson 13) and with the multigrid
@@ -296,3 +302,34 @@ def test_multigrid_poisson(name):
             assert num / den < 1e-9, (sched, k, num / den)
     print(name, "CG iterations jacobi / multigrid", its, flush=True)
     assert its[21] <= 60 and its[21] * 4 < its[13], its
+
+
+@pytest.mark.parametrize("name", UNIFORM)
+def test_multigrid_poisson_unrefined(name):
+    """Multigrid on unrefined meshes gives the oracle's potentials; on the odd
+    Q1 grid the hierarchy is the operator itself, solved exactly by its dense
+    inverse, so the preconditioned CG stops after its first iteration."""
+    torch = _torch()
+    from oracle.poisson import PoissonSolver
+    P = Pair(name, poisson_rtol=1e-12, poisson_maxit=20000)
+    assert P.Nh == 0
+    n = P.w["n_orb"]
+    c = orbitals(P, 4)
+    ref = PoissonSolver(P.ops).pair_potentials(c)
+    x = dev(P.to_lib_orb(c))
+    its = {}
+    for sched in (13, 21, 53):
+        P.op.tune(1, sched, 8192)
+        W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+        it, rc = P.op.poisson_pairs(x, W)
+        assert rc == 0
+        its[sched] = it
+        got = P.W_from_lib(host(W), n)
+        for k in ref:
+            num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref[k]) ** 2))
+            den = np.sqrt(np.sum(P.ops.m * np.abs(ref[k]) ** 2))
+            assert num / den < 1e-9, (sched, k, num / den)
+    print(name, "CG iterations", its, flush=True)
+    assert its[21] <= its[13] and its[53] <= its[13], its
+    if name == "uniform_q1_odd":
+        assert its[21] <= 2 and its[53] <= 2, its

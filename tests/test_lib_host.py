@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
-@pytest.mark.parametrize("name", ["h_atom", "tiny_q3", "tiny_q1", "small_n3", "h2"])
+@pytest.mark.parametrize("name", ["h_atom", "tiny_q3", "tiny_q1", "small_n3", "h2", "uniform_q2", "uniform_q1_odd"])
 def test_mesh_equals_oracle(name):
     mh, _ = _lib()
     from tests.lib_cases import match_nodes
