@@ -210,7 +210,8 @@ def _rhs_apply_case(P, name, torch):
 
 @pytest.mark.parametrize("name,tau,m", [("tiny_q3", 0.02, 12), ("small_n3", 0.05, 12), ("h_atom", 0.02, 12),
                                         ("tiny_q3", -0.05j, 12), ("h2", 0.02, 12), ("tiny_q3", 0.02, 1),
-                                        ("uniform_q2", 0.02, 2), ("uniform_q1_odd", 0.05, 12)])
+                                        ("uniform_q2", 0.02, 2), ("uniform_q1_odd", 0.05, 12),
+                                        ("h_atom", 0.02, 16), ("small_n3", 0.05, 24)])
 def test_arnoldi_step(name, tau, m):
     from oracle.mctdhf import arnoldi_step
     P = pair(name)
