@@ -191,3 +191,44 @@ def test_batch_of_one_equals_plain_operator():
     assert np.max(np.abs(recs[0][0] - recs[1][0])) <= 1e-12 * np.abs(recs[0][0]).max()
     assert np.max(np.abs(recs[0][1] - recs[1][1])) <= 1e-12 * np.abs(recs[0][1]).max()
     assert np.max(np.abs(recs[0][2] - recs[1][2])) <= 1e-12 * np.abs(recs[0][2]).max()
+
+
+def test_batch_multigrid_mixed_depths():
+    """A batch whose instances have multigrid hierarchies of different depths,
+    one of them a single level (an unrefined odd Q1 grid, solved by the dense
+    inverse of its whole operator) beside refined Q1 meshes with several
+    levels: every instance's pair potentials against the oracle, with the
+    Jacobi, multigrid and sliced-ELL multigrid schedules."""
+    torch = _torch()
+    import paper_2301_02387_amd as mh
+    from oracle.ci import CISpace
+    from oracle.poisson import PoissonSolver
+    pairs = [Pair("tiny_q1", seed=0, with_op=False), Pair("uniform_q1_odd", with_op=False),
+             Pair("tiny_q1", seed=1, with_op=False)]
+    assert pairs[1].Nh == 0 and pairs[0].Nh > 0
+    w = pairs[0].w
+    n = w["n_orb"]
+    op = mh.Operator.batch([P.mesh for P in pairs], [P.w["nuclei"] for P in pairs], n, w["n_alpha"], w["n_beta"],
+                           poisson_rtol=1e-13, poisson_maxit=20000)
+    cs, Cs = initial_state(pairs, CISpace(n, w["n_alpha"], w["n_beta"]).dim)
+    x, _ = to_device(pairs, cs, Cs)
+    lay = op.layout()
+    refs = [PoissonSolver(P.ops).pair_potentials(c) for P, c in zip(pairs, cs)]
+    its = {}
+    for sched in (13, 21, 53):
+        op.tune(1, sched, 1024)
+        for rep in range(2):
+            W = torch.zeros((op.n_full, n * n), dtype=torch.float64, device="cuda")
+            it, rc = op.poisson_pairs(x, W)
+            assert rc == 0, (sched, rep)
+            its[sched] = it
+            Wh = W.cpu().numpy()
+            for i, P in enumerate(pairs):
+                oF, NF = lay[i, 4], lay[i, 2]
+                got = P.W_from_lib(Wh[oF:oF + NF], n)
+                for k, ref in refs[i].items():
+                    num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref) ** 2))
+                    den = np.sqrt(np.sum(P.ops.m * np.abs(ref) ** 2))
+                    assert num / den < 1e-9, (sched, rep, i, k, num / den)
+    print("mixed-depth batch CG iterations", its, flush=True)
+    assert its[21] < its[13] and its[53] < its[13], its
