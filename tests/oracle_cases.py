@@ -21,6 +21,19 @@ TEST_WORKLOADS = {
                        nuclei=[(1.0, (0.0, 0.0, 0.6)), (1.0, (0.0, 0.0, -0.6))], n_orb=2, n_alpha=1, n_beta=1),
     "uniform_q1_odd": dict(name="uniform_q1_odd", lo=-5.0, hi=5.0, n_coarse=5, p=1, balls=[],
                            nuclei=[(1.0, (0.3, -0.2, 0.1))], n_orb=2, n_alpha=1, n_beta=1),
+    # CI spaces at their edges: no alpha electron (the empty string; with two
+    # orbitals the 1-RDM of one electron has rank one, so that case only feeds
+    # the RDM test, the one-orbital one the propagation), and a full alpha
+    # shell (every orbital occupied) beside one beta electron
+    "beta_one": dict(name="beta_one", lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                     balls=[dict(center=(0.3, -0.2, 0.4), radius=1.0, levels=1)],
+                     nuclei=[(1.0, (0.0, 0.0, 0.0))], n_orb=1, n_alpha=0, n_beta=1),
+    "beta_only": dict(name="beta_only", lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                      balls=[dict(center=(0.3, -0.2, 0.4), radius=1.0, levels=1)],
+                      nuclei=[(1.0, (0.0, 0.0, 0.0))], n_orb=2, n_alpha=0, n_beta=1),
+    "full_alpha": dict(name="full_alpha", lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                       balls=[dict(center=(0.3, -0.2, 0.4), radius=1.0, levels=1)],
+                       nuclei=[(3.0, (0.0, 0.0, 0.0))], n_orb=2, n_alpha=2, n_beta=1),
 }
 
 

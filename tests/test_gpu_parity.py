@@ -141,7 +141,7 @@ def test_poisson_every_schedule(name):
                 assert num / den < 1e-9, (sched, grid, k, num / den)
 
 
-@pytest.mark.parametrize("name,nci", [("tiny_q3", 4), ("small_n3", 9)])
+@pytest.mark.parametrize("name,nci", [("tiny_q3", 4), ("small_n3", 9), ("beta_only", 2), ("full_alpha", 2)])
 def test_ci_rdms(name, nci):
     torch = _torch()
     from oracle.ci import CISpace
@@ -233,7 +233,8 @@ def test_arnoldi_step(name, tau, m):
                                                    ("small_n3", 3, False, 13), ("tiny_q3", 3, True, 13),
                                                    ("tiny_q3", 4, False, 21), ("small_n3", 3, False, 20),
                                                    ("tiny_q3", 4, False, 53), ("small_n3", 3, False, 52),
-                                                   ("uniform_q2", 3, False, 13), ("uniform_q1_odd", 3, False, 53)])
+                                                   ("uniform_q2", 3, False, 13), ("uniform_q1_odd", 3, False, 53),
+                                                   ("beta_one", 3, False, 13), ("full_alpha", 3, False, 13)])
 def test_propagate_observables(name, steps, imag, sched):
     """Propagated dipoles, energies, orbitals and CI vectors against the
     oracle, with the default schedules (Poisson 13) and with the multigrid
