@@ -335,3 +335,45 @@ def test_multigrid_poisson_unrefined(name):
     assert its[21] <= its[13] and its[53] <= its[13], its
     if name == "uniform_q1_odd":
         assert its[21] <= 2 and its[53] <= 2, its
+
+
+def test_propagate_zero_steps():
+    """A propagation of zero steps records the observables of the given state
+    (and leaves it unchanged, its pair potentials solved into W); without the
+    final record it does nothing."""
+    torch = _torch()
+    from oracle.ci import CISpace
+    from oracle.mctdhf import Propagator
+    from oracle.poisson import PoissonSolver
+    P = pair("tiny_q3", poisson_rtol=1e-13, poisson_maxit=20000)
+    P.op.tune(1, 13, 8192)
+    P.op.tune(0, 1, 65536)
+    n = P.w["n_orb"]
+    cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
+    c = orbitals(P, 12)
+    C = random_ci(cs.dim, 13)
+    x = dev(P.to_lib_orb(c))
+    Cd = dev(C)
+    x0, C0 = host(x).copy(), host(Cd).copy()
+    W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+    rec = P.op.propagate(x, Cd, W, [0.013], 0.02)
+    assert rec["status"] == 0 and rec["dipole"].shape == (1,)
+    ref = Propagator(P.ops, cs).final_observables(c, C, 0.013)
+    assert abs(rec["dipole"][0] - ref["dipole"]) <= 1e-8 * max(abs(ref["dipole"]), 1e-3)
+    assert abs(rec["energy"][0] - ref["energy"]) <= 1e-8 * abs(ref["energy"])
+    def unchanged():
+        return (np.max(np.abs(host(x) - x0)) <= 1e-14 * np.abs(x0).max()
+                and np.max(np.abs(host(Cd) - C0)) <= 1e-14 * np.abs(C0).max())
+
+    assert unchanged()
+    Wref = PoissonSolver(P.ops).pair_potentials(c)
+    got = P.W_from_lib(host(W), n)
+    for k in Wref:
+        num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - Wref[k]) ** 2))
+        den = np.sqrt(np.sum(P.ops.m * np.abs(Wref[k]) ** 2))
+        assert num / den < 1e-9, (k, num / den)
+    W2 = torch.zeros_like(W)
+    rec = P.op.propagate(x, Cd, W2, [0.013], 0.02, final=False)
+    assert rec["status"] == 0
+    assert unchanged()
+    assert not host(W2).any()
