@@ -146,7 +146,11 @@ def test_batch_multigrid_poisson():
     assert its[21] <= 60 and its[21] * 4 < its[13], its
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("orb,poi", [(1, 13), (4, 53)])
+def test_graph_replay_matches_eager(orb, poi):
+    """The step replayed from a HIP graph against the eager step, with the
+    default schedules and with those the batch bench tunes to (the assembled
+    orbital stiffness inside the graph, multigrid CG before it)."""
     torch = _torch()
     pairs, op = batch_case()
     w = pairs[0].w
@@ -155,12 +159,18 @@ def test_graph_replay_matches_eager():
     cs, Cs = initial_state(pairs, CISpace(n, w["n_alpha"], w["n_beta"]).dim)
     shape = [0.05 * np.sin(0.3 * k) for k in range(6)]
     out = {}
-    for graph in (False, True):
-        x, Cd = to_device(pairs, cs, Cs)
-        W = torch.zeros((op.n_full, n * n), dtype=torch.float64, device="cuda")
-        rec = op.propagate(x, Cd, W, shape, 0.02, m=12, graph=graph)
-        torch.cuda.synchronize()
-        out[graph] = (rec, x.cpu().numpy(), Cd.cpu().numpy())
+    try:
+        op.tune(0, orb, 65536)
+        op.tune(1, poi, 8192 if poi == 13 else 1024)
+        for graph in (False, True):
+            x, Cd = to_device(pairs, cs, Cs)
+            W = torch.zeros((op.n_full, n * n), dtype=torch.float64, device="cuda")
+            rec = op.propagate(x, Cd, W, shape, 0.02, m=12, graph=graph)
+            torch.cuda.synchronize()
+            out[graph] = (rec, x.cpu().numpy(), Cd.cpu().numpy())
+    finally:
+        op.tune(0, 1, 65536)
+        op.tune(1, 13, 8192)
     (r0, x0, c0), (r1, x1, c1) = out[False], out[True]
     # every replay (one per step) against the eager step, with host syncs
     # between replays.  Not bitwise: the Poisson boundary lift accumulates
