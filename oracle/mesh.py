@@ -5,7 +5,7 @@ are halved recursively where more resolution is needed; each cell carries
 the tensor-product Lagrange basis on Gauss-Lobatto points, and continuity
 across a refinement interface is restored by "bridged" basis functions.
 
-Readings taken where the paper is silent (listed in the design doc):
+Readings taken where the paper is silent:
   * refinement is geometric: a leaf of level l is split while it meets (its
     closest point lies strictly within radius r of) a ball whose level
     count exceeds l; then 2:1 balance is enforced over all 26 neighbours;
