@@ -407,3 +407,155 @@ def test_field_free_norm_and_orthonormality():
         assert abs(np.linalg.norm(CC) - 1) < 1e-12
     # orthonormality drift is O(dt^2) per step: halving dt roughly halves it
     assert drifts[1] < 0.7 * drifts[0]
+
+
+# ------------------------------------------- mesh counts of the workloads ----
+# Integer counts of the three workload meshes, derived independently of the
+# oracle by hand rules (nested Q2 grid) and a separate throwaway script when
+# the workloads were specified: cells, full nodes, hanging nodes, nodes on the
+# box boundary, unknowns, masters of hanging nodes, constraint entries and
+# cells per refinement level.
+APPENDIX_COUNTS = {
+    "h_atom": dict(n_cells=624, n_full=6121, n_hang=576, n_bnd=1538, n_dof=4007, n_masters=196,
+                   level_counts=[504, 56, 64]),
+    "h2": dict(n_cells=2736, n_full=83653, n_hang=9240, n_bnd=7778, n_dof=66635, n_masters=2382,
+               level_counts=[1680, 336, 336, 384], hang_nnz=116160),
+    "h2o": dict(n_cells=58304, n_full=1661342, n_hang=129640, n_bnd=13826, n_dof=1517876, n_masters=33344,
+                level_counts=[3936, 872, 1904, 5064, 46528]),
+}
+
+
+@pytest.mark.parametrize("name", ["h_atom", "h2", "h2o"])
+def test_workload_mesh_counts(name):
+    from synth import workload
+    from tests.oracle_cases import desc_of
+    info = Mesh(desc_of(workload(name))).info()
+    for k, v in APPENDIX_COUNTS[name].items():
+        assert info[k] == v, (name, k, info[k], v)
+    assert info["chain_subst"] == 0          # no constraint chains under 26-neighbour balance
+
+
+# ------------------------------------ energy functional and its gradient ----
+def _complex_state(seed=21):
+    """Three orbitals, two alpha and one beta electron, complex orbitals and a
+    complex CI vector: gamma has complex off-diagonal entries, so any
+    transposition of gamma, Gamma or of a pair index changes the result."""
+    w, mesh, ops = case("small_n3")
+    cs = CISpace(3, 2, 1)
+    c = mctdhf.orthonormalize(ops, random_orbitals(mesh.xyz[mesh.dof_nodes], 3, seed, spread=1.0))
+    C = random_ci(cs.dim, seed + 1)
+    gam, Gam = cs.rdms(C)
+    assert np.abs(gam.imag).max() > 0.1
+    return ops, cs, c, C, gam, Gam
+
+
+def test_mean_field_is_the_energy_gradient():
+    """Sec. II: the orbital equation follows from the variational principle, so
+    the load vector mixed by the 1-RDM is the gradient of the energy functional
+    E(c) = sum h_pq gamma_pq + 1/2 sum g_pqrs Gamma_pqrs at fixed RDMs:
+    dE = 2 Re sum_p d_p^H (sum_o gamma_po F_o(c)).  The energy side runs the
+    Poisson solves, the integrals and the energy assembly; the gradient side
+    the mean field U, gamma^-1 and F.  A transposed gamma^-1, a swapped pair
+    index of g or a transposed RDM in the energy each break the equality by
+    ten per cent or more; the discrete Coulomb map is symmetric only up to its
+    multipole boundary lift, which leaves ~1e-5."""
+    ops, cs, c, C, gam, Gam = _complex_state()
+    ps = PoissonSolver(ops)
+
+    def energy(cc):
+        h, g = mctdhf.integrals(ops, cc, full_pairs(ps.pair_potentials(cc), 3), 0.0)
+        return mctdhf.observables(ops, cc, gam, Gam, h, g)["energy"]
+
+    fr = mctdhf.Frozen(ops, c, gam, Gam, 0.0, ps.pair_potentials(c))
+    grad = fr.F(c) @ gam.T                  # column p: sum_o gamma_po F_o(c)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        d = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
+        eps = 1e-4
+        fd = (energy(c + eps * d) - energy(c - eps * d)) / (2 * eps)
+        an = 2 * np.real(np.sum(np.conj(d) * grad))
+        assert abs(fd - an) < 2e-4 * abs(an), (fd, an)
+
+
+def test_dipole_is_the_field_derivative_of_the_energy():
+    """H1(E) = K/2 + V + E Z, so dE/dE_field = sum gamma_pq c_p^H Z c_q: the
+    recorded dipole equals the field derivative of the recorded energy."""
+    ops, cs, c, C, gam, Gam = _complex_state(31)
+    Wf = full_pairs(PoissonSolver(ops).pair_potentials(c), 3)
+
+    def obs(E):
+        h, g = mctdhf.integrals(ops, c, Wf, E)
+        return mctdhf.observables(ops, c, gam, Gam, h, g)
+
+    e = 1e-3
+    fd = (obs(e)["energy"] - obs(-e)["energy"]) / (2 * e)
+    d = obs(0.0)["dipole"]
+    assert abs(d) > 1e-3 and abs(fd - d) < 1e-10 * max(1.0, abs(d)), (fd, d)
+
+
+def test_field_free_energy_conservation_complex_state():
+    """Field-free MCTDHF conserves the energy; the frozen-operator step is
+    first order, so the drift over a fixed time halves with the step.  A wrong
+    mean field or two-electron integral leaves a drift that does not vanish as
+    dt -> 0 (the ratio then stays near one)."""
+    ops, cs, c, C, gam, Gam = _complex_state()
+    pr = mctdhf.Propagator(ops, cs)
+    drifts = []
+    for dt in (0.01, 0.005):
+        cc, CC = c.copy(), C.copy()
+        E0 = None
+        for _ in range(int(round(0.04 / dt))):
+            cc, CC, rec = pr.step(cc, CC, 0.0, dt)
+            E0 = rec["energy"] if E0 is None else E0
+        drifts.append(abs(pr.final_observables(cc, CC, 0.0)["energy"] - E0))
+    assert drifts[0] < 1e-4
+    assert 0.4 < drifts[1] / drifts[0] < 0.6, drifts
+
+
+# ------------------------------------------------ imaginary time ----
+def test_imaginary_time_relaxes_to_lowest_eigenvalue():
+    """Imaginary-time steps (tau = -i dtau, orbitals re-orthonormalised) from
+    the normalised exp(-r^2) guess on the H-atom mesh reach the lowest
+    generalized eigenvalue of (H1, M) from a shift-invert Lanczos solver."""
+    from synth import initial_guess
+    w, mesh, ops = case("h_atom")
+    e0 = spla.eigsh(ops.H1(0.0).tocsc(), k=1, M=ops.M.tocsc(), sigma=-0.6, which="LM")[0][0]
+    c = mctdhf.orthonormalize(ops, initial_guess("h_atom", mesh.xyz[mesh.dof_nodes]))
+    C = np.ones(1, dtype=complex)
+    pr = mctdhf.Propagator(ops, CISpace(1, 1, 0))
+    for _ in range(60):
+        c, C, rec = pr.step(c, C, 0.0, 0.5, imaginary=True)
+    e = pr.final_observables(c, C, 0.0)["energy"]
+    assert abs(e - e0) < 1e-8, (e, e0)
+    assert abs(np.vdot(c[:, 0], ops.M @ c[:, 0]) - 1) < 1e-12
+
+
+# ---------------------------------------------- CI exponential ----
+@pytest.mark.parametrize("rho", [0.2, 2.0])
+def test_lanczos_expm_beyond_twelve_determinants(rho):
+    """36 determinants (4 orbitals, 2 alpha, 2 beta) with 12 Lanczos vectors:
+    the Krylov approximation of exp(-i tau H) C obeys the a-priori bound
+    2 beta rho^m e^rho / m! (rho = tau |H|_2, Saad 1992) against scipy expm."""
+    import math
+    cs = CISpace(4, 2, 2)
+    h, g = _random_integrals(4, 13)
+    H = cs.hamiltonian(h, g)
+    C = 3.0 * random_ci(cs.dim, 8)
+    tau = rho / np.linalg.norm(H, 2)
+    ref = sla.expm(-1j * tau * H) @ C
+    out = mctdhf.lanczos_expm(H, C, tau, 12)
+    bound = 2 * np.linalg.norm(C) * rho ** 12 * np.exp(rho) / math.factorial(12)
+    assert np.linalg.norm(out - ref) <= bound + 1e-13 * np.linalg.norm(C), (np.linalg.norm(out - ref), bound)
+    if rho > 1:
+        # not exact: the space is truncated (so the bound is what is being tested)
+        assert np.linalg.norm(out - ref) > 1e-14
+    # the same 12-dimensional Krylov space through the orbital Arnoldi step
+    # (pinned against dense exponentials with its error estimate) with the
+    # Euclidean inner product: the two projections agree to rounding
+    import types
+    import scipy.sparse as sp
+    eye = types.SimpleNamespace(M=sp.identity(cs.dim, format="csr"))
+    arn, err, m_eff, _ = mctdhf.arnoldi_step(eye, lambda v: H @ v, C[:, None], tau, 12)
+    assert m_eff == 12
+    assert np.linalg.norm(out - arn[:, 0]) < 1e-12 * np.linalg.norm(C)
+    assert np.linalg.norm(arn[:, 0] - ref) <= 10 * err + 1e-13 * np.linalg.norm(C)
