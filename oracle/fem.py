@@ -8,8 +8,20 @@ constraint matrix C (bridged basis b_k = sum_i C_ik f_i):
 
     M  = C^T diag(m) C                      (mass / overlap matrix)
     K  = C^T K_full C,  K_full = sum_cells (h/2)(A x W x W + W x A x W + W x W x A)
-    H1(E) = K/2 + C^T diag(v + E m (e.x)) C (length gauge, reading of the
-                                             one-body operator)
+    H1(E) = K/2 + C^T diag(v + E m (e.x)) C (length gauge)
+    H1(A) = K/2 + C^T diag(v) C - i A S_e   (velocity gauge, Sec. II: the
+                                             one-body operator carries -i A(t).grad)
+
+The first-derivative matrix of the velocity gauge is the Gauss-Lobatto
+Galerkin form D_d = C^T D_full,d C with (D_full,d)_ij = sum_cells int f_i
+d/dx_d f_j; by collocation (D_full,d u)_i = m_i (d u/d x_d)(x_i) for every u
+of the element space whose derivative is continuous.  S_d = (D_d - D_d^T)/2
+is its antisymmetric part (reading: the paper does not say how the term is
+discretised; the antisymmetric part keeps H1 Hermitian, and it equals D_d
+itself where no hanging nodes interrupt the face integrals, by summation by
+parts of the Gauss-Lobatto rule), and S_e = sum_d e_d S_d along the field
+direction e.  The A^2/2 term of the minimal coupling is dropped: it is a
+constant in space and only adds a phase and N A^2/2 to the energy.
 
 v is the lumped nuclear potential: v_i = sum_cells int_cell f_i V_nuc, the
 row sum of the exact Galerkin potential matrix.  With a nucleus on a mesh
@@ -150,11 +162,43 @@ def nuclear_lumped(mesh, nuclei):
     return v
 
 
-class Operators:
-    """Assembled sparse operators of one mesh and one molecule."""
+def full_gradient(mesh):
+    """[D_x, D_y, D_z] on the full nodes: (D_d)_ij = sum over cells of the
+    Gauss-Lobatto quadrature of f_i d f_j / d x_d, i.e. per cell
+    (h/2)^2 w_a w_b w_c l'_{a'}(xi_a) for nodes i = (a,b,c), j = (a',b,c)
+    (x direction; likewise along y and z)."""
+    P = mesh.P
+    _, w, D, _ = operators_1d(mesh.p)
+    loc = local_index(P)
+    hc = mesh.cell_h()
+    out = []
+    for d in range(3):
+        rows, cols, vals = [], [], []
+        for i, abc in enumerate(loc):
+            for a2 in range(P):
+                jabc = list(abc)
+                jabc[d] = a2
+                j = jabc[0] + P * (jabc[1] + P * jabc[2])
+                rows.append(i); cols.append(j)
+                vals.append(w[abc[0]] * w[abc[1]] * w[abc[2]] * D[abc[d], a2])
+        rows, cols, vals = map(np.array, (rows, cols, vals))
+        R = mesh.cell_nodes[:, rows].ravel()
+        Cc = mesh.cell_nodes[:, cols].ravel()
+        V = ((hc[:, None] / 2.0) ** 2 * vals[None, :]).ravel()
+        out.append(sp.csr_matrix((V, (R, Cc)), shape=(mesh.n_full, mesh.n_full)))
+    return out
 
-    def __init__(self, mesh, nuclei, pol=(0.0, 0.0, 1.0)):
+
+class Operators:
+    """Assembled sparse operators of one mesh and one molecule.  gauge:
+    "length" (field value E(t), term E m (e.x)) or "velocity" (field value
+    A(t), term -i A S_e)."""
+
+    def __init__(self, mesh, nuclei, pol=(0.0, 0.0, 1.0), gauge="length"):
+        if gauge not in ("length", "velocity"):
+            raise ValueError(gauge)
         self.mesh = mesh
+        self.gauge = gauge
         self.nuclei = [(float(Z), tuple(map(float, R))) for Z, R in nuclei]
         self.pol = np.asarray(pol, dtype=float)
         C = mesh.C
@@ -166,10 +210,34 @@ class Operators:
         self.K = (C.T @ self.Kfull @ C).tocsr()
         self.Vn = (C.T @ sp.diags(self.v) @ C).tocsr()
         self.Z = (C.T @ sp.diags(self.mz) @ C).tocsr()
+        self._grad = None
         self._Mlu = None
 
+    def gradient(self):
+        """(D_full, D, S, S_e): the first-derivative matrices, built on first use."""
+        if self._grad is None:
+            C = self.mesh.C
+            Dfull = full_gradient(self.mesh)
+            D = [(C.T @ Dd @ C).tocsr() for Dd in Dfull]
+            S = [(0.5 * (Dd - Dd.T)).tocsr() for Dd in D]
+            Se = sum(e * Sd for e, Sd in zip(self.pol, S)).tocsr()
+            self._grad = (Dfull, D, S, Se)
+        return self._grad
+
+    @property
+    def Se(self):
+        return self.gradient()[3]
+
     def H1(self, E):
+        """One-body matrix at field value E: E(t) in the length gauge, A(t)
+        in the velocity gauge."""
+        if self.gauge == "velocity":
+            return (0.5 * self.K + self.Vn - 1j * E * self.Se).tocsr()
         return (0.5 * self.K + self.Vn + E * self.Z).tocsr()
+
+    def momentum(self):
+        """Matrix of e.p = -i e.grad in the bridged basis (-i S_e)."""
+        return (-1j * self.Se).tocsr()
 
     def mass_solve(self, f):
         """c = M^{-1} f by sparse LU (exact up to rounding)."""

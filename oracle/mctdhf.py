@@ -154,12 +154,19 @@ def integrals(ops, c, Wfull, E):
     return h, g
 
 
-def observables(ops, c, gamma, Gamma, h, g):
+def observables(ops, c, gamma, Gamma, h, g, E=0.0):
+    """Dipole sum gamma_pq c_p^H Z c_q, energy, overlap, and the kinetic
+    momentum along e: sum gamma_pq c_p^H (-i S_e) c_q, plus N A in the
+    velocity gauge (E is then A(t)), the velocity form of the dipole."""
     zmat = c.conj().T @ (ops.Z @ c)
     dip = np.sum(gamma * zmat).real
     energy = (np.sum(h * gamma) + 0.5 * np.sum(g * Gamma)).real + ops.nuclear_repulsion()
     S = c.conj().T @ (ops.M @ c)
-    return dict(dipole=dip, energy=energy, overlap=S)
+    pmat = c.conj().T @ (ops.momentum() @ c)
+    mom = np.sum(gamma * pmat).real
+    if ops.gauge == "velocity":
+        mom += np.trace(gamma).real * E
+    return dict(dipole=dip, energy=energy, overlap=S, momentum=mom)
 
 
 def orthonormalize(ops, c):
@@ -192,7 +199,7 @@ class Propagator:
         """Advance (c, C) by one step from t_n data; returns (c', C', info)."""
         fr = self.freeze(c, C, E)
         h, g = integrals(self.ops, c, fr.Wfull, E)
-        obs = observables(self.ops, c, fr.gamma, fr.Gamma, h, g)
+        obs = observables(self.ops, c, fr.gamma, fr.Gamma, h, g, E)
         tau = -1j * dt if imaginary else dt
         c2, err, m_eff, _ = arnoldi_step(self.ops, fr.G, c, tau, m)
         Hci = self.ci.hamiltonian(h, g)
@@ -206,7 +213,7 @@ class Propagator:
     def final_observables(self, c, C, E):
         fr = self.freeze(c, C, E)
         h, g = integrals(self.ops, c, fr.Wfull, E)
-        return observables(self.ops, c, fr.gamma, fr.Gamma, h, g)
+        return observables(self.ops, c, fr.gamma, fr.Gamma, h, g, E)
 
     def propagate(self, c, C, E_steps, dt, m=12, imaginary=False):
         """Run len(E_steps) steps; returns final (c, C) and per-step records
