@@ -559,3 +559,117 @@ def test_lanczos_expm_beyond_twelve_determinants(rho):
     assert m_eff == 12
     assert np.linalg.norm(out - arn[:, 0]) < 1e-12 * np.linalg.norm(C)
     assert np.linalg.norm(arn[:, 0] - ref) <= 10 * err + 1e-13 * np.linalg.norm(C)
+
+
+# ------------------------------------------------------- velocity gauge ----
+def _poly_and_grad(xyz, p):
+    """A polynomial of degree p in each variable and its gradient."""
+    x, y, z = xyz.T
+    q = min(p, 2)
+    u = (x ** p) * (1 + y) * (2 - z ** q) + 0.3 * y ** p * z
+    du = [p * x ** (p - 1) * (1 + y) * (2 - z ** q),
+          x ** p * (2 - z ** q) + 0.3 * p * y ** (p - 1) * z,
+          -(x ** p) * (1 + y) * q * z ** (q - 1) + 0.3 * y ** p]
+    return u, du
+
+
+@pytest.mark.parametrize("name", ["h_atom", "tiny_q3", "tiny_q1"])
+def test_gradient_exact_on_polynomials(name):
+    """Gauss-Lobatto collocation: the full-node Galerkin derivative applied to
+    any Q_p polynomial u gives m_i du/dx_d(x_i) at every full node, hanging
+    and boundary nodes included."""
+    w, mesh, ops = case(name)
+    Dfull = ops.gradient()[0]
+    u, du = _poly_and_grad(mesh.xyz, mesh.p)
+    for d in range(3):
+        ref = ops.m * du[d]
+        assert np.abs(Dfull[d] @ u - ref).max() < 1e-13 * np.abs(ref).max(), d
+
+
+@pytest.mark.parametrize("name", ["uniform_q2", "uniform_q1_odd"])
+def test_gradient_antisymmetric_without_hanging_nodes(name):
+    """Summation by parts of the Gauss-Lobatto rule: on a mesh without hanging
+    nodes the face terms of neighbouring cells cancel and the box faces carry
+    no unknowns, so C^T D_full C is antisymmetric and equals its
+    antisymmetric part S."""
+    w, mesh, ops = case(name)
+    _, D, S, _ = ops.gradient()
+    for d in range(3):
+        assert abs(D[d] + D[d].T).max() < 1e-14 * abs(D[d]).max()
+        assert abs(D[d] - S[d]).max() < 1e-14 * abs(D[d]).max()
+
+
+def _h_mesh(levels, p=2):
+    return Mesh(MeshDesc(-20, 20, 8, p, [Ball((0, 0, 0), 2.0, levels)]))
+
+
+def test_velocity_gauge_shifts_the_spectrum_by_half_A_squared():
+    """With a constant vector potential A, -Lap/2 - i A d/dz + V is unitarily
+    equivalent to -Lap/2 + V - A^2/2 (the phase exp(-i A z)), so the lowest
+    eigenvalue moves by -A^2/2; on the mesh the phase is represented up to the
+    discretisation error, which shrinks with refinement like the
+    ground-state energy error itself."""
+    errs = []
+    for lev in (2, 3):
+        mesh = _h_mesh(lev)
+        nuc = [(1.0, (0.0, 0.0, 0.0))]
+        opl, opv = Operators(mesh, nuc), Operators(mesh, nuc, gauge="velocity")
+        M = opl.M.tocsc()
+        e0 = spla.eigsh(opl.H1(0.0).tocsc(), k=1, M=M, sigma=-0.6, which="LM")[0][0]
+        A = 0.1
+        ea = spla.eigsh(opv.H1(A).tocsc(), k=1, M=M.astype(complex), sigma=-0.6, which="LM")[0][0]
+        errs.append(abs(ea - e0 + A * A / 2))
+    assert errs[0] < 2e-4 and errs[1] < 2e-5 and errs[1] < errs[0] / 5, errs
+
+
+def test_gauge_invariance_of_the_dipole_response():
+    """The same pulse in the length gauge (E(t)) and in the velocity gauge
+    (A(t) = -int_0^t E): one-electron dipoles <z>(t) and kinetic momenta
+    agree up to the mesh's discretisation error, which shrinks with
+    refinement; a vector-potential term of the wrong sign doubles the
+    response instead (200 % difference)."""
+    from synth import initial_guess
+    dt, T = 0.02, 1.0
+    t = dt * np.arange(int(round(T / dt)) + 1)
+    fE = lambda tt: 0.05 * np.sin(tt) ** 2 * np.sin(3 * tt)  # noqa: E731
+    tf = np.linspace(0, T, 20001)
+    Ef = fE(tf)
+    A = np.interp(t, tf, -np.concatenate([[0], np.cumsum(0.5 * (Ef[1:] + Ef[:-1]) * np.diff(tf))]))
+    diffs = []
+    for lev in (2, 3):
+        mesh = _h_mesh(lev)
+        nuc = [(1.0, (0.0, 0.0, 0.0))]
+        opl, opv = Operators(mesh, nuc), Operators(mesh, nuc, gauge="velocity")
+        c0 = mctdhf.orthonormalize(opl, initial_guess("h_atom", mesh.xyz[mesh.dof_nodes]))
+        out = {}
+        for key, o, F in (("L", opl, fE(t)), ("V", opv, A)):
+            _, _, recs = mctdhf.Propagator(o, CISpace(1, 1, 0)).propagate(c0.copy(), np.ones(1, complex),
+                                                                          list(F), dt, 12)
+            out[key] = np.array([[r["dipole"], r["momentum"]] for r in recs])
+        rel = np.abs(out["L"] - out["V"]).max(axis=0) / np.abs(out["L"]).max(axis=0)
+        diffs.append(rel)
+    # measured: dipole 4.7e-3 -> 7.5e-4, momentum 4.5e-2 -> 2.5e-2 (the momentum
+    # also carries the first-order difference of freezing E or A over a step)
+    assert diffs[0][0] < 0.01 and diffs[1][0] < 0.002 and diffs[1][0] < diffs[0][0] / 3, diffs
+    assert diffs[0][1] < 0.1 and diffs[1][1] < 0.05 and diffs[1][1] < diffs[0][1], diffs
+
+
+def test_velocity_gauge_one_orbital_mctdhf_is_tdse():
+    """One electron in one orbital, velocity gauge: C phi follows
+    exp(-i dt M^-1 H1(A)) with A frozen at t_n, against dense exponentials."""
+    from oracle.fem import Operators as Ops
+    w, mesh, _ = case("tiny_q2")
+    ops = Ops(mesh, w["nuclei"], gauge="velocity")
+    c = mctdhf.orthonormalize(ops, random_orbitals(mesh.xyz[mesh.dof_nodes], 1, 9))
+    C = np.ones(1, dtype=complex)
+    pr = mctdhf.Propagator(ops, CISpace(1, 1, 0))
+    psi = c[:, 0].copy()
+    Minv = np.linalg.inv(ops.M.toarray())
+    dt = 0.05
+    for A in [0.0, 0.3, -0.2, 0.5]:
+        c, C, _ = pr.step(c, C, A, dt, m=12)
+        psi = sla.expm(-1j * dt * Minv @ ops.H1(A).toarray()) @ psi
+        tot = C[0] * c[:, 0]
+        assert np.sqrt(mctdhf.inner(ops, tot - psi, tot - psi).real) < 1e-11
+    # Hermitian H1: the norm is conserved
+    assert abs(mctdhf.inner(ops, psi, psi).real - 1) < 1e-12
