@@ -2,20 +2,26 @@
 """Throughput of the MCTDHF orbital time step on one MI355X.
 
 One step = the whole hot path at t_n: RDMs, pair Poisson solves (multipole
-boundary values + Jacobi PCG on all pairs), mean field U and the frozen
-operator G, m = 12 orbital right-hand-side evaluations inside the
-short-iterative Arnoldi exponential, integrals and the CI Lanczos step, and
-the observables.  `value` counts the Arnoldi right-hand-side evaluations as
-DoF x orbitals per second of whole-step wall time, inputs resident in HBM.
+boundary values + multigrid-preconditioned CG on all pairs), mean field U
+and the frozen operator G, m = 12 orbital right-hand-side evaluations inside
+the short-iterative Arnoldi exponential, integrals and the CI Lanczos step,
+and the observables.  `value` counts the Arnoldi right-hand-side evaluations
+as DoF x orbitals per second of whole-step wall time, inputs resident in HBM.
 
-Default workload: H2, Q3 elements, box [-30,30]^3, 12^3 coarse cells, three
-levels in 1.5-bohr balls at z = +-0.7 (66,635 DoF), 2 orbitals, 4
-determinants, sin^2 800 nm pulse of peak 0.0534 au, dt = 0.02, Krylov 12.
-`--workload h2o` runs the 1,517,876-DoF CAS(10e,8o) H2O mesh.
-`--workload h2x64` runs 64 H2 instances of uneven meshes (bond ~ U[1,2],
-refinement depth in {2,3,4}, E0 ~ U[0.02,0.06], seeded) as one batch in the
-same kernel launches, and times 64 sequential single-instance runs of the
-same instances on a bounded sample for the batched/sequential ratio.
+Default workload: the H2O-shaped molecule, Q3 elements on [-40,40]^3, 16^3
+coarse cells, 4 levels within 6.5 bohr of O and 3 of each H (1,517,876
+unknowns), 8 orbitals, CAS(10e,8o) = 3,136 determinants, sin^2 800 nm pulse
+of peak 0.0534 au, dt = 0.02, Krylov 12.  Its record also carries the H2
+workload (Q3, [-30,30]^3, 12^3 cells, 3 levels in 1.5-bohr balls at
+z = +-0.7, 66,635 unknowns, 2 orbitals, 4 determinants) under "h2", with the
+forward+adjoint against plain forward comparison on that molecule and mesh,
+and a measured device copy rate.
+`--workload h2` runs the H2 record alone (with the oracle's whole steps as the
+CPU baseline).  `--workload h2x64` runs 64 H2 instances of uneven meshes
+(bond ~ U[1,2], refinement depth in {2,3,4}, E0 ~ U[0.02,0.06], seeded) as one
+batch in the same kernel launches, and times 64 sequential single-instance
+runs of the same instances on a bounded sample for the batched/sequential
+ratio.
 """
 import argparse
 import glob
@@ -58,30 +64,70 @@ def initial_state(name, w, mesh, op, torch):
     return phi, torch.from_numpy(np.ascontiguousarray(C)).cuda()
 
 
-def spmv_bytes(N, ncol, nnz, n_inst, fused):
-    """Compulsory HBM bytes of one Poisson operator launch: x rows read and q rows
-    written once, the assembled operator once (column int32 + value), row
-    pointers; with the direction fused in (schedule bit 3) also r and the
-    previous direction read, the new direction written and D^-1 read."""
-    b = 16 * N * ncol + 12 * nnz + 4 * (N + n_inst)
+def stored_matrix_bytes(N, nnz, n_inst):
+    """Bytes of the assembled Poisson operator read by one plain pass (column
+    int32 + value per entry, row pointers): overhead of the assembled form,
+    not part of the algorithmic bytes."""
+    return 12 * nnz + 4 * (N + n_inst)
+
+
+def poisson_algorithmic_bytes(info, op, fused=False):
+    """Matrix-free bytes of one Poisson operator application on the pair
+    columns (the Laplacian applied cell by cell from the 1D Gauss-Lobatto
+    tables): operand rows read and result rows written once (8 B per column
+    each), the cell->node maps (int32), the hanging-node constraint rows (int32
+    index + weight) and h per cell.  With the CG direction formed in the same
+    pass (schedule bit 3) also r and the previous direction read, the new
+    direction written and the diagonal read."""
+    P3 = (info["p"] + 1) ** 3
+    N, ncol, nC = op.n_dof, op.n_pair_cols, info["n_cells"]
+    b = 16 * ncol * N + 4 * P3 * nC + 12 * info["hang_nnz"] + 8 * nC
     if fused:
-        b += 16 * N * ncol + 8 * N   # x is r then; + p_prev read, p written (8 ncol each), D^-1
+        b += 16 * ncol * N + 8 * N
     return b
 
 
-def algorithmic_bytes(kind, info, op, sched_poi=0):
-    """Compulsory HBM bytes of one launch of the dominant operator kernels:
-    every input row read once, every output row written once, index data once."""
+def rhs_algorithmic_bytes(info, op):
+    """B_G: bytes one orbital right-hand-side evaluation must move: the packed
+    vector in and G v out (16 B per complex entry each), the per-node
+    Hermitian mean-field matrix U (n^2 reals per full node), the per-node
+    potential and dipole weights, the cell->node maps, the constraint rows and
+    1/m of the unknowns.  The interface mass system is cache-resident."""
+    P3 = (info["p"] + 1) ** 3
+    n, N, NF, nC = op.n_orb, op.n_dof, info["n_full"], info["n_cells"]
+    return 32 * n * N + 8 * n * n * NF + 16 * NF + 4 * P3 * nC + 12 * info["hang_nnz"] + 8 * N
+
+
+def orbital_pass_bytes(info, op):
+    """Algorithmic bytes of the orbital operator's node pass alone (kernel
+    timing slot 0): orbitals in and out, U, the node tables."""
     P = info["p"] + 1
-    nC, NE, N, n, ncol = info["n_cells"], op.n_ext, op.n_dof, op.n_orb, op.n_pair_cols
-    meta = 32 * NE + 4 * P ** 3 * nC + 8 * nC + 4 * N          # node->cell table, cell maps, h/2, master index
-    if kind == "poisson_spmv":
-        return spmv_bytes(N, ncol, op.n_poisson_nnz, op.n_inst, bool(sched_poi & 8))
-    return 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + meta   # u, out, U, (m, v, mz), 1/m
+    nC, NE, N, n = info["n_cells"], op.n_ext, op.n_dof, op.n_orb
+    meta = 32 * NE + 4 * P ** 3 * nC + 8 * nC + 4 * N
+    return 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + meta
 
 
-def cpu_baseline(name, w, budget_s):
-    """The oracle, as it stands, on one step of the same workload."""
+def copy_bandwidth(torch, gib=2, reps=10):
+    """Measured device-to-device copy rate (a STREAM-copy figure): bytes read
+    plus bytes written per second over `reps` copies of `gib` GiB, event-timed
+    on the current stream."""
+    a = torch.empty((gib << 30) // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * (gib << 30) / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline_h2(w, budget_s):
+    """The oracle, as it stands, on whole time steps of the H2 workload."""
     import numpy as np
     import psutil
     from oracle.mesh import Mesh, MeshDesc, Ball
@@ -96,6 +142,7 @@ def cpu_baseline(name, w, budget_s):
     C = h2_ci_guess()
     pr = Propagator(ops, cs)
     pr.poisson.factor()            # one-off factorisation, as a warm-up would
+    ops.gradient()                 # and the derivative matrices of the momentum record
     Tp = w["cycles"] * 2 * np.pi / 0.0569542
     proc = psutil.Process()
     c0 = proc.cpu_times()
@@ -116,46 +163,91 @@ def cpu_baseline(name, w, budget_s):
             "host_threads_available": os.cpu_count()}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="h2", choices=["h2", "h2o", "h_atom", "h2x64"])
-    ap.add_argument("--batch", type=int, default=64, help="instances of the h2x64 workload")
-    ap.add_argument("--seq-steps", type=int, default=2, help="timed steps per instance of the sequential runs")
-    ap.add_argument("--graph", action="store_true", help="replay each step's fixed part as a HIP graph")
-    ap.add_argument("--no-sequential", action="store_true", help="h2x64: skip the sequential runs")
-    ap.add_argument("--counters", action="store_true",
-                    help="short run for hardware-counter passes: CG iterations and RHS applications on the "
-                         "workload's mesh, then a 1 GiB elementwise multiply for calibration; prints no JSON")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint vs plain comparison")
-    ap.add_argument("--tune-cache", default=None,
-                    help="JSON file of tuned schedules: read if it holds this workload, else written after tuning")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the whole mesh lives on one MI355X; "
-              "--gpus must be 1", file=sys.stderr)
-        sys.exit(2)
-    if args.counters:
-        return run_counters(args)
-    if args.workload == "h2x64":
-        return run_batch(args)
+def cpu_baseline_rhs_child(name, budget_s):
+    """Child process of the CPU baseline: the oracle, as it stands, applying
+    the frozen orbital right-hand side G of the workload.  Set-up first (its
+    own mesh, operators, sparse LU of the mass matrix and the frozen operator
+    with synthetic pair potentials: the oracle's direct Poisson solve does not
+    fit at this size, and the cost of a G application does not depend on the
+    potential values), then it waits for a line on stdin, so that its timed
+    sample of about `budget_s` seconds runs after the GPU's timed work, and
+    prints one JSON record."""
     import numpy as np
-    import torch
+    import psutil
+    from oracle.mesh import Mesh, MeshDesc, Ball
+    from oracle.fem import Operators
+    from oracle.ci import CISpace
+    from oracle.mctdhf import Frozen, orthonormalize
+    from synth import h2o_guess, random_ci
+    w = _workload(name)
+    t_set = time.perf_counter()
+    mesh = Mesh(MeshDesc(w["lo"], w["hi"], w["n_coarse"], w["p"], [Ball(**b) for b in w["balls"]]))
+    ops = Operators(mesh, w["nuclei"])
+    n = w["n_orb"]
+    cs = CISpace(n, w["n_alpha"], w["n_beta"])
+    c = orthonormalize(ops, h2o_guess(mesh.xyz[mesh.dof_nodes]))
+    gam, Gam = cs.rdms(random_ci(cs.dim, 7))
+    r = np.linalg.norm(mesh.xyz, axis=1)
+    W = {(a, b): (1.0 + 0.1 * (a + b)) / np.sqrt(r * r + 1.0) + 0j for a in range(n) for b in range(a, n)}
+    ops.mass_solve(c[:, :1])       # one-off factorisation of the mass matrix
+    fr = Frozen(ops, c, gam, Gam, 0.01, W)
+    t_set = time.perf_counter() - t_set
+    sys.stdin.readline()
+    proc = psutil.Process()
+    c0 = proc.cpu_times()
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        fr.G(c)
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    wall = time.perf_counter() - t0
+    c1 = proc.cpu_times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    print(json.dumps({
+        "value": k * mesh.n_dof * n / wall, "unit": "DoF*orbitals/s", "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": f"{k} orbital right-hand-side evaluations (G applications) of the same {mesh.n_dof}-unknown, "
+                  f"{n}-orbital workload, {wall:.1f} s wall, timed after the GPU's timed work; set-up "
+                  f"({t_set:.0f} s: mesh, operators, mass-matrix LU, frozen operator) ran in a child process "
+                  f"beside the GPU work; the oracle's direct Poisson solve does not fit at this size, so its "
+                  f"whole-step rate is not measured",
+        "setup_s": t_set, "host_threads_available": os.cpu_count()}), flush=True)
+
+
+def start_cpu_baseline(name, budget_s):
+    """Start the oracle's set-up in a child process (before this process
+    touches the GPU); finish_cpu_baseline releases its timed sample."""
+    import subprocess
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child", name, str(budget_s)],
+                            stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+
+
+def finish_cpu_baseline(proc):
+    out, _ = proc.communicate("go\n", timeout=1800)
+    lines = [ln for ln in out.splitlines() if ln.startswith("{")]
+    if proc.returncode != 0 or not lines:
+        raise RuntimeError(f"CPU baseline child failed (exit {proc.returncode})")
+    return json.loads(lines[-1])
+
+
+def run_single(name, args, torch, with_adjoint, with_cpu):
+    """Set-up, warm-up, autotuning and `args.steps` timed steps of one
+    workload; returns the bench record."""
+    import numpy as np
     import paper_2301_02387_amd as mh
     from synth import pulse
 
-    w = _workload(args.workload)
+    w = _workload(name)
     t_setup = time.perf_counter()
     mesh = mh.Mesh.from_workload(w)
     op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_rtol=1e-12,
                      poisson_maxit=20000)
     t_setup = time.perf_counter() - t_setup
+    log(f"{name}: set up in {t_setup:.1f} s, {op.n_dof} unknowns")
     info = mesh.info
-    phi, Ci = initial_state(args.workload, w, mesh, op, torch)
+    phi, Ci = initial_state(name, w, mesh, op, torch)
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     dt, m = w["dt"], w["krylov"]
     Tp = (w["cycles"] * 2 * np.pi / 0.0569542) if w["cycles"] else 1.0
@@ -171,6 +263,7 @@ def main():
     # schedules of the two operator kernels picked by the autotuner (untimed)
     from paper_2301_02387_amd.tune import autotune
     sched = autotune(op, phi, W, cache_file=args.tune_cache)
+    log(f"{name}: warm-up and tuning done, schedules {sched['orbital']} {sched['poisson']}")
     # timed region: exactly `steps` steps
     op.kernel_timing(0, True)
     op.kernel_timing(1, True)
@@ -181,7 +274,9 @@ def main():
     wall = time.perf_counter() - t_a
     k_orb = op.kernel_timing(0, False)
     k_poi = op.kernel_timing(1, False)
-    # Arnoldi step alone (G frozen at the last step), and one G application
+    log(f"{name}: {wall / args.steps * 1e3:.2f} ms per step")
+    # Arnoldi step alone (G frozen at the last step), and G applications by
+    # HIP event pairs on the stream the library launches on
     phi2 = phi.clone()
     reps = 5
     torch.cuda.synchronize()
@@ -194,21 +289,30 @@ def main():
     out = torch.empty_like(phi)
     reps_g = 20
     op.rhs_apply(phi, out)
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    for _ in range(reps_g):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps_g)]
+    for k in range(reps_g):
+        ev[2 * k].record()
         op.rhs_apply(phi, out)
+        ev[2 * k + 1].record()
     torch.cuda.synchronize()
-    rhs_ms = (time.perf_counter() - ta) / reps_g * 1e3
+    rhs_ms = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(reps_g)]))
 
     evals = args.steps * m * op.n_dof * op.n_orb
     kern = {"stencil_orb": {"avg_ms": k_orb[0], "count": k_orb[1]},
             "poisson_spmv": {"avg_ms": k_poi[0], "count": k_poi[1]}}
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["count"])
-    byts = algorithmic_bytes(dom, info, op, sched["poisson"][0])
+    fused = bool(sched["poisson"][0] & 8)
+    if dom == "poisson_spmv":
+        byts = poisson_algorithmic_bytes(info, op, fused)
+        over = stored_matrix_bytes(op.n_dof, op.n_poisson_nnz, op.n_inst)
+    else:
+        byts, over = orbital_pass_bytes(info, op), 0
     sched_tag = "/".join(map(str, sched["poisson"] if dom == "poisson_spmv" else sched["orbital"]))
     ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0
-    orb_b = algorithmic_bytes("stencil_orb", info, op)
+    wl = f"{name}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb"
+    bg = rhs_algorithmic_bytes(info, op)
+    rhs_ach = bg / (rhs_ms * 1e-3) / 1e9
+    orb_b = orbital_pass_bytes(info, op)
     orb_ach = orb_b / (k_orb[0] * 1e-3) / 1e9 if k_orb[0] > 0 else 0.0
     line = {
         "metric": "orbital-RHS evals/s (DoF x orbitals/s)",
@@ -223,9 +327,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb",
-                   "n_dof": op.n_dof, "n_cells": info["n_cells"], "n_orb": op.n_orb, "n_ci": op.n_ci,
-                   "krylov": m, "dt": dt, "parallelism": "none (one GPU)"},
+        "config": {"workload": wl, "n_dof": op.n_dof, "n_full": info["n_full"], "n_cells": info["n_cells"],
+                   "n_orb": op.n_orb, "n_ci": op.n_ci, "krylov": m, "dt": dt, "parallelism": "none (one GPU)"},
         "arnoldi_step_ms": arnoldi_ms,
         "rhs_apply_ms": rhs_ms,
         "rhs_evals_per_s_isolated": op.n_dof * op.n_orb / (rhs_ms * 1e-3),
@@ -236,19 +339,80 @@ def main():
         "kernels": kern,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, f"{args.workload}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb",
-                                                 schedule=sched_tag),
+                     "traffic": measured_traffic(dom, wl, schedule=sched_tag),
                      "schedule": sched_tag,
-                     "algorithmic_bytes_per_launch": byts},
-        # the orbital operator pass of every G application (without its mass solve)
+                     "algorithmic_bytes_per_launch": byts,
+                     "algorithmic_bytes": "matrix-free: operand and result rows, cell maps, constraint rows, h",
+                     "stored_operator_bytes_per_launch": over},
+        # one whole G application (node pass, stiffness, interface mass solve,
+        # hanging fill) against B_G, by event pairs around each call
+        "roofline_rhs": {"kernel": "rhs_apply (all launches of one G application)", "bound": "hbm",
+                         "achieved": rhs_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rhs_ach / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": bg},
+        # the orbital operator's node pass of every G application
         "roofline_orbital": {"kernel": "stencil_orb", "bound": "hbm", "achieved": orb_ach, "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": orb_ach / HBM_PEAK_GBS,
                              "schedule": "/".join(map(str, sched["orbital"])), "algorithmic_bytes_per_launch": orb_b},
     }
-    if not args.no_adjoint and args.workload == "h2":
+    if with_adjoint:
         line["fwd_adjoint_vs_plain"] = adjoint_ratio(op, phi, Ci, w)
-    if not args.no_cpu_baseline and args.workload == "h2":
-        line["cpu_baseline"] = cpu_baseline(args.workload, w, args.cpu_budget)
+    if with_cpu:   # the H2 workload's oracle takes whole steps (its direct Poisson solve fits)
+        line["cpu_baseline"] = cpu_baseline_h2(w, args.cpu_budget)
+    del op, mesh
+    return line
+
+
+def main():
+    if len(sys.argv) == 4 and sys.argv[1] == "--cpu-child":
+        return cpu_baseline_rhs_child(sys.argv[2], float(sys.argv[3]))
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="h2o", choices=["h2", "h2o", "h_atom", "h2x64"])
+    ap.add_argument("--batch", type=int, default=64, help="instances of the h2x64 workload")
+    ap.add_argument("--seq-steps", type=int, default=2, help="timed steps per instance of the sequential runs")
+    ap.add_argument("--graph", action="store_true", help="replay each step's fixed part as a HIP graph")
+    ap.add_argument("--no-sequential", action="store_true", help="h2x64: skip the sequential runs")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware-counter passes: CG iterations and RHS applications on the "
+                         "workload's mesh, then a 1 GiB elementwise multiply for calibration; prints no JSON")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint vs plain comparison")
+    ap.add_argument("--no-h2", action="store_true", help="h2o: skip the H2 workload's extra record")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned schedules: read if it holds this workload, else written after tuning")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the whole mesh lives on one MI355X; "
+              "--gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    if args.counters:
+        return run_counters(args)
+    if args.workload == "h2x64":
+        return run_batch(args)
+    child = None
+    if args.workload == "h2o" and not args.no_cpu_baseline:
+        child = start_cpu_baseline(args.workload, args.cpu_budget)   # before this process touches the GPU
+    import torch
+    line = run_single(args.workload, args, torch, with_adjoint=(args.workload == "h2" and not args.no_adjoint),
+                      with_cpu=(args.workload == "h2" and not args.no_cpu_baseline))
+    if args.workload == "h2o" and not args.no_h2:
+        # the H2 workload (also the differentiation workload's molecule and
+        # mesh): whole-step record and forward+adjoint against plain forward
+        h2 = run_single("h2", args, torch, with_adjoint=not args.no_adjoint, with_cpu=False)
+        line["h2"] = {k: h2[k] for k in ("value", "ms_per_step", "config", "arnoldi_step_ms", "rhs_apply_ms",
+                                         "poisson_cg_iters_per_step", "roofline", "roofline_rhs")}
+        if "fwd_adjoint_vs_plain" in h2:
+            line["fwd_adjoint_vs_plain"] = h2["fwd_adjoint_vs_plain"]
+    bw = copy_bandwidth(torch)
+    line["hbm_copy_measured_GBs"] = bw
+    for key in ("roofline", "roofline_rhs", "roofline_orbital"):
+        line[key]["frac_of_measured_copy"] = line[key]["achieved"] / bw
+    if child is not None:
+        line["cpu_baseline"] = finish_cpu_baseline(child)
+        line["rhs_isolated_vs_cpu_baseline"] = line["rhs_evals_per_s_isolated"] / line["cpu_baseline"]["value"]
     print(json.dumps(line))
 
 
@@ -468,7 +632,11 @@ def run_batch(args):
     evals = args.steps * m * op.n_dof * op.n_orb
     n_cells = sum(mm.info["n_cells"] for mm in meshes)
     ncol = op.n_pair_cols
-    spmv_b = spmv_bytes(op.n_dof, ncol, op.n_poisson_nnz, op.n_inst, bool(sched["poisson"][0] & 8))
+    # matrix-free bytes summed over the instances (one aggregate mesh record)
+    agg = {"p": w0["p"], "n_cells": n_cells, "hang_nnz": sum(mm.info["hang_nnz"] for mm in meshes),
+           "n_full": sum(mm.info["n_full"] for mm in meshes)}
+    spmv_b = poisson_algorithmic_bytes(agg, op, bool(sched["poisson"][0] & 8))
+    spmv_over = stored_matrix_bytes(op.n_dof, op.n_poisson_nnz, op.n_inst)
     P3 = (w0["p"] + 1) ** 3
     NE, N, n = op.n_ext, op.n_dof, op.n_orb
     orb_bytes = 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + 32 * NE + 4 * P3 * n_cells + 8 * n_cells + 4 * N
@@ -511,7 +679,9 @@ def run_batch(args):
                      "frac": ach / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, f"h2x{op.n_inst}_q3_{op.n_dof}dof_{op.n_orb}orb",
                                                  schedule="/".join(map(str, sched["poisson"]))),
-                     "schedule": "/".join(map(str, sched["poisson"])), "algorithmic_bytes_per_launch": byts},
+                     "schedule": "/".join(map(str, sched["poisson"])), "algorithmic_bytes_per_launch": byts,
+                     "algorithmic_bytes": "matrix-free: operand and result rows, cell maps, constraint rows, h",
+                     "stored_operator_bytes_per_launch": spmv_over if dom == "poisson_spmv" else 0},
         "roofline_orbital": {"kernel": "stencil_orb", "bound": "hbm",
                              "achieved": (orb_bytes / (k_orb[0] * 1e-3) / 1e9) if k_orb[0] > 0 else 0.0,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -50,6 +50,7 @@
 #ifndef MH_H
 #define MH_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -124,8 +125,13 @@ typedef struct {
   double poisson_rtol;        /* residual target of the pair Poisson CG: each column of an
                                  instance to |r| <= rtol x the largest |rhs| of its columns */
   int32_t poisson_maxit;      /* CG iteration cap */
-  double rdm_eps;             /* regularisation of the 1-RDM inverse */
+  double rdm_eps;             /* regularisation of the 1-RDM inverse (<= 0 selects 1e-10) */
+  int32_t gauge;              /* MH_GAUGE_LENGTH: field term E(t) e.r; MH_GAUGE_VELOCITY: term
+                                 -i A(t) e.grad (Sec. II one-body operator), the field values
+                                 passed to the calls below then being A(t) */
 } mh_op_desc;
+
+enum { MH_GAUGE_LENGTH = 0, MH_GAUGE_VELOCITY = 1 };
 
 /* Operator set-up (Sec. III.A): Gauss-Lobatto masses, stiffness data, the
  * lumped nuclear potential v_i = sum_cells int f_i V_nuc (six-pyramid Duffy
@@ -146,15 +152,23 @@ int mh_fill_hanging(mh_op* op, double* x, void* stream);
  * c: device c128 [N_E][n] output, hanging rows filled. */
 int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream);
 
-/* One-body load vector f = H1(E) c with H1(E) = K/2 + V_nuc + E (e.r) in
- * Galerkin form (Eq. discretized_eom, length gauge).  c: device c128
- * [N_E][n] (consistent); f: device c128 [N][n]. */
+/* One-body load vector f = H1 c in Galerkin form (Eq. discretized_eom):
+ * length gauge H1(E) = K/2 + V_nuc + E (e.r); velocity gauge
+ * H1(A) = K/2 + V_nuc - i A S_e, where the argument E is the vector
+ * potential A(t) along e and S_e = sum_d e_d S_d, S_d the antisymmetric part
+ * of the Gauss-Lobatto Galerkin derivative C^T D_d C (per cell
+ * (h/2)^2 (Qs x W x W) along x, Qs = (W D - (W D)^T)/2 from the 1D
+ * derivative matrix D and weights W; likewise along y and z; the A^2/2 term
+ * is dropped, a spatial constant).  c: device c128 [N_E][n] (consistent);
+ * f: device c128 [N][n]. */
 int mh_h1_apply(mh_op* op, const double* c, double E, double* f, void* stream);
 
 /* Pair Poisson solves (Sec. III.A): for every pair r <= s, solve
  * Laplace W_rs = -4 pi conj(phi_r) phi_s with Dirichlet values from the
  * multipole expansion (order lmax_bc, about the box centre) of the boundary
- * integral, by Jacobi-preconditioned CG on all pairs at once.
+ * integral, by preconditioned CG on all pairs at once: the preconditioner is
+ * the geometric multigrid V-cycle (Poisson schedule bit 4, the default and
+ * the autotuner's choice on every workload measured) or the diagonal.
  * phi: device c128 [N_E][n] (consistent).
  * W:   device double [N_F][n*n] real columns, column order: for r = 0..n-1,
  *      s = r..n-1: (r == s) one column Re W_rr; (r < s) two columns Re W_rs,
@@ -206,6 +220,10 @@ typedef struct {
   double* err_est;    /* Arnoldi error estimate (0 for the final record) */
   double* ortho;      /* max |S - I|, S_pq = <phi_p|phi_q> */
   int32_t* cg_iters;  /* Poisson CG iterations (all instances iterate together) */
+  double* momentum;   /* velocity form of the dipole: kinetic momentum along e,
+                         sum_pq gamma_pq <phi_p|-i e.grad|phi_q> (+ N A(t) in the
+                         velocity gauge), with the antisymmetric Gauss-Lobatto
+                         derivative of the velocity-gauge term */
 } mh_observables;
 
 /* Propagate orbitals and CI vector together for n_steps steps of size dt
@@ -224,11 +242,15 @@ typedef struct {
  * are those of the eager path.
  * phi: device c128 [N_E][n] in-out; Ci: device c128 [n_inst][N_CI] in-out;
  * E_steps: host double [n_steps + 1] (the last value is used for the final
- * record); instance i sees the field E0_i E_steps[k] (E0 = 1 for
+ * record; in the velocity gauge these are values of A(t)); instance i sees
+ * the field E0_i E_steps[k] (E0 = 1 for
  * mh_op_create).  obs: host arrays (any member may be NULL).  W_work: device
  * double [N_F][n*n] Poisson warm-start buffer (in-out, may hold zeros); the
- * first step of a call starts CG from it, later steps from the linear
- * extrapolation 2 W_n - W_{n-1} of the two previous solutions.
+ * first two steps of a call start CG from the previous solution (from W_work
+ * at the first), the third from the linear extrapolation 2 W_n - W_{n-1} and
+ * later steps from the quadratic extrapolation 3 W_n - 3 W_{n-1} + W_{n-2}
+ * of the previous solutions.  MH_NONFINITE if an observable of a step is not
+ * finite (NaN or Inf in the orbitals or CI vector).
  * Synchronises `stream`. */
 enum { MH_PROP_IMAGINARY = 1, MH_PROP_NO_FINAL = 2, MH_PROP_GRAPH = 4 };
 int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const double* E_steps,
@@ -258,7 +280,8 @@ int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const doubl
  * E_steps: host [N + 1]; dJ_dd: host [N + 1]; dJ_dE: host out [N].
  * Allocates its checkpoint and work vectors per call.  MH_UNSUPPORTED for a
  * batch of several instances, more than 4 orbitals or more than 12
- * determinants (the CI exponential must be exact); MH_NOT_CONVERGED when a
+ * determinants (the CI exponential must be exact), or the velocity gauge;
+ * MH_NOT_CONVERGED when a
  * Poisson solve stopped at the iteration cap (the gradient is still
  * returned).  Synchronises `stream`. */
 int mh_propagate_adjoint(mh_op* op, const double* phi0, const double* Ci0, double* W_work,

@@ -41,13 +41,14 @@ class _OpDesc(C.Structure):
     _fields_ = [("n_nuclei", C.c_int32), ("charges", C.POINTER(C.c_double)),
                 ("positions", C.POINTER(C.c_double)), ("n_orb", C.c_int32), ("n_alpha", C.c_int32),
                 ("n_beta", C.c_int32), ("polarization", C.c_double * 3), ("lmax_bc", C.c_int32),
-                ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int32), ("rdm_eps", C.c_double)]
+                ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int32), ("rdm_eps", C.c_double),
+                ("gauge", C.c_int32)]
 
 
 class _Obs(C.Structure):
     _fields_ = [("dipole", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double)),
                 ("err_est", C.POINTER(C.c_double)), ("ortho", C.POINTER(C.c_double)),
-                ("cg_iters", C.POINTER(C.c_int32))]
+                ("cg_iters", C.POINTER(C.c_int32)), ("momentum", C.POINTER(C.c_double))]
 
 
 class _Sizes(C.Structure):
@@ -216,12 +217,16 @@ class Mesh:
             self._h = None
 
 
-def _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit, rdm_eps):
+GAUGES = {"length": 0, "velocity": 1}
+
+
+def _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit, rdm_eps,
+             gauge="length"):
     Z = np.array([z for z, _ in nuclei], dtype=np.float64)
     R = np.ascontiguousarray(np.array([r for _, r in nuclei], dtype=np.float64).reshape(-1, 3))
     desc = _OpDesc(len(nuclei), Z.ctypes.data_as(C.POINTER(C.c_double)), R.ctypes.data_as(C.POINTER(C.c_double)),
                    int(n_orb), int(n_alpha), int(n_beta), (C.c_double * 3)(*polarization), int(lmax_bc),
-                   float(poisson_rtol), int(poisson_maxit), float(rdm_eps))
+                   float(poisson_rtol), int(poisson_maxit), float(rdm_eps), GAUGES[gauge])
     return desc, (Z, R)
 
 
@@ -229,17 +234,17 @@ class Operator:
     """Operator set-up and device entry points (see include/mh.h)."""
 
     def __init__(self, mesh, nuclei, n_orb, n_alpha, n_beta, polarization=(0.0, 0.0, 1.0), lmax_bc=12,
-                 poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, stream=None):
+                 poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", stream=None):
         lib = load_library()
         desc, keep = _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol,
-                              poisson_maxit, rdm_eps)
+                              poisson_maxit, rdm_eps, gauge)
         h = C.c_void_p()
         _check(lib.mh_op_create(mesh._h, C.byref(desc), _stream(stream), C.byref(h)))
         self._attach(h, [mesh])
 
     @classmethod
     def batch(cls, meshes, nuclei_list, n_orb, n_alpha, n_beta, field_scale=None, polarization=(0.0, 0.0, 1.0),
-              lmax_bc=12, poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, stream=None):
+              lmax_bc=12, poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", stream=None):
         """Batch of independent instances (mh_batch_create): one mesh and one
         molecule per instance, one shared orbital/electron space."""
         lib = load_library()
@@ -250,7 +255,7 @@ class Operator:
         keep = []
         for i, nuc in enumerate(nuclei_list):
             d, k = _op_desc(nuc, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit,
-                            rdm_eps)
+                            rdm_eps, gauge)
             descs[i] = d
             keep.append(k)
         hs = (C.c_void_p * ni)(*[m._h.value for m in meshes])
@@ -351,11 +356,11 @@ class Operator:
         E = np.ascontiguousarray(E_steps, dtype=np.float64)
         n_steps = len(E) - 1
         shape = (n_steps + 1,) if self.n_inst == 1 else (n_steps + 1, self.n_inst)
-        rec = {k: np.zeros(shape) for k in ("dipole", "energy", "err_est", "ortho")}
+        rec = {k: np.zeros(shape) for k in ("dipole", "energy", "err_est", "ortho", "momentum")}
         rec["cg_iters"] = np.zeros(n_steps + 1, dtype=np.int32)
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
         obs = _Obs(dp(rec["dipole"]), dp(rec["energy"]), dp(rec["err_est"]), dp(rec["ortho"]),
-                   rec["cg_iters"].ctypes.data_as(C.POINTER(C.c_int32)))
+                   rec["cg_iters"].ctypes.data_as(C.POINTER(C.c_int32)), dp(rec["momentum"]))
         rc = _check(_lib.mh_propagate(self._h, _ptr(phi), _ptr(Ci), _ptr(W), E.ctypes.data_as(C.c_void_p),
                                       n_steps, float(dt), int(m),
                                       (1 if imaginary else 0) | (0 if final else 2) | (4 if graph else 0),

@@ -135,6 +135,7 @@ struct mh_op {
   double** Qdev = nullptr;
   Krylov KC;
   double* gam = nullptr, *Gam = nullptr, *hmat = nullptr, *gint = nullptr, *S = nullptr, *zmat = nullptr;
+  double* pmat = nullptr;   // [ni][n][n] c128: <phi_p| -i S_e |phi_q> (momentum along e)
   double* obs = nullptr;    // [ni][8]
   double* Rinv = nullptr;
   double* Wprev = nullptr;  // [tF][n*n] potentials of the previous step (start extrapolation)
@@ -468,10 +469,16 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
     d.vnn = nuclear_repulsion(spec[i].nuc);
     for (int k = 0; k < 16; ++k) d.A[k] = 0.0;
     for (int k = 0; k < 4; ++k) d.w[k] = 0.0;
+    for (int k = 0; k < 16; ++k) d.Qs[k] = 0.0;
     for (int a = 0; a < M.P; ++a) {
       d.w[a] = M.gll.w[a];
-      for (int b = 0; b < M.P; ++b) d.A[a * M.P + b] = M.gll.A[a * M.P + b];
+      for (int b = 0; b < M.P; ++b) {
+        d.A[a * M.P + b] = M.gll.A[a * M.P + b];
+        d.Qs[a * M.P + b] = M.gll.Qs[a * M.P + b];
+      }
     }
+    for (int k = 0; k < 3; ++k) d.pol[k] = spec[i].pol[k];
+    d.gauge = desc.gauge;
     if (i == 0) mx = d;
     mx.nC = std::max(mx.nC, d.nC);
     mx.N = std::max(mx.N, d.N);
@@ -544,6 +551,7 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   op->gint = op->alloc<double>(ni * 2 * n4);
   op->S = op->alloc<double>(ni * 2 * nn);
   op->zmat = op->alloc<double>(ni * 2 * nn);
+  op->pmat = op->alloc<double>(ni * 2 * nn);
   op->obs = op->alloc<double>(ni * 8);
   op->Rinv = op->alloc<double>(ni * 2 * nn);
   op->hostpin_len = (size_t)ni * std::max((8 + RED_SLOTS) * ncol, 64) + 4096;
@@ -604,6 +612,7 @@ static int check_desc(const mh_op_desc* desc) {
     return fail(MH_INVALID_ARG, "nuclei");
   const int lmax = desc->lmax_bc > 0 ? desc->lmax_bc : 12;
   if (lmax > 12) return fail(MH_UNSUPPORTED, "lmax_bc must be <= 12");
+  if (desc->gauge != MH_GAUGE_LENGTH && desc->gauge != MH_GAUGE_VELOCITY) return fail(MH_INVALID_ARG, "gauge");
   if ((lmax + 1) * (lmax + 1) * desc->n_orb * desc->n_orb > 48 * 256)
     return fail(MH_UNSUPPORTED, "multipole table too large");
   return MH_OK;
@@ -644,8 +653,9 @@ extern "C" int mh_batch_create(const mh_mesh* const* meshes, const mh_op_desc* d
     if (rc != MH_OK) return rc;
     const mh_op_desc& a = descs[0];
     const mh_op_desc& b = descs[i];
-    if (a.n_orb != b.n_orb || a.n_alpha != b.n_alpha || a.n_beta != b.n_beta || a.lmax_bc != b.lmax_bc)
-      return fail(MH_INVALID_ARG, "instances of a batch must share n_orb, electron counts and lmax_bc");
+    if (a.n_orb != b.n_orb || a.n_alpha != b.n_alpha || a.n_beta != b.n_beta || a.lmax_bc != b.lmax_bc ||
+        a.gauge != b.gauge)
+      return fail(MH_INVALID_ARG, "instances of a batch must share n_orb, electron counts, lmax_bc and the gauge");
     if (meshes[i]->M.P != meshes[0]->M.P) return fail(MH_INVALID_ARG, "instances of a batch must share p");
   }
   return guarded([&]() -> int {
@@ -1158,7 +1168,9 @@ static void step_after_poisson(mh_op* op, double* phi, double* Ci, const double*
   launch_gint_full(B, phi, W, op->colmap, op->gpart, gint_blocks(B), op->Gtmp, op->gint, s);
   launch_gram(B, phi, phi, WT_MASS, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), op->S, s);
   launch_gram(B, phi, phi, WT_DIPOLE, ROWS_EXT, op->gpart, gram_blocks(B.mx.NE), op->zmat, s);
-  launch_observe(B, op->gam, op->Gam, op->hmat, op->gint, op->zmat, op->S, op->obs, s);
+  load_vector(op, phi, op->Ebuf, 4, op->F, s);   // -i S_e phi: momentum along e
+  launch_gram(B, phi, op->F, WT_NONE, ROWS_DOF, op->gpart, gram_blocks(B.mx.N), op->pmat, s);
+  launch_observe(B, op->gam, op->Gam, op->hmat, op->gint, op->zmat, op->S, op->pmat, op->Ebuf, op->obs, s);
   if (!advance) return;
   arnoldi(op, phi, tre, tim, m, s);
   launch_ci_hprime(op->ni, op->ci, op->hmat, op->gint, s);
@@ -1270,6 +1282,7 @@ extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const
           if (obs->dipole) obs->dipole[o] = hs[8 * i + 1];
           if (obs->energy) obs->energy[o] = hs[8 * i];
           if (obs->ortho) obs->ortho[o] = hs[8 * i + 2];
+          if (obs->momentum) obs->momentum[o] = hs[8 * i + 3];
           if (obs->err_est) obs->err_est[o] = advance ? hk[8 * i + 3] : 0.0;
         }
         if (obs->cg_iters) obs->cg_iters[step] = it;
@@ -1450,6 +1463,7 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
   if (op->ni != 1) return fail(MH_UNSUPPORTED, "the adjoint takes a single instance");
   if (op->n > 4) return fail(MH_UNSUPPORTED, "the adjoint is implemented for at most 4 orbitals");
   if (op->ci.dim > 12) return fail(MH_UNSUPPORTED, "the adjoint needs an exact CI exponential (at most 12 determinants)");
+  if (op->B.mx.gauge != MH_GAUGE_LENGTH) return fail(MH_UNSUPPORTED, "the adjoint is implemented in the length gauge");
   if (n_steps < 1 || m < 1 || m > 24 || n_quad < 1 || n_quad > 16) return fail(MH_INVALID_ARG, "bad sizes");
   return guarded([&]() -> int {
     hipStream_t s = S(stream);

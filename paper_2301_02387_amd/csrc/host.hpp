@@ -6,11 +6,13 @@
 
 namespace mh {
 
-// Gauss-Lobatto-Legendre nodes/weights on [-1,1] and the 1D stiffness
-// A_ab = sum_q w_q l_a'(x_q) l_b'(x_q) (Sec. III.A element basis/quadrature).
+// Gauss-Lobatto-Legendre nodes/weights on [-1,1], the 1D stiffness
+// A_ab = sum_q w_q l_a'(x_q) l_b'(x_q) (Sec. III.A element basis/quadrature)
+// and the antisymmetric part of the 1D first-derivative form,
+// Qs_ab = (w_a l_b'(x_a) - w_b l_a'(x_b)) / 2 (velocity-gauge term).
 struct Gll {
   int p = 0;
-  std::vector<double> x, w, A;  // A row-major (p+1)^2
+  std::vector<double> x, w, A, Qs;  // A, Qs row-major (p+1)^2
 };
 Gll make_gll(int p);
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);  // on [-1,1]

@@ -109,6 +109,10 @@ Gll make_gll(int p) {
       for (int q = 0; q < P; ++q) s += g.w[q] * lagrange_d(g.x, a, g.x[q]) * lagrange_d(g.x, b, g.x[q]);
       g.A[a * P + b] = s;
     }
+  g.Qs.assign(P * P, 0.0);
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < P; ++b)
+      g.Qs[a * P + b] = 0.5 * (g.w[a] * lagrange_d(g.x, b, g.x[a]) - g.w[b] * lagrange_d(g.x, a, g.x[b]));
   return g;
 }
 

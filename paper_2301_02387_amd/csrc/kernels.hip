@@ -1494,11 +1494,12 @@ void launch_ginv(int ni, const double* gamma, int n, double eps, double* ginv, i
   hipLaunchKernelGGL(k_ginv, dim3(ni), dim3(64), 0, s, (const double2*)gamma, n, eps, (double2*)ginv, flag);
 }
 
-// out[i]: [0] energy, [1] dipole, [2] max |S - I|
+// out[i]: [0] energy, [1] dipole, [2] max |S - I|, [3] kinetic momentum along
+// e (sum gamma_pq <phi_p|-i S_e|phi_q>, plus N A in the velocity gauge)
 __global__ void k_observe(const DevMesh* __restrict__ dm, const double2* __restrict__ gamma,
                           const double2* __restrict__ Gamma, const double2* __restrict__ h,
                           const double2* __restrict__ g, const double2* __restrict__ z, const double2* __restrict__ S,
-                          double* __restrict__ out) {
+                          const double2* __restrict__ pm, const double* __restrict__ Ef, double* __restrict__ out) {
   if (threadIdx.x != 0) return;
   const int inst = blockIdx.x;
   const DevMesh& d = dm[inst];
@@ -1509,11 +1510,14 @@ __global__ void k_observe(const DevMesh* __restrict__ dm, const double2* __restr
   g += (int64_t)inst * nn * nn;
   z += (int64_t)inst * nn;
   S += (int64_t)inst * nn;
+  pm += (int64_t)inst * nn;
   out += 8 * inst;
-  double e1 = 0.0, e2 = 0.0, dip = 0.0, orth = 0.0;
+  double e1 = 0.0, e2 = 0.0, dip = 0.0, orth = 0.0, mom = 0.0, tr = 0.0;
   for (int i = 0; i < nn; ++i) {
     e1 += h[i].x * gamma[i].x - h[i].y * gamma[i].y;
     dip += gamma[i].x * z[i].x - gamma[i].y * z[i].y;
+    mom += gamma[i].x * pm[i].x - gamma[i].y * pm[i].y;
+    if (i % (n + 1) == 0) tr += gamma[i].x;
     int p = i / n, q = i % n;
     double dx = S[i].x - (p == q ? 1.0 : 0.0);
     orth = fmax(orth, hypot(dx, S[i].y));
@@ -1522,12 +1526,15 @@ __global__ void k_observe(const DevMesh* __restrict__ dm, const double2* __restr
   out[0] = e1 + 0.5 * e2 + d.vnn;
   out[1] = dip;
   out[2] = orth;
+  out[3] = mom + (d.gauge == 1 ? tr * Ef[0] * d.E0 : 0.0);
 }
 
 void launch_observe(const Batch& b, const double* gamma, const double* Gamma, const double* h, const double* g,
-                    const double* zmat, const double* S, double* out, hipStream_t s) {
+                    const double* zmat, const double* S, const double* pmat, const double* Ef, double* out,
+                    hipStream_t s) {
   hipLaunchKernelGGL(k_observe, dim3(b.ni), dim3(64), 0, s, b.dm, (const double2*)gamma, (const double2*)Gamma,
-                     (const double2*)h, (const double2*)g, (const double2*)zmat, (const double2*)S, out);
+                     (const double2*)h, (const double2*)g, (const double2*)zmat, (const double2*)S,
+                     (const double2*)pmat, Ef, out);
 }
 
 // Gram-Schmidt in M as x <- x R^-1 with S = R^H R (Cholesky), R upper.

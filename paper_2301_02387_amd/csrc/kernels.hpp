@@ -77,6 +77,9 @@ struct DevMesh {
   int sched_orb = 1, sched_poi = 13, grid_orb = 65536, grid_poi = 8192;
   double A[16];                         // 1D stiffness (P x P, P <= 4)
   double w[4];                          // GLL weights
+  double Qs[16];                        // antisymmetric 1D first-derivative form (P x P)
+  double pol[3] = {0.0, 0.0, 1.0};      // unit field direction e
+  int gauge = 0;                        // 0: length (E(t) e.r), 1: velocity (-i A(t) e.grad)
 };
 
 // Rows of the assembled Poisson operator longer than this are handled by whole
@@ -97,11 +100,14 @@ struct Batch {
 };
 
 // ---- orbital-space operator -------------------------------------------------
-// Node-centric operator (no atomics); diag_mode 0: K/2 only, 1: + v + E mz,
-// 2: + mean field, 3: mz only.  mode 0: load vector F; 1: M^-1 F; 2: M^-1 F
-// - v lam.  Non-master DoFs are final in out; masters and hanging nodes go to
-// acc.  E is read from the device scalar *Ef (times each instance's E0).
-// Orbital schedule bit 2: the stiffness part by the assembled K~ (kq, kred scratch).
+// Node-centric operator (no atomics); diag_mode 0: K/2 only, 1: + v + E mz
+// (length gauge) or + v - i A S_e (velocity gauge, the field value being A),
+// 2: + mean field, 3: mz only, 4: -i S_e only (momentum along e).  mode 0:
+// load vector F; 1: M^-1 F; 2: M^-1 F - v lam.  Non-master DoFs are final in
+// out; masters and hanging nodes go to acc.  E is read from the device scalar
+// *Ef (times each instance's E0).  Orbital schedule bit 2: the stiffness part
+// by the assembled K~ (kq, kred scratch); not taken where the velocity term
+// or the momentum is applied (those run node by node).
 void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
                         const double* ginv, int mode, const double* lam, double* out, double* acc, double* kq,
                         double* kred, hipStream_t s);
@@ -218,7 +224,8 @@ void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_b
 // ---- small dense work (one workgroup per instance) ------------------------------------
 void launch_ginv(int ni, const double* gamma, int n, double eps, double* ginv, int* flag, hipStream_t s);
 void launch_observe(const Batch& b, const double* gamma, const double* Gamma, const double* h, const double* g,
-                    const double* zmat, const double* S, double* out, hipStream_t s);
+                    const double* zmat, const double* S, const double* pmat, const double* Ef, double* out,
+                    hipStream_t s);
 void launch_orthonormalize_full(const Batch& b, const double* S, double* Rinv, double* x, hipStream_t s);
 
 // ---- CI (one space shared by the instances; vectors [ni][dim]) ---------------------------

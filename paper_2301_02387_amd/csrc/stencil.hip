@@ -40,7 +40,11 @@ namespace mh {
 // rows (constraints folded in, so hanging rows carry no stiffness and the
 // masters already hold their hanging neighbours' share); the node then only
 // adds its diagonal and mean-field terms.
-template <int P, int L, bool ASM>
+// VEL: the first-derivative term -i a.S u of the velocity gauge (a = A(t) e,
+// or e alone for the momentum, diag_mode 4), S the Gauss-Lobatto Galerkin
+// derivative in its antisymmetric form: per cell (h/2)^2 (Qs x W x W) along x
+// and likewise along y and z, so its line sums share the stiffness's loads.
+template <int P, int L, bool ASM, bool VEL>
 __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ dm, const double2* __restrict__ u,
                                                     const double* __restrict__ Ef, int diag_mode,
                                                     const double* __restrict__ Upk, const double2* __restrict__ ginv,
@@ -61,6 +65,11 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
   ginv += (int64_t)blockIdx.y * n * n;
   if (lam) lam += (int64_t)blockIdx.y * n * n;
   const double E = (diag_mode == 1 || diag_mode == 2) ? Ef[0] * d.E0 : 0.0;
+  // velocity term: vector potential a = A e (diag_mode 4: a = e); no stiffness for diag_mode 4
+  const double av = diag_mode == 4 ? 1.0 : E;
+  const double ax = VEL ? av * d.pol[0] : 0.0, ay = VEL ? av * d.pol[1] : 0.0, az = VEL ? av * d.pol[2] : 0.0;
+  const bool stiff = diag_mode <= 2;
+  const double Elen = d.gauge == 1 ? 0.0 : E;   // the length-gauge term only in the length gauge
   const XcdSweep sw = xcd_sweep(d.NE, NT / L, d.sched_orb & 1);
   // all L lanes of a node share i, so a node group enters and leaves together
   for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
@@ -89,23 +98,45 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
       const int a = loc % P, b = (loc / P) % P, c = loc / (P * P);
       const auto* cn = gbl(d.cell_nodes) + K * P3;
       double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
+      double2 t0 = s0, t1 = s0, t2 = s0;
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         const int j0 = cn[(c * P + b) * P + q], j1 = cn[(c * P + q) * P + a], j2 = cn[(q * P + b) * P + a];
         const double A0 = d.A[a * P + q], A1 = d.A[b * P + q], A2 = d.A[c * P + q];
         if (act) {
-          if (j0 < d.NE) { const double2 v = u[(int64_t)j0 * n + p]; s0.x += A0 * v.x; s0.y += A0 * v.y; }
-          if (j1 < d.NE) { const double2 v = u[(int64_t)j1 * n + p]; s1.x += A1 * v.x; s1.y += A1 * v.y; }
-          if (j2 < d.NE) { const double2 v = u[(int64_t)j2 * n + p]; s2.x += A2 * v.x; s2.y += A2 * v.y; }
+          if (j0 < d.NE) {
+            const double2 v = u[(int64_t)j0 * n + p];
+            s0.x += A0 * v.x; s0.y += A0 * v.y;
+            if (VEL) { const double Q = d.Qs[a * P + q]; t0.x += Q * v.x; t0.y += Q * v.y; }
+          }
+          if (j1 < d.NE) {
+            const double2 v = u[(int64_t)j1 * n + p];
+            s1.x += A1 * v.x; s1.y += A1 * v.y;
+            if (VEL) { const double Q = d.Qs[b * P + q]; t1.x += Q * v.x; t1.y += Q * v.y; }
+          }
+          if (j2 < d.NE) {
+            const double2 v = u[(int64_t)j2 * n + p];
+            s2.x += A2 * v.x; s2.y += A2 * v.y;
+            if (VEL) { const double Q = d.Qs[c * P + q]; t2.x += Q * v.x; t2.y += Q * v.y; }
+          }
         }
       }
-      const double hh = 0.5 * gbl(d.cell_hh)[K];  // (1/2) K with K_cell = (h/2)(...)
-      const double f0 = hh * d.w[b] * d.w[c], f1 = hh * d.w[a] * d.w[c], f2 = hh * d.w[a] * d.w[b];
-      y.x += f0 * s0.x + f1 * s1.x + f2 * s2.x;
-      y.y += f0 * s0.y + f1 * s1.y + f2 * s2.y;
+      const double hk = gbl(d.cell_hh)[K];  // h/2
+      if (stiff) {
+        const double hh = 0.5 * hk;  // (1/2) K with K_cell = (h/2)(...)
+        const double f0 = hh * d.w[b] * d.w[c], f1 = hh * d.w[a] * d.w[c], f2 = hh * d.w[a] * d.w[b];
+        y.x += f0 * s0.x + f1 * s1.x + f2 * s2.x;
+        y.y += f0 * s0.y + f1 * s1.y + f2 * s2.y;
+      }
+      if (VEL) {  // y += -i (h/2)^2 (ax Wb Wc t0 + ay Wa Wc t1 + az Wa Wb t2)
+        const double h2 = hk * hk;
+        const double g0 = h2 * ax * d.w[b] * d.w[c], g1 = h2 * ay * d.w[a] * d.w[c], g2 = h2 * az * d.w[a] * d.w[b];
+        y.x += g0 * t0.y + g1 * t1.y + g2 * t2.y;
+        y.y -= g0 * t0.x + g1 * t1.x + g2 * t2.x;
+      }
     }
-    if (diag_mode >= 1 && act) {
-      const double dg = diag_mode == 3 ? gbl(d.mz)[i] : gbl(d.v)[i] + E * gbl(d.mz)[i];
+    if (diag_mode >= 1 && diag_mode <= 3 && act) {
+      const double dg = diag_mode == 3 ? gbl(d.mz)[i] : gbl(d.v)[i] + Elen * gbl(d.mz)[i];
       y.x += dg * ui.x;
       y.y += dg * ui.y;
     }
@@ -241,14 +272,19 @@ static void launch_stencil_orb_t(const Batch& b, const double* u, const double* 
                                  const double* ginv, int mode, const double* lam, double* out, double* acc,
                                  const double* kq, hipStream_t s) {
   const int grid = xcd_grid(b.mx.NE, NT / L, b.mx.grid_orb);
+  const bool vel = diag_mode == 4 || (b.mx.gauge == 1 && (diag_mode == 1 || diag_mode == 2));
   if (kq)
-    hipLaunchKernelGGL((k_stencil_orb<P, L, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u, Ef,
-                       diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out, (double2*)acc,
-                       (const double2*)kq);
+    hipLaunchKernelGGL((k_stencil_orb<P, L, true, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u,
+                       Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out,
+                       (double2*)acc, (const double2*)kq);
+  else if (vel)
+    hipLaunchKernelGGL((k_stencil_orb<P, L, false, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u,
+                       Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out,
+                       (double2*)acc, (const double2*)nullptr);
   else
-    hipLaunchKernelGGL((k_stencil_orb<P, L, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u, Ef,
-                       diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out, (double2*)acc,
-                       (const double2*)nullptr);
+    hipLaunchKernelGGL((k_stencil_orb<P, L, false, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u,
+                       Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out,
+                       (double2*)acc, (const double2*)nullptr);
 }
 
 template <int P>
@@ -270,7 +306,9 @@ static void launch_stencil_orb_p(const Batch& b, const double* u, const double* 
 void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
                         const double* ginv, int mode, const double* lam, double* out, double* acc, double* kq,
                         double* kred, hipStream_t s) {
-  const bool asm_k = (b.mx.sched_orb & 4) && kq && kred;
+  // the velocity term and the momentum run node by node (their line sums share the stiffness's loads)
+  const bool vel = diag_mode == 4 || (b.mx.gauge == 1 && (diag_mode == 1 || diag_mode == 2));
+  const bool asm_k = (b.mx.sched_orb & 4) && kq && kred && !vel;
   if (asm_k && diag_mode != 3) {
     PoissonWs Pk;
     Pk.red = kred;

@@ -74,6 +74,14 @@ def small_workload(name, seed=0):
         return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
                     balls=[_ball(rng.uniform(-1, 1, 3), 1.0, 1)],
                     nuclei=[(3.0, (0.0, 0.0, 0.0))], n_orb=8, n_alpha=1, n_beta=1)
+    if name == "tiny_n8_2a2b":   # eight orbitals, 2 alpha + 2 beta electrons: C(8,2)^2 = 784 determinants
+        return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                    balls=[_ball(rng.uniform(-1, 1, 3), 1.0, 1)],
+                    nuclei=[(4.0, (0.0, 0.0, 0.0))], n_orb=8, n_alpha=2, n_beta=2)
+    if name == "small_n6":       # six orbitals, 3 alpha + 3 beta electrons: C(6,3)^2 = 400 determinants
+        return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
+                    balls=[_ball((0.2, -0.3, 0.1), 1.5, 2)],
+                    nuclei=[(6.0, (0.0, 0.0, 0.0))], n_orb=6, n_alpha=3, n_beta=3)
     if name == "h2_hmesh":  # H2 (nuclei at z = +-0.7, 2 orbitals) on the H-atom workload's Q2 mesh
         return dict(name=name, lo=-20.0, hi=20.0, n_coarse=8, p=2,
                     balls=[_ball((0, 0, 0), 2.0, 2)],

@@ -82,3 +82,25 @@ def rel_err_cols(a, b):
     a = np.asarray(a).reshape(len(a), -1)
     b = np.asarray(b).reshape(len(b), -1)
     return max(np.linalg.norm(a[:, j] - b[:, j]) / max(np.linalg.norm(b[:, j]), 1e-300) for j in range(b.shape[1]))
+
+
+def max_rel_cols(a, b):
+    """max over columns of max_i |a_ij - b_ij| / max_i |b_ij|: an element-wise
+    check beside the column 2-norms, so that a few wrong rows (hanging,
+    master or boundary-lift rows) of a large mesh cannot hide in a norm."""
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return max(np.abs(a[:, j] - b[:, j]).max() / max(np.abs(b[:, j]).max(), 1e-300) for j in range(b.shape[1]))
+
+
+_SOLVERS = {}
+
+
+def poisson_solver(ops):
+    """The oracle's Poisson solver of one operator set, factorised once and
+    shared by the tests (the sparse LU of the H2 mesh takes tens of seconds)."""
+    from oracle.poisson import PoissonSolver
+    key = id(ops)
+    if key not in _SOLVERS:
+        _SOLVERS[key] = (ops, PoissonSolver(ops))
+    return _SOLVERS[key][1]

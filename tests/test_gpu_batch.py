@@ -242,3 +242,72 @@ def test_batch_multigrid_mixed_depths():
                     assert num / den < 1e-9, (sched, rep, i, k, num / den)
     print("mixed-depth batch CG iterations", its, flush=True)
     assert its[21] < its[13] and its[53] < its[13], its
+
+
+def test_batch_workload_instances_equal_plain_runs():
+    """Three instances of the 64-molecule workload itself (refinement depths
+    2, 3 and 4: 45k-120k unknowns each) propagated as one batch and each on
+    its own plain operator, with the same schedules (the interface mass block
+    by Chebyshev on both sides) and the same inputs.  The two runs differ
+    only in the order of FP64 atomic sums (Poisson boundary lift, CG
+    accumulators), the Chebyshev count (the batch takes the largest) and the
+    CG iteration count (the batch iterates until every instance has met the
+    1e-13 target), so dipoles, energies, orbitals and CI vectors agree to the
+    CG target, not bitwise: measured up to 2.4e-12 (orbitals, relative), 2e-13
+    (CI vector), 7e-14 (energies, relative) and 6e-13 bohr (dipoles), so the
+    gate is 1e-11."""
+    torch = _torch()
+    import paper_2301_02387_amd as mh
+    from synth import batch_instances, h2_guess, h2_ci_guess
+    ws, seen = [], set()
+    for i, w in enumerate(batch_instances()):
+        depth = w["balls"][0]["levels"]
+        if depth not in seen:
+            seen.add(depth)
+            ws.append(w)
+    assert sorted(w["balls"][0]["levels"] for w in ws) == [2, 3, 4]
+    meshes = [mh.Mesh.from_workload(w) for w in ws]
+    kw = dict(poisson_rtol=1e-13, poisson_maxit=20000)
+    E0 = [w["E0"] for w in ws]
+    batch = mh.Operator.batch(meshes, [w["nuclei"] for w in ws], 2, 1, 1, field_scale=E0, **kw)
+    plains = [mh.Operator(m, w["nuclei"], 2, 1, 1, **kw) for m, w in zip(meshes, ws)]
+    xs = []
+    for m, w, op in zip(meshes, ws, plains):
+        NE = op.n_ext
+        xyz = m.coords()[:NE]
+        x = torch.from_numpy(np.ascontiguousarray(h2_guess(xyz, w["nuclei"][0][1][2]))).cuda()
+        op.fill_hanging(x)
+        xs.append(x)
+    shape = [np.sin(0.3 + 0.2 * k) for k in range(4)]
+    for orb, poi in ((3, 13), (6, 53)):          # bit 1 of the orbital schedule: Chebyshev interface solve
+        batch.tune(0, orb, 65536)
+        batch.tune(1, poi, 1024)
+        xb = torch.cat([x.clone() for x in xs], dim=0)
+        Cb = torch.from_numpy(np.stack([h2_ci_guess()] * 3)).cuda()
+        Wb = torch.zeros((batch.n_full, 4), dtype=torch.float64, device="cuda")
+        rb = batch.propagate(xb, Cb, Wb, shape, 0.02, m=12)
+        assert rb["status"] == 0
+        lay = batch.layout()
+        for i, op in enumerate(plains):
+            op.tune(0, orb, 65536)
+            op.tune(1, poi, 8192)
+            x = xs[i].clone()
+            C = torch.from_numpy(h2_ci_guess()[None, :].copy()).cuda()
+            W = torch.zeros((op.n_full, 4), dtype=torch.float64, device="cuda")
+            rp = op.propagate(x, C, W, [E0[i] * v for v in shape], 0.02, m=12)
+            assert rp["status"] == 0
+            torch.cuda.synchronize()
+            # the field-induced dipole of these symmetric molecules is 1e-2 bohr
+            # or less, a small difference of large contributions of either
+            # sign, so its difference is taken in bohr (the molecules span
+            # about one bohr)
+            dd = np.max(np.abs(rb["dipole"][:, i] - rp["dipole"]))
+            de = np.max(np.abs(rb["energy"][:, i] - rp["energy"])) / np.abs(rp["energy"]).max()
+            oE, NE = lay[i, 3], lay[i, 1]
+            xh = x.cpu().numpy()
+            dx = np.abs(xb.cpu().numpy()[oE:oE + NE] - xh).max() / np.abs(xh).max()
+            dc = np.abs(Cb.cpu().numpy()[i] - C.cpu().numpy()[0]).max()
+            print(f"instance depth {ws[i]['balls'][0]['levels']} ({op.n_dof} unknowns), schedules {orb}/{poi}: "
+                  f"dipole {dd:.2e} (max |d| {np.abs(rp['dipole']).max():.2e}) energy {de:.2e} "
+                  f"orbitals {dx:.2e} CI {dc:.2e}", flush=True)
+            assert max(dd, de, dx, dc) <= 1e-11, (i, orb, poi, dd, de, dx, dc)

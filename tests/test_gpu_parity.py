@@ -3,16 +3,17 @@ same seeded inputs (small meshes spanning several cell tiles and a ragged
 tail, plus the full H2 mesh).
 
 Bar: operator applications (h1_apply, mass_solve, rhs_apply, arnoldi_step)
-max over orbitals of |y_gpu - y_oracle|_2 / |y_oracle|_2 <= 1e-10; Poisson
-potentials <= 1e-9 (CG driven to 1e-13 relative residual; the oracle uses a
-direct solve, so the gap is CG's round-off floor, about cond(K) eps);
+max over orbitals of |y_gpu - y_oracle|_2 / |y_oracle|_2 <= 1e-10, and
+element-wise max_i |y_gpu - y_oracle| <= 1e-10 of each column's largest
+entry; Poisson potentials <= 1e-10 in the m-weighted norm and element-wise
+(CG driven to 1e-13 relative residual against the oracle's direct solve);
 propagated dipoles and energies <= 1e-8.
 """
 import numpy as np
 import pytest
 
 from synth import random_orbitals, random_ci
-from tests.lib_cases import Pair, rel_err_cols
+from tests.lib_cases import Pair, rel_err_cols, max_rel_cols, poisson_solver
 
 pytestmark = pytest.mark.gpu
 
@@ -73,6 +74,7 @@ def test_fill_hanging_and_mass_solve(name):
     ref = P.ops.mass_solve(f_or)
     o = host(out)
     assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-12
+    assert max_rel_cols(P.from_lib_dof(o), ref) < 1e-12
     if P.Nh:
         assert rel_err_cols(o[P.N:], (P.om.C @ ref)[P.perm[P.N:P.NE]]) < 1e-12
 
@@ -88,6 +90,7 @@ def test_h1_apply(name):
     P.op.h1_apply(dev(P.to_lib_orb(c)), E, f)
     ref = P.ops.H1(E) @ c
     assert rel_err_cols(P.from_lib_dof(host(f)), ref) < 1e-10
+    assert max_rel_cols(P.from_lib_dof(host(f)), ref) < 1e-10
 
 
 def _poisson(P, c, rtol=1e-13):
@@ -100,18 +103,21 @@ def _poisson(P, c, rtol=1e-13):
 
 @pytest.mark.parametrize("name", SMALL + UNIFORM + ["h2"])
 def test_poisson_pairs(name):
-    from oracle.poisson import PoissonSolver
     P = pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     n = P.w["n_orb"]
     c = orbitals(P, 3)
     W, it, rc = _poisson(P, c)
     assert rc == 0 and it > 0
-    ref = PoissonSolver(P.ops).pair_potentials(c)
+    ref = poisson_solver(P.ops).pair_potentials(c)
     got = P.W_from_lib(host(W), n)
+    worst = 0.0
     for k in ref:
         num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref[k]) ** 2))
         den = np.sqrt(np.sum(P.ops.m * np.abs(ref[k]) ** 2))
-        assert num / den < 1e-9, (k, num / den, it)
+        el = np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()
+        worst = max(worst, num / den, el)
+        assert num / den < 1e-10 and el < 1e-10, (k, num / den, el, it)
+    print(name, "Poisson potentials: worst relative difference", worst, "after", it, "CG iterations", flush=True)
 
 
 @pytest.mark.parametrize("name", ["tiny_q3", "small_n3", "tiny_n8"])
@@ -119,11 +125,10 @@ def test_poisson_every_schedule(name):
     """Each Poisson launch schedule (sweep order, column blocks, long rows by
     waves, direction fused into the operator pass, multigrid preconditioner,
     sliced-ELL short rows) gives the oracle's potentials, cold and warm."""
-    from oracle.poisson import PoissonSolver
     P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     n = P.w["n_orb"]
     c = orbitals(P, 4)
-    ref = PoissonSolver(P.ops).pair_potentials(c)
+    ref = poisson_solver(P.ops).pair_potentials(c)
     torch = _torch()
     x = dev(P.to_lib_orb(c))
     for sched in (63, 61, 53, 45, 44, 39, 37, 36, 33, 32, 31, 29, 22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2,
@@ -162,12 +167,11 @@ def _frozen(P, c, C, E):
     """Oracle frozen operator and the library frozen on the same inputs."""
     from oracle.ci import CISpace
     from oracle.mctdhf import Frozen
-    from oracle.poisson import PoissonSolver
     torch = _torch()
     n = P.w["n_orb"]
     cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
     gam, Gam = cs.rdms(C)
-    W = PoissonSolver(P.ops).pair_potentials(c)
+    W = poisson_solver(P.ops).pair_potentials(c)
     fr = Frozen(P.ops, c, gam, Gam, E, W)
     P.op.freeze(dev(P.to_lib_orb(c)), dev(gam), dev(Gam), E, dev(P.W_to_lib(W, n)))
     return fr, cs
@@ -204,6 +208,7 @@ def _rhs_apply_case(P, name, torch):
     ref = fr.G(v)
     o = host(out)
     assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-10
+    assert max_rel_cols(P.from_lib_dof(o), ref) < 1e-10
     if P.Nh:
         assert rel_err_cols(o[P.N:], (P.om.C @ ref)[P.perm[P.N:P.NE]]) < 1e-10
 
@@ -226,6 +231,7 @@ def test_arnoldi_step(name, tau, m):
     assert m_used == m_ref
     o = host(x)
     assert rel_err_cols(P.from_lib_dof(o), ref) < 1e-10
+    assert max_rel_cols(P.from_lib_dof(o), ref) < 1e-10
     assert abs(err - err_ref) <= 1e-6 * err_ref + 1e-14
 
 
@@ -256,7 +262,7 @@ def test_propagate_observables(name, steps, imag, sched):
     Cd = dev(C)
     W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
     rec = P.op.propagate(x, Cd, W, E_steps, dt, m=12, imaginary=imag)
-    pr = Propagator(P.ops, cs)
+    pr = Propagator(P.ops, cs, poisson_solver(P.ops))
     recs = []
     cc, CC = c.copy(), C.copy()
     for k in range(steps):
@@ -284,11 +290,10 @@ def test_multigrid_poisson(name):
     """The multigrid-preconditioned CG gives the oracle's potentials in a few
     tens of iterations, far fewer than the Jacobi-preconditioned one."""
     torch = _torch()
-    from oracle.poisson import PoissonSolver
     P = Pair(name, poisson_rtol=1e-12, poisson_maxit=20000)
     n = P.w["n_orb"]
     c = orbitals(P, 4)
-    ref = PoissonSolver(P.ops).pair_potentials(c)
+    ref = poisson_solver(P.ops).pair_potentials(c)
     x = dev(P.to_lib_orb(c))
     its = {}
     for sched in (13, 21):
@@ -312,12 +317,11 @@ def test_multigrid_poisson_unrefined(name):
     Q1 grid the hierarchy is the operator itself, solved exactly by its dense
     inverse, so the preconditioned CG stops after its first iteration."""
     torch = _torch()
-    from oracle.poisson import PoissonSolver
     P = Pair(name, poisson_rtol=1e-12, poisson_maxit=20000)
     assert P.Nh == 0
     n = P.w["n_orb"]
     c = orbitals(P, 4)
-    ref = PoissonSolver(P.ops).pair_potentials(c)
+    ref = poisson_solver(P.ops).pair_potentials(c)
     x = dev(P.to_lib_orb(c))
     its = {}
     for sched in (13, 21, 53):
@@ -344,7 +348,6 @@ def test_propagate_zero_steps():
     torch = _torch()
     from oracle.ci import CISpace
     from oracle.mctdhf import Propagator
-    from oracle.poisson import PoissonSolver
     P = pair("tiny_q3", poisson_rtol=1e-13, poisson_maxit=20000)
     P.op.tune(1, 13, 8192)
     P.op.tune(0, 1, 65536)
@@ -366,7 +369,7 @@ def test_propagate_zero_steps():
                 and np.max(np.abs(host(Cd) - C0)) <= 1e-14 * np.abs(C0).max())
 
     assert unchanged()
-    Wref = PoissonSolver(P.ops).pair_potentials(c)
+    Wref = poisson_solver(P.ops).pair_potentials(c)
     got = P.W_from_lib(host(W), n)
     for k in Wref:
         num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - Wref[k]) ** 2))
@@ -377,3 +380,39 @@ def test_propagate_zero_steps():
     assert rec["status"] == 0
     assert unchanged()
     assert not host(W2).any()
+
+
+def test_propagate_h2_full_mesh():
+    """Three steps of the H2 workload itself (66,635 unknowns, Q3, two
+    orbitals, four determinants) with the library's default schedules
+    against the oracle: dipoles and energies <= 1e-8, orbitals and CI
+    vector <= 1e-8."""
+    torch = _torch()
+    from oracle.ci import CISpace
+    from oracle.mctdhf import Propagator
+    P = pair("h2", poisson_rtol=1e-13, poisson_maxit=20000)
+    n = P.w["n_orb"]
+    cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
+    c = orbitals(P, 14)
+    C = random_ci(cs.dim, 15)
+    dt, steps = 0.02, 3
+    E_steps = [0.0534 * np.sin(0.7 + 0.4 * k) for k in range(steps + 1)]
+    x, Cd = dev(P.to_lib_orb(c)), dev(C)
+    W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+    rec = P.op.propagate(x, Cd, W, E_steps, dt, m=12)
+    assert rec["status"] == 0
+    pr = Propagator(P.ops, cs, poisson_solver(P.ops))
+    recs = []
+    cc, CC = c.copy(), C.copy()
+    for k in range(steps):
+        cc, CC, ob = pr.step(cc, CC, E_steps[k], dt, 12)
+        recs.append(ob)
+    recs.append(pr.final_observables(cc, CC, E_steps[-1]))
+    d_ref = np.array([r["dipole"] for r in recs])
+    e_ref = np.array([r["energy"] for r in recs])
+    dd = np.max(np.abs(rec["dipole"] - d_ref)) / max(np.abs(d_ref).max(), 1e-3)
+    de = np.max(np.abs(rec["energy"] - e_ref)) / np.abs(e_ref).max()
+    print("h2 propagation: dipole", dd, "energy", de, flush=True)
+    assert dd <= 1e-8 and de <= 1e-8
+    assert rel_err_cols(P.from_lib_dof(host(x)), cc) < 1e-8
+    assert np.max(np.abs(host(Cd) - CC)) < 1e-8

@@ -156,3 +156,15 @@ def test_argument_errors_before_device_work():
     assert w1["p"] != w["p"]
     assert batch([M, M1], [d0, d1]) == INVALID
     assert "share p" in lib.mh_last_error().decode()
+
+
+def test_header_compiles_as_c(tmp_path):
+    """include/mh.h is a C header: it compiles with a C99 compiler alone."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    src = tmp_path / "use.c"
+    src.write_text('#include "mh.h"\nint main(void) { return mh_mass_solve(0, 0, 0, 0) == MH_INVALID_ARG ? 0 : 1; }\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"),
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
