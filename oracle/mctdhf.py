@@ -24,7 +24,11 @@ Arnoldi: inner product <U,V> = sum_p u_p^H M v_p over the packed vector;
 modified Gram-Schmidt with one full re-orthogonalisation pass; happy
 breakdown when h_{k+1,k} <= 1e-14 |G v_k|; phi' = beta V_m expm(-i tau H_m) e1
 (tau = dt in real time, -i dtau in imaginary time); error estimate
-beta h_{m+1,m} |e_m^T expm(-i tau H_m) e1|.
+beta h_{m+1,m} |e_m^T expm(-i tau H_m) e1|.  With an error threshold
+(Sec. III.B: the dimension chosen adaptively against a threshold on the
+error estimate) the space stops growing at the first dimension k whose
+estimate beta h_{k+1,k} |e_k^T expm(-i tau H_k) e1| is at or below it, m
+being then the largest dimension allowed.
 
 CI: C' = expm(-i dt H_CI) C by Lanczos with min(12, N_CI) vectors, from the
 same t_n integrals (orbitals and CI advance together from t_n data).
@@ -88,8 +92,9 @@ def inner(ops, u, v):
     return np.vdot(u, ops.M @ v)
 
 
-def arnoldi_step(ops, Gop, phi, tau, m, breakdown=1e-14):
-    """One short-iterative Arnoldi step; returns (phi', err_estimate, m_used, H)."""
+def arnoldi_step(ops, Gop, phi, tau, m, breakdown=1e-14, tol=None):
+    """One short-iterative Arnoldi step; returns (phi', err_estimate, m_used, H).
+    tol: error threshold of the adaptive dimension (None: fixed dimension m)."""
     beta = np.sqrt(inner(ops, phi, phi).real)
     V = [phi / beta]
     Hm = np.zeros((m + 1, m), dtype=complex)
@@ -106,6 +111,11 @@ def arnoldi_step(ops, Gop, phi, tau, m, breakdown=1e-14):
         if Hm[k + 1, k].real <= breakdown * wn:
             m_eff = k + 1
             break
+        if tol is not None and k + 1 < m:
+            yk = sla.expm(-1j * tau * Hm[:k + 1, :k + 1])[:, 0]
+            if beta * abs(Hm[k + 1, k]) * abs(yk[k]) <= tol:
+                m_eff = k + 1
+                break
         V.append(w / Hm[k + 1, k])
     y = sla.expm(-1j * tau * Hm[:m_eff, :m_eff])[:, 0]
     out = beta * sum(y[j] * V[j] for j in range(m_eff))
@@ -195,13 +205,14 @@ class Propagator:
         fr = Frozen(self.ops, c, gamma, Gamma, E, W)
         return fr
 
-    def step(self, c, C, E, dt, m=12, imaginary=False):
-        """Advance (c, C) by one step from t_n data; returns (c', C', info)."""
+    def step(self, c, C, E, dt, m=12, imaginary=False, krylov_tol=None):
+        """Advance (c, C) by one step from t_n data; returns (c', C', info).
+        krylov_tol: error threshold of the adaptive Krylov dimension (at most m)."""
         fr = self.freeze(c, C, E)
         h, g = integrals(self.ops, c, fr.Wfull, E)
         obs = observables(self.ops, c, fr.gamma, fr.Gamma, h, g, E)
         tau = -1j * dt if imaginary else dt
-        c2, err, m_eff, _ = arnoldi_step(self.ops, fr.G, c, tau, m)
+        c2, err, m_eff, _ = arnoldi_step(self.ops, fr.G, c, tau, m, tol=krylov_tol)
         Hci = self.ci.hamiltonian(h, g)
         C2 = lanczos_expm(Hci, C, tau, 12)
         if imaginary:
@@ -215,12 +226,12 @@ class Propagator:
         h, g = integrals(self.ops, c, fr.Wfull, E)
         return observables(self.ops, c, fr.gamma, fr.Gamma, h, g, E)
 
-    def propagate(self, c, C, E_steps, dt, m=12, imaginary=False):
+    def propagate(self, c, C, E_steps, dt, m=12, imaginary=False, krylov_tol=None):
         """Run len(E_steps) steps; returns final (c, C) and per-step records
         for t_0 .. t_N (the last one from a final freeze at E_steps[-1])."""
         recs = []
         for E in E_steps:
-            c, C, obs = self.step(c, C, E, dt, m, imaginary)
+            c, C, obs = self.step(c, C, E, dt, m, imaginary, krylov_tol)
             recs.append(obs)
         recs.append(self.final_observables(c, C, E_steps[-1] if len(E_steps) else 0.0))
         return c, C, recs

@@ -673,3 +673,34 @@ def test_velocity_gauge_one_orbital_mctdhf_is_tdse():
         assert np.sqrt(mctdhf.inner(ops, tot - psi, tot - psi).real) < 1e-11
     # Hermitian H1: the norm is conserved
     assert abs(mctdhf.inner(ops, psi, psi).real - 1) < 1e-12
+
+
+# ------------------------------------------------ adaptive Krylov dimension ----
+@pytest.mark.parametrize("tau", [0.05, -0.05j])
+def test_adaptive_krylov_dimension(tau):
+    """Sec. III.B: the Krylov dimension grows until the error estimate meets
+    the threshold.  Against dense exponentials on a tiny mesh: the result is
+    within ten times the threshold, the dimension chosen is the smallest whose
+    estimate meets it (one less does not), and a threshold no dimension meets
+    uses the largest dimension allowed."""
+    w, mesh, ops = case("tiny_q1")
+    n = 2
+    cs = CISpace(n, 1, 1)
+    c = mctdhf.orthonormalize(ops, random_orbitals(mesh.xyz[mesh.dof_nodes], n, 4))
+    pr = mctdhf.Propagator(ops, cs)
+    fr = pr.freeze(c, random_ci(cs.dim, 2), 0.01)
+    N = mesh.n_dof
+    G = _dense_G(fr, N, n)
+    ex = (sla.expm(-1j * tau * G) @ c.ravel()).reshape(N, n)
+    nrm = np.sqrt(mctdhf.inner(ops, ex, ex).real)
+    dims = []
+    for tol in (1e-6, 1e-10):
+        out, err, m_eff, _ = mctdhf.arnoldi_step(ops, fr.G, c, tau, 24, tol=tol)
+        d = np.sqrt(mctdhf.inner(ops, out - ex, out - ex).real)
+        assert err <= tol and d <= 10 * tol * nrm, (tol, err, d)
+        _, err_less, _, _ = mctdhf.arnoldi_step(ops, fr.G, c, tau, m_eff - 1)
+        assert err_less > tol, (tol, m_eff, err_less)
+        dims.append(m_eff)
+    assert dims[0] < dims[1] < 24, dims
+    _, _, m_all, _ = mctdhf.arnoldi_step(ops, fr.G, c, tau, 6, tol=1e-30)
+    assert m_all == 6
