@@ -152,6 +152,24 @@ int mh_fill_hanging(mh_op* op, double* x, void* stream);
  * c: device c128 [N_E][n] output, hanging rows filled. */
 int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream);
 
+/* Allocation-free variant of mh_mass_solve, for callers that cannot
+ * allocate device memory during the call (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, result
+ * and kernels as mh_mass_solve; the interface system's right-hand side,
+ * iterate, residual and search directions live in a static device array of
+ * 32 MiB that every GPU the library runs on holds until the process ends
+ * (its address is taken when an operator is created on that device), instead
+ * of the operator's own workspaces.  The call allocates nothing (no
+ * hipMalloc, no registered allocator).  MH_UNSUPPORTED when the interface
+ * system needs more than 32 MiB (5 x 16 x n bytes per interface unknown,
+ * summed over the instances); MH_INVALID_ARG when called with another device
+ * current than the one the operator was created on.  All calls on one GPU
+ * share the array: calls that overlap in time on one GPU (two streams, two
+ * threads) race and give wrong results; calls in one stream are ordered and
+ * safe.  Nothing in the array needs clearing: each call writes every element
+ * it reads before reading it. */
+int mh_mass_solve_noalloc(mh_op* op, const double* f, double* c, void* stream);
+
 /* One-body load vector f = H1 c in Galerkin form (Eq. discretized_eom):
  * length gauge H1(E) = K/2 + V_nuc + E (e.r); velocity gauge
  * H1(A) = K/2 + V_nuc - i A S_e, where the argument E is the vector

@@ -10,7 +10,7 @@ _NAMES = {-1: "INVALID_ARG", -2: "OOM", -3: "HIP_ERROR", -4: "SINGULAR_RDM", -5:
           -6: "UNSUPPORTED"}
 
 EXPORTS = ["mh_mesh_create", "mh_mesh_info_get", "mh_mesh_node_coords", "mh_mesh_constraints",
-           "mh_mesh_destroy", "mh_op_create", "mh_op_destroy", "mh_fill_hanging", "mh_mass_solve",
+           "mh_mesh_destroy", "mh_op_create", "mh_op_destroy", "mh_fill_hanging", "mh_mass_solve", "mh_mass_solve_noalloc",
            "mh_h1_apply", "mh_poisson_pairs", "mh_ci_rdms", "mh_freeze", "mh_rhs_apply",
            "mh_arnoldi_step", "mh_propagate", "mh_op_sizes_get", "mh_kernel_timing", "mh_tune",
            "mh_propagate_adjoint", "mh_batch_create", "mh_batch_layout", "mh_set_allocator", "mh_last_error"]
@@ -90,6 +90,7 @@ def load_library():
     lib.mh_op_sizes_get.argtypes = [vp, C.POINTER(_Sizes)]
     lib.mh_fill_hanging.argtypes = [vp, vp, vp]
     lib.mh_mass_solve.argtypes = [vp, vp, vp, vp]
+    lib.mh_mass_solve_noalloc.argtypes = [vp, vp, vp, vp]
     lib.mh_h1_apply.argtypes = [vp, vp, C.c_double, vp, vp]
     lib.mh_poisson_pairs.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_int32), vp]
     lib.mh_ci_rdms.argtypes = [vp, vp, vp, vp, vp]
@@ -309,6 +310,14 @@ class Operator:
         if f.numel() < self.n_dof * self.n_orb:
             raise ValueError("f too small")
         _check(_lib.mh_mass_solve(self._h, _ptr(f), _ptr(c), _stream(stream)))
+
+    def mass_solve_noalloc(self, f, c, stream=None):
+        """mh_mass_solve through the library's static device scratch (no allocation)."""
+        import torch
+        self._need(c, self.n_ext, self.n_orb, torch.complex128)
+        if f.numel() < self.n_dof * self.n_orb:
+            raise ValueError("f too small")
+        _check(_lib.mh_mass_solve_noalloc(self._h, _ptr(f), _ptr(c), _stream(stream)))
 
     def h1_apply(self, c, E, f, stream=None):
         import torch

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -88,6 +89,7 @@ struct mh_mesh {
 
 struct mh_op {
   int ni = 1;                  // instances
+  int device = 0;              // HIP device current at creation (all its buffers live there)
   std::vector<Mesh> Ms;        // per instance
   std::vector<OpHost> Hs;
   std::vector<DevMesh> dh;     // host copies of the device instance records
@@ -361,6 +363,40 @@ static void upload_instances(mh_op* op, hipStream_t s) {
 
 // Build the host operators of all instances (in parallel), upload them and
 // allocate the batch workspaces.
+// Device scratch of the allocation-free mass solve (mh_mass_solve_noalloc):
+// the interface system's gathered right-hand side, iterate, residual and two
+// Chebyshev directions, laid out one after another.  Every GPU the library
+// runs on holds one copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: its device address is
+// taken once per device with hipGetSymbolAddress (with that device current,
+// when an operator is created there) and kept in g_scratch_dev.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // device address of `scratch` per device id (nullptr: not yet taken)
+
+// Device address of the scratch array on the current device, taken on first use.
+int resolve_scratch() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = ptr;
+  }
+  return dev;
+}
+
+void* scratch_on(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return dev < (int)g_scratch_dev.size() ? g_scratch_dev[dev] : nullptr;
+}
+}  // namespace
+
 static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_desc& desc, hipStream_t s) {
   const int ni = (int)spec.size();
   const int n = desc.n_orb, ncol = n * n;
@@ -370,6 +406,7 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   HIPCHK(hipFree(nullptr));
   auto op = std::make_unique<mh_op>();
   op->ni = ni;
+  op->device = resolve_scratch();
   op->Ms.resize(ni);
   op->Hs.resize(ni);
   {
@@ -1057,6 +1094,33 @@ extern "C" int mh_mass_solve(mh_op* op, const double* f, double* c, void* stream
     const Batch& B = op->B;
     launch_mass_direct(B, f, c, op->ma_b, s);
     launch_ma_solve(B, op->ma_b, op->ma_x, op->ma_r, op->ma_d0, op->ma_d1, nullptr, nullptr, c, s);
+    launch_fill_orb(B, c, nullptr, s);
+    HIPCHK(hipGetLastError());
+    return MH_OK;
+  });
+}
+
+extern "C" int mh_mass_solve_noalloc(mh_op* op, const double* f, double* c, void* stream) {
+  if (!op || !f || !c) return fail(MH_INVALID_ARG, "null argument");
+  return guarded([&]() -> int {
+    hipStream_t s = S(stream);
+    const Batch& B = op->B;
+    // five buffers of [sum of interface unknowns][n] complex values
+    const size_t buf = 2 * std::max<size_t>(1, B.tMa) * (size_t)op->n;   // doubles per buffer
+    const size_t need = 5 * buf * sizeof(double);
+    if (need > kScratchBytes)
+      return fail(MH_UNSUPPORTED, "interface mass system needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                      std::to_string(kScratchBytes) + " bytes of mh_mass_solve_noalloc");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != op->device) return fail(MH_INVALID_ARG, "call on the device the operator was created on");
+    double* base = static_cast<double*>(scratch_on(dev));
+    if (!base) return fail(MH_INVALID_ARG, "scratch of this device not set up");
+    // every scratch element the kernels read is written first in this call
+    // (gather of the right-hand side, then the iteration's initial state)
+    double* mb = base;
+    launch_mass_direct(B, f, c, mb, s);
+    launch_ma_solve(B, mb, mb + buf, mb + 2 * buf, mb + 3 * buf, mb + 4 * buf, nullptr, nullptr, c, s);
     launch_fill_orb(B, c, nullptr, s);
     HIPCHK(hipGetLastError());
     return MH_OK;
