@@ -269,7 +269,7 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
     op.kernel_timing(1, True)
     torch.cuda.synchronize()
     t_a = time.perf_counter()
-    rec = op.propagate(phi, Ci, W, E, dt, m=m, final=False, graph=args.graph)
+    rec = op.propagate(phi, Ci, W, E, dt, m=m, final=False, graph=args.graph, graph_step=args.graph_step)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_a
     k_orb = op.kernel_timing(0, False)
@@ -328,7 +328,8 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": wl, "n_dof": op.n_dof, "n_full": info["n_full"], "n_cells": info["n_cells"],
-                   "n_orb": op.n_orb, "n_ci": op.n_ci, "krylov": m, "dt": dt, "parallelism": "none (one GPU)"},
+                   "n_orb": op.n_orb, "n_ci": op.n_ci, "krylov": m, "dt": dt, "graph": bool(args.graph),
+                   "graph_step": bool(args.graph_step), "parallelism": "none (one GPU)"},
         "arnoldi_step_ms": arnoldi_ms,
         "rhs_apply_ms": rhs_ms,
         "rhs_evals_per_s_isolated": op.n_dof * op.n_orb / (rhs_ms * 1e-3),
@@ -373,6 +374,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="instances of the h2x64 workload")
     ap.add_argument("--seq-steps", type=int, default=2, help="timed steps per instance of the sequential runs")
     ap.add_argument("--graph", action="store_true", help="replay each step's fixed part as a HIP graph")
+    ap.add_argument("--graph-step", action="store_true",
+                    help="replay whole steps (Poisson CG with a fixed iteration count included) as one HIP graph each")
     ap.add_argument("--no-sequential", action="store_true", help="h2x64: skip the sequential runs")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes: CG iterations and RHS applications on the "
@@ -583,12 +586,12 @@ def run_batch(args):
     op.kernel_timing(1, True)
     torch.cuda.synchronize()
     t_a = time.perf_counter()
-    rec = op.propagate(phi, Ci, W, shape, dt, m=m, final=False, graph=args.graph)
+    rec = op.propagate(phi, Ci, W, shape, dt, m=m, final=False, graph=args.graph, graph_step=args.graph_step)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_a
     k_orb = op.kernel_timing(0, False)
     k_poi = op.kernel_timing(1, False)
-    log(f"batched: {wall / args.steps * 1e3:.1f} ms per step")
+    log(f"batched: {wall / args.steps * 1e3:.1f} ms per step, status {rec['status']}")
     # sequential baseline: each instance alone (plain operator, with the
     # schedules tuned on the first instance alone), from this batch's current
     # state, `seq_steps` timed steps after one untimed step
@@ -662,6 +665,7 @@ def run_batch(args):
         "config": {"workload": f"h2x{op.n_inst}_q3_{op.n_dof}dof_{op.n_orb}orb", "n_inst": op.n_inst,
                    "n_dof_total": op.n_dof, "n_dof_min": int(lay[:, 0].min()), "n_dof_max": int(lay[:, 0].max()),
                    "n_cells_total": n_cells, "krylov": m, "dt": dt, "graph": bool(args.graph),
+                   "graph_step": bool(args.graph_step),
                    "parallelism": "none (one GPU, batch of instances)"},
         "batched_vs_sequential": (seq_step_s * 1e3 / ms_step) if not args.no_sequential else None,
         "sequential_ms_per_step": seq_step_s * 1e3,

@@ -129,6 +129,10 @@ typedef struct {
   int32_t gauge;              /* MH_GAUGE_LENGTH: field term E(t) e.r; MH_GAUGE_VELOCITY: term
                                  -i A(t) e.grad (Sec. II one-body operator), the field values
                                  passed to the calls below then being A(t) */
+  double krylov_tol;          /* 0: Arnoldi steps use the Krylov dimension m they are given;
+                                 > 0: adaptive dimension (Sec. III.B): the space stops growing
+                                 at the first dimension whose error estimate is <= krylov_tol,
+                                 m being the largest (one small synchronising read per vector) */
 } mh_op_desc;
 
 enum { MH_GAUGE_LENGTH = 0, MH_GAUGE_VELOCITY = 1 };
@@ -242,6 +246,7 @@ typedef struct {
                          sum_pq gamma_pq <phi_p|-i e.grad|phi_q> (+ N A(t) in the
                          velocity gauge), with the antisymmetric Gauss-Lobatto
                          derivative of the velocity-gauge term */
+  int32_t* krylov_dim; /* Krylov dimension of each step's Arnoldi step (0 for the final record) */
 } mh_observables;
 
 /* Propagate orbitals and CI vector together for n_steps steps of size dt
@@ -257,7 +262,18 @@ typedef struct {
  * the Poisson solve (freeze, integrals, observables, Arnoldi and CI steps)
  * once as a HIP graph on a stream of the library and replay it every step;
  * the Poisson CG, whose length depends on the data, stays eager.  Results
- * are those of the eager path.
+ * are those of the eager path.  Not with an adaptive Krylov dimension
+ * (MH_INVALID_ARG).
+ * MH_PROP_GRAPH_STEP (multigrid Poisson schedule, bit 4; not with
+ * MH_PROP_GRAPH): from the fourth step of a call on, a whole step is one
+ * replay of a HIP graph captured once per call: RDMs, the extrapolated CG
+ * start, the pair Poisson solves with a fixed count of multigrid-
+ * preconditioned CG iterations (three more than the third step took; no host
+ * check inside the step), the boundary values, the step's field value from a
+ * device copy of E_steps, then the step after the Poisson solve.  After each
+ * replay the residual is checked on the host; a step whose CG stopped short
+ * of the target makes the call return MH_NOT_CONVERGED (its records are
+ * still filed).  The cg_iters record holds the fixed count for those steps.
  * phi: device c128 [N_E][n] in-out; Ci: device c128 [n_inst][N_CI] in-out;
  * E_steps: host double [n_steps + 1] (the last value is used for the final
  * record; in the velocity gauge these are values of A(t)); instance i sees
@@ -270,7 +286,7 @@ typedef struct {
  * of the previous solutions.  MH_NONFINITE if an observable of a step is not
  * finite (NaN or Inf in the orbitals or CI vector).
  * Synchronises `stream`. */
-enum { MH_PROP_IMAGINARY = 1, MH_PROP_NO_FINAL = 2, MH_PROP_GRAPH = 4 };
+enum { MH_PROP_IMAGINARY = 1, MH_PROP_NO_FINAL = 2, MH_PROP_GRAPH = 4, MH_PROP_GRAPH_STEP = 8 };
 int mh_propagate(mh_op* op, double* phi, double* Ci, double* W_work, const double* E_steps,
                  int32_t n_steps, double dt, int32_t m, int32_t flags, mh_observables* obs,
                  void* stream);
@@ -367,9 +383,14 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * the rows of at most 48 entries read from a sliced-ELL copy of the operator
  * (built when the bit is first set: rows sorted by length within windows of
  * 4096, slices of 64 rows stored entry-major, so the lanes of a wave read
- * consecutive words), the longer rows by whole waves as with bit 2.
+ * consecutive words), the longer rows by whole waves as with bit 2; bit 6
+ * (with bit 4): the multigrid preconditioner's finest-level passes (smoothing,
+ * residual and transfers) on float copies of their arrays (the residual, the
+ * correction, the smoothing direction and the operator product); the CG
+ * vectors, its own operator pass and every sum stay double, so the solution
+ * meets the same residual target.
  * Default sched 13.  Allowed values: 0 to 7 (orbital); any combination of
- * bits 0 to 5 (Poisson).
+ * bits 0 to 6 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
  * sums change order only). */

@@ -42,13 +42,14 @@ class _OpDesc(C.Structure):
                 ("positions", C.POINTER(C.c_double)), ("n_orb", C.c_int32), ("n_alpha", C.c_int32),
                 ("n_beta", C.c_int32), ("polarization", C.c_double * 3), ("lmax_bc", C.c_int32),
                 ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int32), ("rdm_eps", C.c_double),
-                ("gauge", C.c_int32)]
+                ("gauge", C.c_int32), ("krylov_tol", C.c_double)]
 
 
 class _Obs(C.Structure):
     _fields_ = [("dipole", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double)),
                 ("err_est", C.POINTER(C.c_double)), ("ortho", C.POINTER(C.c_double)),
-                ("cg_iters", C.POINTER(C.c_int32)), ("momentum", C.POINTER(C.c_double))]
+                ("cg_iters", C.POINTER(C.c_int32)), ("momentum", C.POINTER(C.c_double)),
+                ("krylov_dim", C.POINTER(C.c_int32))]
 
 
 class _Sizes(C.Structure):
@@ -222,12 +223,12 @@ GAUGES = {"length": 0, "velocity": 1}
 
 
 def _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit, rdm_eps,
-             gauge="length"):
+             gauge="length", krylov_tol=0.0):
     Z = np.array([z for z, _ in nuclei], dtype=np.float64)
     R = np.ascontiguousarray(np.array([r for _, r in nuclei], dtype=np.float64).reshape(-1, 3))
     desc = _OpDesc(len(nuclei), Z.ctypes.data_as(C.POINTER(C.c_double)), R.ctypes.data_as(C.POINTER(C.c_double)),
                    int(n_orb), int(n_alpha), int(n_beta), (C.c_double * 3)(*polarization), int(lmax_bc),
-                   float(poisson_rtol), int(poisson_maxit), float(rdm_eps), GAUGES[gauge])
+                   float(poisson_rtol), int(poisson_maxit), float(rdm_eps), GAUGES[gauge], float(krylov_tol))
     return desc, (Z, R)
 
 
@@ -235,17 +236,19 @@ class Operator:
     """Operator set-up and device entry points (see include/mh.h)."""
 
     def __init__(self, mesh, nuclei, n_orb, n_alpha, n_beta, polarization=(0.0, 0.0, 1.0), lmax_bc=12,
-                 poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", stream=None):
+                 poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", krylov_tol=0.0,
+                 stream=None):
         lib = load_library()
         desc, keep = _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol,
-                              poisson_maxit, rdm_eps, gauge)
+                              poisson_maxit, rdm_eps, gauge, krylov_tol)
         h = C.c_void_p()
         _check(lib.mh_op_create(mesh._h, C.byref(desc), _stream(stream), C.byref(h)))
         self._attach(h, [mesh])
 
     @classmethod
     def batch(cls, meshes, nuclei_list, n_orb, n_alpha, n_beta, field_scale=None, polarization=(0.0, 0.0, 1.0),
-              lmax_bc=12, poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", stream=None):
+              lmax_bc=12, poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", krylov_tol=0.0,
+              stream=None):
         """Batch of independent instances (mh_batch_create): one mesh and one
         molecule per instance, one shared orbital/electron space."""
         lib = load_library()
@@ -256,7 +259,7 @@ class Operator:
         keep = []
         for i, nuc in enumerate(nuclei_list):
             d, k = _op_desc(nuc, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit,
-                            rdm_eps, gauge)
+                            rdm_eps, gauge, krylov_tol)
             descs[i] = d
             keep.append(k)
         hs = (C.c_void_p * ni)(*[m._h.value for m in meshes])
@@ -356,8 +359,11 @@ class Operator:
                                     _stream(stream)))
         return err.value, mu.value
 
-    def propagate(self, phi, Ci, W, E_steps, dt, m=12, imaginary=False, final=True, graph=False, stream=None):
-        """Records are [n_steps + 1] for one instance, [n_steps + 1][n_inst] for a batch."""
+    def propagate(self, phi, Ci, W, E_steps, dt, m=12, imaginary=False, final=True, graph=False, graph_step=False,
+                  stream=None):
+        """Records are [n_steps + 1] for one instance, [n_steps + 1][n_inst] for a batch.
+        graph: replay the part of each step after the Poisson solve from a HIP
+        graph; graph_step: replay whole steps (MH_PROP_GRAPH_STEP)."""
         import torch
         self._need(phi, self.n_ext, self.n_orb, torch.complex128)
         self._need(W, self.n_full, self.n_pair_cols, torch.float64)
@@ -367,12 +373,15 @@ class Operator:
         shape = (n_steps + 1,) if self.n_inst == 1 else (n_steps + 1, self.n_inst)
         rec = {k: np.zeros(shape) for k in ("dipole", "energy", "err_est", "ortho", "momentum")}
         rec["cg_iters"] = np.zeros(n_steps + 1, dtype=np.int32)
+        rec["krylov_dim"] = np.zeros(shape, dtype=np.int32)
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
         obs = _Obs(dp(rec["dipole"]), dp(rec["energy"]), dp(rec["err_est"]), dp(rec["ortho"]),
-                   rec["cg_iters"].ctypes.data_as(C.POINTER(C.c_int32)), dp(rec["momentum"]))
+                   ip(rec["cg_iters"]), dp(rec["momentum"]), ip(rec["krylov_dim"]))
         rc = _check(_lib.mh_propagate(self._h, _ptr(phi), _ptr(Ci), _ptr(W), E.ctypes.data_as(C.c_void_p),
                                       n_steps, float(dt), int(m),
-                                      (1 if imaginary else 0) | (0 if final else 2) | (4 if graph else 0),
+                                      (1 if imaginary else 0) | (0 if final else 2) | (4 if graph else 0)
+                                      | (8 if graph_step else 0),
                                       C.byref(obs),
                                       _stream(stream)), allow_nc=True)
         rec["status"] = rc

@@ -98,6 +98,7 @@ struct mh_op {
   std::vector<DevBlock> allocs;
   int n = 0, ncol = 0, lmax = 12;
   double rtol = 1e-12, rdm_eps = 1e-10;
+  double krylov_tol = 0.0;     // error threshold of the adaptive Krylov dimension (0: fixed dimension)
   int maxit = 5000;
   // device data
   int* colinfo = nullptr;  // per real Poisson column: r | s<<8 | part<<16
@@ -145,6 +146,9 @@ struct mh_op {
   double* hostpin = nullptr;
   size_t hostpin_len = 0;
   hipStream_t gstream = nullptr;  // stream for graph capture and replay
+  double* Etab = nullptr;         // field values of a propagation call (whole-step graph replay)
+  int64_t Etab_len = 0;
+  int* step_ctr = nullptr;        // device step counter of the replayed steps
   // timing of the dominant kernels: pools of event pairs recorded on the
   // launch stream around each launch (no synchronisation while recording)
   std::vector<hipEvent_t> ev[2];
@@ -434,6 +438,7 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   op->rtol = desc.poisson_rtol > 0 ? desc.poisson_rtol : 1e-12;
   op->maxit = desc.poisson_maxit > 0 ? desc.poisson_maxit : 5000;
   op->rdm_eps = desc.rdm_eps > 0 ? desc.rdm_eps : 1e-10;
+  op->krylov_tol = desc.krylov_tol;
   Batch& B = op->B;
   B.ni = ni;
   int iters = 0;
@@ -476,7 +481,7 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
     d.hang_col = op->upload(hc, s);
     d.hang_w = op->upload(M.hang_w, s);
     d.ma_index = op->upload(H.ma_index, s);
-    d.ma_dof = op->upload(M.masters, s);
+    d.ma_dof = op->upload(H.ma_dof, s);
     d.ma_ptr = op->upload(H.ma_ptr, s);
     d.ma_col = op->upload(H.ma_col, s);
     d.ma_val = op->upload(H.ma_val, s);
@@ -650,6 +655,7 @@ static int check_desc(const mh_op_desc* desc) {
   const int lmax = desc->lmax_bc > 0 ? desc->lmax_bc : 12;
   if (lmax > 12) return fail(MH_UNSUPPORTED, "lmax_bc must be <= 12");
   if (desc->gauge != MH_GAUGE_LENGTH && desc->gauge != MH_GAUGE_VELOCITY) return fail(MH_INVALID_ARG, "gauge");
+  if (!(desc->krylov_tol >= 0.0)) return fail(MH_INVALID_ARG, "krylov_tol must be >= 0");
   if ((lmax + 1) * (lmax + 1) * desc->n_orb * desc->n_orb > 48 * 256)
     return fail(MH_UNSUPPORTED, "multipole table too large");
   return MH_OK;
@@ -857,6 +863,13 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
   HIPCHK(hipMemsetAsync(mg->z0b, 0, tlen * sizeof(double), s));
   HIPCHK(hipMemsetAsync(mg->t0, 0, tlen * sizeof(double), s));
   HIPCHK(hipMemsetAsync(d0, 0, tlen * sizeof(double), s));
+  // the same level-0 arrays on float storage (Poisson schedule bit 6)
+  mg->z0f = op->alloc<float>(tlen);
+  mg->z0bf = op->alloc<float>(tlen);
+  mg->t0f = op->alloc<float>(tlen);
+  mg->d0f = op->alloc<float>(tlen);
+  mg->rf = op->alloc<float>(tlen);
+  for (float* f : {mg->z0f, mg->z0bf, mg->t0f, mg->d0f, mg->rf}) HIPCHK(hipMemsetAsync(f, 0, tlen * sizeof(float), s));
   // level-0 Chebyshev coefficients of the fused smoothing passes: s0 = 1/theta
   // (first step), then c1, c2 of the second step of the three-term recurrence
   for (int i = 0; i < ni; ++i) {
@@ -889,6 +902,9 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
         L.z = mg->z0 + off;
         L.t = mg->t0 + off;
         L.d = d0 + off;
+        L.rf = mg->rf + off;
+        L.zf = mg->z0f + off;
+        L.tf = mg->t0f + off;
       } else {
         L.a_ptr = op->upload(h.k_ptr, s);
         L.a_col = op->upload(h.k_col, s);
@@ -920,6 +936,9 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
   }
   mg->nlev = nlev;
   for (int l = 0; l < nlev; ++l) mg->lv.push_back(op->upload(rec[l], s));
+  mg->lv0_double = mg->lv[0];
+  for (MgLevelDev& L : rec[0]) L.f32 = 1;
+  mg->lv0_float = op->upload(rec[0], s);
   mg->coarse = op->upload(co, s);
   op->mg_red = op->alloc<double>((size_t)ni * RED_SLOTS * ncol);
   op->mg_part = op->alloc<double>((size_t)ni * MG_RZ_BLOCKS * ncol);
@@ -938,24 +957,39 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
 // runs before the first iteration and after every iteration from two before
 // the previous solve's count on (successive solves of a propagation take
 // nearly the same count; an unchecked iteration only lowers the residual).
-static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
+// fixed > 0: exactly `fixed` iterations with no host check (the launch
+// sequence of a captured step; every update stays well defined past
+// convergence, alpha and beta being zero where their denominators vanish);
+// the caller checks the residual afterwards.
+static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0) {
   const Batch& B = op->B;
   PoissonWs& P = op->P;
   const MgDev& mg = *op->mg;
   const int ncol = op->ncol, ni = op->ni;
   const int64_t N = B.mx.N;
   const bool fused = mg.nlev > 1 && mg.nu == 2;
+  // Poisson schedule bit 6: the finest level's smoothing passes, residual
+  // pass and transfers on float copies of its arrays (the preconditioner
+  // only; the CG vectors, its operator pass and every sum stay double)
+  const bool f32 = fused && (B.mx.sched_poi & 64);
+  op->mg->lv[0] = f32 ? mg.lv0_float : mg.lv0_double;
   int rz_slot = RED_RZ;
   MgLevel0Ops ops;
-  ops.spmv = [&](const double* x, double* y, hipStream_t st) {
-    launch_poisson_apply(B, x, y, ncol, op->mg_red, P, st);
-  };
-  ops.cheb0 = [&](double* z, double* d, hipStream_t st) {
-    launch_mg_cheb0(B, P.r, z, d, P.red, rz_slot, ncol, st);
-  };
-  ops.cheb = [&](const double* zin, double* zout, double* d, int k, hipStream_t st) {
-    launch_mg_cheb_step(B, zin, P.r, zout, d, P.red, ncol, k, k == 1 ? rz_slot : -1, st);
-  };
+  if (f32) {
+    ops.spmv = [&](hipStream_t st) { launch_poisson_apply_f(B, mg.z0f, mg.t0f, ncol, op->mg_red, st); };
+    ops.cheb0 = [&](hipStream_t st) { launch_mg_cheb0_f(B, mg.rf, mg.z0f, mg.d0f, P.red, rz_slot, ncol, st); };
+    ops.cheb = [&](int k, hipStream_t st) {
+      launch_mg_cheb_step_f(B, k == 0 ? mg.z0f : mg.z0bf, mg.rf, k == 0 ? mg.z0bf : mg.z0f, mg.d0f, P.red, ncol, k,
+                            k == 1 ? rz_slot : -1, st);
+    };
+  } else {
+    ops.spmv = [&](hipStream_t st) { launch_poisson_apply(B, mg.z0, mg.t0, ncol, op->mg_red, P, st); };
+    ops.cheb0 = [&](hipStream_t st) { launch_mg_cheb0(B, P.r, mg.z0, mg.d0, P.red, rz_slot, ncol, st); };
+    ops.cheb = [&](int k, hipStream_t st) {
+      launch_mg_cheb_step(B, k == 0 ? mg.z0 : mg.z0b, P.r, k == 0 ? mg.z0b : mg.z0, mg.d0, P.red, ncol, k,
+                          k == 1 ? rz_slot : -1, st);
+    };
+  }
   double* z = mg.z0;
   auto precondition = [&](int it) {  // z = B r with r.z in slot RED_RZ + it % 3
     rz_slot = RED_RZ + it % 3;
@@ -963,25 +997,37 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s) {
     if (!fused) mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, rz_slot, s);
   };
   P.it = 0;
-  int conv = poisson_converged(op, s);
+  int conv = fixed > 0 ? 0 : poisson_converged(op, s);
   int k = 0;
   const int check_from = op->cg_hint - 2;
-  if (conv == 0) precondition(0);
-  while (conv == 0 && k < op->maxit) {
+  const int kmax = fixed > 0 ? fixed : op->maxit;
+  if (conv == 0) {
+    if (f32) launch_to_float(P.r, mg.rf, (int64_t)B.tE * ncol, s);  // later residuals by the update pass
+    precondition(0);
+  }
+  while (conv == 0 && k < kmax) {
     double* pcur = (k % 2) ? P.p2 : P.p;
     double* pold = (k % 2) ? P.p : P.p2;
-    mg_dir(B.dm, ni, N, ncol, z, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1, RED_RR + k % 2,
-           s);
+    if (f32)
+      mg_dir(B.dm, ni, N, ncol, mg.z0f, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1,
+             RED_RR + k % 2, s);
+    else
+      mg_dir(B.dm, ni, N, ncol, z, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1,
+             RED_RR + k % 2, s);
     launch_cg_apply_plain(B, P, pcur, k, s);
-    launch_cg_update(B, W, P, pcur, k, s);
+    launch_cg_update(B, W, P, pcur, k, s, f32 ? mg.rf : nullptr);
     ++k;
     P.it = k;
+    if (fixed > 0) {
+      if (k < fixed) precondition(k);
+      continue;
+    }
     if (k >= check_from || k == op->maxit) conv = poisson_converged(op, s);
     if (conv != 0) break;
     precondition(k);
   }
   if (iters) *iters = k;
-  op->cg_hint = k;
+  if (fixed == 0) op->cg_hint = k;
   return conv;
 }
 
@@ -1057,6 +1103,11 @@ static void ensure_krylov(mh_op* op, int m) {
   op->m_alloc = m;
 }
 
+// With an error threshold (krylov_tol > 0) the space stops growing at the
+// first dimension whose error estimate meets it (Sec. III.B), m being the
+// largest: after each vector the estimate is evaluated on the device and the
+// instances' dimensions read back (one small synchronising read per vector);
+// a batch grows until every instance has stopped.
 static int arnoldi(mh_op* op, double* phi, double tau_re, double tau_im, int m, hipStream_t s) {
   const Batch& B = op->B;
   ensure_krylov(op, m);
@@ -1064,6 +1115,8 @@ static int arnoldi(mh_op* op, double* phi, double tau_re, double tau_im, int m, 
   K.m_max = op->m_alloc;
   launch_norm_init(B, phi, K, m, s);
   launch_krylov_scale(B, phi, op->V[0], K, 5, s);
+  const bool adaptive = op->krylov_tol > 0.0;
+  int built = m;
   for (int k = 0; k < m; ++k) {
     double* w = op->V[k + 1];
     g_apply(op, op->V[k], w, 1, s);
@@ -1071,9 +1124,21 @@ static int arnoldi(mh_op* op, double* phi, double tau_re, double tau_im, int m, 
     launch_orth_dot(B, op->Vdev, k, w, K, s);
     launch_orth_update(B, op->Vdev, k, w, K, 2, s);
     launch_krylov_scale(B, w, w, K, 1, s);
+    if (adaptive && k + 1 < m) {
+      launch_krylov_check(op->ni, K, tau_re, tau_im, k + 1, op->krylov_tol, s);
+      HIPCHK(hipMemcpyAsync(op->hostpin, K.scal, (size_t)op->ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool all = true;
+      for (int i = 0; i < op->ni; ++i)
+        if ((int)op->hostpin[8 * i + 4] > k + 1) all = false;
+      if (all) {
+        built = k + 1;
+        break;
+      }
+    }
   }
   launch_expm(op->ni, K, tau_re, tau_im, s);
-  launch_combine(B, op->Vdev, m, phi, K, s);
+  launch_combine(B, op->Vdev, built, phi, K, s);
   return MH_OK;
 }
 
@@ -1247,6 +1312,56 @@ static void step_after_poisson(mh_op* op, double* phi, double* Ci, const double*
 }
 
 namespace {
+// One whole time step as a fixed launch sequence (MH_PROP_GRAPH_STEP), for
+// the steps whose CG start is the quadratic extrapolation: the RDMs, the
+// start, the pair Poisson solves with `K` multigrid-preconditioned CG
+// iterations and no host check, the boundary fill, the step's field value
+// from the device table, then the step after the Poisson solve; the counter
+// moves on to the next step.
+static void whole_step(mh_op* op, double* phi, double* Ci, double* W, int K, double tre, double tim, int m,
+                       int imaginary, hipStream_t s) {
+  const Batch& B = op->B;
+  const int64_t wlen = (int64_t)B.tF * op->ncol;
+  launch_ci_rdm_full(op->ni, op->ci, Ci, op->gam, op->Gam, op->Gtmp, s);
+  launch_extrapolate2(W, op->Wprev, op->Wprev2, wlen, s);
+  poisson_begin(op, phi, W, 1, s);
+  mg_pcg(op, W, nullptr, s, K);
+  launch_fill_real(B, W, 1, op->ncol, 1, op->P.acc, s);
+  launch_set_indexed(op->Ebuf, op->Etab, op->step_ctr, s);
+  step_after_poisson(op, phi, Ci, W, 1, tre, tim, m, imaginary, s);
+  launch_counter(op->step_ctr, 0, 1, s);
+}
+
+// Copy the step's scalars to the host (a synchronising read) and file its
+// records; MH_SINGULAR_RDM / MH_NONFINITE where the step went wrong.
+static int record_step(mh_op* op, mh_observables* obs, int step, int advance, int it, hipStream_t s) {
+  const int ni = op->ni;
+  double* hs = op->hostpin;
+  double* hk = hs + 8 * (size_t)ni;
+  int* hf = (int*)(hs + 16 * (size_t)ni);
+  HIPCHK(hipMemcpyAsync(hs, op->obs, (size_t)ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (advance) HIPCHK(hipMemcpyAsync(hk, op->K.scal, (size_t)ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hf, op->flag, ni * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < ni; ++i) {
+    if (hf[i]) return fail(MH_SINGULAR_RDM, "1-RDM not positive after regularisation");
+    if (!std::isfinite(hs[8 * i]) || !std::isfinite(hs[8 * i + 1])) return fail(MH_NONFINITE, "non-finite observables");
+  }
+  if (obs) {
+    for (int i = 0; i < ni; ++i) {
+      const size_t o = (size_t)step * ni + i;
+      if (obs->dipole) obs->dipole[o] = hs[8 * i + 1];
+      if (obs->energy) obs->energy[o] = hs[8 * i];
+      if (obs->ortho) obs->ortho[o] = hs[8 * i + 2];
+      if (obs->momentum) obs->momentum[o] = hs[8 * i + 3];
+      if (obs->krylov_dim) obs->krylov_dim[o] = advance ? (int32_t)hk[8 * i + 4] : 0;
+      if (obs->err_est) obs->err_est[o] = advance ? hk[8 * i + 3] : 0.0;
+    }
+    if (obs->cg_iters) obs->cg_iters[step] = it;
+  }
+  return MH_OK;
+}
+
 struct GraphHolder {
   hipGraph_t g = nullptr;
   hipGraphExec_t x = nullptr;
@@ -1268,9 +1383,15 @@ extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const
                             double dt, int32_t m, int32_t flags, mh_observables* obs, void* stream) {
   const int imaginary = flags & MH_PROP_IMAGINARY;
   const bool use_graph = (flags & MH_PROP_GRAPH) != 0;
+  const bool graph_step = (flags & MH_PROP_GRAPH_STEP) != 0;
   const int last_step = (flags & MH_PROP_NO_FINAL) ? n_steps - 1 : n_steps;
   if (!op || !phi || !Ci || !W || (n_steps > 0 && !E_steps)) return fail(MH_INVALID_ARG, "null argument");
   if (n_steps < 0 || m < 1 || m > 24) return fail(MH_INVALID_ARG, "bad step count or Krylov dimension");
+  if ((use_graph || graph_step) && op->krylov_tol > 0.0)
+    return fail(MH_INVALID_ARG, "graph replay needs a fixed Krylov dimension (krylov_tol = 0)");
+  if (use_graph && graph_step) return fail(MH_INVALID_ARG, "MH_PROP_GRAPH and MH_PROP_GRAPH_STEP exclude each other");
+  if (graph_step && !(op->B.mx.sched_poi & 16))
+    return fail(MH_INVALID_ARG, "whole-step graph replay needs the multigrid Poisson schedule (bit 4)");
   return guarded([&]() -> int {
     hipStream_t s = S(stream);
     const int ni = op->ni;
@@ -1279,14 +1400,57 @@ extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const
     GraphHolder gh;
     EventHolder evh;
     const bool saved_timing = op->timing;
-    if (use_graph) {
+    if (use_graph || graph_step) {
       ensure_krylov(op, m);
       if (!op->gstream) HIPCHK(hipStreamCreateWithFlags(&op->gstream, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&evh.e[0], hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&evh.e[1], hipEventDisableTiming));
     }
+    if (graph_step && n_steps > 3) {
+      if (op->Etab_len < n_steps + 1) {
+        op->Etab = op->alloc<double>((size_t)n_steps + 1);
+        op->Etab_len = n_steps + 1;
+      }
+      if (!op->step_ctr) op->step_ctr = op->alloc<int>(1);
+      HIPCHK(hipMemcpyAsync(op->Etab, E_steps, (size_t)(n_steps + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      ensure_mg(op, s);
+    }
+    int K_fixed = 0;   // CG iterations of the replayed steps
     for (int step = 0; step <= last_step; ++step) {
       const double E = (n_steps > 0 || E_steps) ? E_steps[step] : 0.0;
+      if (graph_step && step >= 3 && step < n_steps) {
+        // whole step from the graph: one launch; then the residual check and
+        // the step's records
+        hipStream_t g = op->gstream;
+        if (!gh.x) {
+          K_fixed = op->cg_hint + 3;
+          launch_counter(op->step_ctr, 1, step, s);
+          op->timing = false;  // no timing events inside the graph
+          hipEvent_t* saved_ev = op->P.ev;
+          op->P.ev = nullptr;
+          HIPCHK(hipEventRecord(evh.e[0], s));
+          HIPCHK(hipStreamWaitEvent(g, evh.e[0], 0));
+          HIPCHK(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
+          whole_step(op, phi, Ci, W, K_fixed, tre, tim, m, imaginary, g);
+          HIPCHK(hipStreamEndCapture(g, &gh.g));
+          HIPCHK(hipGraphInstantiate(&gh.x, gh.g, nullptr, nullptr, 0));
+          op->P.ev = saved_ev;
+          op->timing = saved_timing;
+        }
+        HIPCHK(hipEventRecord(evh.e[0], s));
+        HIPCHK(hipStreamWaitEvent(g, evh.e[0], 0));
+        HIPCHK(hipGraphLaunch(gh.x, g));
+        HIPCHK(hipEventRecord(evh.e[1], g));
+        HIPCHK(hipStreamWaitEvent(s, evh.e[1], 0));
+        op->P.it = K_fixed;
+        const int conv = poisson_converged(op, s);
+        if (conv < 0) return fail(MH_NONFINITE, "non-finite Poisson residual");
+        if (conv == 0) status = MH_NOT_CONVERGED;
+        const int rr = record_step(op, obs, step, 1, K_fixed, s);
+        if (rr != MH_OK) return rr;
+        continue;
+      }
       launch_ci_rdm_full(ni, op->ci, Ci, op->gam, op->Gam, op->Gtmp, s);
       int it = 0;
       // CG start: the previous solution; at the third step of the call the
@@ -1327,30 +1491,8 @@ extern "C" int mh_propagate(mh_op* op, double* phi, double* Ci, double* W, const
       } else {
         step_after_poisson(op, phi, Ci, W, advance, tre, tim, m, imaginary, s);
       }
-      // copy this step's scalars
-      double* hs = op->hostpin;
-      double* hk = hs + 8 * (size_t)ni;
-      int* hf = (int*)(hs + 16 * (size_t)ni);
-      HIPCHK(hipMemcpyAsync(hs, op->obs, (size_t)ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-      if (advance)
-        HIPCHK(hipMemcpyAsync(hk, op->K.scal, (size_t)ni * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hf, op->flag, ni * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i < ni; ++i) {
-        if (hf[i]) return fail(MH_SINGULAR_RDM, "1-RDM not positive after regularisation");
-        if (!std::isfinite(hs[8 * i]) || !std::isfinite(hs[8 * i + 1])) return fail(MH_NONFINITE, "non-finite observables");
-      }
-      if (obs) {
-        for (int i = 0; i < ni; ++i) {
-          const size_t o = (size_t)step * ni + i;
-          if (obs->dipole) obs->dipole[o] = hs[8 * i + 1];
-          if (obs->energy) obs->energy[o] = hs[8 * i];
-          if (obs->ortho) obs->ortho[o] = hs[8 * i + 2];
-          if (obs->momentum) obs->momentum[o] = hs[8 * i + 3];
-          if (obs->err_est) obs->err_est[o] = advance ? hk[8 * i + 3] : 0.0;
-        }
-        if (obs->cg_iters) obs->cg_iters[step] = it;
-      }
+      const int rr = record_step(op, obs, step, advance, it, s);
+      if (rr != MH_OK) return rr;
     }
     return status;
   });
@@ -1440,7 +1582,7 @@ static void build_sell(mh_op* op, int i, hipStream_t s) {
 }
 
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 63 : 7)) != 0)
+  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 127 : 7)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");

@@ -34,6 +34,43 @@ __device__ __forceinline__ double2 ldg2(const double* p, int64_t i) {
   return ldg2(reinterpret_cast<const double2*>(p), i);
 }
 
+// V consecutive values of a global row as doubles, in 16-byte loads (double
+// pairs or float quads; the row is aligned to V elements).
+typedef float fvec2_t __attribute__((ext_vector_type(2)));
+typedef float fvec4_t __attribute__((ext_vector_type(4)));
+template <int V>
+__device__ __forceinline__ void load_vals(const __attribute__((address_space(1))) double* row, double* out) {
+  if constexpr (V == 1) {
+    out[0] = row[0];
+  } else {
+#pragma unroll
+    for (int v = 0; v < V / 2; ++v) {
+      const double2 r2 = ldg2((const double*)row, v);
+      out[2 * v] = r2.x;
+      out[2 * v + 1] = r2.y;
+    }
+  }
+}
+template <int V>
+__device__ __forceinline__ void load_vals(const __attribute__((address_space(1))) float* row, double* out) {
+  if constexpr (V == 1) {
+    out[0] = row[0];
+  } else if constexpr (V == 2) {
+    const fvec2_t f = *(const __attribute__((address_space(1))) fvec2_t*)row;
+    out[0] = f.x;
+    out[1] = f.y;
+  } else {
+#pragma unroll
+    for (int v = 0; v < V / 4; ++v) {
+      const fvec4_t f = ((const __attribute__((address_space(1))) fvec4_t*)row)[v];
+      out[4 * v] = f.x;
+      out[4 * v + 1] = f.y;
+      out[4 * v + 2] = f.z;
+      out[4 * v + 3] = f.w;
+    }
+  }
+}
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {

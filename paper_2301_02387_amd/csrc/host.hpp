@@ -61,6 +61,7 @@ struct OpHost {
   std::vector<int32_t> node_inc;           // NE x 8: cell*64 + local index of each incident cell, -1 padded
   // interface (hanging-master) block of the mass matrix, rows = masters
   std::vector<int32_t> ma_index;           // N: index into masters or -1
+  std::vector<int32_t> ma_dof;             // DoF of each interface unknown (reverse Cuthill-McKee order)
   std::vector<int32_t> ma_ptr, ma_col;     // CSR over masters (columns = master index)
   std::vector<double> ma_val;
   std::vector<double> ma_dinv;             // 1 / diagonal

@@ -67,8 +67,10 @@ __global__ void __launch_bounds__(NT) k_cheb_iter(const DevMesh* __restrict__ dm
   const double c1 = d.cheb[1 + 2 * k], c2 = d.cheb[2 + 2 * k];
   const double2* dI = din + o;
   const int g = (int)(threadIdx.x & (CHEB_G - 1));
-  const int64_t groups = (int64_t)gridDim.x * (NT / CHEB_G);
-  for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) / CHEB_G; i < d.nMa; i += groups) {
+  // XCD x sweeps the x-th eighth of the (band-ordered) rows, so its gathers
+  // stay within that part of the vectors and hit its own L2
+  const XcdSweep sw = xcd_sweep(d.nMa, NT / CHEB_G);
+  for (int64_t i = sw.start + threadIdx.x / CHEB_G; i < sw.end; i += sw.step) {
     double sx[8], sy[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) { sx[p] = 0.0; sy[p] = 0.0; }
@@ -247,7 +249,7 @@ void launch_ma_solve(const Batch& b, const double* ma_b, double* x, double* r, d
                      (double2*)dbuf0);
   double* din = dbuf0;
   double* dout = dbuf1;
-  const dim3 gi(nblocks(b.mx.nMa * CHEB_G), b.ni);
+  const dim3 gi(xcd_grid(b.mx.nMa, NT / CHEB_G, 65536), b.ni);
   for (int k = 0; k < b.cheb_iters; ++k) {
     hipLaunchKernelGGL(k_cheb_iter, gi, dim3(NT), 0, s, b.dm, (double2*)x, (double2*)r, (const double2*)din,
                        (double2*)dout, k);
@@ -331,6 +333,21 @@ void launch_extrapolate2(double* x, double* p1, double* p2, int64_t nd, hipStrea
 }
 void launch_set(double* out, double value, hipStream_t s) {
   hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, out, value);
+}
+// A step counter on the device, so that a captured step reads its own field
+// value from a table: out = table[*ctr]; ctr += add.
+__global__ void k_set_indexed(double* __restrict__ out, const double* __restrict__ table,
+                              const int* __restrict__ ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = table[ctr[0]];
+}
+__global__ void k_counter(int* __restrict__ ctr, int set, int value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] = set ? value : ctr[0] + value;
+}
+void launch_set_indexed(double* out, const double* table, const int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_indexed, dim3(1), dim3(64), 0, s, out, table, ctr);
+}
+void launch_counter(int* ctr, int set, int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, ctr, set, value);
 }
 
 // =====================================================================
@@ -498,60 +515,72 @@ void launch_xgram_flat(int ni, const double* X, int na, const double* Y, int nb,
 
 // Pair-product integrals: G[(p,q)][col] = sum_i m_i conj(phi_p) phi_q Wcol_i
 // (X built on the fly as phi_p conj(phi_q) so that conj(X) = conj(phi_p) phi_q).
+// Register tiles of GT_A pair products x GT_C columns per thread: every
+// round of LDS reads (four products, four potentials) feeds 32 FMAs; tiles
+// numbered column-tile fastest, at most NT of them (n <= 8).
+constexpr int GT_A = 4, GT_C = 4;
 __global__ void __launch_bounds__(NT) k_gint(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
                                              const double* __restrict__ W, int ncol, double2* __restrict__ part) {
   INSTANCE;
   __shared__ double2 sx[XG_CH * 64];
   __shared__ double sw[XG_CH * 64];
   const int n = d.n, na = n * n, nout = na * ncol;
+  const int nap = (na + GT_A - 1) / GT_A * GT_A, ncp = (ncol + GT_C - 1) / GT_C * GT_C;
   phi += d.oE * n;
   W += d.oF * ncol;
-  constexpr int MAXO = 16;
-  double2 accv[MAXO];
+  const int tiles_c = ncp / GT_C, tiles = (nap / GT_A) * tiles_c;
+  const bool act = (int)threadIdx.x < tiles;
+  const int a0 = act ? ((int)threadIdx.x / tiles_c) * GT_A : 0, c0 = act ? ((int)threadIdx.x % tiles_c) * GT_C : 0;
+  double2 acc[GT_A][GT_C];
 #pragma unroll
-  for (int j = 0; j < MAXO; ++j) accv[j] = make_double2(0.0, 0.0);
+  for (int u = 0; u < GT_A; ++u)
+#pragma unroll
+    for (int v = 0; v < GT_C; ++v) acc[u][v] = make_double2(0.0, 0.0);
   const int64_t rows = d.NE;
   for (int64_t base = (int64_t)blockIdx.x * XG_CH; base < rows; base += (int64_t)gridDim.x * XG_CH) {
     const int cnt = (int)((rows - base) < XG_CH ? (rows - base) : XG_CH);
     __syncthreads();
-    for (int e = threadIdx.x; e < XG_CH * na; e += NT) {
-      int r = e / na, a = e - r * na;
-      int p = a / n, q = a - p * n;
+    for (int e = threadIdx.x; e < XG_CH * nap; e += NT) {
+      const int r = e / nap, a = e - r * nap;
       double2 v = make_double2(0.0, 0.0);
-      if (r < cnt) {
-        int64_t i = base + r;
-        double2 fp = phi[i * n + p], fq = phi[i * n + q];
+      if (r < cnt && a < na) {
+        const int p = a / n, q = a - p * n;
+        const int64_t i = base + r;
+        const double2 fp = phi[i * n + p], fq = phi[i * n + q];
         // phi_p conj(phi_q) * m_i
         v = cscale(d.m[i], make_double2(fp.x * fq.x + fp.y * fq.y, fp.y * fq.x - fp.x * fq.y));
       }
-      sx[r * na + a] = v;
+      sx[r * nap + a] = v;
     }
-    for (int e = threadIdx.x; e < XG_CH * ncol; e += NT) {
-      int r = e / ncol, c = e - r * ncol;
-      sw[r * ncol + c] = (r < cnt) ? W[(base + r) * ncol + c] : 0.0;
+    for (int e = threadIdx.x; e < XG_CH * ncp; e += NT) {
+      const int r = e / ncp, c = e - r * ncp;
+      sw[r * ncp + c] = (r < cnt && c < ncol) ? W[(base + r) * ncol + c] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < MAXO; ++j) {
-      int o = threadIdx.x + j * NT;
-      if (o >= nout) break;
-      int a = o / ncol, c = o - a * ncol;
-      double2 s = accv[j];
+    if (act)
       for (int r = 0; r < cnt; ++r) {
-        double2 xv = sx[r * na + a];
-        double yv = sw[r * ncol + c];
-        s.x += xv.x * yv;
-        s.y -= xv.y * yv;
+        double2 xv[GT_A];
+        double yv[GT_C];
+#pragma unroll
+        for (int u = 0; u < GT_A; ++u) xv[u] = sx[r * nap + a0 + u];
+#pragma unroll
+        for (int v = 0; v < GT_C; ++v) yv[v] = sw[r * ncp + c0 + v];
+#pragma unroll
+        for (int u = 0; u < GT_A; ++u)
+#pragma unroll
+          for (int v = 0; v < GT_C; ++v) {
+            acc[u][v].x += xv[u].x * yv[v];
+            acc[u][v].y -= xv[u].y * yv[v];
+          }
       }
-      accv[j] = s;
-    }
   }
+  if (!act) return;
   double2* pb = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout;
 #pragma unroll
-  for (int j = 0; j < MAXO; ++j) {
-    int o = threadIdx.x + j * NT;
-    if (o < nout) pb[o] = accv[j];
-  }
+  for (int u = 0; u < GT_A; ++u)
+#pragma unroll
+    for (int v = 0; v < GT_C; ++v)
+      if (a0 + u < na && c0 + v < ncol) pb[(a0 + u) * ncol + c0 + v] = acc[u][v];
 }
 
 // The same for n^2 x ncol <= 16 outputs (two orbitals): every thread
@@ -698,6 +727,58 @@ __global__ void __launch_bounds__(NT) k_build_U(const DevMesh* __restrict__ dm, 
   }
 }
 
+// Eight orbitals (64 x 64 map): a register-tiled product per workgroup of
+// 64 nodes, U_tile = W_tile Mr^T, each thread a block of 4 nodes x 4 outputs
+// (16 FMAs per 8 LDS reads); the node rows of W are read once, coalesced.
+// Mr is staged as sM[c][v * 16 + g] = Mr[4 g + v][c], so the 16 output groups
+// of a wave read consecutive words.
+__global__ void __launch_bounds__(NT) k_build_U64(const DevMesh* __restrict__ dm, const double* __restrict__ W,
+                                                  const double* __restrict__ Mr, double* __restrict__ Upk) {
+  INSTANCE;
+  __shared__ double sM[64 * 64];
+  __shared__ double sW[64 * 65];
+  Mr += (int64_t)blockIdx.y * 64 * 64;
+  W += d.oF * 64;
+  Upk += d.oE * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int o = e / 64, c = e - o * 64;
+    sM[c * 64 + (o % 4) * 16 + o / 4] = Mr[e];
+  }
+  const int ng = threadIdx.x / 16, og = threadIdx.x % 16;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < d.NE; base += (int64_t)gridDim.x * 64) {
+    const int cnt = (int)((d.NE - base) < 64 ? (d.NE - base) : 64);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+      const int r = e / 64, c = e - r * 64;
+      sW[r * 65 + c] = r < cnt ? W[(base + r) * 64 + c] : 0.0;
+    }
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int c = 0; c < 64; ++c) {
+      double wv[4], mv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wv[u] = sW[(4 * ng + u) * 65 + c];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mv[v] = sM[c * 64 + v * 16 + og];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += wv[u] * mv[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 4 * ng + u;
+      if (r < cnt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Upk[(base + r) * 64 + 4 * og + v] = acc[u][v];
+    }
+  }
+}
+
 void launch_build_U_full(const Batch& b, const double* W, const double* Gamma, const int* colmap, double* Mr,
                          double* Upk, hipStream_t s) {
   const int nn = b.mx.n * b.mx.n;
@@ -707,7 +788,8 @@ void launch_build_U_full(const Batch& b, const double* W, const double* Gamma, c
   if (nn <= 1) hipLaunchKernelGGL(k_build_U<1>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
   else if (nn <= 4) hipLaunchKernelGGL(k_build_U<4>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
   else if (nn <= 16) hipLaunchKernelGGL(k_build_U<16>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
-  else hipLaunchKernelGGL(k_build_U<64>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
+  else if (nn < 64) hipLaunchKernelGGL(k_build_U<64>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
+  else hipLaunchKernelGGL(k_build_U64, dim3(nblocks(b.mx.NE, 64, 8192), b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
 }
 
 // =====================================================================
@@ -985,8 +1067,13 @@ void launch_norm_init(const Batch& b, const double* phi, Krylov& K, int m, hipSt
 // y = beta expm(A) e1, A = -i tau H_m (m = scal[4]); scaling and squaring
 // with a degree-18 Taylor polynomial at |A/2^s|_1 <= 1/2 (remainder below
 // 1e-22).  One workgroup per instance; matrices in LDS.
+// m_try > 0 (adaptive dimension): only the error estimate of dimension m_try,
+// beta h_{m_try+1,m_try} |e_{m_try}^T expm(A_{m_try}) e1|; where it is at or
+// below tol the instance's dimension scal[4] becomes m_try (instances whose
+// space already ended, by breakdown or an earlier estimate, are left alone).
 __global__ void __launch_bounds__(NT) k_expm(const double2* __restrict__ H, int m_max, double tau_re, double tau_im,
-                                             double* __restrict__ scal, double2* __restrict__ y) {
+                                             double* __restrict__ scal, double2* __restrict__ y, int m_try,
+                                             double tol) {
   __shared__ double2 A[KMAX * KMAX], T[KMAX * KMAX], S[KMAX * KMAX];
   __shared__ int sh_s;
   __shared__ double sh_norm;
@@ -994,7 +1081,8 @@ __global__ void __launch_bounds__(NT) k_expm(const double2* __restrict__ H, int 
   H += (int64_t)inst * (m_max + 1) * m_max;
   scal += 8 * inst;
   y += (int64_t)inst * m_max;
-  const int m = (int)scal[4];
+  if (m_try > 0 && (int)scal[4] <= m_try) return;  // uniform over the workgroup
+  const int m = m_try > 0 ? m_try : (int)scal[4];
   const int mm = m * m;
   // A = -i tau H = (tau_im - i tau_re) H
   const double2 f = make_double2(tau_im, -tau_re);
@@ -1050,6 +1138,14 @@ __global__ void __launch_bounds__(NT) k_expm(const double2* __restrict__ H, int 
     __syncthreads();
   }
   const double beta = scal[0];
+  if (m_try > 0) {
+    if (threadIdx.x == 0) {
+      const double2 hlast = H[m + (int64_t)(m_max + 1) * (m - 1)];
+      const double2 ylast = T[(m - 1) * m];
+      if (beta * hypot(hlast.x, hlast.y) * hypot(ylast.x, ylast.y) <= tol) scal[4] = m;
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < m_max; i += NT) y[i] = (i < m) ? cscale(beta, T[i * m]) : make_double2(0.0, 0.0);
   if (threadIdx.x == 0) {
     double2 hlast = H[m + (int64_t)(m_max + 1) * (m - 1)];
@@ -1060,7 +1156,12 @@ __global__ void __launch_bounds__(NT) k_expm(const double2* __restrict__ H, int 
 
 void launch_expm(int ni, Krylov& K, double tau_re, double tau_im, hipStream_t s) {
   hipLaunchKernelGGL(k_expm, dim3(1, ni), dim3(NT), 0, s, (const double2*)K.H, K.m_max, tau_re, tau_im, K.scal,
-                     (double2*)K.y);
+                     (double2*)K.y, 0, 0.0);
+}
+
+void launch_krylov_check(int ni, Krylov& K, double tau_re, double tau_im, int m_try, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_expm, dim3(1, ni), dim3(NT), 0, s, (const double2*)K.H, K.m_max, tau_re, tau_im, K.scal,
+                     (double2*)K.y, m_try, tol);
 }
 
 __global__ void __launch_bounds__(NT) k_combine(const DevMesh* __restrict__ dm, const double2* const* __restrict__ V,
@@ -1091,7 +1192,6 @@ void launch_combine(const Batch& b, double* const* V, int m, double* phi, Krylov
 // real columns is (r, s, part) = colinfo[c].
 // =====================================================================
 constexpr int MP_CH = 32;
-constexpr int MP_MAXH = 169;  // (lmax+1)^2 for lmax <= 12
 
 __device__ __forceinline__ double pair_density(const double2* phi, int n, int64_t i, int r, int s, int part) {
   double2 a = phi[i * n + r], b = phi[i * n + s];
@@ -1099,32 +1199,43 @@ __device__ __forceinline__ double pair_density(const double2* phi, int n, int64_
   return part == 0 ? (a.x * b.x + a.y * b.y) : (a.x * b.y - a.y * b.x);
 }
 
-// MAXO: outputs (harmonic x column) per thread, at least ceil(nout / NT);
-// compile-time, so the accumulators stay in registers.
-template <int MAXO>
-__global__ void __launch_bounds__(NT) k_moments(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
-                                                int lmax, int ncol, const int* __restrict__ colinfo,
-                                                double* __restrict__ part) {
+// Multipole moments Q[t][c] = sum_i R_t(x_i) m_i rho_c(x_i) of the pair
+// densities, per instance, with register tiles: each thread accumulates a
+// tile of MT_H harmonics x MT_C columns, so every pair of LDS reads (one
+// harmonic quadruple, one column quadruple) feeds 16 FMAs.  Tiles are
+// numbered column-tile fastest; grid.z splits the tiles in sets of NT.
+constexpr int MT_H = 4, MT_C = 4;
+constexpr int MP_HP = 172;  // harmonics padded to a multiple of MT_H
+__global__ void __launch_bounds__(NT) k_moments_rb(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
+                                                   int lmax, int ncol, const int* __restrict__ colinfo,
+                                                   double* __restrict__ part) {
   INSTANCE;
-  __shared__ double sR[MP_CH * MP_MAXH];
+  __shared__ double sR[MP_CH * MP_HP];
   __shared__ double sW[MP_CH * 64];
   const int nh = (lmax + 1) * (lmax + 1);
+  const int nhp = (nh + MT_H - 1) / MT_H * MT_H;
+  const int ncp = (ncol + MT_C - 1) / MT_C * MT_C;
   const int nout = nh * ncol;
   const int n = d.n;
   phi += d.oE * n;
   const double cx = d.center[0], cy = d.center[1], cz = d.center[2];
-  const int o0 = blockIdx.z * MAXO * NT;  // this workgroup's slice of the outputs
-  double accv[MAXO];
+  const int tiles_c = ncp / MT_C, tiles = (nhp / MT_H) * tiles_c;
+  const int tile = blockIdx.z * NT + threadIdx.x;
+  const bool act = tile < tiles;
+  const int t0 = act ? (tile / tiles_c) * MT_H : 0, c0 = act ? (tile % tiles_c) * MT_C : 0;
+  double acc[MT_H][MT_C];
 #pragma unroll
-  for (int j = 0; j < MAXO; ++j) accv[j] = 0.0;
+  for (int a = 0; a < MT_H; ++a)
+#pragma unroll
+    for (int b = 0; b < MT_C; ++b) acc[a][b] = 0.0;
   const int64_t rows = d.NE;
   for (int64_t base = (int64_t)blockIdx.x * MP_CH; base < rows; base += (int64_t)gridDim.x * MP_CH) {
     const int cnt = (int)((rows - base) < MP_CH ? (rows - base) : MP_CH);
     __syncthreads();
-    // harmonics of the chunk's rows, one (row, order m) per thread
+    // harmonics of the chunk's rows, one (row, order m) per thread; padding zero
     for (int w = threadIdx.x; w < MP_CH * (lmax + 1); w += NT) {
       const int r = w / (lmax + 1), m = w - r * (lmax + 1);
-      double* R = sR + r * nh;
+      double* R = sR + r * nhp;
       if (r < cnt) {
         const int64_t i = base + r;
         solid_regular_m(d.xyz[3 * i] - cx, d.xyz[3 * i + 1] - cy, d.xyz[3 * i + 2] - cz, lmax, m, R);
@@ -1135,36 +1246,40 @@ __global__ void __launch_bounds__(NT) k_moments(const DevMesh* __restrict__ dm, 
         }
       }
     }
-    for (int e = threadIdx.x; e < MP_CH * ncol; e += NT) {
-      int r = e / ncol, c = e - r * ncol;
+    if (nhp > nh)
+      for (int e = threadIdx.x; e < MP_CH * (nhp - nh); e += NT) sR[(e / (nhp - nh)) * nhp + nh + e % (nhp - nh)] = 0.0;
+    for (int e = threadIdx.x; e < MP_CH * ncp; e += NT) {
+      const int r = e / ncp, c = e - r * ncp;
       double v = 0.0;
-      if (r < cnt) {
-        int64_t i = base + r;
-        int ci = colinfo[c];
+      if (r < cnt && c < ncol) {
+        const int64_t i = base + r;
+        const int ci = colinfo[c];
         v = d.m[i] * pair_density(phi, n, i, ci & 255, (ci >> 8) & 255, ci >> 16);
       }
-      sW[r * ncol + c] = v;
+      sW[r * ncp + c] = v;
     }
     __syncthreads();
+    if (act)
+      for (int r = 0; r < cnt; ++r) {
+        double hv[MT_H], wv[MT_C];
 #pragma unroll
-    for (int j = 0; j < MAXO; ++j) {
-      const int o = o0 + threadIdx.x + j * NT;
-      if (o < nout) {
-        const int t = o / ncol, c = o - t * ncol;
-        double s = accv[j];
-        for (int r = 0; r < cnt; ++r) s += sR[r * nh + t] * sW[r * ncol + c];
-        accv[j] = s;
+        for (int a = 0; a < MT_H; ++a) hv[a] = sR[r * nhp + t0 + a];
+#pragma unroll
+        for (int b = 0; b < MT_C; ++b) wv[b] = sW[r * ncp + c0 + b];
+#pragma unroll
+        for (int a = 0; a < MT_H; ++a)
+#pragma unroll
+          for (int b = 0; b < MT_C; ++b) acc[a][b] += hv[a] * wv[b];
       }
-    }
   }
+  if (!act) return;
   double* pb = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout;
 #pragma unroll
-  for (int j = 0; j < MAXO; ++j) {
-    const int o = o0 + threadIdx.x + j * NT;
-    if (o < nout) pb[o] = accv[j];
-  }
+  for (int a = 0; a < MT_H; ++a)
+#pragma unroll
+    for (int b = 0; b < MT_C; ++b)
+      if (t0 + a < nh && c0 + b < ncol) pb[(t0 + a) * ncol + c0 + b] = acc[a][b];
 }
-
 // out[i][o] = sum_b part[i][b][o]; one workgroup per (output, instance)
 __global__ void __launch_bounds__(NT) k_sum_parts_real(const double* __restrict__ part, int nblk, int nout,
                                                        double* __restrict__ out) {
@@ -1340,20 +1455,12 @@ static int rhs_blocks(const Batch& b, int ncol) { return nblocks(b.mx.N, NT / nc
 void launch_poisson_pipeline_moments(const Batch& b, const double* phi, const int* colinfo, PoissonWs& P,
                                      hipStream_t s) {
   const int nout = P.nharm * P.ncol;
-  // outputs per thread: at most 16 (registers); larger sets split over grid.z
-  const int per = (nout + NT - 1) / NT;
   const double2* ph = (const double2*)phi;
-  if (per <= 4) {
-    hipLaunchKernelGGL(k_moments<4>, dim3(P.mblk, b.ni, 1), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
-                       P.mpart);
-  } else if (per <= 8) {
-    hipLaunchKernelGGL(k_moments<8>, dim3(P.mblk, b.ni, 1), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
-                       P.mpart);
-  } else {
-    const unsigned nz = (unsigned)((nout + 16 * NT - 1) / (16 * NT));
-    hipLaunchKernelGGL(k_moments<16>, dim3(P.mblk, b.ni, nz), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
-                       P.mpart);
-  }
+  // register tiles of 4 harmonics x 4 columns, sets of NT tiles over grid.z
+  const int tiles = ((P.nharm + MT_H - 1) / MT_H) * ((P.ncol + MT_C - 1) / MT_C);
+  const unsigned nz = (unsigned)((tiles + NT - 1) / NT);
+  hipLaunchKernelGGL(k_moments_rb, dim3(P.mblk, b.ni, nz), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
+                     P.mpart);
   hipLaunchKernelGGL(k_sum_parts_real, dim3(nout, b.ni), dim3(NT), 0, s, P.mpart, P.mblk, nout, P.Q);
 }
 
@@ -1880,7 +1987,7 @@ void launch_ci_lanczos(int ni, const CIDev& c, double* const* Qdev, double* cons
                        (double2*)K.H, K.m_max, K.scal, (k == m - 1) ? 1 : 0);
   }
   hipLaunchKernelGGL(k_expm, dim3(1, ni), dim3(NT), 0, s, (const double2*)K.H, K.m_max, tau_re, tau_im, K.scal,
-                     (double2*)K.y);
+                     (double2*)K.y, 0, 0.0);
   hipLaunchKernelGGL(k_ci_combine, dim3(ni), dim3(1024), 0, s, c.dim, (double2* const*)Qdev, m, K.m_max,
                      (const double2*)K.y, (double2*)Cvec, normalize);
 }

@@ -123,6 +123,8 @@ void launch_copy(const double* in, double* out, int64_t nd, hipStream_t s);
 void launch_axpby(int64_t nd, double a, const double* x, double b, double* y, hipStream_t s);
 void launch_zero(double* out, int64_t nd, hipStream_t s);
 void launch_set(double* out, double value, hipStream_t s);
+void launch_set_indexed(double* out, const double* table, const int* ctr, hipStream_t s);  // out = table[*ctr]
+void launch_counter(int* ctr, int set, int value, hipStream_t s);                        // *ctr = value or += value
 // x <- 2 x - xprev and xprev <- the old x (linear extrapolation in time) over nd doubles
 void launch_extrapolate(double* x, double* xprev, int64_t nd, hipStream_t s);
 // x <- 3 x - 3 p1 + p2 (quadratic extrapolation in time), then p2 <- p1 and p1 <- the old x
@@ -163,6 +165,9 @@ void launch_orth_update(const Batch& b, double* const* V, int k, double* w, Kryl
 void launch_orth_dot(const Batch& b, double* const* V, int k, double* w, Krylov& K, hipStream_t s);
 void launch_krylov_scale(const Batch& b, const double* src, double* dst, Krylov& K, int which, hipStream_t s);
 void launch_expm(int ni, Krylov& K, double tau_re, double tau_im, hipStream_t s);
+// Adaptive dimension: where the error estimate of dimension m_try meets tol,
+// the instance's dimension (scal[4]) becomes m_try.
+void launch_krylov_check(int ni, Krylov& K, double tau_re, double tau_im, int m_try, double tol, hipStream_t s);
 void launch_combine(const Batch& b, double* const* V, int m, double* phi, Krylov& K, hipStream_t s);
 
 // ---- Poisson ---------------------------------------------------------------------
@@ -204,7 +209,10 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s);
 // Pieces of a CG iteration with another preconditioner: q = K p with p.q into
 // slot RED_PQ + k % 2, and the update pass (alpha_k = red[RED_RZ + k % 3] / p.q).
 void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k, hipStream_t s);
-void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s);
+// rf (may be null): a float copy of the updated residual (Poisson schedule bit 6)
+void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s,
+                      float* rf = nullptr);
+void launch_to_float(const double* x, float* y, int64_t nd, hipStream_t s);
 // q = K x on the DoF rows with the tuned operator kernel, p.q partials into red_scratch
 void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch, PoissonWs& P,
                           hipStream_t s);
@@ -218,6 +226,12 @@ void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, doub
                      hipStream_t s);
 void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* red,
                          int ncol, int k, int rz_slot, hipStream_t s);
+// Poisson schedule bit 6: the finest multigrid level's passes on float arrays
+void launch_poisson_apply_f(const Batch& b, const float* x, float* q, int ncol, double* red_scratch, hipStream_t s);
+void launch_mg_cheb0_f(const Batch& b, const float* r, float* z, float* d, double* red, int rz_slot, int ncol,
+                       hipStream_t s);
+void launch_mg_cheb_step_f(const Batch& b, const float* zin, const float* r, float* zout, float* d, double* red,
+                           int ncol, int k, int rz_slot, hipStream_t s);
 // Hanging rows of a real column array (xfull: x is over full rows, else extended).
 void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s);
 

@@ -23,8 +23,8 @@ namespace mh {
 // the indices and coefficients of the next round are requested before this
 // round's gathers, so each round waits for one memory latency.  Entries past
 // the end repeat the last one with coefficient 0 (in-bounds loads, no branch).
-template <bool SUB, class IP, class DP>
-__device__ __forceinline__ double row_gather_dot(IP col, DP val, int beg, int end, int stride, DP x, DP xm, int ncol,
+template <bool SUB, class IP, class DP, class XP>
+__device__ __forceinline__ double row_gather_dot(IP col, DP val, int beg, int end, int stride, XP x, XP xm, int ncol,
                                                  int c) {
   double s = 0.0;
   int jn[8];
@@ -56,7 +56,7 @@ __device__ __forceinline__ double row_gather_dot(IP col, DP val, int beg, int en
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       const int64_t j = (int64_t)jc[h] * ncol + c;
-      s += ac[h] * (SUB ? x[j] - xm[j] : x[j]);
+      s += ac[h] * (SUB ? (double)x[j] - (double)xm[j] : (double)x[j]);
     }
   }
   return s;
@@ -95,6 +95,9 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(const MgLevelDev* __restrict
   const auto* val = gbl(F.r_val);
   const auto* r = gbl((const double*)F.r);
   const auto* t = gbl((const double*)F.t);
+  const auto* rf = gbl(F.rf);
+  const auto* tf = gbl((const float*)F.tf);
+  const bool f32 = F.f32 != 0;
   auto* y = gblw(C.r);
   const int lane = threadIdx.x & 63;
   const int grp = lane / cw, c = lane - grp * cw, ngrp = 64 / cw;
@@ -103,7 +106,9 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(const MgLevelDev* __restrict
     double s = 0.0;
     if (c < ncol) {
       const int beg = ptr[w] + grp, end = ptr[w + 1];
-      if (end > beg) s = row_gather_dot<true>(col, val, beg, end, ngrp, r, t, ncol, c);
+      if (end > beg)
+        s = f32 ? row_gather_dot<true>(col, val, beg, end, ngrp, rf, tf, ncol, c)
+                : row_gather_dot<true>(col, val, beg, end, ngrp, r, t, ncol, c);
     }
     for (int off = 32; off >= cw; off >>= 1) s += __shfl_xor(s, off, 64);
     if (grp == 0 && c < ncol) y[w * ncol + c] = s;
@@ -122,11 +127,17 @@ __global__ void __launch_bounds__(NT) k_mg_prolong(const MgLevelDev* __restrict_
   const auto* val = gbl(F.p_val);
   const auto* x = gbl((const double*)C.z);
   auto* z = gblw(F.z);
+  auto* zf = gblw(F.zf);
+  const bool f32 = F.f32 != 0;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int64_t i = e / ncol;
     const int c = (int)(e - i * ncol);
     const int beg = ptr[i], end = ptr[i + 1];
-    if (end > beg) z[e] += row_gather_dot<false>(col, val, beg, end, 1, x, x, ncol, c);
+    if (end > beg) {
+      const double v = row_gather_dot<false>(col, val, beg, end, 1, x, x, ncol, c);
+      if (f32) zf[e] = (float)((double)zf[e] + v);
+      else z[e] += v;
+    }
   }
 }
 
@@ -219,17 +230,17 @@ static dim3 level_grid(int64_t n, int ncol, int ni) { return dim3(nblocks(n * nc
 
 // A z -> t on level l of every instance
 static void level_spmv(const MgDev& mg, int l, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s) {
-  if (l == 0) ops.spmv(mg.z0, mg.t0, s);
+  if (l == 0) ops.spmv(s);
   else hipLaunchKernelGGL(k_mg_spmv, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], ncol);
 }
 
 static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, const MgLevel0Ops& ops, hipStream_t s) {
   if (l == 0 && ops.cheb0 && mg.nu == 2) {  // fused into the level-0 operator passes
     if (from_zero) {
-      ops.cheb0(mg.z0, mg.d0, s);
+      ops.cheb0(s);
     } else {
-      ops.cheb(mg.z0, mg.z0b, mg.d0, 0, s);
-      ops.cheb(mg.z0b, mg.z0, mg.d0, 1, s);
+      ops.cheb(0, s);
+      ops.cheb(1, s);
     }
     return;
   }
@@ -297,7 +308,8 @@ void mg_rz(const DevMesh* dm, int ni, int ncol, const double* r, const double* z
   hipLaunchKernelGGL(k_rz_finish, dim3(ncol, ni), dim3(NT), 0, s, part, MG_RZ_BLOCKS, ncol, red, slot);
 }
 
-__global__ void __launch_bounds__(NT) k_mg_dir(const DevMesh* __restrict__ dm, int ncol, const double* __restrict__ z,
+template <class Z>
+__global__ void __launch_bounds__(NT) k_mg_dir(const DevMesh* __restrict__ dm, int ncol, const Z* __restrict__ z,
                                                const double* __restrict__ pprev, double* __restrict__ pcur,
                                                double* __restrict__ red, int rz_cur, int rz_prev, int rr_clear) {
   INSTANCE;
@@ -318,14 +330,19 @@ __global__ void __launch_bounds__(NT) k_mg_dir(const DevMesh* __restrict__ dm, i
   const int64_t total = d.N * ncol;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int c = (int)(e % ncol);
-    pcur[e] = z[e] + (beta[c] != 0.0 ? beta[c] * pprev[e] : 0.0);
+    pcur[e] = (double)z[e] + (beta[c] != 0.0 ? beta[c] * pprev[e] : 0.0);
   }
   if (blockIdx.x == 0 && threadIdx.x < (unsigned)ncol) red[rr_clear * ncol + threadIdx.x] = 0.0;
 }
 void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const double* z, const double* pprev, double* pcur,
             double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s) {
-  hipLaunchKernelGGL(k_mg_dir, dim3(nblocks(max_n * ncol, NT, 8192), ni), dim3(NT), 0, s, dm, ncol, z, pprev, pcur,
-                     red, rz_cur, rz_prev, rr_clear);
+  hipLaunchKernelGGL(k_mg_dir<double>, dim3(nblocks(max_n * ncol, NT, 8192), ni), dim3(NT), 0, s, dm, ncol, z, pprev,
+                     pcur, red, rz_cur, rz_prev, rr_clear);
+}
+void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const float* z, const double* pprev, double* pcur,
+            double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s) {
+  hipLaunchKernelGGL(k_mg_dir<float>, dim3(nblocks(max_n * ncol, NT, 8192), ni), dim3(NT), 0, s, dm, ncol, z, pprev,
+                     pcur, red, rz_cur, rz_prev, rr_clear);
 }
 
 }  // namespace mh

@@ -34,6 +34,12 @@ struct MgLevelDev {
   double* z = nullptr;   // correction
   double* d = nullptr;   // Chebyshev direction
   double* t = nullptr;   // operator product scratch
+  // level 0 on float storage (Poisson schedule bit 6): the residual copy, the
+  // correction and the operator product the transfers read and write
+  int f32 = 0;
+  const float* rf = nullptr;
+  float* zf = nullptr;
+  float* tf = nullptr;
 };
 
 // The batch hierarchy: lv[l] = device array [ni] of level-l records (an
@@ -50,15 +56,23 @@ struct MgDev {
   double* z0b = nullptr;    // second level-0 correction array (the fused smoothing steps alternate)
   double* t0 = nullptr;
   double* d0 = nullptr;
+  // the same level-0 arrays in float, with the float copy of the residual (schedule bit 6)
+  float* z0f = nullptr;
+  float* z0bf = nullptr;
+  float* t0f = nullptr;
+  float* d0f = nullptr;
+  float* rf = nullptr;
+  MgLevelDev* lv0_double = nullptr;  // device [ni] level-0 records on double / float storage
+  MgLevelDev* lv0_float = nullptr;
   int nu = 2;               // smoothing steps before and after the coarse correction
 };
-// Level-0 passes over the batch (batch arrays): y = A x; and, when set, the
+// Level-0 passes over the batch (batch arrays): t0 = A z0; and, when set, the
 // smoothing steps fused into the operator pass (nu = 2): the two steps from
-// zero (z, d from r0), and step k from zin into zout.
+// zero (z0, d0 from r0), and step k (k = 0: z0 -> z0b, k = 1: z0b -> z0).
 struct MgLevel0Ops {
-  std::function<void(const double* x, double* y, hipStream_t s)> spmv;
-  std::function<void(double* z, double* d, hipStream_t s)> cheb0;
-  std::function<void(const double* zin, double* zout, double* d, int k, hipStream_t s)> cheb;
+  std::function<void(hipStream_t s)> spmv;
+  std::function<void(hipStream_t s)> cheb0;
+  std::function<void(int k, hipStream_t s)> cheb;
 };
 
 // z0 = B r0 for one symmetric V-cycle per instance (r0: the batch residual)
@@ -71,6 +85,8 @@ void mg_rz(const DevMesh* dm, int ni, int ncol, const double* r, const double* z
 // pcur = z + beta pprev per instance and column, beta = red[rz_cur] / red[rz_prev]
 // (rz_prev < 0: beta = 0); clears red[rr_clear]
 void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const double* z, const double* pprev, double* pcur,
+            double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s);
+void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const float* z, const double* pprev, double* pcur,
             double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s);
 
 }  // namespace mh

@@ -362,22 +362,14 @@ enum { SP_PLAIN = 0, SP_CG = 1, SP_CHEB0 = 2, SP_CHEB = 3, SP_CHEB_RZ = 4 };
 // Value of the operand at row j, columns c0 .. c0+V: x itself; (SP_CG) the CG
 // direction p_j = D^-1_j r_j + beta p_prev,j formed on the fly (x = r then);
 // (SP_CHEB0) beta D^-1_j x_j (x = r, beta = s0).
-template <int V, int MODE>
-__device__ __forceinline__ void operand_row(const __attribute__((address_space(1))) double* xg,
-                                            const __attribute__((address_space(1))) double* pg,
+// T: storage type of the operand arrays (double; float for the finest-level
+// multigrid arrays of Poisson schedule bit 6).  Arithmetic is in double.
+template <int V, int MODE, class T>
+__device__ __forceinline__ void operand_row(const __attribute__((address_space(1))) T* xg,
+                                            const __attribute__((address_space(1))) T* pg,
                                             const __attribute__((address_space(1))) double* dinv, const double* beta,
                                             int64_t j, int ld, int c0, double* out) {
-  const auto* row = xg + j * ld + c0;
-  if constexpr (V == 1) {
-    out[0] = row[0];
-  } else {
-#pragma unroll
-    for (int v = 0; v < V / 2; ++v) {
-      const double2 r2 = ldg2((const double*)row, v);  // 16-byte aligned (ncol, c0 even)
-      out[2 * v] = r2.x;
-      out[2 * v + 1] = r2.y;
-    }
-  }
+  load_vals<V>(xg + j * ld + c0, out);  // 16-byte loads (ncol and c0 multiples of V)
   if constexpr (MODE == SP_CHEB0) {
     const double dj = dinv[j];
 #pragma unroll
@@ -386,17 +378,7 @@ __device__ __forceinline__ void operand_row(const __attribute__((address_space(1
   if constexpr (MODE == SP_CG) {
     const double dj = dinv[j];
     double pv[V];
-    const auto* prow = pg + j * ld + c0;
-    if constexpr (V == 1) {
-      pv[0] = prow[0];
-    } else {
-#pragma unroll
-      for (int v = 0; v < V / 2; ++v) {
-        const double2 r2 = ldg2((const double*)prow, v);
-        pv[2 * v] = r2.x;
-        pv[2 * v + 1] = r2.y;
-      }
-    }
+    load_vals<V>(pg + j * ld + c0, pv);
 #pragma unroll
     for (int v = 0; v < V; ++v) out[v] = dj * out[v] + (beta[v] != 0.0 ? beta[v] * pv[v] : 0.0);
   }
@@ -406,9 +388,9 @@ __device__ __forceinline__ void operand_row(const __attribute__((address_space(1
 // four entries per round with all their loads issued together.  Past the end
 // the index is clamped to the row's last entry (every row holds its diagonal)
 // and the coefficient zeroed, so the loads need no branch.
-template <int V, int MODE>
-__device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __restrict__ x,
-                                              const double* __restrict__ pprev, const double* beta, int ld, int c0,
+template <int V, int MODE, class T>
+__device__ __forceinline__ void spmv_row_part(const DevMesh& d, const T* __restrict__ x,
+                                              const T* __restrict__ pprev, const double* beta, int ld, int c0,
                                               int beg, int end, int stride, double* y) {
   const auto* kcol = gbl(d.kt_col);
   const auto* kval = gbl(d.kt_val);
@@ -425,7 +407,7 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __
       const int64_t j = kcol[tc];
       const double a = kval[tc];
       av[u] = tt < end ? a : 0.0;
-      operand_row<V, MODE>(xg, pg, dinv, beta, j, ld, c0, xv[u]);
+      operand_row<V, MODE, T>(xg, pg, dinv, beta, j, ld, c0, xv[u]);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -442,46 +424,46 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const double* __
 //   SP_CHEB0: d0 = s0 D^-1 r, d = c1 d0 + c2 D^-1 (r - y), z = d0 + d;
 //   SP_CHEB:  d = c1 d + c D^-1 (r - y) (k = 0: c1 d dropped, c = s0; else
 //             c = c2), z = x + d; SP_CHEB_RZ also the r.z partial (in pq).
-template <int V, int MODE>
-__device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict__ q, double* __restrict__ pout,
-                                           const double* __restrict__ x, const double* __restrict__ pprev,
+template <int V, int MODE, class T>
+__device__ __forceinline__ void spmv_store(const DevMesh& d, T* __restrict__ q, T* __restrict__ pout,
+                                           const T* __restrict__ x, const T* __restrict__ pprev,
                                            const double* beta, int64_t i, int ld, int c0, const double* y,
                                            double* pq, const double* cf, int k) {
   if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_CHEB_RZ) {
     const int step = MODE == SP_CHEB_RZ ? 1 : k;
     const double di = gbl(d.kdiag_inv)[i];
     double rv[V], xv[V], dv[V];
-    operand_row<V, SP_PLAIN>(gbl(pprev), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, rv);
+    operand_row<V, SP_PLAIN, T>(gbl(pprev), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, rv);
     if constexpr (MODE != SP_CHEB0) {
-      operand_row<V, SP_PLAIN>(gbl(x), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, xv);
-      if (step > 0) operand_row<V, SP_PLAIN>(gbl((const double*)q), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, dv);
+      operand_row<V, SP_PLAIN, T>(gbl(x), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, xv);
+      if (step > 0) operand_row<V, SP_PLAIN, T>(gbl((const T*)q), gbl(x), gbl(d.kdiag_inv), beta, i, ld, c0, dv);
     }
-    double* qo = q + i * ld + c0;
-    double* po = pout + i * ld + c0;
+    T* qo = q + i * ld + c0;
+    T* po = pout + i * ld + c0;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       if constexpr (MODE == SP_CHEB0) {
         const double d0 = cf[0] * di * rv[v];
         const double dn = cf[1] * d0 + cf[2] * di * (rv[v] - y[v]);
-        qo[v] = dn;
-        po[v] = d0 + dn;
+        qo[v] = (T)dn;
+        po[v] = (T)(d0 + dn);
       } else {
         const double dn = (step > 0 ? cf[1] * dv[v] + cf[2] * di * (rv[v] - y[v]) : cf[0] * di * (rv[v] - y[v]));
         const double zn = xv[v] + dn;
-        qo[v] = dn;
-        po[v] = zn;
+        qo[v] = (T)dn;
+        po[v] = (T)zn;
         if constexpr (MODE == SP_CHEB_RZ) pq[v] += rv[v] * zn;
       }
     }
   } else {
     double pi[V];
-    operand_row<V, MODE>(gbl(x), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, pi);
-    double* qo = q + i * ld + c0;
-    double* po = pout + i * ld + c0;
+    operand_row<V, MODE, T>(gbl(x), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, pi);
+    T* qo = q + i * ld + c0;
+    T* po = pout + i * ld + c0;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      qo[v] = y[v];
-      if constexpr (MODE == SP_CG) po[v] = pi[v];
+      qo[v] = (T)y[v];
+      if constexpr (MODE == SP_CG) po[v] = (T)pi[v];
       pq[v] += y[v] * pi[v];
     }
   }
@@ -495,10 +477,10 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, double* __restrict_
 // iteration (SP_CG; see launch_spmv_poisson for SP_PLAIN), the
 // smoothing step (SP_CHEB) or the r.z slot (SP_CHEB0 clears it, SP_CHEB_RZ
 // accumulates into it).
-template <int L, int V, int MODE, bool SELL>
-__global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const double* __restrict__ x,
-                                                     const double* __restrict__ pprev, double* __restrict__ pout,
-                                                     int ld, int nc, double* __restrict__ q, int nlb,
+template <int L, int V, int MODE, bool SELL, class T>
+__global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const T* __restrict__ x,
+                                                     const T* __restrict__ pprev, T* __restrict__ pout,
+                                                     int ld, int nc, T* __restrict__ q, int nlb,
                                                      double* __restrict__ red, int k) {
   constexpr bool FUSE = MODE == SP_CG;
   INSTANCE;
@@ -537,12 +519,12 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       double y[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) y[v] = 0.0;
-      if (col_ok) spmv_row_part<V, MODE>(d, x, pprev, beta, ld, c0, beg + seg, end, SEG, y);
+      if (col_ok) spmv_row_part<V, MODE, T>(d, x, pprev, beta, ld, c0, beg + seg, end, SEG, y);
 #pragma unroll
       for (int off = L; off < 64; off <<= 1)
 #pragma unroll
         for (int v = 0; v < V; ++v) y[v] += __shfl_xor(y[v], off, 64);
-      if (seg == 0 && col_ok) spmv_store<V, MODE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
+      if (seg == 0 && col_ok) spmv_store<V, MODE, T>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   } else if constexpr (SELL) {
     constexpr int R = 64 / L;  // slots per wave
@@ -572,14 +554,14 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
         for (int h = 0; h < 4; ++h) {
           const int e = base + (t + h) * SELL_H + slot;
           av[h] = sval[e];
-          operand_row<V, MODE>(xg, pg, dinv, beta, (int64_t)scol[e], ld, c0, xv[h]);
+          operand_row<V, MODE, T>(xg, pg, dinv, beta, (int64_t)scol[e], ld, c0, xv[h]);
         }
 #pragma unroll
         for (int h = 0; h < 4; ++h)
 #pragma unroll
           for (int v = 0; v < V; ++v) y[v] += av[h] * xv[h][v];
       }
-      spmv_store<V, MODE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
+      spmv_store<V, MODE, T>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   } else {
     const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
@@ -590,8 +572,8 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       double y[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) y[v] = 0.0;
-      spmv_row_part<V, MODE>(d, x, pprev, beta, ld, c0, beg, end, 1, y);
-      spmv_store<V, MODE>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
+      spmv_row_part<V, MODE, T>(d, x, pprev, beta, ld, c0, beg, end, 1, y);
+      spmv_store<V, MODE, T>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   }
   if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB) {
@@ -634,29 +616,31 @@ static int long_row_blocks(const Batch& b) {
   return (int)((nb + N_XCD - 1) / N_XCD * N_XCD);
 }
 
-template <int L, int V, int MODE>
-static void launch_spmv_m(const Batch& b, const double* x, const double* pprev, double* pout, int ld, int nc,
-                          double* q, double* red, int k, hipStream_t s) {
+template <int L, int V, int MODE, class T>
+static void launch_spmv_m(const Batch& b, const T* x, const T* pprev, T* pout, int ld, int nc, T* q, double* red,
+                          int k, hipStream_t s) {
   const int nlb = long_row_blocks(b);
   if (b.mx.sched_poi & 32) {
     const dim3 g(nlb + xcd_grid(b.mx.n_slices * L, NT / 64, b.mx.grid_poi), b.ni, ld / nc);
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, true>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
-                       red, k);
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, true, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
+                       nlb, red, k);
   } else {
     const dim3 g(nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi), b.ni, ld / nc);
-    hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, false>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q, nlb,
-                       red, k);
+    hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, false, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
+                       nlb, red, k);
   }
 }
-template <int L, int V>
-static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, double* pout, int ld, int nc,
-                          double* q, double* red, int mode, int k, hipStream_t s) {
+template <int L, int V, class T>
+static void launch_spmv_t(const Batch& b, const T* x, const T* pprev, T* pout, int ld, int nc, T* q, double* red,
+                          int mode, int k, hipStream_t s) {
   switch (mode) {
-    case SP_PLAIN: return launch_spmv_m<L, V, SP_PLAIN>(b, x, pprev, pout, ld, nc, q, red, k, s);
-    case SP_CG: return launch_spmv_m<L, V, SP_CG>(b, x, pprev, pout, ld, nc, q, red, k, s);
-    case SP_CHEB0: return launch_spmv_m<L, V, SP_CHEB0>(b, x, pprev, pout, ld, nc, q, red, k, s);
-    case SP_CHEB: return launch_spmv_m<L, V, SP_CHEB>(b, x, pprev, pout, ld, nc, q, red, k, s);
-    default: return launch_spmv_m<L, V, SP_CHEB_RZ>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    case SP_PLAIN: return launch_spmv_m<L, V, SP_PLAIN, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    case SP_CG:  // the CG direction: double arrays only
+      if constexpr (sizeof(T) == sizeof(double)) return launch_spmv_m<L, V, SP_CG, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
+      return;
+    case SP_CHEB0: return launch_spmv_m<L, V, SP_CHEB0, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    case SP_CHEB: return launch_spmv_m<L, V, SP_CHEB, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    default: return launch_spmv_m<L, V, SP_CHEB_RZ, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
   }
 }
 
@@ -666,35 +650,37 @@ static void launch_spmv_t(const Batch& b, const double* x, const double* pprev, 
 // Schedule bit 1 (column blocking): with 32 or more columns in multiples of 16,
 // grid.z runs over blocks of 16 columns, so a row slice is 128 B and the band of
 // neighbour rows a sweep touches stays in L2 (the matrix is read once per block).
-static void launch_spmv_mode(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
-                             double* q, double* red, int mode, int k, hipStream_t s);
+template <class T>
+static void launch_spmv_mode(const Batch& b, const T* x, const T* pprev, T* pout, int ncol, T* q, double* red,
+                             int mode, int k, hipStream_t s);
 static void launch_spmv_poisson(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
                                 double* q, const PoissonWs& P, int k, hipStream_t s) {
   launch_spmv_mode(b, x, pprev, pout, ncol, q, P.red, k >= 0 ? SP_CG : SP_PLAIN, k, s);
 }
-static void launch_spmv_mode(const Batch& b, const double* x, const double* pprev, double* pout, int ncol,
-                             double* q, double* red, int mode, int k, hipStream_t s) {
+template <class T>
+static void launch_spmv_mode(const Batch& b, const T* x, const T* pprev, T* pout, int ncol, T* q, double* red,
+                             int mode, int k, hipStream_t s) {
   if ((b.mx.sched_poi & 2) && ncol >= 32 && ncol % 16 == 0)
-    return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, 16, q, red, mode, k, s);
-  if (ncol % 4 == 0 && ncol > 4) {  // 4 columns per lane (two 16-byte loads)
-    if (ncol <= 16) return launch_spmv_t<4, 4>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-    if (ncol <= 32) return launch_spmv_t<8, 4>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-    return launch_spmv_t<16, 4>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    return launch_spmv_t<4, 4, T>(b, x, pprev, pout, ncol, 16, q, red, mode, k, s);
+  if (ncol % 4 == 0 && ncol > 4) {  // 4 columns per lane (two 16-byte loads; one for float)
+    if (ncol <= 16) return launch_spmv_t<4, 4, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 32) return launch_spmv_t<8, 4, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    return launch_spmv_t<16, 4, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
   }
-  if (ncol % 2 == 0) {  // 16-byte column pairs
-    if (ncol <= 4) return launch_spmv_t<2, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-    if (ncol <= 8) return launch_spmv_t<4, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-    if (ncol <= 16) return launch_spmv_t<8, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-    if (ncol <= 32) return launch_spmv_t<16, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-    return launch_spmv_t<32, 2>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol % 2 == 0) {  // column pairs
+    if (ncol <= 4) return launch_spmv_t<2, 2, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 8) return launch_spmv_t<4, 2, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 16) return launch_spmv_t<8, 2, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    if (ncol <= 32) return launch_spmv_t<16, 2, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+    return launch_spmv_t<32, 2, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
   }
-  if (ncol <= 1) return launch_spmv_t<1, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-  if (ncol <= 2) return launch_spmv_t<2, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-  if (ncol <= 4) return launch_spmv_t<4, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-  if (ncol <= 8) return launch_spmv_t<8, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-  if (ncol <= 16) return launch_spmv_t<16, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-  if (ncol <= 32) return launch_spmv_t<32, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
-  return launch_spmv_t<64, 1>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 1) return launch_spmv_t<1, 1, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 2) return launch_spmv_t<2, 1, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 4) return launch_spmv_t<4, 1, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 8) return launch_spmv_t<8, 1, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 16) return launch_spmv_t<16, 1, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  if (ncol <= 32) return launch_spmv_t<32, 1, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
+  return launch_spmv_t<64, 1, T>(b, x, pprev, pout, ncol, ncol, q, red, mode, k, s);
 }
 
 // --------------------------------------------------------------------------
@@ -714,10 +700,11 @@ static void launch_spmv_mode(const Batch& b, const double* x, const double* ppre
 __global__ void __launch_bounds__(NT) k_cg_update2(const DevMesh* __restrict__ dm, double* __restrict__ x,
                                                    double* __restrict__ r, const double* __restrict__ p,
                                                    const double* __restrict__ q, int ncol, double* __restrict__ red,
-                                                   int k) {
+                                                   int k, float* __restrict__ rf) {
   INSTANCE;
   __shared__ double lds[2 * NT];
   x += d.oF * ncol;
+  if (rf) rf += d.oE * ncol;
   r += d.oE * ncol;
   p += d.oE * ncol;
   q += d.oE * ncol;
@@ -735,6 +722,7 @@ __global__ void __launch_bounds__(NT) k_cg_update2(const DevMesh* __restrict__ d
       x[e] += al * p[e];
       const double rn = r[e] - al * q[e];
       r[e] = rn;
+      if (rf) rf[e] = (float)rn;  // the finest multigrid level's float copy (Poisson schedule bit 6)
       rz += rn * rn * dinv[kk];
       rr += rn * rn;
     }
@@ -895,7 +883,8 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s) {
     cg_apply2(b, P, pcur, pprev, pcur, P.q, -2 - k, s);  // plain operator pass of iteration k
   }
   const int nb = cg_blocks(b, ncol);
-  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, pcur, P.q, ncol, P.red, k);
+  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, pcur, P.q, ncol, P.red, k,
+                     (float*)nullptr);
   P.it = k + 1;
 }
 
@@ -927,14 +916,38 @@ void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, dou
   else launch_spmv_mode(b, zin, r, zout, ncol, d, red, SP_CHEB, k, s);
 }
 
+// The same finest-level passes on float storage (Poisson schedule bit 6):
+// operand, residual copy, corrections and directions in float, sums in
+// double.  The operator product of the residual pass is not event-timed
+// (the timing slot holds the double passes of the CG itself).
+void launch_poisson_apply_f(const Batch& b, const float* x, float* q, int ncol, double* red_scratch, hipStream_t s) {
+  launch_spmv_mode<float>(b, x, x, q, ncol, q, red_scratch, SP_PLAIN, -1, s);
+}
+void launch_mg_cheb0_f(const Batch& b, const float* r, float* z, float* d, double* red, int rz_slot, int ncol,
+                       hipStream_t s) {
+  launch_spmv_mode<float>(b, r, r, z, ncol, d, red, SP_CHEB0, rz_slot, s);
+}
+void launch_mg_cheb_step_f(const Batch& b, const float* zin, const float* r, float* zout, float* d, double* red,
+                           int ncol, int k, int rz_slot, hipStream_t s) {
+  if (rz_slot >= 0) launch_spmv_mode<float>(b, zin, r, zout, ncol, d, red, SP_CHEB_RZ, rz_slot, s);
+  else launch_spmv_mode<float>(b, zin, r, zout, ncol, d, red, SP_CHEB, k, s);
+}
+
 // The plain operator pass of CG iteration k on the direction p (q = K p, p.q
 // accumulated for the update pass), and the update pass itself.
 void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k, hipStream_t s) {
   cg_apply2(b, P, p, p, const_cast<double*>(p), P.q, -2 - k, s);
 }
-void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s) {
+void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s, float* rf) {
   const int nb = cg_blocks(b, P.ncol);
-  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, p, P.q, P.ncol, P.red, k);
+  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, p, P.q, P.ncol, P.red, k, rf);
+}
+
+__global__ void __launch_bounds__(NT) k_to_float(const double* __restrict__ x, float* __restrict__ y, int64_t nd) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nd; i += (int64_t)gridDim.x * NT) y[i] = (float)x[i];
+}
+void launch_to_float(const double* x, float* y, int64_t nd, hipStream_t s) {
+  if (nd > 0) hipLaunchKernelGGL(k_to_float, dim3(nblocks(nd, NT, 8192)), dim3(NT), 0, s, x, y, nd);
 }
 
 // y = a x + b y over nd doubles (a, b real)

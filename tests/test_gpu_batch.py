@@ -65,7 +65,8 @@ def test_layout_is_concatenation():
     assert len(set(lay[:, 0])) == len(SEEDS)  # uneven sizes
 
 
-@pytest.mark.parametrize("imag,steps,orb,poi", [(False, 3, 1, 13), (True, 2, 1, 13), (False, 3, 4, 53)])
+@pytest.mark.parametrize("imag,steps,orb,poi", [(False, 3, 1, 13), (True, 2, 1, 13), (False, 3, 4, 53),
+                                                 (False, 3, 4, 117)])
 def test_batch_propagate_matches_oracle(imag, steps, orb, poi):
     """Each instance of the batch against the oracle on its own mesh, with the
     default schedules and with those the batch bench tunes to (assembled
@@ -311,3 +312,42 @@ def test_batch_workload_instances_equal_plain_runs():
                   f"dipole {dd:.2e} (max |d| {np.abs(rp['dipole']).max():.2e}) energy {de:.2e} "
                   f"orbitals {dx:.2e} CI {dc:.2e}", flush=True)
             assert max(dd, de, dx, dc) <= 1e-11, (i, orb, poi, dd, de, dx, dc)
+
+
+@pytest.mark.parametrize("orb,poi", [(4, 53), (4, 117)])
+def test_whole_step_graph_matches_eager(orb, poi):
+    """Whole steps replayed from one HIP graph (MH_PROP_GRAPH_STEP: RDMs, CG
+    start, pair Poisson solves with a fixed multigrid-CG count, boundary
+    values, the step's field value from the device table, freeze, integrals,
+    Arnoldi and CI steps) against the eager steps: from the fourth step on
+    every step is one replay, with the host reading records between the
+    replays.  Each replayed step's records and the final state equal the
+    eager run's up to the CG target (the fixed count runs past it)."""
+    torch = _torch()
+    pairs, op = batch_case()
+    w = pairs[0].w
+    n = w["n_orb"]
+    from oracle.ci import CISpace
+    cs, Cs = initial_state(pairs, CISpace(n, w["n_alpha"], w["n_beta"]).dim)
+    shape = [0.05 * np.sin(0.3 * k) for k in range(8)]
+    out = {}
+    try:
+        op.tune(0, orb, 65536)
+        op.tune(1, poi, 1024)
+        for mode in ("eager", "graph_step"):
+            x, Cd = to_device(pairs, cs, Cs)
+            W = torch.zeros((op.n_full, n * n), dtype=torch.float64, device="cuda")
+            rec = op.propagate(x, Cd, W, shape, 0.02, m=12, graph_step=(mode == "graph_step"))
+            torch.cuda.synchronize()
+            assert rec["status"] == 0, mode
+            out[mode] = (rec, x.cpu().numpy(), Cd.cpu().numpy())
+    finally:
+        op.tune(0, 1, 65536)
+        op.tune(1, 13, 8192)
+    (r0, x0, c0), (r1, x1, c1) = out["eager"], out["graph_step"]
+    print("cg iterations eager", r0["cg_iters"], "graph", r1["cg_iters"], flush=True)
+    assert np.all(r1["cg_iters"][3:7] >= r0["cg_iters"][3:7])
+    for k in ("dipole", "energy", "momentum"):
+        assert np.max(np.abs(r0[k] - r1[k])) <= 1e-10 * max(np.abs(r0[k]).max(), 1e-3), k
+    assert np.max(np.abs(x0 - x1)) <= 1e-10 * np.abs(x0).max()
+    assert np.max(np.abs(c0 - c1)) <= 1e-10

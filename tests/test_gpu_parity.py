@@ -131,8 +131,8 @@ def test_poisson_every_schedule(name):
     ref = poisson_solver(P.ops).pair_potentials(c)
     torch = _torch()
     x = dev(P.to_lib_orb(c))
-    for sched in (63, 61, 53, 45, 44, 39, 37, 36, 33, 32, 31, 29, 22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2,
-                  1, 0):
+    for sched in (127, 117, 116, 85, 84, 63, 61, 53, 45, 44, 39, 37, 36, 33, 32, 31, 29, 22, 21, 20, 16, 15, 14, 13,
+                  12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
         for grid in (8, 2048):
             P.op.tune(1, sched, grid)
             W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
@@ -240,7 +240,8 @@ def test_arnoldi_step(name, tau, m):
                                                    ("tiny_q3", 4, False, 21), ("small_n3", 3, False, 20),
                                                    ("tiny_q3", 4, False, 53), ("small_n3", 3, False, 52),
                                                    ("uniform_q2", 3, False, 13), ("uniform_q1_odd", 3, False, 53),
-                                                   ("beta_one", 3, False, 13), ("full_alpha", 3, False, 13)])
+                                                   ("beta_one", 3, False, 13), ("full_alpha", 3, False, 13),
+                                                   ("tiny_q3", 4, False, 117), ("small_n3", 3, False, 116)])
 def test_propagate_observables(name, steps, imag, sched):
     """Propagated dipoles, energies, orbitals and CI vectors against the
     oracle, with the default schedules (Poisson 13) and with the multigrid
@@ -296,7 +297,7 @@ def test_multigrid_poisson(name):
     ref = poisson_solver(P.ops).pair_potentials(c)
     x = dev(P.to_lib_orb(c))
     its = {}
-    for sched in (13, 21):
+    for sched in (13, 21, 85):       # Jacobi, multigrid, multigrid on float finest-level arrays (bit 6)
         P.op.tune(1, sched, 8192)
         W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
         it, rc = P.op.poisson_pairs(x, W)
@@ -307,8 +308,9 @@ def test_multigrid_poisson(name):
             num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref[k]) ** 2))
             den = np.sqrt(np.sum(P.ops.m * np.abs(ref[k]) ** 2))
             assert num / den < 1e-9, (sched, k, num / den)
-    print(name, "CG iterations jacobi / multigrid", its, flush=True)
+    print(name, "CG iterations jacobi / multigrid / multigrid float", its, flush=True)
     assert its[21] <= 60 and its[21] * 4 < its[13], its
+    assert its[85] <= its[21] + 2, its
 
 
 @pytest.mark.parametrize("name", UNIFORM)
