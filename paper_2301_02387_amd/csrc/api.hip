@@ -977,6 +977,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
   MgLevel0Ops ops;
   if (f32) {
     ops.spmv = [&](hipStream_t st) { launch_poisson_apply_f(B, mg.z0f, mg.t0f, ncol, op->mg_red, st); };
+    ops.resid = [&](hipStream_t st) { launch_mg_resid_f(B, mg.z0f, mg.rf, mg.t0f, ncol, op->mg_red, st); };
     ops.cheb0 = [&](hipStream_t st) { launch_mg_cheb0_f(B, mg.rf, mg.z0f, mg.d0f, P.red, rz_slot, ncol, st); };
     ops.cheb = [&](int k, hipStream_t st) {
       launch_mg_cheb_step_f(B, k == 0 ? mg.z0f : mg.z0bf, mg.rf, k == 0 ? mg.z0bf : mg.z0f, mg.d0f, P.red, ncol, k,
@@ -984,6 +985,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     };
   } else {
     ops.spmv = [&](hipStream_t st) { launch_poisson_apply(B, mg.z0, mg.t0, ncol, op->mg_red, P, st); };
+    ops.resid = [&](hipStream_t st) { launch_mg_resid(B, mg.z0, P.r, mg.t0, ncol, op->mg_red, st); };
     ops.cheb0 = [&](hipStream_t st) { launch_mg_cheb0(B, P.r, mg.z0, mg.d0, P.red, rz_slot, ncol, st); };
     ops.cheb = [&](int k, hipStream_t st) {
       launch_mg_cheb_step(B, k == 0 ? mg.z0 : mg.z0b, P.r, k == 0 ? mg.z0b : mg.z0, mg.d0, P.red, ncol, k,

@@ -226,12 +226,18 @@ void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, doub
                      hipStream_t s);
 void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* red,
                          int ncol, int k, int rz_slot, hipStream_t s);
+//  - the residual t = r - K z that the restriction to the next level reads
+//    (red_scratch: accumulators the pass may touch, not the CG's).
+void launch_mg_resid(const Batch& b, const double* z, const double* r, double* t, int ncol, double* red_scratch,
+                     hipStream_t s);
 // Poisson schedule bit 6: the finest multigrid level's passes on float arrays
 void launch_poisson_apply_f(const Batch& b, const float* x, float* q, int ncol, double* red_scratch, hipStream_t s);
 void launch_mg_cheb0_f(const Batch& b, const float* r, float* z, float* d, double* red, int rz_slot, int ncol,
                        hipStream_t s);
 void launch_mg_cheb_step_f(const Batch& b, const float* zin, const float* r, float* zout, float* d, double* red,
                            int ncol, int k, int rz_slot, hipStream_t s);
+void launch_mg_resid_f(const Batch& b, const float* z, const float* r, float* t, int ncol, double* red_scratch,
+                       hipStream_t s);
 // Hanging rows of a real column array (xfull: x is over full rows, else extended).
 void launch_fill_real(const Batch& b, double* x, int xfull, int ncol, int with_bnd, double* acc, hipStream_t s);
 

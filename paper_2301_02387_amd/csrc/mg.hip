@@ -62,6 +62,55 @@ __device__ __forceinline__ double row_gather_dot(IP col, DP val, int beg, int en
   return s;
 }
 
+// The same with V adjacent columns per lane (c0 .. c0 + V, 16-byte loads;
+// ncol and c0 multiples of V): s[v] += the entries' sum for column c0 + v.
+template <int V, bool SUB, class IP, class DP, class XP>
+__device__ __forceinline__ void row_gather_v(IP col, DP val, int beg, int end, int stride, XP x, XP xm, int ncol,
+                                             int c0, double* s) {
+  int jn[8];
+  double an[8];
+#pragma unroll
+  for (int h = 0; h < 8; ++h) {
+    const int tt = beg + h * stride;
+    const int tc = tt < end ? tt : end - 1;
+    jn[h] = col[tc];
+    an[h] = tt < end ? val[tc] : 0.0;
+  }
+  for (int t = beg; t < end; t += 8 * stride) {
+    int jc[8];
+    double ac[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      jc[h] = jn[h];
+      ac[h] = an[h];
+    }
+    if (t + 8 * stride < end) {
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int tt = t + (8 + h) * stride;
+        const int tc = tt < end ? tt : end - 1;
+        jn[h] = col[tc];
+        an[h] = tt < end ? val[tc] : 0.0;
+      }
+    }
+    double xv[8][V];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      load_vals<V>(x + (int64_t)jc[h] * ncol + c0, xv[h]);
+      if constexpr (SUB) {
+        double mv[V];
+        load_vals<V>(xm + (int64_t)jc[h] * ncol + c0, mv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) xv[h][v] -= mv[v];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h)
+#pragma unroll
+      for (int v = 0; v < V; ++v) s[v] += ac[h] * xv[h][v];
+  }
+}
+
 // t = A z on each active record
 __global__ void __launch_bounds__(NT) k_mg_spmv(const MgLevelDev* __restrict__ lv, int ncol) {
   const MgLevelDev& L = lv[blockIdx.y];
@@ -81,12 +130,14 @@ __global__ void __launch_bounds__(NT) k_mg_spmv(const MgLevelDev* __restrict__ l
 }
 
 // coarse.r = R (fine.r - fine.t) for each instance whose fine record is
-// active.  A restriction row gathers every fine node in the support of a
-// coarse basis function (up to 343 entries from Q3 to Q1), so one wave takes
-// a row: groups of cw lanes (a power of two >= ncol) split its entries, lane c
-// of a group holds column c, and the groups are combined by shuffles.
+// active (tres: fine.t holds the residual r - A z already, R fine.t).  A
+// restriction row gathers every fine node in the support of a coarse basis
+// function (up to 343 entries from Q3 to Q1), so one wave takes a row: groups
+// of cw lanes (a power of two >= ncol) split its entries, lane c of a group
+// holds column c, and the groups are combined by shuffles.
 __global__ void __launch_bounds__(NT) k_mg_restrict(const MgLevelDev* __restrict__ fine,
-                                                    const MgLevelDev* __restrict__ coarse, int ncol, int cw) {
+                                                    const MgLevelDev* __restrict__ coarse, int ncol, int cw,
+                                                    int tres) {
   const MgLevelDev& F = fine[blockIdx.y];
   if (!F.active) return;
   const MgLevelDev& C = coarse[blockIdx.y];
@@ -106,12 +157,102 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(const MgLevelDev* __restrict
     double s = 0.0;
     if (c < ncol) {
       const int beg = ptr[w] + grp, end = ptr[w + 1];
-      if (end > beg)
-        s = f32 ? row_gather_dot<true>(col, val, beg, end, ngrp, rf, tf, ncol, c)
-                : row_gather_dot<true>(col, val, beg, end, ngrp, r, t, ncol, c);
+      if (end > beg) {
+        if (tres)
+          s = f32 ? row_gather_dot<false>(col, val, beg, end, ngrp, tf, tf, ncol, c)
+                  : row_gather_dot<false>(col, val, beg, end, ngrp, t, t, ncol, c);
+        else
+          s = f32 ? row_gather_dot<true>(col, val, beg, end, ngrp, rf, tf, ncol, c)
+                  : row_gather_dot<true>(col, val, beg, end, ngrp, r, t, ncol, c);
+      }
     }
     for (int off = 32; off >= cw; off >>= 1) s += __shfl_xor(s, off, 64);
     if (grp == 0 && c < ncol) y[w * ncol + c] = s;
+  }
+}
+
+// The restriction with V columns per lane (ncol a multiple of V, cw a power
+// of two >= ncol / V lanes per group): 64 / cw groups split a row's entries,
+// each with eight entries in flight, and the coarse rows are swept by XCD.
+// TRES as tres of k_mg_restrict.
+template <int V, bool TRES>
+__global__ void __launch_bounds__(NT) k_mg_restrict_v(const MgLevelDev* __restrict__ fine,
+                                                      const MgLevelDev* __restrict__ coarse, int ncol, int cw) {
+  const MgLevelDev& F = fine[blockIdx.y];
+  if (!F.active) return;
+  const MgLevelDev& C = coarse[blockIdx.y];
+  const auto* ptr = gbl(F.r_ptr);
+  const auto* col = gbl(F.r_col);
+  const auto* val = gbl(F.r_val);
+  const auto* r = gbl((const double*)F.r);
+  const auto* t = gbl((const double*)F.t);
+  const auto* rf = gbl(F.rf);
+  const auto* tf = gbl((const float*)F.tf);
+  const bool f32 = F.f32 != 0;
+  auto* y = gblw(C.r);
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / cw, c0 = (lane - grp * cw) * V, ngrp = 64 / cw;
+  const bool act = c0 < ncol;
+  const XcdSweep sw = xcd_sweep(C.N, NT / 64);
+  for (int64_t w = sw.start + (threadIdx.x >> 6); w < sw.end; w += sw.step) {
+    double s[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) s[v] = 0.0;
+    const int beg = ptr[w] + grp, end = ptr[w + 1];
+    if (act && end > beg) {
+      if constexpr (TRES) {
+        if (f32) row_gather_v<V, false>(col, val, beg, end, ngrp, tf, tf, ncol, c0, s);
+        else row_gather_v<V, false>(col, val, beg, end, ngrp, t, t, ncol, c0, s);
+      } else {
+        if (f32) row_gather_v<V, true>(col, val, beg, end, ngrp, rf, tf, ncol, c0, s);
+        else row_gather_v<V, true>(col, val, beg, end, ngrp, r, t, ncol, c0, s);
+      }
+    }
+    for (int off = 32; off >= cw; off >>= 1)
+#pragma unroll
+      for (int v = 0; v < V; ++v) s[v] += __shfl_xor(s[v], off, 64);
+    if (grp == 0 && act)
+#pragma unroll
+      for (int v = 0; v < V; ++v) y[w * ncol + c0 + v] = s[v];
+  }
+}
+
+// fine.z += P coarse.z with V columns per lane and L lanes per row (a power
+// of two >= ncol / V), so a wave takes 64 / L rows at once; rows swept by XCD.
+template <int V, int L>
+__global__ void __launch_bounds__(NT) k_mg_prolong_v(const MgLevelDev* __restrict__ fine,
+                                                     const MgLevelDev* __restrict__ coarse, int ncol) {
+  const MgLevelDev& F = fine[blockIdx.y];
+  if (!F.active) return;
+  const MgLevelDev& C = coarse[blockIdx.y];
+  const auto* ptr = gbl(F.p_ptr);
+  const auto* col = gbl(F.p_col);
+  const auto* val = gbl(F.p_val);
+  const auto* x = gbl((const double*)C.z);
+  auto* z = gblw(F.z);
+  auto* zf = gblw(F.zf);
+  const bool f32 = F.f32 != 0;
+  const int c0 = (int)(threadIdx.x & (L - 1)) * V;
+  const bool act = c0 < ncol;
+  const XcdSweep sw = xcd_sweep(F.N, NT / L);
+  for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
+    const int beg = ptr[i], end = ptr[i + 1];
+    if (!act || end <= beg) continue;
+    double s[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) s[v] = 0.0;
+    row_gather_v<V, false>(col, val, beg, end, 1, x, x, ncol, c0, s);
+    const int64_t e = i * ncol + c0;
+    double zo[V];
+    if (f32) {
+      load_vals<V>(zf + e, zo);
+#pragma unroll
+      for (int v = 0; v < V; ++v) zf[e + v] = (float)(zo[v] + s[v]);
+    } else {
+      load_vals<V>(z + e, zo);
+#pragma unroll
+      for (int v = 0; v < V; ++v) z[e + v] = zo[v] + s[v];
+    }
   }
 }
 
@@ -253,18 +394,41 @@ static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, con
 
 void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s) {
   const int nl = mg.nlev;
+  // 4 columns per lane in the transfers for 16 or more columns (multiples of 4)
+  const bool wide = ncol >= 16 && ncol % 4 == 0;
   for (int l = 0; l + 1 < nl; ++l) {
     smooth(mg, l, ni, ncol, true, ops, s);
-    level_spmv(mg, l, ni, ncol, ops, s);
-    int cw = 1;
-    while (cw < ncol) cw *= 2;
-    hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(mg.max_n[l + 1] * 64, NT, 16384), ni), dim3(NT), 0, s, mg.lv[l],
-                       mg.lv[l + 1], ncol, cw);
+    const int tres = l == 0 && ops.resid ? 1 : 0;
+    if (tres) ops.resid(s);
+    else level_spmv(mg, l, ni, ncol, ops, s);
+    if (wide) {
+      int cw = 1;
+      while (cw * 4 < ncol) cw *= 2;
+      const dim3 g(xcd_grid(mg.max_n[l + 1], NT / 64, 16384), ni);
+      if (tres) hipLaunchKernelGGL((k_mg_restrict_v<4, true>), g, dim3(NT), 0, s, mg.lv[l], mg.lv[l + 1], ncol, cw);
+      else hipLaunchKernelGGL((k_mg_restrict_v<4, false>), g, dim3(NT), 0, s, mg.lv[l], mg.lv[l + 1], ncol, cw);
+    } else {
+      int cw = 1;
+      while (cw < ncol) cw *= 2;
+      hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(mg.max_n[l + 1] * 64, NT, 16384), ni), dim3(NT), 0, s,
+                         mg.lv[l], mg.lv[l + 1], ncol, cw, tres);
+    }
   }
   hipLaunchKernelGGL(k_mg_coarse, dim3(nblocks(mg.max_coarse * ((ncol + 7) / 8) * 64, NT, 4096), ni), dim3(NT), 0, s,
                      mg.coarse, ncol);
   for (int l = nl - 2; l >= 0; --l) {
-    hipLaunchKernelGGL(k_mg_prolong, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], mg.lv[l + 1], ncol);
+    if (wide && ncol > 32)
+      hipLaunchKernelGGL((k_mg_prolong_v<4, 16>), dim3(xcd_grid(mg.max_n[l], NT / 16, 16384), ni), dim3(NT), 0, s,
+                         mg.lv[l], mg.lv[l + 1], ncol);
+    else if (wide && ncol > 16)
+      hipLaunchKernelGGL((k_mg_prolong_v<4, 8>), dim3(xcd_grid(mg.max_n[l], NT / 8, 16384), ni), dim3(NT), 0, s,
+                         mg.lv[l], mg.lv[l + 1], ncol);
+    else if (wide)
+      hipLaunchKernelGGL((k_mg_prolong_v<4, 4>), dim3(xcd_grid(mg.max_n[l], NT / 4, 16384), ni), dim3(NT), 0, s,
+                         mg.lv[l], mg.lv[l + 1], ncol);
+    else
+      hipLaunchKernelGGL(k_mg_prolong, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], mg.lv[l + 1],
+                         ncol);
     smooth(mg, l, ni, ncol, false, ops, s);
   }
 }

@@ -71,6 +71,7 @@ struct MgDev {
 // zero (z0, d0 from r0), and step k (k = 0: z0 -> z0b, k = 1: z0b -> z0).
 struct MgLevel0Ops {
   std::function<void(hipStream_t s)> spmv;
+  std::function<void(hipStream_t s)> resid;  // optional: t0 = r0 - A z0, the residual the restriction reads
   std::function<void(hipStream_t s)> cheb0;
   std::function<void(int k, hipStream_t s)> cheb;
 };

@@ -356,8 +356,9 @@ void launch_mass_direct(const Batch& b, const double* f, double* out, double* ma
 // SP_CHEB0 runs the first two steps from z = 0 (its operand s0 D^-1 r is
 // formed on the fly), SP_CHEB runs one step on a given z into another array.
 // SP_CHEB_RZ is the second SP_CHEB step with r.z accumulated for the
-// multigrid-preconditioned CG.
-enum { SP_PLAIN = 0, SP_CG = 1, SP_CHEB0 = 2, SP_CHEB = 3, SP_CHEB_RZ = 4 };
+// multigrid-preconditioned CG.  SP_RES writes the residual r - K z that the
+// restriction to the next multigrid level reads.
+enum { SP_PLAIN = 0, SP_CG = 1, SP_CHEB0 = 2, SP_CHEB = 3, SP_CHEB_RZ = 4, SP_RES = 5 };
 
 // Value of the operand at row j, columns c0 .. c0+V: x itself; (SP_CG) the CG
 // direction p_j = D^-1_j r_j + beta p_prev,j formed on the fly (x = r then);
@@ -424,12 +425,19 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const T* __restr
 //   SP_CHEB0: d0 = s0 D^-1 r, d = c1 d0 + c2 D^-1 (r - y), z = d0 + d;
 //   SP_CHEB:  d = c1 d + c D^-1 (r - y) (k = 0: c1 d dropped, c = s0; else
 //             c = c2), z = x + d; SP_CHEB_RZ also the r.z partial (in pq).
+// SP_RES (x = z, pprev = r): q_i = r_i - y.
 template <int V, int MODE, class T>
 __device__ __forceinline__ void spmv_store(const DevMesh& d, T* __restrict__ q, T* __restrict__ pout,
                                            const T* __restrict__ x, const T* __restrict__ pprev,
                                            const double* beta, int64_t i, int ld, int c0, const double* y,
                                            double* pq, const double* cf, int k) {
-  if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_CHEB_RZ) {
+  if constexpr (MODE == SP_RES) {
+    double rv[V];
+    operand_row<V, SP_PLAIN, T>(gbl(pprev), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, rv);
+    T* qo = q + i * ld + c0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) qo[v] = (T)(rv[v] - y[v]);
+  } else if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_CHEB_RZ) {
     const int step = MODE == SP_CHEB_RZ ? 1 : k;
     const double di = gbl(d.kdiag_inv)[i];
     double rv[V], xv[V], dv[V];
@@ -576,7 +584,7 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       spmv_store<V, MODE, T>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   }
-  if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB) {
+  if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_RES) {
     if (MODE == SP_CHEB0 && blockIdx.x == 0 && threadIdx.x < (unsigned)nc) red[k * ld + threadIdx.x] = 0.0;
     return;
   }
@@ -640,6 +648,7 @@ static void launch_spmv_t(const Batch& b, const T* x, const T* pprev, T* pout, i
       return;
     case SP_CHEB0: return launch_spmv_m<L, V, SP_CHEB0, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
     case SP_CHEB: return launch_spmv_m<L, V, SP_CHEB, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
+    case SP_RES: return launch_spmv_m<L, V, SP_RES, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
     default: return launch_spmv_m<L, V, SP_CHEB_RZ, T>(b, x, pprev, pout, ld, nc, q, red, k, s);
   }
 }
@@ -844,7 +853,13 @@ __global__ void __launch_bounds__(NT) k_copy_dofs(const DevMesh* __restrict__ dm
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) y[e] = x[e];
 }
 
-static int cg_blocks(const Batch& b, int ncol) { return nblocks(b.mx.N, NT / ncol, RED_BLOCKS); }
+// Workgroups of the CG start and update passes: about 32 elements per thread,
+// at least RED_BLOCKS (small meshes: few partial sums) and at most 2048 (eight
+// per compute unit), so the passes over large meshes keep enough loads in flight.
+static int cg_blocks(const Batch& b, int ncol) {
+  const int64_t want = std::min<int64_t>(std::max<int64_t>(b.mx.N * ncol / (NT * 32), RED_BLOCKS), 2048);
+  return nblocks(b.mx.N, NT / ncol, (int)want);
+}
 
 // the operator pass with optional event timing on the launch stream
 static void cg_apply2(const Batch& b, PoissonWs& P, const double* x, const double* pprev, double* pout, double* q,
@@ -906,6 +921,15 @@ void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, 
 // Chebyshev smoothing on the finest multigrid level fused into the operator
 // pass (the spmv_store comment gives the updates): the first two steps from
 // zero (z, d from r), and one further step from zin into zout.
+// t = r - K z on the finest level (the residual the restriction reads)
+void launch_mg_resid(const Batch& b, const double* z, const double* r, double* t, int ncol, double* red_scratch,
+                     hipStream_t s) {
+  launch_spmv_mode(b, z, r, t, ncol, t, red_scratch, SP_RES, -1, s);
+}
+void launch_mg_resid_f(const Batch& b, const float* z, const float* r, float* t, int ncol, double* red_scratch,
+                       hipStream_t s) {
+  launch_spmv_mode<float>(b, z, r, t, ncol, t, red_scratch, SP_RES, -1, s);
+}
 void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* red, int rz_slot, int ncol,
                      hipStream_t s) {
   launch_spmv_mode(b, r, r, z, ncol, d, red, SP_CHEB0, rz_slot, s);
