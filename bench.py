@@ -52,7 +52,7 @@ def initial_state(name, w, mesh, op, torch):
     if name == "h2":
         c = h2_guess(xyz, 0.7)
         C = h2_ci_guess()
-    elif name == "h2o":
+    elif name in ("h2o", "h2o_q1"):
         c = h2o_guess(xyz)
         C = 0.9 * np.eye(1, op.n_ci, 0, dtype=complex)[0] + 0.1 * random_ci(op.n_ci, 7)
         C = C / np.linalg.norm(C)
@@ -237,28 +237,33 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
     workload; returns the bench record."""
     import numpy as np
     import paper_2301_02387_amd as mh
-    from synth import pulse
+    from synth import pulse, pulse_triangular, OMEGA_800NM
 
     w = _workload(name)
     t_setup = time.perf_counter()
     mesh = mh.Mesh.from_workload(w)
-    op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_rtol=1e-12,
-                     poisson_maxit=20000)
+    op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"],
+                     polarization=w.get("polarization", (0.0, 0.0, 1.0)), poisson_rtol=1e-12, poisson_maxit=20000)
     t_setup = time.perf_counter() - t_setup
     log(f"{name}: set up in {t_setup:.1f} s, {op.n_dof} unknowns")
     info = mesh.info
     phi, Ci = initial_state(name, w, mesh, op, torch)
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     dt, m = w["dt"], w["krylov"]
-    Tp = (w["cycles"] * 2 * np.pi / 0.0569542) if w["cycles"] else 1.0
+    omega = w.get("omega", OMEGA_800NM)
+    Tp = (w["cycles"] * 2 * np.pi / omega) if w["cycles"] else 1.0
     if args.tune_cache:   # schedules tuned by an earlier run on this workload, before the warm-up
         from paper_2301_02387_amd.tune import apply_cached
         apply_cached(op, args.tune_cache)
     # warm-up: imaginary-time relaxation steps, then one real-time step
     if args.warmup > 0:
         op.propagate(phi, Ci, W, [0.0] * (args.warmup + 1), 0.05, m=m, imaginary=True, final=False)
-    t0 = Tp / 2
-    E = [float(pulse(t0 + k * dt, w["E0"], w["cycles"])) if w["cycles"] else 0.0 for k in range(args.steps + 1)]
+    t0 = Tp / 2   # the pulse peak
+    if w.get("envelope") == "triangular":
+        E = [float(pulse_triangular(t0 + k * dt, w["E0"], omega)) for k in range(args.steps + 1)]
+    else:
+        E = [float(pulse(t0 + k * dt, w["E0"], w["cycles"], omega)) if w["cycles"] else 0.0
+             for k in range(args.steps + 1)]
     op.propagate(phi, Ci, W, E[:2], dt, m=m, final=False)
     # schedules of the two operator kernels picked by the autotuner (untimed)
     from paper_2301_02387_amd.tune import autotune
@@ -328,6 +333,10 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": wl, "n_dof": op.n_dof, "n_full": info["n_full"], "n_cells": info["n_cells"],
+                   "mesh": ("Kelly indicator of the nuclear potential, cell sizes "
+                            + ", ".join(f"{(w['hi'] - w['lo']) / w['n_coarse'] / 2 ** l:g}"
+                                        for l, c in enumerate(info["level_counts"]) if c)) if w.get("kelly")
+                   else "ball refinement",
                    "n_orb": op.n_orb, "n_ci": op.n_ci, "krylov": m, "dt": dt, "graph": bool(args.graph),
                    "graph_step": bool(args.graph_step), "parallelism": "none (one GPU)"},
         "arnoldi_step_ms": arnoldi_ms,
@@ -370,7 +379,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="h2o", choices=["h2", "h2o", "h_atom", "h2x64"])
+    ap.add_argument("--workload", default="h2o", choices=["h2", "h2o", "h2o_q1", "h_atom", "h2x64"])
     ap.add_argument("--batch", type=int, default=64, help="instances of the h2x64 workload")
     ap.add_argument("--seq-steps", type=int, default=2, help="timed steps per instance of the sequential runs")
     ap.add_argument("--graph", action="store_true", help="replay each step's fixed part as a HIP graph")
@@ -382,6 +391,8 @@ def main():
                          "workload's mesh, then a 1 GiB elementwise multiply for calibration; prints no JSON")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint vs plain comparison")
     ap.add_argument("--no-h2", action="store_true", help="h2o: skip the H2 workload's extra record")
+    ap.add_argument("--no-q1", action="store_true",
+                    help="h2o: skip the extra record of the Q1 water workload on its Kelly-refined mesh")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of tuned schedules: read if it holds this workload, else written after tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -409,6 +420,12 @@ def main():
                                          "poisson_cg_iters_per_step", "roofline", "roofline_rhs")}
         if "fwd_adjoint_vs_plain" in h2:
             line["fwd_adjoint_vs_plain"] = h2["fwd_adjoint_vs_plain"]
+    if args.workload == "h2o" and not args.no_q1:
+        # the water molecule as Sec. IV runs it: Q1 on a Kelly-refined mesh,
+        # triangular 400 nm pulse along x, dt = 0.01
+        q1 = run_single("h2o_q1", args, torch, with_adjoint=False, with_cpu=False)
+        line["h2o_q1"] = {k: q1[k] for k in ("value", "ms_per_step", "config", "arnoldi_step_ms", "rhs_apply_ms",
+                                             "poisson_cg_iters_per_step", "roofline", "roofline_rhs")}
     bw = copy_bandwidth(torch)
     line["hbm_copy_measured_GBs"] = bw
     for key in ("roofline", "roofline_rhs", "roofline_orbital"):

@@ -82,19 +82,36 @@ typedef struct {
 
 /* Box [lo, hi]^3 covered by n_coarse^3 cubes, Lagrange degree p (1..3) on
  * Gauss-Lobatto points (Sec. III.A), refined by the balls, then 2:1 balanced
- * over all 26 neighbours. */
+ * over all 26 neighbours.
+ *
+ * Kelly refinement (Sec. III.A: cells halved until Kelly's indicator of the
+ * nuclear Coulomb potential meets a threshold in every cell), when
+ * n_kelly > 0, after the balls: u_K interpolates the softened potential
+ * V = -sum Z / sqrt(|r - R|^2 + kelly_soft^2) at the Gauss-Lobatto nodes of
+ * leaf K alone; eta_K^2 = (h_K / 24) * sum over K's interior faces of the
+ * integral of the squared jump of du/dn (h_K = sqrt(3) * edge; each part of
+ * a face shared with one neighbour integrated exactly by Gauss-Legendre).
+ * Every leaf with eta_K > kelly_tol below level kelly_max_level is halved,
+ * the tree re-balanced, and the indicators recomputed until none is marked.
+ * MH_INVALID_ARG for kelly_soft <= 0, kelly_tol <= 0 or a negative level. */
 typedef struct {
   double lo, hi;
   int32_t n_coarse;
   int32_t p;
   int32_t n_balls;
-  const mh_ball* balls;   /* host array, read during the call only */
+  const mh_ball* balls;          /* host array, read during the call only */
+  int32_t n_kelly;               /* nuclei of the Kelly target (0: no Kelly refinement) */
+  const double* kelly_nuclei;    /* host [n_kelly][4]: Z, x, y, z; read during the call only */
+  double kelly_tol;              /* threshold on eta_K */
+  double kelly_soft;             /* softening length (bohr) */
+  int32_t kelly_max_level;       /* deepest level a Kelly split may create */
 } mh_mesh_desc;
 
 typedef struct {
   int64_t n_cells, n_full, n_dof, n_hang, n_bnd, n_masters, hang_nnz;
   int32_t p, max_level;
   int64_t level_counts[16];
+  int32_t kelly_rounds;          /* Kelly refinement rounds taken (0 without Kelly) */
 } mh_mesh_info;
 
 /* Build the octree, nodes, hanging-node constraints (bridged basis of

@@ -9,6 +9,8 @@ Readings taken where the paper is silent:
   * refinement is geometric: a leaf of level l is split while it meets (its
     closest point lies strictly within radius r of) a ball whose level
     count exceeds l; then 2:1 balance is enforced over all 26 neighbours;
+    a mesh may then be refined further by Kelly's indicator of the nuclear
+    potential (``oracle/kelly.py`` states that criterion);
   * a full node is *hanging* iff the coarsest leaf whose closed box contains
     it does not have it as one of its own nodes; its value is that leaf's
     Lagrange interpolant at the node (the bridged function), with chains
@@ -46,6 +48,12 @@ class MeshDesc:
     n_coarse: int
     p: int
     balls: list = field(default_factory=list)
+    # Kelly refinement after the balls: nuclei [(Z, (x, y, z))], threshold,
+    # softening length of the potential, deepest level (no nuclei: none)
+    kelly_nuclei: list = field(default_factory=list)
+    kelly_tol: float = 0.0
+    kelly_soft: float = 0.0
+    kelly_max_level: int = 0
 
 
 def _cell_dist(lo, h, idx, c):
@@ -60,7 +68,8 @@ def _cell_dist(lo, h, idx, c):
 
 
 def build_leaves(desc):
-    """Ball refinement to a fixed point, then 26-neighbour 2:1 balance."""
+    """Ball refinement to a fixed point, then 26-neighbour 2:1 balance, then
+    (when nuclei are given) Kelly refinement with re-balancing."""
     nc = desc.n_coarse
     H = (desc.hi - desc.lo) / nc
     leaves = {(0, i, j, k) for i in range(nc) for j in range(nc) for k in range(nc)}
@@ -83,6 +92,24 @@ def build_leaves(desc):
             else:
                 nxt.add((l, i, j, k))
         leaves = nxt
+
+    leaves = balance_21(leaves, nc)
+    if desc.kelly_nuclei:
+        from .kelly import kelly_refine, softened_coulomb
+        f = softened_coulomb(desc.kelly_nuclei, desc.kelly_soft)
+        leaves, _ = kelly_refine(leaves, desc.lo, desc.hi, nc, desc.p, f, desc.kelly_tol, desc.kelly_max_level,
+                                 lambda L: balance_21(L, nc))
+    return sorted(leaves)
+
+
+def balance_21(leaves, nc):
+    """Split leaves until no two leaves sharing a face, edge or corner differ
+    by more than one level (all 26 neighbours)."""
+    leaves = set(leaves)
+
+    def children(l, i, j, k):
+        return [(l + 1, 2 * i + a, 2 * j + b, 2 * k + c)
+                for a in (0, 1) for b in (0, 1) for c in (0, 1)]
 
     def find_leaf(l, i, j, k):
         for L in range(l, -1, -1):

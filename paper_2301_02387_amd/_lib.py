@@ -28,13 +28,15 @@ class _Ball(C.Structure):
 
 class _MeshDesc(C.Structure):
     _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("n_coarse", C.c_int32), ("p", C.c_int32),
-                ("n_balls", C.c_int32), ("balls", C.POINTER(_Ball))]
+                ("n_balls", C.c_int32), ("balls", C.POINTER(_Ball)),
+                ("n_kelly", C.c_int32), ("kelly_nuclei", C.POINTER(C.c_double)), ("kelly_tol", C.c_double),
+                ("kelly_soft", C.c_double), ("kelly_max_level", C.c_int32)]
 
 
 class _MeshInfo(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_full", C.c_int64), ("n_dof", C.c_int64), ("n_hang", C.c_int64),
                 ("n_bnd", C.c_int64), ("n_masters", C.c_int64), ("hang_nnz", C.c_int64), ("p", C.c_int32),
-                ("max_level", C.c_int32), ("level_counts", C.c_int64 * 16)]
+                ("max_level", C.c_int32), ("level_counts", C.c_int64 * 16), ("kelly_rounds", C.c_int32)]
 
 
 class _OpDesc(C.Structure):
@@ -179,14 +181,22 @@ def _stream(stream):
 class Mesh:
     """Octree mesh (host); see mh_mesh_create."""
 
-    def __init__(self, lo, hi, n_coarse, p, balls):
+    def __init__(self, lo, hi, n_coarse, p, balls, kelly=None):
+        """kelly: optional dict(nuclei=[(Z, (x, y, z))], tol, soft, max_level)."""
         lib = load_library()
         arr = (_Ball * max(1, len(balls)))()
         for i, b in enumerate(balls):
             arr[i].center[:] = list(map(float, b["center"]))
             arr[i].radius = float(b["radius"])
             arr[i].levels = int(b["levels"])
-        desc = _MeshDesc(float(lo), float(hi), int(n_coarse), int(p), len(balls), arr)
+        kn = np.zeros((1, 4))
+        nk, ktol, ksoft, klev = 0, 0.0, 0.0, 0
+        if kelly:
+            kn = np.ascontiguousarray([[float(z), *map(float, r)] for z, r in kelly["nuclei"]], dtype=np.float64)
+            nk, ktol, ksoft, klev = len(kn), float(kelly["tol"]), float(kelly["soft"]), int(kelly["max_level"])
+        self._kn = kn
+        desc = _MeshDesc(float(lo), float(hi), int(n_coarse), int(p), len(balls), arr, nk,
+                         kn.ctypes.data_as(C.POINTER(C.c_double)), ktol, ksoft, klev)
         h = C.c_void_p()
         _check(lib.mh_mesh_create(C.byref(desc), C.byref(h)))
         self._h = h
@@ -197,7 +207,7 @@ class Mesh:
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w["lo"], w["hi"], w["n_coarse"], w["p"], w["balls"])
+        return cls(w["lo"], w["hi"], w["n_coarse"], w["p"], w["balls"], w.get("kelly"))
 
     def coords(self):
         out = np.zeros((self.info["n_full"], 3))

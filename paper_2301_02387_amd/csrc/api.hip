@@ -220,6 +220,7 @@ extern "C" int mh_set_allocator(mh_alloc_fn alloc_fn, mh_free_fn free_fn, void* 
 extern "C" int mh_mesh_create(const mh_mesh_desc* desc, mh_mesh** out) {
   if (!desc || !out) return fail(MH_INVALID_ARG, "null argument");
   if (desc->n_balls < 0 || (desc->n_balls > 0 && !desc->balls)) return fail(MH_INVALID_ARG, "bad balls");
+  if (desc->n_kelly < 0 || (desc->n_kelly > 0 && !desc->kelly_nuclei)) return fail(MH_INVALID_ARG, "bad Kelly nuclei");
   return guarded([&]() -> int {
     std::vector<Ball> balls;
     for (int i = 0; i < desc->n_balls; ++i) {
@@ -229,9 +230,19 @@ extern "C" int mh_mesh_create(const mh_mesh_desc* desc, mh_mesh** out) {
       b.levels = desc->balls[i].levels;
       balls.push_back(b);
     }
+    KellyReq kr;
+    for (int i = 0; i < desc->n_kelly; ++i) {
+      Nucleus n;
+      n.Z = desc->kelly_nuclei[4 * i];
+      for (int d = 0; d < 3; ++d) n.R[d] = desc->kelly_nuclei[4 * i + 1 + d];
+      kr.nuclei.push_back(n);
+    }
+    kr.tol = desc->kelly_tol;
+    kr.soft = desc->kelly_soft;
+    kr.max_level = desc->kelly_max_level;
     auto m = std::make_unique<mh_mesh>();
     bool unsup = false;
-    std::string err = build_mesh(desc->lo, desc->hi, desc->n_coarse, desc->p, balls, m->M, unsup);
+    std::string err = build_mesh(desc->lo, desc->hi, desc->n_coarse, desc->p, balls, m->M, unsup, &kr);
     if (!err.empty()) return fail(unsup ? MH_UNSUPPORTED : MH_INVALID_ARG, err);
     *out = m.release();
     return MH_OK;
@@ -252,6 +263,7 @@ extern "C" int mh_mesh_info_get(const mh_mesh* mesh, mh_mesh_info* info) {
   info->p = M.p;
   info->max_level = M.Lmax;
   for (int l = 0; l <= M.Lmax && l < 16; ++l) info->level_counts[l] = M.level_counts[l];
+  info->kelly_rounds = M.kelly_rounds;
   return MH_OK;
 }
 

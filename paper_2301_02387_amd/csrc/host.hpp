@@ -24,6 +24,19 @@ struct Ball {
   int levels;
 };
 
+struct Nucleus {
+  double Z;
+  double R[3];
+};
+
+// Kelly refinement request (Sec. III.A): leaves are halved while the Kelly
+// indicator of the softened nuclear potential exceeds tol, up to max_level.
+struct KellyReq {
+  std::vector<Nucleus> nuclei;  // empty: no Kelly refinement
+  double tol = 0.0, soft = 0.0;
+  int max_level = 0;
+};
+
 struct Mesh {
   double lo = 0, hi = 0, H = 0;
   int nc = 0, p = 0, P = 0, Lmax = 0;
@@ -41,18 +54,21 @@ struct Mesh {
   std::vector<int32_t> masters;      // DoF masters, ascending
   std::vector<int64_t> level_counts;
   std::vector<Ball> balls;           // the refinement request the mesh was built from
+  KellyReq kelly;
+  int kelly_rounds = 0;              // Kelly refinement rounds taken
   Gll gll;
 };
 
 // Returns "" on success, else an error message; `unsupported` set for
 // configurations the library refuses (hanging node on the boundary, ...).
+// kelly: optional Kelly refinement after the balls; level_cap >= 0: leaves
+// deeper than level_cap are then replaced by their ancestors at that level;
+// from: start from that mesh's leaves (same box) instead of the coarse cubes.
+// The coarser multigrid levels of a Kelly mesh are its own leaves capped
+// (from = the fine mesh), so each nests in the one above.
 std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ball>& balls,
-                       Mesh& out, bool& unsupported);
-
-struct Nucleus {
-  double Z;
-  double R[3];
-};
+                       Mesh& out, bool& unsupported, const KellyReq* kelly = nullptr, int level_cap = -1,
+                       const Mesh* from = nullptr);
 
 // Operator tables computed on the host at set-up.
 struct OpHost {

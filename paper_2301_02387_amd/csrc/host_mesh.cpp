@@ -157,8 +157,121 @@ struct Key3Hash {
 
 }  // namespace
 
+// Kelly's indicator (Sec. III.A) of the softened nuclear potential
+// V = -sum Z / sqrt(|r - R|^2 + a^2) on every leaf: u_K interpolates V at the
+// leaf's own Gauss-Lobatto nodes, and eta_K^2 = (h_K / 24) sum over the
+// leaf's interior faces of the integral of the squared jump of du/dn, h_K =
+// sqrt(3) edge.  Each face is integrated on its parts shared with one
+// neighbour (the whole face against a leaf of the same or the next coarser
+// level, else the four faces of the finer leaves across it) by the tensor
+// Gauss-Legendre rule of p + 1 points, exact for the polynomial jump squared.
+static void kelly_indicators(const std::vector<uint64_t>& leaves, const std::unordered_set<uint64_t>& set, double lo,
+                             double H, int nc, int p, const std::vector<double>& xi, const KellyReq& kr,
+                             std::vector<double>& eta2) {
+  const int P = p + 1;
+  std::vector<double> gq, gw;
+  gauss_legendre(P, gq, gw);
+  auto holder = [&](int l, int64_t a, int64_t b, int64_t c) -> int {
+    for (int L = l; L >= 0; --L) {
+      const int s = l - L;
+      if (set.count(pack(L, a >> s, b >> s, c >> s))) return L;
+    }
+    return -1;
+  };
+  auto pot = [&](double x, double y, double z) {
+    double v = 0.0;
+    for (const Nucleus& n : kr.nuclei) {
+      const double dx = x - n.R[0], dy = y - n.R[1], dz = z - n.R[2];
+      v -= n.Z / std::sqrt(dx * dx + dy * dy + dz * dz + kr.soft * kr.soft);
+    }
+    return v;
+  };
+  struct Cell {
+    double h, o[3];
+    std::vector<double> U;  // U[(c P + b) P + a] = V at node (a, b, c)
+  };
+  auto make_cell = [&](int l, int64_t i, int64_t j, int64_t k) {
+    Cell C;
+    C.h = H / std::ldexp(1.0, l);
+    const int64_t idx[3] = {i, j, k};
+    for (int d = 0; d < 3; ++d) C.o[d] = lo + C.h * idx[d];
+    C.U.resize(P * P * P);
+    for (int c = 0; c < P; ++c)
+      for (int b = 0; b < P; ++b)
+        for (int a = 0; a < P; ++a)
+          C.U[(c * P + b) * P + a] = pot(C.o[0] + C.h * (xi[a] + 1.0) / 2.0, C.o[1] + C.h * (xi[b] + 1.0) / 2.0,
+                                         C.o[2] + C.h * (xi[c] + 1.0) / 2.0);
+    return C;
+  };
+  // d u_C / d x_d at a physical point
+  auto dgrad = [&](const Cell& C, int d, const double* x) {
+    double B[3][4];
+    for (int e = 0; e < 3; ++e) {
+      const double t = 2.0 * (x[e] - C.o[e]) / C.h - 1.0;
+      for (int a = 0; a < P; ++a) B[e][a] = e == d ? lagrange_d(xi, a, t) * (2.0 / C.h) : lagrange(xi, a, t);
+    }
+    double s = 0.0;
+    for (int c = 0; c < P; ++c)
+      for (int b = 0; b < P; ++b) {
+        double r = 0.0;
+        for (int a = 0; a < P; ++a) r += C.U[(c * P + b) * P + a] * B[0][a];
+        s += r * B[1][b] * B[2][c];
+      }
+    return s;
+  };
+  eta2.assign(leaves.size(), 0.0);
+  for (size_t n = 0; n < leaves.size(); ++n) {
+    const Leaf L = unpack(leaves[n]);
+    const Cell K = make_cell(L.l, L.i, L.j, L.k);
+    const int64_t idx[3] = {L.i, L.j, L.k};
+    const int64_t n_l = (int64_t)nc << L.l;
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        int64_t nb[3] = {idx[0], idx[1], idx[2]};
+        nb[d] += sgn;
+        if (nb[d] < 0 || nb[d] >= n_l) continue;  // box boundary
+        const double xd = K.o[d] + (sgn > 0 ? K.h : 0.0);
+        struct Part {
+          Cell N;
+          double t0, t1, side;
+        };
+        std::vector<Part> parts;
+        const int Lh = holder(L.l, nb[0], nb[1], nb[2]);
+        if (Lh >= 0) {
+          const int s = L.l - Lh;
+          parts.push_back({make_cell(Lh, nb[0] >> s, nb[1] >> s, nb[2] >> s), K.o[e1], K.o[e2], K.h});
+        } else {
+          for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+              int64_t c[3];
+              c[d] = 2 * nb[d] + (sgn > 0 ? 0 : 1);
+              c[e1] = 2 * idx[e1] + a;
+              c[e2] = 2 * idx[e2] + b;
+              parts.push_back({make_cell(L.l + 1, c[0], c[1], c[2]), K.o[e1] + a * K.h / 2, K.o[e2] + b * K.h / 2,
+                               K.h / 2});
+            }
+        }
+        for (const Part& pt : parts) {
+          for (int u = 0; u < P; ++u)
+            for (int v = 0; v < P; ++v) {
+              double x[3];
+              x[d] = xd;
+              x[e1] = pt.t0 + pt.side * (gq[u] + 1.0) / 2.0;
+              x[e2] = pt.t1 + pt.side * (gq[v] + 1.0) / 2.0;
+              const double jump = dgrad(K, d, x) - dgrad(pt.N, d, x);
+              acc += gw[u] * gw[v] * (pt.side / 2.0) * (pt.side / 2.0) * jump * jump;
+            }
+        }
+      }
+    }
+    eta2[n] = std::sqrt(3.0) * K.h / 24.0 * acc;
+  }
+}
+
 std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ball>& balls, Mesh& M,
-                       bool& unsupported) {
+                       bool& unsupported, const KellyReq* kelly, int level_cap, const Mesh* from) {
   unsupported = false;
   if (p < 1 || p > 3) {
     unsupported = true;
@@ -174,9 +287,16 @@ std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ba
 
   // ---- ball refinement to a fixed point --------------------------------
   std::vector<uint64_t> cur;
-  for (int64_t k = 0; k < nc; ++k)
-    for (int64_t j = 0; j < nc; ++j)
-      for (int64_t i = 0; i < nc; ++i) cur.push_back(pack(0, i, j, k));
+  if (from) {  // start from another mesh's leaves (same box)
+    if (from->nc != nc || from->lo != lo || from->hi != hi) return "leaves of a mesh on another box";
+    for (int64_t e = 0; e < from->n_cells; ++e)
+      cur.push_back(pack(from->cell_level[e], from->cell_ijk[3 * e], from->cell_ijk[3 * e + 1],
+                         from->cell_ijk[3 * e + 2]));
+  } else {
+    for (int64_t k = 0; k < nc; ++k)
+      for (int64_t j = 0; j < nc; ++j)
+        for (int64_t i = 0; i < nc; ++i) cur.push_back(pack(0, i, j, k));
+  }
   for (;;) {
     bool changed = false;
     std::vector<uint64_t> nxt;
@@ -218,33 +338,79 @@ std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ba
     }
     return -1;
   };
-  for (;;) {
-    bool changed = false;
-    std::vector<uint64_t> snap(set.begin(), set.end());
-    std::sort(snap.begin(), snap.end());
-    for (uint64_t c : snap) {
-      if (!set.count(c)) continue;
-      Leaf L = unpack(c);
-      if (L.l < 2) continue;
-      int64_t nl = (int64_t)nc << L.l;
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            if (!dx && !dy && !dz) continue;
-            int64_t a = L.i + dx, b = L.j + dy, cc = L.k + dz;
-            if (a < 0 || b < 0 || cc < 0 || a >= nl || b >= nl || cc >= nl) continue;
-            int Lh = coarsest_holder(L.l, a, b, cc);
-            if (Lh >= 0 && Lh < L.l - 1) {
-              int s = L.l - Lh;
-              int64_t ia = a >> s, ib = b >> s, ic = cc >> s;
-              set.erase(pack(Lh, ia, ib, ic));
-              for (int c3 = 0; c3 < 8; ++c3)
-                set.insert(pack(Lh + 1, 2 * ia + (c3 & 1), 2 * ib + ((c3 >> 1) & 1), 2 * ic + (c3 >> 2)));
-              changed = true;
+  auto balance = [&]() {
+    for (;;) {
+      bool changed = false;
+      std::vector<uint64_t> snap(set.begin(), set.end());
+      std::sort(snap.begin(), snap.end());
+      for (uint64_t c : snap) {
+        if (!set.count(c)) continue;
+        Leaf L = unpack(c);
+        if (L.l < 2) continue;
+        int64_t nl = (int64_t)nc << L.l;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              if (!dx && !dy && !dz) continue;
+              int64_t a = L.i + dx, b = L.j + dy, cc = L.k + dz;
+              if (a < 0 || b < 0 || cc < 0 || a >= nl || b >= nl || cc >= nl) continue;
+              int Lh = coarsest_holder(L.l, a, b, cc);
+              if (Lh >= 0 && Lh < L.l - 1) {
+                int s = L.l - Lh;
+                int64_t ia = a >> s, ib = b >> s, ic = cc >> s;
+                set.erase(pack(Lh, ia, ib, ic));
+                for (int c3 = 0; c3 < 8; ++c3)
+                  set.insert(pack(Lh + 1, 2 * ia + (c3 & 1), 2 * ib + ((c3 >> 1) & 1), 2 * ic + (c3 >> 2)));
+                changed = true;
+              }
             }
-          }
+      }
+      if (!changed) break;
     }
-    if (!changed) break;
+  };
+  balance();
+
+  // ---- Kelly refinement ----------------------------------------------------
+  M.kelly = KellyReq();
+  M.kelly_rounds = 0;
+  if (kelly && !kelly->nuclei.empty()) {
+    if (!(kelly->soft > 0.0) || !(kelly->tol > 0.0) || kelly->max_level < 0) return "invalid Kelly refinement request";
+    M.kelly = *kelly;
+    std::vector<double> eta2;
+    for (;;) {
+      std::vector<uint64_t> cur_leaves(set.begin(), set.end());
+      std::sort(cur_leaves.begin(), cur_leaves.end());
+      kelly_indicators(cur_leaves, set, lo, H, nc, p, M.gll.x, *kelly, eta2);
+      std::vector<uint64_t> marked;
+      for (size_t n = 0; n < cur_leaves.size(); ++n)
+        if (unpack(cur_leaves[n]).l < kelly->max_level && eta2[n] > kelly->tol * kelly->tol)
+          marked.push_back(cur_leaves[n]);
+      if (marked.empty()) break;
+      for (uint64_t c : marked) {
+        const Leaf L = unpack(c);
+        if (L.l + 1 > 12 || ((int64_t)nc << (L.l + 1)) >= (1ll << kIdxBits)) return "refinement too deep";
+        set.erase(c);
+        for (int c3 = 0; c3 < 8; ++c3)
+          set.insert(pack(L.l + 1, 2 * L.i + (c3 & 1), 2 * L.j + ((c3 >> 1) & 1), 2 * L.k + (c3 >> 2)));
+      }
+      balance();
+      ++M.kelly_rounds;
+    }
+  }
+
+  // ---- level cap: ancestors at level_cap replace deeper leaves ---------------
+  if (level_cap >= 0) {
+    std::unordered_set<uint64_t> capped;
+    for (uint64_t c : set) {
+      const Leaf L = unpack(c);
+      if (L.l <= level_cap) {
+        capped.insert(c);
+      } else {
+        const int s = L.l - level_cap;
+        capped.insert(pack(level_cap, L.i >> s, L.j >> s, L.k >> s));
+      }
+    }
+    set.swap(capped);
   }
 
   // ---- Morton order of the leaves -----------------------------------------

@@ -141,28 +141,41 @@ void build_multigrid(const Mesh& fine, const OpHost& fop, MgHost& mg, int max_co
   MgLevel L0;
   take_operator(fop, fine.N, L0);
   mg.lv.push_back(std::move(L0));
-  // coarser meshes: Q1 on the same leaves, then shallower balls, then coarser base grids
-  std::vector<std::pair<int, std::vector<Ball>>> plan;
-  int maxlev = 0;
-  for (const Ball& b : fine.balls) maxlev = std::max(maxlev, b.levels);
-  for (int drop = 0; drop <= maxlev; ++drop) {
-    std::vector<Ball> bl;
-    for (Ball b : fine.balls) {
-      b.levels = std::max(0, b.levels - drop);
-      if (b.levels > 0) bl.push_back(b);
+  // coarser meshes: Q1 on the same leaves, then shallower balls (a Kelly mesh:
+  // its leaves capped one level shallower at a time, so every level nests in
+  // the one above), then coarser base grids
+  struct Plan {
+    int nc;
+    std::vector<Ball> balls;
+    int cap;  // level cap of a Kelly mesh, -1 otherwise
+  };
+  std::vector<Plan> plan;
+  const bool kelly = !fine.kelly.nuclei.empty();
+  if (kelly) {
+    for (int cap = fine.Lmax; cap >= 0; --cap) plan.push_back({fine.nc, {}, cap});
+  } else {
+    int maxlev = 0;
+    for (const Ball& b : fine.balls) maxlev = std::max(maxlev, b.levels);
+    for (int drop = 0; drop <= maxlev; ++drop) {
+      std::vector<Ball> bl;
+      for (Ball b : fine.balls) {
+        b.levels = std::max(0, b.levels - drop);
+        if (b.levels > 0) bl.push_back(b);
+      }
+      plan.push_back({fine.nc, bl, -1});
     }
-    plan.push_back({fine.nc, bl});
   }
   for (int nc = fine.nc; nc % 2 == 0 && (int64_t)(nc - 1) * (nc - 1) * (nc - 1) > max_coarse;) {
     nc /= 2;
-    plan.push_back({nc, {}});
+    plan.push_back({nc, {}, -1});
   }
   const double pol[3] = {0.0, 0.0, 1.0};
   for (size_t pi = 0; pi < plan.size(); ++pi) {
     const auto& pl = plan[pi];
     Mesh C;
     bool uns = false;
-    std::string err = build_mesh(fine.lo, fine.hi, pl.first, 1, pl.second, C, uns);
+    std::string err = pl.cap >= 0 ? build_mesh(fine.lo, fine.hi, pl.nc, 1, {}, C, uns, nullptr, pl.cap, &fine)
+                                  : build_mesh(fine.lo, fine.hi, pl.nc, 1, pl.balls, C, uns);
     if (!err.empty()) throw std::runtime_error("multigrid coarse mesh: " + err);
     const Mesh& F = meshes.back();
     if (F.p == 1 && C.n_cells == F.n_cells && C.nc == F.nc) continue;  // same mesh as the level above

@@ -12,6 +12,12 @@ Workloads (atomic units):
             Q3, box [-40,40]^3, 16^3 coarse cells, 4 levels within 6.5 bohr
             of O and 3 levels within 6.5 bohr of each H; CAS(10e, 8o);
             same pulse, 2 cycles.
+  h2o_q1    the same molecule as the high-harmonic workload of Sec. IV:
+            Q1, box [-64,64]^3 of 32^3 coarse cubes (edge 4 bohr), refined
+            by Kelly's indicator of the nuclear potential (threshold 0.005,
+            softening 0.05 bohr) down to edge 0.125 bohr (six cell sizes);
+            CAS(10e, 8o); triangular 2-cycle pulse along x, 400 nm,
+            8e14 W/cm^2 (E0 = 0.150982), dt = 0.01.
   h2_batch  64 H2 instances, bond length ~ U[1,2], depth ~ {2,3,4},
             E0 ~ U[0.02, 0.06], drawn from default_rng(2301) in that order.
 
@@ -20,7 +26,9 @@ Nothing here evaluates the method; the pulse is an input field.
 import numpy as np
 
 OMEGA_800NM = 0.0569542
+OMEGA_400NM = 0.1139084
 E0_1E14 = 0.0534
+E0_8E14 = 0.150982
 
 
 def _ball(center, radius, levels):
@@ -49,6 +57,13 @@ def workload(name):
                     nuclei=[(8.0, (0.0, 0.0, 0.0)), (1.0, (hx, hy, 0.0)), (1.0, (-hx, hy, 0.0))],
                     n_orb=8, n_alpha=5, n_beta=5, dt=0.02, krylov=12,
                     steps=11032, E0=E0_1E14, cycles=2)
+    if name == "h2o_q1":
+        hx, hy = 1.42994, 1.10718
+        nuclei = [(8.0, (0.0, 0.0, 0.0)), (1.0, (hx, hy, 0.0)), (1.0, (-hx, hy, 0.0))]
+        return dict(name=name, lo=-64.0, hi=64.0, n_coarse=32, p=1, balls=[],
+                    kelly=dict(nuclei=nuclei, tol=0.005, soft=0.05, max_level=5),
+                    nuclei=nuclei, n_orb=8, n_alpha=5, n_beta=5, dt=0.01, krylov=12,
+                    E0=E0_8E14, cycles=2, omega=OMEGA_400NM, envelope="triangular", polarization=(1.0, 0.0, 0.0))
     raise KeyError(name)
 
 
@@ -86,6 +101,12 @@ def small_workload(name, seed=0):
         return dict(name=name, lo=-20.0, hi=20.0, n_coarse=8, p=2,
                     balls=[_ball((0, 0, 0), 2.0, 2)],
                     nuclei=[(1.0, (0.0, 0.0, 0.7)), (1.0, (0.0, 0.0, -0.7))], n_orb=2, n_alpha=1, n_beta=1)
+    if name in ("kelly_q1", "kelly_q2"):  # H2 on a Kelly-refined mesh (no balls), field along x
+        q1 = name == "kelly_q1"
+        nuclei = [(1.0, (0.0, 0.0, 0.7)), (1.0, (0.0, 0.0, -0.7))]
+        return dict(name=name, lo=-8.0, hi=8.0, n_coarse=4, p=1 if q1 else 2, balls=[],
+                    kelly=dict(nuclei=nuclei, tol=0.01 if q1 else 0.005, soft=0.1, max_level=3),
+                    nuclei=nuclei, n_orb=2, n_alpha=1, n_beta=1, polarization=(1.0, 0.0, 0.0))
     if name == "small_n3":
         return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
                     balls=[_ball((0.2, -0.3, 0.1), 1.5, 2)],
@@ -115,6 +136,17 @@ def pulse(t, E0, cycles, omega=OMEGA_800NM):
     Tp = cycles * 2 * np.pi / omega if cycles else 1.0
     env = np.where((t >= 0) & (t <= Tp), np.sin(np.pi * t / Tp) ** 2, 0.0)
     return E0 * env * np.sin(omega * t)
+
+
+def pulse_triangular(t, E0, omega=OMEGA_400NM):
+    """E(t) = E0 f(t) sin(omega t) over two optical cycles, the envelope f
+    rising linearly from 0 to 1 over the first cycle and falling back to 0
+    over the second (the pulse of Sec. IV); zero outside."""
+    t = np.asarray(t, dtype=float)
+    ph = omega * t
+    env = np.where((ph >= 0) & (ph <= 2 * np.pi), ph / (2 * np.pi),
+                   np.where((ph > 2 * np.pi) & (ph <= 4 * np.pi), (4 * np.pi - ph) / (2 * np.pi), 0.0))
+    return E0 * env * np.sin(ph)
 
 
 def gaussian_orbitals(xyz, centers_exps, coeffs):

@@ -33,6 +33,7 @@ class Pair:
         self.op = None
         if with_op:
             w = self.w
+            op_kw.setdefault("polarization", w.get("polarization", (0.0, 0.0, 1.0)))
             self.op = mh.Operator(self.mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], **op_kw)
 
     # ---- layout conversion -------------------------------------------------

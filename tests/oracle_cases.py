@@ -9,7 +9,10 @@ from synth import workload, small_workload
 
 
 def desc_of(w):
-    return MeshDesc(w["lo"], w["hi"], w["n_coarse"], w["p"], [Ball(**b) for b in w["balls"]])
+    k = w.get("kelly") or {}
+    return MeshDesc(w["lo"], w["hi"], w["n_coarse"], w["p"], [Ball(**b) for b in w["balls"]],
+                    kelly_nuclei=list(k.get("nuclei", [])), kelly_tol=k.get("tol", 0.0),
+                    kelly_soft=k.get("soft", 0.0), kelly_max_level=k.get("max_level", 0))
 
 
 # Degenerate meshes for the tests only: no refinement, so no hanging nodes and
@@ -47,5 +50,5 @@ def case(name, seed=0):
         except KeyError:
             w = small_workload(name, seed)
     mesh = Mesh(desc_of(w))
-    ops = Operators(mesh, w["nuclei"])
+    ops = Operators(mesh, w["nuclei"], pol=w.get("polarization", (0.0, 0.0, 1.0)))
     return w, mesh, ops

@@ -17,7 +17,9 @@ from tests.lib_cases import Pair, rel_err_cols, max_rel_cols, poisson_solver
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["h_atom", "tiny_q3", "tiny_q1", "small_n3"]
+# kelly_*: meshes refined by Kelly's indicator of the nuclear potential (no
+# balls; hanging faces at every level), with the field along x
+SMALL = ["h_atom", "tiny_q3", "tiny_q1", "small_n3", "kelly_q1", "kelly_q2"]
 # unrefined meshes: no hanging nodes, no interface mass block; on the odd Q1
 # grid the multigrid hierarchy is the operator alone (dense inverse)
 UNIFORM = ["uniform_q2", "uniform_q1_odd"]
@@ -241,7 +243,8 @@ def test_arnoldi_step(name, tau, m):
                                                    ("tiny_q3", 4, False, 53), ("small_n3", 3, False, 52),
                                                    ("uniform_q2", 3, False, 13), ("uniform_q1_odd", 3, False, 53),
                                                    ("beta_one", 3, False, 13), ("full_alpha", 3, False, 13),
-                                                   ("tiny_q3", 4, False, 117), ("small_n3", 3, False, 116)])
+                                                   ("tiny_q3", 4, False, 117), ("small_n3", 3, False, 116),
+                                                   ("kelly_q1", 3, False, 13), ("kelly_q2", 3, False, 117)])
 def test_propagate_observables(name, steps, imag, sched):
     """Propagated dipoles, energies, orbitals and CI vectors against the
     oracle, with the default schedules (Poisson 13) and with the multigrid
@@ -286,7 +289,7 @@ def test_poisson_not_converged_status():
     assert rc == 1 and it == 1
 
 
-@pytest.mark.parametrize("name", ["tiny_q3", "small_n3", "h2"])
+@pytest.mark.parametrize("name", ["tiny_q3", "small_n3", "h2", "kelly_q1", "kelly_q2"])
 def test_multigrid_poisson(name):
     """The multigrid-preconditioned CG gives the oracle's potentials in a few
     tens of iterations, far fewer than the Jacobi-preconditioned one."""

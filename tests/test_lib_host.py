@@ -26,7 +26,8 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
-@pytest.mark.parametrize("name", ["h_atom", "tiny_q3", "tiny_q1", "small_n3", "h2", "uniform_q2", "uniform_q1_odd"])
+@pytest.mark.parametrize("name", ["h_atom", "tiny_q3", "tiny_q1", "small_n3", "h2", "uniform_q2", "uniform_q1_odd",
+                                  "kelly_q1", "kelly_q2"])
 def test_mesh_equals_oracle(name):
     mh, _ = _lib()
     from tests.lib_cases import match_nodes
@@ -50,6 +51,51 @@ def test_mesh_equals_oracle(name):
         assert set(mine) == set(ref)
         for k, v in ref.items():
             assert abs(mine[k] - v) < 1e-14
+
+
+@pytest.mark.parametrize("p,tol", [(1, 0.05), (2, 0.02), (3, 0.02)])
+def test_kelly_mesh_equals_oracle(p, tol):
+    """The water nuclei's Kelly refinement (Sec. III.A) in the library and in
+    the oracle: the same leaves (cell and level counts, the same node set)
+    after the same number of refinement rounds, at degrees 1 to 3."""
+    mh, _ = _lib()
+    from tests.lib_cases import match_nodes
+    from oracle.kelly import kelly_refine, softened_coulomb
+    from oracle.mesh import Mesh as OMesh, MeshDesc, balance_21, build_leaves
+    hx, hy = 1.42994, 1.10718
+    nuc = [(8.0, (0.0, 0.0, 0.0)), (1.0, (hx, hy, 0.0)), (1.0, (-hx, hy, 0.0))]
+    M = mh.Mesh(-16.0, 16.0, 4, p, [], kelly=dict(nuclei=nuc, tol=tol, soft=0.05, max_level=3))
+    desc = MeshDesc(-16.0, 16.0, 4, p, [], kelly_nuclei=nuc, kelly_tol=tol, kelly_soft=0.05, kelly_max_level=3)
+    om = OMesh(desc)
+    base = build_leaves(MeshDesc(-16.0, 16.0, 4, p, []))
+    _, rounds = kelly_refine(base, -16.0, 16.0, 4, p, softened_coulomb(nuc, 0.05), tol, 3,
+                             lambda L: balance_21(L, 4))
+    oi = om.info()
+    for k in ("n_cells", "n_full", "n_dof", "n_hang", "n_masters", "hang_nnz"):
+        assert M.info[k] == oi[k], k
+    assert M.info["level_counts"] == oi["level_counts"]
+    assert M.info["kelly_rounds"] == rounds > 0
+    perm = match_nodes(M.coords(), om.xyz)
+    assert len(perm) == om.n_full
+
+
+def test_kelly_request_errors():
+    mh, _ = _lib()
+    nuc = [(1.0, (0.0, 0.0, 0.0))]
+    for bad in (dict(tol=0.0, soft=0.1, max_level=2), dict(tol=0.01, soft=0.0, max_level=2),
+                dict(tol=0.01, soft=0.1, max_level=-1)):
+        with pytest.raises(mh.MHError):
+            mh.Mesh(-4.0, 4.0, 2, 1, [], kelly=dict(nuclei=nuc, **bad))
+
+
+def test_h2o_q1_mesh_levels():
+    """The Q1 water workload's Kelly mesh spans six cell sizes, 4.0 down to
+    0.125 bohr, as the mesh of Sec. IV does."""
+    mh, _ = _lib()
+    from synth import workload
+    M = mh.Mesh.from_workload(workload("h2o_q1"))
+    assert len(M.info["level_counts"]) == 6 and all(c > 0 for c in M.info["level_counts"])
+    assert M.info["p"] == 1 and M.info["kelly_rounds"] == 5
 
 
 def test_h2o_mesh_counts():
