@@ -314,7 +314,8 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
         byts, over = orbital_pass_bytes(info, op), 0
     sched_tag = "/".join(map(str, sched["poisson"] if dom == "poisson_spmv" else sched["orbital"]))
     ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0
-    wl = f"{name}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb"
+    wl = (f"{name}_{op.n_dof}dof_{op.n_orb}orb" if name.endswith(f"_q{w['p']}")
+          else f"{name}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb")
     bg = rhs_algorithmic_bytes(info, op)
     rhs_ach = bg / (rhs_ms * 1e-3) / 1e9
     orb_b = orbital_pass_bytes(info, op)

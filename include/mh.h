@@ -405,9 +405,12 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * residual and transfers) on float copies of their arrays (the residual, the
  * correction, the smoothing direction and the operator product); the CG
  * vectors, its own operator pass and every sum stay double, so the solution
- * meets the same residual target.
+ * meets the same residual target; bit 7 (with bit 1, when the number of
+ * column blocks divides 8): the column blocks bound to XCDs, XCD x serving
+ * block x mod the block count and the XCDs of one block splitting its rows
+ * into contiguous ranges, so each XCD's L2 holds rows of one block only.
  * Default sched 13.  Allowed values: 0 to 7 (orbital); any combination of
- * bits 0 to 6 (Poisson).
+ * bits 0 to 7 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
  * sums change order only). */

@@ -205,6 +205,23 @@ __device__ __forceinline__ XcdSweep xcd_sweep(int64_t total, int per_block, bool
 __device__ __forceinline__ XcdSweep xcd_sweep(int64_t total, int per_block, bool xcd = true) {
   return xcd_sweep(total, per_block, xcd, (int)blockIdx.x, (int)gridDim.x);
 }
+// Column blocks bound to XCDs: with B column blocks (B divides 8), XCD x
+// serves column block x % B and the 8 / B XCDs of one column block split the
+// items into contiguous ranges, so each L2 holds one column block's rows.
+// (bx, gx) as in xcd_sweep.
+__device__ __forceinline__ XcdSweep xcd_sweep_cols(int64_t total, int per_block, int B, int bx, int gx) {
+  const int x = bx % N_XCD;
+  const int G = N_XCD / B;   // XCDs per column block
+  const int xg = x / B;      // this XCD's rank among them
+  const int lb = bx / N_XCD;
+  const int nbx = gx / N_XCD;
+  const int64_t R = (total + G - 1) / G;
+  XcdSweep s;
+  s.start = xg * R + (int64_t)lb * per_block;
+  s.end = (xg + 1) * R < total ? (xg + 1) * R : total;
+  s.step = (int64_t)nbx * per_block;
+  return s;
+}
 static inline int xcd_grid(int64_t items, int per_block, int cap) {
   int64_t b = (items + per_block - 1) / per_block;
   if (b > cap) b = cap;

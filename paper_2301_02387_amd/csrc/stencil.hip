@@ -493,7 +493,14 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
   constexpr bool FUSE = MODE == SP_CG;
   INSTANCE;
   __shared__ double lds[NT * V];
-  const int col0 = blockIdx.z * nc;
+  // column block: blockIdx.z, or with schedule bit 7 the XCD's (xcd_sweep_cols;
+  // the grid then runs all column blocks along x)
+  const int nb_col = ld / nc;
+  const bool aff = (d.sched_poi & 128) && nb_col > 1 && N_XCD % nb_col == 0;
+  const int col0 = (aff ? ((int)blockIdx.x % N_XCD) % nb_col : (int)blockIdx.z) * nc;
+  // one workgroup per column block clears the slots below (workgroup 0 of the
+  // block's z slice; with bit 7 workgroups 0 .. nb_col - 1, one per block)
+  const bool first_wg = aff ? (int)blockIdx.x < nb_col : blockIdx.x == 0;
   x += d.oE * ld + col0;
   q += d.oE * ld + col0;
   pprev += d.oE * ld + col0;
@@ -521,7 +528,15 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
     // entries, combined by shuffles (no workgroup barrier)
     constexpr int SEG = 64 / L;
     const int wave = threadIdx.x >> 6, seg = (threadIdx.x & 63) / L;
-    for (int64_t lr = (int64_t)blockIdx.x * (NT / 64) + wave; lr < d.n_long; lr += (int64_t)nlb * (NT / 64)) {
+    // the long-row workgroups of this column block: all of them, or with column
+    // blocks bound to XCDs those on this XCD's group (index gi of ng)
+    int gi = (int)blockIdx.x, ng = nlb;
+    if (aff) {
+      const int G = N_XCD / nb_col;
+      gi = ((int)blockIdx.x / N_XCD) * G + ((int)blockIdx.x % N_XCD) / nb_col;
+      ng = nlb / N_XCD * G;
+    }
+    for (int64_t lr = (int64_t)gi * (NT / 64) + wave; lr < d.n_long; lr += (int64_t)ng * (NT / 64)) {
       const int64_t i = gbl(d.kt_long)[lr];
       const int beg = gbl(d.kt_ptr)[i], end = gbl(d.kt_ptr)[i + 1];
       double y[V];
@@ -538,7 +553,8 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
     constexpr int R = 64 / L;  // slots per wave
     const int wave = threadIdx.x >> 6, slot_in = (threadIdx.x & 63) / L;
     const XcdSweep sw =
-        xcd_sweep(d.n_slices * L, NT / 64, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
+        aff ? xcd_sweep_cols(d.n_slices * L, NT / 64, nb_col, (int)blockIdx.x - nlb, (int)gridDim.x - nlb)
+            : xcd_sweep(d.n_slices * L, NT / 64, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
     const auto* sptr = gbl(d.sell_ptr);
     const auto* srow = gbl(d.sell_row);
     const auto* scol = gbl(d.sell_col);
@@ -572,7 +588,8 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       spmv_store<V, MODE, T>(d, q, pout, x, pprev, beta, i, ld, c0, y, pq, cf, k);
     }
   } else {
-    const XcdSweep sw = xcd_sweep(d.N, NT / L, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
+    const XcdSweep sw = aff ? xcd_sweep_cols(d.N, NT / L, nb_col, (int)blockIdx.x - nlb, (int)gridDim.x - nlb)
+                            : xcd_sweep(d.N, NT / L, d.sched_poi & 1, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
     for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
       if (!col_ok) continue;
       const int beg = gbl(d.kt_ptr)[i], end = gbl(d.kt_ptr)[i + 1];
@@ -585,7 +602,7 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
     }
   }
   if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_RES) {
-    if (MODE == SP_CHEB0 && blockIdx.x == 0 && threadIdx.x < (unsigned)nc) red[k * ld + threadIdx.x] = 0.0;
+    if (MODE == SP_CHEB0 && first_wg && threadIdx.x < (unsigned)nc) red[k * ld + threadIdx.x] = 0.0;
     return;
   }
   // p.q (r.z for SP_CHEB_RZ) of the workgroup: shuffles over the rows of each wave, then 4 waves
@@ -607,7 +624,7 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
       // iteration of this pass: k (fused), -2 - k (plain pass of a CG iteration), 0 (k = -1: start)
       const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
       atomicAdd(red + (RED_PQ + kk % 2) * ld + threadIdx.x, sum);  // p.q of this instance and column
-      if (FUSE && blockIdx.x == 0) {  // clear what the update pass of this iteration accumulates into
+      if (FUSE && first_wg) {  // clear what the update pass of this iteration accumulates into
         red[(RED_RZ + (k + 1) % 3) * ld + threadIdx.x] = 0.0;
         red[(RED_RR + k % 2) * ld + threadIdx.x] = 0.0;
       }
@@ -627,6 +644,22 @@ static int long_row_blocks(const Batch& b) {
 template <int L, int V, int MODE, class T>
 static void launch_spmv_m(const Batch& b, const T* x, const T* pprev, T* pout, int ld, int nc, T* q, double* red,
                           int k, hipStream_t s) {
+  // schedule bit 7 with column blocks: the blocks ride along x, bound to XCDs
+  // (the kernel takes the column block from the XCD), each block the whole sweep
+  const int nbc = ld / nc;
+  if ((b.mx.sched_poi & 128) && nbc > 1 && N_XCD % nbc == 0) {
+    const int nlb = long_row_blocks(b) * nbc;
+    const int sweep = (b.mx.sched_poi & 32) ? xcd_grid(b.mx.n_slices * L, NT / 64, b.mx.grid_poi)
+                                            : xcd_grid(b.mx.N, NT / L, b.mx.grid_poi);
+    const dim3 g(nlb + sweep * nbc, b.ni, 1);
+    if (b.mx.sched_poi & 32)
+      hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, true, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
+                         nlb, red, k);
+    else
+      hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, false, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
+                         nlb, red, k);
+    return;
+  }
   const int nlb = long_row_blocks(b);
   if (b.mx.sched_poi & 32) {
     const dim3 g(nlb + xcd_grid(b.mx.n_slices * L, NT / 64, b.mx.grid_poi), b.ni, ld / nc);

@@ -126,15 +126,16 @@ def test_poisson_pairs(name):
 def test_poisson_every_schedule(name):
     """Each Poisson launch schedule (sweep order, column blocks, long rows by
     waves, direction fused into the operator pass, multigrid preconditioner,
-    sliced-ELL short rows) gives the oracle's potentials, cold and warm."""
+    sliced-ELL short rows, float finest level, column blocks bound to XCDs)
+    gives the oracle's potentials, cold and warm."""
     P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     n = P.w["n_orb"]
     c = orbitals(P, 4)
     ref = poisson_solver(P.ops).pair_potentials(c)
     torch = _torch()
     x = dev(P.to_lib_orb(c))
-    for sched in (127, 117, 116, 85, 84, 63, 61, 53, 45, 44, 39, 37, 36, 33, 32, 31, 29, 22, 21, 20, 16, 15, 14, 13,
-                  12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
+    for sched in (255, 246, 214, 182, 170, 130, 127, 117, 116, 85, 84, 63, 61, 53, 45, 44, 39, 37, 36, 33, 32, 31, 29,
+                  22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
         for grid in (8, 2048):
             P.op.tune(1, sched, grid)
             W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
