@@ -408,9 +408,12 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * meets the same residual target; bit 7 (with bit 1, when the number of
  * column blocks divides 8): the column blocks bound to XCDs, XCD x serving
  * block x mod the block count and the XCDs of one block splitting its rows
- * into contiguous ranges, so each XCD's L2 holds rows of one block only.
+ * into contiguous ranges, so each XCD's L2 holds rows of one block only;
+ * bits 8-9 (with bit 4): the degree of the Chebyshev smoothing before and
+ * after each coarse correction, 2 + their value (2 to 5; more passes per
+ * cycle, fewer CG iterations).
  * Default sched 13.  Allowed values: 0 to 7 (orbital); any combination of
- * bits 0 to 7 (Poisson).
+ * bits 0 to 9 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
  * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
  * sums change order only). */

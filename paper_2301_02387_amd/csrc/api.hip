@@ -630,7 +630,8 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   P.part_stride = (int64_t)8192 * 2 * ncol;
   P.part = op->alloc<double>((size_t)ni * P.part_stride);
   P.Q = op->alloc<double>((size_t)ni * P.nharm * ncol);
-  P.mblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (mx.NE + 31) / 32));
+  // moment partial sums: up to 2048 workgroups on the matrix-core form (16 or more columns), 512 otherwise
+  P.mblk = (int)std::min<int64_t>(ncol >= 16 ? 2048 : 512, std::max<int64_t>(1, (mx.NE + 31) / 32));
   P.mpart = op->alloc<double>((size_t)ni * P.mblk * P.nharm * ncol);
   // CI space
   op->na = desc.n_alpha;
@@ -883,14 +884,18 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
   mg->rf = op->alloc<float>(tlen);
   for (float* f : {mg->z0f, mg->z0bf, mg->t0f, mg->d0f, mg->rf}) HIPCHK(hipMemsetAsync(f, 0, tlen * sizeof(float), s));
   // level-0 Chebyshev coefficients of the fused smoothing passes: s0 = 1/theta
-  // (first step), then c1, c2 of the second step of the three-term recurrence
+  // (first step), then c1, c2 of each later step of the three-term recurrence
   for (int i = 0; i < ni; ++i) {
     const double b = H[i].lv[0].lmax, a = b / MG_RANGE;
     const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
-    const double rho0 = 1.0 / sigma, rn = 1.0 / (2.0 * sigma - rho0);
+    double rho = 1.0 / sigma;
     op->dh[i].mgc[0] = 1.0 / theta;
-    op->dh[i].mgc[1] = rn * rho0;
-    op->dh[i].mgc[2] = 2.0 * rn / delta;
+    for (int k = 1; k < MG_MAX_DEG; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      op->dh[i].mgc[2 * k - 1] = rn * rho;
+      op->dh[i].mgc[2 * k] = 2.0 * rn / delta;
+      rho = rn;
+    }
   }
   upload_instances(op, s);
   std::vector<std::vector<MgLevelDev>> rec(nlev, std::vector<MgLevelDev>(ni));
@@ -979,32 +984,53 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
   const MgDev& mg = *op->mg;
   const int ncol = op->ncol, ni = op->ni;
   const int64_t N = B.mx.N;
-  const bool fused = mg.nlev > 1 && mg.nu == 2;
+  // Poisson schedule bits 8-9: Chebyshev smoothing degree 2 + their value
+  op->mg->nu = 2 + ((B.mx.sched_poi >> 8) & 3);
+  const int nu = mg.nu;
+  const bool fused = mg.nlev > 1 && nu >= 2;
   // Poisson schedule bit 6: the finest level's smoothing passes, residual
   // pass and transfers on float copies of its arrays (the preconditioner
   // only; the CG vectors, its operator pass and every sum stay double)
   const bool f32 = fused && (B.mx.sched_poi & 64);
   op->mg->lv[0] = f32 ? mg.lv0_float : mg.lv0_double;
   int rz_slot = RED_RZ;
+  // the level-0 correction alternates between two buffers (a smoothing step
+  // reads one and writes the other): zc = 1 while it is in the second.  The
+  // pre-smoothing starts in the buffer that makes it end in the first, where
+  // the residual pass and the prolongation read it; after the post-smoothing
+  // it ends in the second when the degree is odd.
+  int zc = 0;
   MgLevel0Ops ops;
   if (f32) {
     ops.spmv = [&](hipStream_t st) { launch_poisson_apply_f(B, mg.z0f, mg.t0f, ncol, op->mg_red, st); };
     ops.resid = [&](hipStream_t st) { launch_mg_resid_f(B, mg.z0f, mg.rf, mg.t0f, ncol, op->mg_red, st); };
-    ops.cheb0 = [&](hipStream_t st) { launch_mg_cheb0_f(B, mg.rf, mg.z0f, mg.d0f, P.red, rz_slot, ncol, st); };
-    ops.cheb = [&](int k, hipStream_t st) {
-      launch_mg_cheb_step_f(B, k == 0 ? mg.z0f : mg.z0bf, mg.rf, k == 0 ? mg.z0bf : mg.z0f, mg.d0f, P.red, ncol, k,
-                            k == 1 ? rz_slot : -1, st);
+    ops.cheb0 = [&](hipStream_t st) {
+      zc = nu % 2;
+      launch_mg_cheb0_f(B, mg.rf, zc ? mg.z0bf : mg.z0f, mg.d0f, P.red, rz_slot, ncol, st);
+    };
+    ops.cheb = [&](int k, bool rz, hipStream_t st) {
+      float* zi = zc ? mg.z0bf : mg.z0f;
+      float* zo = zc ? mg.z0f : mg.z0bf;
+      zc ^= 1;
+      launch_mg_cheb_step_f(B, zi, mg.rf, zo, mg.d0f, P.red, ncol, k, rz ? rz_slot : -1, st);
     };
   } else {
     ops.spmv = [&](hipStream_t st) { launch_poisson_apply(B, mg.z0, mg.t0, ncol, op->mg_red, P, st); };
     ops.resid = [&](hipStream_t st) { launch_mg_resid(B, mg.z0, P.r, mg.t0, ncol, op->mg_red, st); };
-    ops.cheb0 = [&](hipStream_t st) { launch_mg_cheb0(B, P.r, mg.z0, mg.d0, P.red, rz_slot, ncol, st); };
-    ops.cheb = [&](int k, hipStream_t st) {
-      launch_mg_cheb_step(B, k == 0 ? mg.z0 : mg.z0b, P.r, k == 0 ? mg.z0b : mg.z0, mg.d0, P.red, ncol, k,
-                          k == 1 ? rz_slot : -1, st);
+    ops.cheb0 = [&](hipStream_t st) {
+      zc = nu % 2;
+      launch_mg_cheb0(B, P.r, zc ? mg.z0b : mg.z0, mg.d0, P.red, rz_slot, ncol, st);
+    };
+    ops.cheb = [&](int k, bool rz, hipStream_t st) {
+      double* zi = zc ? mg.z0b : mg.z0;
+      double* zo = zc ? mg.z0 : mg.z0b;
+      zc ^= 1;
+      launch_mg_cheb_step(B, zi, P.r, zo, mg.d0, P.red, ncol, k, rz ? rz_slot : -1, st);
     };
   }
-  double* z = mg.z0;
+  // the preconditioned residual after a fused cycle (single level: the dense solve's z0)
+  double* z = fused && nu % 2 ? mg.z0b : mg.z0;
+  float* zf = nu % 2 ? mg.z0bf : mg.z0f;
   auto precondition = [&](int it) {  // z = B r with r.z in slot RED_RZ + it % 3
     rz_slot = RED_RZ + it % 3;
     mg_vcycle(mg, ni, ncol, ops, s);
@@ -1023,7 +1049,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     double* pcur = (k % 2) ? P.p2 : P.p;
     double* pold = (k % 2) ? P.p : P.p2;
     if (f32)
-      mg_dir(B.dm, ni, N, ncol, mg.z0f, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1,
+      mg_dir(B.dm, ni, N, ncol, zf, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1,
              RED_RR + k % 2, s);
     else
       mg_dir(B.dm, ni, N, ncol, z, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1,
@@ -1596,7 +1622,7 @@ static void build_sell(mh_op* op, int i, hipStream_t s) {
 }
 
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
-  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 255 : 7)) != 0)
+  if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 1023 : 7)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
   const int cap_max = which == 0 ? 65536 : 8192;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");

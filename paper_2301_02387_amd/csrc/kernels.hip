@@ -583,6 +583,87 @@ __global__ void __launch_bounds__(NT) k_gint(const DevMesh* __restrict__ dm, con
       if (a0 + u < na && c0 + v < ncol) pb[(a0 + u) * ncol + c0 + v] = acc[u][v];
 }
 
+// The same on the matrix cores (n >= 4): per chunk of GM_CH rows the real
+// and imaginary parts of the products X and the potentials are staged in
+// LDS, and Re G = sum Re X W, Im G = -sum Im X W accumulate in FP64 MFMA tiles
+// of 16 products x 16 columns (the lane layout of k_moments_mfma), the tiles
+// (real and imaginary product tiles x column tiles) dealt round-robin to the
+// four waves, at most GM_TW per wave.
+constexpr int GM_CH = 16, GM_TW = 8;
+typedef double dvec4g_t __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(NT) k_gint_mfma(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
+                                                  const double* __restrict__ W, int ncol,
+                                                  double2* __restrict__ part) {
+  INSTANCE;
+  __shared__ double sxr[GM_CH * 64];
+  __shared__ double sxi[GM_CH * 64];
+  __shared__ double sw[GM_CH * 64];
+  const int n = d.n, na = n * n, nout = na * ncol;
+  phi += d.oE * n;
+  W += d.oF * ncol;
+  const int nat = (na + 15) / 16, nct = (ncol + 15) / 16, ntile = 2 * nat * nct;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  dvec4g_t acc[GM_TW];
+#pragma unroll
+  for (int j = 0; j < GM_TW; ++j) acc[j] = dvec4g_t{0.0, 0.0, 0.0, 0.0};
+  const int64_t rows = d.NE;
+  for (int64_t base = (int64_t)blockIdx.x * GM_CH; base < rows; base += (int64_t)gridDim.x * GM_CH) {
+    const int cnt = (int)((rows - base) < GM_CH ? (rows - base) : GM_CH);
+    __syncthreads();
+    for (int e = threadIdx.x; e < GM_CH * 64; e += NT) {
+      const int r = e >> 6, a = e & 63;
+      double xr = 0.0, xi = 0.0, wv = 0.0;
+      if (r < cnt) {
+        const int64_t i = base + r;
+        if (a < na) {
+          const int p = a / n, q = a - p * n;
+          const double2 fp = phi[i * n + p], fq = phi[i * n + q];
+          const double mi = d.m[i];
+          // m_i phi_p conj(phi_q)
+          xr = mi * (fp.x * fq.x + fp.y * fq.y);
+          xi = mi * (fp.y * fq.x - fp.x * fq.y);
+        }
+        if (a < ncol) wv = W[i * ncol + a];
+      }
+      sxr[e] = xr;
+      sxi[e] = xi;
+      sw[e] = wv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < GM_CH; k0 += 4) {
+      const int kr = k0 + (lane >> 4), li = lane & 15;
+#pragma unroll
+      for (int j = 0; j < GM_TW; ++j) {
+        const int tile = wave + 4 * j;
+        if (tile < ntile) {
+          const int u = tile % nct, ta = tile / nct;   // ta < nat: real tiles, then imaginary
+          const int t = ta < nat ? ta : ta - nat;
+          const double a = (ta < nat ? sxr : sxi)[kr * 64 + 16 * t + li];
+          const double b = sw[kr * 64 + 16 * u + li];
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    }
+  }
+  double* pb = (double*)(part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout);
+#pragma unroll
+  for (int j = 0; j < GM_TW; ++j) {
+    const int tile = wave + 4 * j;
+    if (tile >= ntile) continue;
+    const int u = tile % nct, ta = tile / nct;
+    const bool im = ta >= nat;
+    const int t = im ? ta - nat : ta;
+    const int c = 16 * u + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * t + 4 * v + (lane >> 4);
+      // conj(X) W: the imaginary part enters with a minus sign
+      if (a < na && c < ncol) pb[2 * (a * ncol + c) + (im ? 1 : 0)] = im ? -acc[j][v] : acc[j][v];
+    }
+  }
+}
+
 // The same for n^2 x ncol <= 16 outputs (two orbitals): every thread
 // accumulates all outputs over a grid-stride set of rows, then one reduction
 // per workgroup.
@@ -647,13 +728,17 @@ __global__ void k_gint_assemble(const double2* __restrict__ G, int n, const int*
   }
 }
 
-int gint_blocks(const Batch& b) { return nblocks(b.mx.NE, XG_CH, 512); }
+// up to 2048 workgroups for the matrix-core form (n >= 4), 512 otherwise
+int gint_blocks(const Batch& b) { return nblocks(b.mx.NE, XG_CH, b.mx.n >= 4 ? 2048 : 512); }
 
 void launch_gint_full(const Batch& b, const double* phi, const double* W, const int* colmap, double* part, int nblk,
                       double* Gtmp, double* g, hipStream_t s) {
   const int n = b.mx.n, ncol = n * n;
   if (ncol * ncol <= 16)
     hipLaunchKernelGGL(k_gint_small, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol,
+                       (double2*)part);
+  else if (n >= 4)   // matrix cores: at least one full 16 x 16 tile
+    hipLaunchKernelGGL(k_gint_mfma, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol,
                        (double2*)part);
   else
     hipLaunchKernelGGL(k_gint, dim3(nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2*)phi, W, ncol,
@@ -727,54 +812,50 @@ __global__ void __launch_bounds__(NT) k_build_U(const DevMesh* __restrict__ dm, 
   }
 }
 
-// Eight orbitals (64 x 64 map): a register-tiled product per workgroup of
-// 64 nodes, U_tile = W_tile Mr^T, each thread a block of 4 nodes x 4 outputs
-// (16 FMAs per 8 LDS reads); the node rows of W are read once, coalesced.
-// Mr is staged as sM[c][v * 16 + g] = Mr[4 g + v][c], so the 16 output groups
-// of a wave read consecutive words.
-__global__ void __launch_bounds__(NT) k_build_U64(const DevMesh* __restrict__ dm, const double* __restrict__ W,
-                                                  const double* __restrict__ Mr, double* __restrict__ Upk) {
+// Eight orbitals (64 x 64 map) on the matrix cores: per chunk of 64 rows, wave w takes rows
+// 16 w .. 16 w + 15 and all four 16-output tiles, U = W M^T accumulated in
+// FP64 MFMA tiles (lane layout of k_moments_mfma) over the 64 columns, four
+// per instruction; W rows staged in LDS (row stride 65), M transposed in LDS.
+typedef double dvec4u_t __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(NT) k_build_U64_mfma(const DevMesh* __restrict__ dm, const double* __restrict__ W,
+                                                       const double* __restrict__ Mr, double* __restrict__ Upk) {
   INSTANCE;
-  __shared__ double sM[64 * 64];
+  __shared__ double sMT[64 * 64];
   __shared__ double sW[64 * 65];
   Mr += (int64_t)blockIdx.y * 64 * 64;
   W += d.oF * 64;
   Upk += d.oE * 64;
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int o = e / 64, c = e - o * 64;
-    sM[c * 64 + (o % 4) * 16 + o / 4] = Mr[e];
+    const int o = e >> 6, c = e & 63;
+    sMT[c * 64 + o] = Mr[e];
   }
-  const int ng = threadIdx.x / 16, og = threadIdx.x % 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   for (int64_t base = (int64_t)blockIdx.x * 64; base < d.NE; base += (int64_t)gridDim.x * 64) {
     const int cnt = (int)((d.NE - base) < 64 ? (d.NE - base) : 64);
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-      const int r = e / 64, c = e - r * 64;
+      const int r = e >> 6, c = e & 63;
       sW[r * 65 + c] = r < cnt ? W[(base + r) * 64 + c] : 0.0;
     }
     __syncthreads();
-    double acc[4][4];
+    dvec4u_t acc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int ot = 0; ot < 4; ++ot) acc[ot] = dvec4u_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int c0 = 0; c0 < 64; c0 += 4) {
+      const double a = sW[(16 * wave + li) * 65 + c0 + lk];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-    for (int c = 0; c < 64; ++c) {
-      double wv[4], mv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) wv[u] = sW[(4 * ng + u) * 65 + c];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) mv[v] = sM[c * 64 + v * 16 + og];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += wv[u] * mv[v];
+      for (int ot = 0; ot < 4; ++ot) {
+        const double bv = sMT[(c0 + lk) * 64 + 16 * ot + li];
+        acc[ot] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[ot], 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = 4 * ng + u;
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * wave + 4 * v + lk;
       if (r < cnt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Upk[(base + r) * 64 + 4 * og + v] = acc[u][v];
+        for (int ot = 0; ot < 4; ++ot) Upk[(base + r) * 64 + 16 * ot + li] = acc[ot][v];
     }
   }
 }
@@ -789,7 +870,7 @@ void launch_build_U_full(const Batch& b, const double* W, const double* Gamma, c
   else if (nn <= 4) hipLaunchKernelGGL(k_build_U<4>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
   else if (nn <= 16) hipLaunchKernelGGL(k_build_U<16>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
   else if (nn < 64) hipLaunchKernelGGL(k_build_U<64>, dim3(g, b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
-  else hipLaunchKernelGGL(k_build_U64, dim3(nblocks(b.mx.NE, 64, 8192), b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
+  else hipLaunchKernelGGL(k_build_U64_mfma, dim3(nblocks(b.mx.NE, 64, 8192), b.ni), dim3(NT), 0, s, b.dm, W, Mr, Upk);
 }
 
 // =====================================================================
@@ -1280,6 +1361,95 @@ __global__ void __launch_bounds__(NT) k_moments_rb(const DevMesh* __restrict__ d
     for (int b = 0; b < MT_C; ++b)
       if (t0 + a < nh && c0 + b < ncol) pb[(t0 + a) * ncol + c0 + b] = acc[a][b];
 }
+// The same moments on the matrix cores (16 or more columns): per chunk of
+// MP_CH rows the harmonics R[row][h] and the weighted pair densities
+// W[row][c] are staged in LDS once, and Q[h][c] += sum over rows of
+// R[row][h] W[row][c] accumulates in FP64 MFMA tiles of 16 harmonics x 16
+// columns, four rows per instruction.  The (harmonic tile, column tile)
+// pairs are dealt round-robin to the four waves, at most MM_TW per wave.
+// Lane layout of v_mfma_f64_16x16x4_f64 (measured): A[i][k] from lane 16 k + i,
+// B[k][j] from lane 16 k + j, and accumulator v of lane l holds
+// D[4 v + l / 16][l % 16].
+constexpr int MM_HP = 176;  // harmonics padded to a multiple of 16 (lmax <= 12: 169)
+constexpr int MM_TW = 11;   // 11 harmonic tiles x 4 column tiles over 4 waves
+constexpr int MM_CH = 16;   // rows per chunk (30.5 KB of LDS: five workgroups per compute unit)
+typedef double dvec4_t __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(NT) k_moments_mfma(const DevMesh* __restrict__ dm, const double2* __restrict__ phi,
+                                                     int lmax, int ncol, const int* __restrict__ colinfo,
+                                                     double* __restrict__ part) {
+  INSTANCE;
+  __shared__ double sR[MM_CH * MM_HP];
+  __shared__ double sW[MM_CH * 64];
+  const int nh = (lmax + 1) * (lmax + 1);
+  const int nct = (ncol + 15) / 16, ntile = ((nh + 15) / 16) * nct;
+  const int nout = nh * ncol;
+  const int n = d.n;
+  phi += d.oE * n;
+  const double cx = d.center[0], cy = d.center[1], cz = d.center[2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  dvec4_t acc[MM_TW];
+#pragma unroll
+  for (int j = 0; j < MM_TW; ++j) acc[j] = dvec4_t{0.0, 0.0, 0.0, 0.0};
+  const int64_t rows = d.NE;
+  for (int64_t base = (int64_t)blockIdx.x * MM_CH; base < rows; base += (int64_t)gridDim.x * MM_CH) {
+    const int cnt = (int)((rows - base) < MM_CH ? (rows - base) : MM_CH);
+    __syncthreads();
+    for (int w = threadIdx.x; w < MM_CH * (lmax + 1); w += NT) {
+      const int r = w / (lmax + 1), m = w - r * (lmax + 1);
+      double* R = sR + r * MM_HP;
+      if (r < cnt) {
+        const int64_t i = base + r;
+        solid_regular_m(d.xyz[3 * i] - cx, d.xyz[3 * i + 1] - cy, d.xyz[3 * i + 2] - cz, lmax, m, R);
+      } else {
+        for (int l = m; l <= lmax; ++l) {
+          R[l * l + m] = 0.0;
+          if (m > 0) R[l * l + l + m] = 0.0;
+        }
+      }
+    }
+    for (int e = threadIdx.x; e < MM_CH * (MM_HP - nh); e += NT)
+      sR[(e / (MM_HP - nh)) * MM_HP + nh + e % (MM_HP - nh)] = 0.0;
+    for (int e = threadIdx.x; e < MM_CH * 64; e += NT) {
+      const int r = e >> 6, c = e & 63;
+      double v = 0.0;
+      if (r < cnt && c < ncol) {
+        const int64_t i = base + r;
+        const int ci = colinfo[c];
+        v = d.m[i] * pair_density(phi, n, i, ci & 255, (ci >> 8) & 255, ci >> 16);
+      }
+      sW[e] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < MM_CH; k0 += 4) {
+      const int kr = k0 + (lane >> 4), li = lane & 15;
+#pragma unroll
+      for (int j = 0; j < MM_TW; ++j) {
+        const int tile = wave + 4 * j;
+        if (tile < ntile) {
+          const int t = tile / nct, u = tile - t * nct;
+          const double a = sR[kr * MM_HP + 16 * t + li];
+          const double b = sW[kr * 64 + 16 * u + li];
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    }
+  }
+  double* pb = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nout;
+#pragma unroll
+  for (int j = 0; j < MM_TW; ++j) {
+    const int tile = wave + 4 * j;
+    if (tile >= ntile) continue;
+    const int t = tile / nct, u = tile - t * nct;
+    const int c = 16 * u + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int h = 16 * t + 4 * v + (lane >> 4);
+      if (h < nh && c < ncol) pb[h * ncol + c] = acc[j][v];
+    }
+  }
+}
+
 // out[i][o] = sum_b part[i][b][o]; one workgroup per (output, instance)
 __global__ void __launch_bounds__(NT) k_sum_parts_real(const double* __restrict__ part, int nblk, int nout,
                                                        double* __restrict__ out) {
@@ -1456,11 +1626,16 @@ void launch_poisson_pipeline_moments(const Batch& b, const double* phi, const in
                                      hipStream_t s) {
   const int nout = P.nharm * P.ncol;
   const double2* ph = (const double2*)phi;
-  // register tiles of 4 harmonics x 4 columns, sets of NT tiles over grid.z
-  const int tiles = ((P.nharm + MT_H - 1) / MT_H) * ((P.ncol + MT_C - 1) / MT_C);
-  const unsigned nz = (unsigned)((tiles + NT - 1) / NT);
-  hipLaunchKernelGGL(k_moments_rb, dim3(P.mblk, b.ni, nz), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
-                     P.mpart);
+  if (P.ncol >= 16 && P.ncol <= 64 && P.nharm <= MM_HP) {  // matrix cores: every tile in one workgroup
+    hipLaunchKernelGGL(k_moments_mfma, dim3(P.mblk, b.ni), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
+                       P.mpart);
+  } else {
+    // register tiles of 4 harmonics x 4 columns, sets of NT tiles over grid.z
+    const int tiles = ((P.nharm + MT_H - 1) / MT_H) * ((P.ncol + MT_C - 1) / MT_C);
+    const unsigned nz = (unsigned)((tiles + NT - 1) / NT);
+    hipLaunchKernelGGL(k_moments_rb, dim3(P.mblk, b.ni, nz), dim3(NT), 0, s, b.dm, ph, P.lmax, P.ncol, colinfo,
+                       P.mpart);
+  }
   hipLaunchKernelGGL(k_sum_parts_real, dim3(nout, b.ni), dim3(NT), 0, s, P.mpart, P.mblk, nout, P.Q);
 }
 

@@ -18,6 +18,10 @@
 namespace mh {
 
 // Read-only mesh/operator data of one instance, resident in HBM.
+// Largest Chebyshev smoothing degree of the multigrid cycle (Poisson schedule
+// bits 8-9 choose 2 + their value).
+constexpr int MG_MAX_DEG = 5;
+
 struct DevMesh {
   int P = 0, n = 0;                // nodes per cell edge, orbitals
   int inst = 0;                    // instance index (== blockIdx.y of its workgroups)
@@ -65,7 +69,9 @@ struct DevMesh {
   const double* bnd_table = nullptr;    // [Nb][nharm] multipole boundary table
   double center[3] = {0.0, 0.0, 0.0};   // multipole expansion centre
   double E0 = 1.0;                      // field amplitude of this instance (E = E0 x the step's field value)
-  double mgc[3] = {0.0, 0.0, 0.0};      // multigrid level-0 Chebyshev coefficients: s0 = 1/theta, c1, c2
+  // multigrid level-0 Chebyshev coefficients: s0 = 1/theta, then (c1, c2) of
+  // steps 1 .. MG_MAX_DEG - 1 of the three-term recurrence
+  double mgc[2 * MG_MAX_DEG - 1] = {};
   double vnn = 0.0;                     // nuclear repulsion
   // launch schedules (set by mh_tune): bit 0 = XCD-contiguous sweep; orbital bit 1 = interface
   // solve by Chebyshev even where a dense inverse is held, bit 2 = stiffness part by the
@@ -220,8 +226,9 @@ void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, 
 // Chebyshev coefficients are each instance's DevMesh::mgc; red: the CG
 // accumulators [ni][RED_SLOTS][ncol]):
 //  - the first two smoothing steps from z = 0 (z and d from r); clears red slot rz_slot;
-//  - smoothing step k (0 or 1) from zin into zout (d updated in place); with
-//    rz_slot >= 0 (step 1 only) it also accumulates r.zout into that slot.
+//  - smoothing step k (0 .. degree - 1) from zin into zout (d updated in
+//    place); with rz_slot >= 0 (the last step after the coarse correction)
+//    it also accumulates r.zout into that slot.
 void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* red, int rz_slot, int ncol,
                      hipStream_t s);
 void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* red,

@@ -376,12 +376,12 @@ static void level_spmv(const MgDev& mg, int l, int ni, int ncol, const MgLevel0O
 }
 
 static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, const MgLevel0Ops& ops, hipStream_t s) {
-  if (l == 0 && ops.cheb0 && mg.nu == 2) {  // fused into the level-0 operator passes
+  if (l == 0 && ops.cheb0 && mg.nu >= 2) {  // fused into the level-0 operator passes
     if (from_zero) {
-      ops.cheb0(s);
+      ops.cheb0(s);                                   // steps 0 and 1
+      for (int k = 2; k < mg.nu; ++k) ops.cheb(k, false, s);
     } else {
-      ops.cheb(0, s);
-      ops.cheb(1, s);
+      for (int k = 0; k < mg.nu; ++k) ops.cheb(k, k == mg.nu - 1, s);
     }
     return;
   }

@@ -64,16 +64,19 @@ struct MgDev {
   float* rf = nullptr;
   MgLevelDev* lv0_double = nullptr;  // device [ni] level-0 records on double / float storage
   MgLevelDev* lv0_float = nullptr;
-  int nu = 2;               // smoothing steps before and after the coarse correction
+  int nu = 2;               // smoothing steps before and after the coarse correction (Chebyshev degree)
 };
 // Level-0 passes over the batch (batch arrays): t0 = A z0; and, when set, the
-// smoothing steps fused into the operator pass (nu = 2): the two steps from
-// zero (z0, d0 from r0), and step k (k = 0: z0 -> z0b, k = 1: z0b -> z0).
+// smoothing steps fused into the operator pass (nu >= 2): the two steps from
+// zero (z0, d0 from r0), and step k (from the current correction into the
+// other buffer; rz: the last step after the coarse correction, which also
+// accumulates r.z).  The caller keeps the correction in z0 wherever the
+// cycle reads it (residual pass, prolongation).
 struct MgLevel0Ops {
   std::function<void(hipStream_t s)> spmv;
   std::function<void(hipStream_t s)> resid;  // optional: t0 = r0 - A z0, the residual the restriction reads
   std::function<void(hipStream_t s)> cheb0;
-  std::function<void(int k, hipStream_t s)> cheb;
+  std::function<void(int k, bool rz, hipStream_t s)> cheb;
 };
 
 // z0 = B r0 for one symmetric V-cycle per instance (r0: the batch residual)

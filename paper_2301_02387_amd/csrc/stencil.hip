@@ -424,7 +424,9 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const T* __restr
 // SP_CHEB_RZ):
 //   SP_CHEB0: d0 = s0 D^-1 r, d = c1 d0 + c2 D^-1 (r - y), z = d0 + d;
 //   SP_CHEB:  d = c1 d + c D^-1 (r - y) (k = 0: c1 d dropped, c = s0; else
-//             c = c2), z = x + d; SP_CHEB_RZ also the r.z partial (in pq).
+//             c1, c = c2 of step k), z = x + d; SP_CHEB_RZ also the r.z
+//             partial (in pq), its step being k >> 4 (its slot k & 15).
+// cf: s0, then (c1, c2) of each step from 1 on.
 // SP_RES (x = z, pprev = r): q_i = r_i - y.
 template <int V, int MODE, class T>
 __device__ __forceinline__ void spmv_store(const DevMesh& d, T* __restrict__ q, T* __restrict__ pout,
@@ -438,7 +440,7 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, T* __restrict__ q, 
 #pragma unroll
     for (int v = 0; v < V; ++v) qo[v] = (T)(rv[v] - y[v]);
   } else if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_CHEB_RZ) {
-    const int step = MODE == SP_CHEB_RZ ? 1 : k;
+    const int step = MODE == SP_CHEB_RZ ? k >> 4 : k;
     const double di = gbl(d.kdiag_inv)[i];
     double rv[V], xv[V], dv[V];
     operand_row<V, SP_PLAIN, T>(gbl(pprev), gbl(pprev), gbl(d.kdiag_inv), beta, i, ld, c0, rv);
@@ -452,11 +454,12 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, T* __restrict__ q, 
     for (int v = 0; v < V; ++v) {
       if constexpr (MODE == SP_CHEB0) {
         const double d0 = cf[0] * di * rv[v];
-        const double dn = cf[1] * d0 + cf[2] * di * (rv[v] - y[v]);
+        const double dn = cf[1] * d0 + cf[2] * di * (rv[v] - y[v]);  // step 1
         qo[v] = (T)dn;
         po[v] = (T)(d0 + dn);
       } else {
-        const double dn = (step > 0 ? cf[1] * dv[v] + cf[2] * di * (rv[v] - y[v]) : cf[0] * di * (rv[v] - y[v]));
+        const double dn = (step > 0 ? cf[2 * step - 1] * dv[v] + cf[2 * step] * di * (rv[v] - y[v])
+                                    : cf[0] * di * (rv[v] - y[v]));
         const double zn = xv[v] + dn;
         qo[v] = (T)dn;
         po[v] = (T)zn;
@@ -484,7 +487,7 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, T* __restrict__ q, 
 // MODE: SP_*; red: the CG accumulators ([ni][RED_SLOTS][ld]); k: the CG
 // iteration (SP_CG; see launch_spmv_poisson for SP_PLAIN), the
 // smoothing step (SP_CHEB) or the r.z slot (SP_CHEB0 clears it, SP_CHEB_RZ
-// accumulates into it).
+// accumulates into slot k & 15 at step k >> 4).
 template <int L, int V, int MODE, bool SELL, class T>
 __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const T* __restrict__ x,
                                                      const T* __restrict__ pprev, T* __restrict__ pout,
@@ -505,7 +508,9 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
   q += d.oE * ld + col0;
   pprev += d.oE * ld + col0;
   pout += d.oE * ld + col0;
-  const double cf[3] = {d.mgc[0], d.mgc[1], d.mgc[2]};
+  double cf[2 * MG_MAX_DEG - 1];
+#pragma unroll
+  for (int j = 0; j < 2 * MG_MAX_DEG - 1; ++j) cf[j] = d.mgc[j];
   red += (int64_t)blockIdx.y * RED_SLOTS * ld + col0;
   const int lane = (int)(threadIdx.x & (L - 1));
   const int c0 = lane * V;
@@ -619,7 +624,7 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) sum += lds[w * (L * V) + threadIdx.x];
     if constexpr (MODE == SP_CHEB_RZ) {
-      atomicAdd(red + k * ld + threadIdx.x, sum);  // r.z of this instance and column
+      atomicAdd(red + (k & 15) * ld + threadIdx.x, sum);  // r.z of this instance and column
     } else {
       // iteration of this pass: k (fused), -2 - k (plain pass of a CG iteration), 0 (k = -1: start)
       const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
@@ -969,7 +974,7 @@ void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, doub
 }
 void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* red,
                          int ncol, int k, int rz_slot, hipStream_t s) {
-  if (rz_slot >= 0) launch_spmv_mode(b, zin, r, zout, ncol, d, red, SP_CHEB_RZ, rz_slot, s);
+  if (rz_slot >= 0) launch_spmv_mode(b, zin, r, zout, ncol, d, red, SP_CHEB_RZ, rz_slot | (k << 4), s);
   else launch_spmv_mode(b, zin, r, zout, ncol, d, red, SP_CHEB, k, s);
 }
 
@@ -986,7 +991,7 @@ void launch_mg_cheb0_f(const Batch& b, const float* r, float* z, float* d, doubl
 }
 void launch_mg_cheb_step_f(const Batch& b, const float* zin, const float* r, float* zout, float* d, double* red,
                            int ncol, int k, int rz_slot, hipStream_t s) {
-  if (rz_slot >= 0) launch_spmv_mode<float>(b, zin, r, zout, ncol, d, red, SP_CHEB_RZ, rz_slot, s);
+  if (rz_slot >= 0) launch_spmv_mode<float>(b, zin, r, zout, ncol, d, red, SP_CHEB_RZ, rz_slot | (k << 4), s);
   else launch_spmv_mode<float>(b, zin, r, zout, ncol, d, red, SP_CHEB, k, s);
 }
 

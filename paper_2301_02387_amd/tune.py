@@ -13,13 +13,14 @@ import os
 
 ORB_CANDIDATES = [(s, g) for s in (1, 0, 5, 4) for g in (2048, 8192, 65536)]
 POI_CANDIDATES = ([(s, g) for s in (13, 12, 5, 4, 9, 1, 45, 44, 37, 36) for g in (2048, 8192)]
-                  + [(s, 8192) for s in (21, 20, 29, 53, 52, 85, 84, 117, 116)])
+                  + [(s, 8192) for s in (21, 20, 29, 53, 52, 85, 84, 117, 116, 373, 372, 629, 628)])
 # column blocking only changes anything at 32 or more columns (n >= 6 orbitals).
 # On such wide column sets a Jacobi-preconditioned solve from zero takes
 # seconds (about 1,000 iterations on the 1.5M-unknown water mesh, against
 # about 15 with multigrid), so only one Jacobi schedule is timed there.
 POI_CANDIDATES_WIDE = ([(13, 8192)]
-                       + [(s, 8192) for s in (22, 20, 23, 21, 54, 52, 55, 53, 118, 116, 119, 117, 182, 214, 246)])
+                       + [(s, 8192) for s in (22, 20, 23, 21, 54, 52, 55, 53, 118, 116, 119, 117, 182, 214, 246,
+                                               372, 628, 884)])
 # grid caps are per instance: a batch fills the chip with fewer workgroups each
 ORB_CANDIDATES_BATCH = [(s, g) for s in (1, 0, 5, 4) for g in (256, 1024, 65536)]
 POI_CANDIDATES_BATCH = ([(s, g) for s in (13, 12, 5, 4, 1, 45, 37, 36) for g in (256, 1024)]

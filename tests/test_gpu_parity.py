@@ -126,16 +126,16 @@ def test_poisson_pairs(name):
 def test_poisson_every_schedule(name):
     """Each Poisson launch schedule (sweep order, column blocks, long rows by
     waves, direction fused into the operator pass, multigrid preconditioner,
-    sliced-ELL short rows, float finest level, column blocks bound to XCDs)
-    gives the oracle's potentials, cold and warm."""
+    sliced-ELL short rows, float finest level, column blocks bound to XCDs,
+    smoothing degrees 3 to 5) gives the oracle's potentials, cold and warm."""
     P = Pair(name, poisson_rtol=1e-13, poisson_maxit=20000)
     n = P.w["n_orb"]
     c = orbitals(P, 4)
     ref = poisson_solver(P.ops).pair_potentials(c)
     torch = _torch()
     x = dev(P.to_lib_orb(c))
-    for sched in (255, 246, 214, 182, 170, 130, 127, 117, 116, 85, 84, 63, 61, 53, 45, 44, 39, 37, 36, 33, 32, 31, 29,
-                  22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
+    for sched in (884, 629, 372, 373, 277, 255, 246, 214, 182, 170, 130, 127, 117, 116, 85, 84, 63, 61, 53, 45, 44,
+                  39, 37, 36, 33, 32, 31, 29, 22, 21, 20, 16, 15, 14, 13, 12, 9, 8, 7, 6, 5, 4, 2, 1, 0):
         for grid in (8, 2048):
             P.op.tune(1, sched, grid)
             W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
@@ -301,7 +301,9 @@ def test_multigrid_poisson(name):
     ref = poisson_solver(P.ops).pair_potentials(c)
     x = dev(P.to_lib_orb(c))
     its = {}
-    for sched in (13, 21, 85):       # Jacobi, multigrid, multigrid on float finest-level arrays (bit 6)
+    # Jacobi, multigrid, multigrid on float finest-level arrays (bit 6), and
+    # multigrid with smoothing of degree 3 and 4 (bits 8-9)
+    for sched in (13, 21, 85, 277, 533):
         P.op.tune(1, sched, 8192)
         W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
         it, rc = P.op.poisson_pairs(x, W)
@@ -312,9 +314,10 @@ def test_multigrid_poisson(name):
             num = np.sqrt(np.sum(P.ops.m * np.abs(got[k] - ref[k]) ** 2))
             den = np.sqrt(np.sum(P.ops.m * np.abs(ref[k]) ** 2))
             assert num / den < 1e-9, (sched, k, num / den)
-    print(name, "CG iterations jacobi / multigrid / multigrid float", its, flush=True)
+    print(name, "CG iterations jacobi / multigrid / float / degree 3 / degree 4", its, flush=True)
     assert its[21] <= 60 and its[21] * 4 < its[13], its
     assert its[85] <= its[21] + 2, its
+    assert its[533] <= its[277] <= its[21], its   # stronger smoothing, no more iterations
 
 
 @pytest.mark.parametrize("name", UNIFORM)
