@@ -382,7 +382,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="h2o", choices=["h2", "h2o", "h2o_q1", "h_atom", "h2x64"])
     ap.add_argument("--batch", type=int, default=64, help="instances of the h2x64 workload")
-    ap.add_argument("--seq-steps", type=int, default=2, help="timed steps per instance of the sequential runs")
+    ap.add_argument("--seq-steps", type=int, default=None,
+                    help="timed steps per instance of the sequential runs (default: --steps, the batch's own count)")
     ap.add_argument("--graph", action="store_true", help="replay each step's fixed part as a HIP graph")
     ap.add_argument("--graph-step", action="store_true",
                     help="replay whole steps (Poisson CG with a fixed iteration count included) as one HIP graph each")
@@ -584,6 +585,8 @@ def run_batch(args):
     from synth import h2_ci_guess, pulse
     from paper_2301_02387_amd.tune import autotune
 
+    if args.seq_steps is None:
+        args.seq_steps = args.steps
     ws, meshes, op, lay, phi, t_setup = batch_setup(args)
     w0 = ws[0]
     Ci = torch.from_numpy(np.stack([h2_ci_guess()] * op.n_inst)).cuda()
@@ -596,7 +599,8 @@ def run_batch(args):
     if args.warmup > 0:
         op.propagate(phi, Ci, W, [0.0] * (args.warmup + 1), 0.05, m=m, imaginary=True, final=False)
     t0 = Tp / 2
-    shape = [float(pulse(t0 + k * dt, 1.0, cycles)) for k in range(args.steps + 1)]
+    # field shape for the batch's steps and the sequential runs' untimed + timed steps
+    shape = [float(pulse(t0 + k * dt, 1.0, cycles)) for k in range(max(args.steps, args.seq_steps + 1) + 1)]
     op.propagate(phi, Ci, W, shape[:2], dt, m=m, final=False)
     sched = autotune(op, phi, W, cache_file=args.tune_cache)
     log(f"warm-up and tuning done: {sched['orbital']} {sched['poisson']}")
@@ -604,7 +608,8 @@ def run_batch(args):
     op.kernel_timing(1, True)
     torch.cuda.synchronize()
     t_a = time.perf_counter()
-    rec = op.propagate(phi, Ci, W, shape, dt, m=m, final=False, graph=args.graph, graph_step=args.graph_step)
+    rec = op.propagate(phi, Ci, W, shape[:args.steps + 1], dt, m=m, final=False, graph=args.graph,
+                       graph_step=args.graph_step)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_a
     k_orb = op.kernel_timing(0, False)
@@ -666,6 +671,7 @@ def run_batch(args):
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["count"])
     byts = kern[dom]["algorithmic_bytes"]
     ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0
+    batch_tag = "/".join(map(str, sched["poisson"] if dom == "poisson_spmv" else sched["orbital"]))
     ms_step = wall / args.steps * 1e3
     line = {
         "metric": "orbital-RHS evals/s (DoF x orbitals/s)",
@@ -700,8 +706,8 @@ def run_batch(args):
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, f"h2x{op.n_inst}_q3_{op.n_dof}dof_{op.n_orb}orb",
-                                                 schedule="/".join(map(str, sched["poisson"]))),
-                     "schedule": "/".join(map(str, sched["poisson"])), "algorithmic_bytes_per_launch": byts,
+                                                 schedule=batch_tag),
+                     "schedule": batch_tag, "algorithmic_bytes_per_launch": byts,
                      "algorithmic_bytes": "matrix-free: operand and result rows, cell maps, constraint rows, h",
                      "stored_operator_bytes_per_launch": spmv_over if dom == "poisson_spmv" else 0},
         "roofline_orbital": {"kernel": "stencil_orb", "bound": "hbm",

@@ -409,9 +409,10 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * column blocks divides 8): the column blocks bound to XCDs, XCD x serving
  * block x mod the block count and the XCDs of one block splitting its rows
  * into contiguous ranges, so each XCD's L2 holds rows of one block only;
- * bits 8-9 (with bit 4): the degree of the Chebyshev smoothing before and
- * after each coarse correction, 2 + their value (2 to 5; more passes per
- * cycle, fewer CG iterations).
+ * bits 8-9 (with bit 4): the degree of the Chebyshev smoothing on the finest
+ * level before and after each coarse correction, 2 + their value (2 to 5;
+ * more passes per cycle, fewer CG iterations); coarser levels smooth with
+ * degree 2.
  * Default sched 13.  Allowed values: 0 to 7 (orbital); any combination of
  * bits 0 to 9 (Poisson).
  * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192

@@ -1002,7 +1002,6 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
   int zc = 0;
   MgLevel0Ops ops;
   if (f32) {
-    ops.spmv = [&](hipStream_t st) { launch_poisson_apply_f(B, mg.z0f, mg.t0f, ncol, op->mg_red, st); };
     ops.resid = [&](hipStream_t st) { launch_mg_resid_f(B, mg.z0f, mg.rf, mg.t0f, ncol, op->mg_red, st); };
     ops.cheb0 = [&](hipStream_t st) {
       zc = nu % 2;
@@ -1015,7 +1014,6 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
       launch_mg_cheb_step_f(B, zi, mg.rf, zo, mg.d0f, P.red, ncol, k, rz ? rz_slot : -1, st);
     };
   } else {
-    ops.spmv = [&](hipStream_t st) { launch_poisson_apply(B, mg.z0, mg.t0, ncol, op->mg_red, P, st); };
     ops.resid = [&](hipStream_t st) { launch_mg_resid(B, mg.z0, P.r, mg.t0, ncol, op->mg_red, st); };
     ops.cheb0 = [&](hipStream_t st) {
       zc = nu % 2;

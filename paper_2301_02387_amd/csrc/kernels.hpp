@@ -219,9 +219,6 @@ void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k,
 void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s,
                       float* rf = nullptr);
 void launch_to_float(const double* x, float* y, int64_t nd, hipStream_t s);
-// q = K x on the DoF rows with the tuned operator kernel, p.q partials into red_scratch
-void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch, PoissonWs& P,
-                          hipStream_t s);
 // Multigrid-preconditioned CG on the finest level, in operator passes (the
 // Chebyshev coefficients are each instance's DevMesh::mgc; red: the CG
 // accumulators [ni][RED_SLOTS][ncol]):
@@ -238,7 +235,6 @@ void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, dou
 void launch_mg_resid(const Batch& b, const double* z, const double* r, double* t, int ncol, double* red_scratch,
                      hipStream_t s);
 // Poisson schedule bit 6: the finest multigrid level's passes on float arrays
-void launch_poisson_apply_f(const Batch& b, const float* x, float* q, int ncol, double* red_scratch, hipStream_t s);
 void launch_mg_cheb0_f(const Batch& b, const float* r, float* z, float* d, double* red, int rz_slot, int ncol,
                        hipStream_t s);
 void launch_mg_cheb_step_f(const Batch& b, const float* zin, const float* r, float* zout, float* d, double* red,

@@ -111,24 +111,6 @@ __device__ __forceinline__ void row_gather_v(IP col, DP val, int beg, int end, i
   }
 }
 
-// t = A z on each active record
-__global__ void __launch_bounds__(NT) k_mg_spmv(const MgLevelDev* __restrict__ lv, int ncol) {
-  const MgLevelDev& L = lv[blockIdx.y];
-  if (!L.active) return;
-  const int64_t total = L.N * ncol;
-  const auto* ptr = gbl(L.a_ptr);
-  const auto* col = gbl(L.a_col);
-  const auto* val = gbl(L.a_val);
-  const auto* x = gbl((const double*)L.z);
-  auto* y = gblw(L.t);
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int64_t i = e / ncol;
-    const int c = (int)(e - i * ncol);
-    const int beg = ptr[i], end = ptr[i + 1];
-    y[e] = end > beg ? row_gather_dot<false>(col, val, beg, end, 1, x, x, ncol, c) : 0.0;
-  }
-}
-
 // coarse.r = R (fine.r - fine.t) for each instance whose fine record is
 // active (tres: fine.t holds the residual r - A z already, R fine.t).  A
 // restriction row gathers every fine node in the support of a coarse basis
@@ -282,39 +264,6 @@ __global__ void __launch_bounds__(NT) k_mg_prolong(const MgLevelDev* __restrict_
   }
 }
 
-// Step k of the Chebyshev smoother on [lmax / MG_RANGE, lmax] for D^-1 A
-// applied to A z = r: res = r - t (t = A z; res = r on the first step from
-// z = 0), d = c1 d + c2 D^-1 res, z = d (first step from zero) or z += d.
-// The three-term coefficients follow the standard Chebyshev recurrence.
-__global__ void __launch_bounds__(NT) k_mg_cheb(const MgLevelDev* __restrict__ lv, int ncol, int k, int from_zero) {
-  const MgLevelDev& L = lv[blockIdx.y];
-  if (!L.active) return;
-  const double b = L.lmax, a = L.lmax / MG_RANGE;
-  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
-  double c1 = 0.0, c2 = 1.0 / theta;
-  double rho = 1.0 / sigma;
-  for (int j = 1; j <= k; ++j) {
-    const double rn = 1.0 / (2.0 * sigma - rho);
-    c1 = rn * rho;
-    c2 = 2.0 * rn / delta;
-    rho = rn;
-  }
-  const bool first = from_zero && k == 0;
-  const int64_t total = L.N * ncol;
-  const auto* dinv = gbl(L.dinv);
-  const auto* r = gbl((const double*)L.r);
-  const auto* t = gbl((const double*)L.t);
-  auto* dd = gblw(L.d);
-  auto* z = gblw(L.z);
-  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int64_t i = e / ncol;
-    const double res = first ? r[e] : r[e] - t[e];
-    const double dn = (k > 0 ? c1 * dd[e] : 0.0) + c2 * dinv[i] * res;
-    dd[e] = dn;
-    z[e] = first ? dn : z[e] + dn;
-  }
-}
-
 // z = Ainv r on each instance's coarsest level (dense, row-major): one wave
 // per (row, block of 8 columns), the lanes splitting the row's entries
 __global__ void __launch_bounds__(NT) k_mg_coarse(const MgLevelDev* __restrict__ co, int ncol) {
@@ -369,14 +318,91 @@ __global__ void __launch_bounds__(NT) k_mg_coarse(const MgLevelDev* __restrict__
 
 static dim3 level_grid(int64_t n, int ncol, int ni) { return dim3(nblocks(n * ncol, NT, 16384), ni); }
 
-// A z -> t on level l of every instance
-static void level_spmv(const MgDev& mg, int l, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s) {
-  if (l == 0) ops.spmv(s);
-  else hipLaunchKernelGGL(k_mg_spmv, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], ncol);
+// Coarse-level passes with the operator product fused in, LN lanes per row
+// and V adjacent columns per lane (16-byte loads for V = 4):
+//  - MODE 0, one Chebyshev smoothing step k (the recurrence of k_mg_cheb):
+//    res = r - A zin (res = r for the first step from zero), d = c1 d +
+//    c2 D^-1 res, zout = zin + d (zout = d for the first step from zero).
+//    zin and zout are the level's z and t arrays (into_t: z -> t, else
+//    t -> z), so the rows gathered from zin are never the rows written.
+//  - MODE 1, the residual t = r - A z that the restriction reads.
+template <int MODE, int V, int LN>
+__global__ void __launch_bounds__(NT) k_mg_level_pass(const MgLevelDev* __restrict__ lv, int ncol, int k,
+                                                      int from_zero, int into_t) {
+  const MgLevelDev& L = lv[blockIdx.y];
+  if (!L.active) return;
+  const double b = L.lmax, a = L.lmax / MG_RANGE;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+  double c1 = 0.0, c2 = 1.0 / theta;
+  double rho = 1.0 / sigma;
+  for (int j = 1; j <= k; ++j) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c1 = rn * rho;
+    c2 = 2.0 * rn / delta;
+    rho = rn;
+  }
+  const bool first = MODE == 0 && from_zero && k == 0;
+  const auto* ptr = gbl(L.a_ptr);
+  const auto* col = gbl(L.a_col);
+  const auto* val = gbl(L.a_val);
+  const auto* dinv = gbl(L.dinv);
+  const auto* r = gbl((const double*)L.r);
+  const auto* zin = gbl((const double*)(MODE == 1 || into_t ? L.z : L.t));
+  auto* zout = gblw(MODE == 1 || into_t ? L.t : L.z);
+  auto* dd = gblw(L.d);
+  const int c0 = (int)(threadIdx.x % LN) * V;
+  const bool act = c0 < ncol;
+  for (int64_t i = ((int64_t)blockIdx.x * NT + threadIdx.x) / LN; i < L.N; i += (int64_t)gridDim.x * NT / LN) {
+    if (!act) continue;
+    double y[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) y[v] = 0.0;
+    if (!first) {
+      const int beg = ptr[i], end = ptr[i + 1];
+      if (end > beg) row_gather_v<V, false>(col, val, beg, end, 1, zin, zin, ncol, c0, y);
+    }
+    const int64_t e = i * ncol + c0;
+    double rv[V];
+    load_vals<V>(r + e, rv);
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) zout[e + v] = rv[v] - y[v];
+    } else {
+      const double di = dinv[i];
+      double dv[V], zv[V];
+      if (k > 0) load_vals<V>(dd + e, dv);
+      if (!first) load_vals<V>(zin + e, zv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double dn = (k > 0 ? c1 * dv[v] : 0.0) + c2 * di * (rv[v] - y[v]);
+        dd[e + v] = dn;
+        zout[e + v] = first ? dn : zv[v] + dn;
+      }
+    }
+  }
+}
+
+template <int MODE>
+static void coarse_pass(const MgDev& mg, int l, int ni, int ncol, int k, int from_zero, int into_t, hipStream_t s) {
+  auto go = [&](auto kern, int ln) {
+    hipLaunchKernelGGL(kern, dim3(nblocks(mg.max_n[l] * ln, NT, 16384), ni), dim3(NT), 0, s, mg.lv[l], ncol, k,
+                       from_zero, into_t);
+  };
+  if (ncol >= 16 && ncol % 4 == 0) {
+    if (ncol > 32) go(k_mg_level_pass<MODE, 4, 16>, 16);
+    else if (ncol > 16) go(k_mg_level_pass<MODE, 4, 8>, 8);
+    else go(k_mg_level_pass<MODE, 4, 4>, 4);
+  } else if (ncol <= 1) go(k_mg_level_pass<MODE, 1, 1>, 1);
+  else if (ncol <= 2) go(k_mg_level_pass<MODE, 1, 2>, 2);
+  else if (ncol <= 4) go(k_mg_level_pass<MODE, 1, 4>, 4);
+  else if (ncol <= 8) go(k_mg_level_pass<MODE, 1, 8>, 8);
+  else if (ncol <= 16) go(k_mg_level_pass<MODE, 1, 16>, 16);
+  else if (ncol <= 32) go(k_mg_level_pass<MODE, 1, 32>, 32);
+  else go(k_mg_level_pass<MODE, 1, 64>, 64);
 }
 
 static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, const MgLevel0Ops& ops, hipStream_t s) {
-  if (l == 0 && ops.cheb0 && mg.nu >= 2) {  // fused into the level-0 operator passes
+  if (l == 0) {  // fused into the level-0 operator passes (degree mg.nu >= 2)
     if (from_zero) {
       ops.cheb0(s);                                   // steps 0 and 1
       for (int k = 2; k < mg.nu; ++k) ops.cheb(k, false, s);
@@ -385,11 +411,10 @@ static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, con
     }
     return;
   }
-  for (int k = 0; k < mg.nu; ++k) {
-    if (!(from_zero && k == 0)) level_spmv(mg, l, ni, ncol, ops, s);
-    hipLaunchKernelGGL(k_mg_cheb, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], ncol, k,
-                       from_zero ? 1 : 0);
-  }
+  // coarser levels: Chebyshev degree 2 with the products fused into the
+  // steps; the first step writes t, the second brings the correction back to z
+  coarse_pass<0>(mg, l, ni, ncol, 0, from_zero ? 1 : 0, 1, s);
+  coarse_pass<0>(mg, l, ni, ncol, 1, from_zero ? 1 : 0, 0, s);
 }
 
 void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s) {
@@ -398,9 +423,11 @@ void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgLevel0Ops& ops, hipStr
   const bool wide = ncol >= 16 && ncol % 4 == 0;
   for (int l = 0; l + 1 < nl; ++l) {
     smooth(mg, l, ni, ncol, true, ops, s);
-    const int tres = l == 0 && ops.resid ? 1 : 0;
-    if (tres) ops.resid(s);
-    else level_spmv(mg, l, ni, ncol, ops, s);
+    // the residual r - A z that the restriction reads: the level-0 residual
+    // pass, or the coarse level's fused pass
+    const int tres = 1;
+    if (l > 0) coarse_pass<1>(mg, l, ni, ncol, 0, 0, 1, s);
+    else ops.resid(s);
     if (wide) {
       int cw = 1;
       while (cw * 4 < ncol) cw *= 2;

@@ -64,17 +64,17 @@ struct MgDev {
   float* rf = nullptr;
   MgLevelDev* lv0_double = nullptr;  // device [ni] level-0 records on double / float storage
   MgLevelDev* lv0_float = nullptr;
-  int nu = 2;               // smoothing steps before and after the coarse correction (Chebyshev degree)
+  int nu = 2;               // finest level's smoothing steps before and after the coarse correction (Chebyshev degree)
 };
-// Level-0 passes over the batch (batch arrays): t0 = A z0; and, when set, the
-// smoothing steps fused into the operator pass (nu >= 2): the two steps from
-// zero (z0, d0 from r0), and step k (from the current correction into the
-// other buffer; rz: the last step after the coarse correction, which also
-// accumulates r.z).  The caller keeps the correction in z0 wherever the
-// cycle reads it (residual pass, prolongation).
+// Level-0 passes over the batch (batch arrays): the residual t0 = r0 - A z0
+// that the restriction reads, and the smoothing steps fused into the
+// operator pass (degree nu >= 2): the two steps from zero (z0, d0 from r0),
+// and step k (from the current correction into the other buffer; rz: the
+// last step after the coarse correction, which also accumulates r.z).  The
+// caller keeps the correction in z0 wherever the cycle reads it (residual
+// pass, prolongation).
 struct MgLevel0Ops {
-  std::function<void(hipStream_t s)> spmv;
-  std::function<void(hipStream_t s)> resid;  // optional: t0 = r0 - A z0, the residual the restriction reads
+  std::function<void(hipStream_t s)> resid;
   std::function<void(hipStream_t s)> cheb0;
   std::function<void(int k, bool rz, hipStream_t s)> cheb;
 };

@@ -941,21 +941,6 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s) {
   P.it = k + 1;
 }
 
-// q = K x on the DoF rows (one instance or a batch), p.q partials into the
-// caller's scratch accumulators red_scratch ([ni][RED_SLOTS][ncol]).
-void launch_poisson_apply(const Batch& b, const double* x, double* q, int ncol, double* red_scratch, PoissonWs& P,
-                          hipStream_t s) {
-  PoissonWs Ps = P;
-  Ps.red = red_scratch;
-  const bool rec = P.ev && P.ev_used + 2 <= P.ev_cap;  // timed like the CG's own operator passes
-  if (rec) (void)hipEventRecord(P.ev[P.ev_used], s);
-  launch_spmv_poisson(b, x, x, q, ncol, q, Ps, -1, s);
-  if (rec) {
-    (void)hipEventRecord(P.ev[P.ev_used + 1], s);
-    P.ev_used += 2;
-  }
-}
-
 // Chebyshev smoothing on the finest multigrid level fused into the operator
 // pass (the spmv_store comment gives the updates): the first two steps from
 // zero (z, d from r), and one further step from zin into zout.
@@ -980,11 +965,8 @@ void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, dou
 
 // The same finest-level passes on float storage (Poisson schedule bit 6):
 // operand, residual copy, corrections and directions in float, sums in
-// double.  The operator product of the residual pass is not event-timed
-// (the timing slot holds the double passes of the CG itself).
-void launch_poisson_apply_f(const Batch& b, const float* x, float* q, int ncol, double* red_scratch, hipStream_t s) {
-  launch_spmv_mode<float>(b, x, x, q, ncol, q, red_scratch, SP_PLAIN, -1, s);
-}
+// double.  These passes are not event-timed (the timing slot holds the
+// double passes of the CG itself).
 void launch_mg_cheb0_f(const Batch& b, const float* r, float* z, float* d, double* red, int rz_slot, int ncol,
                        hipStream_t s) {
   launch_spmv_mode<float>(b, r, r, z, ncol, d, red, SP_CHEB0, rz_slot, s);
