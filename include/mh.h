@@ -127,6 +127,12 @@ int mh_mesh_node_coords(const mh_mesh* mesh, double* xyz);
  * boundary nodes).  ptr: int64 [N_h + 1]; col: int64 [hang_nnz]; w: double
  * [hang_nnz].  Any pointer may be NULL to skip it. */
 int mh_mesh_constraints(const mh_mesh* mesh, int64_t* ptr, int64_t* col, double* w);
+/* Host: the leaves in library order (Morton order of the octree, Sec. III.A).
+ * nodes: int32 [n_cells][(p+1)^3], the library index of each cell-local
+ * Gauss-Lobatto node (a, b, c) at (c (p+1) + b) (p+1) + a, x fastest;
+ * level: int32 [n_cells] refinement level (edge = (hi - lo) / n_coarse / 2^level);
+ * origin: double [n_cells][3] lower corner.  Any pointer may be NULL. */
+int mh_mesh_cells(const mh_mesh* mesh, int32_t* nodes, int32_t* level, double* origin);
 int mh_mesh_destroy(mh_mesh* mesh);
 
 /* Molecule and operator settings. */

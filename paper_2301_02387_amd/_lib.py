@@ -87,6 +87,7 @@ def load_library():
     lib.mh_mesh_info_get.argtypes = [vp, C.POINTER(_MeshInfo)]
     lib.mh_mesh_node_coords.argtypes = [vp, vp]
     lib.mh_mesh_constraints.argtypes = [vp, vp, vp, vp]
+    lib.mh_mesh_cells.argtypes = [vp, vp, vp, vp]
     lib.mh_mesh_destroy.argtypes = [vp]
     lib.mh_op_create.argtypes = [vp, C.POINTER(_OpDesc), vp, C.POINTER(vp)]
     lib.mh_op_destroy.argtypes = [vp]
@@ -213,6 +214,16 @@ class Mesh:
         out = np.zeros((self.info["n_full"], 3))
         _check(_lib.mh_mesh_node_coords(self._h, out.ctypes.data_as(C.c_void_p)))
         return out
+
+    def cells(self):
+        """(nodes [n_cells][(p+1)^3] int32, level [n_cells] int32, origin [n_cells][3]) in library order."""
+        nc, P3 = self.info["n_cells"], (self.info["p"] + 1) ** 3
+        nodes = np.zeros((nc, P3), dtype=np.int32)
+        level = np.zeros(nc, dtype=np.int32)
+        origin = np.zeros((nc, 3))
+        _check(_lib.mh_mesh_cells(self._h, nodes.ctypes.data_as(C.c_void_p), level.ctypes.data_as(C.c_void_p),
+                                  origin.ctypes.data_as(C.c_void_p)))
+        return nodes, level, origin
 
     def constraints(self):
         nh, nnz = self.info["n_hang"], self.info["hang_nnz"]

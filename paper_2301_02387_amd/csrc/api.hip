@@ -282,6 +282,15 @@ extern "C" int mh_mesh_constraints(const mh_mesh* mesh, int64_t* ptr, int64_t* c
   return MH_OK;
 }
 
+extern "C" int mh_mesh_cells(const mh_mesh* mesh, int32_t* nodes, int32_t* level, double* origin) {
+  if (!mesh) return fail(MH_INVALID_ARG, "null argument");
+  const Mesh& M = mesh->M;
+  if (nodes) std::memcpy(nodes, M.cell_nodes.data(), M.cell_nodes.size() * sizeof(int32_t));
+  if (level) std::memcpy(level, M.cell_level.data(), M.cell_level.size() * sizeof(int32_t));
+  if (origin) std::memcpy(origin, M.cell_org.data(), M.cell_org.size() * sizeof(double));
+  return MH_OK;
+}
+
 extern "C" int mh_mesh_destroy(mh_mesh* mesh) {
   delete mesh;
   return MH_OK;

@@ -53,6 +53,32 @@ def test_mesh_equals_oracle(name):
             assert abs(mine[k] - v) < 1e-14
 
 
+@pytest.mark.parametrize("name", ["tiny_q3", "kelly_q2"])
+def test_mesh_cells(name):
+    """mh_mesh_cells: each cell's local node (a, b, c) sits at origin + edge
+    (xi + 1) / 2 of the Gauss-Lobatto points, x fastest; every full node
+    belongs to a cell; the leaves are the oracle's (same levels and corners)."""
+    mh, _ = _lib()
+    from oracle.gll import gll
+    w, om, ops = case(name)
+    M = mh.Mesh.from_workload(w)
+    nodes, level, origin = M.cells()
+    p = M.info["p"]
+    xi, _ = gll(p)
+    H = (w["hi"] - w["lo"]) / w["n_coarse"]
+    edge = H / 2.0 ** level
+    xyz = M.coords()
+    t = (xi + 1.0) / 2.0
+    loc = np.array([(t[a], t[b], t[c]) for c in range(p + 1) for b in range(p + 1) for a in range(p + 1)])
+    want = origin[:, None, :] + edge[:, None, None] * loc[None, :, :]
+    assert np.abs(xyz[nodes] - want).max() < 1e-12
+    assert len(np.unique(nodes)) == M.info["n_full"]
+    key = lambda l, o: (int(l),) + tuple(int(round(v * 1e6)) for v in o)  # noqa: E731
+    lib_cells = sorted(key(l, o) for l, o in zip(level, origin))
+    or_cells = sorted(key(l, [w["lo"] + H / 2.0 ** l * v for v in (i, j, k)]) for l, i, j, k in om.cells)
+    assert lib_cells == or_cells
+
+
 @pytest.mark.parametrize("p,tol", [(1, 0.05), (2, 0.02), (3, 0.02)])
 def test_kelly_mesh_equals_oracle(p, tol):
     """The water nuclei's Kelly refinement (Sec. III.A) in the library and in
