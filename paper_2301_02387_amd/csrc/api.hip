@@ -120,6 +120,7 @@ struct mh_op {
   // multigrid preconditioner of the Poisson solves (built on first use)
   std::unique_ptr<MgDev> mg;
   double* mg_red = nullptr;   // scratch accumulators of the level-0 operator passes
+  int* cg_done = nullptr;     // [ni] convergence flags of a batch's multigrid CG (zero outside it)
   double* mg_part = nullptr;  // r.z partials
   int mg_levels = 0;
   int cg_hint = 0;            // iterations of the last multigrid-preconditioned solve
@@ -906,6 +907,13 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
       rho = rn;
     }
   }
+  // convergence flags of a batch's CG: every CG and multigrid launch of an
+  // instance returns at once while its flag is set (batches only)
+  if (ni > 1) {
+    op->cg_done = op->alloc<int>(ni);
+    HIPCHK(hipMemsetAsync(op->cg_done, 0, ni * sizeof(int), s));
+    for (int i = 0; i < ni; ++i) op->dh[i].cg_done = op->cg_done + i;
+  }
   upload_instances(op, s);
   std::vector<std::vector<MgLevelDev>> rec(nlev, std::vector<MgLevelDev>(ni));
   std::vector<MgLevelDev> co(ni);
@@ -943,6 +951,7 @@ static void ensure_mg(mh_op* op, hipStream_t s) {
         L.t = op->alloc<double>(len);
       }
       L.lmax = h.lmax;
+      L.done = op->cg_done ? op->cg_done + i : nullptr;
       if (L.active) {
         L.p_ptr = op->upload(h.p_ptr, s);
         L.p_col = op->upload(h.p_col, s);
@@ -1044,6 +1053,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     if (!fused) mg_rz(B.dm, ni, ncol, P.r, z, op->mg_part, P.red, rz_slot, s);
   };
   P.it = 0;
+  if (op->cg_done) launch_zero_int(op->cg_done, ni, s);  // batch convergence flags start clear
   int conv = fixed > 0 ? 0 : poisson_converged(op, s);
   int k = 0;
   const int check_from = op->cg_hint - 2;
@@ -1063,6 +1073,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
              RED_RR + k % 2, s);
     launch_cg_apply_plain(B, P, pcur, k, s);
     launch_cg_update(B, W, P, pcur, k, s, f32 ? mg.rf : nullptr);
+    if (op->cg_done) launch_cg_done(B, P, k, op->rtol, s);  // converged instances skip the rest
     ++k;
     P.it = k;
     if (fixed > 0) {
@@ -1073,6 +1084,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     if (conv != 0) break;
     precondition(k);
   }
+  if (op->cg_done) launch_zero_int(op->cg_done, ni, s);  // no flag outside the CG
   if (iters) *iters = k;
   if (fixed == 0) op->cg_hint = k;
   return conv;

@@ -23,6 +23,9 @@ namespace mh {
 constexpr int MG_MAX_DEG = 5;
 
 struct DevMesh {
+  // this instance's convergence flag in a batch's multigrid CG (nonzero: the
+  // CG and multigrid launches skip the instance); zero outside the CG
+  const int* cg_done = nullptr;
   int P = 0, n = 0;                // nodes per cell edge, orbitals
   int inst = 0;                    // instance index (== blockIdx.y of its workgroups)
   int64_t nC = 0, N = 0, NE = 0, NF = 0, Nh = 0, Nb = 0, nMa = 0;
@@ -216,6 +219,11 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s);
 // slot RED_PQ + k % 2, and the update pass (alpha_k = red[RED_RZ + k % 3] / p.q).
 void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k, hipStream_t s);
 // rf (may be null): a float copy of the updated residual (Poisson schedule bit 6)
+// Batch CG convergence flags (DevMesh::cg_done, device int [ni]): set an
+// instance's flag once every column's r.r after iteration k is at most
+// rtol^2 times its largest column's b.b; clear all flags.
+void launch_cg_done(const Batch& b, const PoissonWs& P, int k, double rtol, hipStream_t s);
+void launch_zero_int(int* x, int n, hipStream_t s);
 void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s,
                       float* rf = nullptr);
 void launch_to_float(const double* x, float* y, int64_t nd, hipStream_t s);

@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(NT) k_mg_restrict(const MgLevelDev* __restrict
                                                     const MgLevelDev* __restrict__ coarse, int ncol, int cw,
                                                     int tres) {
   const MgLevelDev& F = fine[blockIdx.y];
-  if (!F.active) return;
+  if (!F.active || (F.done && *F.done)) return;
   const MgLevelDev& C = coarse[blockIdx.y];
   const auto* ptr = gbl(F.r_ptr);
   const auto* col = gbl(F.r_col);
@@ -161,7 +161,7 @@ template <int V, bool TRES>
 __global__ void __launch_bounds__(NT) k_mg_restrict_v(const MgLevelDev* __restrict__ fine,
                                                       const MgLevelDev* __restrict__ coarse, int ncol, int cw) {
   const MgLevelDev& F = fine[blockIdx.y];
-  if (!F.active) return;
+  if (!F.active || (F.done && *F.done)) return;
   const MgLevelDev& C = coarse[blockIdx.y];
   const auto* ptr = gbl(F.r_ptr);
   const auto* col = gbl(F.r_col);
@@ -205,7 +205,7 @@ template <int V, int L>
 __global__ void __launch_bounds__(NT) k_mg_prolong_v(const MgLevelDev* __restrict__ fine,
                                                      const MgLevelDev* __restrict__ coarse, int ncol) {
   const MgLevelDev& F = fine[blockIdx.y];
-  if (!F.active) return;
+  if (!F.active || (F.done && *F.done)) return;
   const MgLevelDev& C = coarse[blockIdx.y];
   const auto* ptr = gbl(F.p_ptr);
   const auto* col = gbl(F.p_col);
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(NT) k_mg_prolong_v(const MgLevelDev* __restric
 __global__ void __launch_bounds__(NT) k_mg_prolong(const MgLevelDev* __restrict__ fine,
                                                    const MgLevelDev* __restrict__ coarse, int ncol) {
   const MgLevelDev& F = fine[blockIdx.y];
-  if (!F.active) return;
+  if (!F.active || (F.done && *F.done)) return;
   const MgLevelDev& C = coarse[blockIdx.y];
   const int64_t total = F.N * ncol;
   const auto* ptr = gbl(F.p_ptr);
@@ -268,6 +268,7 @@ __global__ void __launch_bounds__(NT) k_mg_prolong(const MgLevelDev* __restrict_
 // per (row, block of 8 columns), the lanes splitting the row's entries
 __global__ void __launch_bounds__(NT) k_mg_coarse(const MgLevelDev* __restrict__ co, int ncol) {
   const MgLevelDev& L = co[blockIdx.y];
+  if (L.done && *L.done) return;
   const int64_t n = L.N;
   const auto* Ainv = gbl(L.cinv);
   const auto* r = gbl((const double*)L.r);
@@ -330,7 +331,7 @@ template <int MODE, int V, int LN>
 __global__ void __launch_bounds__(NT) k_mg_level_pass(const MgLevelDev* __restrict__ lv, int ncol, int k,
                                                       int from_zero, int into_t) {
   const MgLevelDev& L = lv[blockIdx.y];
-  if (!L.active) return;
+  if (!L.active || (L.done && *L.done)) return;
   const double b = L.lmax, a = L.lmax / MG_RANGE;
   const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
   double c1 = 0.0, c2 = 1.0 / theta;
@@ -504,6 +505,7 @@ __global__ void __launch_bounds__(NT) k_mg_dir(const DevMesh* __restrict__ dm, i
                                                const double* __restrict__ pprev, double* __restrict__ pcur,
                                                double* __restrict__ red, int rz_cur, int rz_prev, int rr_clear) {
   INSTANCE;
+  if (d.cg_done && *d.cg_done) return;  // converged instance of a batch CG
   __shared__ double beta[64];
   red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
   if (threadIdx.x < (unsigned)ncol) {

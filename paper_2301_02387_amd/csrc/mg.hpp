@@ -37,6 +37,7 @@ struct MgLevelDev {
   // level 0 on float storage (Poisson schedule bit 6): the residual copy, the
   // correction and the operator product the transfers read and write
   int f32 = 0;
+  const int* done = nullptr;  // the instance's CG convergence flag (nonzero: skip)
   const float* rf = nullptr;
   float* zf = nullptr;
   float* tf = nullptr;

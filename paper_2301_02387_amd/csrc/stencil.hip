@@ -495,6 +495,7 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
                                                      double* __restrict__ red, int k) {
   constexpr bool FUSE = MODE == SP_CG;
   INSTANCE;
+  if (d.cg_done && *d.cg_done) return;  // converged instance of a batch CG
   __shared__ double lds[NT * V];
   // column block: blockIdx.z, or with schedule bit 7 the XCD's (xcd_sweep_cols;
   // the grid then runs all column blocks along x)
@@ -749,6 +750,7 @@ __global__ void __launch_bounds__(NT) k_cg_update2(const DevMesh* __restrict__ d
                                                    const double* __restrict__ q, int ncol, double* __restrict__ red,
                                                    int k, float* __restrict__ rf) {
   INSTANCE;
+  if (d.cg_done && *d.cg_done) return;
   __shared__ double lds[2 * NT];
   x += d.oF * ncol;
   if (rf) rf += d.oE * ncol;
@@ -982,6 +984,39 @@ void launch_mg_cheb_step_f(const Batch& b, const float* zin, const float* r, flo
 void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k, hipStream_t s) {
   cg_apply2(b, P, p, p, const_cast<double*>(p), P.q, -2 - k, s);
 }
+// Convergence flags of a batch's multigrid CG (the host test of the same
+// solve, on the device): after the update pass of iteration k an instance is
+// done once every column's r.r is at most rtol^2 times its largest column's
+// b.b.  Its r.r is then copied into the other r.r slot as well, so the final
+// test reads a converged value whichever iteration the solve stops after,
+// and its later CG and multigrid launches return at once.  One wave per
+// instance (ncol <= 64).
+__global__ void k_cg_done(const DevMesh* __restrict__ dm, const double* __restrict__ sc, double* __restrict__ red,
+                          int ncol, int k, double rtol2) {
+  INSTANCE;
+  if (!d.cg_done || *d.cg_done) return;
+  sc += (int64_t)blockIdx.y * 8 * ncol;
+  red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
+  const int c = threadIdx.x;
+  double bb = c < ncol ? sc[SC_BB * ncol + c] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) bb = fmax(bb, __shfl_xor(bb, off, 64));
+  const double rr = c < ncol ? red[(RED_RR + k % 2) * ncol + c] : 0.0;
+  const bool ok = c >= ncol || rr <= rtol2 * bb;
+  if (__all(ok)) {
+    if (c < ncol) red[(RED_RR + (k + 1) % 2) * ncol + c] = rr;
+    if (c == 0) *const_cast<int*>(d.cg_done) = 1;
+  }
+}
+void launch_cg_done(const Batch& b, const PoissonWs& P, int k, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_done, dim3(1, b.ni), dim3(64), 0, s, b.dm, P.sc, P.red, P.ncol, k, rtol * rtol);
+}
+__global__ void k_zero_int(int* __restrict__ x, int n) {
+  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) x[i] = 0;
+}
+void launch_zero_int(int* x, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_zero_int, dim3(nblocks(n)), dim3(NT), 0, s, x, n);
+}
+
 void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s, float* rf) {
   const int nb = cg_blocks(b, P.ncol);
   hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, p, P.q, P.ncol, P.red, k, rf);
