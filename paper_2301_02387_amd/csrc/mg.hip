@@ -420,8 +420,11 @@ static void smooth(const MgDev& mg, int l, int ni, int ncol, bool from_zero, con
 
 void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgLevel0Ops& ops, hipStream_t s) {
   const int nl = mg.nlev;
-  // 4 columns per lane in the transfers for 16 or more columns (multiples of 4)
+  // 4 columns per lane in the transfers when the column count is a multiple of
+  // 4: for the restriction from 16 columns on (at 4 columns its 64 lane groups
+  // spend more on combining than they gain), for the prolongation from 4 on
   const bool wide = ncol >= 16 && ncol % 4 == 0;
+  const bool wide_p = ncol % 4 == 0;
   for (int l = 0; l + 1 < nl; ++l) {
     smooth(mg, l, ni, ncol, true, ops, s);
     // the residual r - A z that the restriction reads: the level-0 residual
@@ -445,14 +448,17 @@ void mg_vcycle(const MgDev& mg, int ni, int ncol, const MgLevel0Ops& ops, hipStr
   hipLaunchKernelGGL(k_mg_coarse, dim3(nblocks(mg.max_coarse * ((ncol + 7) / 8) * 64, NT, 4096), ni), dim3(NT), 0, s,
                      mg.coarse, ncol);
   for (int l = nl - 2; l >= 0; --l) {
-    if (wide && ncol > 32)
+    if (wide_p && ncol > 32)
       hipLaunchKernelGGL((k_mg_prolong_v<4, 16>), dim3(xcd_grid(mg.max_n[l], NT / 16, 16384), ni), dim3(NT), 0, s,
                          mg.lv[l], mg.lv[l + 1], ncol);
-    else if (wide && ncol > 16)
+    else if (wide_p && ncol > 16)
       hipLaunchKernelGGL((k_mg_prolong_v<4, 8>), dim3(xcd_grid(mg.max_n[l], NT / 8, 16384), ni), dim3(NT), 0, s,
                          mg.lv[l], mg.lv[l + 1], ncol);
-    else if (wide)
+    else if (wide_p && ncol > 4)
       hipLaunchKernelGGL((k_mg_prolong_v<4, 4>), dim3(xcd_grid(mg.max_n[l], NT / 4, 16384), ni), dim3(NT), 0, s,
+                         mg.lv[l], mg.lv[l + 1], ncol);
+    else if (wide_p)
+      hipLaunchKernelGGL((k_mg_prolong_v<4, 1>), dim3(xcd_grid(mg.max_n[l], NT, 16384), ni), dim3(NT), 0, s,
                          mg.lv[l], mg.lv[l + 1], ncol);
     else
       hipLaunchKernelGGL(k_mg_prolong, level_grid(mg.max_n[l], ncol, ni), dim3(NT), 0, s, mg.lv[l], mg.lv[l + 1],
