@@ -496,11 +496,10 @@ std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ba
 
   // ---- breadth-first cell order (Cuthill-McKee on cells sharing a node) -------
   // Starting from the first Morton cell (a box corner), cells are visited
-  // level set by level set, and nodes are renumbered by first touch in that
-  // order.  Every line neighbour of a node then lies within about one level
-  // set of it in index space, so operator passes that walk the nodes in order
-  // reuse each row from cache instead of re-fetching it (Morton order makes
-  // long jumps between octants).
+  // level set by level set, so cells that share nodes sit near each other in
+  // the cell order (the node-centric passes read the data of a node's
+  // incident cells).  The nodes get a provisional first-touch numbering here;
+  // the library numbering below orders them by position.
   {
     const int P3 = P * P * P;
     std::vector<int64_t> cptr(nF + 1, 0), cidx((size_t)nC * P3);
@@ -676,12 +675,41 @@ std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ba
   // lie on the same boundary face): zero for orbitals, the interpolated
   // boundary value for the Poisson potentials.
 
-  // ---- library numbering: DoFs, hanging, boundary (first-touch order) ------
+  // ---- library numbering: DoFs, hanging, boundary -----------------------------
+  // Each group in the Morton order of the node positions (21 bits per axis
+  // over the box).  A node's line neighbours in every incident cell are then
+  // near it in index space for all but the few entries that cross a Morton
+  // jump (H2O: 90 % of the operator entries within 1,500 rows, against 90,000
+  // in the first-touch order of the breadth-first cell visit), so a pass that
+  // walks the rows in order finds the rows it gathers in cache.
   std::vector<int64_t> lib(nF, -1);
   int64_t N = 0, Nh = 0, Nb = 0;
-  for (int64_t n = 0; n < nF; ++n) if (!is_hang[n] && !is_bnd[n]) lib[n] = N++;
-  for (int64_t n = 0; n < nF; ++n) if (is_hang[n]) lib[n] = N + Nh++;
-  for (int64_t n = 0; n < nF; ++n) if (!is_hang[n] && is_bnd[n]) lib[n] = N + Nh + Nb++;
+  {
+    auto group = [&](int64_t n) { return is_hang[n] ? 1 : (is_bnd[n] ? 2 : 0); };
+    std::vector<uint64_t> code(nF);
+    const double scale = std::ldexp(1.0, 21) / nc;   // key_t is in coarse-cell units, 0 .. nc
+    for (int64_t n = 0; n < nF; ++n) {
+      uint64_t q[3];
+      for (int d = 0; d < 3; ++d) {
+        const double t = key_t(keys[n].k[d]) * scale;
+        q[d] = t <= 0.0 ? 0 : std::min<uint64_t>((uint64_t)t, (1ull << 21) - 1);
+      }
+      code[n] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    }
+    std::vector<int64_t> idx(nF);
+    for (int64_t n = 0; n < nF; ++n) idx[n] = n;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+      const int ga = group(a), gb = group(b);
+      return ga != gb ? ga < gb : code[a] < code[b];
+    });
+    for (int64_t k = 0; k < nF; ++k) lib[idx[k]] = k;
+    for (int64_t n = 0; n < nF; ++n) {
+      const int g = group(n);
+      if (g == 0) ++N;
+      else if (g == 1) ++Nh;
+      else ++Nb;
+    }
+  }
   M.nF = nF; M.N = N; M.Nh = Nh; M.Nb = Nb;
   M.cell_nodes.resize(tmp_nodes.size());
   for (size_t t = 0; t < tmp_nodes.size(); ++t) M.cell_nodes[t] = (int32_t)lib[tmp_nodes[t]];
