@@ -16,6 +16,7 @@ mesh     octree refinement, 2:1 balance, full nodes, hanging-node
          constraints and DoF numbering (Sec. III.A, "bridged functions").
 fem      mass, stiffness, lumped nuclear potential, dipole and H1 matrices
          (Sec. III.A, Eq. discretized_eom and the GLL quadrature rule).
+ecs      exterior complex scaling of the one-body operator (Sec. IV).
 poisson  pair densities, multipole boundary values and the Poisson solve
          for the mean-field potentials (Sec. III.A, Poisson equation + BC).
 ci       determinant strings, sigma vector, RDMs, CI Hamiltonian (Sec. II).

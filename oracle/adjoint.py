@@ -65,6 +65,8 @@ class DenseModel:
     """The oracle's operators of one mesh and CI space as dense torch tensors."""
 
     def __init__(self, ops, cispace):
+        if getattr(ops, "ecs", None) is not None or ops.gauge != "length":
+            raise ValueError("the dense model is the length-gauge operator without complex scaling")
         mesh = ops.mesh
         self.ops, self.ci = ops, cispace
         self.n = cispace.n

@@ -23,6 +23,11 @@ parts of the Gauss-Lobatto rule), and S_e = sum_d e_d S_d along the field
 direction e.  The A^2/2 term of the minimal coupling is dropped: it is a
 constant in space and only adds a phase and N A^2/2 to the energy.
 
+With exterior complex scaling (``ecs``: theta and the inner cuboid) every
+cell integral above takes the contour's factors: the mass J, the stiffness
+along d J / eta_d^2, the derivative along d J / eta_d, the potential
+V(z(x)) J and the field e.z(x) J; ``ecs`` states the readings.
+
 v is the lumped nuclear potential: v_i = sum_cells int_cell f_i V_nuc, the
 row sum of the exact Galerkin potential matrix.  With a nucleus on a mesh
 node, the Gauss-Lobatto value m_i V(x_i) is infinite; the lumped integral is
@@ -45,39 +50,50 @@ def local_index(P):
     return np.array([(a, b, c) for c in range(P) for b in range(P) for a in range(P)])
 
 
-def full_mass(mesh):
+def full_mass(mesh, J=None):
+    """m_i = sum over cells holding node i of J (h/2)^3 w_a w_b w_c (J = 1
+    without complex scaling, else the cell's volume factor [n_cells])."""
     P = mesh.P
     _, w, _, _ = operators_1d(mesh.p)
     loc = local_index(P)
     wloc = w[loc[:, 0]] * w[loc[:, 1]] * w[loc[:, 2]]
     hc = mesh.cell_h()
-    m = np.zeros(mesh.n_full)
-    np.add.at(m, mesh.cell_nodes, (hc[:, None] / 2.0) ** 3 * wloc[None, :])
+    cw = (hc[:, None] / 2.0) ** 3 * wloc[None, :]
+    if J is None:
+        m = np.zeros(mesh.n_full)
+    else:
+        m = np.zeros(mesh.n_full, dtype=complex)
+        cw = cw * J[:, None]
+    np.add.at(m, mesh.cell_nodes, cw)
     return m
 
 
-def full_stiffness(mesh):
-    """K_full = sum over cells of (h/2)(A x W x W + W x A x W + W x W x A)."""
+def full_stiffness(mesh, fac=None):
+    """K_full = sum over cells of (h/2)(A x W x W + W x A x W + W x W x A);
+    fac [n_cells, 3] (complex scaling) multiplies each cell's part along x,
+    y and z."""
     P = mesh.P
     _, w, _, A = operators_1d(mesh.p)
     loc = local_index(P)
-    rows, cols, vals = [], [], []
+    rows, cols, vals, dirs = [], [], [], []
     for i, (a, b, c) in enumerate(loc):
         for a2 in range(P):
             j = a2 + P * (b + P * c)
-            rows.append(i); cols.append(j); vals.append(A[a, a2] * w[b] * w[c])
+            rows.append(i); cols.append(j); vals.append(A[a, a2] * w[b] * w[c]); dirs.append(0)
         for b2 in range(P):
             j = a + P * (b2 + P * c)
-            rows.append(i); cols.append(j); vals.append(w[a] * A[b, b2] * w[c])
+            rows.append(i); cols.append(j); vals.append(w[a] * A[b, b2] * w[c]); dirs.append(1)
         for c2 in range(P):
             j = a + P * (b + P * c2)
-            rows.append(i); cols.append(j); vals.append(w[a] * w[b] * A[c, c2])
-    rows, cols, vals = map(np.array, (rows, cols, vals))
+            rows.append(i); cols.append(j); vals.append(w[a] * w[b] * A[c, c2]); dirs.append(2)
+    rows, cols, vals, dirs = map(np.array, (rows, cols, vals, dirs))
     hc = mesh.cell_h()
     R = mesh.cell_nodes[:, rows].ravel()
     Cc = mesh.cell_nodes[:, cols].ravel()
-    V = ((hc[:, None] / 2.0) * vals[None, :]).ravel()
-    return sp.csr_matrix((V, (R, Cc)), shape=(mesh.n_full, mesh.n_full))
+    V = (hc[:, None] / 2.0) * vals[None, :]
+    if fac is not None:
+        V = V * fac[:, dirs]
+    return sp.csr_matrix((V.ravel(), (R, Cc)), shape=(mesh.n_full, mesh.n_full))
 
 
 def _gauss(n):
@@ -85,23 +101,29 @@ def _gauss(n):
     return (x + 1.0) / 2.0, w / 2.0          # on [0, 1]
 
 
-def _regular_cells(mesh, Z, R, cells, q):
-    """int_cell f_i(x) (-Z/|x-R|) dx by tensor Gauss-Legendre, q points/dim."""
+def _regular_cells(mesh, Z, R, cells, q, ecs=None, J=None):
+    """int_cell f_i(x) (-Z/|x-R|) dx by tensor Gauss-Legendre, q points/dim;
+    with complex scaling, int_cell f_i(x) (-Z/r(z(x))) J dx, r the principal
+    square root of sum_d (z_d - R_d)^2."""
     P = mesh.P
     g, gw = _gauss(q)
     Lg = lagrange_eval(mesh.xi, 2.0 * g - 1.0)           # [P, q]
     hc = mesh.cell_h()[cells]
     org = mesh.cell_origin()[cells]
-    out = np.zeros((len(cells), P, P, P))
+    out = np.zeros((len(cells), P, P, P), dtype=float if ecs is None else complex)
     for s in range(0, len(cells), 4096):
         hh = hc[s:s + 4096]
         oo = org[s:s + 4096]
         X = oo[:, 0, None] + hh[:, None] * g[None, :]
         Y = oo[:, 1, None] + hh[:, None] * g[None, :]
         Zc = oo[:, 2, None] + hh[:, None] * g[None, :]
+        if ecs is not None:
+            X, Y, Zc = ecs.contour(X, 0), ecs.contour(Y, 1), ecs.contour(Zc, 2)
         r = np.sqrt((X[:, :, None, None] - R[0]) ** 2 + (Y[:, None, :, None] - R[1]) ** 2
                     + (Zc[:, None, None, :] - R[2]) ** 2)
         f = -Z / r * (gw[:, None, None] * gw[None, :, None] * gw[None, None, :])
+        if ecs is not None:
+            f = f * J[cells[s:s + 4096], None, None, None]
         t = np.einsum('aq,cqrs->cars', Lg, f)
         t = np.einsum('br,cars->cabs', Lg, t)
         t = np.einsum('cs,nabs->nabc', Lg, t)
@@ -110,16 +132,18 @@ def _regular_cells(mesh, Z, R, cells, q):
     return out.transpose(0, 3, 2, 1).reshape(len(cells), P ** 3)
 
 
-def duffy_cell(mesh, Z, R, origin, h, n=DUFFY_POINTS):
+def duffy_cell(mesh, Z, R, origin, h, n=DUFFY_POINTS, ecs=None, J=1.0):
     """int_cell f_i(x) (-Z/|x-R|) dx with R in the closed cell.
 
     The cube is split into six pyramids with apex R and a face as base;
     x = R + s (F(u,v) - R) gives dx = s^2 d h^2 ds du dv (d = apex height), so
     the 1/|x-R| singularity cancels.  Pyramids of zero height are skipped.
+    With complex scaling the integrand is -Z J / r(z(x)): the real rule's
+    weights times J |x - R| / r(z(x)).
     """
     P = mesh.P
     g, gw = _gauss(n)
-    out = np.zeros((P, P, P))
+    out = np.zeros((P, P, P), dtype=float if ecs is None else complex)
     for d in range(3):
         d1, d2 = [e for e in range(3) if e != d]
         for side in (0, 1):
@@ -140,13 +164,18 @@ def duffy_cell(mesh, Z, R, origin, h, n=DUFFY_POINTS):
             Lz = lagrange_eval(mesh.xi, xi[..., 2].ravel()).reshape(P, n, n, n)
             wt = (gw[:, None, None] * gw[None, :, None] * gw[None, None, :]
                   * g[:, None, None] * height * h * h * (-Z) / dist[None, :, :])
+            if ecs is not None:
+                rz = np.sqrt(sum((ecs.contour(X[..., k], k) - R[k]) ** 2 for k in range(3)))
+                wt = wt * J * np.linalg.norm(X - np.asarray(R), axis=-1) / rz
             out += np.einsum('asuv,bsuv,csuv,suv->abc', Lx, Ly, Lz, wt)
     return out.transpose(2, 1, 0).reshape(P ** 3)
 
 
-def nuclear_lumped(mesh, nuclei):
-    """v_i = sum_cells int_cell f_i V_nuc with V_nuc = -sum_a Z_a/|x - R_a|."""
-    v = np.zeros(mesh.n_full)
+def nuclear_lumped(mesh, nuclei, ecs=None):
+    """v_i = sum_cells int_cell f_i V_nuc with V_nuc = -sum_a Z_a/|x - R_a|
+    (with complex scaling: V_nuc(z(x)) J)."""
+    J = None if ecs is None else np.prod(ecs.cell_eta(mesh), axis=1)
+    v = np.zeros(mesh.n_full, dtype=float if ecs is None else complex)
     hc = mesh.cell_h()
     org = mesh.cell_origin()
     q = mesh.p + 5
@@ -155,18 +184,22 @@ def nuclear_lumped(mesh, nuclei):
         tol = 1e-12 * hc
         inside = np.all((R[None, :] >= org - tol[:, None]) & (R[None, :] <= org + hc[:, None] + tol[:, None]), axis=1)
         reg = np.nonzero(~inside)[0]
-        vals = _regular_cells(mesh, Z, R, reg, q)
+        vals = _regular_cells(mesh, Z, R, reg, q, ecs, J)
         np.add.at(v, mesh.cell_nodes[reg], vals)
         for c in np.nonzero(inside)[0]:
-            np.add.at(v, mesh.cell_nodes[c], duffy_cell(mesh, Z, R, org[c], hc[c]))
+            if ecs is None:
+                np.add.at(v, mesh.cell_nodes[c], duffy_cell(mesh, Z, R, org[c], hc[c]))
+            else:
+                np.add.at(v, mesh.cell_nodes[c], duffy_cell(mesh, Z, R, org[c], hc[c], ecs=ecs, J=J[c]))
     return v
 
 
-def full_gradient(mesh):
+def full_gradient(mesh, fac=None):
     """[D_x, D_y, D_z] on the full nodes: (D_d)_ij = sum over cells of the
     Gauss-Lobatto quadrature of f_i d f_j / d x_d, i.e. per cell
     (h/2)^2 w_a w_b w_c l'_{a'}(xi_a) for nodes i = (a,b,c), j = (a',b,c)
-    (x direction; likewise along y and z)."""
+    (x direction; likewise along y and z); fac [n_cells, 3] (complex
+    scaling) multiplies each cell's part along d."""
     P = mesh.P
     _, w, D, _ = operators_1d(mesh.p)
     loc = local_index(P)
@@ -184,21 +217,25 @@ def full_gradient(mesh):
         rows, cols, vals = map(np.array, (rows, cols, vals))
         R = mesh.cell_nodes[:, rows].ravel()
         Cc = mesh.cell_nodes[:, cols].ravel()
-        V = ((hc[:, None] / 2.0) ** 2 * vals[None, :]).ravel()
-        out.append(sp.csr_matrix((V, (R, Cc)), shape=(mesh.n_full, mesh.n_full)))
+        V = (hc[:, None] / 2.0) ** 2 * vals[None, :]
+        if fac is not None:
+            V = V * fac[:, d, None]
+        out.append(sp.csr_matrix((V.ravel(), (R, Cc)), shape=(mesh.n_full, mesh.n_full)))
     return out
 
 
 class Operators:
     """Assembled sparse operators of one mesh and one molecule.  gauge:
     "length" (field value E(t), term E m (e.x)) or "velocity" (field value
-    A(t), term -i A S_e)."""
+    A(t), term -i A S_e).  ecs: an ``ecs.ECS`` (complex scaling of the
+    one-body operator) or None."""
 
-    def __init__(self, mesh, nuclei, pol=(0.0, 0.0, 1.0), gauge="length"):
+    def __init__(self, mesh, nuclei, pol=(0.0, 0.0, 1.0), gauge="length", ecs=None):
         if gauge not in ("length", "velocity"):
             raise ValueError(gauge)
         self.mesh = mesh
         self.gauge = gauge
+        self.ecs = ecs
         self.nuclei = [(float(Z), tuple(map(float, R))) for Z, R in nuclei]
         self.pol = np.asarray(pol, dtype=float)
         C = mesh.C
@@ -211,29 +248,79 @@ class Operators:
         self.Vn = (C.T @ sp.diags(self.v) @ C).tocsr()
         self.Z = (C.T @ sp.diags(self.mz) @ C).tocsr()
         self._grad = None
+        self._grad_theta = None
         self._Mlu = None
+        self._Mtlu = None
+        if ecs is not None:
+            # the one-body operator on the scaled contour
+            self.eta = ecs.cell_eta(mesh)
+            self.J = np.prod(self.eta, axis=1)
+            self.m_theta = full_mass(mesh, self.J)
+            self.K_theta = (C.T @ full_stiffness(mesh, self.J[:, None] / self.eta ** 2) @ C).tocsr()
+            self.v_theta = nuclear_lumped(mesh, self.nuclei, ecs)
+            ez = sum(self.pol[d] * ecs.contour(mesh.xyz[:, d], d) for d in range(3))
+            self.M_theta = (C.T @ sp.diags(self.m_theta) @ C).tocsc()
+            self.Vn_theta = (C.T @ sp.diags(self.v_theta) @ C).tocsr()
+            self.Z_theta = (C.T @ sp.diags(self.m_theta * ez) @ C).tocsr()
+        else:
+            self.m_theta = self.m
 
     def gradient(self):
         """(D_full, D, S, S_e): the first-derivative matrices, built on first use."""
         if self._grad is None:
-            C = self.mesh.C
-            Dfull = full_gradient(self.mesh)
-            D = [(C.T @ Dd @ C).tocsr() for Dd in Dfull]
-            S = [(0.5 * (Dd - Dd.T)).tocsr() for Dd in D]
-            Se = sum(e * Sd for e, Sd in zip(self.pol, S)).tocsr()
-            self._grad = (Dfull, D, S, Se)
+            self._grad = self._derivatives(None)
         return self._grad
+
+    def _derivatives(self, fac):
+        C = self.mesh.C
+        Dfull = full_gradient(self.mesh, fac)
+        D = [(C.T @ Dd @ C).tocsr() for Dd in Dfull]
+        S = [(0.5 * (Dd - Dd.T)).tocsr() for Dd in D]
+        Se = sum(e * Sd for e, Sd in zip(self.pol, S)).tocsr()
+        return (Dfull, D, S, Se)
 
     @property
     def Se(self):
         return self.gradient()[3]
 
+    @property
+    def Se_theta(self):
+        """S_e on the scaled contour (per cell J / eta_d along d)."""
+        if self.ecs is None:
+            return self.Se
+        if self._grad_theta is None:
+            self._grad_theta = self._derivatives(self.J[:, None] / self.eta)
+        return self._grad_theta[3]
+
     def H1(self, E):
         """One-body matrix at field value E: E(t) in the length gauge, A(t)
-        in the velocity gauge."""
+        in the velocity gauge (with complex scaling, its form on the scaled
+        contour, to be inverted by M_theta)."""
+        if self.ecs is not None:
+            if self.gauge == "velocity":
+                return (0.5 * self.K_theta + self.Vn_theta - 1j * E * self.Se_theta).tocsr()
+            return (0.5 * self.K_theta + self.Vn_theta + E * self.Z_theta).tocsr()
         if self.gauge == "velocity":
             return (0.5 * self.K + self.Vn - 1j * E * self.Se).tocsr()
         return (0.5 * self.K + self.Vn + E * self.Z).tocsr()
+
+    def theta_solve(self, f):
+        """M_theta^{-1} f (the mass of the one-body operator's own form:
+        M itself without complex scaling)."""
+        if self.ecs is None:
+            return self.mass_solve(f)
+        if self._Mtlu is None:
+            import scipy.sparse.linalg as spla
+            self._Mtlu = spla.splu(self.M_theta)
+        return self._Mtlu.solve(np.asarray(f, dtype=complex))
+
+    def hermitian_load(self, f):
+        """The load vector whose M^{-1} is M_theta^{-1} f: M M_theta^{-1} f
+        (f itself without complex scaling), so that c^H of it is the M inner
+        product of c with M_theta^{-1} f."""
+        if self.ecs is None:
+            return f
+        return self.M @ self.theta_solve(f)
 
     def momentum(self):
         """Matrix of e.p = -i e.grad in the bridged basis (-i S_e)."""

@@ -13,6 +13,11 @@ potentials W all taken at t_n):
     lam_qp   = c_q^H F_p(c)
     (G v)_p  = M^{-1} F_p(v) - sum_q lam_qp v_q
 
+With exterior complex scaling (``ecs``) the load vector is the one-body
+operator's contour form, M becomes M_theta in (G v)_p and in the mean-field
+weights, and lam_qp = c_q^H M M_theta^{-1} F_p(c), the M inner product of
+the unprojected right-hand side with the orbital (likewise h_pq).
+
 The last line is the packed operator with its projector term read as a
 frozen scalar lam_qp multiplying component q (at v = c it reproduces the
 projector Q of Eq. orb_eom).  The mean-field index placement follows from
@@ -30,8 +35,11 @@ error estimate) the space stops growing at the first dimension k whose
 estimate beta h_{k+1,k} |e_k^T expm(-i tau H_k) e1| is at or below it, m
 being then the largest dimension allowed.
 
-CI: C' = expm(-i dt H_CI) C by Lanczos with min(12, N_CI) vectors, from the
-same t_n integrals (orbitals and CI advance together from t_n data).
+CI: C' = expm(-i dt H_CI) C in the Krylov space of min(12, N_CI) vectors,
+built with full re-orthogonalisation (the Arnoldi process, which for a
+Hermitian H_CI is the Lanczos recursion and also serves the non-Hermitian
+H_CI of complex scaling), from the same t_n integrals (orbitals and CI
+advance together from t_n data).
 
 Test infrastructure only (see ``oracle/__init__``).
 """
@@ -76,16 +84,16 @@ class Frozen:
         self.ginv = gamma_reg_inv(gamma)
         self.V = np.einsum('po,xoq->xpq', self.ginv, self.U)
         self.H1 = ops.H1(E)
-        self.lam = c.conj().T @ self.F(c)           # lam[q, p] = c_q^H F_p(c)
+        self.lam = c.conj().T @ ops.hermitian_load(self.F(c))   # lam[q, p] = <c_q, M^-1 F_p(c)>_M
 
     def F(self, v):
         ops, C = self.ops, self.ops.mesh.C
         vf = C @ v
-        mf = np.einsum('xpq,xq->xp', self.V, vf) * ops.m[:, None]
+        mf = np.einsum('xpq,xq->xp', self.V, vf) * ops.m_theta[:, None]
         return self.H1 @ v + C.T @ mf
 
     def G(self, v):
-        return self.ops.mass_solve(self.F(v)) - v @ self.lam
+        return self.ops.theta_solve(self.F(v)) - v @ self.lam
 
 
 def inner(ops, u, v):
@@ -124,7 +132,9 @@ def arnoldi_step(ops, Gop, phi, tau, m, breakdown=1e-14, tol=None):
 
 
 def lanczos_expm(H, C, tau, m=12):
-    """expm(-i tau H) C for Hermitian H by Lanczos (full reorthogonalisation)."""
+    """expm(-i tau H) C in the Krylov space of m vectors, orthogonalised
+    against all earlier ones twice (Lanczos for Hermitian H; the same
+    Arnoldi process serves a non-Hermitian H)."""
     m = min(m, len(C))
     beta0 = np.linalg.norm(C)
     Q = [C / beta0]
@@ -152,9 +162,10 @@ def lanczos_expm(H, C, tau, m=12):
 
 
 def integrals(ops, c, Wfull, E):
-    """h_pq = c_p^H H1(E) c_q and g_pqrs = sum_F m conj(phi_p) phi_q W_rs."""
+    """h_pq = <c_p, M^-1 H1(E) c_q>_M (= c_p^H H1(E) c_q without complex
+    scaling) and g_pqrs = sum_F m conj(phi_p) phi_q W_rs."""
     n = c.shape[1]
-    h = c.conj().T @ (ops.H1(E) @ c)
+    h = c.conj().T @ ops.hermitian_load(ops.H1(E) @ c)
     phi = ops.to_full(c)
     g = np.zeros((n, n, n, n), dtype=complex)
     for p, q in itertools.product(range(n), repeat=2):
