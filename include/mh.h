@@ -156,7 +156,29 @@ typedef struct {
                                  > 0: adaptive dimension (Sec. III.B): the space stops growing
                                  at the first dimension whose error estimate is <= krylov_tol,
                                  m being the largest (one small synchronising read per vector) */
+  double ecs_theta;           /* exterior complex scaling angle (0 <= theta < pi/2; 0: none) */
+  double ecs_inner[3];        /* half-widths R_d of the unscaled cuboid |x_d| <= R_d about the origin */
 } mh_op_desc;
+
+/* Exterior complex scaling (Sec. IV: an absorbing boundary outside an inner
+ * cuboid), when ecs_theta > 0.  Each coordinate beyond |x_d| = R_d continues
+ * along z_d = sign(x_d) R_d + e^{i theta} (x_d - sign(x_d) R_d); the
+ * one-body operator takes its Galerkin form on that contour (per cell the
+ * volume factor J = prod_d dz_d/dx_d on the mass, J / eta_d^2 on the
+ * stiffness along d, J / eta_d on the velocity-gauge derivative along d, the
+ * Coulomb potential continued to V(z(x)) J with the principal square root,
+ * and the length-gauge field e.z(x) J).  The orbital inner product stays the
+ * Hermitian one of the real coordinates (M), the pair Poisson solves and the
+ * mean field stay on the real grid, and the orbital operator is
+ * M_theta^{-1} F_theta, M_theta the contour's mass.  The library hands that
+ * on as the load vector M M_theta^{-1} F_theta (for the real mass solve),
+ * which is what mh_h1_apply returns; h_pq and lam are then M inner products
+ * and H_CI is non-Hermitian (the CI step's Krylov process orthogonalises
+ * fully, so it needs no symmetry).  Dipole and momentum records use the
+ * real coordinates; the energy record is the real part.  mh_op_create
+ * returns MH_INVALID_ARG when a cell straddles a plane |x_d| = R_d, a
+ * nucleus lies outside the open cuboid, or a hanging node or a master of
+ * one touches a scaled cell; the adjoint returns MH_UNSUPPORTED. */
 
 enum { MH_GAUGE_LENGTH = 0, MH_GAUGE_VELOCITY = 1 };
 

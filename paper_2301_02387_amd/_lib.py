@@ -44,7 +44,8 @@ class _OpDesc(C.Structure):
                 ("positions", C.POINTER(C.c_double)), ("n_orb", C.c_int32), ("n_alpha", C.c_int32),
                 ("n_beta", C.c_int32), ("polarization", C.c_double * 3), ("lmax_bc", C.c_int32),
                 ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int32), ("rdm_eps", C.c_double),
-                ("gauge", C.c_int32), ("krylov_tol", C.c_double)]
+                ("gauge", C.c_int32), ("krylov_tol", C.c_double), ("ecs_theta", C.c_double),
+                ("ecs_inner", C.c_double * 3)]
 
 
 class _Obs(C.Structure):
@@ -244,12 +245,15 @@ GAUGES = {"length": 0, "velocity": 1}
 
 
 def _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit, rdm_eps,
-             gauge="length", krylov_tol=0.0):
+             gauge="length", krylov_tol=0.0, ecs=None):
+    """ecs: None or (theta, (Rx, Ry, Rz)), exterior complex scaling."""
     Z = np.array([z for z, _ in nuclei], dtype=np.float64)
     R = np.ascontiguousarray(np.array([r for _, r in nuclei], dtype=np.float64).reshape(-1, 3))
+    theta, inner = (0.0, (0.0, 0.0, 0.0)) if ecs is None else (float(ecs[0]), tuple(map(float, ecs[1])))
     desc = _OpDesc(len(nuclei), Z.ctypes.data_as(C.POINTER(C.c_double)), R.ctypes.data_as(C.POINTER(C.c_double)),
                    int(n_orb), int(n_alpha), int(n_beta), (C.c_double * 3)(*polarization), int(lmax_bc),
-                   float(poisson_rtol), int(poisson_maxit), float(rdm_eps), GAUGES[gauge], float(krylov_tol))
+                   float(poisson_rtol), int(poisson_maxit), float(rdm_eps), GAUGES[gauge], float(krylov_tol),
+                   theta, (C.c_double * 3)(*inner))
     return desc, (Z, R)
 
 
@@ -258,10 +262,10 @@ class Operator:
 
     def __init__(self, mesh, nuclei, n_orb, n_alpha, n_beta, polarization=(0.0, 0.0, 1.0), lmax_bc=12,
                  poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", krylov_tol=0.0,
-                 stream=None):
+                 stream=None, ecs=None):
         lib = load_library()
         desc, keep = _op_desc(nuclei, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol,
-                              poisson_maxit, rdm_eps, gauge, krylov_tol)
+                              poisson_maxit, rdm_eps, gauge, krylov_tol, ecs)
         h = C.c_void_p()
         _check(lib.mh_op_create(mesh._h, C.byref(desc), _stream(stream), C.byref(h)))
         self._attach(h, [mesh])
@@ -269,9 +273,11 @@ class Operator:
     @classmethod
     def batch(cls, meshes, nuclei_list, n_orb, n_alpha, n_beta, field_scale=None, polarization=(0.0, 0.0, 1.0),
               lmax_bc=12, poisson_rtol=1e-12, poisson_maxit=5000, rdm_eps=1e-10, gauge="length", krylov_tol=0.0,
-              stream=None):
+              stream=None, ecs=None):
         """Batch of independent instances (mh_batch_create): one mesh and one
-        molecule per instance, one shared orbital/electron space."""
+        molecule per instance, one shared orbital/electron space.  ecs: None,
+        one (theta, inner) for every instance, or a list of them (or None)
+        per instance."""
         lib = load_library()
         ni = len(meshes)
         if len(nuclei_list) != ni:
@@ -279,8 +285,9 @@ class Operator:
         descs = (_OpDesc * ni)()
         keep = []
         for i, nuc in enumerate(nuclei_list):
+            ei = ecs[i] if isinstance(ecs, list) else ecs
             d, k = _op_desc(nuc, n_orb, n_alpha, n_beta, polarization, lmax_bc, poisson_rtol, poisson_maxit,
-                            rdm_eps, gauge, krylov_tol)
+                            rdm_eps, gauge, krylov_tol, ei)
             descs[i] = d
             keep.append(k)
         hs = (C.c_void_p * ni)(*[m._h.value for m in meshes])

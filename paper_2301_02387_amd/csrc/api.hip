@@ -366,6 +366,7 @@ struct InstanceSpec {
   std::vector<Nucleus> nuc;
   double pol[3];
   double E0;
+  EcsReq ecs;
 };
 
 static double nuclear_repulsion(const std::vector<Nucleus>& nuc) {
@@ -444,7 +445,7 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
         try {
           for (int i = t; i < ni; i += nthr) {
             op->Ms[i] = *spec[i].mesh;
-            build_operator(op->Ms[i], spec[i].nuc, spec[i].pol, lmax, op->Hs[i]);
+            build_operator(op->Ms[i], spec[i].nuc, spec[i].pol, lmax, op->Hs[i], &spec[i].ecs);
           }
         } catch (const std::exception& e) {
           errs[t] = e.what();
@@ -543,7 +544,19 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
     }
     for (int k = 0; k < 3; ++k) d.pol[k] = spec[i].pol[k];
     d.gauge = desc.gauge;
+    if (H.ecs) {
+      d.ecs = 1;
+      d.ecs_code = op->upload(H.ecs_code, s);
+      d.ecs_rho = op->upload(H.ecs_rho, s);
+      d.ecs_v = op->upload(H.ecs_v, s);
+      d.ecs_mz = op->upload(H.ecs_mz, s);
+      for (int k = 0; k < 6; ++k) {
+        d.ecs_pw[2 * k] = std::cos((k - 2) * H.ecs_theta);
+        d.ecs_pw[2 * k + 1] = std::sin((k - 2) * H.ecs_theta);
+      }
+    }
     if (i == 0) mx = d;
+    mx.ecs = std::max(mx.ecs, d.ecs);
     mx.nC = std::max(mx.nC, d.nC);
     mx.N = std::max(mx.N, d.N);
     mx.NE = std::max(mx.NE, d.NE);
@@ -679,6 +692,11 @@ static int check_desc(const mh_op_desc* desc) {
   if (lmax > 12) return fail(MH_UNSUPPORTED, "lmax_bc must be <= 12");
   if (desc->gauge != MH_GAUGE_LENGTH && desc->gauge != MH_GAUGE_VELOCITY) return fail(MH_INVALID_ARG, "gauge");
   if (!(desc->krylov_tol >= 0.0)) return fail(MH_INVALID_ARG, "krylov_tol must be >= 0");
+  if (!(desc->ecs_theta >= 0.0 && desc->ecs_theta < 1.5707963267948966))
+    return fail(MH_INVALID_ARG, "ecs_theta must lie in [0, pi/2)");
+  if (desc->ecs_theta > 0.0)
+    for (int d = 0; d < 3; ++d)
+      if (!(desc->ecs_inner[d] >= 0.0)) return fail(MH_INVALID_ARG, "ecs_inner must be >= 0");
   if ((lmax + 1) * (lmax + 1) * desc->n_orb * desc->n_orb > 48 * 256)
     return fail(MH_UNSUPPORTED, "multipole table too large");
   return MH_OK;
@@ -695,6 +713,8 @@ static InstanceSpec make_spec(const mh_mesh* mesh, const mh_op_desc* desc, doubl
   }
   for (int k = 0; k < 3; ++k) sp.pol[k] = desc->polarization[k];
   sp.E0 = E0;
+  sp.ecs.theta = desc->ecs_theta;
+  for (int k = 0; k < 3; ++k) sp.ecs.inner[k] = desc->ecs_inner[k];
   return sp;
 }
 
@@ -1729,6 +1749,7 @@ extern "C" int mh_propagate_adjoint(mh_op* op, const double* phi0, const double*
   if (op->n > 4) return fail(MH_UNSUPPORTED, "the adjoint is implemented for at most 4 orbitals");
   if (op->ci.dim > 12) return fail(MH_UNSUPPORTED, "the adjoint needs an exact CI exponential (at most 12 determinants)");
   if (op->B.mx.gauge != MH_GAUGE_LENGTH) return fail(MH_UNSUPPORTED, "the adjoint is implemented in the length gauge");
+  if (op->B.mx.ecs) return fail(MH_UNSUPPORTED, "the adjoint is implemented without complex scaling");
   if (n_steps < 1 || m < 1 || m > 24 || n_quad < 1 || n_quad > 16) return fail(MH_INVALID_ARG, "bad sizes");
   return guarded([&]() -> int {
     hipStream_t s = S(stream);

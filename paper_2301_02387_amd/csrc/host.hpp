@@ -71,8 +71,23 @@ std::string build_mesh(double lo, double hi, int nc, int p, const std::vector<Ba
                        const Mesh* from = nullptr);
 
 // Operator tables computed on the host at set-up.
+// Exterior complex scaling of the one-body operator (Sec. IV absorber):
+// coordinates beyond |x_d| = inner[d] continue along x_d -> sign(x_d) inner[d]
+// + e^{i theta} (x_d - sign(x_d) inner[d]); theta = 0 leaves them real.
+struct EcsReq {
+  double theta = 0.0;
+  double inner[3] = {0.0, 0.0, 0.0};
+};
+
 struct OpHost {
   std::vector<double> m, v, mz;            // nF: mass, lumped nuclear potential, m*(e.x)
+  // complex scaling (ecs): the scaled directions of each cell (bit d), and per
+  // extended row (re, im) the factor rho = m / m_theta, rho times the continued
+  // lumped potential, and the continued field weights m (e.z)
+  bool ecs = false;
+  double ecs_theta = 0.0;
+  std::vector<uint8_t> ecs_code;           // nC
+  std::vector<double> ecs_rho, ecs_v, ecs_mz;  // NE x 2
   std::vector<uint64_t> owner_mask;        // per cell: local nodes whose diagonal terms it adds
   std::vector<int32_t> node_inc;           // NE x 8: cell*64 + local index of each incident cell, -1 padded
   // interface (hanging-master) block of the mass matrix, rows = masters
@@ -95,8 +110,12 @@ struct OpHost {
   int nharm = 0;
 };
 
+// ecs: complex scaling of the one-body operator (null or theta = 0: none);
+// throws std::invalid_argument for a cell straddling a scaling plane, a
+// nucleus outside the unscaled cuboid, or a hanging node or master touching a
+// scaled cell.
 void build_operator(const Mesh& mesh, const std::vector<Nucleus>& nuc, const double pol[3],
-                    int lmax, OpHost& op);
+                    int lmax, OpHost& op, const EcsReq* ecs = nullptr);
 
 // Geometric multigrid hierarchy for the assembled pair Poisson operator
 // (homogeneous Dirichlet problem on the DoFs).  Level 0 is the operator's own

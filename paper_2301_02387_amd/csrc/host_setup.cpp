@@ -12,6 +12,8 @@
 // Gauss-Legendre with p+5 points per direction elsewhere.
 #include <algorithm>
 #include <cmath>
+#include <complex>
+#include <functional>
 #include <map>
 #include <stdexcept>
 
@@ -71,6 +73,52 @@ void cell_regular(const Mesh& M, int64_t e, double Z, const double* R, int q, co
     for (int b = 0; b < P; ++b)
       for (int a = 0; a < P; ++a) {
         double s = 0.0;
+        for (int k = 0; k < q; ++k) s += Lg[c * q + k] * t2[(a * P + b) * q + k];
+        out[(c * P + b) * P + a] += vol * s;
+      }
+}
+
+// The same integral on a complex-scaled cell: int f_i (-Z / r(z(x))) J dx,
+// z the contour of each coordinate, r the principal square root of
+// sum_d (z_d - R_d)^2 (the continuation of |x - R|).
+void cell_regular_scaled(const Mesh& M, int64_t e, double Z, const double* R, int q, const std::vector<double>& g,
+                         const std::vector<double>& gw, const std::vector<double>& Lg,
+                         const std::function<std::complex<double>(double, int)>& zc, std::complex<double> J,
+                         std::complex<double>* out) {
+  typedef std::complex<double> cd;
+  const int P = M.P;
+  const double h = M.cell_h[e];
+  const double* o = &M.cell_org[3 * e];
+  std::vector<cd> f(q * q * q), t1(P * q * q), t2(P * P * q);
+  std::vector<cd> zx(q), zy(q), zz(q);
+  for (int i = 0; i < q; ++i) {
+    zx[i] = zc(o[0] + h * g[i], 0) - R[0];
+    zy[i] = zc(o[1] + h * g[i], 1) - R[1];
+    zz[i] = zc(o[2] + h * g[i], 2) - R[2];
+  }
+  for (int k = 0; k < q; ++k)
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i)
+        f[(k * q + j) * q + i] = -Z * J / std::sqrt(zx[i] * zx[i] + zy[j] * zy[j] + zz[k] * zz[k]) * (gw[i] * gw[j] * gw[k]);
+  for (int a = 0; a < P; ++a)
+    for (int k = 0; k < q; ++k)
+      for (int j = 0; j < q; ++j) {
+        cd s = 0.0;
+        for (int i = 0; i < q; ++i) s += Lg[a * q + i] * f[(k * q + j) * q + i];
+        t1[(a * q + k) * q + j] = s;
+      }
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < P; ++b)
+      for (int k = 0; k < q; ++k) {
+        cd s = 0.0;
+        for (int j = 0; j < q; ++j) s += Lg[b * q + j] * t1[(a * q + k) * q + j];
+        t2[(a * P + b) * q + k] = s;
+      }
+  const double vol = h * h * h;
+  for (int c = 0; c < P; ++c)
+    for (int b = 0; b < P; ++b)
+      for (int a = 0; a < P; ++a) {
+        cd s = 0.0;
         for (int k = 0; k < q; ++k) s += Lg[c * q + k] * t2[(a * P + b) * q + k];
         out[(c * P + b) * P + a] += vol * s;
       }
@@ -153,10 +201,42 @@ std::vector<double> sym_eigs(std::vector<double> a, int n) {
 
 }  // namespace
 
-void build_operator(const Mesh& M, const std::vector<Nucleus>& nuc, const double pol[3], int lmax, OpHost& op) {
+void build_operator(const Mesh& M, const std::vector<Nucleus>& nuc, const double pol[3], int lmax, OpHost& op,
+                    const EcsReq* ecs) {
+  typedef std::complex<double> cd;
   const int P = M.P, P3 = P * P * P;
   const int64_t nC = M.n_cells, nF = M.nF, N = M.N, NE = M.N + M.Nh;
   const std::vector<double>& w = M.gll.w;
+
+  // ---- complex scaling: the scaled directions of every cell ---------------------
+  op.ecs = ecs && ecs->theta > 0.0;
+  op.ecs_theta = op.ecs ? ecs->theta : 0.0;
+  const cd ph = std::polar(1.0, op.ecs_theta);
+  auto zc = [&](double x, int d) -> cd {
+    const double R = ecs->inner[d];
+    if (std::fabs(x) <= R) return cd(x, 0.0);
+    const double sg = x > 0 ? 1.0 : -1.0;
+    return sg * R + ph * (x - sg * R);
+  };
+  if (op.ecs) {
+    op.ecs_code.assign(nC, 0);
+    for (int64_t e = 0; e < nC; ++e) {
+      const double h = M.cell_h[e], tol = 1e-12 * h;
+      for (int d = 0; d < 3; ++d) {
+        const double lo = M.cell_org[3 * e + d], hi = lo + h, R = ecs->inner[d];
+        const bool out = lo >= R - tol || hi <= -R + tol;
+        const bool in = lo >= -R - tol && hi <= R + tol;
+        if (!out && !in) throw std::invalid_argument("a cell straddles a complex-scaling plane");
+        if (out) op.ecs_code[e] |= (uint8_t)(1 << d);
+      }
+    }
+    for (const Nucleus& nu : nuc)
+      for (int d = 0; d < 3; ++d)
+        if (!(std::fabs(nu.R[d]) < ecs->inner[d]))
+          throw std::invalid_argument("complex scaling: every nucleus must lie inside the unscaled cuboid");
+  }
+  std::vector<cd> vt;  // continued lumped potential (complex scaling only)
+  if (op.ecs) vt.assign(nF, cd(0.0, 0.0));
 
   // ---- masses and dipole weights --------------------------------------------
   op.m.assign(nF, 0.0);
@@ -181,6 +261,7 @@ void build_operator(const Mesh& M, const std::vector<Nucleus>& nuc, const double
     for (int a = 0; a < P; ++a)
       for (int i = 0; i < q; ++i) Lg[a * q + i] = lagrange(M.gll.x, a, 2.0 * g[i] - 1.0);
     std::vector<double> cellv(P3);
+    std::vector<cd> cellc(P3);
     for (int64_t e = 0; e < nC; ++e) {
       std::fill(cellv.begin(), cellv.end(), 0.0);
       const double h = M.cell_h[e];
@@ -194,6 +275,16 @@ void build_operator(const Mesh& M, const std::vector<Nucleus>& nuc, const double
         else cell_regular(M, e, nu.Z, nu.R, q, g, gw, Lg, cellv.data());
       }
       for (int t = 0; t < P3; ++t) op.v[M.cell_nodes[e * P3 + t]] += cellv[t];
+      if (!op.ecs) continue;
+      if (op.ecs_code[e] == 0) {
+        for (int t = 0; t < P3; ++t) vt[M.cell_nodes[e * P3 + t]] += cellv[t];
+        continue;
+      }
+      // a scaled cell holds no nucleus (they lie inside the unscaled cuboid)
+      std::fill(cellc.begin(), cellc.end(), cd(0.0, 0.0));
+      const cd J = std::pow(ph, (double)__builtin_popcount(op.ecs_code[e]));
+      for (const Nucleus& nu : nuc) cell_regular_scaled(M, e, nu.Z, nu.R, q, g, gw, Lg, zc, J, cellc.data());
+      for (int t = 0; t < P3; ++t) vt[M.cell_nodes[e * P3 + t]] += cellc[t];
     }
   }
 
@@ -354,6 +445,55 @@ void build_operator(const Mesh& M, const std::vector<Nucleus>& nuc, const double
   op.inv_mass.assign(N, 0.0);
   for (int64_t k = 0; k < N; ++k)
     if (op.ma_index[k] < 0) op.inv_mass[k] = 1.0 / op.m[k];
+
+  // ---- complex scaling: the load vector in units of the real mass -------------
+  // The scaled operator is M_theta^-1 F_theta with M_theta = C^T diag(m_theta) C;
+  // the orbital product stays the real one (M).  When no hanging node or
+  // master touches a scaled cell, M and M_theta share the interface block and
+  // M M_theta^-1 = diag(rho), rho = m / m_theta (1 on the interface), so
+  // rho F_theta is a load vector for the real mass solve, and the products
+  // c^H (rho F_theta) are M inner products: rho multiplies the stiffness and
+  // derivative loads and the potential; the field weights become m (e.z) and
+  // the mean-field load m V u is unchanged.
+  if (op.ecs) {
+    auto touches_scaled = [&](int64_t nd) {
+      for (int t = 0; t < 8; ++t) {
+        const int32_t code = op.node_inc[(size_t)nd * 8 + t];
+        if (code < 0) break;
+        if (op.ecs_code[code >> 6]) return true;
+      }
+      return false;
+    };
+    for (int64_t r = N; r < NE; ++r)
+      if (touches_scaled(r)) throw std::invalid_argument("complex scaling: a hanging node touches a scaled cell");
+    for (int64_t i = 0; i < nMa; ++i)
+      if (touches_scaled(op.ma_dof[i])) throw std::invalid_argument("complex scaling: a master touches a scaled cell");
+    std::vector<cd> mt(nF, cd(0.0, 0.0));
+    for (int64_t e = 0; e < nC; ++e) {
+      const cd J = std::pow(ph, (double)__builtin_popcount(op.ecs_code[e]));
+      const double s = 0.125 * M.cell_h[e] * M.cell_h[e] * M.cell_h[e];
+      for (int c = 0; c < P; ++c)
+        for (int b = 0; b < P; ++b)
+          for (int a = 0; a < P; ++a)
+            mt[M.cell_nodes[e * P3 + (c * P + b) * P + a]] += (op.ecs_code[e] ? J : cd(1.0, 0.0)) * (s * w[a] * w[b] * w[c]);
+    }
+    op.ecs_rho.assign(2 * NE, 0.0);
+    op.ecs_v.assign(2 * NE, 0.0);
+    op.ecs_mz.assign(2 * NE, 0.0);
+    for (int64_t r = 0; r < NE; ++r) {
+      const cd rho = op.m[r] / mt[r];
+      const cd vr = rho * vt[r];
+      cd ez(0.0, 0.0);
+      for (int d = 0; d < 3; ++d) ez += pol[d] * zc(M.xyz[3 * r + d], d);
+      const cd mzr = op.m[r] * ez;
+      op.ecs_rho[2 * r] = rho.real();
+      op.ecs_rho[2 * r + 1] = rho.imag();
+      op.ecs_v[2 * r] = vr.real();
+      op.ecs_v[2 * r + 1] = vr.imag();
+      op.ecs_mz[2 * r] = mzr.real();
+      op.ecs_mz[2 * r + 1] = mzr.imag();
+    }
+  }
 
   // ---- assembled Poisson operator K~ = C^T K_full C on the DoFs --------------
   // Row k of K_full is the sum over k's cells of its three line couplings

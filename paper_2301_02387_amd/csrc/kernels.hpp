@@ -89,6 +89,18 @@ struct DevMesh {
   double Qs[16];                        // antisymmetric 1D first-derivative form (P x P)
   double pol[3] = {0.0, 0.0, 1.0};      // unit field direction e
   int gauge = 0;                        // 0: length (E(t) e.r), 1: velocity (-i A(t) e.grad)
+  // exterior complex scaling of the one-body operator (ecs != 0): the scaled
+  // directions of each cell (bit d); per extended row (re, im) rho = m / m_theta,
+  // rho times the continued lumped potential and the continued field weights
+  // m (e.z); ecs_pw[k] = e^{i (k - 2) theta} (re, im), k = 0..5: a cell with s
+  // scaled directions carries e^{i (s - 2 b_d) theta} on its stiffness along d
+  // and e^{i (s - b_d) theta} on its derivative along d (b_d: d scaled)
+  int ecs = 0;
+  const uint8_t* ecs_code = nullptr;
+  const double* ecs_rho = nullptr;
+  const double* ecs_v = nullptr;
+  const double* ecs_mz = nullptr;
+  double ecs_pw[12] = {};
 };
 
 // Rows of the assembled Poisson operator longer than this are handled by whole

@@ -44,7 +44,14 @@ namespace mh {
 // or e alone for the momentum, diag_mode 4), S the Gauss-Lobatto Galerkin
 // derivative in its antisymmetric form: per cell (h/2)^2 (Qs x W x W) along x
 // and likewise along y and z, so its line sums share the stiffness's loads.
-template <int P, int L, bool ASM, bool VEL>
+// ECS: exterior complex scaling of the one-body part (diag_mode 0..2, on
+// instances that carry it): each cell's stiffness and derivative loads along
+// d take the contour factors e^{i (s - 2 b_d) theta} and e^{i (s - b_d) theta}
+// (s scaled directions, b_d whether d is one), the node's cell sum is
+// multiplied by rho = m / m_theta, and the potential and field weights are the
+// continued complex ones, so the load is in units of the real mass; the
+// mean-field load is unchanged.
+template <int P, int L, bool ASM, bool VEL, bool ECS>
 __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ dm, const double2* __restrict__ u,
                                                     const double* __restrict__ Ef, int diag_mode,
                                                     const double* __restrict__ Upk, const double2* __restrict__ ginv,
@@ -70,6 +77,8 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
   const double ax = VEL ? av * d.pol[0] : 0.0, ay = VEL ? av * d.pol[1] : 0.0, az = VEL ? av * d.pol[2] : 0.0;
   const bool stiff = diag_mode <= 2;
   const double Elen = d.gauge == 1 ? 0.0 : E;   // the length-gauge term only in the length gauge
+  const bool ecs_i = ECS && d.ecs && diag_mode <= 2;
+  auto pw = [&](int k) { return make_double2(d.ecs_pw[2 * k + 4], d.ecs_pw[2 * k + 5]); };  // e^{i k theta}
   const XcdSweep sw = xcd_sweep(d.NE, NT / L, d.sched_orb & 1);
   // all L lanes of a node share i, so a node group enters and leaves together
   for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
@@ -122,23 +131,53 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
         }
       }
       const double hk = gbl(d.cell_hh)[K];  // h/2
+      int sc = 0, b0 = 0, b1 = 0, b2 = 0;    // scaled directions of the cell (complex scaling)
+      if (ecs_i) {
+        const int code = gbl(d.ecs_code)[K];
+        b0 = code & 1;
+        b1 = (code >> 1) & 1;
+        b2 = (code >> 2) & 1;
+        sc = b0 + b1 + b2;
+      }
       if (stiff) {
         const double hh = 0.5 * hk;  // (1/2) K with K_cell = (h/2)(...)
         const double f0 = hh * d.w[b] * d.w[c], f1 = hh * d.w[a] * d.w[c], f2 = hh * d.w[a] * d.w[b];
-        y.x += f0 * s0.x + f1 * s1.x + f2 * s2.x;
-        y.y += f0 * s0.y + f1 * s1.y + f2 * s2.y;
+        if (ecs_i && sc) {
+          y = cadd(y, cscale(f0, cmul(pw(sc - 2 * b0), s0)));
+          y = cadd(y, cscale(f1, cmul(pw(sc - 2 * b1), s1)));
+          y = cadd(y, cscale(f2, cmul(pw(sc - 2 * b2), s2)));
+        } else {
+          y.x += f0 * s0.x + f1 * s1.x + f2 * s2.x;
+          y.y += f0 * s0.y + f1 * s1.y + f2 * s2.y;
+        }
       }
       if (VEL) {  // y += -i (h/2)^2 (ax Wb Wc t0 + ay Wa Wc t1 + az Wa Wb t2)
         const double h2 = hk * hk;
         const double g0 = h2 * ax * d.w[b] * d.w[c], g1 = h2 * ay * d.w[a] * d.w[c], g2 = h2 * az * d.w[a] * d.w[b];
+        if (ecs_i && sc) {
+          t0 = cmul(pw(sc - b0), t0);
+          t1 = cmul(pw(sc - b1), t1);
+          t2 = cmul(pw(sc - b2), t2);
+        }
         y.x += g0 * t0.y + g1 * t1.y + g2 * t2.y;
         y.y -= g0 * t0.x + g1 * t1.x + g2 * t2.x;
       }
     }
+    if (ecs_i && act) {
+      const auto* rho = gbl(d.ecs_rho);
+      y = cmul(make_double2(rho[2 * i], rho[2 * i + 1]), y);
+    }
     if (diag_mode >= 1 && diag_mode <= 3 && act) {
-      const double dg = diag_mode == 3 ? gbl(d.mz)[i] : gbl(d.v)[i] + Elen * gbl(d.mz)[i];
-      y.x += dg * ui.x;
-      y.y += dg * ui.y;
+      if (ecs_i && diag_mode != 3) {
+        const auto* vc = gbl(d.ecs_v);
+        const auto* zc = gbl(d.ecs_mz);
+        const double2 dg = make_double2(vc[2 * i] + Elen * zc[2 * i], vc[2 * i + 1] + Elen * zc[2 * i + 1]);
+        y = cadd(y, cmul(dg, ui));
+      } else {
+        const double dg = diag_mode == 3 ? gbl(d.mz)[i] : gbl(d.v)[i] + Elen * gbl(d.mz)[i];
+        y.x += dg * ui.x;
+        y.y += dg * ui.y;
+      }
     }
     if (diag_mode == 2) {
       // z_p = sum_q U_pq u_q (U Hermitian, packed: Up[o][q] = Re U_oq, Up[q][o] = Im U_oq for o < q).
@@ -273,18 +312,27 @@ static void launch_stencil_orb_t(const Batch& b, const double* u, const double* 
                                  const double* kq, hipStream_t s) {
   const int grid = xcd_grid(b.mx.NE, NT / L, b.mx.grid_orb);
   const bool vel = diag_mode == 4 || (b.mx.gauge == 1 && (diag_mode == 1 || diag_mode == 2));
+  const bool ecs = b.mx.ecs && diag_mode <= 2;
   if (kq)
-    hipLaunchKernelGGL((k_stencil_orb<P, L, true, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u,
-                       Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out,
-                       (double2*)acc, (const double2*)kq);
+    hipLaunchKernelGGL((k_stencil_orb<P, L, true, false, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm,
+                       (const double2*)u, Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam,
+                       (double2*)out, (double2*)acc, (const double2*)kq);
+  else if (vel && ecs)
+    hipLaunchKernelGGL((k_stencil_orb<P, L, false, true, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm,
+                       (const double2*)u, Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam,
+                       (double2*)out, (double2*)acc, (const double2*)nullptr);
   else if (vel)
-    hipLaunchKernelGGL((k_stencil_orb<P, L, false, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u,
-                       Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out,
-                       (double2*)acc, (const double2*)nullptr);
+    hipLaunchKernelGGL((k_stencil_orb<P, L, false, true, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm,
+                       (const double2*)u, Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam,
+                       (double2*)out, (double2*)acc, (const double2*)nullptr);
+  else if (ecs)
+    hipLaunchKernelGGL((k_stencil_orb<P, L, false, false, true>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm,
+                       (const double2*)u, Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam,
+                       (double2*)out, (double2*)acc, (const double2*)nullptr);
   else
-    hipLaunchKernelGGL((k_stencil_orb<P, L, false, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm, (const double2*)u,
-                       Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam, (double2*)out,
-                       (double2*)acc, (const double2*)nullptr);
+    hipLaunchKernelGGL((k_stencil_orb<P, L, false, false, false>), dim3(grid, b.ni), dim3(NT), 0, s, b.dm,
+                       (const double2*)u, Ef, diag_mode, Upk, (const double2*)ginv, mode, (const double2*)lam,
+                       (double2*)out, (double2*)acc, (const double2*)nullptr);
 }
 
 template <int P>
@@ -306,9 +354,10 @@ static void launch_stencil_orb_p(const Batch& b, const double* u, const double* 
 void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int diag_mode, const double* Upk,
                         const double* ginv, int mode, const double* lam, double* out, double* acc, double* kq,
                         double* kred, hipStream_t s) {
-  // the velocity term and the momentum run node by node (their line sums share the stiffness's loads)
+  // the velocity term, the momentum and complex scaling run node by node (their line sums
+  // share the stiffness's loads; the scaled stiffness is complex)
   const bool vel = diag_mode == 4 || (b.mx.gauge == 1 && (diag_mode == 1 || diag_mode == 2));
-  const bool asm_k = (b.mx.sched_orb & 4) && kq && kred && !vel;
+  const bool asm_k = (b.mx.sched_orb & 4) && kq && kred && !vel && !(b.mx.ecs && diag_mode <= 2);
   if (asm_k && diag_mode != 3) {
     PoissonWs Pk;
     Pk.red = kred;

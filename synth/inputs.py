@@ -107,6 +107,31 @@ def small_workload(name, seed=0):
         return dict(name=name, lo=-8.0, hi=8.0, n_coarse=4, p=1 if q1 else 2, balls=[],
                     kelly=dict(nuclei=nuclei, tol=0.01 if q1 else 0.005, soft=0.1, max_level=3),
                     nuclei=nuclei, n_orb=2, n_alpha=1, n_beta=1, polarization=(1.0, 0.0, 0.0))
+    # exterior complex scaling cases: the refined block stays inside |x_d| < 4,
+    # so every hanging node and master lies in unscaled cells; "ecs" gives the
+    # angle and the inner half-widths (cell faces)
+    if name == "ecs_q2":
+        return dict(name=name, lo=-12.0, hi=12.0, n_coarse=6, p=2,
+                    balls=[_ball(rng.uniform(-1, 1, 3), 1.0, 1)],
+                    nuclei=[(1.0, (0.0, 0.0, 0.7)), (1.0, (0.0, 0.0, -0.7))], n_orb=2, n_alpha=1, n_beta=1,
+                    polarization=(1.0, 0.0, 0.0), ecs=dict(theta=0.35, inner=(8.0, 8.0, 8.0)))
+    if name == "ecs_q3":
+        c1 = rng.uniform(-1.5, 1.5, 3)
+        return dict(name=name, lo=-12.0, hi=12.0, n_coarse=6, p=3,
+                    balls=[_ball(c1, 1.2, 1), _ball(-c1, 0.8, 1)],
+                    nuclei=[(1.0, tuple(c1 * 0.5)), (1.0, tuple(-c1 * 0.5))], n_orb=2, n_alpha=1, n_beta=1,
+                    polarization=(0.6, 0.0, 0.8), ecs=dict(theta=0.5, inner=(8.0, 8.0, 8.0)))
+    if name == "ecs_n3":    # three orbitals, 9 determinants; y left unscaled
+        return dict(name=name, lo=-12.0, hi=12.0, n_coarse=6, p=2,
+                    balls=[_ball((0.2, -0.3, 0.1), 1.5, 1)],
+                    nuclei=[(2.0, (0.0, 0.0, 0.0))], n_orb=3, n_alpha=2, n_beta=1,
+                    polarization=(0.0, 0.0, 1.0), ecs=dict(theta=0.3, inner=(8.0, 12.0, 8.0)))
+    if name == "kelly_ecs_q1":  # H2 on a Kelly mesh (refined within |x_d| < 16), scaled beyond 24
+        nuclei = [(1.0, (0.0, 0.0, 0.7)), (1.0, (0.0, 0.0, -0.7))]
+        return dict(name=name, lo=-32.0, hi=32.0, n_coarse=8, p=1, balls=[],
+                    kelly=dict(nuclei=nuclei, tol=0.05, soft=0.1, max_level=4),
+                    nuclei=nuclei, n_orb=2, n_alpha=1, n_beta=1, polarization=(1.0, 0.0, 0.0),
+                    ecs=dict(theta=0.35, inner=(24.0, 24.0, 24.0)))
     if name == "small_n3":
         return dict(name=name, lo=-6.0, hi=6.0, n_coarse=3, p=2,
                     balls=[_ball((0.2, -0.3, 0.1), 1.5, 2)],
@@ -163,6 +188,15 @@ def random_orbitals(xyz, n, seed, n_gauss=6, spread=2.0):
     """Seeded smooth complex test functions (sums of Gaussians) at xyz."""
     rng = np.random.default_rng(seed)
     ce = [(rng.uniform(-spread, spread, 3), rng.uniform(0.3, 2.0)) for _ in range(n_gauss)]
+    co = rng.standard_normal((n_gauss, n)) + 1j * rng.standard_normal((n_gauss, n))
+    return gaussian_orbitals(xyz, ce, co)
+
+
+def broad_orbitals(xyz, n, seed, length, n_gauss=6):
+    """Seeded complex test functions spread over a region of the given
+    length: Gaussians centred within +-length, of widths 0.7 to 1.4 length."""
+    rng = np.random.default_rng(seed)
+    ce = [(rng.uniform(-length, length, 3), rng.uniform(0.5, 2.0) / length ** 2) for _ in range(n_gauss)]
     co = rng.standard_normal((n_gauss, n)) + 1j * rng.standard_normal((n_gauss, n))
     return gaussian_orbitals(xyz, ce, co)
 

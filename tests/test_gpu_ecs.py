@@ -1,0 +1,213 @@
+"""GPU parity of exterior complex scaling (Sec. IV: the one-body operator
+continued to complex coordinates outside an inner cuboid absorbs what
+leaves the molecule): the node pass with the contour factors and the
+complex potential and field, handed on as the load vector of the real mass
+solve, against the oracle's scaled matrices and its M_theta solve.
+
+Bars: operator applications <= 1e-10 relative per orbital and element-wise;
+propagated records, orbitals and CI vectors <= 1e-8."""
+import numpy as np
+import pytest
+
+from synth import broad_orbitals, random_ci
+from tests.lib_cases import Pair, rel_err_cols, max_rel_cols, poisson_solver
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["ecs_q2", "ecs_q3", "ecs_n3", "kelly_ecs_q1"]
+_PAIRS = {}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+def pair(name, gauge="length", **kw):
+    key = (name, gauge, tuple(sorted(kw.items())))
+    if key not in _PAIRS:
+        from oracle.ecs import ECS
+        from oracle.fem import Operators
+        from tests.oracle_cases import case
+        e = case(name)[0]["ecs"]
+        P = Pair(name, gauge=gauge, ecs=(e["theta"], e["inner"]), **kw)
+        P.ope = Operators(P.om, P.w["nuclei"], pol=P.w["polarization"], gauge=gauge,
+                          ecs=ECS(e["theta"], e["inner"]))
+        _PAIRS[key] = P
+    return _PAIRS[key]
+
+
+def dev(a):
+    return _torch().from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    _torch().cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def orbitals(P, seed):
+    """Broad orbitals reaching the scaling planes: each carries at least 5 %
+    of its weight on nodes of scaled cells."""
+    from oracle.mctdhf import orthonormalize
+    om = P.om
+    inner = np.asarray(P.w["ecs"]["inner"])
+    xyz = om.xyz[om.dof_nodes]
+    c = orthonormalize(P.ops, broad_orbitals(xyz, P.w["n_orb"], seed, float(inner.min())))
+    far = np.any(np.abs(xyz) >= inner[None, :] - 1e-9, axis=1)    # nodes of scaled cells
+    m = P.ops.M.diagonal()
+    share = (m[far, None] * np.abs(c[far]) ** 2).sum(axis=0) / (m[:, None] * np.abs(c) ** 2).sum(axis=0)
+    assert share.min() > 0.05, share
+    return c
+
+
+@pytest.mark.parametrize("gauge", ["length", "velocity"])
+@pytest.mark.parametrize("name", CASES)
+def test_h1_apply_ecs(name, gauge):
+    """The load vector M M_theta^-1 H1_theta c."""
+    torch = _torch()
+    P = pair(name, gauge)
+    n = P.w["n_orb"]
+    c = orbitals(P, 2)
+    print(name, gauge, flush=True)
+    for E in (0.0, 0.37, -1.3):
+        f = torch.zeros((P.N, n), dtype=torch.complex128, device="cuda")
+        P.op.h1_apply(dev(P.to_lib_orb(c)), E, f)
+        ref = P.ope.hermitian_load(P.ope.H1(E) @ c)
+        got = P.from_lib_dof(host(f))
+        assert rel_err_cols(got, ref) < 1e-10 and max_rel_cols(got, ref) < 1e-10, E
+
+
+@pytest.mark.parametrize("gauge", ["length", "velocity"])
+@pytest.mark.parametrize("name", CASES)
+def test_rhs_apply_ecs(name, gauge):
+    """G = M_theta^-1 F_theta - v lam; orbital schedules that would take the
+    stiffness from the assembled (real) operator run the node pass."""
+    torch = _torch()
+    from oracle.ci import CISpace
+    from oracle.mctdhf import Frozen
+    P = pair(name, gauge)
+    n = P.w["n_orb"]
+    cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
+    c = orbitals(P, 5)
+    C = random_ci(cs.dim, 6)
+    gam, Gam = cs.rdms(C)
+    W = poisson_solver(P.ops).pair_potentials(c)
+    E = 0.21
+    fr = Frozen(P.ope, c, gam, Gam, E, W)
+    P.op.freeze(dev(P.to_lib_orb(c)), dev(gam), dev(Gam), E, dev(P.W_to_lib(W, n)))
+    v = orbitals(P, 7)
+    ref = fr.G(v)
+    print(name, gauge, flush=True)
+    for orb_sched in (1, 3, 5):
+        P.op.tune(0, orb_sched, 65536)
+        out = torch.zeros((P.NE, n), dtype=torch.complex128, device="cuda")
+        P.op.rhs_apply(dev(P.to_lib_orb(v)), out)
+        got = P.from_lib_dof(host(out))
+        assert rel_err_cols(got, ref) < 1e-10 and max_rel_cols(got, ref) < 1e-10, orb_sched
+    P.op.tune(0, 1, 65536)
+
+
+def _oracle_run(P, c, C, cs, E_steps, dt):
+    from oracle.mctdhf import Propagator
+    pr = Propagator(P.ope, cs, poisson_solver(P.ops))
+    recs = []
+    cc, CC = c.copy(), C.copy()
+    for k in range(len(E_steps) - 1):
+        cc, CC, ob = pr.step(cc, CC, E_steps[k], dt, 12)
+        recs.append(ob)
+    recs.append(pr.final_observables(cc, CC, E_steps[-1]))
+    return cc, CC, recs
+
+
+@pytest.mark.parametrize("name,gauge", [("ecs_q2", "length"), ("ecs_q2", "velocity"), ("ecs_n3", "length"),
+                                        ("ecs_q3", "velocity"), ("kelly_ecs_q1", "length")])
+def test_propagate_ecs(name, gauge):
+    """Three steps under a field: records, orbitals and the CI vector (no
+    longer of unit norm) against the oracle."""
+    torch = _torch()
+    from oracle.ci import CISpace
+    P = pair(name, gauge, poisson_rtol=1e-13, poisson_maxit=20000)
+    n = P.w["n_orb"]
+    cs = CISpace(n, P.w["n_alpha"], P.w["n_beta"])
+    c = orbitals(P, 10)
+    C = random_ci(cs.dim, 11)
+    dt = 0.05
+    F_steps = [0.3 * np.sin(0.5 * k + 0.2) for k in range(4)]
+    x, Cd = dev(P.to_lib_orb(c)), dev(C)
+    W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+    print(name, gauge, flush=True)
+    rec = P.op.propagate(x, Cd, W, F_steps, dt, m=12)
+    cc, CC, recs = _oracle_run(P, c, C, cs, F_steps, dt)
+    for key in ("dipole", "energy", "momentum"):
+        ref = np.array([r[key] for r in recs])
+        diff = np.max(np.abs(rec[key] - ref)) / max(np.abs(ref).max(), 1e-3)
+        print(name, key, diff, flush=True)
+        assert diff <= 1e-8, key
+    assert rel_err_cols(P.from_lib_dof(host(x)), cc) < 1e-8
+    Cg = host(Cd)
+    assert np.max(np.abs(Cg - CC)) < 1e-8
+    assert abs(np.linalg.norm(Cg) - 1.0) > 1e-8          # the scaled operator moved the norm
+    # orthonormality drifts at first order in dt (frozen lam), as without scaling
+    ortho = np.array([np.abs(r["overlap"] - np.eye(n)).max() for r in recs])
+    assert np.max(np.abs(rec["ortho"] - ortho)) < 1e-10
+
+
+def test_batch_mixes_scaled_and_plain_instances():
+    """A batch of the scaled and the unscaled operator on one mesh: each
+    instance equals its own single-operator run."""
+    torch = _torch()
+    import paper_2301_02387_amd as mh
+    from oracle.ci import CISpace
+    P = pair("ecs_q2", poisson_rtol=1e-13, poisson_maxit=20000)
+    w = P.w
+    e = (w["ecs"]["theta"], w["ecs"]["inner"])
+    kw = dict(polarization=w["polarization"], poisson_rtol=1e-13, poisson_maxit=20000)
+    plain = mh.Operator(P.mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], **kw)
+    B = mh.Operator.batch([P.mesh, P.mesh], [w["nuclei"], w["nuclei"]], w["n_orb"], w["n_alpha"], w["n_beta"],
+                          ecs=[e, None], **kw)
+    n = w["n_orb"]
+    cs = CISpace(n, w["n_alpha"], w["n_beta"])
+    c = P.to_lib_orb(orbitals(P, 20))
+    C = random_ci(cs.dim, 21)
+    F_steps = [0.0, 0.2, 0.1]
+    outs = []
+    for op in (P.op, plain):
+        x, Cd = dev(c), dev(C)
+        W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+        rec = op.propagate(x, Cd, W, F_steps, 0.05, m=12)
+        outs.append((host(x), host(Cd), rec))
+    xb, Cb = dev(np.concatenate([c, c])), dev(np.stack([C, C]))
+    Wb = torch.zeros((2 * P.NF, n * n), dtype=torch.float64, device="cuda")
+    recb = B.propagate(xb, Cb, Wb, F_steps, 0.05, m=12)
+    xb, Cb = host(xb), host(Cb)
+    for i, (x1, C1, r1) in enumerate(outs):
+        assert rel_err_cols(xb[i * P.NE:(i + 1) * P.NE], x1) < 1e-10
+        assert np.max(np.abs(Cb[i] - C1)) < 1e-10
+        for key in ("dipole", "energy"):
+            assert np.max(np.abs(recb[key][:, i] - r1[key])) < 1e-10 * max(np.abs(r1[key]).max(), 1e-3), (i, key)
+    assert abs(np.linalg.norm(outs[0][1]) - np.linalg.norm(outs[1][1])) > 1e-8
+
+
+def test_ecs_rejections():
+    """Straddling cells, nuclei outside the unscaled cuboid, hanging nodes or
+    masters in scaled cells and bad angles are refused at set-up; the adjoint
+    refuses a scaled operator."""
+    torch = _torch()
+    import paper_2301_02387_amd as mh
+    P = pair("ecs_q2")
+    w = P.w
+    args = (P.mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"])
+    for ecs, msg in (((0.3, (3.0, 8.0, 8.0)), "straddles"), ((0.3, (4.0, 4.0, 4.0)), "touches a scaled cell"),
+                     ((0.3, (8.0, 8.0, 0.0)), "nucleus"), ((1.7, (8.0, 8.0, 8.0)), "ecs_theta")):
+        with pytest.raises(mh.MHError) as ex:
+            mh.Operator(*args, ecs=ecs)
+        assert ex.value.code == -1 and msg in str(ex.value), (ecs, str(ex.value))
+    n = w["n_orb"]
+    x = dev(P.to_lib_orb(orbitals(P, 3)))
+    C = dev(random_ci(4, 2))
+    W = torch.zeros((P.NF, n * n), dtype=torch.float64, device="cuda")
+    with pytest.raises(mh.MHError) as ex:
+        P.op.propagate_adjoint(x, C, W, [0.0, 0.1, 0.2], 0.02, np.ones(3))
+    assert ex.value.code == -6
