@@ -87,24 +87,30 @@ def poisson_algorithmic_bytes(info, op, fused=False):
     return b
 
 
-def rhs_algorithmic_bytes(info, op):
+def rhs_algorithmic_bytes(info, op, ecs=False):
     """B_G: bytes one orbital right-hand-side evaluation must move: the packed
     vector in and G v out (16 B per complex entry each), the per-node
     Hermitian mean-field matrix U (n^2 reals per full node), the per-node
     potential and dipole weights, the cell->node maps, the constraint rows and
-    1/m of the unknowns.  The interface mass system is cache-resident."""
+    1/m of the unknowns.  The interface mass system is cache-resident.  With
+    complex scaling the potential and field weights are complex and the row
+    factor rho and a byte per cell join them."""
     P3 = (info["p"] + 1) ** 3
     n, N, NF, nC = op.n_orb, op.n_dof, info["n_full"], info["n_cells"]
-    return 32 * n * N + 8 * n * n * NF + 16 * NF + 4 * P3 * nC + 12 * info["hang_nnz"] + 8 * N
+    extra = 32 * op.n_ext + nC if ecs else 0
+    return 32 * n * N + 8 * n * n * NF + 16 * NF + 4 * P3 * nC + 12 * info["hang_nnz"] + 8 * N + extra
 
 
-def orbital_pass_bytes(info, op):
+def orbital_pass_bytes(info, op, ecs=False):
     """Algorithmic bytes of the orbital operator's node pass alone (kernel
-    timing slot 0): orbitals in and out, U, the node tables."""
+    timing slot 0): orbitals in and out, U, the node tables (with complex
+    scaling also the complex row factor, potential and field weights and the
+    cells' scaled directions)."""
     P = info["p"] + 1
     nC, NE, N, n = info["n_cells"], op.n_ext, op.n_dof, op.n_orb
     meta = 32 * NE + 4 * P ** 3 * nC + 8 * nC + 4 * N
-    return 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + meta
+    extra = 32 * NE + nC if ecs else 0
+    return 32 * n * NE + 8 * n * n * NE + 24 * NE + 8 * N + meta + extra
 
 
 def copy_bandwidth(torch, gib=2, reps=10):
@@ -237,13 +243,16 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
     workload; returns the bench record."""
     import numpy as np
     import paper_2301_02387_amd as mh
-    from synth import pulse, pulse_triangular, OMEGA_800NM
+    from synth import pulse, pulse_triangular, vector_potential_triangular, OMEGA_800NM
 
     w = _workload(name)
+    gauge = w.get("gauge", "length")
+    ecs = w.get("ecs")
     t_setup = time.perf_counter()
     mesh = mh.Mesh.from_workload(w)
     op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"],
-                     polarization=w.get("polarization", (0.0, 0.0, 1.0)), poisson_rtol=1e-12, poisson_maxit=20000)
+                     polarization=w.get("polarization", (0.0, 0.0, 1.0)), poisson_rtol=1e-12, poisson_maxit=20000,
+                     gauge=gauge, ecs=(ecs["theta"], ecs["inner"]) if ecs else None)
     t_setup = time.perf_counter() - t_setup
     log(f"{name}: set up in {t_setup:.1f} s, {op.n_dof} unknowns")
     info = mesh.info
@@ -259,8 +268,9 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
     if args.warmup > 0:
         op.propagate(phi, Ci, W, [0.0] * (args.warmup + 1), 0.05, m=m, imaginary=True, final=False)
     t0 = Tp / 2   # the pulse peak
-    if w.get("envelope") == "triangular":
-        E = [float(pulse_triangular(t0 + k * dt, w["E0"], omega)) for k in range(args.steps + 1)]
+    if w.get("envelope") == "triangular":   # field values: E(t), or A(t) in the velocity gauge
+        fv = vector_potential_triangular if gauge == "velocity" else pulse_triangular
+        E = [float(fv(t0 + k * dt, w["E0"], omega)) for k in range(args.steps + 1)]
     else:
         E = [float(pulse(t0 + k * dt, w["E0"], w["cycles"], omega)) if w["cycles"] else 0.0
              for k in range(args.steps + 1)]
@@ -311,14 +321,14 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
         byts = poisson_algorithmic_bytes(info, op, fused)
         over = stored_matrix_bytes(op.n_dof, op.n_poisson_nnz, op.n_inst)
     else:
-        byts, over = orbital_pass_bytes(info, op), 0
+        byts, over = orbital_pass_bytes(info, op, bool(ecs)), 0
     sched_tag = "/".join(map(str, sched["poisson"] if dom == "poisson_spmv" else sched["orbital"]))
     ach = byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if kern[dom]["avg_ms"] > 0 else 0.0
     wl = (f"{name}_{op.n_dof}dof_{op.n_orb}orb" if name.endswith(f"_q{w['p']}")
           else f"{name}_q{w['p']}_{op.n_dof}dof_{op.n_orb}orb")
-    bg = rhs_algorithmic_bytes(info, op)
+    bg = rhs_algorithmic_bytes(info, op, bool(ecs))
     rhs_ach = bg / (rhs_ms * 1e-3) / 1e9
-    orb_b = orbital_pass_bytes(info, op)
+    orb_b = orbital_pass_bytes(info, op, bool(ecs))
     orb_ach = orb_b / (k_orb[0] * 1e-3) / 1e9 if k_orb[0] > 0 else 0.0
     line = {
         "metric": "orbital-RHS evals/s (DoF x orbitals/s)",
@@ -338,6 +348,9 @@ def run_single(name, args, torch, with_adjoint, with_cpu):
                             + ", ".join(f"{(w['hi'] - w['lo']) / w['n_coarse'] / 2 ** l:g}"
                                         for l, c in enumerate(info["level_counts"]) if c)) if w.get("kelly")
                    else "ball refinement",
+                   "gauge": gauge,
+                   "absorber": (f"exterior complex scaling, {ecs['theta']} rad beyond |x_d| = "
+                                + "/".join(f"{r:g}" for r in ecs["inner"])) if ecs else "none (Dirichlet box)",
                    "n_orb": op.n_orb, "n_ci": op.n_ci, "krylov": m, "dt": dt, "graph": bool(args.graph),
                    "graph_step": bool(args.graph_step), "parallelism": "none (one GPU)"},
         "arnoldi_step_ms": arnoldi_ms,

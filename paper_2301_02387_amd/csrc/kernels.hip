@@ -1781,11 +1781,12 @@ void launch_ginv(int ni, const double* gamma, int n, double eps, double* ginv, i
 
 // out[i]: [0] energy, [1] dipole, [2] max |S - I|, [3] kinetic momentum along
 // e (sum gamma_pq <phi_p|-i S_e|phi_q>, plus N A in the velocity gauge)
-__global__ void k_observe(const DevMesh* __restrict__ dm, const double2* __restrict__ gamma,
-                          const double2* __restrict__ Gamma, const double2* __restrict__ h,
-                          const double2* __restrict__ g, const double2* __restrict__ z, const double2* __restrict__ S,
-                          const double2* __restrict__ pm, const double* __restrict__ Ef, double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(NT) k_observe(const DevMesh* __restrict__ dm, const double2* __restrict__ gamma,
+                                                const double2* __restrict__ Gamma, const double2* __restrict__ h,
+                                                const double2* __restrict__ g, const double2* __restrict__ z,
+                                                const double2* __restrict__ S, const double2* __restrict__ pm,
+                                                const double* __restrict__ Ef, double* __restrict__ out) {
+  __shared__ double lds4[4];
   const int inst = blockIdx.x;
   const DevMesh& d = dm[inst];
   const int n = d.n, nn = n * n;
@@ -1797,17 +1798,27 @@ __global__ void k_observe(const DevMesh* __restrict__ dm, const double2* __restr
   S += (int64_t)inst * nn;
   pm += (int64_t)inst * nn;
   out += 8 * inst;
-  double e1 = 0.0, e2 = 0.0, dip = 0.0, orth = 0.0, mom = 0.0, tr = 0.0;
-  for (int i = 0; i < nn; ++i) {
+  // Re sum h gamma, Re sum gamma z, Re sum gamma p, tr gamma and Re sum g Gamma over the block
+  double e1 = 0.0, e2 = 0.0, dip = 0.0, mom = 0.0, tr = 0.0;
+  for (int i = threadIdx.x; i < nn; i += NT) {
     e1 += h[i].x * gamma[i].x - h[i].y * gamma[i].y;
     dip += gamma[i].x * z[i].x - gamma[i].y * z[i].y;
     mom += gamma[i].x * pm[i].x - gamma[i].y * pm[i].y;
     if (i % (n + 1) == 0) tr += gamma[i].x;
-    int p = i / n, q = i % n;
-    double dx = S[i].x - (p == q ? 1.0 : 0.0);
+  }
+  for (int i = threadIdx.x; i < nn * nn; i += NT) e2 += g[i].x * Gamma[i].x - g[i].y * Gamma[i].y;
+  e1 = block_sum_all(e1, lds4);
+  e2 = block_sum_all(e2, lds4);
+  dip = block_sum_all(dip, lds4);
+  mom = block_sum_all(mom, lds4);
+  tr = block_sum_all(tr, lds4);
+  if (threadIdx.x != 0) return;
+  double orth = 0.0;
+  for (int i = 0; i < nn; ++i) {
+    const int p = i / n, q = i % n;
+    const double dx = S[i].x - (p == q ? 1.0 : 0.0);
     orth = fmax(orth, hypot(dx, S[i].y));
   }
-  for (int i = 0; i < nn * nn; ++i) e2 += g[i].x * Gamma[i].x - g[i].y * Gamma[i].y;
   out[0] = e1 + 0.5 * e2 + d.vnn;
   out[1] = dip;
   out[2] = orth;
@@ -1817,7 +1828,7 @@ __global__ void k_observe(const DevMesh* __restrict__ dm, const double2* __restr
 void launch_observe(const Batch& b, const double* gamma, const double* Gamma, const double* h, const double* g,
                     const double* zmat, const double* S, const double* pmat, const double* Ef, double* out,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_observe, dim3(b.ni), dim3(64), 0, s, b.dm, (const double2*)gamma, (const double2*)Gamma,
+  hipLaunchKernelGGL(k_observe, dim3(b.ni), dim3(NT), 0, s, b.dm, (const double2*)gamma, (const double2*)Gamma,
                      (const double2*)h, (const double2*)g, (const double2*)zmat, (const double2*)S,
                      (const double2*)pmat, Ef, out);
 }

@@ -78,7 +78,13 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
   const bool stiff = diag_mode <= 2;
   const double Elen = d.gauge == 1 ? 0.0 : E;   // the length-gauge term only in the length gauge
   const bool ecs_i = ECS && d.ecs && diag_mode <= 2;
-  auto pw = [&](int k) { return make_double2(d.ecs_pw[2 * k + 4], d.ecs_pw[2 * k + 5]); };  // e^{i k theta}
+  // e^{i k theta}, k = -2..3, staged in LDS: the cells pick their factors by a per-lane index
+  __shared__ double2 spw[6];
+  if (ECS) {
+    if (threadIdx.x < 6) spw[threadIdx.x] = make_double2(d.ecs_pw[2 * threadIdx.x], d.ecs_pw[2 * threadIdx.x + 1]);
+    __syncthreads();
+  }
+  auto pw = [&](int k) { return spw[k + 2]; };
   const XcdSweep sw = xcd_sweep(d.NE, NT / L, d.sched_orb & 1);
   // all L lanes of a node share i, so a node group enters and leaves together
   for (int64_t i = sw.start + threadIdx.x / L; i < sw.end; i += sw.step) {
@@ -112,19 +118,27 @@ __global__ void __launch_bounds__(NT) k_stencil_orb(const DevMesh* __restrict__ 
       for (int q = 0; q < P; ++q) {
         const int j0 = cn[(c * P + b) * P + q], j1 = cn[(c * P + q) * P + a], j2 = cn[(q * P + b) * P + a];
         const double A0 = d.A[a * P + q], A1 = d.A[b * P + q], A2 = d.A[c * P + q];
+        // the point q of a line through the node that is the node itself
+        // (q == a along x, ...) takes its value from the register, not memory
         if (act) {
           if (j0 < d.NE) {
-            const double2 v = u[(int64_t)j0 * n + p];
+            double2 v;
+            if (q == a) v = ui;
+            else v = u[(int64_t)j0 * n + p];
             s0.x += A0 * v.x; s0.y += A0 * v.y;
             if (VEL) { const double Q = d.Qs[a * P + q]; t0.x += Q * v.x; t0.y += Q * v.y; }
           }
           if (j1 < d.NE) {
-            const double2 v = u[(int64_t)j1 * n + p];
+            double2 v;
+            if (q == b) v = ui;
+            else v = u[(int64_t)j1 * n + p];
             s1.x += A1 * v.x; s1.y += A1 * v.y;
             if (VEL) { const double Q = d.Qs[b * P + q]; t1.x += Q * v.x; t1.y += Q * v.y; }
           }
           if (j2 < d.NE) {
-            const double2 v = u[(int64_t)j2 * n + p];
+            double2 v;
+            if (q == c) v = ui;
+            else v = u[(int64_t)j2 * n + p];
             s2.x += A2 * v.x; s2.y += A2 * v.y;
             if (VEL) { const double Q = d.Qs[c * P + q]; t2.x += Q * v.x; t2.y += Q * v.y; }
           }

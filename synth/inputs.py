@@ -17,7 +17,9 @@ Workloads (atomic units):
             by Kelly's indicator of the nuclear potential (threshold 0.005,
             softening 0.05 bohr) down to edge 0.125 bohr (six cell sizes);
             CAS(10e, 8o); triangular 2-cycle pulse along x, 400 nm,
-            8e14 W/cm^2 (E0 = 0.150982), dt = 0.01.
+            8e14 W/cm^2 (E0 = 0.150982), dt = 0.01; velocity gauge (field
+            values A(t)); exterior complex scaling at 0.3 rad beyond
+            |x_d| = 44 (the refined cells end at 40, one 4-bohr layer inside).
   h2_batch  64 H2 instances, bond length ~ U[1,2], depth ~ {2,3,4},
             E0 ~ U[0.02, 0.06], drawn from default_rng(2301) in that order.
 
@@ -63,7 +65,8 @@ def workload(name):
         return dict(name=name, lo=-64.0, hi=64.0, n_coarse=32, p=1, balls=[],
                     kelly=dict(nuclei=nuclei, tol=0.005, soft=0.05, max_level=5),
                     nuclei=nuclei, n_orb=8, n_alpha=5, n_beta=5, dt=0.01, krylov=12,
-                    E0=E0_8E14, cycles=2, omega=OMEGA_400NM, envelope="triangular", polarization=(1.0, 0.0, 0.0))
+                    E0=E0_8E14, cycles=2, omega=OMEGA_400NM, envelope="triangular", polarization=(1.0, 0.0, 0.0),
+                    gauge="velocity", ecs=dict(theta=0.3, inner=(44.0, 44.0, 44.0)))
     raise KeyError(name)
 
 
@@ -172,6 +175,19 @@ def pulse_triangular(t, E0, omega=OMEGA_400NM):
     env = np.where((ph >= 0) & (ph <= 2 * np.pi), ph / (2 * np.pi),
                    np.where((ph > 2 * np.pi) & (ph <= 4 * np.pi), (4 * np.pi - ph) / (2 * np.pi), 0.0))
     return E0 * env * np.sin(ph)
+
+
+def vector_potential_triangular(t, E0, omega=OMEGA_400NM):
+    """A(t) = -int_0^t E of the triangular pulse, in closed form: with
+    phi = omega t and c = E0 / (2 pi omega), int_0^t E = c (sin phi -
+    phi cos phi) over the rising cycle and c ((phi - 4 pi) cos phi - sin phi)
+    over the falling one, which ends at zero; zero outside the pulse."""
+    t = np.asarray(t, dtype=float)
+    ph = np.clip(omega * t, 0.0, 4 * np.pi)
+    c = E0 / (2 * np.pi * omega)
+    rise = np.sin(ph) - ph * np.cos(ph)
+    fall = (ph - 4 * np.pi) * np.cos(ph) - np.sin(ph)
+    return -c * np.where(ph <= 2 * np.pi, rise, fall)
 
 
 def gaussian_orbitals(xyz, centers_exps, coeffs):

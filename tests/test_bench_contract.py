@@ -54,3 +54,18 @@ def test_traffic_only_for_unchanged_sources(tmp_path):
     (csrc / "api.hip").write_text("a new source file\n")
     assert traffic() is None
 
+
+
+def test_vector_potential_is_minus_the_field_integral():
+    """The velocity-gauge field values of the triangular pulse: A(t) equals
+    minus the running integral of E(t) (trapezoid rule on a fine grid), starts
+    and ends at zero."""
+    import numpy as np
+    from scipy.integrate import cumulative_trapezoid
+    from synth import vector_potential_triangular, pulse_triangular, OMEGA_400NM, E0_8E14
+    T = 4 * np.pi / OMEGA_400NM
+    t = np.linspace(-1.0, 1.1 * T, 200001)
+    ref = -cumulative_trapezoid(pulse_triangular(t, E0_8E14), t, initial=0.0)
+    A = vector_potential_triangular(t, E0_8E14)
+    assert np.abs(A - ref).max() < 1e-8 * np.abs(ref).max()
+    assert A[0] == 0.0 and abs(A[-1]) < 1e-12
