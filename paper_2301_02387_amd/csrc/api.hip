@@ -471,6 +471,8 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   op->dh.resize(ni);
   DevMesh& mx = B.mx;
   int64_t oE = 0, oF = 0, oMa = 0;
+  std::vector<std::vector<float>> keep_f;
+  keep_f.reserve(ni);
   for (int i = 0; i < ni; ++i) {
     const Mesh& M = op->Ms[i];
     const OpHost& H = op->Hs[i];
@@ -519,6 +521,8 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
     d.kt_ptr = op->upload(H.kt_ptr, s);
     d.kt_col = op->upload(H.kt_col, s);
     d.kt_val = op->upload(H.kt_val, s);
+    keep_f.emplace_back(H.kt_val.begin(), H.kt_val.end());   // host copy alive until the final synchronisation
+    d.kt_valf = op->upload(keep_f.back(), s);
     {
       std::vector<int32_t> lr;
       for (int64_t r = 0; r < d.N; ++r)
@@ -1656,6 +1660,8 @@ static void build_sell(mh_op* op, int i, hipStream_t s) {
   d.sell_row = op->upload(row, s);
   d.sell_col = op->upload(col, s);
   d.sell_val = op->upload(val, s);
+  const std::vector<float> valf(val.begin(), val.end());
+  d.sell_valf = op->upload(valf, s);
   d.n_slices = (int64_t)ptr.size() - 1;
   HIPCHK(hipStreamSynchronize(s));  // the host tables are temporaries
 }

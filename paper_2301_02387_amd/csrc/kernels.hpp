@@ -67,6 +67,11 @@ struct DevMesh {
   const int32_t* sell_col = nullptr;
   const double* sell_val = nullptr;
   int64_t n_slices = 0;
+  // the same values rounded to float, read by the passes of the multigrid
+  // preconditioner's finest level on float storage (Poisson schedule bit 6);
+  // the CG's own operator pass reads the double values
+  const float* kt_valf = nullptr;
+  const float* sell_valf = nullptr;
   const int32_t* bnd_cells = nullptr;
   int64_t n_bnd_cells = 0;
   const double* bnd_table = nullptr;    // [Nb][nharm] multipole boundary table

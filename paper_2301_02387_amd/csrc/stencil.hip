@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "devutil.hpp"
 #include "kernels.hpp"
@@ -458,6 +459,7 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const T* __restr
                                               int beg, int end, int stride, double* y) {
   const auto* kcol = gbl(d.kt_col);
   const auto* kval = gbl(d.kt_val);
+  const auto* kvalf = gbl(d.kt_valf);   // the float passes read the float copy
   const auto* xg = gbl(x);
   const auto* pg = gbl(pprev);
   const auto* dinv = gbl(d.kdiag_inv);
@@ -469,7 +471,9 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const T* __restr
       const int tt = t + u * stride;
       const int tc = tt < end ? tt : end - 1;
       const int64_t j = kcol[tc];
-      const double a = kval[tc];
+      double a;
+      if constexpr (std::is_same<T, float>::value) a = kvalf[tc];
+      else a = kval[tc];
       av[u] = tt < end ? a : 0.0;
       operand_row<V, MODE, T>(xg, pg, dinv, beta, j, ld, c0, xv[u]);
     }
@@ -628,6 +632,7 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
     const auto* srow = gbl(d.sell_row);
     const auto* scol = gbl(d.sell_col);
     const auto* sval = gbl(d.sell_val);
+    const auto* svalf = gbl(d.sell_valf);   // the float passes read the float copy
     const auto* xg = gbl(x);
     const auto* pg = gbl(pprev);
     const auto* dinv = gbl(d.kdiag_inv);
@@ -646,7 +651,8 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
           const int e = base + (t + h) * SELL_H + slot;
-          av[h] = sval[e];
+          if constexpr (std::is_same<T, float>::value) av[h] = svalf[e];
+          else av[h] = sval[e];
           operand_row<V, MODE, T>(xg, pg, dinv, beta, (int64_t)scol[e], ld, c0, xv[h]);
         }
 #pragma unroll
