@@ -443,9 +443,9 @@ int mh_kernel_timing(mh_op* op, int32_t which, int32_t enable, double* avg_ms, i
  * degree 2.
  * Default sched 13.  Allowed values: 0 to 7 (orbital); any combination of
  * bits 0 to 9 (Poisson).
- * grid_cap: maximum number of workgroups (8..65536 orbital, 8..8192
- * Poisson).  Results do not depend on the schedule (the Poisson p.q partial
- * sums change order only). */
+ * grid_cap: maximum number of workgroups per instance (8..65536).  Results
+ * do not depend on the schedule (the Poisson p.q partial sums change order
+ * only). */
 int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap);
 
 const char* mh_last_error(void);

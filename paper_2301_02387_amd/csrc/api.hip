@@ -1669,7 +1669,7 @@ static void build_sell(mh_op* op, int i, hipStream_t s) {
 extern "C" int mh_tune(mh_op* op, int32_t which, int32_t sched, int32_t grid_cap) {
   if (!op || which < 0 || which > 1 || sched < 0 || (sched & ~(which == 1 ? 1023 : 7)) != 0)
     return fail(MH_INVALID_ARG, "bad schedule");
-  const int cap_max = which == 0 ? 65536 : 8192;
+  const int cap_max = 65536;
   if (grid_cap < 8 || grid_cap > cap_max) return fail(MH_INVALID_ARG, "grid_cap out of range");
   return guarded([&]() -> int {
     HIPCHK(hipDeviceSynchronize());

@@ -54,7 +54,7 @@ def test_candidate_schedules_are_valid():
     for sched, grid in tune.ORB_CANDIDATES + tune.ORB_CANDIDATES_BATCH:
         assert 0 <= sched <= 7 and 8 <= grid <= 65536
     for sched, grid in tune.POI_CANDIDATES + tune.POI_CANDIDATES_WIDE + tune.POI_CANDIDATES_BATCH:
-        assert 0 <= sched <= 1023 and 8 <= grid <= 8192
+        assert 0 <= sched <= 1023 and 8 <= grid <= 65536
         assert not (sched & 64) or (sched & 16)   # float finest level only with the multigrid preconditioner
         assert not (sched & 128) or (sched & 2)   # column blocks bound to XCDs only with column blocks
         assert not (sched & 768) or (sched & 16)  # smoothing degree only with the multigrid preconditioner
