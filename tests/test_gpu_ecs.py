@@ -211,3 +211,56 @@ def test_ecs_rejections():
     with pytest.raises(mh.MHError) as ex:
         P.op.propagate_adjoint(x, C, W, [0.0, 0.1, 0.2], 0.02, np.ones(3))
     assert ex.value.code == -6
+
+
+def test_water_q1_scaling_properties_at_full_size():
+    """The Q1 water workload as benched (Kelly mesh, 195,648 unknowns,
+    velocity gauge, scaling beyond |x_d| = 44), where the oracle cannot run:
+    rows of h1_apply whose cells are all unscaled equal those of the unscaled
+    operator to rounding; without nuclei and field, rows whose cells are all
+    scaled in every direction are e^{-2 i theta} times the unscaled ones
+    (there rho J / eta_d^2 = e^{-2 i theta} for every d)."""
+    torch = _torch()
+    import paper_2301_02387_amd as mh
+    from synth import workload
+    w = workload("h2o_q1")
+    th, inner = w["ecs"]["theta"], np.asarray(w["ecs"]["inner"])
+    mesh = mh.Mesh.from_workload(w)
+    info = mesh.info
+    N, NE = info["n_dof"], info["n_dof"] + info["n_hang"]
+    nodes, level, origin = mesh.cells()
+    h = (w["hi"] - w["lo"]) / w["n_coarse"] / 2.0 ** level
+    lo, hi = origin, origin + h[:, None]
+    out = (lo >= inner[None, :] - 1e-9) | (hi <= -inner[None, :] + 1e-9)
+    scaled_any, scaled_all = out.any(axis=1), out.all(axis=1)
+    touch_any = np.zeros(info["n_full"], bool)
+    touch_any[nodes[scaled_any].ravel()] = True
+    in_all = np.zeros(info["n_full"], bool)
+    in_all[nodes[scaled_all].ravel()] = True
+    not_all = np.zeros(info["n_full"], bool)
+    not_all[nodes[~scaled_all].ravel()] = True
+    plain_rows = np.nonzero(~touch_any[:N])[0]
+    corner_rows = np.nonzero(in_all[:N] & ~not_all[:N])[0]
+    assert len(plain_rows) > 100000 and len(corner_rows) > 1000, (len(plain_rows), len(corner_rows))
+    xyz = mesh.coords()[:NE]
+    c = broad_orbitals(xyz, w["n_orb"], 3, 50.0)
+    kw = dict(polarization=w["polarization"], gauge="velocity")
+    for nuclei, A, check in ((w["nuclei"], 0.2, "plain"), ([], 0.0, "corner")):
+        f = []
+        for ecs in (None, (th, tuple(inner))):
+            op = mh.Operator(mesh, nuclei, w["n_orb"], w["n_alpha"], w["n_beta"], ecs=ecs, **kw)
+            x = dev(c)
+            op.fill_hanging(x)
+            y = torch.zeros((N, w["n_orb"]), dtype=torch.complex128, device="cuda")
+            op.h1_apply(x, A, y)
+            f.append(host(y))
+            del op
+        print(check, flush=True)
+        if check == "plain":
+            d = np.abs(f[1][plain_rows] - f[0][plain_rows]).max()
+            assert d <= 1e-14 * np.abs(f[0][plain_rows]).max(), d
+            far = np.nonzero(touch_any[:N])[0]
+            assert np.abs(f[1][far] - f[0][far]).max() > 1e-3 * np.abs(f[0][far]).max()
+        else:
+            ref = np.exp(-2j * th) * f[0][corner_rows]
+            assert np.abs(f[1][corner_rows] - ref).max() <= 1e-13 * np.abs(ref).max()
