@@ -241,7 +241,8 @@ def test_water_q1_scaling_properties_at_full_size():
     not_all[nodes[~scaled_all].ravel()] = True
     plain_rows = np.nonzero(~touch_any[:N])[0]
     corner_rows = np.nonzero(in_all[:N] & ~not_all[:N])[0]
-    assert len(plain_rows) > 100000 and len(corner_rows) > 1000, (len(plain_rows), len(corner_rows))
+    # the eight corner blocks of 5^3 cubes hold 4^3 interior unknowns each
+    assert len(plain_rows) > 100000 and len(corner_rows) == 512, (len(plain_rows), len(corner_rows))
     xyz = mesh.coords()[:NE]
     c = broad_orbitals(xyz, w["n_orb"], 3, 50.0)
     kw = dict(polarization=w["polarization"], gauge="velocity")
