@@ -376,7 +376,11 @@ void launch_stencil_orb(const Batch& b, const double* u, const double* Ef, int d
   if (asm_k && diag_mode != 3) {
     PoissonWs Pk;
     Pk.red = kred;
-    launch_spmv_poisson(b, u, u, kq, 2 * b.mx.n, kq, Pk, -1, s);
+    // at 2n <= 16 columns the stiffness pass runs best on at most 8192
+    // workgroups, whatever cap the Poisson schedule of the pair columns takes
+    Batch bk = b;
+    bk.mx.grid_poi = std::min(b.mx.grid_poi, 8192);
+    launch_spmv_poisson(bk, u, u, kq, 2 * b.mx.n, kq, Pk, -1, s);
   }
   const double* q = asm_k ? kq : nullptr;
   switch (b.mx.P) {
