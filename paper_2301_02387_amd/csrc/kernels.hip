@@ -940,6 +940,7 @@ __global__ void __launch_bounds__(NT) k_mdot_finish(const double* __restrict__ p
   hcur += (int64_t)i * (m_max + 1);
   scal += 8 * i;
   const int nv = 2 * (k + 1) + 1;
+  if (pass == 2 && scal[6] != 0.0) return;  // one Gram-Schmidt pass was enough (k_orth_decide)
   const double s = sum_partials(part, nblk, nv, v, lds4);
   if (threadIdx.x != 0) return;
   if (v == nv - 1) {
@@ -961,11 +962,30 @@ void launch_mdot(const Batch& b, double* const* V, int k, const double* w, Krylo
                      (double2*)K.H, (double2*)K.hcur, K.scal);
 }
 
+// Whether the first classical Gram-Schmidt pass suffices (Kahan's criterion
+// with 1/sqrt(2), as in Daniel, Gragg, Kaufman and Stewart 1976): with the
+// basis orthonormal, |w - V h|^2 = |w|^2 - sum |h_j|^2 after the first pass;
+// when that keeps at least half of |w|^2 the second pass is skipped
+// (scal[6] = 1): the fused update then forms the norm, and the second
+// update and dot finish return at once.
+__global__ void k_orth_decide(const double2* __restrict__ hcur, double* __restrict__ scal, int k, int m_max) {
+  if (threadIdx.x != 0) return;
+  const int i = blockIdx.x;
+  hcur += (int64_t)i * (m_max + 1);
+  scal += 8 * i;
+  double hs = 0.0;
+  for (int j = 0; j <= k; ++j) hs += hcur[j].x * hcur[j].x + hcur[j].y * hcur[j].y;
+  const double w2 = scal[2];
+  scal[6] = (w2 > 0.0 && w2 - hs >= 0.5 * w2) ? 1.0 : 0.0;
+}
+
 __global__ void __launch_bounds__(NT) k_orth_update(const DevMesh* __restrict__ dm,
                                                     const double2* const* __restrict__ V, int k,
                                                     double2* __restrict__ w, const double2* __restrict__ hcur,
-                                                    int with_norm, int m_max, double* __restrict__ part) {
+                                                    int with_norm, int m_max, double* __restrict__ part,
+                                                    const double* __restrict__ scal) {
   INSTANCE;
+  if (with_norm && scal[8 * blockIdx.y + 6] != 0.0) return;  // the first pass was enough
   __shared__ double lds[8];
   const int n = d.n;
   const int64_t total = d.NE * n, o = d.oE * n;
@@ -994,12 +1014,31 @@ __global__ void __launch_bounds__(NT) k_orth_update(const DevMesh* __restrict__ 
 template <int KM>
 __global__ void __launch_bounds__(NT) k_orth_dot(const DevMesh* __restrict__ dm, const double2* const* __restrict__ V,
                                                  int k, double2* __restrict__ w, const double2* __restrict__ hcur,
-                                                 int m_max, double* __restrict__ part) {
+                                                 int m_max, double* __restrict__ part, const double* __restrict__ scal) {
   INSTANCE;
   __shared__ double lw[NT / 64][2 * KM + 1];
   const int n = d.n;
   const int64_t total = d.NE * n, o = d.oE * n;
   hcur += (int64_t)blockIdx.y * (m_max + 1);
+  if (scal[8 * blockIdx.y + 6] != 0.0) {
+    // single pass: w -= sum_j V_j hcur_j and the partials of |w|_M^2 (layout of
+    // the norm after the second update)
+    double2 h[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) h[j] = (j <= k) ? hcur[j] : make_double2(0.0, 0.0);
+    double nrm = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+      double2 we = w[o + e];
+#pragma unroll
+      for (int j = 0; j < KM; ++j)
+        if (j <= k) we = csub(we, cmul(h[j], ldg2(V[j], o + e)));
+      w[o + e] = we;
+      nrm += gbl(d.m)[e / n] * (we.x * we.x + we.y * we.y);
+    }
+    const double c = block_sum(nrm, &lw[0][0]);
+    if (threadIdx.x == 0) part[blockIdx.y * kpart_stride(gridDim.x, m_max) + blockIdx.x] = c;
+    return;
+  }
   double2 h[KM];
   double hr[KM], hi[KM];
 #pragma unroll
@@ -1068,7 +1107,7 @@ __global__ void k_norm_finish(const double* __restrict__ part, int nblk, int k, 
 
 void launch_orth_update(const Batch& b, double* const* V, int k, double* w, Krylov& K, int pass, hipStream_t s) {
   hipLaunchKernelGGL(k_orth_update, dim3(K.nblk, b.ni), dim3(NT), 0, s, b.dm, (const double2* const*)V, k,
-                     (double2*)w, (const double2*)K.hcur, pass == 2 ? 1 : 0, K.m_max, K.part);
+                     (double2*)w, (const double2*)K.hcur, pass == 2 ? 1 : 0, K.m_max, K.part, (const double*)K.scal);
   if (pass == 2)
     hipLaunchKernelGGL(k_norm_finish, dim3(1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, (double2*)K.H,
                        K.scal);
@@ -1077,18 +1116,20 @@ void launch_orth_update(const Batch& b, double* const* V, int k, double* w, Kryl
 void launch_orth_dot(const Batch& b, double* const* V, int k, double* w, Krylov& K, hipStream_t s) {
   const dim3 g(K.nblk, b.ni);
   const auto* Vc = (const double2* const*)V;
+  const double* sc = K.scal;
+  hipLaunchKernelGGL(k_orth_decide, dim3(b.ni), dim3(64), 0, s, (const double2*)K.hcur, K.scal, k, K.m_max);
   if (k + 1 <= 4)
     hipLaunchKernelGGL(k_orth_dot<4>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur, K.m_max,
-                       K.part);
+                       K.part, sc);
   else if (k + 1 <= 8)
     hipLaunchKernelGGL(k_orth_dot<8>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur, K.m_max,
-                       K.part);
+                       K.part, sc);
   else if (k + 1 <= 13)
     hipLaunchKernelGGL(k_orth_dot<13>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur, K.m_max,
-                       K.part);
+                       K.part, sc);
   else
     hipLaunchKernelGGL(k_orth_dot<KMAX>, g, dim3(NT), 0, s, b.dm, Vc, k, (double2*)w, (const double2*)K.hcur,
-                       K.m_max, K.part);
+                       K.m_max, K.part, sc);
   hipLaunchKernelGGL(k_mdot_finish, dim3(2 * (k + 1) + 1, b.ni), dim3(NT), 0, s, K.part, K.nblk, k, K.m_max, 2,
                      (double2*)K.H, (double2*)K.hcur, K.scal);
 }
