@@ -543,9 +543,12 @@ def run_counters(args):
     else:
         w = _workload(args.workload)
         mesh = mh.Mesh.from_workload(w)
-        op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_maxit=24)
+        ecs = w.get("ecs")
+        op = mh.Operator(mesh, w["nuclei"], w["n_orb"], w["n_alpha"], w["n_beta"], poisson_maxit=24,
+                         polarization=w.get("polarization", (0.0, 0.0, 1.0)), gauge=w.get("gauge", "length"),
+                         ecs=(ecs["theta"], ecs["inner"]) if ecs else None)
         xyz = mesh.coords()[:op.n_ext]
-        c = h2o_guess(xyz) if args.workload == "h2o" else h2_guess(xyz, 0.7)
+        c = h2o_guess(xyz) if args.workload in ("h2o", "h2o_q1") else h2_guess(xyz, 0.7)
         phi = torch.from_numpy(np.ascontiguousarray(c)).cuda()
         op.fill_hanging(phi)
     if args.tune_cache:   # the schedules the bench run tuned for this workload
