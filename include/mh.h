@@ -271,7 +271,7 @@ int mh_rhs_apply(mh_op* op, const double* v, double* Gv, void* stream);
 /* Short-iterative Arnoldi step (Sec. III.B): phi <- exp(-i tau G) phi with
  * the frozen G, Krylov dimension m (<= 24), M-inner product over the packed
  * orbital vector, classical Gram-Schmidt with one re-orthogonalisation
- * (skipped when the first pass keeps at least half of |w|^2),
+ * (skipped when the first pass keeps at least a tenth of |w|),
  * happy breakdown at h_{k+1,k} <= 1e-14 |G v_k|.  tau = (tau_re, tau_im):
  * (dt, 0) real time, (0, -dtau) imaginary time.  err_est (host, may be
  * NULL) receives beta h_{m+1,m} |e_m^T expm(-i tau H_m) e_1|; m_used (host,

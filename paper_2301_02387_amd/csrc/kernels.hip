@@ -962,12 +962,14 @@ void launch_mdot(const Batch& b, double* const* V, int k, const double* w, Krylo
                      (double2*)K.H, (double2*)K.hcur, K.scal);
 }
 
-// Whether the first classical Gram-Schmidt pass suffices (Kahan's criterion
-// with 1/sqrt(2), as in Daniel, Gragg, Kaufman and Stewart 1976): with the
-// basis orthonormal, |w - V h|^2 = |w|^2 - sum |h_j|^2 after the first pass;
-// when that keeps at least half of |w|^2 the second pass is skipped
-// (scal[6] = 1): the fused update then forms the norm, and the second
-// update and dot finish return at once.
+// Whether the first classical Gram-Schmidt pass suffices (the criterion of
+// Daniel, Gragg, Kaufman and Stewart 1976, on the norm kept by the pass):
+// with the basis orthonormal, |w - V h|^2 = |w|^2 - sum |h_j|^2 after the
+// first pass.  One pass leaves the new vector orthogonal to the basis to about
+// eps |w| / |w - V h|, so while the pass keeps at least a tenth of |w|
+// (1/100 of |w|^2) the loss stays within ten rounding units and the second
+// pass is skipped (scal[6] = 1): the fused update then forms the norm, and
+// the second update and dot finish return at once.
 __global__ void k_orth_decide(const double2* __restrict__ hcur, double* __restrict__ scal, int k, int m_max) {
   if (threadIdx.x != 0) return;
   const int i = blockIdx.x;
@@ -976,7 +978,7 @@ __global__ void k_orth_decide(const double2* __restrict__ hcur, double* __restri
   double hs = 0.0;
   for (int j = 0; j <= k; ++j) hs += hcur[j].x * hcur[j].x + hcur[j].y * hcur[j].y;
   const double w2 = scal[2];
-  scal[6] = (w2 > 0.0 && w2 - hs >= 0.5 * w2) ? 1.0 : 0.0;
+  scal[6] = (w2 > 0.0 && w2 - hs >= 0.01 * w2) ? 1.0 : 0.0;
 }
 
 __global__ void __launch_bounds__(NT) k_orth_update(const DevMesh* __restrict__ dm,
