@@ -1086,17 +1086,24 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     if (f32) launch_to_float(P.r, mg.rf, (int64_t)B.tE * ncol, s);  // later residuals by the update pass
     precondition(0);
   }
+  // one instance: each iteration's x += alpha p is deferred to the next
+  // direction pass, which reads p anyway (and to cg_xfinal after the last);
+  // a batch keeps it in the update pass (its instances stop at different
+  // iterations)
+  const bool defer = ni == 1;
+  double* xd = defer ? W : nullptr;
   while (conv == 0 && k < kmax) {
     double* pcur = (k % 2) ? P.p2 : P.p;
     double* pold = (k % 2) ? P.p : P.p2;
+    const int pq_prev = RED_PQ + (k + 1) % 2;   // the p.q slot of iteration k - 1
     if (f32)
       mg_dir(B.dm, ni, N, ncol, zf, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1,
-             RED_RR + k % 2, s);
+             RED_RR + k % 2, xd, pq_prev, s);
     else
       mg_dir(B.dm, ni, N, ncol, z, pold, pcur, P.red, RED_RZ + k % 3, k > 0 ? RED_RZ + (k - 1) % 3 : -1,
-             RED_RR + k % 2, s);
+             RED_RR + k % 2, xd, pq_prev, s);
     launch_cg_apply_plain(B, P, pcur, k, s);
-    launch_cg_update(B, W, P, pcur, k, s, f32 ? mg.rf : nullptr);
+    launch_cg_update(B, W, P, pcur, k, s, f32 ? mg.rf : nullptr, defer ? 0 : 1);
     if (op->cg_done) launch_cg_done(B, P, k, op->rtol, s);  // converged instances skip the rest
     ++k;
     P.it = k;
@@ -1108,6 +1115,8 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     if (conv != 0) break;
     precondition(k);
   }
+  if (defer && k > 0)   // the last iteration's x += alpha p
+    cg_xfinal(B.dm, ni, N, ncol, W, ((k - 1) % 2) ? P.p2 : P.p, P.red, RED_RZ + (k - 1) % 3, RED_PQ + (k - 1) % 2, s);
   if (op->cg_done) launch_zero_int(op->cg_done, ni, s);  // no flag outside the CG
   if (iters) *iters = k;
   if (fixed == 0) op->cg_hint = k;

@@ -241,8 +241,10 @@ void launch_cg_apply_plain(const Batch& b, PoissonWs& P, const double* p, int k,
 // rtol^2 times its largest column's b.b; clear all flags.
 void launch_cg_done(const Batch& b, const PoissonWs& P, int k, double rtol, hipStream_t s);
 void launch_zero_int(int* x, int n, hipStream_t s);
+// upd_x = 0: the x += alpha p of this iteration is left to the next direction
+// pass (mg_dir with x) or to cg_xfinal after the last iteration.
 void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s,
-                      float* rf = nullptr);
+                      float* rf = nullptr, int upd_x = 1);
 void launch_to_float(const double* x, float* y, int64_t nd, hipStream_t s);
 // Multigrid-preconditioned CG on the finest level, in operator passes (the
 // Chebyshev coefficients are each instance's DevMesh::mgc; red: the CG

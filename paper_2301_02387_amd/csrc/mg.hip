@@ -507,41 +507,79 @@ void mg_rz(const DevMesh* dm, int ni, int ncol, const double* r, const double* z
 }
 
 template <class Z>
+// With x (deferred solution update): also x += alpha_{k-1} p_{k-1}, alpha from
+// the r.z slot rz_prev and the p.q slot pq_prev of the previous iteration,
+// while p_{k-1} is read for the direction anyway.
 __global__ void __launch_bounds__(NT) k_mg_dir(const DevMesh* __restrict__ dm, int ncol, const Z* __restrict__ z,
                                                const double* __restrict__ pprev, double* __restrict__ pcur,
-                                               double* __restrict__ red, int rz_cur, int rz_prev, int rr_clear) {
+                                               double* __restrict__ red, int rz_cur, int rz_prev, int rr_clear,
+                                               double* __restrict__ x, int pq_prev) {
   INSTANCE;
   if (d.cg_done && *d.cg_done) return;  // converged instance of a batch CG
-  __shared__ double beta[64];
+  __shared__ double beta[64], alpha[64];
   red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
+  const bool upd = x != nullptr && rz_prev >= 0;
   if (threadIdx.x < (unsigned)ncol) {
-    double bt = 0.0;
+    double bt = 0.0, al = 0.0;
     if (rz_prev >= 0) {
       const double a = red[rz_cur * ncol + threadIdx.x], b = red[rz_prev * ncol + threadIdx.x];
       bt = b != 0.0 ? a / b : 0.0;
+      if (upd) {
+        const double pq = red[pq_prev * ncol + threadIdx.x];
+        al = (pq != 0.0 && b != 0.0) ? b / pq : 0.0;
+      }
     }
     beta[threadIdx.x] = bt;
+    alpha[threadIdx.x] = al;
   }
   __syncthreads();
   z += d.oE * ncol;
   pprev += d.oE * ncol;
   pcur += d.oE * ncol;
+  if (upd) x += d.oF * ncol;
   const int64_t total = d.N * ncol;
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int c = (int)(e % ncol);
-    pcur[e] = (double)z[e] + (beta[c] != 0.0 ? beta[c] * pprev[e] : 0.0);
+    const double pp = pprev[e];
+    pcur[e] = (double)z[e] + (beta[c] != 0.0 ? beta[c] * pp : 0.0);
+    if (upd) x[e] += alpha[c] * pp;
   }
   if (blockIdx.x == 0 && threadIdx.x < (unsigned)ncol) red[rr_clear * ncol + threadIdx.x] = 0.0;
 }
+
+// The deferred solution update of the last CG iteration: x += alpha p with
+// alpha from the r.z slot rz_slot and the p.q slot pq_slot.
+__global__ void __launch_bounds__(NT) k_cg_xfinal(const DevMesh* __restrict__ dm, int ncol, double* __restrict__ x,
+                                                  const double* __restrict__ p, const double* __restrict__ red,
+                                                  int rz_slot, int pq_slot) {
+  INSTANCE;
+  __shared__ double alpha[64];
+  red += (int64_t)blockIdx.y * RED_SLOTS * ncol;
+  if (threadIdx.x < (unsigned)ncol) {
+    const double rz = red[rz_slot * ncol + threadIdx.x], pq = red[pq_slot * ncol + threadIdx.x];
+    alpha[threadIdx.x] = (pq != 0.0 && rz != 0.0) ? rz / pq : 0.0;
+  }
+  __syncthreads();
+  x += d.oF * ncol;
+  p += d.oE * ncol;
+  const int64_t total = d.N * ncol;
+  for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT)
+    x[e] += alpha[e % ncol] * p[e];
+}
+void cg_xfinal(const DevMesh* dm, int ni, int64_t max_n, int ncol, double* x, const double* p, const double* red,
+               int rz_slot, int pq_slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xfinal, dim3(nblocks(max_n * ncol, NT, 8192), ni), dim3(NT), 0, s, dm, ncol, x, p, red,
+                     rz_slot, pq_slot);
+}
 void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const double* z, const double* pprev, double* pcur,
-            double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s) {
+            double* red, int rz_cur, int rz_prev, int rr_clear, double* x, int pq_prev, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_dir<double>, dim3(nblocks(max_n * ncol, NT, 8192), ni), dim3(NT), 0, s, dm, ncol, z, pprev,
-                     pcur, red, rz_cur, rz_prev, rr_clear);
+                     pcur, red, rz_cur, rz_prev, rr_clear, x, pq_prev);
 }
 void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const float* z, const double* pprev, double* pcur,
-            double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s) {
+            double* red, int rz_cur, int rz_prev, int rr_clear, double* x, int pq_prev, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_dir<float>, dim3(nblocks(max_n * ncol, NT, 8192), ni), dim3(NT), 0, s, dm, ncol, z, pprev,
-                     pcur, red, rz_cur, rz_prev, rr_clear);
+                     pcur, red, rz_cur, rz_prev, rr_clear, x, pq_prev);
 }
 
 }  // namespace mh

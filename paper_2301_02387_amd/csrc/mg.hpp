@@ -88,10 +88,14 @@ struct DevMesh;
 void mg_rz(const DevMesh* dm, int ni, int ncol, const double* r, const double* z, double* part, double* red,
            int slot, hipStream_t s);
 // pcur = z + beta pprev per instance and column, beta = red[rz_cur] / red[rz_prev]
-// (rz_prev < 0: beta = 0); clears red[rr_clear]
+// (rz_prev < 0: beta = 0); clears red[rr_clear].  With x (not null, rz_prev >= 0):
+// also the previous iteration's deferred x += (red[rz_prev] / red[pq_prev]) pprev.
 void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const double* z, const double* pprev, double* pcur,
-            double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s);
+            double* red, int rz_cur, int rz_prev, int rr_clear, double* x, int pq_prev, hipStream_t s);
 void mg_dir(const DevMesh* dm, int ni, int64_t max_n, int ncol, const float* z, const double* pprev, double* pcur,
-            double* red, int rz_cur, int rz_prev, int rr_clear, hipStream_t s);
+            double* red, int rz_cur, int rz_prev, int rr_clear, double* x, int pq_prev, hipStream_t s);
+// x += (red[rz_slot] / red[pq_slot]) p: the deferred update of the last iteration
+void cg_xfinal(const DevMesh* dm, int ni, int64_t max_n, int ncol, double* x, const double* p, const double* red,
+               int rz_slot, int pq_slot, hipStream_t s);
 
 }  // namespace mh

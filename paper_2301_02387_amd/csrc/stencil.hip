@@ -821,7 +821,7 @@ static void launch_spmv_mode(const Batch& b, const T* x, const T* pprev, T* pout
 __global__ void __launch_bounds__(NT) k_cg_update2(const DevMesh* __restrict__ dm, double* __restrict__ x,
                                                    double* __restrict__ r, const double* __restrict__ p,
                                                    const double* __restrict__ q, int ncol, double* __restrict__ red,
-                                                   int k, float* __restrict__ rf) {
+                                                   int k, float* __restrict__ rf, int upd_x) {
   INSTANCE;
   if (d.cg_done && *d.cg_done) return;
   __shared__ double lds[2 * NT];
@@ -841,7 +841,7 @@ __global__ void __launch_bounds__(NT) k_cg_update2(const DevMesh* __restrict__ d
     const double al = (pq != 0.0 && rz0 != 0.0) ? rz0 / pq : 0.0;
     for (int64_t kk = (int64_t)blockIdx.x * groups + g; kk < d.N; kk += (int64_t)gridDim.x * groups) {
       const int64_t e = kk * ncol + c;
-      x[e] += al * p[e];
+      if (upd_x) x[e] += al * p[e];   // else deferred to the next direction pass
       const double rn = r[e] - al * q[e];
       r[e] = rn;
       if (rf) rf[e] = (float)rn;  // the finest multigrid level's float copy (Poisson schedule bit 6)
@@ -1012,7 +1012,7 @@ void launch_cg_step(const Batch& b, double* W, PoissonWs& P, hipStream_t s) {
   }
   const int nb = cg_blocks(b, ncol);
   hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, pcur, P.q, ncol, P.red, k,
-                     (float*)nullptr);
+                     (float*)nullptr, 1);
   P.it = k + 1;
 }
 
@@ -1090,9 +1090,10 @@ void launch_zero_int(int* x, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_zero_int, dim3(nblocks(n)), dim3(NT), 0, s, x, n);
 }
 
-void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s, float* rf) {
+void launch_cg_update(const Batch& b, double* W, PoissonWs& P, const double* p, int k, hipStream_t s, float* rf,
+                      int upd_x) {
   const int nb = cg_blocks(b, P.ncol);
-  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, p, P.q, P.ncol, P.red, k, rf);
+  hipLaunchKernelGGL(k_cg_update2, dim3(nb, b.ni), dim3(NT), 0, s, b.dm, W, P.r, p, P.q, P.ncol, P.red, k, rf, upd_x);
 }
 
 __global__ void __launch_bounds__(NT) k_to_float(const double* __restrict__ x, float* __restrict__ y, int64_t nd) {
