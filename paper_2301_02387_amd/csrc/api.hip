@@ -654,6 +654,10 @@ static mh_op* create_batch(const std::vector<InstanceSpec>& spec, const mh_op_de
   launch_zero(P.sc, (size_t)ni * 8 * ncol, s);
   P.red = op->alloc<double>((size_t)ni * RED_SLOTS * ncol);
   launch_zero(P.red, (size_t)ni * RED_SLOTS * ncol, s);
+  if (ni == 1) {  // the largest operator-pass grid (65,536 sweeping and up to 2,056 long-row workgroups)
+    B.spart_cap = (int64_t)(65536 + 4096) * std::max(ncol, 2 * n);
+    B.spart = op->alloc<double>((size_t)B.spart_cap);
+  }
   P.part_stride = (int64_t)8192 * 2 * ncol;
   P.part = op->alloc<double>((size_t)ni * P.part_stride);
   P.Q = op->alloc<double>((size_t)ni * P.nharm * ncol);

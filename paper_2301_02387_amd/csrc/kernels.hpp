@@ -123,6 +123,11 @@ struct Batch {
   DevMesh mx;                   // host: shared fields, per-class maximum sizes
   int64_t tE = 0, tF = 0, tMa = 0;  // batch totals of extended, full and master rows
   int cheb_iters = 0;           // Chebyshev iterations (the largest instance count)
+  // one instance: the Poisson operator passes leave their per-workgroup p.q
+  // (r.z) sums here, [workgroup][column], folded by a second small launch
+  // instead of every workgroup adding into the same accumulators
+  double* spart = nullptr;
+  int64_t spart_cap = 0;        // doubles
 };
 
 // ---- orbital-space operator -------------------------------------------------

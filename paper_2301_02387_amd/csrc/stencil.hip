@@ -563,10 +563,10 @@ template <int L, int V, int MODE, bool SELL, class T>
 __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__ dm, const T* __restrict__ x,
                                                      const T* __restrict__ pprev, T* __restrict__ pout,
                                                      int ld, int nc, T* __restrict__ q, int nlb,
-                                                     double* __restrict__ red, int k) {
+                                                     double* __restrict__ red, int k, double* __restrict__ part) {
   constexpr bool FUSE = MODE == SP_CG;
   INSTANCE;
-  if (d.cg_done && *d.cg_done) return;  // converged instance of a batch CG
+  if (d.cg_done && *d.cg_done) return;  // converged instance of a batch CG (batches take no partials)
   __shared__ double lds[NT * V];
   // column block: blockIdx.z, or with schedule bit 7 the XCD's (xcd_sweep_cols;
   // the grid then runs all column blocks along x)
@@ -697,17 +697,39 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) sum += lds[w * (L * V) + threadIdx.x];
-    if constexpr (MODE == SP_CHEB_RZ) {
+    if (part) {
+      part[(int64_t)blockIdx.x * nc + threadIdx.x] = sum;  // folded by k_fold_parts
+    } else if constexpr (MODE == SP_CHEB_RZ) {
       atomicAdd(red + (k & 15) * ld + threadIdx.x, sum);  // r.z of this instance and column
     } else {
       // iteration of this pass: k (fused), -2 - k (plain pass of a CG iteration), 0 (k = -1: start)
       const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
       atomicAdd(red + (RED_PQ + kk % 2) * ld + threadIdx.x, sum);  // p.q of this instance and column
-      if (FUSE && first_wg) {  // clear what the update pass of this iteration accumulates into
-        red[(RED_RZ + (k + 1) % 3) * ld + threadIdx.x] = 0.0;
-        red[(RED_RR + k % 2) * ld + threadIdx.x] = 0.0;
-      }
     }
+    if (FUSE && first_wg) {  // clear what the update pass of this iteration accumulates into
+      red[(RED_RZ + (k + 1) % 3) * ld + threadIdx.x] = 0.0;
+      red[(RED_RR + k % 2) * ld + threadIdx.x] = 0.0;
+    }
+  }
+}
+
+// dst[c] += sum over the rows workgroups w of part[w][c] (one instance; nc
+// divides NT): the per-workgroup sums of an operator pass, added with a few
+// hundred atomics where the pass itself would issue one per workgroup and
+// column, all on the same nc addresses.
+__global__ void __launch_bounds__(NT) k_fold_parts(const double* __restrict__ part, int rows, int nc,
+                                                   double* __restrict__ dst) {
+  __shared__ double lds[NT];
+  const int per = NT / nc;
+  const int c = (int)threadIdx.x % nc, g = (int)threadIdx.x / nc;
+  double s = 0.0;
+  for (int64_t w = (int64_t)blockIdx.x * per + g; w < rows; w += (int64_t)gridDim.x * per) s += part[w * nc + c];
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nc) {
+    double t = 0.0;
+    for (int j = 0; j < per; ++j) t += lds[j * nc + threadIdx.x];
+    atomicAdd(dst + threadIdx.x, t);
   }
 }
 
@@ -719,6 +741,10 @@ static int long_row_blocks(const Batch& b) {
   const int64_t nb = std::min<int64_t>((b.mx.n_long + 2 * (NT / 64) - 1) / (2 * (NT / 64)), 2048);
   return (int)((nb + N_XCD - 1) / N_XCD * N_XCD);
 }
+
+// Set by the timed operator pass: the end event, recorded right after the pass
+// kernel and before its fold, so the event pair spans that kernel alone.
+static thread_local hipEvent_t t_pass_end = nullptr;
 
 template <int L, int V, int MODE, class T>
 static void launch_spmv_m(const Batch& b, const T* x, const T* pprev, T* pout, int ld, int nc, T* q, double* red,
@@ -733,21 +759,33 @@ static void launch_spmv_m(const Batch& b, const T* x, const T* pprev, T* pout, i
     const dim3 g(nlb + sweep * nbc, b.ni, 1);
     if (b.mx.sched_poi & 32)
       hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, true, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
-                         nlb, red, k);
+                         nlb, red, k, (double*)nullptr);
     else
       hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, false, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
-                         nlb, red, k);
+                         nlb, red, k, (double*)nullptr);
+    if (t_pass_end) (void)hipEventRecord(t_pass_end, s);
     return;
   }
   const int nlb = long_row_blocks(b);
-  if (b.mx.sched_poi & 32) {
-    const dim3 g(nlb + xcd_grid(b.mx.n_slices * L, NT / 64, b.mx.grid_poi), b.ni, ld / nc);
+  const bool sell = b.mx.sched_poi & 32;
+  const int gx = nlb + (sell ? xcd_grid(b.mx.n_slices * L, NT / 64, b.mx.grid_poi) : xcd_grid(b.mx.N, NT / L, b.mx.grid_poi));
+  // one instance: per-workgroup sums to the partial buffer, then one fold
+  double* part = nullptr;
+  if constexpr (MODE == SP_PLAIN || MODE == SP_CG || MODE == SP_CHEB_RZ)
+    if (b.spart && b.ni == 1 && nc == ld && NT % nc == 0 && (int64_t)gx * nc <= b.spart_cap) part = b.spart;
+  const dim3 g(gx, b.ni, ld / nc);
+  if (sell)
     hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, true, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
-                       nlb, red, k);
-  } else {
-    const dim3 g(nlb + xcd_grid(b.mx.N, NT / L, b.mx.grid_poi), b.ni, ld / nc);
+                       nlb, red, k, part);
+  else
     hipLaunchKernelGGL((k_spmv_poisson<L, V, MODE, false, T>), g, dim3(NT), 0, s, b.dm, x, pprev, pout, ld, nc, q,
-                       nlb, red, k);
+                       nlb, red, k, part);
+  if (t_pass_end) (void)hipEventRecord(t_pass_end, s);
+  if (part) {
+    const int kk = k >= 0 ? k : (k <= -2 ? -2 - k : 0);
+    const int slot = MODE == SP_CHEB_RZ ? (k & 15) : RED_PQ + kk % 2;
+    const int fb = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)gx / (NT / nc * 16)));
+    hipLaunchKernelGGL(k_fold_parts, dim3(fb), dim3(NT), 0, s, part, gx, nc, red + (int64_t)slot * ld);
   }
 }
 template <int L, int V, class T>
@@ -978,10 +1016,13 @@ static int cg_blocks(const Batch& b, int ncol) {
 static void cg_apply2(const Batch& b, PoissonWs& P, const double* x, const double* pprev, double* pout, double* q,
                       int k, hipStream_t s) {
   const bool rec = P.ev && P.ev_used + 2 <= P.ev_cap;
-  if (rec) (void)hipEventRecord(P.ev[P.ev_used], s);
+  if (rec) {
+    (void)hipEventRecord(P.ev[P.ev_used], s);
+    t_pass_end = P.ev[P.ev_used + 1];
+  }
   launch_spmv_poisson(b, x, pprev, pout, P.ncol, q, P, k, s);
   if (rec) {
-    (void)hipEventRecord(P.ev[P.ev_used + 1], s);
+    t_pass_end = nullptr;
     P.ev_used += 2;
   }
 }
