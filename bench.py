@@ -410,6 +410,8 @@ def main():
                     help="h2o: skip the extra record of the Q1 water workload on its Kelly-refined mesh")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of tuned schedules: read if it holds this workload, else written after tuning")
+    ap.add_argument("--poisson-schedule", default=None,
+                    help="--counters: Poisson schedule/grid cap to count under (e.g. 117/32768) instead of the cache's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -554,6 +556,10 @@ def run_counters(args):
     if args.tune_cache:   # the schedules the bench run tuned for this workload
         from paper_2301_02387_amd.tune import apply_cached
         log(f"schedules from the cache: {apply_cached(op, args.tune_cache)}")
+    if args.poisson_schedule:   # counters of another Poisson schedule than the tuned one
+        sched, grid = map(int, args.poisson_schedule.split("/"))
+        op.tune(1, sched, grid)
+        log(f"Poisson schedule {sched}/{grid}")
     W = torch.zeros((op.n_full, op.n_pair_cols), dtype=torch.float64, device="cuda")
     it, _ = op.poisson_pairs(phi, W)
     log(f"cg iterations {it}")
