@@ -1051,7 +1051,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     ops.resid = [&](hipStream_t st) { launch_mg_resid_f(B, mg.z0f, mg.rf, mg.t0f, ncol, op->mg_red, st); };
     ops.cheb0 = [&](hipStream_t st) {
       zc = nu % 2;
-      launch_mg_cheb0_f(B, mg.rf, zc ? mg.z0bf : mg.z0f, mg.d0f, P.red, rz_slot, ncol, st);
+      launch_mg_cheb0_f(B, mg.rf, zc ? mg.z0bf : mg.z0f, mg.d0f, P.red, rz_slot | (nu > 2 ? 0 : 256), ncol, st);
     };
     ops.cheb = [&](int k, bool rz, hipStream_t st) {
       float* zi = zc ? mg.z0bf : mg.z0f;
@@ -1063,7 +1063,7 @@ static int mg_pcg(mh_op* op, double* W, int* iters, hipStream_t s, int fixed = 0
     ops.resid = [&](hipStream_t st) { launch_mg_resid(B, mg.z0, P.r, mg.t0, ncol, op->mg_red, st); };
     ops.cheb0 = [&](hipStream_t st) {
       zc = nu % 2;
-      launch_mg_cheb0(B, P.r, zc ? mg.z0b : mg.z0, mg.d0, P.red, rz_slot, ncol, st);
+      launch_mg_cheb0(B, P.r, zc ? mg.z0b : mg.z0, mg.d0, P.red, rz_slot | (nu > 2 ? 0 : 256), ncol, st);
     };
     ops.cheb = [&](int k, bool rz, hipStream_t st) {
       double* zi = zc ? mg.z0b : mg.z0;

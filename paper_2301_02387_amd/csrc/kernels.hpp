@@ -254,10 +254,12 @@ void launch_to_float(const double* x, float* y, int64_t nd, hipStream_t s);
 // Multigrid-preconditioned CG on the finest level, in operator passes (the
 // Chebyshev coefficients are each instance's DevMesh::mgc; red: the CG
 // accumulators [ni][RED_SLOTS][ncol]):
-//  - the first two smoothing steps from z = 0 (z and d from r); clears red slot rz_slot;
+//  - the first two smoothing steps from z = 0 (z and d from r); clears red slot
+//    rz_slot & 255; d is not stored when bit 8 of rz_slot is set (degree 2:
+//    no third step reads it);
 //  - smoothing step k (0 .. degree - 1) from zin into zout (d updated in
 //    place); with rz_slot >= 0 (the last step after the coarse correction)
-//    it also accumulates r.zout into that slot.
+//    it also accumulates r.zout into that slot and leaves d alone.
 void launch_mg_cheb0(const Batch& b, const double* r, double* z, double* d, double* red, int rz_slot, int ncol,
                      hipStream_t s);
 void launch_mg_cheb_step(const Batch& b, const double* zin, const double* r, double* zout, double* d, double* red,

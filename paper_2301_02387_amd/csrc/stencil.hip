@@ -493,10 +493,12 @@ __device__ __forceinline__ void spmv_row_part(const DevMesh& d, const T* __restr
 // Chebyshev passes (x: the operand's source, pprev = r, pout = z out, q = d,
 // cf = the instance's coefficients s0, c1, c2; step k of SP_CHEB, step 1 for
 // SP_CHEB_RZ):
-//   SP_CHEB0: d0 = s0 D^-1 r, d = c1 d0 + c2 D^-1 (r - y), z = d0 + d;
+//   SP_CHEB0: d0 = s0 D^-1 r, d = c1 d0 + c2 D^-1 (r - y), z = d0 + d (d not
+//             stored when bit 8 of k is set: no further step reads it);
 //   SP_CHEB:  d = c1 d + c D^-1 (r - y) (k = 0: c1 d dropped, c = s0; else
 //             c1, c = c2 of step k), z = x + d; SP_CHEB_RZ also the r.z
-//             partial (in pq), its step being k >> 4 (its slot k & 15).
+//             partial (in pq), its step being k >> 4 (its slot k & 15); it is
+//             the last step of a smoothing, so d is not stored.
 // cf: s0, then (c1, c2) of each step from 1 on.
 // SP_RES (x = z, pprev = r): q_i = r_i - y.
 template <int V, int MODE, class T>
@@ -526,13 +528,13 @@ __device__ __forceinline__ void spmv_store(const DevMesh& d, T* __restrict__ q, 
       if constexpr (MODE == SP_CHEB0) {
         const double d0 = cf[0] * di * rv[v];
         const double dn = cf[1] * d0 + cf[2] * di * (rv[v] - y[v]);  // step 1
-        qo[v] = (T)dn;
+        if (!(k & 256)) qo[v] = (T)dn;
         po[v] = (T)(d0 + dn);
       } else {
         const double dn = (step > 0 ? cf[2 * step - 1] * dv[v] + cf[2 * step] * di * (rv[v] - y[v])
                                     : cf[0] * di * (rv[v] - y[v]));
         const double zn = xv[v] + dn;
-        qo[v] = (T)dn;
+        if constexpr (MODE != SP_CHEB_RZ) qo[v] = (T)dn;
         po[v] = (T)zn;
         if constexpr (MODE == SP_CHEB_RZ) pq[v] += rv[v] * zn;
       }
@@ -681,7 +683,7 @@ __global__ void __launch_bounds__(NT) k_spmv_poisson(const DevMesh* __restrict__
     }
   }
   if constexpr (MODE == SP_CHEB0 || MODE == SP_CHEB || MODE == SP_RES) {
-    if (MODE == SP_CHEB0 && first_wg && threadIdx.x < (unsigned)nc) red[k * ld + threadIdx.x] = 0.0;
+    if (MODE == SP_CHEB0 && first_wg && threadIdx.x < (unsigned)nc) red[(k & 255) * ld + threadIdx.x] = 0.0;
     return;
   }
   // p.q (r.z for SP_CHEB_RZ) of the workgroup: shuffles over the rows of each wave, then 4 waves
