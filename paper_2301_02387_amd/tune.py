@@ -21,11 +21,14 @@ POI_CANDIDATES = ([(s, g) for s in (13, 12, 5, 4, 9, 1, 45, 44, 37, 36) for g in
 # Grid caps above 8192 give each workgroup of the sliced-ELL sweep one or two
 # slices, so the hardware's in-order dispatch keeps the rows in flight on an
 # XCD in one window (measured on the water mesh: CG pass 1.47 ms at 8192,
-# 1.37 ms at 32768, 1.81 ms at 65536).
+# 1.37 ms at 32768, 1.81 ms at 65536).  On those grids the sweep stays
+# XCD-contiguous (bit 0): without it the operator pass fetches 9.2 instead of
+# 6.7 GB per launch in the same time (the extra bytes come from the last-level
+# cache), and the tuner's short solves from zero do not tell the two apart.
 POI_CANDIDATES_WIDE = ([(13, 8192)]
                        + [(s, 8192) for s in (22, 20, 23, 21, 54, 52, 55, 53, 118, 116, 119, 117, 182, 214, 246,
                                                372, 628, 884)]
-                       + [(s, g) for s in (116, 117, 372, 373, 628) for g in (16384, 32768)])
+                       + [(s, g) for s in (117, 372, 373, 628) for g in (16384, 32768)])
 # grid caps are per instance: a batch fills the chip with fewer workgroups each
 ORB_CANDIDATES_BATCH = [(s, g) for s in (1, 0, 5, 4) for g in (256, 1024, 65536)]
 POI_CANDIDATES_BATCH = ([(s, g) for s in (13, 12, 5, 4, 1, 45, 37, 36) for g in (256, 1024)]
