@@ -324,6 +324,8 @@ static dim3 level_grid(int64_t n, int ncol, int ni) { return dim3(nblocks(n * nc
 //  - MODE 0, one Chebyshev smoothing step k (the recurrence of k_mg_cheb):
 //    res = r - A zin (res = r for the first step from zero), d = c1 d +
 //    c2 D^-1 res, zout = zin + d (zout = d for the first step from zero).
+//    The smoothing has degree 2 (k = 0, 1): d is stored only by step 0 from
+//    a nonzero z; from zero, step 1 takes d from its zin, which step 0 wrote.
 //    zin and zout are the level's z and t arrays (into_t: z -> t, else
 //    t -> z), so the rows gathered from zin are never the rows written.
 //  - MODE 1, the residual t = r - A z that the restriction reads.
@@ -371,12 +373,19 @@ __global__ void __launch_bounds__(NT) k_mg_level_pass(const MgLevelDev* __restri
     } else {
       const double di = dinv[i];
       double dv[V], zv[V];
-      if (k > 0) load_vals<V>(dd + e, dv);
       if (!first) load_vals<V>(zin + e, zv);
+      if (k > 0) {
+        if (from_zero) {  // the first step's d is its zout, this step's zin
+#pragma unroll
+          for (int v = 0; v < V; ++v) dv[v] = zv[v];
+        } else {
+          load_vals<V>(dd + e, dv);
+        }
+      }
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double dn = (k > 0 ? c1 * dv[v] : 0.0) + c2 * di * (rv[v] - y[v]);
-        dd[e + v] = dn;
+        if (k == 0 && !from_zero) dd[e + v] = dn;   // the only d a later step reads
         zout[e + v] = first ? dn : zv[v] + dn;
       }
     }
